@@ -1,0 +1,298 @@
+"""Throughput of the local SpMM hot path on one MI355X, as one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+
+A step is one pass of the hot path over one batch of synthetic input that is
+already resident in HBM.  The default workload is one GPU's share of a 4 x 4
+stationary-C SpMM (Algorithm 2): row block 0 of an R-MAT scale-22, edge-factor-16
+matrix (Graph500 quadrant probabilities, duplicates merged, U[-1,1) FP32 values)
+times dense B_k of 1,048,576 x 128 FP32, accumulated over its 4 k-tiles into a
+1,048,576 x 128 FP32 C tile that is written once.  Other workloads:
+
+    er4096_n32              4096^2 uniform tile, 16 non-zeros per row, N = 32, forward
+    powerlaw2m_n128_fwdbwd  2,097,152^2 heavy-tailed rows (mean 32, max 65,536), N = 128,
+                            forward + dA (sampled dense-dense product) + dB = A^T dC
+    rmat23_n256_bf16        R-MAT scale 23, edge factor 32, N = 256, BF16 B and C
+    rmat23_n256_f32         the same with FP32 B and C
+
+value = 2 * nnz * N * passes / step time (GFLOP/s).  The roofline object prices
+the step's kernels with their algorithmic bytes (CSR arrays + dense inputs read
+once + outputs written once; the performance-model accounting of Section 4)
+against the 8 TB/s HBM peak.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def _threads():
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        n = min(n, int(env))
+    return max(1, n)
+
+
+# ---------------------------------------------------------------------------
+class Workload:
+    name = ""
+    dtype = "f32"
+    kernel = ""
+
+    def setup(self):  # build device inputs and handles
+        raise NotImplementedError
+
+    def step(self):  # one pass of the hot path (asynchronous)
+        raise NotImplementedError
+
+    flops = 0.0
+    alg_bytes = 0.0
+    config = {}
+
+    def cpu_sample(self):  # -> (flops, seconds, description)
+        raise NotImplementedError
+
+
+def _fwd_bytes(tiles, N, esize):
+    b = 0
+    for t in tiles:
+        b += 8 * t.nnz + 4 * (t.rows + 1) + t.cols * N * esize
+    return b + tiles[0].rows * N * esize
+
+
+class TileRowForward(Workload):
+    """C = sum_k A_k B_k over a tile row (one tile or several k-tiles)."""
+
+    def __init__(self, name, make_tiles, N, dtype, config):
+        self.name = name
+        self.make_tiles = make_tiles
+        self.N = N
+        self.dtype = dtype
+        self.config = config
+        self.kernel = "spmm_fwd (fwd_main + fwd_fixup)"
+
+    def setup(self):
+        import torch
+        import synth
+        from paper_2311_18141_amd import ops
+        t0 = time.time()
+        self.tiles = self.make_tiles()
+        _log("%s: inputs generated in %.1f s (nnz %d)" % (self.name, time.time() - t0, sum(t.nnz for t in self.tiles)))
+        rng = synth.streams(self.config.get("seed", 1))[2]
+        self.Bh = [synth.dense(t.cols, self.N, rng) for t in self.tiles]
+        tdt = torch.float32 if self.dtype == "f32" else torch.bfloat16
+        dev = "cuda:0"
+        self.dev_tiles = [(torch.from_numpy(t.rowptr).to(dev), torch.from_numpy(t.colind).to(dev),
+                           torch.from_numpy(t.values).to(dev), t.cols) for t in self.tiles]
+        self.B = [torch.from_numpy(b).to(tdt).to(dev) for b in self.Bh]
+        self.tile = ops.spmm_tile_create(self.tiles[0].rows, self.dev_tiles, validate=True)
+        self.C = torch.empty(self.tiles[0].rows, self.N, dtype=tdt, device=dev)
+        self.ws = self.tile.workspace(self.N)
+        nnz = sum(t.nnz for t in self.tiles)
+        self.flops = 2.0 * nnz * self.N
+        self.alg_bytes = float(_fwd_bytes(self.tiles, self.N, 4 if self.dtype == "f32" else 2))
+        self.config = dict(self.config, nnz=nnz, rows=self.tiles[0].rows, N=self.N, k_tiles=len(self.tiles),
+                           tile_stats={k: v for k, v in self.tile.stats().items()
+                                       if k in ("max_row", "empty_rows", "long_rows", "segments")})
+
+    def step(self):
+        from paper_2311_18141_amd import ops
+        ops.spmm_fwd(self.tile, self.B, C=self.C, workspace=self.ws)
+
+    def cpu_sample(self):
+        import oracle
+        Bs = self.Bh
+        if self.dtype == "bf16":
+            Bs = [oracle.bf16_to_f32(oracle.f32_to_bf16(b)) for b in Bs]
+        rows = self.tiles[0].rows
+        lens = sum(t.row_lengths() for t in self.tiles)
+        # rows [0, r): enough non-zeros for about 20 GFLOP of oracle work (or the whole tile row)
+        target = 2.0e10 / (2.0 * self.N)
+        r = int(min(rows, np.searchsorted(np.cumsum(lens), target) + 1))
+        sel = np.arange(r, dtype=np.int64)
+        t0 = time.perf_counter()
+        oracle.spmm([(t.rowptr, t.colind, t.values) for t in self.tiles], Bs, rows=sel, scale=False)
+        dt = time.perf_counter() - t0
+        nnz = float(lens[:r].sum())
+        return 2.0 * nnz * self.N, dt, "oracle FP64 forward on rows [0, %d) of %d (%d non-zeros)" % (r, rows, nnz)
+
+
+class ForwardBackward(Workload):
+    """Forward, dA = SDDMM on A's pattern, dB = A^T dC: three passes of 2 nnz N flops."""
+
+    def __init__(self, name, make_tile, N, config):
+        self.name = name
+        self.make_tile = make_tile
+        self.N = N
+        self.config = config
+        self.kernel = "spmm_fwd + spmm_bwd (fwd_main, fwd_fixup, sddmm_kernel)"
+
+    def setup(self):
+        import torch
+        import synth
+        from paper_2311_18141_amd import ops
+        t0 = time.time()
+        self.A = self.make_tile()
+        _log("%s: inputs generated in %.1f s (nnz %d)" % (self.name, time.time() - t0, self.A.nnz))
+        rs = synth.streams(self.config.get("seed", 3))
+        self.Bh = synth.dense(self.A.cols, self.N, rs[2], "normal")
+        self.dCh = synth.dense(self.A.rows, self.N, rs[3], "normal")
+        dev = "cuda:0"
+        t = (torch.from_numpy(self.A.rowptr).to(dev), torch.from_numpy(self.A.colind).to(dev),
+             torch.from_numpy(self.A.values).to(dev), self.A.cols)
+        self.tile = ops.spmm_tile_create(self.A.rows, [t], validate=True, transpose=True)
+        self.B = torch.from_numpy(self.Bh).to(dev)
+        self.dC = torch.from_numpy(self.dCh).to(dev)
+        self.C = torch.empty(self.A.rows, self.N, device=dev)
+        self.dA = torch.empty(self.A.nnz, device=dev)
+        self.dB = torch.empty(self.A.cols, self.N, device=dev)
+        self.wsf = self.tile.workspace(self.N, "fwd")
+        self.wsb = self.tile.workspace(self.N, "bwd")
+        A, N = self.A, self.N
+        self.flops = 3 * 2.0 * A.nnz * N
+        fwd = 8 * A.nnz + 4 * (A.rows + 1) + 4 * A.cols * N + 4 * A.rows * N
+        sddmm = 4 * A.nnz + 4 * (A.rows + 1) + 4 * A.rows * N + 4 * A.cols * N + 4 * A.nnz
+        dB = 4 * (A.cols + 1) + 12 * A.nnz + 4 * A.rows * N + 4 * A.cols * N
+        self.alg_bytes = float(fwd + sddmm + dB)
+        st = self.tile.stats()
+        self.config = dict(self.config, nnz=A.nnz, rows=A.rows, N=N,
+                           tile_stats={k: st[k] for k in ("max_row", "empty_rows", "long_rows", "segments",
+                                                          "long_rows_t", "segments_t")})
+
+    def step(self):
+        from paper_2311_18141_amd import ops
+        ops.spmm_fwd(self.tile, [self.B], C=self.C, workspace=self.wsf)
+        ops.spmm_bwd(self.tile, self.dC, self.B, dA=self.dA, dB=self.dB, workspace=self.wsb)
+
+    def cpu_sample(self):
+        import oracle
+        A, N = self.A, self.N
+        lens = A.row_lengths()
+        target = 0.6e10 / (2.0 * N)   # per pass; three passes
+        r = int(min(A.rows, np.searchsorted(np.cumsum(lens), target) + 1))
+        rows = np.arange(r, dtype=np.int64)
+        nnz = int(lens[:r].sum())
+        cols = np.arange(min(A.cols, r), dtype=np.int64)
+        t0 = time.perf_counter()
+        oracle.spmm([(A.rowptr, A.colind, A.values)], [self.Bh], rows=rows, scale=False)
+        oracle.sddmm(A.rowptr, A.colind, self.dCh, self.Bh, entries=np.arange(nnz, dtype=np.int64))
+        oracle.spmm_t(A.rowptr, A.colind, A.values, A.cols, self.dCh, out_rows=cols)
+        dt = time.perf_counter() - t0
+        nnz_t = float(np.isin(A.colind, cols).sum()) if A.nnz < 2e8 else float(nnz)
+        flops = 2.0 * N * (2 * nnz + nnz_t)
+        return flops, dt, ("oracle FP64 forward + SDDMM on rows [0, %d) and A^T dC on output rows [0, %d) of %d"
+                           % (r, len(cols), A.rows))
+
+
+def workloads():
+    import synth
+    return {
+        "rmat22_rowblock0_4x4_n128": lambda: TileRowForward(
+            "rmat22_rowblock0_4x4_n128",
+            lambda: synth.rmat_row_block(22, 16, 4, 0, seed=2).tiles, 128, "f32",
+            {"workload": "rmat22_rowblock0_4x4_n128", "matrix": "R-MAT scale 22, edge factor 16, "
+             "(0.57,0.19,0.19,0.05), row block 0 of a 4x4 tile grid", "seed": 2}),
+        "er4096_n32": lambda: TileRowForward(
+            "er4096_n32", lambda: [synth.uniform_csr(4096, 4096, 16, seed=1)], 32, "f32",
+            {"workload": "er4096_n32", "matrix": "4096^2 uniform, 16 nnz/row", "seed": 1}),
+        "rmat23_n256_bf16": lambda: TileRowForward(
+            "rmat23_n256_bf16", lambda: [synth.rmat_csr(23, 32, seed=5)], 256, "bf16",
+            {"workload": "rmat23_n256_bf16", "matrix": "R-MAT scale 23, edge factor 32", "seed": 5}),
+        "rmat23_n256_f32": lambda: TileRowForward(
+            "rmat23_n256_f32", lambda: [synth.rmat_csr(23, 32, seed=5)], 256, "f32",
+            {"workload": "rmat23_n256_f32", "matrix": "R-MAT scale 23, edge factor 32", "seed": 5}),
+        "powerlaw2m_n128_fwdbwd": lambda: ForwardBackward(
+            "powerlaw2m_n128_fwdbwd", lambda: synth.powerlaw_csr(1 << 21, 1 << 21, 32, 65536, seed=3), 128,
+            {"workload": "powerlaw2m_n128_fwdbwd", "matrix": "2,097,152^2, Pareto(2.1) row degrees, mean 32, "
+             "max 65,536, values N(0,1)/sqrt(deg)", "seed": 3}),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rmat22_rowblock0_4x4_n128")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the stationary-C tile row is "
+              "one GPU's share); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    wl = workloads()[args.workload]()
+    wl.setup()
+    torch.cuda.synchronize()
+    _log("setup done; warmup %d" % args.warmup)
+    for _ in range(args.warmup):
+        wl.step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t_all0 = torch.cuda.Event(enable_timing=True)
+    t_all1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_all0.record(stream)
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        wl.step()
+        ev[i][1].record(stream)
+    t_all1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = t_all0.elapsed_time(t_all1)
+    per = [a.elapsed_time(b) for a, b in ev]
+    ms_step = ms_total / args.steps
+    value = wl.flops / (ms_step * 1e-3) / 1e9
+    avg_kernel_ms = float(np.mean(per))
+    achieved = wl.alg_bytes / (avg_kernel_ms * 1e-3) / 1e9
+    _log("timed %d steps: %.4f ms/step (per-step events mean %.4f, min %.4f, max %.4f)"
+         % (args.steps, ms_step, avg_kernel_ms, min(per), max(per)))
+    out = {
+        "metric": "SpMM GFLOP/s (2*nnz*N) and % HBM roofline",
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": wl.dtype,
+        "data": "synthetic",
+        "config": wl.config,
+        "roofline": {"bound": "hbm", "kernel": wl.kernel, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "alg_bytes_per_step": wl.alg_bytes, "avg_kernel_ms": round(avg_kernel_ms, 5)},
+    }
+    if not args.no_cpu_baseline:
+        threads = _threads()
+        os.environ["OMP_NUM_THREADS"] = str(threads)
+        flops, secs, desc = wl.cpu_sample()
+        out["cpu_baseline"] = {"value": round(flops / secs / 1e9, 3), "unit": "GFLOP/s", "cores": threads,
+                               "kind": "oracle", "sample": desc, "seconds": round(secs, 2)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

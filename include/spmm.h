@@ -1,0 +1,158 @@
+/*
+ * spmm.h -- C ABI of the MI355X (gfx950) local sparse-times-dense multiply.
+ *
+ * The operation is the local tile product that every GPU runs inside the
+ * stationary-C algorithm of Brock, Buluc and Yelick, "RDMA-Based Algorithms
+ * for Sparse Matrix Multiplication on GPUs" (ICS'24):
+ *
+ *     C_ij  =  C_ij  +  sum over k of  A_ik * B_kj          (Section 2.1)
+ *
+ * with the owner of C(i,j) walking k' = 0..K-1 and multiplying tile
+ * k = (k' + offset) mod K (Section 3.3, Algorithm 2), A's tiles in CSR
+ * (values, row pointer, column indices; Section 3.1 and Section 5.2) with FP32
+ * values and 32-bit indices (Section 6).  The gradient pass, BF16 storage of
+ * the dense operands and the batched launch are additions of this library.
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers documented "device" point to GPU memory of the current HIP
+ *     device; "host" pointers to CPU memory.  The caller owns every buffer it
+ *     passes in; buffers handed to spmm_tile_create must outlive the handle.
+ *   - Dense matrices are row-major with a leading dimension (in elements)
+ *     >= their width.  A B_k row is one contiguous run of N elements.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     spmm_fwd, spmm_bwd and spmm_batched only enqueue work: no host
+ *     synchronisation, no device allocation, so they can be captured in a
+ *     HIP graph.  Creation and destruction calls are synchronous.
+ *   - Every function returns an spmm_status; nothing is thrown across the ABI.
+ *     Argument checks finish before any HIP call.  spmm_last_error() returns a
+ *     thread-local message describing the most recent failure.
+ *   - Values are read live on every call: a handle caches structure only
+ *     (pattern, transposed pattern, work plans), never values, so changes to
+ *     `values` between calls take effect without re-creating the handle.
+ */
+#ifndef SPMM_H
+#define SPMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SPMM_OK = 0,
+  SPMM_ERR_INVALID_ARG = 1,  /* null pointer, negative size, ld < width, bad enum ... */
+  SPMM_ERR_BAD_CSR = 2,      /* validation found a malformed CSR tile */
+  SPMM_ERR_UNSUPPORTED = 3,  /* valid request this build does not implement */
+  SPMM_ERR_WORKSPACE = 4,    /* workspace pointer null or smaller than required */
+  SPMM_ERR_HIP = 5,          /* a HIP runtime call failed; see spmm_last_error() */
+  SPMM_ERR_ALLOC = 6         /* host or device allocation failed (creation calls only) */
+} spmm_status;
+
+typedef enum { SPMM_F32 = 0, SPMM_BF16 = 1 } spmm_dtype;
+
+/* One CSR tile A_ik of a tile row. */
+typedef struct {
+  int64_t cols;            /* columns of the tile = rows of its dense operand B_k */
+  int64_t nnz;             /* stored entries; must be < 2^31 */
+  const int32_t* rowptr;   /* device, rows+1 entries, rowptr[0] = 0, rowptr[rows] = nnz */
+  const int32_t* colind;   /* device, nnz entries, tile-local, strictly increasing per row */
+  const float* values;     /* device, nnz entries, FP32; read on every call */
+} spmm_csr;
+
+/* Flags for spmm_tile_opts.flags. */
+#define SPMM_TILE_VALIDATE 1u   /* check the CSR invariants on the device; SPMM_ERR_BAD_CSR on failure */
+#define SPMM_TILE_TRANSPOSE 2u  /* also build the transposed structure needed by spmm_bwd (needs num_k = 1) */
+
+typedef struct {
+  unsigned flags;
+  int32_t long_row;        /* rows whose length over all k-tiles exceeds this are split across
+                              work units with a deterministic fix-up; 0 = library default */
+  int32_t segment;         /* non-zeros per split work unit; 0 = library default */
+} spmm_tile_opts;
+
+/* Opaque handle to one tile row (A_i0 ... A_i,K-1): the sparse operand of one C
+   tile's stationary-C loop.  A single tile is the case K = 1. */
+typedef struct spmm_tile_s* spmm_tile_t;
+
+/* Structural statistics gathered at creation (Section 6 defines load
+   imbalance as max/avg non-zeros; these are the per-row analogues). */
+typedef struct {
+  int64_t rows, num_k, nnz_total;
+  int64_t max_row;           /* longest row, non-zeros summed over the k-tiles */
+  int64_t empty_rows;        /* rows with no non-zero in any k-tile */
+  int64_t long_rows;         /* rows handled by the split path */
+  int64_t segments;          /* split work units */
+  int64_t hist_log2[33];     /* rows by bit length of their combined length (0 = empty) */
+  int64_t nnz_per_k[16];
+  int64_t has_transpose;
+  int64_t long_rows_t, segments_t;   /* the same for the transposed structure */
+} spmm_tile_stats;
+
+/*
+ * Create a tile-row handle from num_k (1..16) CSR tiles that share `rows`.
+ * Builds, on `stream`, the work plan for the row-split and split-row paths
+ * and, with SPMM_TILE_TRANSPOSE, the transposed structure (rowptrT, colindT,
+ * perm) by a stable sort on column index.  Synchronous.  The library allocates
+ * the handle's own device memory here (released by spmm_tile_destroy); the
+ * tile arrays stay owned by the caller and must outlive the handle.
+ * Errors: INVALID_ARG (null/negative/num_k out of range/nnz >= 2^31),
+ * BAD_CSR (with VALIDATE), UNSUPPORTED (TRANSPOSE with num_k > 1), ALLOC, HIP.
+ */
+spmm_status spmm_tile_create(int64_t rows, int num_k, const spmm_csr* tiles /* host, num_k */,
+                             const spmm_tile_opts* opts /* host, nullable */, void* stream,
+                             spmm_tile_t* out /* host */);
+spmm_status spmm_tile_destroy(spmm_tile_t tile);
+spmm_status spmm_tile_get_stats(spmm_tile_t tile, spmm_tile_stats* out /* host */);
+
+/*
+ * Copy the transposed structure of a K = 1 handle into caller buffers (device):
+ * rowptrT[cols+1], colindT[nnz] (original row of each entry), perm[nnz]
+ * (original CSR position).  Entries of one output row are ordered by
+ * increasing original row.  Asynchronous on `stream`.  Errors: INVALID_ARG,
+ * UNSUPPORTED (handle built without SPMM_TILE_TRANSPOSE), HIP.
+ */
+spmm_status spmm_tile_export_transpose(spmm_tile_t tile, int32_t* rowptrT, int32_t* colindT,
+                                       int32_t* perm, void* stream);
+
+/* Workspace (device bytes) spmm_fwd needs for this handle at width N. */
+spmm_status spmm_fwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes /* host */);
+
+/*
+ * Forward local SpMM over a tile row (Section 2.1; k order of Algorithm 2):
+ *   C = [accumulate ? C : 0] + sum_{k'=0}^{K-1} A_k B_k,   k = (k' + k_offset) mod K.
+ * B: host array of K device pointers; B[k] is cols_k x N row-major with leading
+ * dimension ldb[k] (host array).  C: device, rows x N, leading dimension ldc.
+ * dtype: (F32, F32) or (BF16, BF16) for (B, C); products and sums are FP32 and
+ * a BF16 C is rounded once (nearest-even) at the store.  N >= 1.  Asynchronous.
+ * Errors: INVALID_ARG, UNSUPPORTED (mixed dtypes), WORKSPACE, HIP.
+ */
+spmm_status spmm_fwd(spmm_tile_t A, int k_offset, const void* const* B, const int64_t* ldb,
+                     spmm_dtype b_dtype, void* C, int64_t ldc, spmm_dtype c_dtype, int64_t N,
+                     int accumulate, void* workspace, size_t ws_bytes, void* stream);
+
+/* Workspace (device bytes) spmm_bwd needs for this handle at width N. */
+spmm_status spmm_bwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes /* host */);
+
+/*
+ * Backward of C = A B for a K = 1 handle built with SPMM_TILE_TRANSPOSE, given
+ * dC = dL/dC (device, rows x N, ld lddc) and B (device, cols x N, ld ldb), FP32:
+ *   dA_values[p] = sum_n dC[i, n] * B[colind[p], n]   for p in row i   (nullable: skipped)
+ *   dB = A^T dC   (device, cols x N, ld lddb; nullable: skipped)
+ * dA is on A's pattern, in A's CSR order; no gradient flows to the pattern.
+ * Asynchronous.  Errors: INVALID_ARG, UNSUPPORTED (no transpose, num_k > 1,
+ * BF16), WORKSPACE, HIP.
+ */
+spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* B, int64_t ldb,
+                     int64_t N, float* dA_values, float* dB, int64_t lddb, void* workspace,
+                     size_t ws_bytes, void* stream);
+
+const char* spmm_status_string(spmm_status status);
+const char* spmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPMM_H */

@@ -1,0 +1,73 @@
+// Backward of C = A B with respect to A's stored values: the sampled dense-dense
+// product on A's pattern,  dA[p] = <dC[row(p), :], B[colind[p], :]>.
+// (dB = A^T dC reuses the forward kernels on the transposed structure.)
+//
+// A group of G lanes owns one non-zero; each lane loads V consecutive columns of
+// dC's row and B's row per step (coalesced within the group), accumulates the
+// partial dot product in FP32 and the group reduces with a fixed butterfly, so
+// the result does not depend on scheduling.
+#include "elem.hpp"
+#include "internal.hpp"
+
+namespace spmm {
+namespace {
+
+template <int G>
+__device__ __forceinline__ float group_sum(float x) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+template <int G, int V>
+__global__ void __launch_bounds__(kBlock) sddmm_kernel(SddmmParams P) {
+  constexpr int GPB = kBlock / G;
+  const int gl = threadIdx.x & (G - 1);
+  const int64_t p = (int64_t)blockIdx.x * GPB + threadIdx.x / G;
+  if (p >= P.nnz) return;
+  const int64_t i = __builtin_nontemporal_load(P.rowid + p);
+  const int64_t j = __builtin_nontemporal_load(P.colind + p);
+  const float* g = P.dC + i * P.lddc;
+  const float* b = P.B + j * P.ldb;
+  float acc = 0.0f;
+  for (int64_t c = (int64_t)gl * V; c < P.N; c += G * V) {
+    float x[V], y[V];
+    load_f32v<V>(g + c, x);
+    load_f32v<V>(b + c, y);
+#pragma unroll
+    for (int e = 0; e < V; ++e) acc = fmaf(x[e], y[e], acc);
+  }
+  acc = group_sum<G>(acc);
+  if (gl == 0) P.dA[p] = acc;
+}
+
+template <int V>
+hipError_t launch_sddmm_v(const SddmmParams& P, int G, hipStream_t s) {
+  auto go = [&](auto kern, int gpb) {
+    const int64_t blocks = (P.nnz + gpb - 1) / gpb;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kBlock), 0, s, P);
+    return hipGetLastError();
+  };
+  switch (G) {
+    case 4: return go(sddmm_kernel<4, V>, kBlock / 4);
+    case 8: return go(sddmm_kernel<8, V>, kBlock / 8);
+    case 16: return go(sddmm_kernel<16, V>, kBlock / 16);
+    case 32: return go(sddmm_kernel<32, V>, kBlock / 32);
+    case 64: return go(sddmm_kernel<64, V>, kBlock / 64);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_sddmm(const SddmmParams& P, Variant v, hipStream_t s) {
+  switch (v.V) {
+    case 1: return launch_sddmm_v<1>(P, v.G, s);
+    case 2: return launch_sddmm_v<2>(P, v.G, s);
+    case 4: return launch_sddmm_v<4>(P, v.G, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace spmm

@@ -1,0 +1,122 @@
+// Internal declarations shared by the HIP translation units of libspmm.
+// Nothing here is part of the public ABI (include/spmm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace spmm {
+
+constexpr int kMaxK = 16;      // k-tiles per tile row in one fused launch
+constexpr int kBlock = 256;    // threads per workgroup for every kernel here
+
+enum class DT : int { F32 = 0, BF16 = 1 };
+
+// One k-tile as the forward kernels see it.
+struct TileDev {
+  const int32_t* rowptr;
+  const int32_t* colind;
+  const float* values;
+  const int32_t* perm;   // nullable: the value of position q is values[perm[q]]
+  const void* B;         // dense operand rows for this tile's columns
+  int64_t ldb;
+};
+
+// A split work unit: row, k-tile, [p0, p1) in that tile's CSR positions.
+struct Seg {
+  int32_t row, k, p0, p1;
+};
+
+// A split row: row, and its units [s0, s1) in the unit list.
+struct LongRow {
+  int32_t row, s0, s1, pad;
+};
+
+struct FwdParams {
+  TileDev t[kMaxK];
+  int num_k;
+  int k_offset;          // normalised to [0, num_k)
+  int64_t rows;
+  int64_t N;
+  void* C;
+  int64_t ldc;
+  int accumulate;
+  int32_t long_row;      // rows with combined length > long_row are done by units + fix-up
+  const Seg* seg;
+  int64_t n_seg;
+  const LongRow* lrow;
+  int64_t n_long;
+  float* partial;        // n_seg x ldp FP32 partial sums
+  int64_t ldp;
+  int64_t row_blocks;    // workgroups of the row-split part (units come after)
+};
+
+// Kernel variant: G lanes per row (group), V elements per lane per load.
+struct Variant {
+  int G;
+  int V;
+};
+
+// ---- launchers (defined in the .hip files) --------------------------------
+hipError_t launch_fwd(const FwdParams& P, Variant v, DT dt, hipStream_t s);
+
+struct SddmmParams {
+  const int32_t* rowid;
+  const int32_t* colind;
+  int64_t nnz;
+  const float* dC;
+  int64_t lddc;
+  const float* B;
+  int64_t ldb;
+  int64_t N;
+  float* dA;
+};
+hipError_t launch_sddmm(const SddmmParams& P, Variant v, hipStream_t s);
+
+// Structure utilities (utils.hip).
+hipError_t launch_validate_rowptr(const int32_t* rowptr, int64_t rows, int64_t nnz, uint32_t* status,
+                                  hipStream_t s);
+hipError_t launch_validate_colind(const int32_t* rowptr, const int32_t* colind, int64_t rows,
+                                  int64_t cols, uint32_t* status, hipStream_t s);
+
+struct PlanCountParams {
+  const int32_t* rowptr[kMaxK];
+  int num_k;
+  int64_t rows;
+  int32_t long_row;
+  int32_t segment;
+  int32_t* nseg;          // per row
+  int32_t* islong;        // per row
+  unsigned long long* stats;  // [0] max row, [1] empty rows, [2..34] log2 histogram
+};
+hipError_t launch_plan_count(const PlanCountParams& P, hipStream_t s);
+
+struct PlanEmitParams {
+  const int32_t* rowptr[kMaxK];
+  int num_k;
+  int64_t rows;
+  int32_t segment;
+  const int32_t* nseg;
+  const int32_t* seg_off;
+  const int32_t* islong;
+  const int32_t* long_off;
+  Seg* seg;
+  LongRow* lrow;
+};
+hipError_t launch_plan_emit(const PlanEmitParams& P, hipStream_t s);
+
+// Exclusive scan of n int32 values; total (nullable, device) receives the sum.
+// temp must hold scan_temp_elems(n) int32 values.
+int64_t scan_temp_elems(int64_t n);
+hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* total, int32_t* temp,
+                          hipStream_t s);
+
+// Transposed structure by a stable LSD radix sort of (colind, position).
+int64_t transpose_temp_bytes(int64_t rows, int64_t cols, int64_t nnz);
+hipError_t build_transpose(const int32_t* rowptr, const int32_t* colind, int64_t rows, int64_t cols,
+                           int64_t nnz, int32_t* rowid, int32_t* rowptrT, int32_t* colindT, int32_t* perm,
+                           void* temp, hipStream_t s);
+
+}  // namespace spmm

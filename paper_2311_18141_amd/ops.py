@@ -1,0 +1,207 @@
+"""Python binding of the C ABI with the same names (include/spmm.h).
+
+PyTorch tensors supply device memory and the current HIP stream; every step of
+the computation runs in libspmm's kernels.  Tensors handed to spmm_tile_create
+are kept referenced by the returned Tile so that they outlive the handle.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib
+from ._lib import SpmmCsr, SpmmTileOpts, SpmmTileStats, check, lib
+
+_DTYPES = {torch.float32: _lib.SPMM_F32, torch.bfloat16: _lib.SPMM_BF16}
+
+
+def _stream_ptr(stream: Optional[torch.cuda.Stream]) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _need(t: torch.Tensor, dtype, name: str):
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
+def _row_major_ld(t: torch.Tensor, name: str) -> int:
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("%s must be a 2-D row-major tensor (unit column stride)" % name)
+    return max(t.stride(0), t.shape[1])
+
+
+class Tile:
+    """A tile-row handle: num_k CSR tiles sharing their rows (one tile for num_k = 1)."""
+
+    def __init__(self, handle: int, rows: int, cols: List[int], nnz: List[int], keep: list, values: List[torch.Tensor]):
+        self.handle = handle
+        self.rows = rows
+        self.cols = cols
+        self.nnz = nnz
+        self.values = values
+        self._keep = keep
+        self._ws = {}
+
+    @property
+    def num_k(self) -> int:
+        return len(self.cols)
+
+    def stats(self) -> dict:
+        st = SpmmTileStats()
+        check(lib().spmm_tile_get_stats(self.handle, ctypes.byref(st)))
+        out = {f: getattr(st, f) for f, _ in SpmmTileStats._fields_}
+        out["hist_log2"] = list(st.hist_log2)
+        out["nnz_per_k"] = list(st.nnz_per_k)[: self.num_k]
+        return out
+
+    def workspace(self, N: int, kind: str = "fwd") -> Optional[torch.Tensor]:
+        """A cached device workspace large enough for spmm_fwd / spmm_bwd at width N."""
+        nbytes = spmm_fwd_workspace_bytes(self, N) if kind == "fwd" else spmm_bwd_workspace_bytes(self, N)
+        if nbytes == 0:
+            return None
+        ws = self._ws.get(kind)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=self.values[0].device)
+            self._ws[kind] = ws
+        return ws
+
+    def close(self):
+        if self.handle:
+            check(lib().spmm_tile_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def spmm_tile_create(rows: int, tiles: Sequence[Tuple[torch.Tensor, torch.Tensor, torch.Tensor, int]],
+                     validate: bool = False, transpose: bool = False, long_row: int = 0, segment: int = 0,
+                     stream: Optional[torch.cuda.Stream] = None) -> Tile:
+    """Create a handle from k-tiles given as (rowptr int32, colind int32, values float32, cols)."""
+    K = len(tiles)
+    arr = (SpmmCsr * max(K, 1))()
+    keep = []
+    cols, nnz, vals = [], [], []
+    for k, (rp, ci, va, nc) in enumerate(tiles):
+        _need(rp, torch.int32, "rowptr")
+        _need(ci, torch.int32, "colind")
+        _need(va, torch.float32, "values")
+        if rp.numel() != rows + 1:
+            raise ValueError("rowptr of tile %d has %d entries, expected %d" % (k, rp.numel(), rows + 1))
+        if ci.numel() != va.numel():
+            raise ValueError("colind and values of tile %d differ in length" % k)
+        arr[k].cols = int(nc)
+        arr[k].nnz = ci.numel()
+        arr[k].rowptr = rp.data_ptr()
+        arr[k].colind = ci.data_ptr() if ci.numel() else None
+        arr[k].values = va.data_ptr() if va.numel() else None
+        keep += [rp, ci, va]
+        cols.append(int(nc))
+        nnz.append(ci.numel())
+        vals.append(va)
+    opts = SpmmTileOpts()
+    opts.flags = (_lib.SPMM_TILE_VALIDATE if validate else 0) | (_lib.SPMM_TILE_TRANSPOSE if transpose else 0)
+    opts.long_row = long_row
+    opts.segment = segment
+    h = ctypes.c_void_p()
+    check(lib().spmm_tile_create(rows, K, arr, ctypes.byref(opts), _stream_ptr(stream), ctypes.byref(h)))
+    return Tile(h.value, rows, cols, nnz, keep, vals)
+
+
+def spmm_tile_destroy(tile: Tile) -> None:
+    tile.close()
+
+
+def spmm_tile_export_transpose(tile: Tile, stream=None) -> Tuple[torch.Tensor, torch.Tensor, torch.Tensor]:
+    dev = tile.values[0].device
+    rpT = torch.empty(tile.cols[0] + 1, dtype=torch.int32, device=dev)
+    ciT = torch.empty(tile.nnz[0], dtype=torch.int32, device=dev)
+    perm = torch.empty(tile.nnz[0], dtype=torch.int32, device=dev)
+    check(lib().spmm_tile_export_transpose(tile.handle, rpT.data_ptr(), ciT.data_ptr() if tile.nnz[0] else None,
+                                           perm.data_ptr() if tile.nnz[0] else None, _stream_ptr(stream)))
+    return rpT, ciT, perm
+
+
+def spmm_fwd_workspace_bytes(tile: Tile, N: int) -> int:
+    n = ctypes.c_size_t()
+    check(lib().spmm_fwd_workspace_bytes(tile.handle, N, ctypes.byref(n)))
+    return n.value
+
+
+def spmm_bwd_workspace_bytes(tile: Tile, N: int) -> int:
+    n = ctypes.c_size_t()
+    check(lib().spmm_bwd_workspace_bytes(tile.handle, N, ctypes.byref(n)))
+    return n.value
+
+
+def spmm_fwd(tile: Tile, Bs: Sequence[torch.Tensor], C: Optional[torch.Tensor] = None, k_offset: int = 0,
+             accumulate: bool = False, workspace: Optional[torch.Tensor] = None,
+             stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """C = [C] + sum_k A_k B_k (k from k_offset).  B_k and C share one dtype (float32 or bfloat16)."""
+    K = tile.num_k
+    if len(Bs) != K:
+        raise ValueError("expected %d dense operands, got %d" % (K, len(Bs)))
+    dt = Bs[0].dtype
+    if dt not in _DTYPES:
+        raise ValueError("dense operands must be float32 or bfloat16")
+    N = Bs[0].shape[1]
+    ptrs = (ctypes.c_void_p * K)()
+    lds = (ctypes.c_int64 * K)()
+    for k, B in enumerate(Bs):
+        if B.dtype != dt or not B.is_cuda or B.shape[1] != N or B.shape[0] != tile.cols[k]:
+            raise ValueError("B[%d] must be a device %s tensor of shape (%d, %d)" % (k, dt, tile.cols[k], N))
+        lds[k] = _row_major_ld(B, "B[%d]" % k)
+        ptrs[k] = B.data_ptr()
+    if C is None:
+        if accumulate:
+            raise ValueError("accumulate needs C")
+        C = torch.empty(tile.rows, N, dtype=dt, device=Bs[0].device)
+    if C.dtype != dt or C.shape != (tile.rows, N):
+        raise ValueError("C must be %s of shape (%d, %d)" % (dt, tile.rows, N))
+    ldc = _row_major_ld(C, "C")
+    if workspace is None:
+        workspace = tile.workspace(N, "fwd")
+    ws_ptr = workspace.data_ptr() if workspace is not None else None
+    ws_n = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    check(lib().spmm_fwd(tile.handle, k_offset, ptrs, lds, _DTYPES[dt], C.data_ptr(), ldc, _DTYPES[dt], N,
+                         1 if accumulate else 0, ws_ptr, ws_n, _stream_ptr(stream)))
+    return C
+
+
+def spmm_bwd(tile: Tile, dC: torch.Tensor, B: torch.Tensor, want_dA: bool = True, want_dB: bool = True,
+             dA: Optional[torch.Tensor] = None, dB: Optional[torch.Tensor] = None,
+             workspace: Optional[torch.Tensor] = None,
+             stream: Optional[torch.cuda.Stream] = None) -> Tuple[Optional[torch.Tensor], Optional[torch.Tensor]]:
+    """(dA on A's pattern, dB = A^T dC) for a single-tile handle built with transpose=True."""
+    if tile.num_k != 1:
+        raise ValueError("spmm_bwd needs a single-tile handle")
+    N = dC.shape[1]
+    if dC.dtype != torch.float32 or B.dtype != torch.float32:
+        raise ValueError("spmm_bwd takes float32 dC and B")
+    if dC.shape != (tile.rows, N) or B.shape != (tile.cols[0], N):
+        raise ValueError("dC must be (%d, N) and B (%d, N)" % (tile.rows, tile.cols[0]))
+    lddc = _row_major_ld(dC, "dC")
+    ldb = _row_major_ld(B, "B")
+    if want_dA and dA is None:
+        dA = torch.empty(tile.nnz[0], dtype=torch.float32, device=dC.device)
+    if want_dB and dB is None:
+        dB = torch.empty(tile.cols[0], N, dtype=torch.float32, device=dC.device)
+    lddb = _row_major_ld(dB, "dB") if want_dB else 0
+    if workspace is None and want_dB:
+        workspace = tile.workspace(N, "bwd")
+    ws_ptr = workspace.data_ptr() if workspace is not None else None
+    ws_n = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    check(lib().spmm_bwd(tile.handle, dC.data_ptr(), lddc, B.data_ptr(), ldb, N,
+                         dA.data_ptr() if want_dA else None, dB.data_ptr() if want_dB else None, lddb,
+                         ws_ptr, ws_n, _stream_ptr(stream)))
+    return (dA if want_dA else None), (dB if want_dB else None)

@@ -1,0 +1,112 @@
+"""libspmm loads on a machine without a GPU, exports every entry point its header
+declares, and rejects bad arguments before touching the HIP runtime."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2311_18141_amd import _lib
+from paper_2311_18141_amd._lib import SpmmCsr, SpmmTileOpts
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spmm.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(spmm_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    names = declared_functions()
+    assert "spmm_fwd" in names and "spmm_bwd" in names and "spmm_tile_create" in names
+    for n in names:
+        assert hasattr(L, n), n
+    # and the binding declares every one of them
+    assert set(names) <= set(_lib.EXPORTS), set(names) - set(_lib.EXPORTS)
+
+
+def test_status_strings():
+    L = _lib.lib()
+    for code, name in _lib.STATUS_NAMES.items():
+        assert L.spmm_status_string(code).decode() == name
+    assert L.spmm_status_string(99).decode() == "unknown spmm_status"
+
+
+def _create(rows, num_k, tiles, opts=None):
+    L = _lib.lib()
+    h = ctypes.c_void_p(1234)
+    st = L.spmm_tile_create(rows, num_k, tiles, ctypes.byref(opts) if opts is not None else None, None,
+                            ctypes.byref(h))
+    return st, h.value, L.spmm_last_error().decode()
+
+
+def _tiles(n=1, cols=10, nnz=5, ptr=0x1000):
+    arr = (SpmmCsr * n)()
+    for k in range(n):
+        arr[k].cols, arr[k].nnz = cols, nnz
+        arr[k].rowptr, arr[k].colind, arr[k].values = ptr, ptr, ptr
+    return arr
+
+
+@pytest.mark.parametrize("case,expect", [
+    ("null_out", 1), ("neg_rows", 1), ("huge_rows", 1), ("k0", 1), ("k17", 1), ("null_tiles", 1),
+    ("neg_cols", 1), ("neg_nnz", 1), ("big_nnz", 3), ("null_rowptr", 1), ("null_colind", 1),
+    ("bad_flags", 1), ("transpose_k2", 3), ("neg_long_row", 1),
+])
+def test_create_argument_errors(case, expect):
+    L = _lib.lib()
+    t = _tiles()
+    opts = SpmmTileOpts()
+    rows, K = 4, 1
+    if case == "null_out":
+        assert L.spmm_tile_create(4, 1, t, None, None, None) == expect
+        return
+    if case == "neg_rows":
+        rows = -1
+    elif case == "huge_rows":
+        rows = 1 << 31
+    elif case == "k0":
+        K = 0
+    elif case == "k17":
+        K = 17
+        t = _tiles(17)
+    elif case == "null_tiles":
+        t = None
+    elif case == "neg_cols":
+        t[0].cols = -1
+    elif case == "neg_nnz":
+        t[0].nnz = -5
+    elif case == "big_nnz":
+        t[0].nnz = 1 << 31
+    elif case == "null_rowptr":
+        t[0].rowptr = None
+    elif case == "null_colind":
+        t[0].colind = None
+    elif case == "bad_flags":
+        opts.flags = 0x80
+    elif case == "transpose_k2":
+        t = _tiles(2)
+        K = 2
+        opts.flags = _lib.SPMM_TILE_TRANSPOSE
+    elif case == "neg_long_row":
+        opts.long_row = -3
+    st, h, msg = _create(rows, K, t, opts)
+    assert st == expect, (case, st, msg)
+    assert h is None
+    assert msg
+
+
+def test_null_handle_calls():
+    L = _lib.lib()
+    n = ctypes.c_size_t()
+    assert L.spmm_tile_destroy(None) == 1
+    assert L.spmm_tile_get_stats(None, None) == 1
+    assert L.spmm_fwd_workspace_bytes(None, 8, ctypes.byref(n)) == 1
+    assert L.spmm_bwd_workspace_bytes(None, 8, ctypes.byref(n)) == 1
+    assert L.spmm_fwd(None, 0, None, None, 0, None, 8, 0, 8, 0, None, 0, None) == 1
+    assert L.spmm_bwd(None, None, 8, None, 8, 8, None, None, 8, None, 0, None) == 1
+    assert L.spmm_tile_export_transpose(None, None, None, None, None) == 1

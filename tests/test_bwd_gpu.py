@@ -1,0 +1,173 @@
+"""Backward parity: transposed structure (bit-exact), SDDMM dA and dB = A^T dC against
+the FP64 oracle, the autograd Function, and finite differences."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import compare
+from paper_2311_18141_amd import ops
+from paper_2311_18141_amd.autograd import SpMMFunction
+
+import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _rng(s):
+    return np.random.Generator(np.random.PCG64(s))
+
+
+def _case(name):
+    rng = _rng(hash(name) % 1000)
+    if name == "empty":
+        return synth.CSR(7, 5, np.zeros(8, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    if name == "one_col":
+        L = rng.integers(0, 2, size=300)
+        return synth.random_csr(300, 1, L, rng)
+    if name == "one_row":
+        return synth.random_csr(1, 5000, np.array([4000]), rng)
+    if name == "hot_column":
+        L = rng.integers(0, 30, size=20000)
+        A = synth.random_csr(20000, 700, L, rng)
+        return A
+    if name == "powerlaw":
+        return synth.powerlaw_csr(1 << 15, 1 << 15, 32, 8192, seed=5)
+    if name == "wide":
+        L = rng.integers(0, 12, size=4000)
+        return synth.random_csr(4000, 1 << 20, L, rng)
+    if name == "rmat":
+        return synth.rmat_row_block(13, 16, 2, 0, seed=6).tiles[0]
+    raise KeyError(name)
+
+
+CASES = ["empty", "one_col", "one_row", "hot_column", "powerlaw", "wide", "rmat"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_transpose_bit_exact(name):
+    G.note("transpose %s" % name)
+    A = _case(name)
+    tile = G.make_tile([A], transpose=True)
+    rpT, ciT, perm = ops.spmm_tile_export_transpose(tile)
+    torch.cuda.synchronize()
+    r_rpT, r_ciT, r_perm = oracle.transpose(A.rowptr, A.colind, A.cols)
+    assert np.array_equal(rpT.cpu().numpy(), r_rpT)
+    assert np.array_equal(ciT.cpu().numpy(), r_ciT)
+    assert np.array_equal(perm.cpu().numpy(), r_perm)
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("N", [32, 128])
+def test_backward_vs_oracle(name, N):
+    G.note("backward %s N=%d" % (name, N))
+    A = _case(name)
+    rng = _rng(N + len(name))
+    B = synth.dense(A.cols, N, rng, "normal")
+    dC = synth.dense(A.rows, N, rng, "normal")
+    tile = G.make_tile([A], transpose=True, long_row=512, segment=256)
+    dA, dB = ops.spmm_bwd(tile, G.dense_dev(dC), G.dense_dev(B))
+    torch.cuda.synchronize()
+    rA, SA = oracle.sddmm(A.rowptr, A.colind, dC, B)
+    st = compare.fp32_stats(dA.cpu().numpy(), rA, SA, n_terms=np.full(A.nnz, N))
+    assert compare.fp32_ok(st), st
+    rB, SB = oracle.spmm_t(A.rowptr, A.colind, A.values, A.cols, dC)
+    cnt = np.bincount(A.colind, minlength=A.cols)
+    G.assert_fp32_close(G.host_f32(dB), rB, SB, cnt, what="dB")
+
+
+@pytest.mark.parametrize("split", [False, True])
+def test_backward_integer_exact(split):
+    G.note("backward_integer_exact split=%s" % split)
+    rng = _rng(90 + split)
+    M, K, N = 5000, 3000, 64
+    L = rng.integers(0, 40, size=M)
+    L[[10, 20]] = [2900, 1500]
+    A = synth.random_csr(M, K, L, rng, "int8")
+    B = synth.dense(K, N, rng, "int8")
+    dC = synth.dense(M, N, rng, "int8")
+    kw = dict(long_row=8, segment=4) if split else {}
+    tile = G.make_tile([A], transpose=True, **kw)
+    dA, dB = ops.spmm_bwd(tile, G.dense_dev(dC), G.dense_dev(B))
+    torch.cuda.synchronize()
+    rA, _ = oracle.sddmm(A.rowptr, A.colind, dC, B)
+    rB, _ = oracle.spmm_t(A.rowptr, A.colind, A.values, K, dC)
+    assert np.array_equal(dA.cpu().numpy().astype(np.float64), rA)
+    assert np.array_equal(dB.cpu().numpy().astype(np.float64), rB)
+
+
+def test_autograd_function():
+    G.note("autograd_function")
+    rng = _rng(95)
+    A = synth.powerlaw_csr(4096, 3000, 16, 1024, seed=11)
+    B = synth.dense(A.cols, 64, rng, "normal")
+    dC = synth.dense(A.rows, 64, rng, "normal")
+    rp, ci, va, _ = G.to_dev(A)
+    tile = ops.spmm_tile_create(A.rows, [(rp, ci, va, A.cols)], validate=True, transpose=True)
+    values = va.requires_grad_(True)
+    Bt = G.dense_dev(B).requires_grad_(True)
+    C = SpMMFunction.apply(values, Bt, tile)
+    C.backward(G.dense_dev(dC))
+    rC, SC = G.oracle_fwd([A], [B])
+    G.assert_fp32_close(G.host_f32(C.detach()), rC, SC, G.row_terms([A]))
+    rA, SA = oracle.sddmm(A.rowptr, A.colind, dC, B)
+    assert compare.fp32_ok(compare.fp32_stats(values.grad.cpu().numpy(), rA, SA))
+    rB, SB = oracle.spmm_t(A.rowptr, A.colind, A.values, A.cols, dC)
+    G.assert_fp32_close(G.host_f32(Bt.grad), rB, SB)
+    # needs_input_grad: only B
+    Bt.grad = None
+    values.grad = None
+    v2 = va.detach()
+    C2 = SpMMFunction.apply(v2, Bt, tile)
+    C2.backward(G.dense_dev(dC))
+    assert values.grad is None and Bt.grad is not None
+
+
+def test_finite_differences_scaled():
+    """C is linear in the values and in B, so central differences with h = 1 have no truncation error."""
+    G.note("finite_differences_scaled")
+    rng = _rng(96)
+    A = synth.powerlaw_csr(8192, 8192, 32, 2048, seed=12)
+    N = 128
+    B = synth.dense(A.cols, N, rng, "normal")
+    dC = synth.dense(A.rows, N, rng, "normal")
+    rp, ci, va, _ = G.to_dev(A)
+    tile = ops.spmm_tile_create(A.rows, [(rp, ci, va, A.cols)], validate=True, transpose=True)
+    Bd, dCd = G.dense_dev(B), G.dense_dev(dC)
+    dA, dB = ops.spmm_bwd(tile, dCd, Bd)
+    torch.cuda.synchronize()
+    dA = dA.cpu().numpy().astype(np.float64)
+    dB = dB.cpu().numpy().astype(np.float64)
+    _, SC = G.oracle_fwd([A], [B])
+    _, SA = oracle.sddmm(A.rowptr, A.colind, dC, B)
+    rowid = np.repeat(np.arange(A.rows), A.row_lengths())
+    ps = rng.choice(A.nnz, size=100, replace=False)
+    ps[0] = A.rowptr[np.argmax(A.row_lengths())]
+    for p in ps:
+        i = rowid[p]
+        v0 = va[p].item()
+        va[p] = v0 + 1.0
+        Cp = ops.spmm_fwd(tile, [Bd])[i].double().cpu().numpy()
+        va[p] = v0 - 1.0
+        Cm = ops.spmm_fwd(tile, [Bd])[i].double().cpu().numpy()
+        va[p] = v0
+        fd = float(np.dot(dC[i].astype(np.float64), (Cp - Cm) / 2.0))
+        bound = 1e-5 * (float(np.dot(np.abs(dC[i]), SC[i])) + SA[p])
+        assert abs(fd - dA[p]) <= bound, (p, fd, dA[p], bound)
+    cnt = np.bincount(A.colind, minlength=A.cols)
+    js = rng.choice(A.cols, size=40, replace=False)
+    js[0] = int(np.argmax(cnt))
+    _, SB = oracle.spmm_t(A.rowptr, A.colind, A.values, A.cols, dC, out_rows=js.astype(np.int64))
+    for t, j in enumerate(js):
+        n = int(rng.integers(0, N))
+        b0 = Bd[j, n].item()
+        Bd[j, n] = b0 + 1.0
+        Cp = ops.spmm_fwd(tile, [Bd])[:, n].double()
+        Bd[j, n] = b0 - 1.0
+        Cm = ops.spmm_fwd(tile, [Bd])[:, n].double()
+        Bd[j, n] = b0
+        fd = float((dCd[:, n].double() * (Cp - Cm)).sum().item() / 2.0)
+        rows_j = rowid[A.colind == j]
+        bound = 1e-5 * (float(np.dot(np.abs(dC[rows_j, n]), SC[rows_j, n])) + SB[t, n])
+        assert abs(fd - dB[j, n]) <= bound + 1e-30, (j, n, fd, dB[j, n], bound)

@@ -1,0 +1,204 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py times (default
+handle options), on sampled outputs the oracle computes one by one, plus properties that
+hold at any size (bit-exact transposed structure, finite differences)."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import compare
+from paper_2311_18141_amd import ops
+
+import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _rng(s):
+    return np.random.Generator(np.random.PCG64(s))
+
+
+def _sample_rows(lens, rng, n=2000):
+    rows = len(lens)
+    pick = [rng.choice(rows, size=min(n, rows), replace=False), np.argsort(lens)[-50:]]
+    empty = np.flatnonzero(lens == 0)
+    if empty.size:
+        pick.append(empty[:20])
+    return np.unique(np.concatenate(pick)).astype(np.int64)
+
+
+def test_uniform_4096_n32_full():
+    G.note("full uniform 4096 N=32")
+    A = synth.uniform_csr(4096, 4096, 16, seed=1)
+    B = synth.dense(4096, 32, synth.streams(1)[2])
+    tile = G.make_tile([A])
+    got = G.host_f32(G.fwd(tile, [G.dense_dev(B)]))
+    ref, S = G.oracle_fwd([A], [B])
+    st = G.assert_fp32_close(got, ref, S, G.row_terms([A]))
+    print("uniform4096 N=32:", st)
+
+
+def test_rmat22_rowblock0_kloop_n128():
+    """One GPU's share of a 4x4 stationary-C SpMM: row block 0, 4 k-tiles, N = 128."""
+    t0 = time.time()
+    g = synth.rmat_row_block(22, 16, 4, 0, seed=2)
+    G.note("full rmat22 row block 0 (generated in %.0f s)" % (time.time() - t0))
+    rs = synth.streams(2)
+    Bs = [synth.dense(t.cols, 128, rs[2]) for t in g.tiles]
+    tile = G.make_tile(g.tiles)
+    st = tile.stats()
+    assert st["nnz_total"] == sum(t.nnz for t in g.tiles)
+    Bd = [G.dense_dev(b) for b in Bs]
+    C = G.fwd(tile, Bd)
+    lens = G.row_terms(g.tiles)
+    rows = _sample_rows(lens, _rng(21))
+    got = C[torch.from_numpy(rows).to(C.device)].cpu().numpy()
+    ref, S = G.oracle_fwd(g.tiles, Bs, rows=rows)
+    res = G.assert_fp32_close(got, ref, S, lens[rows], what="rmat22")
+    print("rmat22 k-loop:", res, "sampled rows", rows.size, "imbalance", g.imbalance)
+    # Algorithm 2's k offset: another order gives a result within the same bound.
+    C2 = G.fwd(tile, Bd, k_offset=3)[torch.from_numpy(rows).to(C.device)].cpu().numpy()
+    ref2, S2 = G.oracle_fwd(g.tiles, Bs, k_offset=3, rows=rows)
+    G.assert_fp32_close(C2, ref2, S2, lens[rows], what="rmat22 offset 3")
+
+
+@pytest.fixture(scope="module")
+def powerlaw2m():
+    t0 = time.time()
+    A = synth.powerlaw_csr(1 << 21, 1 << 21, 32, 65536, seed=3)
+    rs = synth.streams(3)
+    B = synth.dense(A.cols, 128, rs[2], "normal")
+    dC = synth.dense(A.rows, 128, rs[3], "normal")
+    G.note("full powerlaw 2M generated in %.0f s" % (time.time() - t0))
+    rp, ci, va, _ = G.to_dev(A)
+    tile = ops.spmm_tile_create(A.rows, [(rp, ci, va, A.cols)], validate=True, transpose=True)
+    return A, B, dC, tile, va
+
+
+def test_powerlaw2m_transpose_bit_exact(powerlaw2m):
+    A, B, dC, tile, va = powerlaw2m
+    G.note("full powerlaw 2M transpose")
+    rpT, ciT, perm = ops.spmm_tile_export_transpose(tile)
+    torch.cuda.synchronize()
+    r = oracle.transpose(A.rowptr, A.colind, A.cols)
+    assert np.array_equal(rpT.cpu().numpy(), r[0])
+    assert np.array_equal(ciT.cpu().numpy(), r[1])
+    assert np.array_equal(perm.cpu().numpy(), r[2])
+
+
+def test_powerlaw2m_fwd_bwd_sampled(powerlaw2m):
+    A, B, dC, tile, va = powerlaw2m
+    G.note("full powerlaw 2M fwd+bwd sampled")
+    Bd, dCd = G.dense_dev(B), G.dense_dev(dC)
+    C = G.fwd(tile, [Bd])
+    dA, dB = ops.spmm_bwd(tile, dCd, Bd)
+    torch.cuda.synchronize()
+    rng = _rng(31)
+    lens = A.row_lengths()
+    rows = _sample_rows(lens, rng)
+    ref, S = G.oracle_fwd([A], [B], rows=rows)
+    G.assert_fp32_close(C[torch.from_numpy(rows).to(C.device)].cpu().numpy(), ref, S, lens[rows], what="C")
+    ents = np.unique(np.concatenate([rng.choice(A.nnz, 1000, replace=False),
+                                     np.arange(A.rowptr[np.argmax(lens)], A.rowptr[np.argmax(lens)] + 50)]))
+    rA, SA = oracle.sddmm(A.rowptr, A.colind, dC, B, entries=ents.astype(np.int64))
+    gotA = dA[torch.from_numpy(ents).to(dA.device)].cpu().numpy()
+    st = compare.fp32_stats(gotA, rA, SA, n_terms=np.full(ents.size, 128))
+    assert compare.fp32_ok(st), st
+    cnt = np.bincount(A.colind, minlength=A.cols)
+    cols = np.unique(np.concatenate([rng.choice(A.cols, 1000, replace=False), np.argsort(cnt)[-20:]]))
+    rB, SB = oracle.spmm_t(A.rowptr, A.colind, A.values, A.cols, dC, out_rows=cols.astype(np.int64))
+    gotB = dB[torch.from_numpy(cols).to(dB.device)].cpu().numpy()
+    G.assert_fp32_close(gotB, rB, SB, cnt[cols], what="dB")
+
+
+def test_powerlaw2m_finite_differences(powerlaw2m):
+    """1,000 sampled entries of dA and 1,000 of dB against central differences (h = 1, exact for a
+    linear map up to the forward's rounding)."""
+    A, B, dC, tile, va = powerlaw2m
+    G.note("full powerlaw 2M finite differences")
+    Bd, dCd = G.dense_dev(B), G.dense_dev(dC)
+    dA, dB = ops.spmm_bwd(tile, dCd, Bd)
+    torch.cuda.synchronize()
+    rng = _rng(32)
+    lens = A.row_lengths()
+    top = int(np.argmax(lens))
+    ps = rng.choice(A.nnz, size=1000, replace=False)
+    ps[:10] = A.rowptr[top] + np.arange(10)
+    rowid = np.repeat(np.arange(A.rows), lens)
+    rows = rowid[ps]
+    _, SC = G.oracle_fwd([A], [B], rows=np.unique(rows).astype(np.int64))
+    SC = dict(zip(np.unique(rows).tolist(), SC))
+    _, SA = oracle.sddmm(A.rowptr, A.colind, dC, B, entries=ps.astype(np.int64))
+    dAh = dA[torch.from_numpy(ps).to(dA.device)].double().cpu().numpy()
+    C = torch.empty(A.rows, 128, device=Bd.device)
+    worst = 0.0
+    for t, p in enumerate(ps):
+        i = int(rows[t])
+        v0 = va[p].item()
+        va[p] = v0 + 1.0
+        Cp = ops.spmm_fwd(tile, [Bd], C=C)[i].double().cpu().numpy()
+        va[p] = v0 - 1.0
+        Cm = ops.spmm_fwd(tile, [Bd], C=C)[i].double().cpu().numpy()
+        va[p] = v0
+        fd = float(np.dot(dC[i].astype(np.float64), (Cp - Cm) / 2.0))
+        bound = 1e-5 * (float(np.dot(np.abs(dC[i]), SC[i])) + SA[t])
+        worst = max(worst, abs(fd - dAh[t]) / bound)
+        assert abs(fd - dAh[t]) <= bound, (p, fd, dAh[t], bound)
+    cnt = np.bincount(A.colind, minlength=A.cols)
+    js = rng.choice(A.cols, size=1000, replace=True)
+    js[:5] = np.argsort(cnt)[-5:]
+    ns = rng.integers(0, 128, size=1000)
+    _, SB = oracle.spmm_t(A.rowptr, A.colind, A.values, A.cols, dC, out_rows=np.unique(js).astype(np.int64))
+    SB = dict(zip(np.unique(js).tolist(), SB))
+    order = np.argsort(A.colind, kind="stable")
+    starts = np.concatenate([[0], np.cumsum(cnt)])
+    worst_b = 0.0
+    for j, n in zip(js, ns):
+        j, n = int(j), int(n)
+        b0 = Bd[j, n].item()
+        Bd[j, n] = b0 + 1.0
+        Cp = ops.spmm_fwd(tile, [Bd], C=C)[:, n].double()
+        Bd[j, n] = b0 - 1.0
+        Cm = ops.spmm_fwd(tile, [Bd], C=C)[:, n].double()
+        Bd[j, n] = b0
+        fd = float((dCd[:, n].double() * (Cp - Cm)).sum().item() / 2.0)
+        rows_j = rowid[order[starts[j]:starts[j + 1]]].astype(np.int64)
+        _, Sx = G.oracle_fwd([A], [B], rows=rows_j)
+        bound = 1e-5 * (float(np.dot(np.abs(dC[rows_j, n]), Sx[:, n])) + SB[j][n])
+        got = dB[j, n].item()
+        worst_b = max(worst_b, abs(fd - got) / max(bound, 1e-300))
+        assert abs(fd - got) <= bound + 1e-30, (j, n, fd, got, bound)
+    print("finite differences: worst |fd - dA|/bound %.3g, worst |fd - dB|/bound %.3g" % (worst, worst_b))
+
+
+def test_rmat23_n256_bf16_and_f32():
+    """BF16 B and C with FP32 accumulation next to the FP32 path on the same inputs."""
+    t0 = time.time()
+    A = synth.rmat_csr(23, 32, seed=5)
+    B = synth.dense(A.cols, 256, synth.streams(5)[2])
+    G.note("full rmat23 N=256 generated in %.0f s (nnz %d)" % (time.time() - t0, A.nnz))
+    tile = G.make_tile([A])
+    lens = A.row_lengths()
+    rows = _sample_rows(lens, _rng(51), n=1000)
+    ridx = None
+    Bd = G.dense_dev(B)
+    C32 = G.fwd(tile, [Bd])
+    ridx = torch.from_numpy(rows).to(C32.device)
+    got32 = C32[ridx].cpu().numpy()
+    del C32
+    ref, S = G.oracle_fwd([A], [B], rows=rows)
+    st32 = G.assert_fp32_close(got32, ref, S, lens[rows], what="fp32")
+    del Bd
+    Bh = G.dense_dev(B, torch.bfloat16)
+    C16 = G.fwd(tile, [Bh])
+    got16 = C16[ridx].float().cpu().numpy()
+    Bt = G.bf16_as_f32(B)
+    reft, St = G.oracle_fwd([A], [Bt], rows=rows)
+    st16 = G.assert_bf16_close(got16, reft, St, what="bf16 kernel-only")
+    total = compare.relative_stats(got16, ref, S)
+    print("rmat23 fp32:", st32)
+    print("rmat23 bf16 vs oracle(bf16(B)):", st16)
+    print("rmat23 bf16 vs oracle(B) [total error]:", total)

@@ -1,0 +1,262 @@
+"""Forward parity: libspmm's HIP path against the FP64 oracle on seeded inputs."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_2311_18141_amd import ops
+from paper_2311_18141_amd._lib import SpmmError
+
+import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _rng(s):
+    return np.random.Generator(np.random.PCG64(s))
+
+
+def _blockdiag_3x3(value_rng):
+    """All 2^9 patterns of a 3x3 block on the diagonal of a 1536 x 1536 tile, small-integer values."""
+    rows, cols, vals = [], [], []
+    for m in range(512):
+        for r in range(3):
+            for c in range(3):
+                if (m >> (3 * r + c)) & 1:
+                    rows.append(3 * m + r)
+                    cols.append(3 * m + c)
+                    v = int(value_rng.integers(-4, 5)) or 1
+                    vals.append(v)
+    rows = np.array(rows)
+    lengths = np.bincount(rows, minlength=1536)
+    return synth.CSR(1536, 1536, synth.rowptr_from_lengths(lengths), np.array(cols, np.int32),
+                     np.array(vals, np.float32))
+
+
+@pytest.mark.parametrize("N", [1, 32, 33, 64, 128, 256])
+def test_all_3x3_patterns_exact(N):
+    G.note("all_3x3_patterns N=%d" % N)
+    rng = _rng(100 + N)
+    A = _blockdiag_3x3(rng)
+    B = synth.dense(1536, N, rng, "int4")
+    tile = G.make_tile([A], validate=True)
+    got = G.host_f32(G.fwd(tile, [G.dense_dev(B)]))
+    ref, _ = G.oracle_fwd([A], [B])
+    assert np.array_equal(got.astype(np.float64), ref)
+
+
+@pytest.mark.parametrize("M", [1, 2, 63, 64, 65])
+@pytest.mark.parametrize("N", [1, 32, 33, 64, 128, 256])
+def test_small_shapes(M, N):
+    G.note("small_shapes M=%d N=%d" % (M, N))
+    rng = _rng(M * 1000 + N)
+    lengths = rng.integers(0, 41, size=M)
+    lengths[rng.random(M) < 0.25] = 0
+    A = synth.random_csr(M, 97, lengths, rng)
+    B = synth.dense(97, N, rng)
+    tile = G.make_tile([A], validate=True)
+    got = G.host_f32(G.fwd(tile, [G.dense_dev(B)]))
+    ref, S = G.oracle_fwd([A], [B])
+    G.assert_fp32_close(got, ref, S, G.row_terms([A]), what="M=%d N=%d" % (M, N))
+
+
+@pytest.mark.parametrize("N", [32, 128])
+@pytest.mark.parametrize("split", [False, True])
+def test_integer_exact_with_long_rows(N, split):
+    """Integer values and B in [-8, 8]: every partial sum is an integer below 2^24, so any order is exact."""
+    G.note("integer_exact N=%d split=%s" % (N, split))
+    rng = _rng(7 + N + split)
+    M, K = 3001, 60000
+    lengths = rng.integers(0, 200, size=M)
+    lengths[rng.random(M) < 0.2] = 0
+    lengths[[5, 1000, 2999]] = [5000, 50000, 1025]
+    A = synth.random_csr(M, K, lengths, rng, "int8")
+    B = synth.dense(K, N, rng, "int8")
+    kw = dict(long_row=16, segment=8) if split else {}
+    tile = G.make_tile([A], validate=True, **kw)
+    st = tile.stats()
+    assert st["max_row"] == 50000 and st["long_rows"] >= 2
+    got = G.host_f32(G.fwd(tile, [G.dense_dev(B)]))
+    ref, _ = G.oracle_fwd([A], [B])
+    assert np.array_equal(got.astype(np.float64), ref)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_identity_and_permutation_exact(dtype):
+    G.note("identity_permutation %s" % dtype)
+    rng = _rng(31)
+    n, N = 5000, 128
+    B = synth.dense(n, N, rng)
+    Bd = G.dense_dev(B, dtype)
+    eye = synth.CSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.ones(n, np.float32))
+    got = G.fwd(G.make_tile([eye]), [Bd])
+    assert torch.equal(got, Bd)
+    pi = rng.permutation(n).astype(np.int32)
+    P = synth.CSR(n, n, np.arange(n + 1, dtype=np.int32), pi, np.ones(n, np.float32))
+    got = G.fwd(G.make_tile([P]), [Bd])
+    assert torch.equal(got, Bd[torch.from_numpy(pi).long().to(Bd.device)])
+
+
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_k_tiles_and_offsets(K):
+    """Section 2.1 / Algorithm 2: a tile row of K k-tiles; every k offset gives the untiled product."""
+    G.note("k_tiles K=%d" % K)
+    rng = _rng(40 + K)
+    M, cols, N = 2049, 3001, 64
+    lengths = rng.integers(0, 120, size=M)
+    lengths[[0, 77]] = [2500, 1800]
+    full = synth.random_csr(M, cols, lengths, rng, "int8")
+    B = synth.dense(cols, N, rng, "int8")
+    ts = -(-cols // K)
+    rowid = np.repeat(np.arange(M), full.row_lengths())
+    tiles, Bs = [], []
+    for k in range(K):
+        c0, c1 = k * ts, min(cols, (k + 1) * ts)
+        sel = (full.colind >= c0) & (full.colind < c1)
+        tiles.append(synth.CSR(M, c1 - c0, synth.rowptr_from_lengths(np.bincount(rowid[sel], minlength=M)),
+                               (full.colind[sel] - c0).astype(np.int32), full.values[sel].copy()))
+        Bs.append(np.ascontiguousarray(B[c0:c1]))
+    tile = G.make_tile(tiles, validate=True, long_row=256, segment=128)
+    Bd = [G.dense_dev(b) for b in Bs]
+    ref, _ = G.oracle_fwd([full], [B])
+    outs = []
+    for off in range(K + 1):
+        got = G.fwd(tile, Bd, k_offset=off)
+        assert np.array_equal(G.host_f32(got).astype(np.float64), ref), off
+        outs.append(got)
+    # real-valued inputs: within tolerance for every offset
+    fv = [synth.CSR(t.rows, t.cols, t.rowptr, t.colind, synth.uniform_pm1(rng, t.nnz)) for t in tiles]
+    Bf = [synth.dense(b.shape[0], N, rng) for b in Bs]
+    tile2 = G.make_tile(fv, long_row=256, segment=128)
+    Bfd = [G.dense_dev(b) for b in Bf]
+    for off in range(K):
+        got = G.host_f32(G.fwd(tile2, Bfd, k_offset=off))
+        ref2, S2 = G.oracle_fwd(fv, Bf, k_offset=off)
+        G.assert_fp32_close(got, ref2, S2, G.row_terms(fv), what="off=%d" % off)
+
+
+def test_accumulate_and_leading_dims():
+    G.note("accumulate_and_leading_dims")
+    rng = _rng(50)
+    M, K, N = 1000, 800, 96
+    lengths = rng.integers(0, 50, size=M)
+    lengths[3] = 3000 if K >= 3000 else K
+    A = synth.random_csr(M, K, lengths, rng)
+    B = synth.dense(K, N, rng)
+    C0 = synth.dense(M, N, rng)
+    tile = G.make_tile([A], long_row=100, segment=64)
+    Bd = G.dense_dev(B, ld=N + 8)
+    Cd = G.dense_dev(C0, ld=N + 4)
+    assert Bd.stride(0) == N + 8 and Cd.stride(0) == N + 4
+    G.fwd(tile, [Bd], C=Cd, accumulate=True)
+    ref, S = G.oracle_fwd([A], [B], accumulate=True, C0=C0)
+    G.assert_fp32_close(G.host_f32(Cd), ref, S + np.abs(C0), G.row_terms([A]) + 1)
+
+
+@pytest.mark.parametrize("N", [32, 128, 256])
+def test_bf16_storage(N):
+    """B and C in BF16, FP32 products and sums, C rounded once."""
+    G.note("bf16 N=%d" % N)
+    rng = _rng(60 + N)
+    M = K = 4096
+    lengths = rng.integers(0, 64, size=M)
+    lengths[[1, 2]] = [4000, 1500]
+    A = synth.random_csr(M, K, lengths, rng)
+    B = synth.dense(K, N, rng)
+    tile = G.make_tile([A], long_row=512, segment=256)
+    got = G.host_f32(G.fwd(tile, [G.dense_dev(B, torch.bfloat16)]))
+    Bt = G.bf16_as_f32(B)
+    ref, S = G.oracle_fwd([A], [Bt])
+    G.assert_bf16_close(got, ref, S)
+    # small integers stay exact in BF16 (|C| <= 64, row length <= 4)
+    Ai = synth.random_csr(M, K, rng.integers(0, 5, size=M), rng, "int4")
+    Bi = synth.dense(K, N, rng, "int4")
+    got = G.host_f32(G.fwd(G.make_tile([Ai]), [G.dense_dev(Bi, torch.bfloat16)]))
+    ref, _ = G.oracle_fwd([Ai], [Bi])
+    assert np.array_equal(got.astype(np.float64), ref)
+
+
+@pytest.mark.parametrize("N", [32, 128])
+def test_workload_shapes_scaled(N):
+    """Scaled-down versions of the workloads: uniform, R-MAT row block, heavy-tailed rows."""
+    G.note("workload_shapes_scaled N=%d" % N)
+    cases = []
+    er = synth.uniform_csr(4096, 4096, 16, seed=1)
+    cases.append(("uniform", [er]))
+    g = synth.rmat_row_block(14, 16, 4, 0, seed=2)
+    cases.append(("rmat14_rowblock0", g.tiles))
+    pl = synth.powerlaw_csr(1 << 15, 1 << 15, 32, 4096, seed=3)
+    cases.append(("powerlaw", [pl]))
+    rng = _rng(70 + N)
+    for name, tiles in cases:
+        Bs = [synth.dense(t.cols, N, rng) for t in tiles]
+        tile = G.make_tile(tiles, validate=True)
+        got = G.host_f32(G.fwd(tile, [G.dense_dev(b) for b in Bs]))
+        ref, S = G.oracle_fwd(tiles, Bs)
+        G.assert_fp32_close(got, ref, S, G.row_terms(tiles), what=name)
+
+
+def test_deterministic_and_graph_replay():
+    G.note("deterministic_and_graph_replay")
+    rng = _rng(80)
+    A = synth.powerlaw_csr(1 << 14, 1 << 14, 32, 8192, seed=8)
+    B = synth.dense(A.cols, 128, rng, "normal")
+    tile = G.make_tile([A], long_row=256, segment=128)
+    Bd = G.dense_dev(B)
+    C1 = G.fwd(tile, [Bd]).clone()
+    C2 = G.fwd(tile, [Bd]).clone()
+    assert torch.equal(C1, C2)
+    Cg = torch.empty_like(C1)
+    ws = tile.workspace(128)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ops.spmm_fwd(tile, [Bd], C=Cg, workspace=ws)       # warm up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ops.spmm_fwd(tile, [Bd], C=Cg, workspace=ws)
+    for r in range(5):
+        Cg.fill_(float("nan"))
+        _ = (Bd * 2).sum()                                  # unrelated eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Cg, C1), r
+
+
+@pytest.mark.parametrize("case", ["first_not_zero", "decreasing", "last_not_nnz", "col_out_of_range",
+                                  "unsorted", "duplicate"])
+def test_validation_rejects_bad_csr(case):
+    G.note("validation %s" % case)
+    rp = np.array([0, 2, 4, 6], np.int32)
+    ci = np.array([0, 3, 1, 2, 0, 4], np.int32)
+    va = np.ones(6, np.float32)
+    if case == "first_not_zero":
+        rp = np.array([1, 2, 4, 6], np.int32)
+    elif case == "decreasing":
+        rp = np.array([0, 4, 2, 6], np.int32)
+    elif case == "last_not_nnz":
+        rp = np.array([0, 2, 4, 5], np.int32)
+    elif case == "col_out_of_range":
+        ci = np.array([0, 3, 1, 2, 0, 5], np.int32)
+    elif case == "unsorted":
+        ci = np.array([3, 0, 1, 2, 0, 4], np.int32)
+    elif case == "duplicate":
+        ci = np.array([0, 3, 2, 2, 0, 4], np.int32)
+    A = synth.CSR(3, 5, rp, ci, va)
+    with pytest.raises(SpmmError) as e:
+        G.make_tile([A], validate=True)
+    assert e.value.status == 2
+
+
+def test_forward_argument_errors():
+    G.note("forward_argument_errors")
+    A = synth.uniform_csr(64, 64, 4, seed=9)
+    tile = G.make_tile([A], long_row=2, segment=1)
+    B = G.dense_dev(synth.dense(64, 32, _rng(1)))
+    with pytest.raises(SpmmError) as e:
+        ops.spmm_fwd(tile, [B], workspace=torch.empty(4, dtype=torch.uint8, device=G.DEV))
+    assert e.value.status == 4
+    with pytest.raises(ValueError):
+        ops.spmm_fwd(tile, [B, B])
