@@ -35,6 +35,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+HANDLE_OPTS = {}
 
 
 def _log(msg):
@@ -101,7 +102,7 @@ class TileRowForward(Workload):
         self.dev_tiles = [(torch.from_numpy(t.rowptr).to(dev), torch.from_numpy(t.colind).to(dev),
                            torch.from_numpy(t.values).to(dev), t.cols) for t in self.tiles]
         self.B = [torch.from_numpy(b).to(tdt).to(dev) for b in self.Bh]
-        self.tile = ops.spmm_tile_create(self.tiles[0].rows, self.dev_tiles, validate=True)
+        self.tile = ops.spmm_tile_create(self.tiles[0].rows, self.dev_tiles, validate=True, **HANDLE_OPTS)
         self.C = torch.empty(self.tiles[0].rows, self.N, dtype=tdt, device=dev)
         self.ws = self.tile.workspace(self.N)
         nnz = sum(t.nnz for t in self.tiles)
@@ -156,7 +157,7 @@ class ForwardBackward(Workload):
         dev = "cuda:0"
         t = (torch.from_numpy(self.A.rowptr).to(dev), torch.from_numpy(self.A.colind).to(dev),
              torch.from_numpy(self.A.values).to(dev), self.A.cols)
-        self.tile = ops.spmm_tile_create(self.A.rows, [t], validate=True, transpose=True)
+        self.tile = ops.spmm_tile_create(self.A.rows, [t], validate=True, transpose=True, **HANDLE_OPTS)
         self.B = torch.from_numpy(self.Bh).to(dev)
         self.dC = torch.from_numpy(self.dCh).to(dev)
         self.C = torch.empty(self.A.rows, self.N, device=dev)
@@ -200,9 +201,36 @@ class ForwardBackward(Workload):
                            % (r, len(cols), A.rows))
 
 
+class CopyCalibration(Workload):
+    """A plain device copy of 1 GiB: the reference against which HBM counters are scaled."""
+
+    def __init__(self):
+        self.name = "copy_1gib"
+        self.kernel = "device copy (torch copy_)"
+        self.config = {"workload": "copy_1gib", "bytes_read": 1 << 30, "bytes_written": 1 << 30}
+
+    def setup(self):
+        import torch
+        self.x = torch.ones(1 << 28, device="cuda:0")
+        self.y = torch.empty_like(self.x)
+        self.flops = 0.0
+        self.alg_bytes = float(2 << 30)
+
+    def step(self):
+        self.y.copy_(self.x)
+
+    def cpu_sample(self):
+        x = np.ones(1 << 26, dtype=np.float32)
+        t0 = time.perf_counter()
+        y = x.copy()
+        dt = time.perf_counter() - t0
+        return 0.0, dt, "numpy copy of 256 MiB (%.0f)" % float(y[0])
+
+
 def workloads():
     import synth
     return {
+        "copy_1gib": lambda: CopyCalibration(),
         "rmat22_rowblock0_4x4_n128": lambda: TileRowForward(
             "rmat22_rowblock0_4x4_n128",
             lambda: synth.rmat_row_block(22, 16, 4, 0, seed=2).tiles, 128, "f32",
@@ -231,7 +259,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat22_rowblock0_4x4_n128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--long-row", type=int, default=0, help="split-row threshold (0 = library default)")
+    ap.add_argument("--segment", type=int, default=0, help="non-zeros per split unit (0 = library default)")
     args = ap.parse_args()
+    HANDLE_OPTS.update(long_row=args.long_row, segment=args.segment)
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the stationary-C tile row is "
               "one GPU's share); run with --gpus 1", file=sys.stderr)
@@ -262,7 +293,7 @@ def main():
     ms_total = t_all0.elapsed_time(t_all1)
     per = [a.elapsed_time(b) for a, b in ev]
     ms_step = ms_total / args.steps
-    value = wl.flops / (ms_step * 1e-3) / 1e9
+    value = wl.flops / (ms_step * 1e-3) / 1e9 if wl.flops else wl.alg_bytes / (ms_step * 1e-3) / 1e9
     avg_kernel_ms = float(np.mean(per))
     achieved = wl.alg_bytes / (avg_kernel_ms * 1e-3) / 1e9
     _log("timed %d steps: %.4f ms/step (per-step events mean %.4f, min %.4f, max %.4f)"

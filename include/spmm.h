@@ -116,6 +116,34 @@ spmm_status spmm_tile_get_stats(spmm_tile_t tile, spmm_tile_stats* out /* host *
 spmm_status spmm_tile_export_transpose(spmm_tile_t tile, int32_t* rowptrT, int32_t* colindT,
                                        int32_t* perm, void* stream);
 
+/* Forward kernel variants.  A handle keeps one variant per (N, dtype); without an
+   entry the library picks by a fixed rule.  These entry points exist for tuning and
+   tests; results of every variant agree within the tolerance of the operation (and
+   bit-for-bit on integer-valued inputs). */
+#define SPMM_KERNEL_AUTO 0
+#define SPMM_KERNEL_ROWSPLIT 1   /* a group of `lanes` lanes owns one row and a column window */
+#define SPMM_KERNEL_STREAM 2     /* a wave streams the non-zeros of 64 consecutive rows */
+typedef struct {
+  int32_t kind;    /* SPMM_KERNEL_* */
+  int32_t lanes;   /* ROWSPLIT: lanes per row, 4..64, power of two; 0 = library choice */
+  int32_t vec;     /* elements per lane per load: 1, 2, 4 (and 8 for BF16); 0 = widest aligned */
+} spmm_variant;
+
+/* Set (v != NULL) or clear (v == NULL) the variant used for width N and `dtype`.
+   A variant whose vector width does not fit a call's alignment falls back to the
+   library's choice for that call.  Errors: INVALID_ARG (bad field values, table of
+   16 entries full). */
+spmm_status spmm_tile_set_variant(spmm_tile_t tile, int64_t N, spmm_dtype dtype, const spmm_variant* v);
+
+/* Time the forward variants (and, with tune_plan != 0, split thresholds, which
+   rebuilds the handle's split-row plan) on the caller's real operands and keep the
+   fastest for (N, dtype).  Synchronous; allocates its own scratch; overwrites C.
+   After it returns, query spmm_fwd_workspace_bytes again (the plan may have
+   changed).  `chosen` (nullable) receives the winner.  Errors: as spmm_fwd, ALLOC. */
+spmm_status spmm_tile_autotune(spmm_tile_t tile, int64_t N, spmm_dtype dtype, const void* const* B,
+                               const int64_t* ldb, void* C, int64_t ldc, int tune_plan, void* stream,
+                               spmm_variant* chosen /* host */);
+
 /* Workspace (device bytes) spmm_fwd needs for this handle at width N. */
 spmm_status spmm_fwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes /* host */);
 
@@ -147,6 +175,43 @@ spmm_status spmm_bwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes /* 
 spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* B, int64_t ldb,
                      int64_t N, float* dA_values, float* dB, int64_t lddb, void* workspace,
                      size_t ws_bytes, void* stream);
+
+/*
+ * Batched launch: many independent single-tile products C_t = [C_t] + A_t B_t in
+ * one persistent kernel (plus a small reset kernel before it and, when some tile
+ * has split rows, a fix-up kernel after it).
+ *
+ * spmm_batch_create builds, synchronously, the work list: items of 64 rows of one
+ * tile and one column window (and the split-row units of each tile's plan), with
+ * each tile's kernel variant taken from its handle's entry for (N_t, dtype) (set
+ * by spmm_tile_autotune or spmm_tile_set_variant) or from a fixed rule, sorted by
+ * descending cost.  Every tile must be a single-tile handle (num_k = 1) on the
+ * current device, and must outlive the batch.  The batch allocates its own device
+ * memory (work list, claim counter).  Errors: INVALID_ARG, UNSUPPORTED (num_k > 1),
+ * ALLOC, HIP.
+ */
+typedef struct spmm_batch_s* spmm_batch_t;
+spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles /* host, count */,
+                              const int64_t* N /* host, count */, spmm_dtype dtype, void* stream,
+                              spmm_batch_t* out /* host */);
+spmm_status spmm_batch_destroy(spmm_batch_t batch);
+/* Workspace (device bytes) spmm_batched needs: FP32 partial rows of split rows. */
+spmm_status spmm_batch_workspace_bytes(spmm_batch_t batch, size_t* bytes /* host */);
+/* The variant the batch uses for tile t (kind STREAM or ROWSPLIT; lanes, vec). */
+spmm_status spmm_batch_get_variant(spmm_batch_t batch, int t, spmm_variant* out /* host */);
+
+/*
+ * Run the batch: B, ldb, C, ldc are DEVICE arrays of `count` entries (pointers to
+ * each tile's B_t (cols_t x N_t) and C_t (rows_t x N_t), row-major, in the batch's
+ * dtype, and their leading dimensions).  Every row of every B_t and C_t must start
+ * on a 16-byte boundary (base pointer and ld * element size multiples of 16); the
+ * library cannot check device-resident arguments.  Asynchronous; no host
+ * synchronisation, no allocation: capturable in a HIP graph, whose replays reset
+ * the claim counter by a kernel.  Calls on one batch must not overlap (they share
+ * the claim counter and the workspace).  Errors: INVALID_ARG, WORKSPACE, HIP.
+ */
+spmm_status spmm_batched(spmm_batch_t batch, const void* const* B, const int64_t* ldb, void* const* C,
+                         const int64_t* ldc, int accumulate, void* workspace, size_t ws_bytes, void* stream);
 
 const char* spmm_status_string(spmm_status status);
 const char* spmm_last_error(void);

@@ -42,6 +42,15 @@ class SpmmTileStats(ctypes.Structure):
                 ("long_rows_t", c_i64), ("segments_t", c_i64)]
 
 
+class SpmmVariant(ctypes.Structure):
+    _fields_ = [("kind", c_i32), ("lanes", c_i32), ("vec", c_i32)]
+
+
+SPMM_KERNEL_AUTO = 0
+SPMM_KERNEL_ROWSPLIT = 1
+SPMM_KERNEL_STREAM = 2
+
+
 class SpmmError(RuntimeError):
     def __init__(self, status: int, message: str):
         self.status = status
@@ -53,10 +62,17 @@ EXPORTS = {
     "spmm_tile_destroy": (c_int, [c_vp]),
     "spmm_tile_get_stats": (c_int, [c_vp, c_vp]),
     "spmm_tile_export_transpose": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "spmm_tile_set_variant": (c_int, [c_vp, c_i64, c_int, c_vp]),
+    "spmm_tile_autotune": (c_int, [c_vp, c_i64, c_int, c_vp, c_vp, c_vp, c_i64, c_int, c_vp, c_vp]),
     "spmm_fwd_workspace_bytes": (c_int, [c_vp, c_i64, c_vp]),
     "spmm_fwd": (c_int, [c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_i64, c_int, c_i64, c_int, c_vp, c_size, c_vp]),
     "spmm_bwd_workspace_bytes": (c_int, [c_vp, c_i64, c_vp]),
     "spmm_bwd": (c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, c_i64, c_vp, c_vp, c_i64, c_vp, c_size, c_vp]),
+    "spmm_batch_create": (c_int, [c_int, c_vp, c_vp, c_int, c_vp, c_vp]),
+    "spmm_batch_destroy": (c_int, [c_vp]),
+    "spmm_batch_workspace_bytes": (c_int, [c_vp, c_vp]),
+    "spmm_batch_get_variant": (c_int, [c_vp, c_int, c_vp]),
+    "spmm_batched": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_int, c_vp, c_size, c_vp]),
     "spmm_status_string": (ctypes.c_char_p, [c_int]),
     "spmm_last_error": (ctypes.c_char_p, []),
 }

@@ -7,6 +7,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <algorithm>
+#include <vector>
 
 #include "internal.hpp"
 #include "spmm.h"
@@ -44,6 +46,8 @@ hipError_t dalloc(T** p, int64_t n) {
 }
 
 struct Plan {
+  int32_t long_row = 0;
+  int32_t segment = 0;
   spmm::Seg* seg = nullptr;
   int64_t n_seg = 0;
   spmm::LongRow* lrow = nullptr;
@@ -76,6 +80,8 @@ spmm_status build_plan(const int32_t* const* rowptr, int K, int64_t rows, int32_
   unsigned long long* stats =
       reinterpret_cast<unsigned long long*>(tmp + ((sizeof(int32_t) * (size_t)n32 + 15) & ~(size_t)15));
   spmm_status st = SPMM_OK;
+  out->long_row = long_row;
+  out->segment = segment;
   auto run = [&]() -> spmm_status {
     HIP_TRY(hipMemsetAsync(totals, 0, 2 * sizeof(int32_t), s));
     HIP_TRY(hipMemsetAsync(stats, 0, 35 * sizeof(unsigned long long), s));
@@ -124,11 +130,6 @@ spmm_status build_plan(const int32_t* const* rowptr, int K, int64_t rows, int32_
 
 size_t partial_ld(int64_t N) { return (size_t)((N + 7) / 8 * 8); }
 
-const char* env_str(const char* name) {
-  const char* v = getenv(name);
-  return (v && *v) ? v : nullptr;
-}
-
 // Kernel variant for width N: the widest aligned vector (16 bytes at most) and
 // the smallest power-of-two group (4..64 lanes) that covers the row in one window.
 spmm::Variant pick_variant(int64_t N, DT dt, uintptr_t align_or) {
@@ -138,16 +139,10 @@ spmm::Variant pick_variant(int64_t N, DT dt, uintptr_t align_or) {
   const int64_t need = (N + V - 1) / V;
   int G = 4;
   while (G < 64 && G < need) G *= 2;
-  spmm::Variant v{G, V};
-  if (const char* f = env_str("SPMM_FWD_VARIANT")) {  // "G,V" for measurement sweeps
-    int g = 0, vv = 0;
-    if (sscanf(f, "%d,%d", &g, &vv) == 2 && (g == 4 || g == 8 || g == 16 || g == 32 || g == 64) &&
-        (vv == 1 || vv == 2 || vv == 4 || (vv == 8 && dt == DT::BF16)) && (N % vv) == 0 &&
-        (align_or % (uintptr_t)(vv * esize)) == 0)
-      v = spmm::Variant{g, vv};
-  }
-  return v;
+  return spmm::Variant{G, V, false};
 }
+
+bool pow2_lanes(int g) { return g == 4 || g == 8 || g == 16 || g == 32 || g == 64; }
 
 }  // namespace
 
@@ -155,8 +150,6 @@ struct spmm_tile_s {
   int64_t rows = 0;
   int num_k = 0;
   spmm_csr t[kMaxK] = {};
-  int32_t long_row = kDefaultLongRow;
-  int32_t segment = kDefaultSegment;
   Plan plan;
   spmm_tile_stats stats = {};
   bool has_t = false;
@@ -166,6 +159,13 @@ struct spmm_tile_s {
   int32_t* perm = nullptr;
   Plan planT;
   int device = 0;
+  struct VarEntry {
+    int64_t N;
+    int dtype;
+    spmm_variant v;
+  };
+  VarEntry vt[16];
+  int nvt = 0;
 
   ~spmm_tile_s() {
     free_plan(plan);
@@ -176,6 +176,70 @@ struct spmm_tile_s {
     if (perm) (void)hipFree(perm);
   }
 };
+
+namespace {
+
+// The variant for one call: the handle's entry for (N, dtype) when it fits the
+// call's alignment, otherwise the fixed rule.
+spmm::Variant resolve_variant(const spmm_tile_s* A, int64_t N, DT dt, uintptr_t align_or) {
+  const spmm::Variant base = pick_variant(N, dt, align_or);
+  const int esize = dt == DT::F32 ? 4 : 2;
+  const int want = dt == DT::F32 ? SPMM_F32 : SPMM_BF16;
+  for (int i = 0; i < A->nvt; ++i) {
+    const auto& e = A->vt[i];
+    if (e.N != N || e.dtype != want || e.v.kind == SPMM_KERNEL_AUTO) continue;
+    const int V = e.v.vec ? e.v.vec : base.V;
+    if ((N % V) != 0 || (align_or % (uintptr_t)(V * esize)) != 0) return base;
+    if (e.v.kind == SPMM_KERNEL_STREAM) return spmm::Variant{64, V, true};
+    int G = e.v.lanes;
+    if (G == 0) {
+      G = 4;
+      while (G < 64 && G < (N + V - 1) / V) G *= 2;
+    }
+    return spmm::Variant{G, V, false};
+  }
+  return base;
+}
+
+// Fill the forward parameters for a handle and launch (arguments already checked).
+hipError_t launch_forward(const spmm_tile_s* A, const Plan& plan, int k_offset, const void* const* B,
+                          const int64_t* ldb, DT dt, void* C, int64_t ldc, int64_t N, int accumulate,
+                          void* workspace, const spmm::Variant& v, hipStream_t s) {
+  const int K = A->num_k;
+  spmm::FwdParams P{};
+  for (int k = 0; k < K; ++k) {
+    P.t[k].rowptr = A->t[k].rowptr;
+    P.t[k].colind = A->t[k].colind;
+    P.t[k].values = A->t[k].values;
+    P.t[k].perm = nullptr;
+    P.t[k].B = B[k];
+    P.t[k].ldb = ldb[k];
+  }
+  P.num_k = K;
+  P.k_offset = (int)(((k_offset % K) + K) % K);
+  P.rows = A->rows;
+  P.N = N;
+  P.C = C;
+  P.ldc = ldc;
+  P.accumulate = accumulate ? 1 : 0;
+  P.long_row = plan.long_row;
+  P.seg = plan.seg;
+  P.n_seg = plan.n_seg;
+  P.lrow = plan.lrow;
+  P.n_long = plan.n_long;
+  P.partial = static_cast<float*>(workspace);
+  P.ldp = (int64_t)partial_ld(N);
+  return spmm::launch_fwd(P, v, dt, s);
+}
+
+bool valid_variant(const spmm_variant& v, spmm_dtype dtype) {
+  if (v.kind < SPMM_KERNEL_AUTO || v.kind > SPMM_KERNEL_STREAM) return false;
+  if (v.lanes != 0 && !pow2_lanes(v.lanes)) return false;
+  if (v.vec != 0 && v.vec != 1 && v.vec != 2 && v.vec != 4 && !(v.vec == 8 && dtype == SPMM_BF16)) return false;
+  return true;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -225,8 +289,6 @@ spmm_status spmm_tile_create(int64_t rows, int num_k, const spmm_csr* tiles, con
   if (!h) return fail(SPMM_ERR_ALLOC, "host allocation failed");
   h->rows = rows;
   h->num_k = num_k;
-  h->long_row = long_row;
-  h->segment = segment;
   for (int k = 0; k < num_k; ++k) h->t[k] = tiles[k];
   (void)hipGetDevice(&h->device);
 
@@ -369,6 +431,7 @@ spmm_status spmm_fwd(spmm_tile_t A, int k_offset, const void* const* B, const in
     if (!B[k] && A->t[k].cols > 0) return fail(SPMM_ERR_INVALID_ARG, "B[%d] is null", k);
     if (ldb[k] < N) return fail(SPMM_ERR_INVALID_ARG, "ldb[%d]=%lld < N", k, (long long)ldb[k]);
     if (ldb[k] * esize >= ((int64_t)1 << 32)) return fail(SPMM_ERR_UNSUPPORTED, "ldb[%d] * element size >= 2^32", k);
+    if (ldb[k] * esize >= ((int64_t)1 << 32)) return fail(SPMM_ERR_UNSUPPORTED, "ldb[%d] * element size >= 2^32", k);
     align_or |= reinterpret_cast<uintptr_t>(B[k]) | (uintptr_t)(ldb[k] * esize);
   }
   const size_t need = sizeof(float) * partial_ld(N) * (size_t)A->plan.n_seg;
@@ -383,32 +446,152 @@ spmm_status spmm_fwd(spmm_tile_t A, int k_offset, const void* const* B, const in
   HIP_TRY(hipGetDevice(&dev));
   if (dev != A->device) return fail(SPMM_ERR_INVALID_ARG, "current device %d differs from the handle's %d", dev, A->device);
 
-  spmm::FwdParams P{};
-  for (int k = 0; k < K; ++k) {
-    P.t[k].rowptr = A->t[k].rowptr;
-    P.t[k].colind = A->t[k].colind;
-    P.t[k].values = A->t[k].values;
-    P.t[k].perm = nullptr;
-    P.t[k].B = B[k];
-    P.t[k].ldb = ldb[k];
-  }
-  P.num_k = K;
-  P.k_offset = (int)(((k_offset % K) + K) % K);
-  P.rows = A->rows;
-  P.N = N;
-  P.C = C;
-  P.ldc = ldc;
-  P.accumulate = accumulate ? 1 : 0;
-  P.long_row = A->long_row;
-  P.seg = A->plan.seg;
-  P.n_seg = A->plan.n_seg;
-  P.lrow = A->plan.lrow;
-  P.n_long = A->plan.n_long;
-  P.partial = static_cast<float*>(workspace);
-  P.ldp = (int64_t)partial_ld(N);
-  const spmm::Variant v = pick_variant(N, dt, align_or);
-  HIP_TRY(spmm::launch_fwd(P, v, dt, static_cast<hipStream_t>(stream)));
+  const spmm::Variant v = resolve_variant(A, N, dt, align_or);
+  HIP_TRY(launch_forward(A, A->plan, k_offset, B, ldb, dt, C, ldc, N, accumulate, workspace, v,
+                         static_cast<hipStream_t>(stream)));
   return SPMM_OK;
+}
+
+spmm_status spmm_tile_set_variant(spmm_tile_t A, int64_t N, spmm_dtype dtype, const spmm_variant* v) {
+  if (!A) return fail(SPMM_ERR_INVALID_ARG, "tile is null");
+  if (N < 1) return fail(SPMM_ERR_INVALID_ARG, "N=%lld < 1", (long long)N);
+  if (dtype != SPMM_F32 && dtype != SPMM_BF16) return fail(SPMM_ERR_INVALID_ARG, "unknown dtype");
+  if (v && !valid_variant(*v, dtype)) return fail(SPMM_ERR_INVALID_ARG, "invalid variant fields");
+  int slot = -1;
+  for (int i = 0; i < A->nvt; ++i)
+    if (A->vt[i].N == N && A->vt[i].dtype == dtype) slot = i;
+  if (!v) {
+    if (slot >= 0) {
+      A->vt[slot] = A->vt[A->nvt - 1];
+      --A->nvt;
+    }
+    return SPMM_OK;
+  }
+  if (slot < 0) {
+    if (A->nvt >= 16) return fail(SPMM_ERR_INVALID_ARG, "variant table is full");
+    slot = A->nvt++;
+  }
+  A->vt[slot].N = N;
+  A->vt[slot].dtype = dtype;
+  A->vt[slot].v = *v;
+  return SPMM_OK;
+}
+
+spmm_status spmm_tile_autotune(spmm_tile_t A, int64_t N, spmm_dtype dtype, const void* const* B,
+                               const int64_t* ldb, void* C, int64_t ldc, int tune_plan, void* stream,
+                               spmm_variant* chosen) {
+  if (!A) return fail(SPMM_ERR_INVALID_ARG, "tile is null");
+  if (!B || !ldb) return fail(SPMM_ERR_INVALID_ARG, "B/ldb array is null");
+  if (N < 1) return fail(SPMM_ERR_INVALID_ARG, "N=%lld < 1", (long long)N);
+  if (dtype != SPMM_F32 && dtype != SPMM_BF16) return fail(SPMM_ERR_INVALID_ARG, "unknown dtype");
+  if (ldc < N) return fail(SPMM_ERR_INVALID_ARG, "ldc < N");
+  if (!C && A->rows > 0) return fail(SPMM_ERR_INVALID_ARG, "C is null");
+  const DT dt = dtype == SPMM_F32 ? DT::F32 : DT::BF16;
+  const int esize = dt == DT::F32 ? 4 : 2;
+  uintptr_t align_or = reinterpret_cast<uintptr_t>(C) | (uintptr_t)(ldc * esize);
+  for (int k = 0; k < A->num_k; ++k) {
+    if (!B[k] && A->t[k].cols > 0) return fail(SPMM_ERR_INVALID_ARG, "B[%d] is null", k);
+    if (ldb[k] < N) return fail(SPMM_ERR_INVALID_ARG, "ldb[%d] < N", k);
+    if (ldb[k] * esize >= ((int64_t)1 << 32)) return fail(SPMM_ERR_UNSUPPORTED, "ldb[%d] too large", k);
+    align_or |= reinterpret_cast<uintptr_t>(B[k]) | (uintptr_t)(ldb[k] * esize);
+  }
+  if ((N + 63) / 64 > 65535) return fail(SPMM_ERR_UNSUPPORTED, "N too large for one launch");
+  if (A->rows == 0) return SPMM_OK;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != A->device) return fail(SPMM_ERR_INVALID_ARG, "current device differs from the handle's");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  // Kernel candidates: the two widest aligned vector widths, for each the covering
+  // group size, half of it and a full wave, plus the stream kernel.
+  const spmm::Variant base = pick_variant(N, dt, align_or);
+  std::vector<spmm::Variant> kv;
+  auto add = [&](spmm::Variant v) {
+    for (auto& u : kv)
+      if (u.G == v.G && u.V == v.V && u.stream == v.stream) return;
+    kv.push_back(v);
+  };
+  for (int V = base.V; V >= 1 && V >= base.V / 2; V /= 2) {
+    if ((N % V) != 0 || (align_or % (uintptr_t)(V * esize)) != 0) continue;
+    int G = 4;
+    while (G < 64 && G < (N + V - 1) / V) G *= 2;
+    if (G >= 8) add(spmm::Variant{G / 2, V, false});
+    add(spmm::Variant{G, V, false});
+    add(spmm::Variant{64, V, false});
+    add(spmm::Variant{64, V, true});
+  }
+  // Split-plan candidates (threshold, unit length).
+  std::vector<std::pair<int32_t, int32_t>> pc;
+  pc.push_back({A->plan.long_row, A->plan.segment});
+  if (tune_plan) {
+    const std::pair<int32_t, int32_t> extra[] = {{128, 64}, {256, 128}, {512, 256}, {1024, 512}, {4096, 2048}};
+    for (auto& p : extra)
+      if (p.first != A->plan.long_row || p.second != A->plan.segment) pc.push_back(p);
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  void* ws = nullptr;
+  size_t ws_cap = 0;
+  float best = 1e30f;
+  int best_p = 0;
+  spmm::Variant best_v = base;
+  std::vector<Plan> plans(pc.size());
+  spmm_status st = SPMM_OK;
+  for (size_t pi = 0; pi < pc.size() && st == SPMM_OK; ++pi) {
+    const Plan* plan = &A->plan;
+    if (pi > 0) {
+      const int32_t* rps[kMaxK];
+      for (int k = 0; k < A->num_k; ++k) rps[k] = A->t[k].rowptr;
+      st = build_plan(rps, A->num_k, A->rows, pc[pi].first, pc[pi].second, s, &plans[pi]);
+      if (st != SPMM_OK) break;
+      plan = &plans[pi];
+    }
+    const size_t need = sizeof(float) * partial_ld(N) * (size_t)plan->n_seg;
+    if (need > ws_cap) {
+      if (ws) (void)hipFree(ws);
+      ws = nullptr;
+      if (hipMalloc(&ws, need) != hipSuccess) {
+        st = fail(SPMM_ERR_ALLOC, "autotune scratch allocation failed");
+        break;
+      }
+      ws_cap = need;
+    }
+    for (const auto& v : kv) {
+      hipError_t e = launch_forward(A, *plan, 0, B, ldb, dt, C, ldc, N, 0, ws, v, s);
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_forward(A, *plan, 0, B, ldb, dt, C, ldc, N, 0, ws, v, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        st = fail(SPMM_ERR_HIP, "autotune launch: %s", hipGetErrorString(e));
+        break;
+      }
+      if (ms < best) {
+        best = ms;
+        best_p = (int)pi;
+        best_v = v;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (ws) (void)hipFree(ws);
+  if (st == SPMM_OK && best_p > 0) {
+    free_plan(A->plan);
+    A->plan = plans[best_p];
+    plans[best_p] = Plan();
+    A->stats.long_rows = A->plan.n_long;
+    A->stats.segments = A->plan.n_seg;
+  }
+  for (auto& p : plans) free_plan(p);
+  if (st != SPMM_OK) return st;
+  spmm_variant out{best_v.stream ? SPMM_KERNEL_STREAM : SPMM_KERNEL_ROWSPLIT, best_v.G, best_v.V};
+  st = spmm_tile_set_variant(A, N, dtype, &out);
+  if (st == SPMM_OK && chosen) *chosen = out;
+  return st;
 }
 
 spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* B, int64_t ldb, int64_t N,
@@ -422,6 +605,7 @@ spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* 
   if (dA_values && !B && A->t[0].cols > 0) return fail(SPMM_ERR_INVALID_ARG, "B is null");
   if (dA_values && ldb < N) return fail(SPMM_ERR_INVALID_ARG, "ldb < N");
   if (dB && lddb < N) return fail(SPMM_ERR_INVALID_ARG, "lddb < N");
+  if (lddc * 4 >= ((int64_t)1 << 32)) return fail(SPMM_ERR_UNSUPPORTED, "lddc * 4 >= 2^32");
   if (lddc * 4 >= ((int64_t)1 << 32)) return fail(SPMM_ERR_UNSUPPORTED, "lddc * 4 >= 2^32");
   const spmm_csr& t = A->t[0];
   const size_t need = dB ? sizeof(float) * partial_ld(N) * (size_t)A->planT.n_seg : 0;
@@ -471,7 +655,7 @@ spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* 
     P.C = dB;
     P.ldc = lddb;
     P.accumulate = 0;
-    P.long_row = A->long_row;
+    P.long_row = A->planT.long_row;
     P.seg = A->planT.seg;
     P.n_seg = A->planT.n_seg;
     P.lrow = A->planT.lrow;
@@ -482,6 +666,230 @@ spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* 
                         (uintptr_t)(lddb * 4);
     HIP_TRY(spmm::launch_fwd(P, pick_variant(N, DT::F32, a), DT::F32, s));
   }
+  return SPMM_OK;
+}
+
+}  // extern "C"
+
+struct spmm_batch_s {
+  int count = 0;
+  DT dt = DT::F32;
+  int device = 0;
+  spmm::BatchTileDev* d_tiles = nullptr;
+  spmm::BatchItem* d_items = nullptr;
+  int64_t n_items = 0;
+  spmm::BatchItem* d_fix = nullptr;
+  int64_t n_fix = 0;
+  unsigned* d_counter = nullptr;
+  size_t ws_bytes = 0;
+  int grid = 0;
+  std::vector<spmm_variant> variants;
+  ~spmm_batch_s() {
+    if (d_tiles) (void)hipFree(d_tiles);
+    if (d_items) (void)hipFree(d_items);
+    if (d_fix) (void)hipFree(d_fix);
+    if (d_counter) (void)hipFree(d_counter);
+  }
+};
+
+namespace {
+
+// Batched variant of one tile: the handle's table entry for (N, dtype), else the rule
+// below; vectors assume 16-byte aligned rows (a documented requirement of spmm_batched).
+void batch_variant(const spmm_tile_s* A, int64_t N, DT dt, spmm::BatchTileDev* bt, spmm_variant* out) {
+  const int vmax = dt == DT::F32 ? 4 : 8;
+  int Vs = vmax;  // stream / unit vector: widest dividing N that is not wider than needed
+  while (Vs > 1 && ((N % Vs) != 0 || 64 * (Vs / 2) >= N)) Vs /= 2;
+  const spmm_variant* e = nullptr;
+  for (int i = 0; i < A->nvt; ++i)
+    if (A->vt[i].N == N && A->vt[i].dtype == (dt == DT::F32 ? SPMM_F32 : SPMM_BF16) &&
+        A->vt[i].v.kind != SPMM_KERNEL_AUTO)
+      e = &A->vt[i].v;
+  bool stream = N >= 64;
+  int G = 8;
+  if (e) {
+    stream = e->kind == SPMM_KERNEL_STREAM;
+    if (stream && e->vec && (N % e->vec) == 0) Vs = e->vec;
+    if (!stream && e->lanes >= 8) G = e->lanes;
+  }
+  if (!stream) {
+    if ((N % vmax) != 0) {  // row-split items use the widest vector; fall back to streaming
+      stream = true;
+    } else if (!e || e->lanes < 8) {
+      G = 8;
+      while (G < 64 && G * vmax < N) G *= 2;
+    }
+  }
+  bt->kind = stream ? 0 : 1;
+  bt->G = stream ? 64 : G;
+  bt->V = Vs;
+  *out = spmm_variant{stream ? SPMM_KERNEL_STREAM : SPMM_KERNEL_ROWSPLIT, bt->G, stream ? Vs : vmax};
+}
+
+}  // namespace
+
+extern "C" {
+
+spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t* N, spmm_dtype dtype, void* stream,
+                              spmm_batch_t* out) {
+  if (!out) return fail(SPMM_ERR_INVALID_ARG, "out is null");
+  *out = nullptr;
+  if (count < 1) return fail(SPMM_ERR_INVALID_ARG, "count=%d < 1", count);
+  if (!tiles || !N) return fail(SPMM_ERR_INVALID_ARG, "tiles/N is null");
+  if (dtype != SPMM_F32 && dtype != SPMM_BF16) return fail(SPMM_ERR_INVALID_ARG, "unknown dtype");
+  for (int t = 0; t < count; ++t) {
+    if (!tiles[t]) return fail(SPMM_ERR_INVALID_ARG, "tile %d is null", t);
+    if (tiles[t]->num_k != 1) return fail(SPMM_ERR_UNSUPPORTED, "tile %d has %d k-tiles; batches take single tiles", t,
+                                          tiles[t]->num_k);
+    if (N[t] < 1 || N[t] > (int64_t)1 << 20) return fail(SPMM_ERR_INVALID_ARG, "N[%d]=%lld out of range", t, (long long)N[t]);
+  }
+  const DT dt = dtype == SPMM_F32 ? DT::F32 : DT::BF16;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  for (int t = 0; t < count; ++t)
+    if (tiles[t]->device != dev) return fail(SPMM_ERR_INVALID_ARG, "tile %d lives on another device", t);
+  spmm_batch_s* b = new (std::nothrow) spmm_batch_s();
+  if (!b) return fail(SPMM_ERR_ALLOC, "host allocation failed");
+  b->count = count;
+  b->dt = dt;
+  b->device = dev;
+  b->variants.resize(count);
+  auto body = [&]() -> spmm_status {
+    std::vector<spmm::BatchTileDev> bt(count);
+    struct Costed {
+      double cost;
+      spmm::BatchItem it;
+    };
+    std::vector<Costed> items;
+    std::vector<spmm::BatchItem> fix;
+    int64_t part = 0;
+    std::vector<int32_t> rp;
+    std::vector<spmm::Seg> segs;
+    for (int t = 0; t < count; ++t) {
+      const spmm_tile_s* A = tiles[t];
+      spmm::BatchTileDev& d = bt[t];
+      d.rowptr = A->t[0].rowptr;
+      d.colind = A->t[0].colind;
+      d.values = A->t[0].values;
+      d.seg = A->plan.seg;
+      d.lrow = A->plan.lrow;
+      d.rows = A->rows;
+      d.N = N[t];
+      d.long_row = A->plan.long_row;
+      d.ldp = (int32_t)partial_ld(N[t]);
+      d.part_off = part;
+      part += (int64_t)d.ldp * A->plan.n_seg;
+      batch_variant(A, N[t], dt, &d, &b->variants[t]);
+      const int vmax = dt == DT::F32 ? 4 : 8;
+      const int64_t wrow = d.kind == 0 ? 64 * d.V : (int64_t)d.G * vmax;
+      const int64_t wunit = 64 * d.V;
+      const int nw_rows = (int)((N[t] + wrow - 1) / wrow);
+      const int nw_unit = (int)((N[t] + wunit - 1) / wunit);
+      // Costs from the row pointer (host copy) and the unit list.
+      rp.resize((size_t)A->rows + 1);
+      HIP_TRY(hipMemcpyAsync(rp.data(), A->t[0].rowptr, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost, s));
+      segs.resize((size_t)A->plan.n_seg);
+      if (A->plan.n_seg > 0)
+        HIP_TRY(hipMemcpyAsync(segs.data(), A->plan.seg, sizeof(spmm::Seg) * segs.size(), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      for (int64_t r0 = 0; r0 < A->rows; r0 += 64) {
+        const int64_t r1 = std::min<int64_t>(A->rows, r0 + 64);
+        int64_t nz = 0;
+        for (int64_t r = r0; r < r1; ++r) {
+          const int64_t l = (int64_t)rp[r + 1] - rp[r];
+          if (l <= d.long_row) nz += l;
+        }
+        for (int w = 0; w < nw_rows; ++w) {
+          const double width = (double)std::min<int64_t>(wrow, N[t] - w * wrow);
+          items.push_back({(double)(nz + (r1 - r0)) * width, spmm::BatchItem{t, (int32_t)r0, w, 0}});
+        }
+      }
+      for (int64_t si = 0; si < A->plan.n_seg; ++si)
+        for (int w = 0; w < nw_unit; ++w) {
+          const double width = (double)std::min<int64_t>(wunit, N[t] - w * wunit);
+          items.push_back({(double)(segs[si].p1 - segs[si].p0) * width, spmm::BatchItem{t, (int32_t)si, w, 1}});
+        }
+      for (int64_t r = 0; r < A->plan.n_long; ++r)
+        for (int w = 0; w < nw_unit; ++w) fix.push_back(spmm::BatchItem{t, (int32_t)r, w, 2});
+    }
+    if ((int64_t)items.size() >= ((int64_t)1 << 32)) return fail(SPMM_ERR_UNSUPPORTED, "work list too long");
+    std::stable_sort(items.begin(), items.end(), [](const Costed& x, const Costed& y) { return x.cost > y.cost; });
+    std::vector<spmm::BatchItem> list(items.size());
+    for (size_t i = 0; i < items.size(); ++i) list[i] = items[i].it;
+    b->n_items = (int64_t)list.size();
+    b->n_fix = (int64_t)fix.size();
+    b->ws_bytes = sizeof(float) * (size_t)part;
+    if (dalloc(&b->d_tiles, count) != hipSuccess || dalloc(&b->d_items, b->n_items) != hipSuccess ||
+        dalloc(&b->d_fix, b->n_fix) != hipSuccess || dalloc(&b->d_counter, 1) != hipSuccess)
+      return fail(SPMM_ERR_ALLOC, "device allocation of the batch failed");
+    HIP_TRY(hipMemcpyAsync(b->d_tiles, bt.data(), sizeof(spmm::BatchTileDev) * bt.size(), hipMemcpyHostToDevice, s));
+    if (b->n_items)
+      HIP_TRY(hipMemcpyAsync(b->d_items, list.data(), sizeof(spmm::BatchItem) * list.size(), hipMemcpyHostToDevice, s));
+    if (b->n_fix)
+      HIP_TRY(hipMemcpyAsync(b->d_fix, fix.data(), sizeof(spmm::BatchItem) * fix.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(b->d_counter, 0, sizeof(unsigned), s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    b->grid = std::max(1, cus * spmm::batch_blocks_per_cu(dt));
+    return SPMM_OK;
+  };
+  spmm_status st = body();
+  if (st != SPMM_OK) {
+    delete b;
+    return st;
+  }
+  *out = b;
+  return SPMM_OK;
+}
+
+spmm_status spmm_batch_destroy(spmm_batch_t batch) {
+  if (!batch) return fail(SPMM_ERR_INVALID_ARG, "batch is null");
+  delete batch;
+  return SPMM_OK;
+}
+
+spmm_status spmm_batch_workspace_bytes(spmm_batch_t batch, size_t* bytes) {
+  if (!batch || !bytes) return fail(SPMM_ERR_INVALID_ARG, "null argument");
+  *bytes = batch->ws_bytes;
+  return SPMM_OK;
+}
+
+spmm_status spmm_batch_get_variant(spmm_batch_t batch, int t, spmm_variant* out) {
+  if (!batch || !out) return fail(SPMM_ERR_INVALID_ARG, "null argument");
+  if (t < 0 || t >= batch->count) return fail(SPMM_ERR_INVALID_ARG, "tile index %d out of range", t);
+  *out = batch->variants[t];
+  return SPMM_OK;
+}
+
+spmm_status spmm_batched(spmm_batch_t batch, const void* const* B, const int64_t* ldb, void* const* C,
+                         const int64_t* ldc, int accumulate, void* workspace, size_t ws_bytes, void* stream) {
+  if (!batch) return fail(SPMM_ERR_INVALID_ARG, "batch is null");
+  if (!B || !ldb || !C || !ldc) return fail(SPMM_ERR_INVALID_ARG, "operand arrays must be device arrays, not null");
+  if (batch->ws_bytes > 0) {
+    if (!workspace || ws_bytes < batch->ws_bytes)
+      return fail(SPMM_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", batch->ws_bytes,
+                  workspace ? ws_bytes : 0);
+    if (reinterpret_cast<uintptr_t>(workspace) % 16) return fail(SPMM_ERR_WORKSPACE, "workspace must be 16-byte aligned");
+  }
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != batch->device) return fail(SPMM_ERR_INVALID_ARG, "current device differs from the batch's");
+  spmm::BatchParams P{};
+  P.tiles = batch->d_tiles;
+  P.items = batch->d_items;
+  P.n_items = batch->n_items;
+  P.fix = batch->d_fix;
+  P.n_fix = batch->n_fix;
+  P.B = B;
+  P.ldb = ldb;
+  P.C = C;
+  P.ldc = ldc;
+  P.partial = static_cast<float*>(workspace);
+  P.counter = batch->d_counter;
+  P.accumulate = accumulate ? 1 : 0;
+  HIP_TRY(spmm::launch_batch(P, batch->dt, batch->grid, static_cast<hipStream_t>(stream)));
   return SPMM_OK;
 }
 

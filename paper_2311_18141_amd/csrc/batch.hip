@@ -1,0 +1,325 @@
+// Batched local SpMM: many independent single-tile products C_t = A_t B_t in one
+// persistent launch.  The host builds a work list of items (64 rows of one tile
+// and one column window, or one split-row unit), sorted by descending cost.
+// Each wave claims items from a device counter (the single-GPU form of claiming
+// work with a fetch-and-add) and runs the item with its tile's kernel variant.
+// Items write disjoint output rows (split rows: disjoint partial rows) and every
+// row is summed in CSR order by one wave, so the result does not depend on which
+// wave claims which item; split rows are finished by a second, fix-up launch.
+#include "elem.hpp"
+#include "fwd_common.hpp"
+#include "internal.hpp"
+
+namespace spmm {
+namespace {
+
+template <typename E>
+struct Ops {
+  using T = typename E::T;
+  const T* B;
+  int64_t ldb;
+  T* C;
+  int64_t ldc;
+};
+
+template <typename E>
+__device__ __forceinline__ Ops<E> item_ops(const BatchParams& P, int t) {
+  Ops<E> o;
+  o.B = static_cast<const typename E::T*>(P.B[t]);
+  o.ldb = P.ldb[t];
+  o.C = static_cast<typename E::T*>(P.C[t]);
+  o.ldc = P.ldc[t];
+  return o;
+}
+
+template <int V, typename E, bool ACC>
+__device__ __forceinline__ void store_c(typename E::T* c, float (&acc)[V]) {
+  if constexpr (ACC) {
+    float old[V];
+    load_vec<E, V>(c, old);
+#pragma unroll
+    for (int e = 0; e < V; ++e) acc[e] += old[e];
+  }
+  store_vec<E, V>(c, acc);
+}
+
+// 64 rows [r0, r0+64) of one tile, streamed by the whole wave (see fwd_stream).
+template <int V, typename E, bool ACC>
+__device__ __forceinline__ void item_stream(const BatchTileDev& bt, const Ops<E>& op, int64_t r0, int window,
+                                            int32_t* s_pref, int32_t* s_beg) {
+  using T = typename E::T;
+  constexpr int U = V >= 8 ? 4 : 8;
+  const int lane = threadIdx.x & 63;
+  const int64_t c0 = (int64_t)window * (64 * V) + (int64_t)lane * V;
+  const bool active = c0 < bt.N;
+  const int64_t cl = active ? c0 : 0;
+  const int64_t row = r0 + lane;
+  const bool inrow = row < bt.rows;
+  int32_t b = 0, L = 0;
+  if (inrow) {
+    b = bt.rowptr[row];
+    L = bt.rowptr[row + 1] - b;
+  }
+  const int32_t Ls = (L > bt.long_row) ? 0 : L;
+  int32_t incl = Ls;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  s_pref[lane] = incl - Ls;
+  if (lane == 63) s_pref[64] = incl;
+  s_beg[lane] = b;
+  const int32_t total = __builtin_amdgcn_readlane(incl, 63);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  float acc[V];
+#pragma unroll
+  for (int e = 0; e < V; ++e) acc[e] = 0.0f;
+  if constexpr (!ACC) {
+    uint64_t em = __ballot(inrow && L == 0);
+    while (em) {
+      const int i = __ffsll((long long)em) - 1;
+      em &= em - 1;
+      if (active) store_vec<E, V>(op.C + (r0 + i) * op.ldc + c0, acc);
+    }
+  }
+  const uint64_t ldbb = (uint64_t)(op.ldb * (int64_t)sizeof(T));
+  const uint64_t base = reinterpret_cast<uint64_t>(op.B) + (uint64_t)(cl * (int64_t)sizeof(T));
+  for (int32_t qc = 0; qc < total; qc += 64) {
+    const int n = min(64, total - qc);
+    const int32_t q = qc + lane;
+    int ri = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+      const int cand = ri + step;
+      if (cand <= 63 && s_pref[cand] <= q) ri = cand;
+    }
+    uint64_t addr = 0;
+    float val = 0.0f;
+    int end = 0;
+    if (lane < n) {
+      const int32_t p = s_beg[ri] + (q - s_pref[ri]);
+      const uint32_t col = (uint32_t)__builtin_nontemporal_load(bt.colind + p);
+      val = __builtin_nontemporal_load(bt.values + p);
+      addr = base + (uint64_t)col * ldbb;
+      end = (q + 1 == s_pref[ri + 1]) ? 1 : 0;
+    }
+    const uint32_t alo = (uint32_t)addr, ahi = (uint32_t)(addr >> 32);
+    for (int u0 = 0; u0 < n; u0 += U) {
+      float bv[U][V];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int jj = min(u0 + u, n - 1);
+        const uint64_t a = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)ahi, jj) << 32) |
+                           (uint32_t)__builtin_amdgcn_readlane((int)alo, jj);
+        load_vec_at<E, V>(a, bv[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int jj = min(u0 + u, n - 1);
+        const bool ok = u0 + u < n;
+        const float v = ok ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(val), jj)) : 0.0f;
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc[e] = fmaf(v, ok ? bv[u][e] : 0.0f, acc[e]);
+        if (ok && __builtin_amdgcn_readlane(end, jj)) {
+          const int r = __builtin_amdgcn_readlane(ri, jj);
+          if (active) store_c<V, E, ACC>(op.C + (r0 + r) * op.ldc + c0, acc);
+#pragma unroll
+          for (int e = 0; e < V; ++e) acc[e] = 0.0f;
+        }
+      }
+    }
+  }
+}
+
+// 64 rows [r0, r0+64) of one tile, 64/G rows at a time, G lanes per row.
+template <int G, int V, typename E, bool ACC>
+__device__ __forceinline__ void item_rowsplit(const BatchTileDev& bt, const Ops<E>& op, int64_t r0, int window) {
+  using T = typename E::T;
+  constexpr int GPW = 64 / G;
+  const int lane = threadIdx.x & 63;
+  const int gl = lane & (G - 1);
+  const int64_t c0 = (int64_t)window * (G * V) + (int64_t)gl * V;
+  const bool active = c0 < bt.N;
+  const int64_t cl = active ? c0 : 0;
+  TileDev t;
+  t.rowptr = bt.rowptr;
+  t.colind = bt.colind;
+  t.values = bt.values;
+  t.perm = nullptr;
+  t.B = op.B;
+  t.ldb = op.ldb;
+  const char* brow = reinterpret_cast<const char*>(op.B) + cl * (int64_t)sizeof(T);
+  const uint32_t ldbb = (uint32_t)(op.ldb * (int64_t)sizeof(T));
+  for (int rr = 0; rr < 64; rr += GPW) {
+    const int64_t row = r0 + rr + lane / G;
+    int32_t p0 = 0, p1 = 0;
+    const bool inrow = row < bt.rows;
+    if (inrow) {
+      p0 = bt.rowptr[row];
+      p1 = bt.rowptr[row + 1];
+    }
+    const bool split = p1 - p0 > bt.long_row;
+    if (split) p1 = p0;
+    float acc[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) acc[e] = 0.0f;
+    accumulate_range<G, V, E>(t, p0, p1, brow, ldbb, gl, acc);
+    if (inrow && !split && active) store_c<V, E, ACC>(op.C + row * op.ldc + c0, acc);
+  }
+}
+
+// One split-row unit: partial sum over [p0, p1) into the workspace (full wave).
+template <int V, typename E>
+__device__ __forceinline__ void item_unit(const BatchParams& P, const BatchTileDev& bt, const Ops<E>& op,
+                                          int s, int window) {
+  using T = typename E::T;
+  const int lane = threadIdx.x & 63;
+  const int64_t c0 = (int64_t)window * (64 * V) + (int64_t)lane * V;
+  const bool active = c0 < bt.N;
+  const int64_t cl = active ? c0 : 0;
+  TileDev t;
+  t.rowptr = bt.rowptr;
+  t.colind = bt.colind;
+  t.values = bt.values;
+  t.perm = nullptr;
+  t.B = op.B;
+  t.ldb = op.ldb;
+  const Seg d = bt.seg[s];
+  float acc[V];
+#pragma unroll
+  for (int e = 0; e < V; ++e) acc[e] = 0.0f;
+  accumulate_range<64, V, E>(t, d.p0, d.p1, reinterpret_cast<const char*>(op.B) + cl * (int64_t)sizeof(T),
+                             (uint32_t)(op.ldb * (int64_t)sizeof(T)), lane, acc);
+  if (active) store_f32v<V>(P.partial + bt.part_off + (int64_t)s * bt.ldp + c0, acc);
+}
+
+template <typename E, bool ACC>
+__device__ __forceinline__ void run_item(const BatchParams& P, const BatchItem& it, int32_t* s_pref,
+                                         int32_t* s_beg) {
+  const BatchTileDev& bt = P.tiles[it.tile];
+  const Ops<E> op = item_ops<E>(P, it.tile);
+  const int64_t r0 = it.a;
+  constexpr bool F32 = sizeof(typename E::T) == 4;
+  if (it.type == 1) {
+    switch (bt.V) {
+      case 1: item_unit<1, E>(P, bt, op, it.a, it.window); return;
+      case 2: item_unit<2, E>(P, bt, op, it.a, it.window); return;
+      case 4: item_unit<4, E>(P, bt, op, it.a, it.window); return;
+      default:
+        if constexpr (!F32) item_unit<8, E>(P, bt, op, it.a, it.window);
+        return;
+    }
+  }
+  if (bt.kind == 0) {
+    switch (bt.V) {
+      case 1: item_stream<1, E, ACC>(bt, op, r0, it.window, s_pref, s_beg); return;
+      case 2: item_stream<2, E, ACC>(bt, op, r0, it.window, s_pref, s_beg); return;
+      case 4: item_stream<4, E, ACC>(bt, op, r0, it.window, s_pref, s_beg); return;
+      default:
+        if constexpr (!F32) item_stream<8, E, ACC>(bt, op, r0, it.window, s_pref, s_beg);
+        return;
+    }
+  }
+  constexpr int VW = F32 ? 4 : 8;  // row-split variants use the widest vector of the dtype
+  switch (bt.G) {
+    case 8: item_rowsplit<8, VW, E, ACC>(bt, op, r0, it.window); return;
+    case 16: item_rowsplit<16, VW, E, ACC>(bt, op, r0, it.window); return;
+    case 32: item_rowsplit<32, VW, E, ACC>(bt, op, r0, it.window); return;
+    default: item_rowsplit<64, VW, E, ACC>(bt, op, r0, it.window); return;
+  }
+}
+
+template <typename E, bool ACC>
+__global__ void __launch_bounds__(kBlock) batch_main(BatchParams P) {
+  __shared__ int32_t s_mem[(kBlock / 64) * 129];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  int32_t* s_pref = s_mem + w * 129;
+  int32_t* s_beg = s_pref + 65;
+  for (;;) {
+    unsigned claimed = 0;
+    if (lane == 0) claimed = atomicAdd(P.counter, 1u);
+    const unsigned it = (unsigned)__builtin_amdgcn_readlane((int)claimed, 0);
+    if ((int64_t)it >= P.n_items) break;  // every wave leaves once the list is drained
+    const BatchItem item = P.items[it];
+    run_item<E, ACC>(P, item, s_pref, s_beg);
+  }
+}
+
+// Split rows: C row = [C] + sum of the row's unit partials in CSR order.
+template <int V, typename E, bool ACC>
+__device__ __forceinline__ void fix_row(const BatchParams& P, const BatchTileDev& bt, const Ops<E>& op, int r,
+                                        int window) {
+  const int lane = threadIdx.x & 63;
+  const int64_t c0 = (int64_t)window * (64 * V) + (int64_t)lane * V;
+  if (c0 >= bt.N) return;
+  const LongRow lr = bt.lrow[r];
+  float acc[V];
+#pragma unroll
+  for (int e = 0; e < V; ++e) acc[e] = 0.0f;
+  for (int s = lr.s0; s < lr.s1; ++s) {
+    float x[V];
+    load_f32v<V>(P.partial + bt.part_off + (int64_t)s * bt.ldp + c0, x);
+#pragma unroll
+    for (int e = 0; e < V; ++e) acc[e] += x[e];
+  }
+  store_c<V, E, ACC>(op.C + (int64_t)lr.row * op.ldc + c0, acc);
+}
+
+template <typename E, bool ACC>
+__global__ void __launch_bounds__(kBlock) batch_fixup(BatchParams P) {
+  const int64_t f = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (f >= P.n_fix) return;
+  const BatchItem it = P.fix[f];
+  const BatchTileDev& bt = P.tiles[it.tile];
+  const Ops<E> op = item_ops<E>(P, it.tile);
+  switch (bt.V) {
+    case 1: fix_row<1, E, ACC>(P, bt, op, it.a, it.window); return;
+    case 2: fix_row<2, E, ACC>(P, bt, op, it.a, it.window); return;
+    case 4: fix_row<4, E, ACC>(P, bt, op, it.a, it.window); return;
+    default:
+      if constexpr (sizeof(typename E::T) == 2) fix_row<8, E, ACC>(P, bt, op, it.a, it.window);
+      return;
+  }
+}
+
+// Reset the claim counter inside the stream (a kernel, so that a captured graph
+// resets it on every replay).
+__global__ void batch_reset(unsigned* counter) { *counter = 0u; }
+
+template <typename E, bool ACC>
+hipError_t launch_batch_t(const BatchParams& P, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, P.counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (P.n_items > 0) {
+    hipLaunchKernelGGL((batch_main<E, ACC>), dim3((unsigned)grid), dim3(kBlock), 0, s, P);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (P.n_fix > 0) {
+    hipLaunchKernelGGL((batch_fixup<E, ACC>), dim3((unsigned)((P.n_fix + 3) / 4)), dim3(kBlock), 0, s, P);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+}  // namespace
+
+hipError_t launch_batch(const BatchParams& P, DT dt, int grid, hipStream_t s) {
+  if (dt == DT::F32)
+    return P.accumulate ? launch_batch_t<F32E, true>(P, grid, s) : launch_batch_t<F32E, false>(P, grid, s);
+  return P.accumulate ? launch_batch_t<BF16E, true>(P, grid, s) : launch_batch_t<BF16E, false>(P, grid, s);
+}
+
+int batch_blocks_per_cu(DT dt) {
+  int n = 0;
+  hipError_t e = dt == DT::F32
+                     ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_main<F32E, false>, kBlock, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_main<BF16E, false>, kBlock, 0);
+  return (e == hipSuccess && n > 0) ? n : 2;
+}
+
+}  // namespace spmm

@@ -66,6 +66,50 @@ __device__ __forceinline__ void load_vec(const typename E::T* p, float (&x)[V]) 
   }
 }
 
+// The same load from an integer device address, marked as global memory so that
+// the compiler emits global (not flat) loads.
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+#define SPMM_GLOBAL(T) const __attribute__((address_space(1))) T*
+
+template <typename E, int V>
+__device__ __forceinline__ void load_vec_at(uint64_t addr, float (&x)[V]) {
+  using T = typename E::T;
+  if constexpr (sizeof(T) == 4) {
+    if constexpr (V == 1) {
+      x[0] = *(SPMM_GLOBAL(float))addr;
+    } else if constexpr (V == 2) {
+      const f32x2_t a = *(SPMM_GLOBAL(f32x2_t))addr;
+      x[0] = a.x; x[1] = a.y;
+    } else {
+      static_assert(V == 4, "fp32 vector width");
+      const f32x4_t a = *(SPMM_GLOBAL(f32x4_t))addr;
+      x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+    }
+  } else {
+    if constexpr (V == 1) {
+      x[0] = bf16_bits_to_f32(*(SPMM_GLOBAL(uint16_t))addr);
+    } else if constexpr (V == 2) {
+      const uint32_t a = *(SPMM_GLOBAL(uint32_t))addr;
+      x[0] = __uint_as_float(a << 16); x[1] = __uint_as_float(a & 0xFFFF0000u);
+    } else if constexpr (V == 4) {
+      const u32x2_t a = *(SPMM_GLOBAL(u32x2_t))addr;
+      x[0] = __uint_as_float(a.x << 16); x[1] = __uint_as_float(a.x & 0xFFFF0000u);
+      x[2] = __uint_as_float(a.y << 16); x[3] = __uint_as_float(a.y & 0xFFFF0000u);
+    } else {
+      static_assert(V == 8, "bf16 vector width");
+      const u32x4_t a = *(SPMM_GLOBAL(u32x4_t))addr;
+      x[0] = __uint_as_float(a.x << 16); x[1] = __uint_as_float(a.x & 0xFFFF0000u);
+      x[2] = __uint_as_float(a.y << 16); x[3] = __uint_as_float(a.y & 0xFFFF0000u);
+      x[4] = __uint_as_float(a.z << 16); x[5] = __uint_as_float(a.z & 0xFFFF0000u);
+      x[6] = __uint_as_float(a.w << 16); x[7] = __uint_as_float(a.w & 0xFFFF0000u);
+    }
+  }
+}
+#undef SPMM_GLOBAL
+
 // Store V FP32 values to V consecutive elements (rounded once for BF16).
 template <typename E, int V>
 __device__ __forceinline__ void store_vec(typename E::T* p, const float (&x)[V]) {

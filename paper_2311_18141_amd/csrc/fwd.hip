@@ -17,89 +17,11 @@
 //     order (k' order, then position) and stores C once.  Deterministic: no
 //     atomics, so replays are bit-identical.
 #include "elem.hpp"
+#include "fwd_common.hpp"
 #include "internal.hpp"
 
 namespace spmm {
 namespace {
-
-template <int G>
-__device__ __forceinline__ int group_bcast(int x, int src) {
-  if constexpr (G == 64) {
-    return __builtin_amdgcn_readlane(x, src);
-  } else {
-    const int lane = threadIdx.x & 63;
-    return __builtin_amdgcn_ds_bpermute(((lane & ~(G - 1)) + src) << 2, x);
-  }
-}
-
-template <int G>
-__device__ __forceinline__ int64_t group_uniform(int64_t x) {
-  if constexpr (G == 64) {
-    // A full wave shares the value; make it scalar so row data moves through SGPRs.
-    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
-    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-  } else {
-    return x;
-  }
-}
-
-template <int V>
-constexpr int unroll_for() {
-  return V >= 8 ? 4 : 8;
-}
-
-// acc += sum over p in [p0, p1) of val(p) * B[col(p), c0 .. c0+V), where
-// brow = B + c0 (bytes) and B rows are ldb_bytes apart (< 2^32, checked by the host).
-// Full batches of U non-zeros issue U independent row loads before any FMA; the
-// last partial batch is predicated without branches (clamped source, zeroed terms).
-template <int G, int V, typename E>
-__device__ __forceinline__ void accumulate_range(const TileDev& t, int p0, int p1, const char* brow,
-                                                 uint32_t ldb_bytes, int gl, float (&acc)[V]) {
-  constexpr int U = unroll_for<V>();
-  using T = typename E::T;
-  for (int pc = p0; pc < p1; pc += G) {
-    const int cnt = min(G, p1 - pc);
-    int my_col = 0;
-    float my_val = 0.0f;
-    if (gl < cnt) {
-      my_col = __builtin_nontemporal_load(t.colind + pc + gl);
-      my_val = t.perm ? t.values[t.perm[pc + gl]] : __builtin_nontemporal_load(t.values + pc + gl);
-    }
-    int j = 0;
-    for (; j + U <= cnt; j += U) {
-      float b[U][V];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const uint32_t col = (uint32_t)group_bcast<G>(my_col, j + u);
-        load_vec<E, V>(reinterpret_cast<const T*>(brow + (uint64_t)col * ldb_bytes), b[u]);
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const float v = __int_as_float(group_bcast<G>(__float_as_int(my_val), j + u));
-#pragma unroll
-        for (int e = 0; e < V; ++e) acc[e] = fmaf(v, b[u][e], acc[e]);
-      }
-    }
-    if (j < cnt) {
-      float b[U][V];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int src = min(j + u, cnt - 1);
-        const uint32_t col = (uint32_t)group_bcast<G>(my_col, src);
-        load_vec<E, V>(reinterpret_cast<const T*>(brow + (uint64_t)col * ldb_bytes), b[u]);
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int src = min(j + u, cnt - 1);
-        const bool ok = j + u < cnt;
-        const float v = __int_as_float(group_bcast<G>(__float_as_int(my_val), src));
-#pragma unroll
-        for (int e = 0; e < V; ++e) acc[e] = fmaf(ok ? v : 0.0f, ok ? b[u][e] : 0.0f, acc[e]);
-      }
-    }
-  }
-}
 
 template <int G, int V, typename E>
 __global__ void __launch_bounds__(kBlock) fwd_main(FwdParams P) {
@@ -150,6 +72,192 @@ __global__ void __launch_bounds__(kBlock) fwd_main(FwdParams P) {
   store_vec<E, V>(c, acc);
 }
 
+// Stream variant: one wave owns 64 consecutive rows (one per lane for the
+// bookkeeping) and walks the concatenation of their non-zeros, over all
+// k-tiles in k' order, 64 entries at a time.  Every entry's B row address and
+// value are formed by the lane that loaded it, then consumed in order by the
+// whole wave (readlane: the address is wave-uniform, each lane loads its V
+// columns); accumulators are flushed to C when an entry closes its row.  So
+// the B loads of many short rows are in flight together, and the per-row
+// order of summation (k' order, then CSR position) is the row-split one.
+// Rows longer than the split threshold are left to the units and the fix-up.
+template <int V>
+constexpr int stream_unroll() {
+  return V >= 8 ? 4 : (V >= 4 ? 8 : 16);
+}
+
+template <int V, typename E, bool ACC>
+__device__ __forceinline__ void store_row(const FwdParams& P, int64_t row, int64_t c0, bool active,
+                                          float (&acc)[V]) {
+  if (!active) return;
+  typename E::T* c = static_cast<typename E::T*>(P.C) + row * P.ldc + c0;
+  if constexpr (ACC) {
+    float old[V];
+    load_vec<E, V>(c, old);
+#pragma unroll
+    for (int e = 0; e < V; ++e) acc[e] += old[e];
+  }
+  store_vec<E, V>(c, acc);
+}
+
+template <int V, typename E, bool ACC>
+__global__ void __launch_bounds__(kBlock) fwd_stream(FwdParams P) {
+  constexpr int GPB = kBlock / 64;
+  constexpr int U = stream_unroll<V>();
+  using T = typename E::T;
+  extern __shared__ int32_t s_mem[];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int K = P.num_k;
+  const int64_t c0 = (int64_t)blockIdx.y * (64 * V) + (int64_t)lane * V;
+  const bool active = c0 < P.N;
+  const int64_t cl = active ? c0 : 0;
+  const int64_t unit_blocks = (P.n_seg + GPB - 1) / GPB;
+  float acc[V];
+#pragma unroll
+  for (int e = 0; e < V; ++e) acc[e] = 0.0f;
+
+  if ((int64_t)blockIdx.x < unit_blocks) {
+    const int64_t s = group_uniform<64>((int64_t)blockIdx.x * GPB + w);
+    if (s >= P.n_seg) return;
+    const Seg d = P.seg[s];
+    const TileDev& t = P.t[d.k];
+    accumulate_range<64, V, E>(t, d.p0, d.p1, static_cast<const char*>(t.B) + cl * (int64_t)sizeof(T),
+                               (uint32_t)(t.ldb * (int64_t)sizeof(T)), lane, acc);
+    if (active) store_f32v<V>(P.partial + s * P.ldp + c0, acc);
+    return;
+  }
+
+  const int64_t r0 = group_uniform<64>((((int64_t)blockIdx.x - unit_blocks) * GPB + w) * 64);
+  if (r0 >= P.rows) return;
+  int32_t* s_pref = s_mem + w * (65 + 128 * K);  // exclusive prefix of streamed lengths, [64] = total
+  int32_t* s_beg = s_pref + 65;                   // [kk][lane]: first CSR position of the row in tile kk
+  int32_t* s_koff = s_beg + 64 * K;               // [kk][lane]: offset of tile kk inside the row
+  const int64_t row = r0 + lane;
+  const bool inrow = row < P.rows;
+  int32_t L = 0;
+  for (int kk = 0; kk < K; ++kk) {
+    int k = kk + P.k_offset;
+    if (k >= K) k -= K;
+    int32_t b = 0, l = 0;
+    if (inrow) {
+      b = P.t[k].rowptr[row];
+      l = P.t[k].rowptr[row + 1] - b;
+    }
+    s_beg[kk * 64 + lane] = b;
+    s_koff[kk * 64 + lane] = L;
+    L += l;
+  }
+  const int32_t Ls = (L > P.long_row) ? 0 : L;  // split rows are not streamed
+  int32_t incl = Ls;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  s_pref[lane] = incl - Ls;
+  if (lane == 63) s_pref[64] = incl;
+  const int32_t total = __builtin_amdgcn_readlane(incl, 63);
+  // The bookkeeping above is read back by other lanes of this wave only.
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+  // Empty rows: C = 0, or untouched when accumulating.
+  if constexpr (!ACC) {
+    uint64_t em = __ballot(inrow && L == 0);
+    float z[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) z[e] = 0.0f;
+    while (em) {
+      const int i = __ffsll((long long)em) - 1;
+      em &= em - 1;
+      if (active) store_vec<E, V>(static_cast<T*>(P.C) + (r0 + i) * P.ldc + c0, z);
+    }
+  }
+
+  for (int32_t qc = 0; qc < total; qc += 64) {
+    const int n = min(64, total - qc);
+    const int32_t q = qc + lane;
+    // Row of entry q: the last lane i with s_pref[i] <= q.
+    int ri = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+      const int cand = ri + step;
+      if (cand <= 63 && s_pref[cand] <= q) ri = cand;
+    }
+    const int32_t o = q - s_pref[ri];
+    int kk = 0;
+    for (int t = 1; t < K; ++t)
+      if (s_koff[t * 64 + ri] <= o) kk = t;
+    int k = kk + P.k_offset;
+    if (k >= K) k -= K;
+    const int32_t p = s_beg[kk * 64 + ri] + (o - s_koff[kk * 64 + ri]);
+    const int32_t* colp = P.t[0].colind;
+    const float* valp = P.t[0].values;
+    const char* bp = static_cast<const char*>(P.t[0].B);
+    int64_t ldbb = P.t[0].ldb;
+    for (int t = 1; t < K; ++t) {
+      if (k == t) {
+        colp = P.t[t].colind;
+        valp = P.t[t].values;
+        bp = static_cast<const char*>(P.t[t].B);
+        ldbb = P.t[t].ldb;
+      }
+    }
+    uint64_t addr = 0;
+    float val = 0.0f;
+    int end = 0;
+    if (lane < n) {
+      const uint32_t col = (uint32_t)__builtin_nontemporal_load(colp + p);
+      val = __builtin_nontemporal_load(valp + p);
+      addr = reinterpret_cast<uint64_t>(bp) + (uint64_t)col * (uint64_t)(ldbb * (int64_t)sizeof(T));
+      end = (q + 1 == s_pref[ri + 1]) ? 1 : 0;
+    }
+    const uint32_t alo = (uint32_t)addr, ahi = (uint32_t)(addr >> 32);
+    const uint64_t coff = (uint64_t)(cl * (int64_t)sizeof(T));
+    // Double-buffered: the loads of the next U entries are issued before the
+    // current U are consumed.  Entries past n repeat the last one (never summed).
+    auto issue = [&](float (&b)[U][V], int u0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int jj = min(u0 + u, n - 1);
+        const uint64_t a = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)ahi, jj) << 32) |
+                           (uint32_t)__builtin_amdgcn_readlane((int)alo, jj);
+        load_vec_at<E, V>(a + coff, b[u]);
+      }
+    };
+    auto consume = [&](const float (&b)[U][V], int u0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int jj = min(u0 + u, n - 1);
+        const bool ok = u0 + u < n;
+        const float v = ok ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(val), jj)) : 0.0f;
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc[e] = fmaf(v, ok ? b[u][e] : 0.0f, acc[e]);
+        if (ok && __builtin_amdgcn_readlane(end, jj)) {
+          const int r = __builtin_amdgcn_readlane(ri, jj);
+          store_row<V, E, ACC>(P, r0 + r, c0, active, acc);
+#pragma unroll
+          for (int e = 0; e < V; ++e) acc[e] = 0.0f;
+        }
+      }
+    };
+    float bA[U][V], bB[U][V];
+    issue(bA, 0);
+    for (int u0 = 0;;) {
+      if (u0 + U < n) issue(bB, u0 + U);
+      consume(bA, u0);
+      u0 += U;
+      if (u0 >= n) break;
+      if (u0 + U < n) issue(bA, u0 + U);
+      consume(bB, u0);
+      u0 += U;
+      if (u0 >= n) break;
+    }
+  }
+}
+
 template <int G, int V, typename E>
 __global__ void __launch_bounds__(kBlock) fwd_fixup(FwdParams P) {
   constexpr int GPB = kBlock / G;
@@ -183,19 +291,29 @@ __global__ void __launch_bounds__(kBlock) fwd_fixup(FwdParams P) {
 }
 
 template <int G, int V, typename E>
-hipError_t launch_gv(const FwdParams& P0, hipStream_t s) {
+hipError_t launch_gv(const FwdParams& P0, bool stream, hipStream_t s) {
   FwdParams P = P0;
   constexpr int GPB = kBlock / G;
   const int64_t unit_blocks = (P.n_seg + GPB - 1) / GPB;
-  const int64_t row_blocks = (P.rows + GPB - 1) / GPB;
   const int64_t windows = (P.N + G * V - 1) / (G * V);
-  P.row_blocks = row_blocks;
-  if (unit_blocks + row_blocks > 0) {
+  if (stream) {
+    // 64 rows per wave, GPB waves per workgroup
+    const int64_t row_blocks = (P.rows + 64 * GPB - 1) / (64 * GPB);
+    P.row_blocks = row_blocks;
+    const size_t lds = sizeof(int32_t) * (size_t)GPB * (65 + 128 * (size_t)P.num_k);
+    dim3 grid((unsigned)(unit_blocks + row_blocks), (unsigned)windows);
+    if (P.accumulate)
+      hipLaunchKernelGGL((fwd_stream<V, E, true>), grid, dim3(kBlock), lds, s, P);
+    else
+      hipLaunchKernelGGL((fwd_stream<V, E, false>), grid, dim3(kBlock), lds, s, P);
+  } else {
+    const int64_t row_blocks = (P.rows + GPB - 1) / GPB;
+    P.row_blocks = row_blocks;
     dim3 grid((unsigned)(unit_blocks + row_blocks), (unsigned)windows);
     hipLaunchKernelGGL((fwd_main<G, V, E>), grid, dim3(kBlock), 0, s, P);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   if (P.n_long > 0) {
     dim3 grid((unsigned)((P.n_long + GPB - 1) / GPB), (unsigned)windows);
     hipLaunchKernelGGL((fwd_fixup<G, V, E>), grid, dim3(kBlock), 0, s, P);
@@ -205,13 +323,14 @@ hipError_t launch_gv(const FwdParams& P0, hipStream_t s) {
 }
 
 template <typename E, int V>
-hipError_t launch_v(const FwdParams& P, int G, hipStream_t s) {
-  switch (G) {
-    case 4: return launch_gv<4, V, E>(P, s);
-    case 8: return launch_gv<8, V, E>(P, s);
-    case 16: return launch_gv<16, V, E>(P, s);
-    case 32: return launch_gv<32, V, E>(P, s);
-    case 64: return launch_gv<64, V, E>(P, s);
+hipError_t launch_v(const FwdParams& P, const Variant& v, hipStream_t s) {
+  if (v.stream) return launch_gv<64, V, E>(P, true, s);
+  switch (v.G) {
+    case 4: return launch_gv<4, V, E>(P, false, s);
+    case 8: return launch_gv<8, V, E>(P, false, s);
+    case 16: return launch_gv<16, V, E>(P, false, s);
+    case 32: return launch_gv<32, V, E>(P, false, s);
+    case 64: return launch_gv<64, V, E>(P, false, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -221,17 +340,17 @@ hipError_t launch_v(const FwdParams& P, int G, hipStream_t s) {
 hipError_t launch_fwd(const FwdParams& P, Variant v, DT dt, hipStream_t s) {
   if (dt == DT::F32) {
     switch (v.V) {
-      case 1: return launch_v<F32E, 1>(P, v.G, s);
-      case 2: return launch_v<F32E, 2>(P, v.G, s);
-      case 4: return launch_v<F32E, 4>(P, v.G, s);
+      case 1: return launch_v<F32E, 1>(P, v, s);
+      case 2: return launch_v<F32E, 2>(P, v, s);
+      case 4: return launch_v<F32E, 4>(P, v, s);
       default: return hipErrorInvalidValue;
     }
   }
   switch (v.V) {
-    case 1: return launch_v<BF16E, 1>(P, v.G, s);
-    case 2: return launch_v<BF16E, 2>(P, v.G, s);
-    case 4: return launch_v<BF16E, 4>(P, v.G, s);
-    case 8: return launch_v<BF16E, 8>(P, v.G, s);
+    case 1: return launch_v<BF16E, 1>(P, v, s);
+    case 2: return launch_v<BF16E, 2>(P, v, s);
+    case 4: return launch_v<BF16E, 4>(P, v, s);
+    case 8: return launch_v<BF16E, 8>(P, v, s);
     default: return hipErrorInvalidValue;
   }
 }

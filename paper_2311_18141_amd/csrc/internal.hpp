@@ -53,14 +53,56 @@ struct FwdParams {
   int64_t row_blocks;    // workgroups of the row-split part (units come after)
 };
 
-// Kernel variant: G lanes per row (group), V elements per lane per load.
+// Kernel variant: G lanes per row (group), V elements per lane per load;
+// stream = one wave streams the non-zeros of 64 consecutive rows (G = 64).
 struct Variant {
   int G;
   int V;
+  bool stream = false;
 };
 
 // ---- launchers (defined in the .hip files) --------------------------------
 hipError_t launch_fwd(const FwdParams& P, Variant v, DT dt, hipStream_t s);
+
+// ---- batched persistent launch (batch.hip) --------------------------------
+struct BatchTileDev {
+  const int32_t* rowptr;
+  const int32_t* colind;
+  const float* values;
+  const Seg* seg;          // the tile's split-row units
+  const LongRow* lrow;     // the tile's split rows
+  int64_t rows;
+  int64_t N;
+  int64_t part_off;        // FP32 offset of this tile's partial rows in the workspace
+  int32_t long_row;
+  int32_t kind;            // 0 stream, 1 row-split
+  int32_t G;               // row-split lanes per row
+  int32_t V;               // stream / unit / fix-up vector width
+  int32_t ldp;             // partial row pitch (floats)
+  int32_t pad;
+};
+
+// type 0: rows [a, a+64) of `tile`, column window `window`; 1: split-row unit a; 2: split row a (fix-up).
+struct BatchItem {
+  int32_t tile, a, window, type;
+};
+
+struct BatchParams {
+  const BatchTileDev* tiles;
+  const BatchItem* items;
+  int64_t n_items;
+  const BatchItem* fix;
+  int64_t n_fix;
+  const void* const* B;    // device array: B[t]
+  const int64_t* ldb;      // device array
+  void* const* C;          // device array: C[t]
+  const int64_t* ldc;      // device array
+  float* partial;
+  unsigned* counter;
+  int accumulate;
+};
+hipError_t launch_batch(const BatchParams& P, DT dt, int grid, hipStream_t s);
+int batch_blocks_per_cu(DT dt);
 
 struct SddmmParams {
   const int32_t* rowid;

@@ -12,7 +12,7 @@ from typing import List, Optional, Sequence, Tuple
 import torch
 
 from . import _lib
-from ._lib import SpmmCsr, SpmmTileOpts, SpmmTileStats, check, lib
+from ._lib import SpmmCsr, SpmmTileOpts, SpmmTileStats, SpmmVariant, check, lib
 
 _DTYPES = {torch.float32: _lib.SPMM_F32, torch.bfloat16: _lib.SPMM_BF16}
 
@@ -132,6 +132,35 @@ def spmm_tile_export_transpose(tile: Tile, stream=None) -> Tuple[torch.Tensor, t
     return rpT, ciT, perm
 
 
+KERNELS = {"auto": _lib.SPMM_KERNEL_AUTO, "rowsplit": _lib.SPMM_KERNEL_ROWSPLIT, "stream": _lib.SPMM_KERNEL_STREAM}
+
+
+def spmm_tile_set_variant(tile: Tile, N: int, dtype=torch.float32, kind: Optional[str] = "auto",
+                          lanes: int = 0, vec: int = 0) -> None:
+    """Pin the forward kernel variant for width N (kind None clears the entry)."""
+    if kind is None:
+        check(lib().spmm_tile_set_variant(tile.handle, N, _DTYPES[dtype], None))
+        return
+    v = SpmmVariant(KERNELS[kind], lanes, vec)
+    check(lib().spmm_tile_set_variant(tile.handle, N, _DTYPES[dtype], ctypes.byref(v)))
+
+
+def spmm_tile_autotune(tile: Tile, Bs: Sequence[torch.Tensor], C: torch.Tensor, tune_plan: bool = True,
+                       stream: Optional[torch.cuda.Stream] = None) -> dict:
+    """Time the forward variants (and split thresholds) on these operands; keep the fastest."""
+    K = tile.num_k
+    ptrs = (ctypes.c_void_p * K)(*[B.data_ptr() for B in Bs])
+    lds = (ctypes.c_int64 * K)(*[_row_major_ld(B, "B") for B in Bs])
+    dt = Bs[0].dtype
+    N = Bs[0].shape[1]
+    out = SpmmVariant()
+    check(lib().spmm_tile_autotune(tile.handle, N, _DTYPES[dt], ptrs, lds, C.data_ptr(), _row_major_ld(C, "C"),
+                                   1 if tune_plan else 0, _stream_ptr(stream), ctypes.byref(out)))
+    tile._ws.pop("fwd", None)
+    inv = {v: k for k, v in KERNELS.items()}
+    return {"kind": inv[out.kind], "lanes": out.lanes, "vec": out.vec}
+
+
 def spmm_fwd_workspace_bytes(tile: Tile, N: int) -> int:
     n = ctypes.c_size_t()
     check(lib().spmm_fwd_workspace_bytes(tile.handle, N, ctypes.byref(n)))
@@ -205,3 +234,90 @@ def spmm_bwd(tile: Tile, dC: torch.Tensor, B: torch.Tensor, want_dA: bool = True
                          dA.data_ptr() if want_dA else None, dB.data_ptr() if want_dB else None, lddb,
                          ws_ptr, ws_n, _stream_ptr(stream)))
     return (dA if want_dA else None), (dB if want_dB else None)
+
+
+class Batch:
+    """A batched launch over many single-tile handles (see spmm_batch_create)."""
+
+    def __init__(self, handle: int, tiles: List[Tile], Ns: List[int], dtype):
+        self.handle = handle
+        self.tiles = tiles
+        self.Ns = Ns
+        self.dtype = dtype
+        self._ws = None
+        self._ptrs = {}
+
+    def workspace_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        check(lib().spmm_batch_workspace_bytes(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def workspace(self) -> Optional[torch.Tensor]:
+        nb = self.workspace_bytes()
+        if nb == 0:
+            return None
+        if self._ws is None or self._ws.numel() < nb:
+            self._ws = torch.empty(nb, dtype=torch.uint8, device=self.tiles[0].values[0].device)
+        return self._ws
+
+    def variant(self, t: int) -> dict:
+        v = SpmmVariant()
+        check(lib().spmm_batch_get_variant(self.handle, t, ctypes.byref(v)))
+        inv = {val: k for k, val in KERNELS.items()}
+        return {"kind": inv[v.kind], "lanes": v.lanes, "vec": v.vec}
+
+    def operand_arrays(self, Bs: Sequence[torch.Tensor], Cs: Sequence[torch.Tensor]):
+        """Device arrays of pointers and leading dimensions (cached per set of tensors)."""
+        key = tuple(B.data_ptr() for B in Bs) + tuple(C.data_ptr() for C in Cs)
+        arr = self._ptrs.get(key)
+        if arr is None:
+            esize = 4 if self.dtype == torch.float32 else 2
+            for t, (B, C) in enumerate(zip(Bs, Cs)):
+                if B.dtype != self.dtype or C.dtype != self.dtype:
+                    raise ValueError("operand %d has the wrong dtype" % t)
+                if B.shape != (self.tiles[t].cols[0], self.Ns[t]) or C.shape != (self.tiles[t].rows, self.Ns[t]):
+                    raise ValueError("operand %d has the wrong shape" % t)
+                for X, name in ((B, "B"), (C, "C")):
+                    ld = _row_major_ld(X, name)
+                    if X.data_ptr() % 16 or (ld * esize) % 16:
+                        raise ValueError("%s[%d] rows must start on 16-byte boundaries" % (name, t))
+            dev = Bs[0].device
+            mk = lambda xs: torch.tensor(xs, dtype=torch.int64).to(dev)
+            arr = (mk([B.data_ptr() for B in Bs]), mk([_row_major_ld(B, "B") for B in Bs]),
+                   mk([C.data_ptr() for C in Cs]), mk([_row_major_ld(C, "C") for C in Cs]))
+            self._ptrs = {key: arr}
+        return arr
+
+    def close(self):
+        if self.handle:
+            check(lib().spmm_batch_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def spmm_batch_create(tiles: Sequence[Tile], Ns: Sequence[int], dtype=torch.float32,
+                      stream: Optional[torch.cuda.Stream] = None) -> Batch:
+    arr = (ctypes.c_void_p * len(tiles))(*[t.handle for t in tiles])
+    ns = (ctypes.c_int64 * len(tiles))(*[int(n) for n in Ns])
+    h = ctypes.c_void_p()
+    check(lib().spmm_batch_create(len(tiles), arr, ns, _DTYPES[dtype], _stream_ptr(stream), ctypes.byref(h)))
+    return Batch(h.value, list(tiles), [int(n) for n in Ns], dtype)
+
+
+def spmm_batched(batch: Batch, Bs: Sequence[torch.Tensor], Cs: Sequence[torch.Tensor], accumulate: bool = False,
+                 workspace: Optional[torch.Tensor] = None, stream: Optional[torch.cuda.Stream] = None) -> None:
+    """C_t = [C_t] + A_t B_t for every tile of the batch, in one persistent launch."""
+    if len(Bs) != len(batch.tiles) or len(Cs) != len(batch.tiles):
+        raise ValueError("one B and one C per tile")
+    b, lb, c, lc = batch.operand_arrays(Bs, Cs)
+    if workspace is None:
+        workspace = batch.workspace()
+    ws_ptr = workspace.data_ptr() if workspace is not None else None
+    ws_n = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    check(lib().spmm_batched(batch.handle, b.data_ptr(), lb.data_ptr(), c.data_ptr(), lc.data_ptr(),
+                             1 if accumulate else 0, ws_ptr, ws_n, _stream_ptr(stream)))

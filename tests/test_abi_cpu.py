@@ -110,3 +110,22 @@ def test_null_handle_calls():
     assert L.spmm_fwd(None, 0, None, None, 0, None, 8, 0, 8, 0, None, 0, None) == 1
     assert L.spmm_bwd(None, None, 8, None, 8, 8, None, None, 8, None, 0, None) == 1
     assert L.spmm_tile_export_transpose(None, None, None, None, None) == 1
+
+
+def test_batch_and_variant_argument_errors():
+    L = _lib.lib()
+    n = ctypes.c_size_t()
+    out = ctypes.c_void_p(7)
+    ns = (ctypes.c_int64 * 1)(32)
+    assert L.spmm_batch_create(1, None, ns, 0, None, ctypes.byref(out)) == 1
+    assert L.spmm_batch_create(0, None, ns, 0, None, ctypes.byref(out)) == 1
+    tiles = (ctypes.c_void_p * 1)(None)
+    assert L.spmm_batch_create(1, tiles, ns, 0, None, ctypes.byref(out)) == 1
+    assert L.spmm_batch_create(1, tiles, ns, 0, None, None) == 1
+    assert L.spmm_batch_destroy(None) == 1
+    assert L.spmm_batch_workspace_bytes(None, ctypes.byref(n)) == 1
+    assert L.spmm_batch_get_variant(None, 0, None) == 1
+    assert L.spmm_batched(None, None, None, None, None, 0, None, 0, None) == 1
+    v = _lib.SpmmVariant(1, 8, 4)
+    assert L.spmm_tile_set_variant(None, 32, 0, ctypes.byref(v)) == 1
+    assert L.spmm_tile_autotune(None, 32, 0, None, None, None, 32, 0, None, None) == 1

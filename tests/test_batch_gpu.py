@@ -1,0 +1,123 @@
+"""Batched persistent launch: every tile of the batch against the FP64 oracle, graph replays."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from paper_2311_18141_amd import ops
+
+import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _rng(s):
+    return np.random.Generator(np.random.PCG64(s))
+
+
+def _tiles(count, seed, rows_hi=4096, value_kind="pm1", long_rows=False):
+    tiles, Ns = synth.uneven_tiles(count, seed, rows_lo=64, rows_hi=rows_hi, per_row_lo=0, per_row_hi=64)
+    rng = _rng(seed + 1)
+    out = []
+    for t in tiles:
+        L = t.row_lengths()
+        if long_rows and t.rows > 200:
+            L = L.copy()
+            L[rng.integers(0, t.rows, size=3)] = min(t.cols, 1500)
+        A = synth.random_csr(t.rows, t.cols, L, rng, value_kind)
+        out.append(A)
+    return out, Ns
+
+
+def _run(As, Ns, dtype=torch.float32, kw=None, variants=None, accumulate=False, value_kind="pm1", seed=0):
+    rng = _rng(seed)
+    handles = [G.make_tile([A], **(kw or {})) for A in As]
+    if variants is not None:
+        for h, N, v in zip(handles, Ns, variants):
+            ops.spmm_tile_set_variant(h, N, dtype, *v)
+    Bh = [synth.dense(A.cols, N, rng, value_kind) for A, N in zip(As, Ns)]
+    C0 = [synth.dense(A.rows, N, rng, value_kind) for A, N in zip(As, Ns)]
+    Bs = [G.dense_dev(b, dtype) for b in Bh]
+    Cs = [G.dense_dev(c, dtype) for c in C0]
+    batch = ops.spmm_batch_create(handles, Ns, dtype)
+    ops.spmm_batched(batch, Bs, Cs, accumulate=accumulate)
+    torch.cuda.synchronize()
+    return handles, batch, Bh, C0, Bs, Cs
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("long_rows", [False, True])
+def test_batch_matches_oracle(dtype, long_rows):
+    G.note("batch dtype=%s long_rows=%s" % (dtype, long_rows))
+    As, Ns = _tiles(24, 3, long_rows=long_rows)
+    kw = dict(long_row=256, segment=128) if long_rows else {}
+    handles, batch, Bh, C0, Bs, Cs = _run(As, Ns, dtype, kw, seed=4)
+    for t, (A, N) in enumerate(zip(As, Ns)):
+        got = G.host_f32(Cs[t])
+        if dtype == torch.float32:
+            ref, S = G.oracle_fwd([A], [Bh[t]])
+            G.assert_fp32_close(got, ref, S, G.row_terms([A]), what="tile %d %s" % (t, batch.variant(t)))
+        else:
+            ref, S = G.oracle_fwd([A], [G.bf16_as_f32(Bh[t])])
+            G.assert_bf16_close(got, ref, S, what="tile %d" % t)
+
+
+@pytest.mark.parametrize("variant", [("stream", 0, 1), ("stream", 0, 2), ("stream", 0, 4),
+                                     ("rowsplit", 8, 0), ("rowsplit", 16, 0), ("rowsplit", 32, 0),
+                                     ("rowsplit", 64, 0)])
+def test_batch_variants_integer_exact(variant):
+    G.note("batch variant %s" % (variant,))
+    As, Ns = _tiles(12, 5, value_kind="int8", long_rows=True)
+    Ns = [128] * len(As)
+    handles, batch, Bh, C0, Bs, Cs = _run(As, Ns, kw=dict(long_row=256, segment=100), value_kind="int8",
+                                          variants=[variant] * len(As), accumulate=True, seed=6)
+    for t, A in enumerate(As):
+        ref, _ = G.oracle_fwd([A], [Bh[t]], accumulate=True, C0=C0[t])
+        assert np.array_equal(G.host_f32(Cs[t]).astype(np.float64), ref), (t, variant, batch.variant(t))
+
+
+def test_batch_graph_replay_deterministic():
+    G.note("batch graph replay")
+    As, Ns = _tiles(40, 7, long_rows=True)
+    handles, batch, Bh, C0, Bs, Cs = _run(As, Ns, kw=dict(long_row=256, segment=128), seed=8)
+    eager = [c.clone() for c in Cs]
+    ws = batch.workspace()
+    ops.spmm_batched(batch, Bs, Cs, workspace=ws)
+    torch.cuda.synchronize()
+    for c, e in zip(Cs, eager):
+        assert torch.equal(c, e)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ops.spmm_batched(batch, Bs, Cs, workspace=ws)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ops.spmm_batched(batch, Bs, Cs, workspace=ws)
+    for r in range(5):
+        for c in Cs:
+            c.fill_(float("nan"))
+        _ = (Bs[0] * 3).sum()
+        g.replay()
+        torch.cuda.synchronize()
+        for t, (c, e) in enumerate(zip(Cs, eager)):
+            assert torch.equal(c, e), (r, t)
+
+
+def test_batch_autotuned_tiles():
+    """Per-tile variants chosen by the autotuner, then one persistent launch."""
+    G.note("batch autotuned")
+    As, Ns = _tiles(16, 9, rows_hi=8192)
+    rng = _rng(10)
+    handles = [G.make_tile([A]) for A in As]
+    Bh = [synth.dense(A.cols, N, rng) for A, N in zip(As, Ns)]
+    Bs = [G.dense_dev(b) for b in Bh]
+    Cs = [torch.empty(A.rows, N, device=G.DEV) for A, N in zip(As, Ns)]
+    for h, B, C in zip(handles, Bs, Cs):
+        ops.spmm_tile_autotune(h, [B], C, tune_plan=False)
+    batch = ops.spmm_batch_create(handles, Ns)
+    ops.spmm_batched(batch, Bs, Cs)
+    torch.cuda.synchronize()
+    for t, A in enumerate(As):
+        ref, S = G.oracle_fwd([A], [Bh[t]])
+        G.assert_fp32_close(G.host_f32(Cs[t]), ref, S, G.row_terms([A]), what="tile %d %s" % (t, batch.variant(t)))

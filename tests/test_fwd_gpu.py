@@ -17,6 +17,13 @@ def _rng(s):
     return np.random.Generator(np.random.PCG64(s))
 
 
+KINDS = ["rowsplit", "stream"]
+
+
+def _pin(tile, N, kind, dtype=torch.float32, lanes=0, vec=0):
+    ops.spmm_tile_set_variant(tile, N, dtype, kind, lanes, vec)
+
+
 def _blockdiag_3x3(value_rng):
     """All 2^9 patterns of a 3x3 block on the diagonal of a 1536 x 1536 tile, small-integer values."""
     rows, cols, vals = [], [], []
@@ -34,38 +41,43 @@ def _blockdiag_3x3(value_rng):
                      np.array(vals, np.float32))
 
 
+@pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("N", [1, 32, 33, 64, 128, 256])
-def test_all_3x3_patterns_exact(N):
-    G.note("all_3x3_patterns N=%d" % N)
+def test_all_3x3_patterns_exact(N, kind):
+    G.note("all_3x3_patterns N=%d %s" % (N, kind))
     rng = _rng(100 + N)
     A = _blockdiag_3x3(rng)
     B = synth.dense(1536, N, rng, "int4")
     tile = G.make_tile([A], validate=True)
+    _pin(tile, N, kind)
     got = G.host_f32(G.fwd(tile, [G.dense_dev(B)]))
     ref, _ = G.oracle_fwd([A], [B])
     assert np.array_equal(got.astype(np.float64), ref)
 
 
-@pytest.mark.parametrize("M", [1, 2, 63, 64, 65])
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("M", [1, 2, 63, 64, 65, 200])
 @pytest.mark.parametrize("N", [1, 32, 33, 64, 128, 256])
-def test_small_shapes(M, N):
-    G.note("small_shapes M=%d N=%d" % (M, N))
+def test_small_shapes(M, N, kind):
+    G.note("small_shapes M=%d N=%d %s" % (M, N, kind))
     rng = _rng(M * 1000 + N)
     lengths = rng.integers(0, 41, size=M)
     lengths[rng.random(M) < 0.25] = 0
     A = synth.random_csr(M, 97, lengths, rng)
     B = synth.dense(97, N, rng)
     tile = G.make_tile([A], validate=True)
+    _pin(tile, N, kind)
     got = G.host_f32(G.fwd(tile, [G.dense_dev(B)]))
     ref, S = G.oracle_fwd([A], [B])
     G.assert_fp32_close(got, ref, S, G.row_terms([A]), what="M=%d N=%d" % (M, N))
 
 
+@pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("N", [32, 128])
 @pytest.mark.parametrize("split", [False, True])
-def test_integer_exact_with_long_rows(N, split):
+def test_integer_exact_with_long_rows(N, split, kind):
     """Integer values and B in [-8, 8]: every partial sum is an integer below 2^24, so any order is exact."""
-    G.note("integer_exact N=%d split=%s" % (N, split))
+    G.note("integer_exact N=%d split=%s %s" % (N, split, kind))
     rng = _rng(7 + N + split)
     M, K = 3001, 60000
     lengths = rng.integers(0, 200, size=M)
@@ -75,6 +87,7 @@ def test_integer_exact_with_long_rows(N, split):
     B = synth.dense(K, N, rng, "int8")
     kw = dict(long_row=16, segment=8) if split else {}
     tile = G.make_tile([A], validate=True, **kw)
+    _pin(tile, N, kind)
     st = tile.stats()
     assert st["max_row"] == 50000 and st["long_rows"] >= 2
     got = G.host_f32(G.fwd(tile, [G.dense_dev(B)]))
@@ -98,10 +111,11 @@ def test_identity_and_permutation_exact(dtype):
     assert torch.equal(got, Bd[torch.from_numpy(pi).long().to(Bd.device)])
 
 
-@pytest.mark.parametrize("K", [2, 3, 4])
-def test_k_tiles_and_offsets(K):
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("K", [2, 3, 4, 7])
+def test_k_tiles_and_offsets(K, kind):
     """Section 2.1 / Algorithm 2: a tile row of K k-tiles; every k offset gives the untiled product."""
-    G.note("k_tiles K=%d" % K)
+    G.note("k_tiles K=%d %s" % (K, kind))
     rng = _rng(40 + K)
     M, cols, N = 2049, 3001, 64
     lengths = rng.integers(0, 120, size=M)
@@ -118,6 +132,7 @@ def test_k_tiles_and_offsets(K):
                                (full.colind[sel] - c0).astype(np.int32), full.values[sel].copy()))
         Bs.append(np.ascontiguousarray(B[c0:c1]))
     tile = G.make_tile(tiles, validate=True, long_row=256, segment=128)
+    _pin(tile, N, kind)
     Bd = [G.dense_dev(b) for b in Bs]
     ref, _ = G.oracle_fwd([full], [B])
     outs = []
@@ -129,6 +144,7 @@ def test_k_tiles_and_offsets(K):
     fv = [synth.CSR(t.rows, t.cols, t.rowptr, t.colind, synth.uniform_pm1(rng, t.nnz)) for t in tiles]
     Bf = [synth.dense(b.shape[0], N, rng) for b in Bs]
     tile2 = G.make_tile(fv, long_row=256, segment=128)
+    _pin(tile2, N, kind)
     Bfd = [G.dense_dev(b) for b in Bf]
     for off in range(K):
         got = G.host_f32(G.fwd(tile2, Bfd, k_offset=off))
@@ -136,8 +152,9 @@ def test_k_tiles_and_offsets(K):
         G.assert_fp32_close(got, ref2, S2, G.row_terms(fv), what="off=%d" % off)
 
 
-def test_accumulate_and_leading_dims():
-    G.note("accumulate_and_leading_dims")
+@pytest.mark.parametrize("kind", KINDS)
+def test_accumulate_and_leading_dims(kind):
+    G.note("accumulate_and_leading_dims %s" % kind)
     rng = _rng(50)
     M, K, N = 1000, 800, 96
     lengths = rng.integers(0, 50, size=M)
@@ -146,6 +163,7 @@ def test_accumulate_and_leading_dims():
     B = synth.dense(K, N, rng)
     C0 = synth.dense(M, N, rng)
     tile = G.make_tile([A], long_row=100, segment=64)
+    _pin(tile, N, kind)
     Bd = G.dense_dev(B, ld=N + 8)
     Cd = G.dense_dev(C0, ld=N + 4)
     assert Bd.stride(0) == N + 8 and Cd.stride(0) == N + 4
@@ -154,10 +172,11 @@ def test_accumulate_and_leading_dims():
     G.assert_fp32_close(G.host_f32(Cd), ref, S + np.abs(C0), G.row_terms([A]) + 1)
 
 
+@pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("N", [32, 128, 256])
-def test_bf16_storage(N):
+def test_bf16_storage(N, kind):
     """B and C in BF16, FP32 products and sums, C rounded once."""
-    G.note("bf16 N=%d" % N)
+    G.note("bf16 N=%d %s" % (N, kind))
     rng = _rng(60 + N)
     M = K = 4096
     lengths = rng.integers(0, 64, size=M)
@@ -165,6 +184,7 @@ def test_bf16_storage(N):
     A = synth.random_csr(M, K, lengths, rng)
     B = synth.dense(K, N, rng)
     tile = G.make_tile([A], long_row=512, segment=256)
+    _pin(tile, N, kind, torch.bfloat16)
     got = G.host_f32(G.fwd(tile, [G.dense_dev(B, torch.bfloat16)]))
     Bt = G.bf16_as_f32(B)
     ref, S = G.oracle_fwd([A], [Bt])
@@ -172,15 +192,18 @@ def test_bf16_storage(N):
     # small integers stay exact in BF16 (|C| <= 64, row length <= 4)
     Ai = synth.random_csr(M, K, rng.integers(0, 5, size=M), rng, "int4")
     Bi = synth.dense(K, N, rng, "int4")
-    got = G.host_f32(G.fwd(G.make_tile([Ai]), [G.dense_dev(Bi, torch.bfloat16)]))
+    ti = G.make_tile([Ai])
+    _pin(ti, N, kind, torch.bfloat16)
+    got = G.host_f32(G.fwd(ti, [G.dense_dev(Bi, torch.bfloat16)]))
     ref, _ = G.oracle_fwd([Ai], [Bi])
     assert np.array_equal(got.astype(np.float64), ref)
 
 
+@pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("N", [32, 128])
-def test_workload_shapes_scaled(N):
+def test_workload_shapes_scaled(N, kind):
     """Scaled-down versions of the workloads: uniform, R-MAT row block, heavy-tailed rows."""
-    G.note("workload_shapes_scaled N=%d" % N)
+    G.note("workload_shapes_scaled N=%d %s" % (N, kind))
     cases = []
     er = synth.uniform_csr(4096, 4096, 16, seed=1)
     cases.append(("uniform", [er]))
@@ -192,17 +215,20 @@ def test_workload_shapes_scaled(N):
     for name, tiles in cases:
         Bs = [synth.dense(t.cols, N, rng) for t in tiles]
         tile = G.make_tile(tiles, validate=True)
+        _pin(tile, N, kind)
         got = G.host_f32(G.fwd(tile, [G.dense_dev(b) for b in Bs]))
         ref, S = G.oracle_fwd(tiles, Bs)
         G.assert_fp32_close(got, ref, S, G.row_terms(tiles), what=name)
 
 
-def test_deterministic_and_graph_replay():
-    G.note("deterministic_and_graph_replay")
+@pytest.mark.parametrize("kind", KINDS)
+def test_deterministic_and_graph_replay(kind):
+    G.note("deterministic_and_graph_replay %s" % kind)
     rng = _rng(80)
     A = synth.powerlaw_csr(1 << 14, 1 << 14, 32, 8192, seed=8)
     B = synth.dense(A.cols, 128, rng, "normal")
     tile = G.make_tile([A], long_row=256, segment=128)
+    _pin(tile, 128, kind)
     Bd = G.dense_dev(B)
     C1 = G.fwd(tile, [Bd]).clone()
     C2 = G.fwd(tile, [Bd]).clone()
@@ -260,3 +286,48 @@ def test_forward_argument_errors():
     assert e.value.status == 4
     with pytest.raises(ValueError):
         ops.spmm_fwd(tile, [B, B])
+
+
+def test_variants_agree_bitwise_on_integers():
+    """Every forward variant gives the same integer-valued C (an order-free exact result)."""
+    G.note("variants_agree_bitwise")
+    rng = _rng(90)
+    g = synth.rmat_row_block(13, 16, 4, 0, seed=9)
+    tiles = [synth.CSR(t.rows, t.cols, t.rowptr, t.colind, synth.draw_values(rng, t.nnz, "int8")) for t in g.tiles]
+    N = 64
+    Bs = [synth.dense(t.cols, N, rng, "int8") for t in tiles]
+    ref, _ = G.oracle_fwd(tiles, Bs)
+    Bd = [G.dense_dev(b) for b in Bs]
+    tile = G.make_tile(tiles, long_row=64, segment=32)
+    for kind, lanes, vec in [("rowsplit", 4, 1), ("rowsplit", 8, 2), ("rowsplit", 16, 4), ("rowsplit", 32, 2),
+                             ("rowsplit", 64, 1), ("stream", 0, 1), ("stream", 0, 2), ("stream", 0, 4)]:
+        _pin(tile, N, kind, lanes=lanes, vec=vec)
+        got = G.host_f32(G.fwd(tile, Bd))
+        assert np.array_equal(got.astype(np.float64), ref), (kind, lanes, vec)
+
+
+def test_autotune_keeps_results():
+    G.note("autotune")
+    rng = _rng(91)
+    A = synth.powerlaw_csr(1 << 15, 1 << 15, 32, 8192, seed=10)
+    N = 128
+    B = synth.dense(A.cols, N, rng)
+    tile = G.make_tile([A])
+    Bd = G.dense_dev(B)
+    C = torch.empty(A.rows, N, device=G.DEV)
+    chosen = ops.spmm_tile_autotune(tile, [Bd], C, tune_plan=True)
+    assert chosen["kind"] in ("rowsplit", "stream")
+    got = G.host_f32(G.fwd(tile, [Bd]))
+    ref, S = G.oracle_fwd([A], [B])
+    G.assert_fp32_close(got, ref, S, G.row_terms([A]), what=str(chosen))
+
+
+def test_variant_argument_errors():
+    G.note("variant_argument_errors")
+    A = synth.uniform_csr(64, 64, 4, seed=9)
+    tile = G.make_tile([A])
+    with pytest.raises(SpmmError):
+        ops.spmm_tile_set_variant(tile, 32, torch.float32, "rowsplit", lanes=3)
+    with pytest.raises(SpmmError):
+        ops.spmm_tile_set_variant(tile, 32, torch.float32, "rowsplit", vec=8)
+    ops.spmm_tile_set_variant(tile, 32, torch.float32, None)
