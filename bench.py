@@ -14,6 +14,9 @@ times dense B_k of 1,048,576 x 128 FP32, accumulated over its 4 k-tiles into a
                             forward + dA (sampled dense-dense product) + dB = A^T dC
     rmat23_n256_bf16        R-MAT scale 23, edge factor 32, N = 256, BF16 B and C
     rmat23_n256_f32         the same with FP32 B and C
+    uneven512_batched       512 uneven tiles (rows 1,024..65,536, 4..256 non-zeros per row,
+                            N_t in {32..256}) in one persistent launch, per-tile autotuned
+                            variants; the per-tile launch loop is reported beside it
 
 value = 2 * nnz * N * passes / step time (GFLOP/s).  The roofline object prices
 the step's kernels with their algorithmic bytes (CSR arrays + dense inputs read
@@ -201,6 +204,93 @@ class ForwardBackward(Workload):
                            % (r, len(cols), A.rows))
 
 
+class Batched(Workload):
+    """Many independent uneven tiles in one persistent launch, per-tile variants from the autotuner."""
+
+    def __init__(self, name, count, config):
+        self.name = name
+        self.count = count
+        self.config = config
+        self.kernel = "spmm_batched (batch_main + batch_fixup)"
+
+    def setup(self):
+        import torch
+        import synth
+        from paper_2311_18141_amd import ops
+        t0 = time.time()
+        self.tiles, self.Ns = synth.uneven_tiles(self.count, seed=self.config.get("seed", 4))
+        _log("%s: %d tiles generated in %.1f s (nnz %d)" % (self.name, self.count, time.time() - t0,
+                                                            sum(t.nnz for t in self.tiles)))
+        rng = synth.streams(self.config.get("seed", 4))[3]
+        dev = "cuda:0"
+        self.handles, self.B, self.C, self.Bh = [], [], [], []
+        for t, N in zip(self.tiles, self.Ns):
+            b = synth.dense(t.cols, N, rng)
+            self.Bh.append(b)
+            self.B.append(torch.from_numpy(b).to(dev))
+            self.C.append(torch.empty(t.rows, N, device=dev))
+            d = (torch.from_numpy(t.rowptr).to(dev), torch.from_numpy(t.colind).to(dev),
+                 torch.from_numpy(t.values).to(dev), t.cols)
+            self.handles.append(ops.spmm_tile_create(t.rows, [d], validate=True, **HANDLE_OPTS))
+        torch.cuda.synchronize()
+        # Reference point: one spmm_fwd launch per tile with the library's default variant.
+        self.loop_ms = self._time(self._loop, reps=5)
+        t0 = time.time()
+        for h, B, C in zip(self.handles, self.B, self.C):
+            ops.spmm_tile_autotune(h, [B], C, tune_plan=False)
+        _log("%s: autotuned %d tiles in %.1f s" % (self.name, self.count, time.time() - t0))
+        self.batch = ops.spmm_batch_create(self.handles, self.Ns)
+        self.ws = self.batch.workspace()
+        kinds = {}
+        for t in range(self.count):
+            v = self.batch.variant(t)
+            key = "%s/%d/%d" % (v["kind"], v["lanes"], v["vec"])
+            kinds[key] = kinds.get(key, 0) + 1
+        nnz = sum(t.nnz for t in self.tiles)
+        self.flops = sum(2.0 * t.nnz * N for t, N in zip(self.tiles, self.Ns))
+        self.alg_bytes = float(sum(8 * t.nnz + 4 * (t.rows + 1) + 4 * (t.cols + t.rows) * N
+                                   for t, N in zip(self.tiles, self.Ns)))
+        self.config = dict(self.config, tiles=self.count, nnz=nnz, rows=sum(t.rows for t in self.tiles),
+                           variants=kinds,
+                           per_tile_loop={"ms": round(self.loop_ms, 4),
+                                          "gflops": round(self.flops / (self.loop_ms * 1e-3) / 1e9, 1)})
+
+    def _loop(self):
+        from paper_2311_18141_amd import ops
+        for h, B, C in zip(self.handles, self.B, self.C):
+            ops.spmm_fwd(h, [B], C=C)
+
+    @staticmethod
+    def _time(fn, reps):
+        import torch
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def step(self):
+        from paper_2311_18141_amd import ops
+        ops.spmm_batched(self.batch, self.B, self.C, workspace=self.ws)
+
+    def cpu_sample(self):
+        import oracle
+        flops, t_total, used = 0.0, 0.0, 0
+        for t, N, b in zip(self.tiles, self.Ns, self.Bh):
+            t0 = time.perf_counter()
+            oracle.spmm([(t.rowptr, t.colind, t.values)], [b], scale=False)
+            t_total += time.perf_counter() - t0
+            flops += 2.0 * t.nnz * N
+            used += 1
+            if t_total > 15.0:
+                break
+        return flops, t_total, "oracle FP64 forward on the first %d of %d tiles" % (used, self.count)
+
+
 class CopyCalibration(Workload):
     """A plain device copy of 1 GiB: the reference against which HBM counters are scaled."""
 
@@ -231,6 +321,10 @@ def workloads():
     import synth
     return {
         "copy_1gib": lambda: CopyCalibration(),
+        "uneven512_batched": lambda: Batched(
+            "uneven512_batched", 512,
+            {"workload": "uneven512_batched", "matrix": "512 square tiles, rows log-uniform in [1024, 65536], "
+             "r_t uniform in [4, 256] non-zeros per row, N_t in {32, 64, 128, 256}", "seed": 4}),
         "rmat22_rowblock0_4x4_n128": lambda: TileRowForward(
             "rmat22_rowblock0_4x4_n128",
             lambda: synth.rmat_row_block(22, 16, 4, 0, seed=2).tiles, 128, "f32",

@@ -70,6 +70,8 @@ typedef struct {
   int32_t long_row;        /* rows whose length over all k-tiles exceeds this are split across
                               work units with a deterministic fix-up; 0 = library default */
   int32_t segment;         /* non-zeros per split work unit; 0 = library default */
+  int32_t bwd_slice;       /* spmm_bwd computes dA in column slices of this width, one launch
+                              per slice, so a slice of B can stay cache-resident; 0 = one launch */
 } spmm_tile_opts;
 
 /* Opaque handle to one tile row (A_i0 ... A_i,K-1): the sparse operand of one C

@@ -32,7 +32,7 @@ class SpmmCsr(ctypes.Structure):
 
 
 class SpmmTileOpts(ctypes.Structure):
-    _fields_ = [("flags", c_uint), ("long_row", c_i32), ("segment", c_i32)]
+    _fields_ = [("flags", c_uint), ("long_row", c_i32), ("segment", c_i32), ("bwd_slice", c_i32)]
 
 
 class SpmmTileStats(ctypes.Structure):

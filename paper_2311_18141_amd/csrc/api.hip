@@ -166,6 +166,7 @@ struct spmm_tile_s {
   };
   VarEntry vt[16];
   int nvt = 0;
+  int64_t bwd_slice = 0;   // SDDMM column slice (0 = all columns in one launch)
 
   ~spmm_tile_s() {
     free_plan(plan);
@@ -269,7 +270,8 @@ spmm_status spmm_tile_create(int64_t rows, int num_k, const spmm_csr* tiles, con
   if (flags & ~(SPMM_TILE_VALIDATE | SPMM_TILE_TRANSPOSE)) return fail(SPMM_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
   int32_t long_row = (opts && opts->long_row > 0) ? opts->long_row : kDefaultLongRow;
   int32_t segment = (opts && opts->segment > 0) ? opts->segment : kDefaultSegment;
-  if (opts && (opts->long_row < 0 || opts->segment < 0)) return fail(SPMM_ERR_INVALID_ARG, "negative long_row/segment");
+  if (opts && (opts->long_row < 0 || opts->segment < 0 || opts->bwd_slice < 0))
+    return fail(SPMM_ERR_INVALID_ARG, "negative long_row/segment/bwd_slice");
   int64_t units_bound = 0;
   for (int k = 0; k < num_k; ++k) {
     const spmm_csr& t = tiles[k];
@@ -290,6 +292,7 @@ spmm_status spmm_tile_create(int64_t rows, int num_k, const spmm_csr* tiles, con
   h->rows = rows;
   h->num_k = num_k;
   for (int k = 0; k < num_k; ++k) h->t[k] = tiles[k];
+  h->bwd_slice = opts ? opts->bwd_slice : 0;
   (void)hipGetDevice(&h->device);
 
   auto body = [&]() -> spmm_status {
@@ -635,10 +638,17 @@ spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* 
                         (uintptr_t)(ldb * 4);
     int V = 4;
     while (V > 1 && ((N % V) != 0 || (a % (uintptr_t)(V * 4)) != 0)) V /= 2;
-    const int64_t need_lanes = (N + V - 1) / V;
+    // Column slices: one launch per slice of `slice` columns (all of N when 0).
+    const int64_t slice = (A->bwd_slice > 0 && A->bwd_slice < N && (A->bwd_slice % V) == 0) ? A->bwd_slice : N;
+    const int64_t need_lanes = (slice + V - 1) / V;
     int G = 4;
     while (G < 16 && G * 2 <= need_lanes) G *= 2;
-    HIP_TRY(spmm::launch_sddmm(P, spmm::Variant{G, V}, s));
+    for (int64_t c = 0; c < N; c += slice) {
+      P.c_begin = c;
+      P.c_end = c + slice < N ? c + slice : N;
+      P.accumulate = c > 0 ? 1 : 0;
+      HIP_TRY(spmm::launch_sddmm(P, spmm::Variant{G, V}, s));
+    }
   }
   if (dB && t.cols > 0) {
     spmm::FwdParams P{};

@@ -86,7 +86,8 @@ __device__ __forceinline__ void item_stream(const BatchTileDev& bt, const Ops<E>
     }
   }
   const uint64_t ldbb = (uint64_t)(op.ldb * (int64_t)sizeof(T));
-  const uint64_t base = reinterpret_cast<uint64_t>(op.B) + (uint64_t)(cl * (int64_t)sizeof(T));
+  const uint64_t base = reinterpret_cast<uint64_t>(op.B);
+  const uint64_t coff = (uint64_t)(cl * (int64_t)sizeof(T));  // this lane's columns, added after the broadcast
   for (int32_t qc = 0; qc < total; qc += 64) {
     const int n = min(64, total - qc);
     const int32_t q = qc + lane;
@@ -114,7 +115,7 @@ __device__ __forceinline__ void item_stream(const BatchTileDev& bt, const Ops<E>
         const int jj = min(u0 + u, n - 1);
         const uint64_t a = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)ahi, jj) << 32) |
                            (uint32_t)__builtin_amdgcn_readlane((int)alo, jj);
-        load_vec_at<E, V>(a, bv[u]);
+        load_vec_at<E, V>(a + coff, bv[u]);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {

@@ -5,7 +5,9 @@
 // A group of G lanes owns one non-zero; each lane loads V consecutive columns of
 // dC's row and B's row per step (coalesced within the group), accumulates the
 // partial dot product in FP32 and the group reduces with a fixed butterfly, so
-// the result does not depend on scheduling.
+// the result does not depend on scheduling.  One launch covers the columns
+// [c_begin, c_end); the host may split N into column slices launched one after
+// the other (each adding to dA), so that one slice of B stays cache-resident.
 #include "elem.hpp"
 #include "internal.hpp"
 
@@ -30,7 +32,7 @@ __global__ void __launch_bounds__(kBlock) sddmm_kernel(SddmmParams P) {
   const float* g = P.dC + i * P.lddc;
   const float* b = P.B + j * P.ldb;
   float acc = 0.0f;
-  for (int64_t c = (int64_t)gl * V; c < P.N; c += G * V) {
+  for (int64_t c = P.c_begin + (int64_t)gl * V; c < P.c_end; c += G * V) {
     float x[V], y[V];
     load_f32v<V>(g + c, x);
     load_f32v<V>(b + c, y);
@@ -38,7 +40,7 @@ __global__ void __launch_bounds__(kBlock) sddmm_kernel(SddmmParams P) {
     for (int e = 0; e < V; ++e) acc = fmaf(x[e], y[e], acc);
   }
   acc = group_sum<G>(acc);
-  if (gl == 0) P.dA[p] = acc;
+  if (gl == 0) P.dA[p] = P.accumulate ? P.dA[p] + acc : acc;
 }
 
 template <int V>

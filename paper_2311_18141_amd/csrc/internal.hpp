@@ -114,6 +114,8 @@ struct SddmmParams {
   int64_t ldb;
   int64_t N;
   float* dA;
+  int64_t c_begin, c_end;  // column range of this launch
+  int accumulate;          // add to dA (later slices)
 };
 hipError_t launch_sddmm(const SddmmParams& P, Variant v, hipStream_t s);
 

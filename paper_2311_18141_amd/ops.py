@@ -86,7 +86,7 @@ class Tile:
 
 def spmm_tile_create(rows: int, tiles: Sequence[Tuple[torch.Tensor, torch.Tensor, torch.Tensor, int]],
                      validate: bool = False, transpose: bool = False, long_row: int = 0, segment: int = 0,
-                     stream: Optional[torch.cuda.Stream] = None) -> Tile:
+                     bwd_slice: int = 0, stream: Optional[torch.cuda.Stream] = None) -> Tile:
     """Create a handle from k-tiles given as (rowptr int32, colind int32, values float32, cols)."""
     K = len(tiles)
     arr = (SpmmCsr * max(K, 1))()
@@ -113,6 +113,7 @@ def spmm_tile_create(rows: int, tiles: Sequence[Tuple[torch.Tensor, torch.Tensor
     opts.flags = (_lib.SPMM_TILE_VALIDATE if validate else 0) | (_lib.SPMM_TILE_TRANSPOSE if transpose else 0)
     opts.long_row = long_row
     opts.segment = segment
+    opts.bwd_slice = bwd_slice
     h = ctypes.c_void_p()
     check(lib().spmm_tile_create(rows, K, arr, ctypes.byref(opts), _stream_ptr(stream), ctypes.byref(h)))
     return Tile(h.value, rows, cols, nnz, keep, vals)

@@ -77,9 +77,10 @@ def test_backward_vs_oracle(name, N):
     G.assert_fp32_close(G.host_f32(dB), rB, SB, cnt, what="dB")
 
 
+@pytest.mark.parametrize("bwd_slice", [0, 16, 32])
 @pytest.mark.parametrize("split", [False, True])
-def test_backward_integer_exact(split):
-    G.note("backward_integer_exact split=%s" % split)
+def test_backward_integer_exact(split, bwd_slice):
+    G.note("backward_integer_exact split=%s slice=%d" % (split, bwd_slice))
     rng = _rng(90 + split)
     M, K, N = 5000, 3000, 64
     L = rng.integers(0, 40, size=M)
@@ -88,7 +89,7 @@ def test_backward_integer_exact(split):
     B = synth.dense(K, N, rng, "int8")
     dC = synth.dense(M, N, rng, "int8")
     kw = dict(long_row=8, segment=4) if split else {}
-    tile = G.make_tile([A], transpose=True, **kw)
+    tile = G.make_tile([A], transpose=True, bwd_slice=bwd_slice, **kw)
     dA, dB = ops.spmm_bwd(tile, G.dense_dev(dC), G.dense_dev(B))
     torch.cuda.synchronize()
     rA, _ = oracle.sddmm(A.rowptr, A.colind, dC, B)
