@@ -39,10 +39,43 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 HANDLE_OPTS = {}
+AUTOTUNE = True
 
 
 def _log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_digest() -> str:
+    """SHA-256 over the HIP sources, to tell whether stored counter readings still describe the kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2311_18141_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def stored_traffic(workload: str):
+    """HBM bytes per step measured by rocprofv3 counters (profiles/traffic_<workload>.md), or None when
+    absent or taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.md" % workload)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("source_sha256") != kernel_source_digest():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_step"])
+    except (KeyError, ValueError):
+        return None
 
 
 def _threads():
@@ -107,6 +140,11 @@ class TileRowForward(Workload):
         self.B = [torch.from_numpy(b).to(tdt).to(dev) for b in self.Bh]
         self.tile = ops.spmm_tile_create(self.tiles[0].rows, self.dev_tiles, validate=True, **HANDLE_OPTS)
         self.C = torch.empty(self.tiles[0].rows, self.N, dtype=tdt, device=dev)
+        if AUTOTUNE:
+            t0 = time.time()
+            chosen = ops.spmm_tile_autotune(self.tile, self.B, self.C, tune_plan=True)
+            _log("%s: autotuned in %.1f s: %s" % (self.name, time.time() - t0, chosen))
+            self.config["variant"] = chosen
         self.ws = self.tile.workspace(self.N)
         nnz = sum(t.nnz for t in self.tiles)
         self.flops = 2.0 * nnz * self.N
@@ -164,6 +202,11 @@ class ForwardBackward(Workload):
         self.B = torch.from_numpy(self.Bh).to(dev)
         self.dC = torch.from_numpy(self.dCh).to(dev)
         self.C = torch.empty(self.A.rows, self.N, device=dev)
+        if AUTOTUNE:
+            t0 = time.time()
+            chosen = ops.spmm_tile_autotune(self.tile, [self.B], self.C, tune_plan=True)
+            _log("%s: forward autotuned in %.1f s: %s" % (self.name, time.time() - t0, chosen))
+            self.config["variant"] = chosen
         self.dA = torch.empty(self.A.nnz, device=dev)
         self.dB = torch.empty(self.A.cols, self.N, device=dev)
         self.wsf = self.tile.workspace(self.N, "fwd")
@@ -236,8 +279,9 @@ class Batched(Workload):
         # Reference point: one spmm_fwd launch per tile with the library's default variant.
         self.loop_ms = self._time(self._loop, reps=5)
         t0 = time.time()
-        for h, B, C in zip(self.handles, self.B, self.C):
-            ops.spmm_tile_autotune(h, [B], C, tune_plan=False)
+        if AUTOTUNE:
+            for h, B, C in zip(self.handles, self.B, self.C):
+                ops.spmm_tile_autotune(h, [B], C, tune_plan=False)
         _log("%s: autotuned %d tiles in %.1f s" % (self.name, self.count, time.time() - t0))
         self.batch = ops.spmm_batch_create(self.handles, self.Ns)
         self.ws = self.batch.workspace()
@@ -355,7 +399,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--long-row", type=int, default=0, help="split-row threshold (0 = library default)")
     ap.add_argument("--segment", type=int, default=0, help="non-zeros per split unit (0 = library default)")
+    ap.add_argument("--no-autotune", action="store_true", help="use the library's default variant and plan")
     args = ap.parse_args()
+    global AUTOTUNE
+    AUTOTUNE = not args.no_autotune
     HANDLE_OPTS.update(long_row=args.long_row, segment=args.segment)
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the stationary-C tile row is "
@@ -408,7 +455,8 @@ def main():
         "config": wl.config,
         "roofline": {"bound": "hbm", "kernel": wl.kernel, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "alg_bytes_per_step": wl.alg_bytes, "avg_kernel_ms": round(avg_kernel_ms, 5)},
+                     "traffic": stored_traffic(args.workload), "alg_bytes_per_step": wl.alg_bytes,
+                     "avg_kernel_ms": round(avg_kernel_ms, 5)},
     }
     if not args.no_cpu_baseline:
         threads = _threads()

@@ -215,6 +215,16 @@ spmm_status spmm_batch_get_variant(spmm_batch_t batch, int t, spmm_variant* out 
 spmm_status spmm_batched(spmm_batch_t batch, const void* const* B, const int64_t* ldb, void* const* C,
                          const int64_t* ldc, int accumulate, void* workspace, size_t ws_bytes, void* stream);
 
+/*
+ * Dense partial-tile accumulate of the stationary-A algorithm (Section 3.2,
+ * Algorithm 1): the owner of C(i,j) adds a partial product tile computed by the
+ * owner of A(i,k):  C = C + Ptile.  C (device, rows x N, ld ldc) and Ptile (device,
+ * rows x N, ld ldp) share `dtype`; the sum is formed in FP32 and a BF16 C is
+ * rounded once.  Asynchronous.  Errors: INVALID_ARG, HIP.
+ */
+spmm_status spmm_tile_accumulate(void* C, int64_t ldc, const void* Ptile, int64_t ldp, int64_t rows, int64_t N,
+                                 spmm_dtype dtype, void* stream);
+
 const char* spmm_status_string(spmm_status status);
 const char* spmm_last_error(void);
 

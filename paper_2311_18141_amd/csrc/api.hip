@@ -36,8 +36,8 @@ spmm_status fail(spmm_status st, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(SPMM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int32_t kDefaultLongRow = 1024;
-constexpr int32_t kDefaultSegment = 512;
+constexpr int32_t kDefaultLongRow = 256;
+constexpr int32_t kDefaultSegment = 128;
 
 // Device allocation owned by a handle.
 template <typename T>
@@ -130,12 +130,19 @@ spmm_status build_plan(const int32_t* const* rowptr, int K, int64_t rows, int32_
 
 size_t partial_ld(int64_t N) { return (size_t)((N + 7) / 8 * 8); }
 
-// Kernel variant for width N: the widest aligned vector (16 bytes at most) and
-// the smallest power-of-two group (4..64 lanes) that covers the row in one window.
+// Kernel variant for width N when the handle has no entry: for N >= 64 the stream
+// kernel with the narrowest vector whose 64-lane window still covers N (measured
+// best on power-law and R-MAT tiles); below that a row-split group with the widest
+// aligned vector and the smallest power-of-two group covering N.
 spmm::Variant pick_variant(int64_t N, DT dt, uintptr_t align_or) {
   const int esize = dt == DT::F32 ? 4 : 2;
   int V = 16 / esize;
   while (V > 1 && ((N % V) != 0 || (align_or % (uintptr_t)(V * esize)) != 0)) V /= 2;
+  if (N >= 64) {
+    int Vs = V;
+    while (Vs > 1 && 64 * (Vs / 2) >= N) Vs /= 2;
+    return spmm::Variant{64, Vs, true};
+  }
   const int64_t need = (N + V - 1) / V;
   int G = 4;
   while (G < 64 && G < need) G *= 2;
@@ -514,20 +521,24 @@ spmm_status spmm_tile_autotune(spmm_tile_t A, int64_t N, spmm_dtype dtype, const
       if (u.G == v.G && u.V == v.V && u.stream == v.stream) return;
     kv.push_back(v);
   };
-  for (int V = base.V; V >= 1 && V >= base.V / 2; V /= 2) {
-    if ((N % V) != 0 || (align_or % (uintptr_t)(V * esize)) != 0) continue;
+  add(base);
+  int vmax = 16 / esize;
+  while (vmax > 1 && ((N % vmax) != 0 || (align_or % (uintptr_t)(vmax * esize)) != 0)) vmax /= 2;
+  for (int V = vmax; V >= 1 && V >= vmax / 4; V /= 2) {
+    if ((N % V) != 0) continue;
+    add(spmm::Variant{64, V, true});
+    if (V < vmax / 2) continue;
     int G = 4;
     while (G < 64 && G < (N + V - 1) / V) G *= 2;
     if (G >= 8) add(spmm::Variant{G / 2, V, false});
     add(spmm::Variant{G, V, false});
     add(spmm::Variant{64, V, false});
-    add(spmm::Variant{64, V, true});
   }
   // Split-plan candidates (threshold, unit length).
   std::vector<std::pair<int32_t, int32_t>> pc;
   pc.push_back({A->plan.long_row, A->plan.segment});
   if (tune_plan) {
-    const std::pair<int32_t, int32_t> extra[] = {{128, 64}, {256, 128}, {512, 256}, {1024, 512}, {4096, 2048}};
+    const std::pair<int32_t, int32_t> extra[] = {{128, 64}, {256, 128}, {512, 256}, {1024, 512}};
     for (auto& p : extra)
       if (p.first != A->plan.long_row || p.second != A->plan.segment) pc.push_back(p);
   }
@@ -595,6 +606,24 @@ spmm_status spmm_tile_autotune(spmm_tile_t A, int64_t N, spmm_dtype dtype, const
   st = spmm_tile_set_variant(A, N, dtype, &out);
   if (st == SPMM_OK && chosen) *chosen = out;
   return st;
+}
+
+spmm_status spmm_tile_accumulate(void* C, int64_t ldc, const void* Ptile, int64_t ldp, int64_t rows, int64_t N,
+                                 spmm_dtype dtype, void* stream) {
+  if (rows < 0 || N < 1) return fail(SPMM_ERR_INVALID_ARG, "rows=%lld N=%lld", (long long)rows, (long long)N);
+  if (dtype != SPMM_F32 && dtype != SPMM_BF16) return fail(SPMM_ERR_INVALID_ARG, "unknown dtype");
+  if (ldc < N || ldp < N) return fail(SPMM_ERR_INVALID_ARG, "leading dimension < N");
+  if (rows > 0 && (!C || !Ptile)) return fail(SPMM_ERR_INVALID_ARG, "C/Ptile is null");
+  if (rows == 0) return SPMM_OK;
+  const DT dt = dtype == SPMM_F32 ? DT::F32 : DT::BF16;
+  const int esize = dt == DT::F32 ? 4 : 2;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(C) | reinterpret_cast<uintptr_t>(Ptile) |
+                      (uintptr_t)(ldc * esize) | (uintptr_t)(ldp * esize);
+  int V = 16 / esize;
+  while (V > 1 && ((N % V) != 0 || (a % (uintptr_t)(V * esize)) != 0)) V /= 2;
+  if (rows * (N / V) / spmm::kBlock >= ((int64_t)1 << 31)) return fail(SPMM_ERR_UNSUPPORTED, "tile too large");
+  HIP_TRY(spmm::launch_accumulate(C, ldc, Ptile, ldp, rows, N, dt, V, static_cast<hipStream_t>(stream)));
+  return SPMM_OK;
 }
 
 spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* B, int64_t ldb, int64_t N,
@@ -707,8 +736,8 @@ namespace {
 // Batched variant of one tile: the handle's table entry for (N, dtype), else the rule
 // below; vectors assume 16-byte aligned rows (a documented requirement of spmm_batched).
 void batch_variant(const spmm_tile_s* A, int64_t N, DT dt, spmm::BatchTileDev* bt, spmm_variant* out) {
-  const int vmax = dt == DT::F32 ? 4 : 8;
-  int Vs = vmax;  // stream / unit vector: widest dividing N that is not wider than needed
+  (void)dt;
+  int Vs = 4;  // stream / unit vector (at most 4 elements per lane): widest dividing N, not wider than needed
   while (Vs > 1 && ((N % Vs) != 0 || 64 * (Vs / 2) >= N)) Vs /= 2;
   const spmm_variant* e = nullptr;
   for (int i = 0; i < A->nvt; ++i)
@@ -723,17 +752,18 @@ void batch_variant(const spmm_tile_s* A, int64_t N, DT dt, spmm::BatchTileDev* b
     if (!stream && e->lanes >= 8) G = e->lanes;
   }
   if (!stream) {
-    if ((N % vmax) != 0) {  // row-split items use the widest vector; fall back to streaming
+    if ((N % 4) != 0) {  // row-split items load 4 elements per lane; otherwise stream
       stream = true;
     } else if (!e || e->lanes < 8) {
       G = 8;
-      while (G < 64 && G * vmax < N) G *= 2;
+      while (G < 32 && G * 4 < N) G *= 2;
     }
   }
+  if (G > 32) G = 32;  // row-split items use 8, 16 or 32 lanes per row (wider rows take more windows)
   bt->kind = stream ? 0 : 1;
   bt->G = stream ? 64 : G;
   bt->V = Vs;
-  *out = spmm_variant{stream ? SPMM_KERNEL_STREAM : SPMM_KERNEL_ROWSPLIT, bt->G, stream ? Vs : vmax};
+  *out = spmm_variant{stream ? SPMM_KERNEL_STREAM : SPMM_KERNEL_ROWSPLIT, bt->G, stream ? Vs : 4};
 }
 
 }  // namespace
@@ -791,8 +821,7 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
       d.part_off = part;
       part += (int64_t)d.ldp * A->plan.n_seg;
       batch_variant(A, N[t], dt, &d, &b->variants[t]);
-      const int vmax = dt == DT::F32 ? 4 : 8;
-      const int64_t wrow = d.kind == 0 ? 64 * d.V : (int64_t)d.G * vmax;
+      const int64_t wrow = d.kind == 0 ? 64 * d.V : (int64_t)d.G * 4;  // row-split items: 4 elements per lane
       const int64_t wunit = 64 * d.V;
       const int nw_rows = (int)((N[t] + wrow - 1) / wrow);
       const int nw_unit = (int)((N[t] + wunit - 1) / wunit);

@@ -48,7 +48,7 @@ template <int V, typename E, bool ACC>
 __device__ __forceinline__ void item_stream(const BatchTileDev& bt, const Ops<E>& op, int64_t r0, int window,
                                             int32_t* s_pref, int32_t* s_beg) {
   using T = typename E::T;
-  constexpr int U = V >= 8 ? 4 : 8;
+  constexpr int U = V >= 4 ? 4 : 8;
   const int lane = threadIdx.x & 63;
   const int64_t c0 = (int64_t)window * (64 * V) + (int64_t)lane * V;
   const bool active = c0 < bt.N;
@@ -167,7 +167,7 @@ __device__ __forceinline__ void item_rowsplit(const BatchTileDev& bt, const Ops<
     float acc[V];
 #pragma unroll
     for (int e = 0; e < V; ++e) acc[e] = 0.0f;
-    accumulate_range<G, V, E>(t, p0, p1, brow, ldbb, gl, acc);
+    accumulate_range_lean<G, V, E, 4>(t, p0, p1, brow, ldbb, gl, acc);
     if (inrow && !split && active) store_c<V, E, ACC>(op.C + row * op.ldc + c0, acc);
   }
 }
@@ -192,8 +192,8 @@ __device__ __forceinline__ void item_unit(const BatchParams& P, const BatchTileD
   float acc[V];
 #pragma unroll
   for (int e = 0; e < V; ++e) acc[e] = 0.0f;
-  accumulate_range<64, V, E>(t, d.p0, d.p1, reinterpret_cast<const char*>(op.B) + cl * (int64_t)sizeof(T),
-                             (uint32_t)(op.ldb * (int64_t)sizeof(T)), lane, acc);
+  accumulate_range_lean<64, V, E, 4>(t, d.p0, d.p1, reinterpret_cast<const char*>(op.B) + cl * (int64_t)sizeof(T),
+                                     (uint32_t)(op.ldb * (int64_t)sizeof(T)), lane, acc);
   if (active) store_f32v<V>(P.partial + bt.part_off + (int64_t)s * bt.ldp + c0, acc);
 }
 
@@ -203,38 +203,31 @@ __device__ __forceinline__ void run_item(const BatchParams& P, const BatchItem& 
   const BatchTileDev& bt = P.tiles[it.tile];
   const Ops<E> op = item_ops<E>(P, it.tile);
   const int64_t r0 = it.a;
-  constexpr bool F32 = sizeof(typename E::T) == 4;
   if (it.type == 1) {
     switch (bt.V) {
       case 1: item_unit<1, E>(P, bt, op, it.a, it.window); return;
       case 2: item_unit<2, E>(P, bt, op, it.a, it.window); return;
-      case 4: item_unit<4, E>(P, bt, op, it.a, it.window); return;
-      default:
-        if constexpr (!F32) item_unit<8, E>(P, bt, op, it.a, it.window);
-        return;
+      default: item_unit<4, E>(P, bt, op, it.a, it.window); return;
     }
   }
   if (bt.kind == 0) {
     switch (bt.V) {
       case 1: item_stream<1, E, ACC>(bt, op, r0, it.window, s_pref, s_beg); return;
       case 2: item_stream<2, E, ACC>(bt, op, r0, it.window, s_pref, s_beg); return;
-      case 4: item_stream<4, E, ACC>(bt, op, r0, it.window, s_pref, s_beg); return;
-      default:
-        if constexpr (!F32) item_stream<8, E, ACC>(bt, op, r0, it.window, s_pref, s_beg);
-        return;
+      default: item_stream<4, E, ACC>(bt, op, r0, it.window, s_pref, s_beg); return;
     }
   }
-  constexpr int VW = F32 ? 4 : 8;  // row-split variants use the widest vector of the dtype
+  constexpr int VW = 4;  // row-split items: 4 elements per lane (16 bytes FP32, 8 bytes BF16)
   switch (bt.G) {
     case 8: item_rowsplit<8, VW, E, ACC>(bt, op, r0, it.window); return;
     case 16: item_rowsplit<16, VW, E, ACC>(bt, op, r0, it.window); return;
-    case 32: item_rowsplit<32, VW, E, ACC>(bt, op, r0, it.window); return;
-    default: item_rowsplit<64, VW, E, ACC>(bt, op, r0, it.window); return;
+    default: item_rowsplit<32, VW, E, ACC>(bt, op, r0, it.window); return;
   }
 }
 
+// At most 80 VGPRs, so that six waves per SIMD can hide the gather latency.
 template <typename E, bool ACC>
-__global__ void __launch_bounds__(kBlock) batch_main(BatchParams P) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) batch_main(BatchParams P) {
   __shared__ int32_t s_mem[(kBlock / 64) * 129];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
@@ -280,10 +273,7 @@ __global__ void __launch_bounds__(kBlock) batch_fixup(BatchParams P) {
   switch (bt.V) {
     case 1: fix_row<1, E, ACC>(P, bt, op, it.a, it.window); return;
     case 2: fix_row<2, E, ACC>(P, bt, op, it.a, it.window); return;
-    case 4: fix_row<4, E, ACC>(P, bt, op, it.a, it.window); return;
-    default:
-      if constexpr (sizeof(typename E::T) == 2) fix_row<8, E, ACC>(P, bt, op, it.a, it.window);
-      return;
+    default: fix_row<4, E, ACC>(P, bt, op, it.a, it.window); return;
   }
 }
 

@@ -61,7 +61,49 @@ hipError_t launch_sddmm_v(const SddmmParams& P, int G, hipStream_t s) {
   }
 }
 
+// C[r, c] += P[r, c] over a rows x N block; one thread per V consecutive elements.
+template <int V, typename E>
+__global__ void __launch_bounds__(kBlock) accumulate_kernel(typename E::T* C, int64_t ldc, const typename E::T* Pt,
+                                                            int64_t ldp, int64_t rows, int64_t N) {
+  const int64_t per_row = N / V;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= rows * per_row) return;
+  const int64_t r = i / per_row, c = (i - r * per_row) * V;
+  float x[V], y[V];
+  load_vec<E, V>(C + r * ldc + c, x);
+  load_vec<E, V>(Pt + r * ldp + c, y);
+#pragma unroll
+  for (int e = 0; e < V; ++e) x[e] += y[e];
+  store_vec<E, V>(C + r * ldc + c, x);
+}
+
+template <typename E, int V>
+hipError_t launch_acc(void* C, int64_t ldc, const void* Pt, int64_t ldp, int64_t rows, int64_t N, hipStream_t s) {
+  const int64_t n = rows * (N / V);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((accumulate_kernel<V, E>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                     static_cast<typename E::T*>(C), ldc, static_cast<const typename E::T*>(Pt), ldp, rows, N);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_accumulate(void* C, int64_t ldc, const void* Pt, int64_t ldp, int64_t rows, int64_t N, DT dt,
+                             int V, hipStream_t s) {
+  if (dt == DT::F32) {
+    switch (V) {
+      case 4: return launch_acc<F32E, 4>(C, ldc, Pt, ldp, rows, N, s);
+      case 2: return launch_acc<F32E, 2>(C, ldc, Pt, ldp, rows, N, s);
+      default: return launch_acc<F32E, 1>(C, ldc, Pt, ldp, rows, N, s);
+    }
+  }
+  switch (V) {
+    case 8: return launch_acc<BF16E, 8>(C, ldc, Pt, ldp, rows, N, s);
+    case 4: return launch_acc<BF16E, 4>(C, ldc, Pt, ldp, rows, N, s);
+    case 2: return launch_acc<BF16E, 2>(C, ldc, Pt, ldp, rows, N, s);
+    default: return launch_acc<BF16E, 1>(C, ldc, Pt, ldp, rows, N, s);
+  }
+}
 
 hipError_t launch_sddmm(const SddmmParams& P, Variant v, hipStream_t s) {
   switch (v.V) {

@@ -86,4 +86,37 @@ __device__ __forceinline__ void accumulate_range(const TileDev& t, int p0, int p
   }
 }
 
+// Register-lean form of accumulate_range for the persistent batched kernel: one
+// predicated code path with U loads in flight (every batch clamps its sources to
+// the last entry and zeroes the terms past the end).
+template <int G, int V, typename E, int U>
+__device__ __forceinline__ void accumulate_range_lean(const TileDev& t, int p0, int p1, const char* brow,
+                                                      uint32_t ldb_bytes, int gl, float (&acc)[V]) {
+  using T = typename E::T;
+  for (int pc = p0; pc < p1; pc += G) {
+    const int cnt = min(G, p1 - pc);
+    int my_col = 0;
+    float my_val = 0.0f;
+    if (gl < cnt) {
+      my_col = __builtin_nontemporal_load(t.colind + pc + gl);
+      my_val = __builtin_nontemporal_load(t.values + pc + gl);
+    }
+    for (int j = 0; j < cnt; j += U) {
+      float b[U][V];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t col = (uint32_t)group_bcast<G>(my_col, min(j + u, cnt - 1));
+        load_vec<E, V>(reinterpret_cast<const T*>(brow + (uint64_t)col * ldb_bytes), b[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool ok = j + u < cnt;
+        const float v = __int_as_float(group_bcast<G>(__float_as_int(my_val), min(j + u, cnt - 1)));
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc[e] = fmaf(ok ? v : 0.0f, ok ? b[u][e] : 0.0f, acc[e]);
+      }
+    }
+  }
+}
+
 }  // namespace spmm

@@ -118,6 +118,8 @@ struct SddmmParams {
   int accumulate;          // add to dA (later slices)
 };
 hipError_t launch_sddmm(const SddmmParams& P, Variant v, hipStream_t s);
+hipError_t launch_accumulate(void* C, int64_t ldc, const void* Pt, int64_t ldp, int64_t rows, int64_t N, DT dt,
+                             int V, hipStream_t s);
 
 // Structure utilities (utils.hip).
 hipError_t launch_validate_rowptr(const int32_t* rowptr, int64_t rows, int64_t nnz, uint32_t* status,

@@ -237,6 +237,16 @@ def spmm_bwd(tile: Tile, dC: torch.Tensor, B: torch.Tensor, want_dA: bool = True
     return (dA if want_dA else None), (dB if want_dB else None)
 
 
+def spmm_tile_accumulate(C: torch.Tensor, Ptile: torch.Tensor, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """C += Ptile (the owner-side accumulate of a stationary-A partial product)."""
+    if C.dtype != Ptile.dtype or C.dtype not in _DTYPES or C.shape != Ptile.shape or not (C.is_cuda and Ptile.is_cuda):
+        raise ValueError("C and Ptile must be device tensors of one shape and dtype (float32 or bfloat16)")
+    rows, N = C.shape
+    check(lib().spmm_tile_accumulate(C.data_ptr(), _row_major_ld(C, "C"), Ptile.data_ptr(), _row_major_ld(Ptile, "Ptile"),
+                                     rows, N, _DTYPES[C.dtype], _stream_ptr(stream)))
+    return C
+
+
 class Batch:
     """A batched launch over many single-tile handles (see spmm_batch_create)."""
 

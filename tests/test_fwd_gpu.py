@@ -331,3 +331,28 @@ def test_variant_argument_errors():
     with pytest.raises(SpmmError):
         ops.spmm_tile_set_variant(tile, 32, torch.float32, "rowsplit", vec=8)
     ops.spmm_tile_set_variant(tile, 32, torch.float32, None)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_stationary_a_partials_and_accumulate(dtype):
+    """Section 3.2 / Algorithm 1: the owner of A(i,k) forms the partial A_ik B_kj (overwriting), the
+    owner of C(i,j) adds every partial into its tile; the sum equals C0 + sum_k A_ik B_kj."""
+    G.note("stationary_a %s" % dtype)
+    rng = _rng(93)
+    K, M, cols, N = 3, 1500, 900, 64
+    tiles = [synth.random_csr(M, cols, rng.integers(0, 30, size=M), rng, "int4") for _ in range(K)]
+    Bs = [synth.dense(cols, N, rng, "int4") for _ in range(K)]
+    C0 = synth.dense(M, N, rng, "int4")
+    Cd = G.dense_dev(C0, dtype)
+    for k in range(K):
+        h = G.make_tile([tiles[k]])
+        part = G.fwd(h, [G.dense_dev(Bs[k], dtype)])            # local_c = local_a * local_b
+        ops.spmm_tile_accumulate(Cd, part)                      # C.my_tile() += partial
+    torch.cuda.synchronize()
+    ref, S = G.oracle_fwd(tiles, Bs, accumulate=True, C0=C0)
+    got = G.host_f32(Cd)
+    if dtype == torch.float32:
+        assert np.array_equal(got.astype(np.float64), ref)      # small integers: exact in any order
+    else:
+        # every partial and every running sum is rounded to BF16 once per step
+        assert np.all(np.abs(got - ref) <= (K + 1) * 2.0 ** -8 * (np.abs(C0) + S) + 1e-6)
