@@ -127,7 +127,8 @@ spmm_status spmm_tile_export_transpose(spmm_tile_t tile, int32_t* rowptrT, int32
 #define SPMM_KERNEL_STREAM 2     /* a wave streams the non-zeros of 64 consecutive rows */
 typedef struct {
   int32_t kind;    /* SPMM_KERNEL_* */
-  int32_t lanes;   /* ROWSPLIT: lanes per row, 4..64, power of two; 0 = library choice */
+  int32_t lanes;   /* ROWSPLIT: lanes per row; STREAM: rows per wave; 4..64, power of two;
+                      0 = library choice */
   int32_t vec;     /* elements per lane per load: 1, 2, 4 (and 8 for BF16); 0 = widest aligned */
 } spmm_variant;
 

@@ -130,18 +130,26 @@ spmm_status build_plan(const int32_t* const* rowptr, int K, int64_t rows, int32_
 
 size_t partial_ld(int64_t N) { return (size_t)((N + 7) / 8 * 8); }
 
+// Rows per wave of the stream kernel: enough waves to fill the GPU for short tiles,
+// 64 (one per lane) for large ones.
+int stream_rows_for(int64_t rows) {
+  int R = 64;
+  while (R > 4 && (rows / R) < 4096) R /= 2;
+  return R;
+}
+
 // Kernel variant for width N when the handle has no entry: for N >= 64 the stream
 // kernel with the narrowest vector whose 64-lane window still covers N (measured
 // best on power-law and R-MAT tiles); below that a row-split group with the widest
 // aligned vector and the smallest power-of-two group covering N.
-spmm::Variant pick_variant(int64_t N, DT dt, uintptr_t align_or) {
+spmm::Variant pick_variant(int64_t N, DT dt, uintptr_t align_or, int64_t rows) {
   const int esize = dt == DT::F32 ? 4 : 2;
   int V = 16 / esize;
   while (V > 1 && ((N % V) != 0 || (align_or % (uintptr_t)(V * esize)) != 0)) V /= 2;
   if (N >= 64) {
     int Vs = V;
     while (Vs > 1 && 64 * (Vs / 2) >= N) Vs /= 2;
-    return spmm::Variant{64, Vs, true};
+    return spmm::Variant{64, Vs, true, stream_rows_for(rows)};
   }
   const int64_t need = (N + V - 1) / V;
   int G = 4;
@@ -190,7 +198,7 @@ namespace {
 // The variant for one call: the handle's entry for (N, dtype) when it fits the
 // call's alignment, otherwise the fixed rule.
 spmm::Variant resolve_variant(const spmm_tile_s* A, int64_t N, DT dt, uintptr_t align_or) {
-  const spmm::Variant base = pick_variant(N, dt, align_or);
+  const spmm::Variant base = pick_variant(N, dt, align_or, A->rows);
   const int esize = dt == DT::F32 ? 4 : 2;
   const int want = dt == DT::F32 ? SPMM_F32 : SPMM_BF16;
   for (int i = 0; i < A->nvt; ++i) {
@@ -198,7 +206,7 @@ spmm::Variant resolve_variant(const spmm_tile_s* A, int64_t N, DT dt, uintptr_t 
     if (e.N != N || e.dtype != want || e.v.kind == SPMM_KERNEL_AUTO) continue;
     const int V = e.v.vec ? e.v.vec : base.V;
     if ((N % V) != 0 || (align_or % (uintptr_t)(V * esize)) != 0) return base;
-    if (e.v.kind == SPMM_KERNEL_STREAM) return spmm::Variant{64, V, true};
+    if (e.v.kind == SPMM_KERNEL_STREAM) return spmm::Variant{64, V, true, e.v.lanes ? e.v.lanes : stream_rows_for(A->rows)};
     int G = e.v.lanes;
     if (G == 0) {
       G = 4;
@@ -514,11 +522,11 @@ spmm_status spmm_tile_autotune(spmm_tile_t A, int64_t N, spmm_dtype dtype, const
 
   // Kernel candidates: the two widest aligned vector widths, for each the covering
   // group size, half of it and a full wave, plus the stream kernel.
-  const spmm::Variant base = pick_variant(N, dt, align_or);
+  const spmm::Variant base = pick_variant(N, dt, align_or, A->rows);
   std::vector<spmm::Variant> kv;
   auto add = [&](spmm::Variant v) {
     for (auto& u : kv)
-      if (u.G == v.G && u.V == v.V && u.stream == v.stream) return;
+      if (u.G == v.G && u.V == v.V && u.stream == v.stream && (!v.stream || u.rows == v.rows)) return;
     kv.push_back(v);
   };
   add(base);
@@ -526,7 +534,7 @@ spmm_status spmm_tile_autotune(spmm_tile_t A, int64_t N, spmm_dtype dtype, const
   while (vmax > 1 && ((N % vmax) != 0 || (align_or % (uintptr_t)(vmax * esize)) != 0)) vmax /= 2;
   for (int V = vmax; V >= 1 && V >= vmax / 4; V /= 2) {
     if ((N % V) != 0) continue;
-    add(spmm::Variant{64, V, true});
+    for (int R : {64, 16, 4}) add(spmm::Variant{64, V, true, R});
     if (V < vmax / 2) continue;
     int G = 4;
     while (G < 64 && G < (N + V - 1) / V) G *= 2;
@@ -602,7 +610,8 @@ spmm_status spmm_tile_autotune(spmm_tile_t A, int64_t N, spmm_dtype dtype, const
   }
   for (auto& p : plans) free_plan(p);
   if (st != SPMM_OK) return st;
-  spmm_variant out{best_v.stream ? SPMM_KERNEL_STREAM : SPMM_KERNEL_ROWSPLIT, best_v.G, best_v.V};
+  spmm_variant out{best_v.stream ? SPMM_KERNEL_STREAM : SPMM_KERNEL_ROWSPLIT, best_v.stream ? best_v.rows : best_v.G,
+                   best_v.V};
   st = spmm_tile_set_variant(A, N, dtype, &out);
   if (st == SPMM_OK && chosen) *chosen = out;
   return st;
@@ -703,7 +712,7 @@ spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* 
     P.ldp = (int64_t)partial_ld(N);
     const uintptr_t a = reinterpret_cast<uintptr_t>(dC) | reinterpret_cast<uintptr_t>(dB) | (uintptr_t)(lddc * 4) |
                         (uintptr_t)(lddb * 4);
-    HIP_TRY(spmm::launch_fwd(P, pick_variant(N, DT::F32, a), DT::F32, s));
+    HIP_TRY(spmm::launch_fwd(P, pick_variant(N, DT::F32, a, t.cols), DT::F32, s));
   }
   return SPMM_OK;
 }
@@ -719,9 +728,11 @@ struct spmm_batch_s {
   int64_t n_items = 0;
   spmm::BatchItem* d_fix = nullptr;
   int64_t n_fix = 0;
-  unsigned* d_counter = nullptr;
+  unsigned* d_counter = nullptr;  // one claim counter per item class
   size_t ws_bytes = 0;
-  int grid = 0;
+  int64_t class_off[spmm::kBatchClasses] = {};
+  int64_t class_cnt[spmm::kBatchClasses] = {};
+  int class_grid[spmm::kBatchClasses] = {};
   std::vector<spmm_variant> variants;
   ~spmm_batch_s() {
     if (d_tiles) (void)hipFree(d_tiles);
@@ -756,10 +767,9 @@ void batch_variant(const spmm_tile_s* A, int64_t N, DT dt, spmm::BatchTileDev* b
       stream = true;
     } else if (!e || e->lanes < 8) {
       G = 8;
-      while (G < 32 && G * 4 < N) G *= 2;
+      while (G < 64 && G * 4 < N) G *= 2;
     }
   }
-  if (G > 32) G = 32;  // row-split items use 8, 16 or 32 lanes per row (wider rows take more windows)
   bt->kind = stream ? 0 : 1;
   bt->G = stream ? 64 : G;
   bt->V = Vs;
@@ -853,25 +863,64 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
         for (int w = 0; w < nw_unit; ++w) fix.push_back(spmm::BatchItem{t, (int32_t)r, w, 2});
     }
     if ((int64_t)items.size() >= ((int64_t)1 << 32)) return fail(SPMM_ERR_UNSUPPORTED, "work list too long");
-    std::stable_sort(items.begin(), items.end(), [](const Costed& x, const Costed& y) { return x.cost > y.cost; });
+    // Order: tiles by descending total cost; inside a tile, split-row units first
+    // (longest first), then the row items in row order.  Keeping a tile's items
+    // together keeps its B resident in the caches while the waves work on it;
+    // big tiles first leave the small ones to fill the end of the launch.
+    std::vector<double> tile_cost(count, 0.0);
+    for (const auto& c : items) tile_cost[c.it.tile] += c.cost;
+    std::vector<int> rank(count);
+    {
+      std::vector<int> order(count);
+      for (int t = 0; t < count; ++t) order[t] = t;
+      std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return tile_cost[x] > tile_cost[y]; });
+      for (int i = 0; i < count; ++i) rank[order[i]] = i;
+    }
+    // item class: stream V -> log2 V; row-split G -> 3 + log2(G / 8); unit V -> 7 + log2 V
+    auto log2i = [](int v) { int l = 0; while ((1 << l) < v) ++l; return l; };
+    auto cls = [&](const spmm::BatchItem& it) {
+      const spmm::BatchTileDev& d = bt[it.tile];
+      if (it.type == 1) return spmm::kClassUnit + log2i(d.V);
+      if (d.kind == 0) return log2i(d.V);
+      return spmm::kClassRowsplit + log2i(d.G / 8);
+    };
+    std::stable_sort(items.begin(), items.end(), [&](const Costed& x, const Costed& y) {
+      const int cx = cls(x.it), cy = cls(y.it);
+      if (cx != cy) return cx < cy;
+      if (x.it.tile != y.it.tile) return rank[x.it.tile] < rank[y.it.tile];
+      if (x.it.type != y.it.type) return x.it.type > y.it.type;  // units (1) before rows (0)
+      if (x.it.type == 1) return x.cost > y.cost;
+      return false;                                               // rows keep their order
+    });
     std::vector<spmm::BatchItem> list(items.size());
-    for (size_t i = 0; i < items.size(); ++i) list[i] = items[i].it;
+    for (size_t i = 0; i < items.size(); ++i) {
+      list[i] = items[i].it;
+      b->class_cnt[cls(list[i])] += 1;
+    }
+    for (int c = 1; c < spmm::kBatchClasses; ++c) b->class_off[c] = b->class_off[c - 1] + b->class_cnt[c - 1];
     b->n_items = (int64_t)list.size();
     b->n_fix = (int64_t)fix.size();
     b->ws_bytes = sizeof(float) * (size_t)part;
     if (dalloc(&b->d_tiles, count) != hipSuccess || dalloc(&b->d_items, b->n_items) != hipSuccess ||
-        dalloc(&b->d_fix, b->n_fix) != hipSuccess || dalloc(&b->d_counter, 1) != hipSuccess)
+        dalloc(&b->d_fix, b->n_fix) != hipSuccess || dalloc(&b->d_counter, spmm::kBatchClasses) != hipSuccess)
       return fail(SPMM_ERR_ALLOC, "device allocation of the batch failed");
     HIP_TRY(hipMemcpyAsync(b->d_tiles, bt.data(), sizeof(spmm::BatchTileDev) * bt.size(), hipMemcpyHostToDevice, s));
     if (b->n_items)
       HIP_TRY(hipMemcpyAsync(b->d_items, list.data(), sizeof(spmm::BatchItem) * list.size(), hipMemcpyHostToDevice, s));
     if (b->n_fix)
       HIP_TRY(hipMemcpyAsync(b->d_fix, fix.data(), sizeof(spmm::BatchItem) * fix.size(), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemsetAsync(b->d_counter, 0, sizeof(unsigned), s));
+    HIP_TRY(hipMemsetAsync(b->d_counter, 0, sizeof(unsigned) * spmm::kBatchClasses, s));
     HIP_TRY(hipStreamSynchronize(s));
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    b->grid = std::max(1, cus * spmm::batch_blocks_per_cu(dt));
+    int occ[spmm::kBatchClasses];
+    spmm::batch_blocks_per_cu(dt, occ);
+    for (int c = 0; c < spmm::kBatchClasses; ++c) {
+      // a persistent grid of at most one wave per item: small classes launch small grids
+      const int64_t full = (int64_t)cus * std::max(1, occ[c]);
+      const int64_t need = (b->class_cnt[c] + 3) / 4;
+      b->class_grid[c] = (int)std::max<int64_t>(1, std::min(full, need));
+    }
     return SPMM_OK;
   };
   spmm_status st = body();
@@ -928,7 +977,8 @@ spmm_status spmm_batched(spmm_batch_t batch, const void* const* B, const int64_t
   P.partial = static_cast<float*>(workspace);
   P.counter = batch->d_counter;
   P.accumulate = accumulate ? 1 : 0;
-  HIP_TRY(spmm::launch_batch(P, batch->dt, batch->grid, static_cast<hipStream_t>(stream)));
+  HIP_TRY(spmm::launch_batch(P, batch->class_off, batch->class_cnt, batch->class_grid, batch->dt,
+                             static_cast<hipStream_t>(stream)));
   return SPMM_OK;
 }
 

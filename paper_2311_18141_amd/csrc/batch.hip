@@ -1,8 +1,9 @@
-// Batched local SpMM: many independent single-tile products C_t = A_t B_t in one
-// persistent launch.  The host builds a work list of items (64 rows of one tile
-// and one column window, or one split-row unit), sorted by descending cost.
-// Each wave claims items from a device counter (the single-GPU form of claiming
-// work with a fetch-and-add) and runs the item with its tile's kernel variant.
+// Batched local SpMM: many independent single-tile products C_t = A_t B_t in a
+// handful of persistent launches (one per kernel class present in the batch).  The host builds a work list of items (64 rows of one tile
+// and one column window, or one split-row unit), tile by tile (largest tiles
+// first), so that the waves share one tile's B in the caches at a time.
+// Each wave claims items of its class from that class's device counter (the
+// single-GPU form of claiming work with a fetch-and-add) and runs them.
 // Items write disjoint output rows (split rows: disjoint partial rows) and every
 // row is summed in CSR order by one wave, so the result does not depend on which
 // wave claims which item; split rows are finished by a second, fix-up launch.
@@ -48,7 +49,7 @@ template <int V, typename E, bool ACC>
 __device__ __forceinline__ void item_stream(const BatchTileDev& bt, const Ops<E>& op, int64_t r0, int window,
                                             int32_t* s_pref, int32_t* s_beg) {
   using T = typename E::T;
-  constexpr int U = V >= 4 ? 4 : 8;
+  constexpr int U = V >= 8 ? 4 : 8;
   const int lane = threadIdx.x & 63;
   const int64_t c0 = (int64_t)window * (64 * V) + (int64_t)lane * V;
   const bool active = c0 < bt.N;
@@ -108,8 +109,7 @@ __device__ __forceinline__ void item_stream(const BatchTileDev& bt, const Ops<E>
       end = (q + 1 == s_pref[ri + 1]) ? 1 : 0;
     }
     const uint32_t alo = (uint32_t)addr, ahi = (uint32_t)(addr >> 32);
-    for (int u0 = 0; u0 < n; u0 += U) {
-      float bv[U][V];
+    auto issue = [&](float (&bv)[U][V], int u0) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int jj = min(u0 + u, n - 1);
@@ -117,6 +117,8 @@ __device__ __forceinline__ void item_stream(const BatchTileDev& bt, const Ops<E>
                            (uint32_t)__builtin_amdgcn_readlane((int)alo, jj);
         load_vec_at<E, V>(a + coff, bv[u]);
       }
+    };
+    auto consume = [&](const float (&bv)[U][V], int u0) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int jj = min(u0 + u, n - 1);
@@ -131,6 +133,18 @@ __device__ __forceinline__ void item_stream(const BatchTileDev& bt, const Ops<E>
           for (int e = 0; e < V; ++e) acc[e] = 0.0f;
         }
       }
+    };
+    float bA[U][V], bB[U][V];
+    issue(bA, 0);
+    for (int u0 = 0;;) {
+      if (u0 + U < n) issue(bB, u0 + U);
+      consume(bA, u0);
+      u0 += U;
+      if (u0 >= n) break;
+      if (u0 + U < n) issue(bA, u0 + U);
+      consume(bB, u0);
+      u0 += U;
+      if (u0 >= n) break;
     }
   }
 }
@@ -167,7 +181,7 @@ __device__ __forceinline__ void item_rowsplit(const BatchTileDev& bt, const Ops<
     float acc[V];
 #pragma unroll
     for (int e = 0; e < V; ++e) acc[e] = 0.0f;
-    accumulate_range_lean<G, V, E, 4>(t, p0, p1, brow, ldbb, gl, acc);
+    accumulate_range<G, V, E>(t, p0, p1, brow, ldbb, gl, acc);
     if (inrow && !split && active) store_c<V, E, ACC>(op.C + row * op.ldc + c0, acc);
   }
 }
@@ -192,42 +206,15 @@ __device__ __forceinline__ void item_unit(const BatchParams& P, const BatchTileD
   float acc[V];
 #pragma unroll
   for (int e = 0; e < V; ++e) acc[e] = 0.0f;
-  accumulate_range_lean<64, V, E, 4>(t, d.p0, d.p1, reinterpret_cast<const char*>(op.B) + cl * (int64_t)sizeof(T),
-                                     (uint32_t)(op.ldb * (int64_t)sizeof(T)), lane, acc);
+  accumulate_range<64, V, E>(t, d.p0, d.p1, reinterpret_cast<const char*>(op.B) + cl * (int64_t)sizeof(T),
+                             (uint32_t)(op.ldb * (int64_t)sizeof(T)), lane, acc);
   if (active) store_f32v<V>(P.partial + bt.part_off + (int64_t)s * bt.ldp + c0, acc);
 }
 
-template <typename E, bool ACC>
-__device__ __forceinline__ void run_item(const BatchParams& P, const BatchItem& it, int32_t* s_pref,
-                                         int32_t* s_beg) {
-  const BatchTileDev& bt = P.tiles[it.tile];
-  const Ops<E> op = item_ops<E>(P, it.tile);
-  const int64_t r0 = it.a;
-  if (it.type == 1) {
-    switch (bt.V) {
-      case 1: item_unit<1, E>(P, bt, op, it.a, it.window); return;
-      case 2: item_unit<2, E>(P, bt, op, it.a, it.window); return;
-      default: item_unit<4, E>(P, bt, op, it.a, it.window); return;
-    }
-  }
-  if (bt.kind == 0) {
-    switch (bt.V) {
-      case 1: item_stream<1, E, ACC>(bt, op, r0, it.window, s_pref, s_beg); return;
-      case 2: item_stream<2, E, ACC>(bt, op, r0, it.window, s_pref, s_beg); return;
-      default: item_stream<4, E, ACC>(bt, op, r0, it.window, s_pref, s_beg); return;
-    }
-  }
-  constexpr int VW = 4;  // row-split items: 4 elements per lane (16 bytes FP32, 8 bytes BF16)
-  switch (bt.G) {
-    case 8: item_rowsplit<8, VW, E, ACC>(bt, op, r0, it.window); return;
-    case 16: item_rowsplit<16, VW, E, ACC>(bt, op, r0, it.window); return;
-    default: item_rowsplit<32, VW, E, ACC>(bt, op, r0, it.window); return;
-  }
-}
-
-// At most 80 VGPRs, so that six waves per SIMD can hide the gather latency.
-template <typename E, bool ACC>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) batch_main(BatchParams P) {
+// One persistent kernel per item class, so that every class runs with its own
+// register allocation (and hence occupancy) instead of the largest one's.
+template <typename E, bool ACC, int CLS>
+__global__ void __launch_bounds__(kBlock) batch_class(BatchParams P) {
   __shared__ int32_t s_mem[(kBlock / 64) * 129];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
@@ -239,7 +226,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))
     const unsigned it = (unsigned)__builtin_amdgcn_readlane((int)claimed, 0);
     if ((int64_t)it >= P.n_items) break;  // every wave leaves once the list is drained
     const BatchItem item = P.items[it];
-    run_item<E, ACC>(P, item, s_pref, s_beg);
+    const BatchTileDev& bt = P.tiles[item.tile];
+    const Ops<E> op = item_ops<E>(P, item.tile);
+    if constexpr (CLS < kClassRowsplit) {
+      item_stream<1 << CLS, E, ACC>(bt, op, item.a, item.window, s_pref, s_beg);
+    } else if constexpr (CLS < kClassUnit) {
+      item_rowsplit<8 << (CLS - kClassRowsplit), 4, E, ACC>(bt, op, item.a, item.window);
+    } else {
+      item_unit<1 << (CLS - kClassUnit), E>(P, bt, op, item.a, item.window);
+    }
   }
 }
 
@@ -277,40 +272,89 @@ __global__ void __launch_bounds__(kBlock) batch_fixup(BatchParams P) {
   }
 }
 
-// Reset the claim counter inside the stream (a kernel, so that a captured graph
-// resets it on every replay).
-__global__ void batch_reset(unsigned* counter) { *counter = 0u; }
+// Reset the claim counters inside the stream (a kernel, so that a captured graph
+// resets them on every replay).
+__global__ void batch_reset(unsigned* counter, int n) {
+  if ((int)threadIdx.x < n) counter[threadIdx.x] = 0u;
+}
+
+template <typename E, bool ACC, int CLS>
+hipError_t launch_class(const BatchParams& P, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((batch_class<E, ACC, CLS>), dim3((unsigned)grid), dim3(kBlock), 0, s, P);
+  return hipGetLastError();
+}
 
 template <typename E, bool ACC>
-hipError_t launch_batch_t(const BatchParams& P, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, P.counter);
+hipError_t launch_batch_t(const BatchParams& P0, const int64_t* off, const int64_t* cnt, const int* grid,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(batch_reset, dim3(1), dim3(64), 0, s, P0.counter, kBatchClasses);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (P.n_items > 0) {
-    hipLaunchKernelGGL((batch_main<E, ACC>), dim3((unsigned)grid), dim3(kBlock), 0, s, P);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+  // units first (their partials feed the fix-up), then the row classes
+  static constexpr int order[kBatchClasses] = {7, 8, 9, 0, 1, 2, 3, 4, 5, 6};
+  for (int oi = 0; oi < kBatchClasses && e == hipSuccess; ++oi) {
+    const int c = order[oi];
+    if (cnt[c] == 0) continue;
+    BatchParams P = P0;
+    P.items = P0.items + off[c];
+    P.n_items = cnt[c];
+    P.counter = P0.counter + c;
+    switch (c) {
+      case 0: e = launch_class<E, ACC, 0>(P, grid[c], s); break;
+      case 1: e = launch_class<E, ACC, 1>(P, grid[c], s); break;
+      case 2: e = launch_class<E, ACC, 2>(P, grid[c], s); break;
+      case 3: e = launch_class<E, ACC, 3>(P, grid[c], s); break;
+      case 4: e = launch_class<E, ACC, 4>(P, grid[c], s); break;
+      case 5: e = launch_class<E, ACC, 5>(P, grid[c], s); break;
+      case 6: e = launch_class<E, ACC, 6>(P, grid[c], s); break;
+      case 7: e = launch_class<E, ACC, 7>(P, grid[c], s); break;
+      case 8: e = launch_class<E, ACC, 8>(P, grid[c], s); break;
+      default: e = launch_class<E, ACC, 9>(P, grid[c], s); break;
+    }
   }
-  if (P.n_fix > 0) {
-    hipLaunchKernelGGL((batch_fixup<E, ACC>), dim3((unsigned)((P.n_fix + 3) / 4)), dim3(kBlock), 0, s, P);
+  if (e == hipSuccess && P0.n_fix > 0) {
+    hipLaunchKernelGGL((batch_fixup<E, ACC>), dim3((unsigned)((P0.n_fix + 3) / 4)), dim3(kBlock), 0, s, P0);
     e = hipGetLastError();
   }
   return e;
 }
 
-}  // namespace
-
-hipError_t launch_batch(const BatchParams& P, DT dt, int grid, hipStream_t s) {
-  if (dt == DT::F32)
-    return P.accumulate ? launch_batch_t<F32E, true>(P, grid, s) : launch_batch_t<F32E, false>(P, grid, s);
-  return P.accumulate ? launch_batch_t<BF16E, true>(P, grid, s) : launch_batch_t<BF16E, false>(P, grid, s);
+template <typename E, int CLS>
+int occupancy_of() {
+  int n = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_class<E, false, CLS>, kBlock, 0);
+  return (e == hipSuccess && n > 0) ? n : 2;
 }
 
-int batch_blocks_per_cu(DT dt) {
-  int n = 0;
-  hipError_t e = dt == DT::F32
-                     ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_main<F32E, false>, kBlock, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_main<BF16E, false>, kBlock, 0);
-  return (e == hipSuccess && n > 0) ? n : 2;
+template <typename E>
+void occupancy_all(int* out) {
+  out[0] = occupancy_of<E, 0>();
+  out[1] = occupancy_of<E, 1>();
+  out[2] = occupancy_of<E, 2>();
+  out[3] = occupancy_of<E, 3>();
+  out[4] = occupancy_of<E, 4>();
+  out[5] = occupancy_of<E, 5>();
+  out[6] = occupancy_of<E, 6>();
+  out[7] = occupancy_of<E, 7>();
+  out[8] = occupancy_of<E, 8>();
+  out[9] = occupancy_of<E, 9>();
+}
+
+}  // namespace
+
+hipError_t launch_batch(const BatchParams& P, const int64_t* off, const int64_t* cnt, const int* grid, DT dt,
+                        hipStream_t s) {
+  if (dt == DT::F32)
+    return P.accumulate ? launch_batch_t<F32E, true>(P, off, cnt, grid, s)
+                        : launch_batch_t<F32E, false>(P, off, cnt, grid, s);
+  return P.accumulate ? launch_batch_t<BF16E, true>(P, off, cnt, grid, s)
+                      : launch_batch_t<BF16E, false>(P, off, cnt, grid, s);
+}
+
+void batch_blocks_per_cu(DT dt, int* out) {
+  if (dt == DT::F32)
+    occupancy_all<F32E>(out);
+  else
+    occupancy_all<BF16E>(out);
 }
 
 }  // namespace spmm

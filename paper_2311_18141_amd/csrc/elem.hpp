@@ -141,6 +141,42 @@ __device__ __forceinline__ void store_vec(typename E::T* p, const float (&x)[V])
   }
 }
 
+// The same store with a non-temporal hint: output rows are written once and never
+// re-read by the kernel, so they should not displace gathered B rows in the caches.
+template <typename E, int V>
+__device__ __forceinline__ void store_vec_nt(typename E::T* p, const float (&x)[V]) {
+  if constexpr (sizeof(typename E::T) == 4) {
+    if constexpr (V == 1) {
+      __builtin_nontemporal_store(x[0], p);
+    } else if constexpr (V == 2) {
+      f32x2_t v = {x[0], x[1]};
+      __builtin_nontemporal_store(v, reinterpret_cast<f32x2_t*>(p));
+    } else if constexpr (V == 4) {
+      f32x4_t v = {x[0], x[1], x[2], x[3]};
+      __builtin_nontemporal_store(v, reinterpret_cast<f32x4_t*>(p));
+    } else {
+      f32x4_t v0 = {x[0], x[1], x[2], x[3]}, v1 = {x[4], x[5], x[6], x[7]};
+      __builtin_nontemporal_store(v0, reinterpret_cast<f32x4_t*>(p));
+      __builtin_nontemporal_store(v1, reinterpret_cast<f32x4_t*>(p) + 1);
+    }
+  } else {
+    uint32_t h[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) h[e] = f32_to_bf16_bits(x[e]);
+    if constexpr (V == 1) {
+      __builtin_nontemporal_store((uint16_t)h[0], p);
+    } else if constexpr (V == 2) {
+      __builtin_nontemporal_store(h[0] | (h[1] << 16), reinterpret_cast<uint32_t*>(p));
+    } else if constexpr (V == 4) {
+      u32x2_t v = {h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
+      __builtin_nontemporal_store(v, reinterpret_cast<u32x2_t*>(p));
+    } else {
+      u32x4_t v = {h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16)};
+      __builtin_nontemporal_store(v, reinterpret_cast<u32x4_t*>(p));
+    }
+  }
+}
+
 // FP32 partial sums (always FP32, V consecutive, aligned).
 template <int V>
 __device__ __forceinline__ void load_f32v(const float* p, float (&x)[V]) {

@@ -69,10 +69,10 @@ __global__ void __launch_bounds__(kBlock) fwd_main(FwdParams P) {
 #pragma unroll
     for (int e = 0; e < V; ++e) acc[e] += old[e];
   }
-  store_vec<E, V>(c, acc);
+  store_vec_nt<E, V>(c, acc);
 }
 
-// Stream variant: one wave owns 64 consecutive rows (one per lane for the
+// Stream variant: one wave owns R <= 64 consecutive rows (one per lane for the
 // bookkeeping) and walks the concatenation of their non-zeros, over all
 // k-tiles in k' order, 64 entries at a time.  Every entry's B row address and
 // value are formed by the lane that loaded it, then consumed in order by the
@@ -97,7 +97,7 @@ __device__ __forceinline__ void store_row(const FwdParams& P, int64_t row, int64
 #pragma unroll
     for (int e = 0; e < V; ++e) acc[e] += old[e];
   }
-  store_vec<E, V>(c, acc);
+  store_vec_nt<E, V>(c, acc);
 }
 
 template <int V, typename E, bool ACC>
@@ -128,13 +128,14 @@ __global__ void __launch_bounds__(kBlock) fwd_stream(FwdParams P) {
     return;
   }
 
-  const int64_t r0 = group_uniform<64>((((int64_t)blockIdx.x - unit_blocks) * GPB + w) * 64);
+  const int R = P.stream_rows;  // rows per wave (1..64); lanes >= R carry no row
+  const int64_t r0 = group_uniform<64>((((int64_t)blockIdx.x - unit_blocks) * GPB + w) * R);
   if (r0 >= P.rows) return;
   int32_t* s_pref = s_mem + w * (65 + 128 * K);  // exclusive prefix of streamed lengths, [64] = total
   int32_t* s_beg = s_pref + 65;                   // [kk][lane]: first CSR position of the row in tile kk
   int32_t* s_koff = s_beg + 64 * K;               // [kk][lane]: offset of tile kk inside the row
   const int64_t row = r0 + lane;
-  const bool inrow = row < P.rows;
+  const bool inrow = lane < R && row < P.rows;
   int32_t L = 0;
   for (int kk = 0; kk < K; ++kk) {
     int k = kk + P.k_offset;
@@ -172,7 +173,7 @@ __global__ void __launch_bounds__(kBlock) fwd_stream(FwdParams P) {
     while (em) {
       const int i = __ffsll((long long)em) - 1;
       em &= em - 1;
-      if (active) store_vec<E, V>(static_cast<T*>(P.C) + (r0 + i) * P.ldc + c0, z);
+      if (active) store_vec_nt<E, V>(static_cast<T*>(P.C) + (r0 + i) * P.ldc + c0, z);
     }
   }
 
@@ -260,6 +261,24 @@ __global__ void __launch_bounds__(kBlock) fwd_stream(FwdParams P) {
   }
 }
 
+// acc += partial rows [a, b) in order, eight loads in flight.
+template <int V>
+__device__ __forceinline__ void sum_partials(const FwdParams& P, int a, int b, int64_t c0, float (&acc)[V]) {
+  for (int s = a; s < b; s += 8) {
+    float x[8][V];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) load_f32v<V>(P.partial + (int64_t)min(s + u, b - 1) * P.ldp + c0, x[u]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (s + u < b) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc[e] += x[u][e];
+      }
+  }
+}
+
+// One group per split row: the row's units are stored by k-tile (0..K-1), so the
+// k' order (k = (k' + k_offset) mod K) is the units of k >= k_offset, then the rest.
 template <int G, int V, typename E>
 __global__ void __launch_bounds__(kBlock) fwd_fixup(FwdParams P) {
   constexpr int GPB = kBlock / G;
@@ -268,20 +287,20 @@ __global__ void __launch_bounds__(kBlock) fwd_fixup(FwdParams P) {
   const int64_t r = group_uniform<G>((int64_t)blockIdx.x * GPB + threadIdx.x / G);
   if (r >= P.n_long || c0 >= P.N) return;
   const LongRow lr = P.lrow[r];
+  int m = lr.s0;
+  if (P.k_offset > 0) {  // first unit with k >= k_offset
+    int lo = lr.s0, hi = lr.s1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (P.seg[mid].k < P.k_offset) lo = mid + 1; else hi = mid;
+    }
+    m = lo;
+  }
   float acc[V];
 #pragma unroll
   for (int e = 0; e < V; ++e) acc[e] = 0.0f;
-  for (int kk = 0; kk < P.num_k; ++kk) {
-    int k = kk + P.k_offset;
-    if (k >= P.num_k) k -= P.num_k;
-    for (int s = lr.s0; s < lr.s1; ++s) {
-      if (P.seg[s].k != k) continue;
-      float x[V];
-      load_f32v<V>(P.partial + (int64_t)s * P.ldp + c0, x);
-#pragma unroll
-      for (int e = 0; e < V; ++e) acc[e] += x[e];
-    }
-  }
+  sum_partials<V>(P, m, lr.s1, c0, acc);
+  sum_partials<V>(P, lr.s0, m, c0, acc);
   typename E::T* c = static_cast<typename E::T*>(P.C) + (int64_t)lr.row * P.ldc + c0;
   if (P.accumulate) {
     float old[V];
@@ -299,8 +318,8 @@ hipError_t launch_gv(const FwdParams& P0, bool stream, hipStream_t s) {
   const int64_t unit_blocks = (P.n_seg + GPB - 1) / GPB;
   const int64_t windows = (P.N + G * V - 1) / (G * V);
   if (stream) {
-    // 64 rows per wave, GPB waves per workgroup
-    const int64_t row_blocks = (P.rows + 64 * GPB - 1) / (64 * GPB);
+    // stream_rows rows per wave, GPB waves per workgroup
+    const int64_t row_blocks = (P.rows + (int64_t)P.stream_rows * GPB - 1) / ((int64_t)P.stream_rows * GPB);
     P.row_blocks = row_blocks;
     const size_t lds = sizeof(int32_t) * (size_t)GPB * (65 + 128 * (size_t)P.num_k);
     dim3 grid((unsigned)(unit_blocks + row_blocks), (unsigned)windows);
@@ -326,7 +345,11 @@ hipError_t launch_gv(const FwdParams& P0, bool stream, hipStream_t s) {
 
 template <typename E, int V>
 hipError_t launch_v(const FwdParams& P, const Variant& v, hipStream_t s) {
-  if (v.stream) return launch_gv<64, V, E>(P, true, s);
+  if (v.stream) {
+    FwdParams Q = P;
+    Q.stream_rows = (v.rows >= 1 && v.rows <= 64) ? v.rows : 64;
+    return launch_gv<64, V, E>(Q, true, s);
+  }
   switch (v.G) {
     case 4: return launch_gv<4, V, E>(P, false, s);
     case 8: return launch_gv<8, V, E>(P, false, s);

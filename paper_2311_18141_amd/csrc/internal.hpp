@@ -51,6 +51,7 @@ struct FwdParams {
   float* partial;        // n_seg x ldp FP32 partial sums
   int64_t ldp;
   int64_t row_blocks;    // workgroups of the row-split part (units come after)
+  int32_t stream_rows;   // stream variant: rows per wave (1..64)
 };
 
 // Kernel variant: G lanes per row (group), V elements per lane per load;
@@ -59,6 +60,7 @@ struct Variant {
   int G;
   int V;
   bool stream = false;
+  int rows = 64;  // stream: rows per wave
 };
 
 // ---- launchers (defined in the .hip files) --------------------------------
@@ -101,8 +103,14 @@ struct BatchParams {
   unsigned* counter;
   int accumulate;
 };
-hipError_t launch_batch(const BatchParams& P, DT dt, int grid, hipStream_t s);
-int batch_blocks_per_cu(DT dt);
+// Item classes: stream V = 1, 2, 4 (0..2); row-split G = 8, 16, 32, 64 with V = 4 (3..6);
+// split-row units with V = 1, 2, 4 (7..9).
+constexpr int kClassRowsplit = 3;
+constexpr int kClassUnit = 7;
+constexpr int kBatchClasses = 10;
+hipError_t launch_batch(const BatchParams& P, const int64_t* off, const int64_t* cnt, const int* grid, DT dt,
+                        hipStream_t s);
+void batch_blocks_per_cu(DT dt, int* out);
 
 struct SddmmParams {
   const int32_t* rowid;

@@ -42,7 +42,16 @@ __global__ void __launch_bounds__(kBlock) validate_colind_kernel(const int32_t* 
 
 // ---------------------------------------------------------------------------
 // Row statistics and the split-row plan.
+// A split row of combined length L is cut into units of max(segment, ceil(sqrt(L)))
+// non-zeros of one k-tile: a unit then costs about as many dependent load rounds as
+// the fix-up that sums the row's units, so neither becomes the tail.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t unit_length(int64_t len, int32_t segment) {
+  int64_t r = (int64_t)sqrtf((float)len);
+  while (r * r < len) ++r;
+  return r > segment ? r : segment;
+}
+
 __global__ void __launch_bounds__(kBlock) plan_count_kernel(PlanCountParams P) {
   __shared__ unsigned long long s_stats[35];
   for (int t = threadIdx.x; t < 35; t += kBlock) s_stats[t] = 0;
@@ -50,10 +59,11 @@ __global__ void __launch_bounds__(kBlock) plan_count_kernel(PlanCountParams P) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < P.rows) {
     int64_t len = 0, units = 0;
+    for (int k = 0; k < P.num_k; ++k) len += (int64_t)P.rowptr[k][i + 1] - P.rowptr[k][i];
+    const int64_t sl = unit_length(len, P.segment);
     for (int k = 0; k < P.num_k; ++k) {
       const int64_t l = (int64_t)P.rowptr[k][i + 1] - P.rowptr[k][i];
-      len += l;
-      units += (l + P.segment - 1) / P.segment;
+      units += (l + sl - 1) / sl;
     }
     const bool split = len > P.long_row;
     P.nseg[i] = split ? (int32_t)units : 0;
@@ -78,10 +88,13 @@ __global__ void __launch_bounds__(kBlock) plan_emit_kernel(PlanEmitParams P) {
   if (i >= P.rows || !P.islong[i]) return;
   int32_t o = P.seg_off[i];
   P.lrow[P.long_off[i]] = LongRow{(int32_t)i, o, o + P.nseg[i], 0};
+  int64_t len = 0;
+  for (int k = 0; k < P.num_k; ++k) len += (int64_t)P.rowptr[k][i + 1] - P.rowptr[k][i];
+  const int32_t sl = (int32_t)unit_length(len, P.segment);
   for (int k = 0; k < P.num_k; ++k) {
     const int32_t p0 = P.rowptr[k][i], p1 = P.rowptr[k][i + 1];
-    for (int32_t p = p0; p < p1; p += P.segment) {
-      const int32_t e = (p1 - p > P.segment) ? p + P.segment : p1;
+    for (int32_t p = p0; p < p1; p += sl) {
+      const int32_t e = (p1 - p > sl) ? p + sl : p1;
       P.seg[o++] = Seg{(int32_t)i, k, p, e};
     }
   }

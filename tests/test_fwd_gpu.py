@@ -300,7 +300,8 @@ def test_variants_agree_bitwise_on_integers():
     Bd = [G.dense_dev(b) for b in Bs]
     tile = G.make_tile(tiles, long_row=64, segment=32)
     for kind, lanes, vec in [("rowsplit", 4, 1), ("rowsplit", 8, 2), ("rowsplit", 16, 4), ("rowsplit", 32, 2),
-                             ("rowsplit", 64, 1), ("stream", 0, 1), ("stream", 0, 2), ("stream", 0, 4)]:
+                             ("rowsplit", 64, 1), ("stream", 0, 1), ("stream", 0, 2), ("stream", 0, 4),
+                             ("stream", 4, 2), ("stream", 16, 1), ("stream", 32, 4), ("stream", 64, 2)]:
         _pin(tile, N, kind, lanes=lanes, vec=vec)
         got = G.host_f32(G.fwd(tile, Bd))
         assert np.array_equal(got.astype(np.float64), ref), (kind, lanes, vec)
