@@ -842,8 +842,22 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
       if (A->plan.n_seg > 0)
         HIP_TRY(hipMemcpyAsync(segs.data(), A->plan.seg, sizeof(spmm::Seg) * segs.size(), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
-      for (int64_t r0 = 0; r0 < A->rows; r0 += 64) {
-        const int64_t r1 = std::min<int64_t>(A->rows, r0 + 64);
+      // Rows per item: about 2K non-zeros of work (so that the waves of the GPU share
+      // few tiles at a time), a whole number of row groups, at most 64 rows.
+      int64_t nz_short = 0, rows_short = 0;
+      for (int64_t r = 0; r < A->rows; ++r) {
+        const int64_t l = (int64_t)rp[r + 1] - rp[r];
+        if (l <= d.long_row) {
+          nz_short += l;
+          ++rows_short;
+        }
+      }
+      const double avg = rows_short ? (double)nz_short / (double)rows_short : 1.0;
+      const int unit_rows = d.kind == 0 ? 1 : 64 / d.G;
+      int rpi = 64;
+      while (rpi > unit_rows && rpi * std::max(avg, 1.0) > 2048.0) rpi /= 2;
+      for (int64_t r0 = 0; r0 < A->rows; r0 += rpi) {
+        const int64_t r1 = std::min<int64_t>(A->rows, r0 + rpi);
         int64_t nz = 0;
         for (int64_t r = r0; r < r1; ++r) {
           const int64_t l = (int64_t)rp[r + 1] - rp[r];
@@ -851,7 +865,7 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
         }
         for (int w = 0; w < nw_rows; ++w) {
           const double width = (double)std::min<int64_t>(wrow, N[t] - w * wrow);
-          items.push_back({(double)(nz + (r1 - r0)) * width, spmm::BatchItem{t, (int32_t)r0, w, 0}});
+          items.push_back({(double)(nz + (r1 - r0)) * width, spmm::BatchItem{t, (int32_t)r0, w, (int32_t)((r1 - r0) << 8)}});
         }
       }
       for (int64_t si = 0; si < A->plan.n_seg; ++si)
@@ -880,7 +894,7 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
     auto log2i = [](int v) { int l = 0; while ((1 << l) < v) ++l; return l; };
     auto cls = [&](const spmm::BatchItem& it) {
       const spmm::BatchTileDev& d = bt[it.tile];
-      if (it.type == 1) return spmm::kClassUnit + log2i(d.V);
+      if ((it.type & 255) == 1) return spmm::kClassUnit + log2i(d.V);
       if (d.kind == 0) return log2i(d.V);
       return spmm::kClassRowsplit + log2i(d.G / 8);
     };
@@ -888,8 +902,8 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
       const int cx = cls(x.it), cy = cls(y.it);
       if (cx != cy) return cx < cy;
       if (x.it.tile != y.it.tile) return rank[x.it.tile] < rank[y.it.tile];
-      if (x.it.type != y.it.type) return x.it.type > y.it.type;  // units (1) before rows (0)
-      if (x.it.type == 1) return x.cost > y.cost;
+      if ((x.it.type & 255) != (y.it.type & 255)) return (x.it.type & 255) > (y.it.type & 255);  // units first
+      if ((x.it.type & 255) == 1) return x.cost > y.cost;
       return false;                                               // rows keep their order
     });
     std::vector<spmm::BatchItem> list(items.size());

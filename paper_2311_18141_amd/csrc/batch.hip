@@ -44,9 +44,9 @@ __device__ __forceinline__ void store_c(typename E::T* c, float (&acc)[V]) {
   store_vec<E, V>(c, acc);
 }
 
-// 64 rows [r0, r0+64) of one tile, streamed by the whole wave (see fwd_stream).
+// Rows [r0, r0+nrows) (nrows <= 64) of one tile, streamed by the whole wave (see fwd_stream).
 template <int V, typename E, bool ACC>
-__device__ __forceinline__ void item_stream(const BatchTileDev& bt, const Ops<E>& op, int64_t r0, int window,
+__device__ __forceinline__ void item_stream(const BatchTileDev& bt, const Ops<E>& op, int64_t r0, int nrows, int window,
                                             int32_t* s_pref, int32_t* s_beg) {
   using T = typename E::T;
   constexpr int U = V >= 8 ? 4 : 8;
@@ -55,7 +55,7 @@ __device__ __forceinline__ void item_stream(const BatchTileDev& bt, const Ops<E>
   const bool active = c0 < bt.N;
   const int64_t cl = active ? c0 : 0;
   const int64_t row = r0 + lane;
-  const bool inrow = row < bt.rows;
+  const bool inrow = lane < nrows && row < bt.rows;
   int32_t b = 0, L = 0;
   if (inrow) {
     b = bt.rowptr[row];
@@ -149,9 +149,10 @@ __device__ __forceinline__ void item_stream(const BatchTileDev& bt, const Ops<E>
   }
 }
 
-// 64 rows [r0, r0+64) of one tile, 64/G rows at a time, G lanes per row.
+// Rows [r0, r0+nrows) of one tile, 64/G rows at a time, G lanes per row.
 template <int G, int V, typename E, bool ACC>
-__device__ __forceinline__ void item_rowsplit(const BatchTileDev& bt, const Ops<E>& op, int64_t r0, int window) {
+__device__ __forceinline__ void item_rowsplit(const BatchTileDev& bt, const Ops<E>& op, int64_t r0, int nrows,
+                                              int window) {
   using T = typename E::T;
   constexpr int GPW = 64 / G;
   const int lane = threadIdx.x & 63;
@@ -168,10 +169,10 @@ __device__ __forceinline__ void item_rowsplit(const BatchTileDev& bt, const Ops<
   t.ldb = op.ldb;
   const char* brow = reinterpret_cast<const char*>(op.B) + cl * (int64_t)sizeof(T);
   const uint32_t ldbb = (uint32_t)(op.ldb * (int64_t)sizeof(T));
-  for (int rr = 0; rr < 64; rr += GPW) {
+  for (int rr = 0; rr < nrows; rr += GPW) {
     const int64_t row = r0 + rr + lane / G;
     int32_t p0 = 0, p1 = 0;
-    const bool inrow = row < bt.rows;
+    const bool inrow = rr + lane / G < nrows && row < bt.rows;
     if (inrow) {
       p0 = bt.rowptr[row];
       p1 = bt.rowptr[row + 1];
@@ -228,10 +229,11 @@ __global__ void __launch_bounds__(kBlock) batch_class(BatchParams P) {
     const BatchItem item = P.items[it];
     const BatchTileDev& bt = P.tiles[item.tile];
     const Ops<E> op = item_ops<E>(P, item.tile);
+    const int nrows = item.type >> 8;
     if constexpr (CLS < kClassRowsplit) {
-      item_stream<1 << CLS, E, ACC>(bt, op, item.a, item.window, s_pref, s_beg);
+      item_stream<1 << CLS, E, ACC>(bt, op, item.a, nrows, item.window, s_pref, s_beg);
     } else if constexpr (CLS < kClassUnit) {
-      item_rowsplit<8 << (CLS - kClassRowsplit), 4, E, ACC>(bt, op, item.a, item.window);
+      item_rowsplit<8 << (CLS - kClassRowsplit), 4, E, ACC>(bt, op, item.a, nrows, item.window);
     } else {
       item_unit<1 << (CLS - kClassUnit), E>(P, bt, op, item.a, item.window);
     }

@@ -84,7 +84,8 @@ struct BatchTileDev {
   int32_t pad;
 };
 
-// type 0: rows [a, a+64) of `tile`, column window `window`; 1: split-row unit a; 2: split row a (fix-up).
+// type & 255 = 0: rows [a, a + (type >> 8)) of `tile` (at most 64), column window `window`;
+// 1: split-row unit a; 2: split row a (fix-up).
 struct BatchItem {
   int32_t tile, a, window, type;
 };
