@@ -760,12 +760,15 @@ void batch_variant(const spmm_tile_s* A, int64_t N, DT dt, spmm::BatchTileDev* b
   if (e) {
     stream = e->kind == SPMM_KERNEL_STREAM;
     if (stream && e->vec && (N % e->vec) == 0) Vs = e->vec;
-    if (!stream && e->lanes >= 8) G = e->lanes;
+    if (!stream && e->lanes >= 4 && e->vec >= 1) {
+      // keep the tuned column window (lanes x vec) with the batch's 4-element vectors
+      G = std::max(8, std::min(64, e->lanes * e->vec / 4));
+    }
   }
   if (!stream) {
     if ((N % 4) != 0) {  // row-split items load 4 elements per lane; otherwise stream
       stream = true;
-    } else if (!e || e->lanes < 8) {
+    } else if (!e || e->lanes < 4) {
       G = 8;
       while (G < 64 && G * 4 < N) G *= 2;
     }
