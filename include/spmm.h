@@ -138,6 +138,14 @@ typedef struct {
    16 entries full). */
 spmm_status spmm_tile_set_variant(spmm_tile_t tile, int64_t N, spmm_dtype dtype, const spmm_variant* v);
 
+/* Shape of the backward's sampled dense-dense kernel (dA on A's pattern; a gradient
+   pass this library adds, not a kernel of the paper) at width N: groups of
+   `lanes` lanes (4, 8, 16, 32, 64), each owning `nnz_per_group` consecutive non-zeros
+   (1, 2, 4, 8; at most `lanes`).  lanes = 0 clears the entry (library choice).  Results
+   do not depend on the shape beyond FP32 summation order within a dot product.
+   Errors: INVALID_ARG (bad values, table of 8 entries full). */
+spmm_status spmm_tile_set_sddmm_variant(spmm_tile_t tile, int64_t N, int32_t lanes, int32_t nnz_per_group);
+
 /* Time the forward variants (and, with tune_plan != 0, split thresholds, which
    rebuilds the handle's split-row plan) on the caller's real operands and keep the
    fastest for (N, dtype).  Synchronous; allocates its own scratch; overwrites C.
@@ -184,10 +192,11 @@ spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* 
  * one persistent kernel (plus a small reset kernel before it and, when some tile
  * has split rows, a fix-up kernel after it).
  *
- * spmm_batch_create builds, synchronously, the work list: items of 64 rows of one
- * tile and one column window (and the split-row units of each tile's plan), with
- * each tile's kernel variant taken from its handle's entry for (N_t, dtype) (set
- * by spmm_tile_autotune or spmm_tile_set_variant) or from a fixed rule, sorted by
+ * spmm_batch_create builds, synchronously, the work list: items of up to 64 rows
+ * of one tile and one column window, holding about `item_nnz` non-zeros (0: 2048;
+ * else 64..1048576), and the split-row units of each tile's plan, with each tile's
+ * kernel variant taken from its handle's entry for (N_t, dtype) (set by
+ * spmm_tile_autotune or spmm_tile_set_variant) or from a fixed rule, sorted by
  * descending cost.  Every tile must be a single-tile handle (num_k = 1) on the
  * current device, and must outlive the batch.  The batch allocates its own device
  * memory (work list, claim counter).  Errors: INVALID_ARG, UNSUPPORTED (num_k > 1),
@@ -195,8 +204,8 @@ spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* 
  */
 typedef struct spmm_batch_s* spmm_batch_t;
 spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles /* host, count */,
-                              const int64_t* N /* host, count */, spmm_dtype dtype, void* stream,
-                              spmm_batch_t* out /* host */);
+                              const int64_t* N /* host, count */, spmm_dtype dtype, int64_t item_nnz,
+                              void* stream, spmm_batch_t* out /* host */);
 spmm_status spmm_batch_destroy(spmm_batch_t batch);
 /* Workspace (device bytes) spmm_batched needs: FP32 partial rows of split rows. */
 spmm_status spmm_batch_workspace_bytes(spmm_batch_t batch, size_t* bytes /* host */);

@@ -182,6 +182,12 @@ struct spmm_tile_s {
   VarEntry vt[16];
   int nvt = 0;
   int64_t bwd_slice = 0;   // SDDMM column slice (0 = all columns in one launch)
+  struct SddmmEntry {
+    int64_t N;
+    int G, U;
+  };
+  SddmmEntry sd[8];
+  int nsd = 0;
 
   ~spmm_tile_s() {
     free_plan(plan);
@@ -495,6 +501,28 @@ spmm_status spmm_tile_set_variant(spmm_tile_t A, int64_t N, spmm_dtype dtype, co
   return SPMM_OK;
 }
 
+spmm_status spmm_tile_set_sddmm_variant(spmm_tile_t A, int64_t N, int32_t lanes, int32_t nnz_per_group) {
+  if (!A) return fail(SPMM_ERR_INVALID_ARG, "tile is null");
+  if (N < 1) return fail(SPMM_ERR_INVALID_ARG, "N=%lld < 1", (long long)N);
+  int slot = -1;
+  for (int i = 0; i < A->nsd; ++i)
+    if (A->sd[i].N == N) slot = i;
+  if (lanes == 0) {
+    if (slot >= 0) A->sd[slot] = A->sd[--A->nsd];
+    return SPMM_OK;
+  }
+  if (!pow2_lanes(lanes)) return fail(SPMM_ERR_INVALID_ARG, "lanes=%d is not 4, 8, 16, 32 or 64", lanes);
+  if (nnz_per_group != 1 && nnz_per_group != 2 && nnz_per_group != 4 && nnz_per_group != 8)
+    return fail(SPMM_ERR_INVALID_ARG, "nnz_per_group=%d is not 1, 2, 4 or 8", nnz_per_group);
+  if (nnz_per_group > lanes) return fail(SPMM_ERR_INVALID_ARG, "nnz_per_group > lanes");
+  if (slot < 0) {
+    if (A->nsd >= 8) return fail(SPMM_ERR_INVALID_ARG, "SDDMM variant table is full");
+    slot = A->nsd++;
+  }
+  A->sd[slot] = {N, lanes, nnz_per_group};
+  return SPMM_OK;
+}
+
 spmm_status spmm_tile_autotune(spmm_tile_t A, int64_t N, spmm_dtype dtype, const void* const* B,
                                const int64_t* ldb, void* C, int64_t ldc, int tune_plan, void* stream,
                                spmm_variant* chosen) {
@@ -647,7 +675,6 @@ spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* 
   if (dA_values && ldb < N) return fail(SPMM_ERR_INVALID_ARG, "ldb < N");
   if (dB && lddb < N) return fail(SPMM_ERR_INVALID_ARG, "lddb < N");
   if (lddc * 4 >= ((int64_t)1 << 32)) return fail(SPMM_ERR_UNSUPPORTED, "lddc * 4 >= 2^32");
-  if (lddc * 4 >= ((int64_t)1 << 32)) return fail(SPMM_ERR_UNSUPPORTED, "lddc * 4 >= 2^32");
   const spmm_csr& t = A->t[0];
   const size_t need = dB ? sizeof(float) * partial_ld(N) * (size_t)A->planT.n_seg : 0;
   if (need > 0) {
@@ -679,13 +706,22 @@ spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* 
     // Column slices: one launch per slice of `slice` columns (all of N when 0).
     const int64_t slice = (A->bwd_slice > 0 && A->bwd_slice < N && (A->bwd_slice % V) == 0) ? A->bwd_slice : N;
     const int64_t need_lanes = (slice + V - 1) / V;
+    // 8 lanes x U = 4 non-zeros per group: 32 B rows in flight per wave measured best
+    // on the heavy-tailed 2M x 2M matrix at N = 128 (narrower slices use fewer lanes).
     int G = 4;
-    while (G < 16 && G * 2 <= need_lanes) G *= 2;
+    while (G < 8 && G < need_lanes) G *= 2;
+    int U = 4;
+    for (int i = 0; i < A->nsd; ++i)
+      if (A->sd[i].N == N) {
+        G = A->sd[i].G;
+        U = A->sd[i].U;
+      }
+    if (U > G) U = G;
     for (int64_t c = 0; c < N; c += slice) {
       P.c_begin = c;
       P.c_end = c + slice < N ? c + slice : N;
       P.accumulate = c > 0 ? 1 : 0;
-      HIP_TRY(spmm::launch_sddmm(P, spmm::Variant{G, V}, s));
+      HIP_TRY(spmm::launch_sddmm(P, G, V, U, s));
     }
   }
   if (dB && t.cols > 0) {
@@ -783,13 +819,16 @@ void batch_variant(const spmm_tile_s* A, int64_t N, DT dt, spmm::BatchTileDev* b
 
 extern "C" {
 
-spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t* N, spmm_dtype dtype, void* stream,
-                              spmm_batch_t* out) {
+spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t* N, spmm_dtype dtype,
+                              int64_t item_nnz, void* stream, spmm_batch_t* out) {
   if (!out) return fail(SPMM_ERR_INVALID_ARG, "out is null");
   *out = nullptr;
   if (count < 1) return fail(SPMM_ERR_INVALID_ARG, "count=%d < 1", count);
   if (!tiles || !N) return fail(SPMM_ERR_INVALID_ARG, "tiles/N is null");
   if (dtype != SPMM_F32 && dtype != SPMM_BF16) return fail(SPMM_ERR_INVALID_ARG, "unknown dtype");
+  if (item_nnz != 0 && (item_nnz < 64 || item_nnz > ((int64_t)1 << 20)))
+    return fail(SPMM_ERR_INVALID_ARG, "item_nnz=%lld out of range", (long long)item_nnz);
+  const double item_target = item_nnz ? (double)item_nnz : 2048.0;
   for (int t = 0; t < count; ++t) {
     if (!tiles[t]) return fail(SPMM_ERR_INVALID_ARG, "tile %d is null", t);
     if (tiles[t]->num_k != 1) return fail(SPMM_ERR_UNSUPPORTED, "tile %d has %d k-tiles; batches take single tiles", t,
@@ -845,8 +884,8 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
       if (A->plan.n_seg > 0)
         HIP_TRY(hipMemcpyAsync(segs.data(), A->plan.seg, sizeof(spmm::Seg) * segs.size(), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
-      // Rows per item: about 2K non-zeros of work (so that the waves of the GPU share
-      // few tiles at a time), a whole number of row groups, at most 64 rows.
+      // Rows per item: about item_target non-zeros of work (so that the waves of the
+      // GPU share few tiles at a time), a whole number of row groups, at most 64 rows.
       int64_t nz_short = 0, rows_short = 0;
       for (int64_t r = 0; r < A->rows; ++r) {
         const int64_t l = (int64_t)rp[r + 1] - rp[r];
@@ -858,7 +897,7 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
       const double avg = rows_short ? (double)nz_short / (double)rows_short : 1.0;
       const int unit_rows = d.kind == 0 ? 1 : 64 / d.G;
       int rpi = 64;
-      while (rpi > unit_rows && rpi * std::max(avg, 1.0) > 2048.0) rpi /= 2;
+      while (rpi > unit_rows && rpi * std::max(avg, 1.0) > item_target) rpi /= 2;
       for (int64_t r0 = 0; r0 < A->rows; r0 += rpi) {
         const int64_t r1 = std::min<int64_t>(A->rows, r0 + rpi);
         int64_t nz = 0;

@@ -11,6 +11,8 @@ namespace spmm {
 
 constexpr int kMaxK = 16;      // k-tiles per tile row in one fused launch
 constexpr int kBlock = 256;    // threads per workgroup for every kernel here
+// Grid cap for grid-stride kernels: a launch must stay below 2^32 threads.
+constexpr int64_t kMaxGridBlocks = (int64_t)1 << 20;
 
 enum class DT : int { F32 = 0, BF16 = 1 };
 
@@ -126,7 +128,8 @@ struct SddmmParams {
   int64_t c_begin, c_end;  // column range of this launch
   int accumulate;          // add to dA (later slices)
 };
-hipError_t launch_sddmm(const SddmmParams& P, Variant v, hipStream_t s);
+// G lanes per group, V columns per lane and load, U non-zeros per group.
+hipError_t launch_sddmm(const SddmmParams& P, int G, int V, int U, hipStream_t s);
 hipError_t launch_accumulate(void* C, int64_t ldc, const void* Pt, int64_t ldp, int64_t rows, int64_t N, DT dt,
                              int V, hipStream_t s);
 

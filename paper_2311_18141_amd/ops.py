@@ -12,7 +12,7 @@ from typing import List, Optional, Sequence, Tuple
 import torch
 
 from . import _lib
-from ._lib import SpmmCsr, SpmmTileOpts, SpmmTileStats, SpmmVariant, check, lib
+from ._lib import SpmmCsr, SpmmError, SpmmTileOpts, SpmmTileStats, SpmmVariant, check, lib
 
 _DTYPES = {torch.float32: _lib.SPMM_F32, torch.bfloat16: _lib.SPMM_BF16}
 
@@ -144,6 +144,11 @@ def spmm_tile_set_variant(tile: Tile, N: int, dtype=torch.float32, kind: Optiona
         return
     v = SpmmVariant(KERNELS[kind], lanes, vec)
     check(lib().spmm_tile_set_variant(tile.handle, N, _DTYPES[dtype], ctypes.byref(v)))
+
+
+def spmm_tile_set_sddmm_variant(tile: Tile, N: int, lanes: int = 0, nnz_per_group: int = 4) -> None:
+    """Shape of the backward's SDDMM kernel at width N (lanes = 0: library choice)."""
+    check(lib().spmm_tile_set_sddmm_variant(tile.handle, N, lanes, nnz_per_group if lanes else 0))
 
 
 def spmm_tile_autotune(tile: Tile, Bs: Sequence[torch.Tensor], C: torch.Tensor, tune_plan: bool = True,
@@ -311,12 +316,13 @@ class Batch:
             pass
 
 
-def spmm_batch_create(tiles: Sequence[Tile], Ns: Sequence[int], dtype=torch.float32,
+def spmm_batch_create(tiles: Sequence[Tile], Ns: Sequence[int], dtype=torch.float32, item_nnz: int = 0,
                       stream: Optional[torch.cuda.Stream] = None) -> Batch:
     arr = (ctypes.c_void_p * len(tiles))(*[t.handle for t in tiles])
     ns = (ctypes.c_int64 * len(tiles))(*[int(n) for n in Ns])
     h = ctypes.c_void_p()
-    check(lib().spmm_batch_create(len(tiles), arr, ns, _DTYPES[dtype], _stream_ptr(stream), ctypes.byref(h)))
+    check(lib().spmm_batch_create(len(tiles), arr, ns, _DTYPES[dtype], item_nnz, _stream_ptr(stream),
+                                  ctypes.byref(h)))
     return Batch(h.value, list(tiles), [int(n) for n in Ns], dtype)
 
 

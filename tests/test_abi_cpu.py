@@ -117,11 +117,12 @@ def test_batch_and_variant_argument_errors():
     n = ctypes.c_size_t()
     out = ctypes.c_void_p(7)
     ns = (ctypes.c_int64 * 1)(32)
-    assert L.spmm_batch_create(1, None, ns, 0, None, ctypes.byref(out)) == 1
-    assert L.spmm_batch_create(0, None, ns, 0, None, ctypes.byref(out)) == 1
+    assert L.spmm_batch_create(1, None, ns, 0, 0, None, ctypes.byref(out)) == 1
+    assert L.spmm_batch_create(0, None, ns, 0, 0, None, ctypes.byref(out)) == 1
     tiles = (ctypes.c_void_p * 1)(None)
-    assert L.spmm_batch_create(1, tiles, ns, 0, None, ctypes.byref(out)) == 1
-    assert L.spmm_batch_create(1, tiles, ns, 0, None, None) == 1
+    assert L.spmm_batch_create(1, tiles, ns, 0, 0, None, ctypes.byref(out)) == 1
+    assert L.spmm_batch_create(1, tiles, ns, 0, 32, None, ctypes.byref(out)) == 1
+    assert L.spmm_batch_create(1, tiles, ns, 0, 0, None, None) == 1
     assert L.spmm_batch_destroy(None) == 1
     assert L.spmm_batch_workspace_bytes(None, ctypes.byref(n)) == 1
     assert L.spmm_batch_get_variant(None, 0, None) == 1
@@ -129,3 +130,4 @@ def test_batch_and_variant_argument_errors():
     v = _lib.SpmmVariant(1, 8, 4)
     assert L.spmm_tile_set_variant(None, 32, 0, ctypes.byref(v)) == 1
     assert L.spmm_tile_autotune(None, 32, 0, None, None, None, 32, 0, None, None) == 1
+    assert L.spmm_tile_set_sddmm_variant(None, 32, 8, 4) == 1

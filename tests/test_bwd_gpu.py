@@ -172,3 +172,35 @@ def test_finite_differences_scaled():
         rows_j = rowid[A.colind == j]
         bound = 1e-5 * (float(np.dot(np.abs(dC[rows_j, n]), SC[rows_j, n])) + SB[t, n])
         assert abs(fd - dB[j, n]) <= bound + 1e-30, (j, n, fd, dB[j, n], bound)
+
+
+@pytest.mark.parametrize("N", [1, 12, 64, 136])
+@pytest.mark.parametrize("lanes,per_group", [(4, 1), (4, 4), (8, 8), (16, 2), (32, 4), (64, 8)])
+def test_sddmm_variants_integer_exact(lanes, per_group, N):
+    """Every SDDMM shape gives the exact dA on integer data, ragged nnz and columns included."""
+    G.note("sddmm_variant lanes=%d per_group=%d N=%d" % (lanes, per_group, N))
+    rng = _rng(300 + N)
+    M, K = 777, 901
+    L = rng.integers(0, 23, size=M)
+    L[5] = 900
+    A = synth.random_csr(M, K, L, rng, "int8")
+    B = synth.dense(K, N, rng, "int8")
+    dC = synth.dense(M, N, rng, "int8")
+    tile = G.make_tile([A], transpose=True)
+    ops.spmm_tile_set_sddmm_variant(tile, N, lanes, per_group)
+    dA, _ = ops.spmm_bwd(tile, G.dense_dev(dC), G.dense_dev(B), want_dB=False)
+    torch.cuda.synchronize()
+    rA, _ = oracle.sddmm(A.rowptr, A.colind, dC, B)
+    assert np.array_equal(dA.cpu().numpy().astype(np.float64), rA)
+
+
+def test_sddmm_variant_argument_errors():
+    G.note("sddmm_variant_argument_errors")
+    A = synth.random_csr(10, 10, np.full(10, 3), _rng(1))
+    tile = G.make_tile([A], transpose=True)
+    for lanes, per_group in [(3, 1), (128, 1), (8, 3), (8, 16), (4, 8)]:
+        with pytest.raises(ops.SpmmError):
+            ops.spmm_tile_set_sddmm_variant(tile, 32, lanes, per_group)
+    with pytest.raises(ops.SpmmError):
+        ops.spmm_tile_set_sddmm_variant(tile, 0, 8, 4)
+    ops.spmm_tile_set_sddmm_variant(tile, 32, 0)   # clearing an absent entry is fine
