@@ -90,6 +90,7 @@ typedef struct {
   int64_t nnz_per_k[16];
   int64_t has_transpose;
   int64_t long_rows_t, segments_t;   /* the same for the transposed structure */
+  int64_t long_row, segment;         /* split threshold and unit length of the current plan */
 } spmm_tile_stats;
 
 /*

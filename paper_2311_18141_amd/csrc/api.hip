@@ -139,16 +139,18 @@ int stream_rows_for(int64_t rows) {
 }
 
 // Kernel variant for width N when the handle has no entry: for N >= 64 the stream
-// kernel with the narrowest vector whose 64-lane window still covers N (measured
-// best on power-law and R-MAT tiles); below that a row-split group with the widest
-// aligned vector and the smallest power-of-two group covering N.
+// kernel over column windows of 64 FP32 / 128 BF16 columns; below that a row-split
+// group with the widest aligned vector and the smallest power-of-two group covering N.
 spmm::Variant pick_variant(int64_t N, DT dt, uintptr_t align_or, int64_t rows) {
   const int esize = dt == DT::F32 ? 4 : 2;
   int V = 16 / esize;
   while (V > 1 && ((N % V) != 0 || (align_or % (uintptr_t)(V * esize)) != 0)) V /= 2;
   if (N >= 64) {
-    int Vs = V;
-    while (Vs > 1 && 64 * (Vs / 2) >= N) Vs /= 2;
+    // column windows of about 256 bytes of each B row (64 FP32 or 128 BF16 columns):
+    // the grid walks the windows one after the other, so a narrower window keeps a
+    // smaller slice of B in the caches; measured faster than one window over all of
+    // N on the R-MAT and heavy-tailed matrices
+    const int Vs = (dt == DT::BF16 && N > 64 && V >= 2) ? 2 : 1;
     return spmm::Variant{64, Vs, true, stream_rows_for(rows)};
   }
   const int64_t need = (N + V - 1) / V;
@@ -390,6 +392,8 @@ spmm_status spmm_tile_create(int64_t rows, int num_k, const spmm_csr* tiles, con
   S.has_transpose = h->has_t ? 1 : 0;
   S.long_rows_t = h->planT.n_long;
   S.segments_t = h->planT.n_seg;
+  S.long_row = h->plan.long_row;
+  S.segment = h->plan.segment;
   *out = h;
   return SPMM_OK;
 }
@@ -635,6 +639,8 @@ spmm_status spmm_tile_autotune(spmm_tile_t A, int64_t N, spmm_dtype dtype, const
     plans[best_p] = Plan();
     A->stats.long_rows = A->plan.n_long;
     A->stats.segments = A->plan.n_seg;
+    A->stats.long_row = A->plan.long_row;
+    A->stats.segment = A->plan.segment;
   }
   for (auto& p : plans) free_plan(p);
   if (st != SPMM_OK) return st;
@@ -919,8 +925,8 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
         for (int w = 0; w < nw_unit; ++w) fix.push_back(spmm::BatchItem{t, (int32_t)r, w, 2});
     }
     if ((int64_t)items.size() >= ((int64_t)1 << 32)) return fail(SPMM_ERR_UNSUPPORTED, "work list too long");
-    // Order: tiles by descending total cost; inside a tile, split-row units first
-    // (longest first), then the row items in row order.  Keeping a tile's items
+    // Order: tiles by descending total cost; inside a tile, column window by column
+    // window, split-row units first (longest first), then the row items in row order.  Keeping a tile's items
     // together keeps its B resident in the caches while the waves work on it;
     // big tiles first leave the small ones to fill the end of the launch.
     std::vector<double> tile_cost(count, 0.0);
@@ -944,6 +950,8 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
       const int cx = cls(x.it), cy = cls(y.it);
       if (cx != cy) return cx < cy;
       if (x.it.tile != y.it.tile) return rank[x.it.tile] < rank[y.it.tile];
+      // one column window at a time: the waves then share that window's slice of B
+      if (x.it.window != y.it.window) return x.it.window < y.it.window;
       if ((x.it.type & 255) != (y.it.type & 255)) return (x.it.type & 255) > (y.it.type & 255);  // units first
       if ((x.it.type & 255) == 1) return x.cost > y.cost;
       return false;                                               // rows keep their order

@@ -131,3 +131,33 @@ def test_batch_and_variant_argument_errors():
     assert L.spmm_tile_set_variant(None, 32, 0, ctypes.byref(v)) == 1
     assert L.spmm_tile_autotune(None, 32, 0, None, None, None, 32, 0, None, None) == 1
     assert L.spmm_tile_set_sddmm_variant(None, 32, 8, 4) == 1
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C sizes and field offsets."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = {"spmm_csr": _lib.SpmmCsr, "spmm_tile_opts": _lib.SpmmTileOpts,
+               "spmm_tile_stats": _lib.SpmmTileStats, "spmm_variant": _lib.SpmmVariant}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "spmm.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (name, name))
+        for field, _ in cls._fields_:
+            lines.append('  printf("%s %s %%zu\\n", offsetof(%s, %s));' % (name, field, name, field))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            a, b, c = line.split()
+            got[(a, b)] = int(c)
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)
