@@ -39,7 +39,37 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 HANDLE_OPTS = {}
-AUTOTUNE = True
+AUTOTUNE = False
+
+# Kernel variant (kind, lanes, vec) and split-row plan (long_row, segment) of each
+# single-tile workload: what spmm_tile_autotune(tune_plan=1) picks for it on MI355X.
+# Pinned, so that a profiled run launches exactly the kernels the timed run launches
+# (no autotuner trials); --autotune re-tunes in set-up instead.
+PINNED = {
+    "rmat22_rowblock0_4x4_n128": {"variant": ("stream", 64, 1), "long_row": 128, "segment": 64},
+    "powerlaw2m_n128_fwdbwd": {"variant": ("stream", 64, 1), "long_row": 128, "segment": 64},
+    "rmat23_n256_bf16": {"variant": ("rowsplit", 16, 8), "long_row": 256, "segment": 128},
+    "rmat23_n256_f32": {"variant": ("stream", 64, 2), "long_row": 256, "segment": 128},
+}
+
+
+def _handle_opts(name):
+    """Split-row plan for a handle: the command line's, else the workload's pinned one."""
+    pin = PINNED.get(name, {})
+    out = {}
+    for key in ("long_row", "segment"):
+        out[key] = HANDLE_OPTS.get(key) or (0 if AUTOTUNE else pin.get(key, 0))
+    return out
+
+
+def _apply_pin(name, tile, N, dtype):
+    from paper_2311_18141_amd import ops
+    pin = PINNED.get(name)
+    if pin is None:
+        return None
+    kind, lanes, vec = pin["variant"]
+    ops.spmm_tile_set_variant(tile, N, dtype, kind, lanes, vec)
+    return {"kind": kind, "lanes": lanes, "vec": vec, "pinned": True}
 
 
 def _log(msg):
@@ -138,13 +168,16 @@ class TileRowForward(Workload):
         self.dev_tiles = [(torch.from_numpy(t.rowptr).to(dev), torch.from_numpy(t.colind).to(dev),
                            torch.from_numpy(t.values).to(dev), t.cols) for t in self.tiles]
         self.B = [torch.from_numpy(b).to(tdt).to(dev) for b in self.Bh]
-        self.tile = ops.spmm_tile_create(self.tiles[0].rows, self.dev_tiles, validate=True, **HANDLE_OPTS)
+        self.tile = ops.spmm_tile_create(self.tiles[0].rows, self.dev_tiles, validate=True,
+                                         **_handle_opts(self.name))
         self.C = torch.empty(self.tiles[0].rows, self.N, dtype=tdt, device=dev)
         if AUTOTUNE:
             t0 = time.time()
             chosen = ops.spmm_tile_autotune(self.tile, self.B, self.C, tune_plan=True)
             _log("%s: autotuned in %.1f s: %s" % (self.name, time.time() - t0, chosen))
             self.config["variant"] = chosen
+        else:
+            self.config["variant"] = _apply_pin(self.name, self.tile, self.N, tdt)
         self.ws = self.tile.workspace(self.N)
         nnz = sum(t.nnz for t in self.tiles)
         self.flops = 2.0 * nnz * self.N
@@ -198,7 +231,8 @@ class ForwardBackward(Workload):
         dev = "cuda:0"
         t = (torch.from_numpy(self.A.rowptr).to(dev), torch.from_numpy(self.A.colind).to(dev),
              torch.from_numpy(self.A.values).to(dev), self.A.cols)
-        self.tile = ops.spmm_tile_create(self.A.rows, [t], validate=True, transpose=True, **HANDLE_OPTS)
+        self.tile = ops.spmm_tile_create(self.A.rows, [t], validate=True, transpose=True,
+                                         **_handle_opts(self.name))
         self.B = torch.from_numpy(self.Bh).to(dev)
         self.dC = torch.from_numpy(self.dCh).to(dev)
         self.C = torch.empty(self.A.rows, self.N, device=dev)
@@ -207,6 +241,8 @@ class ForwardBackward(Workload):
             chosen = ops.spmm_tile_autotune(self.tile, [self.B], self.C, tune_plan=True)
             _log("%s: forward autotuned in %.1f s: %s" % (self.name, time.time() - t0, chosen))
             self.config["variant"] = chosen
+        else:
+            self.config["variant"] = _apply_pin(self.name, self.tile, self.N, torch.float32)
         self.dA = torch.empty(self.A.nnz, device=dev)
         self.dB = torch.empty(self.A.cols, self.N, device=dev)
         self.wsf = self.tile.workspace(self.N, "fwd")
@@ -274,14 +310,15 @@ class Batched(Workload):
             self.C.append(torch.empty(t.rows, N, device=dev))
             d = (torch.from_numpy(t.rowptr).to(dev), torch.from_numpy(t.colind).to(dev),
                  torch.from_numpy(t.values).to(dev), t.cols)
-            self.handles.append(ops.spmm_tile_create(t.rows, [d], validate=True, **HANDLE_OPTS))
+            self.handles.append(ops.spmm_tile_create(t.rows, [d], validate=True, **_handle_opts(self.name)))
         torch.cuda.synchronize()
         # Reference point: one spmm_fwd launch per tile with the library's default variant.
         self.loop_ms = self._time(self._loop, reps=5)
+        # The batch takes every tile's variant from the autotuner (part of its set-up; the
+        # autotuner times the single-tile kernels, not the batch kernels timed below).
         t0 = time.time()
-        if AUTOTUNE:
-            for h, B, C in zip(self.handles, self.B, self.C):
-                ops.spmm_tile_autotune(h, [B], C, tune_plan=False)
+        for h, B, C in zip(self.handles, self.B, self.C):
+            ops.spmm_tile_autotune(h, [B], C, tune_plan=False)
         _log("%s: autotuned %d tiles in %.1f s" % (self.name, self.count, time.time() - t0))
         self.batch = ops.spmm_batch_create(self.handles, self.Ns)
         self.ws = self.batch.workspace()
@@ -399,10 +436,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--long-row", type=int, default=0, help="split-row threshold (0 = library default)")
     ap.add_argument("--segment", type=int, default=0, help="non-zeros per split unit (0 = library default)")
-    ap.add_argument("--no-autotune", action="store_true", help="use the library's default variant and plan")
+    ap.add_argument("--autotune", action="store_true",
+                    help="re-tune variant and split plan in set-up instead of the pinned ones")
     args = ap.parse_args()
     global AUTOTUNE
-    AUTOTUNE = not args.no_autotune
+    AUTOTUNE = args.autotune
     HANDLE_OPTS.update(long_row=args.long_row, segment=args.segment)
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the stationary-C tile row is "

@@ -68,8 +68,10 @@ typedef struct {
 typedef struct {
   unsigned flags;
   int32_t long_row;        /* rows whose length over all k-tiles exceeds this are split across
-                              work units with a deterministic fix-up; 0 = library default */
-  int32_t segment;         /* non-zeros per split work unit; 0 = library default */
+                              work units with a deterministic fix-up; 0 = library default
+                              (128, doubled while below twice the mean row length) */
+  int32_t segment;         /* minimum non-zeros per split work unit (a row of length L gets units
+                              of max(segment, ceil(sqrt(L)))); 0 = library default (64) */
   int32_t bwd_slice;       /* spmm_bwd computes dA in column slices of this width, one launch
                               per slice, so a slice of B can stay cache-resident; 0 = one launch */
 } spmm_tile_opts;
@@ -190,23 +192,31 @@ spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* 
 
 /*
  * Batched launch: many independent single-tile products C_t = [C_t] + A_t B_t in
- * one persistent kernel (plus a small reset kernel before it and, when some tile
- * has split rows, a fix-up kernel after it).
+ * one launch per kernel class present in the batch (a class is one kernel shape:
+ * stream V, row-split G, or split-row unit V), plus, when some tile has split rows,
+ * a fix-up launch.  The batch form and its load balancing are additions of this
+ * library; they stand in, on one GPU, for the work claiming of Section 4 (a remote
+ * fetch-and-add per work item, Algorithm 3).
  *
  * spmm_batch_create builds, synchronously, the work list: items of up to 64 rows
- * of one tile and one column window, holding about `item_nnz` non-zeros (0: 2048;
+ * of one tile and one column window, holding about `item_nnz` non-zeros (0: 1024;
  * else 64..1048576), and the split-row units of each tile's plan, with each tile's
  * kernel variant taken from its handle's entry for (N_t, dtype) (set by
- * spmm_tile_autotune or spmm_tile_set_variant) or from a fixed rule, sorted by
- * descending cost.  Every tile must be a single-tile handle (num_k = 1) on the
- * current device, and must outlive the batch.  The batch allocates its own device
- * memory (work list, claim counter).  Errors: INVALID_ARG, UNSUPPORTED (num_k > 1),
- * ALLOC, HIP.
+ * spmm_tile_autotune or spmm_tile_set_variant) or from a fixed rule.  Items are
+ * ordered tile by tile (largest first) and column window by column window.
+ * `flags`: 0 = one wave per item, handed out by the hardware dispatcher in list
+ * order; SPMM_BATCH_PERSISTENT = resident workgroups (#CU x occupancy) whose waves
+ * claim 8 items at a time from a device counter per class (a reset kernel runs
+ * first).  Both give identical results.  Every tile must be a single-tile handle
+ * (num_k = 1) on the current device, and must outlive the batch.  The batch
+ * allocates its own device memory (work list; claim counters when persistent).
+ * Errors: INVALID_ARG, UNSUPPORTED (num_k > 1, work list too long), ALLOC, HIP.
  */
+#define SPMM_BATCH_PERSISTENT 1u
 typedef struct spmm_batch_s* spmm_batch_t;
 spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles /* host, count */,
                               const int64_t* N /* host, count */, spmm_dtype dtype, int64_t item_nnz,
-                              void* stream, spmm_batch_t* out /* host */);
+                              unsigned flags, void* stream, spmm_batch_t* out /* host */);
 spmm_status spmm_batch_destroy(spmm_batch_t batch);
 /* Workspace (device bytes) spmm_batched needs: FP32 partial rows of split rows. */
 spmm_status spmm_batch_workspace_bytes(spmm_batch_t batch, size_t* bytes /* host */);
@@ -219,9 +229,9 @@ spmm_status spmm_batch_get_variant(spmm_batch_t batch, int t, spmm_variant* out 
  * dtype, and their leading dimensions).  Every row of every B_t and C_t must start
  * on a 16-byte boundary (base pointer and ld * element size multiples of 16); the
  * library cannot check device-resident arguments.  Asynchronous; no host
- * synchronisation, no allocation: capturable in a HIP graph, whose replays reset
- * the claim counter by a kernel.  Calls on one batch must not overlap (they share
- * the claim counter and the workspace).  Errors: INVALID_ARG, WORKSPACE, HIP.
+ * synchronisation, no allocation: capturable in a HIP graph (a persistent batch
+ * resets its claim counters by a kernel on every replay).  Calls on one batch must
+ * not overlap (they share the claim counters and the workspace).  Errors: INVALID_ARG, WORKSPACE, HIP.
  */
 spmm_status spmm_batched(spmm_batch_t batch, const void* const* B, const int64_t* ldb, void* const* C,
                          const int64_t* ldc, int accumulate, void* workspace, size_t ws_bytes, void* stream);

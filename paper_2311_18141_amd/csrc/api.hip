@@ -36,8 +36,8 @@ spmm_status fail(spmm_status st, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(SPMM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int32_t kDefaultLongRow = 256;
-constexpr int32_t kDefaultSegment = 128;
+constexpr int32_t kDefaultLongRow = 128;
+constexpr int32_t kDefaultSegment = 64;
 
 // Device allocation owned by a handle.
 template <typename T>
@@ -306,6 +306,13 @@ spmm_status spmm_tile_create(int64_t rows, int num_k, const spmm_csr* tiles, con
     units_bound += t.nnz / segment + rows;
   }
   if (units_bound >= ((int64_t)1 << 31)) return fail(SPMM_ERR_UNSUPPORTED, "split-row plan would exceed 2^31 units");
+  if (!(opts && opts->long_row > 0) && rows > 0) {
+    // Default split threshold: 128, doubled while below twice the mean combined row
+    // length, so that tiles of near-uniform rows are not split into units.
+    int64_t nnz_total = 0;
+    for (int k = 0; k < num_k; ++k) nnz_total += tiles[k].nnz;
+    while ((int64_t)long_row * rows < 2 * nnz_total && long_row < (1 << 20)) long_row *= 2;
+  }
   if ((flags & SPMM_TILE_TRANSPOSE) && num_k != 1)
     return fail(SPMM_ERR_UNSUPPORTED, "SPMM_TILE_TRANSPOSE needs a single tile (num_k = 1)");
 
@@ -770,7 +777,8 @@ struct spmm_batch_s {
   int64_t n_items = 0;
   spmm::BatchItem* d_fix = nullptr;
   int64_t n_fix = 0;
-  unsigned* d_counter = nullptr;  // one claim counter per item class
+  unsigned* d_counter = nullptr;  // persistent mode: one claim counter per item class
+  bool persistent = false;
   size_t ws_bytes = 0;
   int64_t class_off[spmm::kBatchClasses] = {};
   int64_t class_cnt[spmm::kBatchClasses] = {};
@@ -826,7 +834,7 @@ void batch_variant(const spmm_tile_s* A, int64_t N, DT dt, spmm::BatchTileDev* b
 extern "C" {
 
 spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t* N, spmm_dtype dtype,
-                              int64_t item_nnz, void* stream, spmm_batch_t* out) {
+                              int64_t item_nnz, unsigned flags, void* stream, spmm_batch_t* out) {
   if (!out) return fail(SPMM_ERR_INVALID_ARG, "out is null");
   *out = nullptr;
   if (count < 1) return fail(SPMM_ERR_INVALID_ARG, "count=%d < 1", count);
@@ -834,7 +842,8 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
   if (dtype != SPMM_F32 && dtype != SPMM_BF16) return fail(SPMM_ERR_INVALID_ARG, "unknown dtype");
   if (item_nnz != 0 && (item_nnz < 64 || item_nnz > ((int64_t)1 << 20)))
     return fail(SPMM_ERR_INVALID_ARG, "item_nnz=%lld out of range", (long long)item_nnz);
-  const double item_target = item_nnz ? (double)item_nnz : 2048.0;
+  if (flags & ~(unsigned)SPMM_BATCH_PERSISTENT) return fail(SPMM_ERR_INVALID_ARG, "unknown batch flags 0x%x", flags);
+  const double item_target = item_nnz ? (double)item_nnz : 1024.0;
   for (int t = 0; t < count; ++t) {
     if (!tiles[t]) return fail(SPMM_ERR_INVALID_ARG, "tile %d is null", t);
     if (tiles[t]->num_k != 1) return fail(SPMM_ERR_UNSUPPORTED, "tile %d has %d k-tiles; batches take single tiles", t,
@@ -852,6 +861,7 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
   b->count = count;
   b->dt = dt;
   b->device = dev;
+  b->persistent = (flags & SPMM_BATCH_PERSISTENT) != 0;
   b->variants.resize(count);
   auto body = [&]() -> spmm_status {
     std::vector<spmm::BatchTileDev> bt(count);
@@ -966,24 +976,33 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
     b->n_fix = (int64_t)fix.size();
     b->ws_bytes = sizeof(float) * (size_t)part;
     if (dalloc(&b->d_tiles, count) != hipSuccess || dalloc(&b->d_items, b->n_items) != hipSuccess ||
-        dalloc(&b->d_fix, b->n_fix) != hipSuccess || dalloc(&b->d_counter, spmm::kBatchClasses) != hipSuccess)
+        dalloc(&b->d_fix, b->n_fix) != hipSuccess ||
+        (b->persistent && dalloc(&b->d_counter, spmm::kBatchClasses) != hipSuccess))
       return fail(SPMM_ERR_ALLOC, "device allocation of the batch failed");
     HIP_TRY(hipMemcpyAsync(b->d_tiles, bt.data(), sizeof(spmm::BatchTileDev) * bt.size(), hipMemcpyHostToDevice, s));
     if (b->n_items)
       HIP_TRY(hipMemcpyAsync(b->d_items, list.data(), sizeof(spmm::BatchItem) * list.size(), hipMemcpyHostToDevice, s));
     if (b->n_fix)
       HIP_TRY(hipMemcpyAsync(b->d_fix, fix.data(), sizeof(spmm::BatchItem) * fix.size(), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemsetAsync(b->d_counter, 0, sizeof(unsigned) * spmm::kBatchClasses, s));
+    if (b->persistent) HIP_TRY(hipMemsetAsync(b->d_counter, 0, sizeof(unsigned) * spmm::kBatchClasses, s));
     HIP_TRY(hipStreamSynchronize(s));
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    int occ[spmm::kBatchClasses];
-    spmm::batch_blocks_per_cu(dt, occ);
+    int occ[spmm::kBatchClasses] = {};
+    if (b->persistent) spmm::batch_blocks_per_cu(dt, occ);
     for (int c = 0; c < spmm::kBatchClasses; ++c) {
-      // a persistent grid of at most one wave per item: small classes launch small grids
-      const int64_t full = (int64_t)cus * std::max(1, occ[c]);
-      const int64_t need = (b->class_cnt[c] + 3) / 4;
-      b->class_grid[c] = (int)std::max<int64_t>(1, std::min(full, need));
+      const int64_t waves = (int64_t)(spmm::kBlock / 64);
+      if (b->persistent) {
+        // resident workgroups, at most one wave per claim chunk: small classes launch small grids
+        const int64_t full = (int64_t)cus * std::max(1, occ[c]);
+        const int64_t need = (b->class_cnt[c] + waves * spmm::kClaimChunk - 1) / (waves * spmm::kClaimChunk);
+        b->class_grid[c] = (int)std::max<int64_t>(1, std::min(full, need));
+      } else {
+        const int64_t need = (b->class_cnt[c] + waves - 1) / waves;  // one wave per item
+        if (need * spmm::kBlock >= ((int64_t)1 << 32))
+          return fail(SPMM_ERR_UNSUPPORTED, "work list too long for one launch per class");
+        b->class_grid[c] = (int)std::max<int64_t>(1, need);
+      }
     }
     return SPMM_OK;
   };
@@ -1041,7 +1060,7 @@ spmm_status spmm_batched(spmm_batch_t batch, const void* const* B, const int64_t
   P.partial = static_cast<float*>(workspace);
   P.counter = batch->d_counter;
   P.accumulate = accumulate ? 1 : 0;
-  HIP_TRY(spmm::launch_batch(P, batch->class_off, batch->class_cnt, batch->class_grid, batch->dt,
+  HIP_TRY(spmm::launch_batch(P, batch->class_off, batch->class_cnt, batch->class_grid, batch->dt, batch->persistent,
                              static_cast<hipStream_t>(stream)));
   return SPMM_OK;
 }

@@ -1,12 +1,20 @@
 // Batched local SpMM: many independent single-tile products C_t = A_t B_t in a
-// handful of persistent launches (one per kernel class present in the batch).  The host builds a work list of items (64 rows of one tile
-// and one column window, or one split-row unit), tile by tile (largest tiles
-// first), so that the waves share one tile's B in the caches at a time.
-// Each wave claims items of its class from that class's device counter (the
-// single-GPU form of claiming work with a fetch-and-add) and runs them.
+// handful of launches, one per kernel class present in the batch (so that every
+// class runs with its own register allocation).  The host builds a work list of
+// items (up to 64 rows of one tile and one column window, or one split-row unit),
+// tile by tile (largest tiles first) and window by window, so that the waves share
+// one slice of one tile's B in the caches at a time.
+//
+// Two ways to hand items to waves:
+//  * flat (default): one wave per item, in list order; the hardware dispatcher
+//    hands out workgroups as CUs free up, which is the dynamic load balancing.
+//  * persistent: #CU x occupancy resident workgroups; each wave claims kClaimChunk
+//    consecutive items with one fetch-and-add on the class's device counter (the
+//    single-GPU form of claiming work with a remote fetch-and-add) until the list
+//    is drained.
 // Items write disjoint output rows (split rows: disjoint partial rows) and every
 // row is summed in CSR order by one wave, so the result does not depend on which
-// wave claims which item; split rows are finished by a second, fix-up launch.
+// wave runs which item; split rows are finished by a second, fix-up launch.
 #include "elem.hpp"
 #include "fwd_common.hpp"
 #include "internal.hpp"
@@ -169,14 +177,19 @@ __device__ __forceinline__ void item_rowsplit(const BatchTileDev& bt, const Ops<
   t.ldb = op.ldb;
   const char* brow = reinterpret_cast<const char*>(op.B) + cl * (int64_t)sizeof(T);
   const uint32_t ldbb = (uint32_t)(op.ldb * (int64_t)sizeof(T));
+  // the item's row extents, loaded once: lane l holds rows r0 + l (nrows <= 64)
+  int32_t my_p0 = 0, my_p1 = 0;
+  if (lane < nrows && r0 + lane < bt.rows) {
+    my_p0 = bt.rowptr[r0 + lane];
+    my_p1 = bt.rowptr[r0 + lane + 1];
+  }
   for (int rr = 0; rr < nrows; rr += GPW) {
     const int64_t row = r0 + rr + lane / G;
-    int32_t p0 = 0, p1 = 0;
     const bool inrow = rr + lane / G < nrows && row < bt.rows;
-    if (inrow) {
-      p0 = bt.rowptr[row];
-      p1 = bt.rowptr[row + 1];
-    }
+    const int src = (rr + lane / G) & 63;
+    int32_t p0 = __builtin_amdgcn_ds_bpermute(src << 2, my_p0);
+    int32_t p1 = __builtin_amdgcn_ds_bpermute(src << 2, my_p1);
+    if (!inrow) p1 = p0;
     const bool split = p1 - p0 > bt.long_row;
     if (split) p1 = p0;
     float acc[V];
@@ -212,31 +225,42 @@ __device__ __forceinline__ void item_unit(const BatchParams& P, const BatchTileD
   if (active) store_f32v<V>(P.partial + bt.part_off + (int64_t)s * bt.ldp + c0, acc);
 }
 
-// One persistent kernel per item class, so that every class runs with its own
-// register allocation (and hence occupancy) instead of the largest one's.
 template <typename E, bool ACC, int CLS>
+__device__ __forceinline__ void run_item(const BatchParams& P, int64_t it, int32_t* s_pref, int32_t* s_beg) {
+  const BatchItem item = P.items[it];
+  const BatchTileDev& bt = P.tiles[item.tile];
+  const Ops<E> op = item_ops<E>(P, item.tile);
+  const int nrows = item.type >> 8;
+  if constexpr (CLS < kClassRowsplit) {
+    item_stream<1 << CLS, E, ACC>(bt, op, item.a, nrows, item.window, s_pref, s_beg);
+  } else if constexpr (CLS < kClassUnit) {
+    item_rowsplit<8 << (CLS - kClassRowsplit), 4, E, ACC>(bt, op, item.a, nrows, item.window);
+  } else {
+    item_unit<1 << (CLS - kClassUnit), E>(P, bt, op, item.a, item.window);
+  }
+}
+
+// One kernel per item class and hand-out mode.
+template <typename E, bool ACC, int CLS, bool PERSIST>
 __global__ void __launch_bounds__(kBlock) batch_class(BatchParams P) {
   __shared__ int32_t s_mem[(kBlock / 64) * 129];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   int32_t* s_pref = s_mem + w * 129;
   int32_t* s_beg = s_pref + 65;
-  for (;;) {
-    unsigned claimed = 0;
-    if (lane == 0) claimed = atomicAdd(P.counter, 1u);
-    const unsigned it = (unsigned)__builtin_amdgcn_readlane((int)claimed, 0);
-    if ((int64_t)it >= P.n_items) break;  // every wave leaves once the list is drained
-    const BatchItem item = P.items[it];
-    const BatchTileDev& bt = P.tiles[item.tile];
-    const Ops<E> op = item_ops<E>(P, item.tile);
-    const int nrows = item.type >> 8;
-    if constexpr (CLS < kClassRowsplit) {
-      item_stream<1 << CLS, E, ACC>(bt, op, item.a, nrows, item.window, s_pref, s_beg);
-    } else if constexpr (CLS < kClassUnit) {
-      item_rowsplit<8 << (CLS - kClassRowsplit), 4, E, ACC>(bt, op, item.a, nrows, item.window);
-    } else {
-      item_unit<1 << (CLS - kClassUnit), E>(P, bt, op, item.a, item.window);
+  if constexpr (PERSIST) {
+    for (;;) {
+      unsigned claimed = 0;
+      if (lane == 0) claimed = atomicAdd(P.counter, (unsigned)kClaimChunk);
+      const int64_t base = (unsigned)__builtin_amdgcn_readlane((int)claimed, 0);
+      if (base >= P.n_items) break;  // every wave leaves once the list is drained
+      const int64_t end = base + kClaimChunk < P.n_items ? base + kClaimChunk : P.n_items;
+      for (int64_t it = base; it < end; ++it) run_item<E, ACC, CLS>(P, it, s_pref, s_beg);
     }
+  } else {
+    (void)lane;
+    const int64_t it = (int64_t)blockIdx.x * (kBlock / 64) + w;
+    if (it < P.n_items) run_item<E, ACC, CLS>(P, it, s_pref, s_beg);
   }
 }
 
@@ -281,16 +305,22 @@ __global__ void batch_reset(unsigned* counter, int n) {
 }
 
 template <typename E, bool ACC, int CLS>
-hipError_t launch_class(const BatchParams& P, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((batch_class<E, ACC, CLS>), dim3((unsigned)grid), dim3(kBlock), 0, s, P);
+hipError_t launch_class(const BatchParams& P, int grid, bool persistent, hipStream_t s) {
+  if (persistent)
+    hipLaunchKernelGGL((batch_class<E, ACC, CLS, true>), dim3((unsigned)grid), dim3(kBlock), 0, s, P);
+  else
+    hipLaunchKernelGGL((batch_class<E, ACC, CLS, false>), dim3((unsigned)grid), dim3(kBlock), 0, s, P);
   return hipGetLastError();
 }
 
 template <typename E, bool ACC>
 hipError_t launch_batch_t(const BatchParams& P0, const int64_t* off, const int64_t* cnt, const int* grid,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(batch_reset, dim3(1), dim3(64), 0, s, P0.counter, kBatchClasses);
-  hipError_t e = hipGetLastError();
+                          bool persistent, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (persistent) {
+    hipLaunchKernelGGL(batch_reset, dim3(1), dim3(64), 0, s, P0.counter, kBatchClasses);
+    e = hipGetLastError();
+  }
   // units first (their partials feed the fix-up), then the row classes
   static constexpr int order[kBatchClasses] = {7, 8, 9, 0, 1, 2, 3, 4, 5, 6};
   for (int oi = 0; oi < kBatchClasses && e == hipSuccess; ++oi) {
@@ -299,18 +329,18 @@ hipError_t launch_batch_t(const BatchParams& P0, const int64_t* off, const int64
     BatchParams P = P0;
     P.items = P0.items + off[c];
     P.n_items = cnt[c];
-    P.counter = P0.counter + c;
+    P.counter = P0.counter ? P0.counter + c : nullptr;
     switch (c) {
-      case 0: e = launch_class<E, ACC, 0>(P, grid[c], s); break;
-      case 1: e = launch_class<E, ACC, 1>(P, grid[c], s); break;
-      case 2: e = launch_class<E, ACC, 2>(P, grid[c], s); break;
-      case 3: e = launch_class<E, ACC, 3>(P, grid[c], s); break;
-      case 4: e = launch_class<E, ACC, 4>(P, grid[c], s); break;
-      case 5: e = launch_class<E, ACC, 5>(P, grid[c], s); break;
-      case 6: e = launch_class<E, ACC, 6>(P, grid[c], s); break;
-      case 7: e = launch_class<E, ACC, 7>(P, grid[c], s); break;
-      case 8: e = launch_class<E, ACC, 8>(P, grid[c], s); break;
-      default: e = launch_class<E, ACC, 9>(P, grid[c], s); break;
+      case 0: e = launch_class<E, ACC, 0>(P, grid[c], persistent, s); break;
+      case 1: e = launch_class<E, ACC, 1>(P, grid[c], persistent, s); break;
+      case 2: e = launch_class<E, ACC, 2>(P, grid[c], persistent, s); break;
+      case 3: e = launch_class<E, ACC, 3>(P, grid[c], persistent, s); break;
+      case 4: e = launch_class<E, ACC, 4>(P, grid[c], persistent, s); break;
+      case 5: e = launch_class<E, ACC, 5>(P, grid[c], persistent, s); break;
+      case 6: e = launch_class<E, ACC, 6>(P, grid[c], persistent, s); break;
+      case 7: e = launch_class<E, ACC, 7>(P, grid[c], persistent, s); break;
+      case 8: e = launch_class<E, ACC, 8>(P, grid[c], persistent, s); break;
+      default: e = launch_class<E, ACC, 9>(P, grid[c], persistent, s); break;
     }
   }
   if (e == hipSuccess && P0.n_fix > 0) {
@@ -323,7 +353,7 @@ hipError_t launch_batch_t(const BatchParams& P0, const int64_t* off, const int64
 template <typename E, int CLS>
 int occupancy_of() {
   int n = 0;
-  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_class<E, false, CLS>, kBlock, 0);
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_class<E, false, CLS, true>, kBlock, 0);
   return (e == hipSuccess && n > 0) ? n : 2;
 }
 
@@ -344,12 +374,12 @@ void occupancy_all(int* out) {
 }  // namespace
 
 hipError_t launch_batch(const BatchParams& P, const int64_t* off, const int64_t* cnt, const int* grid, DT dt,
-                        hipStream_t s) {
+                        bool persistent, hipStream_t s) {
   if (dt == DT::F32)
-    return P.accumulate ? launch_batch_t<F32E, true>(P, off, cnt, grid, s)
-                        : launch_batch_t<F32E, false>(P, off, cnt, grid, s);
-  return P.accumulate ? launch_batch_t<BF16E, true>(P, off, cnt, grid, s)
-                      : launch_batch_t<BF16E, false>(P, off, cnt, grid, s);
+    return P.accumulate ? launch_batch_t<F32E, true>(P, off, cnt, grid, persistent, s)
+                        : launch_batch_t<F32E, false>(P, off, cnt, grid, persistent, s);
+  return P.accumulate ? launch_batch_t<BF16E, true>(P, off, cnt, grid, persistent, s)
+                      : launch_batch_t<BF16E, false>(P, off, cnt, grid, persistent, s);
 }
 
 void batch_blocks_per_cu(DT dt, int* out) {

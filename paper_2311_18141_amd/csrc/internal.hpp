@@ -103,16 +103,22 @@ struct BatchParams {
   void* const* C;          // device array: C[t]
   const int64_t* ldc;      // device array
   float* partial;
-  unsigned* counter;
+  unsigned* counter;       // persistent mode: one claim counter per item class
   int accumulate;
 };
+// Items a persistent wave claims with one fetch-and-add.
+constexpr int kClaimChunk = 8;
 // Item classes: stream V = 1, 2, 4 (0..2); row-split G = 8, 16, 32, 64 with V = 4 (3..6);
 // split-row units with V = 1, 2, 4 (7..9).
 constexpr int kClassRowsplit = 3;
 constexpr int kClassUnit = 7;
 constexpr int kBatchClasses = 10;
+// One launch per item class present (off/cnt: the class's slice of the item list;
+// grid: its workgroups), then the fix-up.  persistent = false: one wave per item;
+// true: `grid` resident workgroups claim kClaimChunk items at a time from the
+// class's counter (reset by a kernel first, so graph replays start clean).
 hipError_t launch_batch(const BatchParams& P, const int64_t* off, const int64_t* cnt, const int* grid, DT dt,
-                        hipStream_t s);
+                        bool persistent, hipStream_t s);
 void batch_blocks_per_cu(DT dt, int* out);
 
 struct SddmmParams {

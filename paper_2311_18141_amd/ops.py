@@ -317,18 +317,19 @@ class Batch:
 
 
 def spmm_batch_create(tiles: Sequence[Tile], Ns: Sequence[int], dtype=torch.float32, item_nnz: int = 0,
-                      stream: Optional[torch.cuda.Stream] = None) -> Batch:
+                      persistent: bool = False, stream: Optional[torch.cuda.Stream] = None) -> Batch:
+    """Work list for spmm_batched over single-tile handles (persistent: claim-counter hand-out)."""
     arr = (ctypes.c_void_p * len(tiles))(*[t.handle for t in tiles])
     ns = (ctypes.c_int64 * len(tiles))(*[int(n) for n in Ns])
     h = ctypes.c_void_p()
-    check(lib().spmm_batch_create(len(tiles), arr, ns, _DTYPES[dtype], item_nnz, _stream_ptr(stream),
-                                  ctypes.byref(h)))
+    check(lib().spmm_batch_create(len(tiles), arr, ns, _DTYPES[dtype], item_nnz, 1 if persistent else 0,
+                                  _stream_ptr(stream), ctypes.byref(h)))
     return Batch(h.value, list(tiles), [int(n) for n in Ns], dtype)
 
 
 def spmm_batched(batch: Batch, Bs: Sequence[torch.Tensor], Cs: Sequence[torch.Tensor], accumulate: bool = False,
                  workspace: Optional[torch.Tensor] = None, stream: Optional[torch.cuda.Stream] = None) -> None:
-    """C_t = [C_t] + A_t B_t for every tile of the batch, in one persistent launch."""
+    """C_t = [C_t] + A_t B_t for every tile of the batch (one launch per kernel class, then the fix-up)."""
     if len(Bs) != len(batch.tiles) or len(Cs) != len(batch.tiles):
         raise ValueError("one B and one C per tile")
     b, lb, c, lc = batch.operand_arrays(Bs, Cs)

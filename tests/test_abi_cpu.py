@@ -117,12 +117,13 @@ def test_batch_and_variant_argument_errors():
     n = ctypes.c_size_t()
     out = ctypes.c_void_p(7)
     ns = (ctypes.c_int64 * 1)(32)
-    assert L.spmm_batch_create(1, None, ns, 0, 0, None, ctypes.byref(out)) == 1
-    assert L.spmm_batch_create(0, None, ns, 0, 0, None, ctypes.byref(out)) == 1
+    assert L.spmm_batch_create(1, None, ns, 0, 0, 0, None, ctypes.byref(out)) == 1
+    assert L.spmm_batch_create(0, None, ns, 0, 0, 0, None, ctypes.byref(out)) == 1
     tiles = (ctypes.c_void_p * 1)(None)
-    assert L.spmm_batch_create(1, tiles, ns, 0, 0, None, ctypes.byref(out)) == 1
-    assert L.spmm_batch_create(1, tiles, ns, 0, 32, None, ctypes.byref(out)) == 1
-    assert L.spmm_batch_create(1, tiles, ns, 0, 0, None, None) == 1
+    assert L.spmm_batch_create(1, tiles, ns, 0, 0, 0, None, ctypes.byref(out)) == 1
+    assert L.spmm_batch_create(1, tiles, ns, 0, 0, 2, None, ctypes.byref(out)) == 1
+    assert L.spmm_batch_create(1, tiles, ns, 0, 32, 0, None, ctypes.byref(out)) == 1
+    assert L.spmm_batch_create(1, tiles, ns, 0, 0, 0, None, None) == 1
     assert L.spmm_batch_destroy(None) == 1
     assert L.spmm_batch_workspace_bytes(None, ctypes.byref(n)) == 1
     assert L.spmm_batch_get_variant(None, 0, None) == 1
