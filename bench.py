@@ -15,8 +15,9 @@ times dense B_k of 1,048,576 x 128 FP32, accumulated over its 4 k-tiles into a
     rmat23_n256_bf16        R-MAT scale 23, edge factor 32, N = 256, BF16 B and C
     rmat23_n256_f32         the same with FP32 B and C
     uneven512_batched       512 uneven tiles (rows 1,024..65,536, 4..256 non-zeros per row,
-                            N_t in {32..256}) in one persistent launch, per-tile autotuned
-                            variants; the per-tile launch loop is reported beside it
+                            N_t in {32..256}) in one batched launch, per-tile autotuned
+                            variants; the per-tile launch loop and the persistent (claim
+                            counter) hand-out are reported beside it
 
 value = 2 * nnz * N * passes / step time (GFLOP/s).  The roofline object prices
 the step's kernels with their algorithmic bytes (CSR arrays + dense inputs read
@@ -284,13 +285,15 @@ class ForwardBackward(Workload):
 
 
 class Batched(Workload):
-    """Many independent uneven tiles in one persistent launch, per-tile variants from the autotuner."""
+    """Many independent uneven tiles in one batched launch (flat hand-out), per-tile variants from the
+    autotuner; the per-tile launch loop (default and autotuned variants) and the persistent hand-out are
+    timed beside it."""
 
     def __init__(self, name, count, config):
         self.name = name
         self.count = count
         self.config = config
-        self.kernel = "spmm_batched (batch_main + batch_fixup)"
+        self.kernel = "spmm_batched (batch_class per kernel class + batch_fixup)"
 
     def setup(self):
         import torch
@@ -322,6 +325,12 @@ class Batched(Workload):
         _log("%s: autotuned %d tiles in %.1f s" % (self.name, self.count, time.time() - t0))
         self.batch = ops.spmm_batch_create(self.handles, self.Ns)
         self.ws = self.batch.workspace()
+        # The persistent hand-out (claim counters), timed for comparison.
+        pb = ops.spmm_batch_create(self.handles, self.Ns, persistent=True)
+        pws = pb.workspace()
+        self.persistent_ms = self._time(lambda: ops.spmm_batched(pb, self.B, self.C, workspace=pws), reps=5)
+        del pb, pws
+        self.tuned_loop_ms = self._time(self._loop, reps=5)
         kinds = {}
         for t in range(self.count):
             v = self.batch.variant(t)
@@ -334,7 +343,11 @@ class Batched(Workload):
         self.config = dict(self.config, tiles=self.count, nnz=nnz, rows=sum(t.rows for t in self.tiles),
                            variants=kinds,
                            per_tile_loop={"ms": round(self.loop_ms, 4),
-                                          "gflops": round(self.flops / (self.loop_ms * 1e-3) / 1e9, 1)})
+                                          "gflops": round(self.flops / (self.loop_ms * 1e-3) / 1e9, 1)},
+                           per_tile_loop_autotuned={"ms": round(self.tuned_loop_ms, 4),
+                                                    "gflops": round(self.flops / (self.tuned_loop_ms * 1e-3) / 1e9, 1)},
+                           persistent={"ms": round(self.persistent_ms, 4),
+                                       "gflops": round(self.flops / (self.persistent_ms * 1e-3) / 1e9, 1)})
 
     def _loop(self):
         from paper_2311_18141_amd import ops

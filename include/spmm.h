@@ -199,7 +199,7 @@ spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* 
  * fetch-and-add per work item, Algorithm 3).
  *
  * spmm_batch_create builds, synchronously, the work list: items of up to 64 rows
- * of one tile and one column window, holding about `item_nnz` non-zeros (0: 1024;
+ * of one tile and one column window, holding about `item_nnz` non-zeros (0: 256;
  * else 64..1048576), and the split-row units of each tile's plan, with each tile's
  * kernel variant taken from its handle's entry for (N_t, dtype) (set by
  * spmm_tile_autotune or spmm_tile_set_variant) or from a fixed rule.  Items are

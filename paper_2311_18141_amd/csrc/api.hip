@@ -843,7 +843,7 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
   if (item_nnz != 0 && (item_nnz < 64 || item_nnz > ((int64_t)1 << 20)))
     return fail(SPMM_ERR_INVALID_ARG, "item_nnz=%lld out of range", (long long)item_nnz);
   if (flags & ~(unsigned)SPMM_BATCH_PERSISTENT) return fail(SPMM_ERR_INVALID_ARG, "unknown batch flags 0x%x", flags);
-  const double item_target = item_nnz ? (double)item_nnz : 1024.0;
+  const double item_target = item_nnz ? (double)item_nnz : 256.0;
   for (int t = 0; t < count; ++t) {
     if (!tiles[t]) return fail(SPMM_ERR_INVALID_ARG, "tile %d is null", t);
     if (tiles[t]->num_k != 1) return fail(SPMM_ERR_UNSUPPORTED, "tile %d has %d k-tiles; batches take single tiles", t,

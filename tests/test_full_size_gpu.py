@@ -1,6 +1,9 @@
-"""Parity at the full workload sizes, in the launch configuration bench.py times (default
-handle options), on sampled outputs the oracle computes one by one, plus properties that
-hold at any size (bit-exact transposed structure, finite differences)."""
+"""Parity at the full workload sizes, in the launch configuration bench.py times (its pinned
+kernel variant and split plan per workload), on sampled outputs the oracle computes one by
+one, plus properties that hold at any size (bit-exact transposed structure, finite
+differences)."""
+import os
+import sys
 import time
 
 import numpy as np
@@ -14,7 +17,22 @@ from paper_2311_18141_amd import ops
 
 import gpu_util as G
 
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import bench  # noqa: E402  (the pinned launch configuration of each workload)
+
 pytestmark = pytest.mark.gpu
+
+
+def _bench_tile(workload, tiles, N, dtypes=(torch.float32,), transpose=False, dev_tiles=None):
+    """A handle built and pinned the way bench.py builds it for `workload`."""
+    pin = bench.PINNED[workload]
+    dt = dev_tiles or [G.to_dev(t) for t in tiles]
+    tile = ops.spmm_tile_create(tiles[0].rows, dt, validate=True, transpose=transpose,
+                                long_row=pin["long_row"], segment=pin["segment"])
+    for d in dtypes:
+        kind, lanes, vec = pin["variant"]
+        ops.spmm_tile_set_variant(tile, N, d, kind, lanes, vec)
+    return tile
 
 
 def _rng(s):
@@ -48,7 +66,7 @@ def test_rmat22_rowblock0_kloop_n128():
     G.note("full rmat22 row block 0 (generated in %.0f s)" % (time.time() - t0))
     rs = synth.streams(2)
     Bs = [synth.dense(t.cols, 128, rs[2]) for t in g.tiles]
-    tile = G.make_tile(g.tiles)
+    tile = _bench_tile("rmat22_rowblock0_4x4_n128", g.tiles, 128)
     st = tile.stats()
     assert st["nnz_total"] == sum(t.nnz for t in g.tiles)
     Bd = [G.dense_dev(b) for b in Bs]
@@ -74,7 +92,7 @@ def powerlaw2m():
     dC = synth.dense(A.rows, 128, rs[3], "normal")
     G.note("full powerlaw 2M generated in %.0f s" % (time.time() - t0))
     rp, ci, va, _ = G.to_dev(A)
-    tile = ops.spmm_tile_create(A.rows, [(rp, ci, va, A.cols)], validate=True, transpose=True)
+    tile = _bench_tile("powerlaw2m_n128_fwdbwd", [A], 128, transpose=True, dev_tiles=[(rp, ci, va, A.cols)])
     return A, B, dC, tile, va
 
 
@@ -180,7 +198,10 @@ def test_rmat23_n256_bf16_and_f32():
     A = synth.rmat_csr(23, 32, seed=5)
     B = synth.dense(A.cols, 256, synth.streams(5)[2])
     G.note("full rmat23 N=256 generated in %.0f s (nnz %d)" % (time.time() - t0, A.nnz))
-    tile = G.make_tile([A])
+    tile = _bench_tile("rmat23_n256_f32", [A], 256)
+    kind, lanes, vec = bench.PINNED["rmat23_n256_bf16"]["variant"]
+    ops.spmm_tile_set_variant(tile, 256, torch.bfloat16, kind, lanes, vec)
+    assert bench.PINNED["rmat23_n256_bf16"]["long_row"] == bench.PINNED["rmat23_n256_f32"]["long_row"]
     lens = A.row_lengths()
     rows = _sample_rows(lens, _rng(51), n=1000)
     ridx = None
@@ -205,8 +226,8 @@ def test_rmat23_n256_bf16_and_f32():
 
 
 def test_uneven512_batched_sampled():
-    """512 uneven tiles in one persistent launch with autotuned per-tile variants; sampled rows of every
-    tile against the oracle."""
+    """512 uneven tiles in one batched launch with autotuned per-tile variants; sampled rows of every
+    tile against the oracle; the persistent hand-out gives the same bits."""
     t0 = time.time()
     tiles, Ns = synth.uneven_tiles(512, seed=4)
     G.note("full uneven512 generated in %.0f s (nnz %d)" % (time.time() - t0, sum(t.nnz for t in tiles)))
@@ -232,3 +253,11 @@ def test_uneven512_batched_sampled():
         st = G.assert_fp32_close(got, ref, S, A.row_lengths()[rows], what="tile %d %s" % (t, batch.variant(t)))
         worst = max(worst, st["max_rel_to_scale"])
     print("uneven512 batched: worst |err|/S over sampled rows %.3g" % worst)
+    flat = [c.clone() for c in Cs]
+    pb = ops.spmm_batch_create(handles, Ns, persistent=True)
+    for c in Cs:
+        c.fill_(float("nan"))
+    ops.spmm_batched(pb, Bs, Cs)
+    torch.cuda.synchronize()
+    for t, (c, f) in enumerate(zip(Cs, flat)):
+        assert torch.equal(c, f), t
