@@ -109,6 +109,17 @@ def stored_traffic(workload: str):
         return None
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def _threads():
     n = len(os.sched_getaffinity(0))
     env = os.environ.get("OMP_NUM_THREADS")
@@ -490,8 +501,9 @@ def main():
     achieved = wl.alg_bytes / (avg_kernel_ms * 1e-3) / 1e9
     _log("timed %d steps: %.4f ms/step (per-step events mean %.4f, min %.4f, max %.4f)"
          % (args.steps, ms_step, avg_kernel_ms, min(per), max(per)))
+    traffic = stored_traffic(args.workload)
     out = {
-        "metric": "SpMM GFLOP/s (2*nnz*N) and % HBM roofline",
+        "metric": "SpMM GFLOP/s (2*nnz*N) and % HBM roofline, fwd+bwd, BF16/batched vs FP32",
         "value": round(value, 2),
         "unit": "GFLOP/s",
         "n_gpus": 1,
@@ -506,15 +518,19 @@ def main():
         "config": wl.config,
         "roofline": {"bound": "hbm", "kernel": wl.kernel, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": stored_traffic(args.workload), "alg_bytes_per_step": wl.alg_bytes,
-                     "avg_kernel_ms": round(avg_kernel_ms, 5)},
+                     "traffic": traffic, "alg_bytes_per_step": wl.alg_bytes,
+                     "avg_kernel_ms": round(avg_kernel_ms, 5),
+                     # counter-measured HBM bytes per step over the same time, against the same peak
+                     "traffic_frac": (round(traffic / (avg_kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                      if traffic else None)},
     }
     if not args.no_cpu_baseline:
         threads = _threads()
         os.environ["OMP_NUM_THREADS"] = str(threads)
         flops, secs, desc = wl.cpu_sample()
         out["cpu_baseline"] = {"value": round(flops / secs / 1e9, 3), "unit": "GFLOP/s", "cores": threads,
-                               "kind": "oracle", "sample": desc, "seconds": round(secs, 2)}
+                               "kind": "oracle", "sample": desc, "seconds": round(secs, 2),
+                               "cpu_model": _cpu_model()}
     print(json.dumps(out), flush=True)
 
 
