@@ -174,7 +174,9 @@ spmm_status spmm_fwd(spmm_tile_t A, int k_offset, const void* const* B, const in
                      spmm_dtype b_dtype, void* C, int64_t ldc, spmm_dtype c_dtype, int64_t N,
                      int accumulate, void* workspace, size_t ws_bytes, void* stream);
 
-/* Workspace (device bytes) spmm_bwd needs for this handle at width N. */
+/* Workspace (device bytes) spmm_bwd needs for this handle at width N when dB is
+   wanted: FP32 partial rows of the transposed plan's split rows plus 4 bytes per
+   non-zero (A's values gathered into the transposed order on every call). */
 spmm_status spmm_bwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes /* host */);
 
 /*

@@ -235,7 +235,6 @@ hipError_t launch_forward(const spmm_tile_s* A, const Plan& plan, int k_offset, 
     P.t[k].rowptr = A->t[k].rowptr;
     P.t[k].colind = A->t[k].colind;
     P.t[k].values = A->t[k].values;
-    P.t[k].perm = nullptr;
     P.t[k].B = B[k];
     P.t[k].ldb = ldb[k];
   }
@@ -440,10 +439,19 @@ spmm_status spmm_fwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes) {
   return SPMM_OK;
 }
 
+// Backward workspace: FP32 partial rows of the transposed plan's split rows, then
+// (16-byte aligned) A's values gathered into the transposed order.
+static size_t bwd_partial_bytes(const spmm_tile_s* A, int64_t N) {
+  return (sizeof(float) * partial_ld(N) * (size_t)A->planT.n_seg + 15) & ~(size_t)15;
+}
+static size_t bwd_workspace(const spmm_tile_s* A, int64_t N) {
+  return bwd_partial_bytes(A, N) + sizeof(float) * (size_t)A->t[0].nnz;
+}
+
 spmm_status spmm_bwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes) {
   if (!A || !bytes) return fail(SPMM_ERR_INVALID_ARG, "null argument");
   if (N < 1) return fail(SPMM_ERR_INVALID_ARG, "N=%lld < 1", (long long)N);
-  *bytes = sizeof(float) * partial_ld(N) * (size_t)A->planT.n_seg;
+  *bytes = bwd_workspace(A, N);
   return SPMM_OK;
 }
 
@@ -689,7 +697,7 @@ spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* 
   if (dB && lddb < N) return fail(SPMM_ERR_INVALID_ARG, "lddb < N");
   if (lddc * 4 >= ((int64_t)1 << 32)) return fail(SPMM_ERR_UNSUPPORTED, "lddc * 4 >= 2^32");
   const spmm_csr& t = A->t[0];
-  const size_t need = dB ? sizeof(float) * partial_ld(N) * (size_t)A->planT.n_seg : 0;
+  const size_t need = dB ? bwd_workspace(A, N) : 0;
   if (need > 0) {
     if (!workspace || ws_bytes < need)
       return fail(SPMM_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
@@ -738,11 +746,12 @@ spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* 
     }
   }
   if (dB && t.cols > 0) {
+    float* valuesT = reinterpret_cast<float*>(static_cast<char*>(workspace) + bwd_partial_bytes(A, N));
+    HIP_TRY(spmm::launch_gather_values(A->perm, t.values, valuesT, t.nnz, s));
     spmm::FwdParams P{};
     P.t[0].rowptr = A->rowptrT;
     P.t[0].colind = A->colindT;
-    P.t[0].values = t.values;
-    P.t[0].perm = A->perm;
+    P.t[0].values = valuesT;
     P.t[0].B = dC;
     P.t[0].ldb = lddc;
     P.num_k = 1;

@@ -172,7 +172,6 @@ __device__ __forceinline__ void item_rowsplit(const BatchTileDev& bt, const Ops<
   t.rowptr = bt.rowptr;
   t.colind = bt.colind;
   t.values = bt.values;
-  t.perm = nullptr;
   t.B = op.B;
   t.ldb = op.ldb;
   const char* brow = reinterpret_cast<const char*>(op.B) + cl * (int64_t)sizeof(T);
@@ -213,7 +212,6 @@ __device__ __forceinline__ void item_unit(const BatchParams& P, const BatchTileD
   t.rowptr = bt.rowptr;
   t.colind = bt.colind;
   t.values = bt.values;
-  t.perm = nullptr;
   t.B = op.B;
   t.ldb = op.ldb;
   const Seg d = bt.seg[s];

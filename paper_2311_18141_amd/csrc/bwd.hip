@@ -113,6 +113,15 @@ hipError_t launch_sddmm_v(const SddmmParams& P, int G, int U, hipStream_t s) {
   }
 }
 
+// out[q] = values[perm[q]]: A's values in the transposed structure's order, so that the
+// dB pass reads them coalesced (every load here is independent, so the random reads
+// of `values` overlap freely).
+__global__ void __launch_bounds__(kBlock) gather_values_kernel(const int32_t* perm, const float* values, float* out,
+                                                                int64_t nnz) {
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nnz; q += (int64_t)gridDim.x * kBlock)
+    out[q] = values[__builtin_nontemporal_load(perm + q)];
+}
+
 // C[r, c] += P[r, c] over a rows x N block; one thread per V consecutive elements.
 template <int V, typename E>
 __global__ void __launch_bounds__(kBlock) accumulate_kernel(typename E::T* C, int64_t ldc, const typename E::T* Pt,
@@ -156,6 +165,13 @@ hipError_t launch_accumulate(void* C, int64_t ldc, const void* Pt, int64_t ldp, 
     case 2: return launch_acc<BF16E, 2>(C, ldc, Pt, ldp, rows, N, s);
     default: return launch_acc<BF16E, 1>(C, ldc, Pt, ldp, rows, N, s);
   }
+}
+
+hipError_t launch_gather_values(const int32_t* perm, const float* values, float* out, int64_t nnz, hipStream_t s) {
+  if (nnz == 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((nnz + kBlock - 1) / kBlock, kMaxGridBlocks);
+  hipLaunchKernelGGL(gather_values_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, perm, values, out, nnz);
+  return hipGetLastError();
 }
 
 hipError_t launch_sddmm(const SddmmParams& P, int G, int V, int U, hipStream_t s) {

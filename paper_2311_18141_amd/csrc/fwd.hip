@@ -196,14 +196,12 @@ __global__ void __launch_bounds__(kBlock) fwd_stream(FwdParams P) {
     const int32_t p = s_beg[kk * 64 + ri] + (o - s_koff[kk * 64 + ri]);
     const int32_t* colp = P.t[0].colind;
     const float* valp = P.t[0].values;
-    const int32_t* permp = P.t[0].perm;
     const char* bp = static_cast<const char*>(P.t[0].B);
     int64_t ldbb = P.t[0].ldb;
     for (int t = 1; t < K; ++t) {
       if (k == t) {
         colp = P.t[t].colind;
         valp = P.t[t].values;
-        permp = P.t[t].perm;
         bp = static_cast<const char*>(P.t[t].B);
         ldbb = P.t[t].ldb;
       }
@@ -213,7 +211,7 @@ __global__ void __launch_bounds__(kBlock) fwd_stream(FwdParams P) {
     int end = 0;
     if (lane < n) {
       const uint32_t col = (uint32_t)__builtin_nontemporal_load(colp + p);
-      val = permp ? valp[permp[p]] : __builtin_nontemporal_load(valp + p);
+      val = __builtin_nontemporal_load(valp + p);
       addr = reinterpret_cast<uint64_t>(bp) + (uint64_t)col * (uint64_t)(ldbb * (int64_t)sizeof(T));
       end = (q + 1 == s_pref[ri + 1]) ? 1 : 0;
     }

@@ -49,7 +49,7 @@ __device__ __forceinline__ void accumulate_range(const TileDev& t, int p0, int p
     float my_val = 0.0f;
     if (gl < cnt) {
       my_col = __builtin_nontemporal_load(t.colind + pc + gl);
-      my_val = t.perm ? t.values[t.perm[pc + gl]] : __builtin_nontemporal_load(t.values + pc + gl);
+      my_val = __builtin_nontemporal_load(t.values + pc + gl);
     }
     int j = 0;
     for (; j + U <= cnt; j += U) {

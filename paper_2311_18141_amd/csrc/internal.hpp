@@ -21,7 +21,6 @@ struct TileDev {
   const int32_t* rowptr;
   const int32_t* colind;
   const float* values;
-  const int32_t* perm;   // nullable: the value of position q is values[perm[q]]
   const void* B;         // dense operand rows for this tile's columns
   int64_t ldb;
 };
@@ -134,6 +133,8 @@ struct SddmmParams {
   int64_t c_begin, c_end;  // column range of this launch
   int accumulate;          // add to dA (later slices)
 };
+// out[q] = values[perm[q]] for q < nnz.
+hipError_t launch_gather_values(const int32_t* perm, const float* values, float* out, int64_t nnz, hipStream_t s);
 // G lanes per group, V columns per lane and load, U non-zeros per group.
 hipError_t launch_sddmm(const SddmmParams& P, int G, int V, int U, hipStream_t s);
 hipError_t launch_accumulate(void* C, int64_t ldc, const void* Pt, int64_t ldp, int64_t rows, int64_t N, DT dt,

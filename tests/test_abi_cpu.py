@@ -29,6 +29,20 @@ def test_library_exports_every_declared_symbol():
     assert set(names) <= set(_lib.EXPORTS), set(names) - set(_lib.EXPORTS)
 
 
+def test_library_exports_only_declared_c_symbols():
+    """No C-linkage symbol leaks beyond the header's declarations (C++ symbols are mangled)."""
+    import shutil
+    import subprocess
+    if shutil.which("nm") is None:
+        pytest.skip("nm not available")
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], check=True, capture_output=True,
+                         text=True).stdout
+    names = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    c_names = {n for n in names if not n.startswith("_Z") and not n.startswith("__") and not n.startswith("_")}
+    c_names -= {"_init", "_fini"}
+    assert c_names == set(declared_functions()), c_names ^ set(declared_functions())
+
+
 def test_status_strings():
     L = _lib.lib()
     for code, name in _lib.STATUS_NAMES.items():
