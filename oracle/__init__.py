@@ -1,4 +1,4 @@
-"""FP64 CPU oracle for the local SpMM, its backward and BF16 rounding.
+"""FP64 CPU oracle for the local SpMM, its backward, BF16 rounding and the local SpGEMM.
 
 TEST INFRASTRUCTURE ONLY: imported by the tests, by the package's smoke check
 and by the bench's CPU-baseline leg, never by the product path.  The arithmetic
@@ -51,6 +51,10 @@ def load(path: str) -> ctypes.CDLL:
     L.oracle_transpose.argtypes = [_i64, _i64, _vp, _vp, _vp, _vp, _vp]
     L.oracle_f32_to_bf16.restype = None
     L.oracle_f32_to_bf16.argtypes = [_i64, _vp, _vp]
+    L.oracle_spgemm_count.restype = _int
+    L.oracle_spgemm_count.argtypes = [_i64, _vp, _vp, _vp, _vp, _vp, _i64, _vp]
+    L.oracle_spgemm_fill.restype = _int
+    L.oracle_spgemm_fill.argtypes = [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp]
     return L
 
 
@@ -174,3 +178,34 @@ def f32_to_bf16(x: np.ndarray) -> np.ndarray:
 def bf16_to_f32(h: np.ndarray) -> np.ndarray:
     """BF16 bit patterns (uint16) -> FP32, exact widening."""
     return (np.asarray(h, dtype=np.uint16).astype(np.uint32) << 16).view(np.float32)
+
+
+def spgemm(A: Tuple[np.ndarray, np.ndarray, np.ndarray], B: Tuple[np.ndarray, np.ndarray, np.ndarray], N: int,
+           rows: Optional[np.ndarray] = None, scale: bool = True
+           ) -> Tuple[np.ndarray, np.ndarray, np.ndarray, Optional[np.ndarray]]:
+    """C = A B for CSR A (rowptr, colind, values) and B (K x N), in FP64.
+
+    Returns (rowptr int64[n_out+1], colind int64[nnz], values float64[nnz], S) for the
+    output rows ``rows`` (or all rows of A), columns sorted within each row, the
+    pattern structural (products that cancel keep their entry); S = sum |a||b| per entry.
+    """
+    rpA, ciA, vaA = _c(A[0], np.int32), _c(A[1], np.int32), _c(A[2], np.float32)
+    rpB, ciB, vaB = _c(B[0], np.int32), _c(B[1], np.int32), _c(B[2], np.float32)
+    M = rpA.shape[0] - 1
+    rows_a = None if rows is None else _c(rows, np.int64)
+    n_out = M if rows_a is None else rows_a.shape[0]
+    counts = np.empty(n_out, dtype=np.int64)
+    if lib().oracle_spgemm_count(n_out, _ptr(rows_a), rpA.ctypes.data, ciA.ctypes.data, rpB.ctypes.data,
+                                 ciB.ctypes.data, int(N), counts.ctypes.data) != 0:
+        raise MemoryError("oracle_spgemm_count could not allocate its marker array")
+    rowptr = np.zeros(n_out + 1, dtype=np.int64)
+    np.cumsum(counts, out=rowptr[1:])
+    nnz = int(rowptr[-1])
+    colC = np.empty(max(nnz, 1), dtype=np.int64)
+    valC = np.empty(max(nnz, 1), dtype=np.float64)
+    S = np.empty(max(nnz, 1), dtype=np.float64) if scale else None
+    if lib().oracle_spgemm_fill(n_out, _ptr(rows_a), rpA.ctypes.data, ciA.ctypes.data, vaA.ctypes.data,
+                                rpB.ctypes.data, ciB.ctypes.data, vaB.ctypes.data, int(N), rowptr.ctypes.data,
+                                colC.ctypes.data, valC.ctypes.data, _ptr(S)) != 0:
+        raise MemoryError("oracle_spgemm_fill could not allocate its accumulators")
+    return rowptr, colC[:nnz], valC[:nnz], (S[:nnz] if S is not None else None)

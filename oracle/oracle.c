@@ -20,6 +20,9 @@
  *     column indices); Section 6: FP32 values, 32-bit indices.
  * The backward routines (SDDMM, A^T dC, transposed structure) and the BF16
  * rounding are not in the paper; they are the textbook definitions.
+ * The sparse-times-sparse product (Section 6.2 multiplies C = A A with a local
+ * SpGEMM inside the same distributed algorithms) is its textbook definition too:
+ * a structural product pattern with the products summed in Gustavson order.
  */
 #include <math.h>
 #include <stdint.h>
@@ -183,4 +186,102 @@ EXPORT void oracle_f32_to_bf16(int64_t n, const float* x, uint16_t* y) {
     if (lower > 0x8000u || (lower == 0x8000u && (upper & 1u))) upper += 1u;
     y[t] = (uint16_t)upper;
   }
+}
+
+/*
+ * Sparse times sparse, C = A B, for output rows i = rows[r] (or r when rows is
+ * NULL), A M x K and B K x N in CSR.  The pattern of C is structural: (i, j) is
+ * present when some p in row i of A has j in row colA[p] of B (whatever the values,
+ * so cancellation to zero keeps the entry).  Pass 1 counts the distinct columns of
+ * every output row: counts[r].
+ */
+EXPORT int oracle_spgemm_count(int64_t n_out, const int64_t* rows, const int32_t* rowptrA, const int32_t* colA,
+                               const int32_t* rowptrB, const int32_t* colB, int64_t N, int64_t* counts) {
+  int failed = 0;
+#pragma omp parallel
+  {
+    int64_t* mark = (int64_t*)malloc((size_t)(N > 0 ? N : 1) * sizeof(int64_t));
+    if (!mark) {
+#pragma omp atomic write
+      failed = 1;
+    } else {
+      for (int64_t j = 0; j < N; ++j) mark[j] = -1;
+#pragma omp for schedule(dynamic, 256)
+      for (int64_t r = 0; r < n_out; ++r) {
+        int64_t i = rows ? rows[r] : r, cnt = 0;
+        for (int64_t p = rowptrA[i]; p < rowptrA[i + 1]; ++p) {
+          int64_t k = colA[p];
+          for (int64_t q = rowptrB[k]; q < rowptrB[k + 1]; ++q) {
+            int64_t j = colB[q];
+            if (mark[j] != r) {
+              mark[j] = r;
+              ++cnt;
+            }
+          }
+        }
+        counts[r] = cnt;
+      }
+      free(mark);
+    }
+  }
+  return failed ? -1 : 0;
+}
+
+static int cmp_i64(const void* a, const void* b) {
+  int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+  return (x > y) - (x < y);
+}
+
+/*
+ * Pass 2 of C = A B: for every output row r (offset[r] = its start in the output),
+ *   C[i, j] = sum over p in row i of A, q in row colA[p] of B with colB[q] = j of valA[p] * valB[q]
+ * accumulated in that (Gustavson) order in double, written with the row's columns in
+ * increasing order; S[i, j] (nullable) is the same sum over |valA[p]| * |valB[q]|.
+ */
+EXPORT int oracle_spgemm_fill(int64_t n_out, const int64_t* rows, const int32_t* rowptrA, const int32_t* colA,
+                              const float* valA, const int32_t* rowptrB, const int32_t* colB, const float* valB,
+                              int64_t N, const int64_t* offset, int64_t* colC, double* valC, double* S) {
+  int failed = 0;
+#pragma omp parallel
+  {
+    double* acc = (double*)malloc((size_t)(N > 0 ? N : 1) * sizeof(double));
+    double* sc = (double*)malloc((size_t)(N > 0 ? N : 1) * sizeof(double));
+    int64_t* mark = (int64_t*)malloc((size_t)(N > 0 ? N : 1) * sizeof(int64_t));
+    if (!acc || !sc || !mark) {
+#pragma omp atomic write
+      failed = 1;
+    } else {
+      for (int64_t j = 0; j < N; ++j) mark[j] = -1;
+#pragma omp for schedule(dynamic, 256)
+      for (int64_t r = 0; r < n_out; ++r) {
+        int64_t i = rows ? rows[r] : r;
+        int64_t* cols = colC + offset[r];
+        int64_t cnt = 0;
+        for (int64_t p = rowptrA[i]; p < rowptrA[i + 1]; ++p) {
+          int64_t k = colA[p];
+          double a = (double)valA[p];
+          for (int64_t q = rowptrB[k]; q < rowptrB[k + 1]; ++q) {
+            int64_t j = colB[q];
+            if (mark[j] != r) {
+              mark[j] = r;
+              acc[j] = 0.0;
+              sc[j] = 0.0;
+              cols[cnt++] = j;
+            }
+            acc[j] += a * (double)valB[q];
+            sc[j] += fabs(a) * fabs((double)valB[q]);
+          }
+        }
+        qsort(cols, (size_t)cnt, sizeof(int64_t), cmp_i64);
+        for (int64_t t = 0; t < cnt; ++t) {
+          valC[offset[r] + t] = acc[cols[t]];
+          if (S) S[offset[r] + t] = sc[cols[t]];
+        }
+      }
+    }
+    free(acc);
+    free(sc);
+    free(mark);
+  }
+  return failed ? -1 : 0;
 }

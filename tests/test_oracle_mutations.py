@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 import test_oracle as T
+import test_oracle_spgemm as TS
 
 MUTANTS = {
     "drop_accumulate_term": ("c[n] = accumulate ? (double)C0[i * ldc0 + n] : 0.0;", "c[n] = 0.0;"),
@@ -27,6 +28,13 @@ MUTANTS = {
     "bf16_ties_away": ("(lower == 0x8000u && (upper & 1u))", "(lower == 0x8000u)"),
     "bf16_truncate": ("upper += 1u;", "upper += 0u;"),
     "bf16_nan_passthrough": ("      y[t] = 0x7FC0u;\n      continue;", "      y[t] = (uint16_t)(bits >> 16);\n      continue;"),
+    "spgemm_first_b_row_only": ("          int64_t k = colA[p];\n          double a", "          int64_t k = colA[rowptrA[i]];\n          double a"),
+    "spgemm_count_all_products": ("            if (mark[j] != r) {\n              mark[j] = r;\n              ++cnt;",
+                                  "            if (1) {\n              mark[j] = r;\n              ++cnt;"),
+    "spgemm_unsorted_row": ("        qsort(cols, (size_t)cnt, sizeof(int64_t), cmp_i64);\n", ""),
+    "spgemm_drop_b_value": ("            acc[j] += a * (double)valB[q];", "            acc[j] += a;"),
+    "spgemm_skip_last_b": ("          for (int64_t q = rowptrB[k]; q < rowptrB[k + 1]; ++q) {\n            int64_t j = colB[q];\n            if (mark[j] != r) {\n              mark[j] = r;\n              acc",
+                           "          for (int64_t q = rowptrB[k]; q < rowptrB[k + 1] - 1; ++q) {\n            int64_t j = colB[q];\n            if (mark[j] != r) {\n              mark[j] = r;\n              acc"),
 }
 
 
@@ -47,6 +55,11 @@ def _pins():
         lambda: T.test_spmm_t_vs_dense_and_scipy(),
         lambda: T.test_transpose_vs_scipy(300, 200, 1),
         lambda: T.test_bf16_vs_torch_stratified(),
+        lambda: TS.test_spgemm_vs_dense(40, 30, 50, 0.1),
+        lambda: TS.test_spgemm_integer_exact(),
+        lambda: TS.test_spgemm_exhaustive_2x2_patterns(),
+        lambda: TS.test_spgemm_cancellation_keeps_entry(),
+        lambda: TS.test_spgemm_identity_and_permutation(),
     ]
 
 
@@ -66,7 +79,8 @@ def test_pins_catch_mutant(name, tmp_path):
         for i, pin in enumerate(_pins()):
             try:
                 pin()
-            except AssertionError:
+            except (AssertionError, IndexError, ValueError):
+                # a failed comparison, or output so malformed that the pin cannot index it
                 caught.append(i)
     finally:
         oracle._lib = saved
