@@ -77,15 +77,19 @@ def _log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+# Sources of the kernels the SpMM workloads launch (forward, split-row fix-up, SDDMM,
+# value gather): stored counter readings are valid while these are unchanged.
+KERNEL_SOURCES = ("elem.hpp", "fwd_common.hpp", "fwd.hip", "bwd.hip")
+
+
 def kernel_source_digest() -> str:
-    """SHA-256 over the HIP sources, to tell whether stored counter readings still describe the kernels."""
+    """SHA-256 over the SpMM kernel sources, to tell whether stored counter readings still describe them."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2311_18141_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 

@@ -248,6 +248,40 @@ spmm_status spmm_batched(spmm_batch_t batch, const void* const* B, const int64_t
 spmm_status spmm_tile_accumulate(void* C, int64_t ldc, const void* Ptile, int64_t ldp, int64_t rows, int64_t N,
                                  spmm_dtype dtype, void* stream);
 
+/*
+ * Local sparse-times-sparse product C = A B (CSR x CSR -> CSR): the local step of
+ * the paper's SpGEMM experiments (Section 6.2 computes C = A A with the same
+ * distributed algorithms, each GPU multiplying pairs of sparse tiles; Section 4
+ * bounds the local product's arithmetic intensity by its compression factor).
+ *
+ * A is M x A->cols, B is A->cols x B->cols; both canonical CSR (int32 indices,
+ * FP32 values, strictly increasing columns per row; SPMM_TILE_VALIDATE checks it),
+ * device arrays owned by the caller that must outlive the plan.
+ *
+ * spgemm_create analyses the structure and runs the symbolic product,
+ * synchronously: products per row, C's entries per row and C's row pointer
+ * (kept in the plan), and allocates the plan's own device memory (row lists;
+ * dense accumulators for long rows, zeroed).  C's pattern is structural: (i, j) is
+ * present when some product a_ip * b_pj exists, even if the sum is zero.
+ * spgemm_info returns nnz(C) and the number of products (2 x products = flops).
+ * spgemm_rowptr copies C's row pointer (M + 1 int32) to a device buffer.
+ * spgemm_compute writes C's column indices (sorted within each row) and values
+ * (FP32 sums; their order of summation inside a row is not fixed, so the last bits
+ * may differ between calls) into device buffers of nnz(C) entries, reading A's
+ * and B's values live; asynchronous, no allocation, no host synchronisation.
+ * Calls on one plan must not overlap (they share the dense accumulators).
+ * Errors: INVALID_ARG, BAD_CSR (with SPMM_TILE_VALIDATE), UNSUPPORTED (nnz >= 2^31,
+ * C with >= 2^31 entries), ALLOC, HIP.
+ */
+typedef struct spgemm_s* spgemm_t;
+spmm_status spgemm_create(int64_t M, const spmm_csr* A /* host */, const spmm_csr* B /* host */, unsigned flags,
+                          void* stream, spgemm_t* out /* host */);
+spmm_status spgemm_destroy(spgemm_t plan);
+spmm_status spgemm_info(spgemm_t plan, int64_t* nnz_c /* host, nullable */, int64_t* products /* host, nullable */);
+spmm_status spgemm_rowptr(spgemm_t plan, int32_t* rowptrC /* device, M + 1 */, void* stream);
+spmm_status spgemm_compute(spgemm_t plan, int32_t* colindC /* device, nnz(C) */, float* valuesC /* device */,
+                           void* stream);
+
 const char* spmm_status_string(spmm_status status);
 const char* spmm_last_error(void);
 

@@ -69,6 +69,11 @@ EXPORTS = {
     "spmm_fwd": (c_int, [c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_i64, c_int, c_i64, c_int, c_vp, c_size, c_vp]),
     "spmm_bwd_workspace_bytes": (c_int, [c_vp, c_i64, c_vp]),
     "spmm_bwd": (c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, c_i64, c_vp, c_vp, c_i64, c_vp, c_size, c_vp]),
+    "spgemm_create": (c_int, [c_i64, c_vp, c_vp, c_uint, c_vp, c_vp]),
+    "spgemm_destroy": (c_int, [c_vp]),
+    "spgemm_info": (c_int, [c_vp, c_vp, c_vp]),
+    "spgemm_rowptr": (c_int, [c_vp, c_vp, c_vp]),
+    "spgemm_compute": (c_int, [c_vp, c_vp, c_vp, c_vp]),
     "spmm_batch_create": (c_int, [c_int, c_vp, c_vp, c_int, c_i64, c_uint, c_vp, c_vp]),
     "spmm_batch_destroy": (c_int, [c_vp]),
     "spmm_batch_workspace_bytes": (c_int, [c_vp, c_vp]),

@@ -163,6 +163,49 @@ bool pow2_lanes(int g) { return g == 4 || g == 8 || g == 16 || g == 32 || g == 6
 
 }  // namespace
 
+namespace spmm {
+
+spmm_status set_error(spmm_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+spmm_status validate_csr(const int32_t* rowptr, const int32_t* colind, int64_t rows, int64_t cols, int64_t nnz,
+                         hipStream_t s) {
+  uint32_t* status = nullptr;
+  HIP_TRY(hipMalloc(reinterpret_cast<void**>(&status), sizeof(uint32_t)));
+  uint32_t bits = 0;
+  auto run = [&](bool cols_pass) -> spmm_status {
+    HIP_TRY(hipMemsetAsync(status, 0, sizeof(uint32_t), s));
+    if (!cols_pass)
+      HIP_TRY(launch_validate_rowptr(rowptr, rows, nnz, status, s));
+    else
+      HIP_TRY(launch_validate_colind(rowptr, colind, rows, cols, status, s));
+    HIP_TRY(hipMemcpyAsync(&bits, status, sizeof bits, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return SPMM_OK;
+  };
+  spmm_status st = run(false);
+  if (st == SPMM_OK && bits)
+    st = fail(SPMM_ERR_BAD_CSR, "row pointer invalid (bits 0x%x: 1 first!=0, 2 decreasing, 4 last!=nnz, "
+              "8 out of [0,nnz])", bits);
+  if (st == SPMM_OK) {
+    st = run(true);
+    if (st == SPMM_OK && bits)
+      st = fail(SPMM_ERR_BAD_CSR, "column indices invalid (bits 0x%x: 16 out of range, 32 not strictly "
+                "increasing in a row)", bits);
+  }
+  (void)hipFree(status);
+  return st;
+}
+
+}  // namespace spmm
+
 struct spmm_tile_s {
   int64_t rows = 0;
   int num_k = 0;

@@ -7,6 +7,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "spmm.h"
+
 namespace spmm {
 
 constexpr int kMaxK = 16;      // k-tiles per tile row in one fused launch
@@ -15,6 +17,12 @@ constexpr int kBlock = 256;    // threads per workgroup for every kernel here
 constexpr int64_t kMaxGridBlocks = (int64_t)1 << 20;
 
 enum class DT : int { F32 = 0, BF16 = 1 };
+
+// Record the thread-local message spmm_last_error() returns; returns st.
+spmm_status set_error(spmm_status st, const char* fmt, ...);
+// Row-pointer and column-index checks of one CSR matrix (synchronous on s).
+spmm_status validate_csr(const int32_t* rowptr, const int32_t* colind, int64_t rows, int64_t cols, int64_t nnz,
+                         hipStream_t s);
 
 // One k-tile as the forward kernels see it.
 struct TileDev {

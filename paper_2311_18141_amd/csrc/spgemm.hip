@@ -1,0 +1,770 @@
+// Local sparse-times-sparse product C = A B (CSR x CSR -> CSR), the local step of
+// the paper's SpGEMM experiments (Section 6.2 multiplies C = A A with the same
+// distributed algorithms; each GPU runs a local SpGEMM per tile pair).
+//
+// Row-wise (Gustavson) product: row i of C is the sum over p in row i of A of
+// a_p times row colA[p] of B.  Two phases, both binned by row:
+//  * symbolic (at plan creation): the number of products of each row, then the
+//    number of distinct output columns: rows with few products in a wave-local LDS
+//    hash set, the others in a workgroup-wide bitmap over all N columns (LDS when
+//    it fits, else a global slot), new bits counted as they are set;
+//  * numeric: rows with few output entries accumulate in a wave-local LDS hash
+//    table, medium rows in a workgroup-wide LDS table, both bitonic-sorted by column
+//    afterwards; long rows accumulate in a dense global row (values + bitmap) owned
+//    by one workgroup, then compacted in column order (sorted for free) and cleared.
+// Every product (p, q) of a row is visited once: the row's A entries are taken 64
+// (a wave) or 1024 (a workgroup) at a time, the lengths of their B rows are
+// prefix-summed, and each lane takes products t, t + lanes, ... locating its A entry
+// by binary search in the prefix, so that short B rows still fill every lane.
+// Output columns are sorted and the pattern is exact; values are FP32 sums whose
+// order inside a row follows the atomics (no fixed order).
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+#include "spmm.h"
+
+namespace spmm {
+namespace {
+
+constexpr int kWG = 1024;            // threads of the workgroup-wide kernels
+constexpr int kWGWaves = kWG / 64;
+
+__device__ __forceinline__ uint32_t hash_slot(int32_t col, int shift) {
+  return ((uint32_t)col * 2654435761u) >> shift;
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int64_t wave_sum64(int64_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const int lo = __shfl_xor((int)(uint32_t)x, o, 64);
+    const int hi = __shfl_xor((int)(x >> 32), o, 64);
+    x += (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+  }
+  return x;
+}
+
+__device__ __forceinline__ int wave_sum(int x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+struct SgOperands {
+  const int32_t* rowptrA;
+  const int32_t* colA;
+  const float* valA;
+  const int32_t* rowptrB;
+  const int32_t* colB;
+  const float* valB;
+  int64_t M, N;
+};
+
+// Products of every row: sum over p in row i of the length of B row colA[p].
+__global__ void __launch_bounds__(kBlock) row_products_kernel(SgOperands O, int64_t* fl) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t i = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); i < O.M;
+       i += (int64_t)gridDim.x * (kBlock / 64)) {
+    int64_t acc = 0;
+    for (int64_t p = O.rowptrA[i] + lane; p < O.rowptrA[i + 1]; p += 64) {
+      const int32_t k = O.colA[p];
+      acc += O.rowptrB[k + 1] - O.rowptrB[k];
+    }
+    acc = wave_sum64(acc);
+    if (lane == 0) fl[i] = acc;
+  }
+}
+
+// Visit the products of A entries [a0, a1) with one wave: f(col, a * b).
+template <bool VALS, typename F>
+__device__ __forceinline__ void wave_products(const SgOperands& O, int32_t a0, int32_t a1, int32_t* s_pref,
+                                              int32_t* s_start, float* s_aval, F&& f) {
+  const int lane = threadIdx.x & 63;
+  for (int32_t c = a0; c < a1; c += 64) {
+    const int n = min(64, a1 - c);
+    int32_t st = 0, len = 0;
+    float av = 0.0f;
+    if (lane < n) {
+      const int32_t k = O.colA[c + lane];
+      st = O.rowptrB[k];
+      len = O.rowptrB[k + 1] - st;
+      if constexpr (VALS) av = O.valA[c + lane];
+    }
+    int32_t incl = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    s_pref[lane] = incl - len;
+    s_start[lane] = st;
+    if constexpr (VALS) s_aval[lane] = av;
+    const int32_t tot = __builtin_amdgcn_readlane(incl, 63);
+    wave_sync_lds();
+    for (int32_t t = lane; t < tot; t += 64) {
+      int pi = 0;
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1)
+        if (s_pref[pi + step] <= t) pi += step;
+      const int32_t q = s_start[pi] + (t - s_pref[pi]);
+      f(O.colB[q], VALS ? s_aval[pi] * O.valB[q] : 0.0f);
+    }
+    wave_sync_lds();
+  }
+}
+
+// Exclusive scan of one value per thread over a kWG-thread workgroup; returns the
+// total.  s_tmp holds kWGWaves ints.
+__device__ __forceinline__ int32_t block_scan(int32_t v, int32_t* excl, int32_t* s_tmp) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int32_t incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) s_tmp[w] = incl;
+  __syncthreads();
+  int32_t base = 0, total = 0;
+  for (int u = 0; u < kWGWaves; ++u) {
+    const int32_t x = s_tmp[u];
+    if (u < w) base += x;
+    total += x;
+  }
+  __syncthreads();
+  *excl = base + incl - v;
+  return total;
+}
+
+// Visit the products of A entries [a0, a1) with the whole workgroup: f(col, a * b).
+// LDS: s_pref[kWG + 1], s_start[kWG], s_aval[kWG], s_tmp[kWGWaves].
+template <bool VALS, typename F>
+__device__ __forceinline__ void block_products(const SgOperands& O, int32_t a0, int32_t a1, int32_t* s_pref,
+                                               int32_t* s_start, float* s_aval, int32_t* s_tmp, F&& f) {
+  const int tid = threadIdx.x;
+  for (int32_t c = a0; c < a1; c += kWG) {
+    const int n = min(kWG, a1 - c);
+    int32_t st = 0, len = 0;
+    float av = 0.0f;
+    if (tid < n) {
+      const int32_t k = O.colA[c + tid];
+      st = O.rowptrB[k];
+      len = O.rowptrB[k + 1] - st;
+      if constexpr (VALS) av = O.valA[c + tid];
+    }
+    int32_t excl;
+    const int32_t tot = block_scan(len, &excl, s_tmp);
+    s_pref[tid] = excl;
+    s_start[tid] = st;
+    if constexpr (VALS) s_aval[tid] = av;
+    __syncthreads();
+    for (int32_t t = tid; t < tot; t += kWG) {
+      int pi = 0;
+#pragma unroll
+      for (int step = kWG / 2; step > 0; step >>= 1)
+        if (pi + step < kWG && s_pref[pi + step] <= t) pi += step;
+      const int32_t q = s_start[pi] + (t - s_pref[pi]);
+      f(O.colB[q], VALS ? s_aval[pi] * O.valB[q] : 0.0f);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- symbolic
+
+// Rows with at most TS/2 products: distinct columns in a wave-local hash set.
+template <int TS>
+__global__ void __launch_bounds__(kBlock) sym_wave_kernel(SgOperands O, const int32_t* rows, int64_t n_rows,
+                                                          int32_t* nnz_row) {
+  constexpr int W = kBlock / 64;
+  constexpr int SHIFT = 32 - __builtin_ctz(TS);
+  __shared__ int32_t s_tab[W][TS];
+  __shared__ int32_t s_pref[W][64], s_start[W][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int32_t* tab = s_tab[w];
+  for (int64_t r = (int64_t)blockIdx.x * W + w; r < n_rows; r += (int64_t)gridDim.x * W) {
+    const int32_t i = rows[r];
+    for (int j = lane; j < TS; j += 64) tab[j] = -1;
+    wave_sync_lds();
+    int cnt = 0;
+    wave_products<false>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref[w], s_start[w], nullptr,
+                         [&](int32_t col, float) {
+                           uint32_t h = hash_slot(col, SHIFT);
+                           for (;;) {
+                             const int32_t old = atomicCAS(&tab[h], -1, col);
+                             if (old == -1) {
+                               ++cnt;
+                               break;
+                             }
+                             if (old == col) break;
+                             h = (h + 1) & (TS - 1);
+                           }
+                         });
+    cnt = wave_sum(cnt);
+    if (lane == 0) nnz_row[i] = cnt;
+    wave_sync_lds();
+  }
+}
+
+// Other rows: one workgroup per row, a bitmap over the N output columns (LDS when
+// `words` fit, else the workgroup's global slot), counting bits as they turn on.
+template <bool GLOBAL>
+__global__ void __launch_bounds__(kWG) sym_bitmap_kernel(SgOperands O, const int32_t* rows, int64_t n_rows,
+                                                         int32_t* nnz_row, uint32_t* gbits, int64_t slot_words) {
+  extern __shared__ int32_t s_dyn[];
+  int32_t* s_pref = s_dyn;
+  int32_t* s_start = s_pref + kWG + 1;
+  int32_t* s_tmp = s_start + kWG;
+  int32_t* s_cnt = s_tmp + kWGWaves;
+  uint32_t* bits = GLOBAL ? gbits + (int64_t)blockIdx.x * slot_words
+                          : reinterpret_cast<uint32_t*>(s_cnt + kWGWaves);
+  const int64_t words = (O.N + 31) / 32;
+  const int tid = threadIdx.x;
+  if constexpr (!GLOBAL) {
+    for (int64_t j = tid; j < words; j += kWG) bits[j] = 0u;
+  }
+  __syncthreads();
+  for (int64_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
+    const int32_t i = rows[r];
+    int cnt = 0;
+    block_products<false>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref, s_start, nullptr, s_tmp,
+                          [&](int32_t col, float) {
+                            const uint32_t bit = 1u << (col & 31);
+                            uint32_t old;
+                            if constexpr (GLOBAL)
+                              old = __hip_atomic_fetch_or(bits + (col >> 5), bit, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+                            else
+                              old = atomicOr(bits + (col >> 5), bit);
+                            if (!(old & bit)) ++cnt;
+                          });
+    cnt = wave_sum(cnt);
+    if ((tid & 63) == 0) s_cnt[tid >> 6] = cnt;
+    __syncthreads();
+    if (tid == 0) {
+      int total = 0;
+      for (int u = 0; u < kWGWaves; ++u) total += s_cnt[u];
+      nnz_row[i] = total;
+    }
+    // clear for the next row
+    for (int64_t j = tid; j < words; j += kWG) {
+      if constexpr (GLOBAL)
+        __hip_atomic_store(bits + j, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      else
+        bits[j] = 0u;
+    }
+    if constexpr (GLOBAL) __threadfence();
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- numeric
+
+struct SgOut {
+  const int32_t* rowptrC;
+  int32_t* colC;
+  float* valC;
+};
+
+// Sort TS (key, value) pairs by key with bitonic merges; `lanes` threads starting at
+// thread `t0` take part; sync() orders the stages.
+template <int TS, typename Sync>
+__device__ __forceinline__ void bitonic_sort(int32_t* key, float* val, int t0, int lanes, Sync&& sync) {
+  for (int k = 2; k <= TS; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = t0; t < TS / 2; t += lanes) {
+        // t-th pair of this stage: lower index a, partner a + j
+        const int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));  // j is a power of two
+        const int b = a + j;
+        const bool up = (a & k) == 0;
+        const int32_t ka = key[a], kb = key[b];
+        if ((ka > kb) == up) {
+          key[a] = kb;
+          key[b] = ka;
+          const float va = val[a];
+          val[a] = val[b];
+          val[b] = va;
+        }
+      }
+      sync();
+    }
+  }
+}
+
+// Rows with at most TS/2 output entries: a wave-local hash table of (column, sum).
+template <int TS>
+__global__ void __launch_bounds__(kBlock) num_wave_kernel(SgOperands O, SgOut Co, const int32_t* rows,
+                                                          int64_t n_rows) {
+  constexpr int W = kBlock / 64;
+  constexpr int SHIFT = 32 - __builtin_ctz(TS);
+  __shared__ int32_t s_key[W][TS];
+  __shared__ float s_val[W][TS];
+  __shared__ int32_t s_pref[W][64], s_start[W][64];
+  __shared__ float s_aval[W][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int32_t* key = s_key[w];
+  float* val = s_val[w];
+  for (int64_t r = (int64_t)blockIdx.x * W + w; r < n_rows; r += (int64_t)gridDim.x * W) {
+    const int32_t i = rows[r];
+    for (int j = lane; j < TS; j += 64) {
+      key[j] = -1;
+      val[j] = 0.0f;
+    }
+    wave_sync_lds();
+    wave_products<true>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref[w], s_start[w], s_aval[w],
+                        [&](int32_t col, float prod) {
+                          uint32_t h = hash_slot(col, SHIFT);
+                          for (;;) {
+                            const int32_t old = atomicCAS(&key[h], -1, col);
+                            if (old == -1 || old == col) break;
+                            h = (h + 1) & (TS - 1);
+                          }
+                          atomicAdd(&val[h], prod);
+                        });
+    for (int j = lane; j < TS; j += 64)
+      if (key[j] < 0) key[j] = 0x7fffffff;  // empty slots sort last
+    wave_sync_lds();
+    bitonic_sort<TS>(key, val, lane, 64, [] { wave_sync_lds(); });
+    const int32_t base = Co.rowptrC[i], cnt = Co.rowptrC[i + 1] - base;
+    for (int j = lane; j < cnt; j += 64) {
+      Co.colC[base + j] = key[j];
+      Co.valC[base + j] = val[j];
+    }
+    wave_sync_lds();
+  }
+}
+
+// Rows with at most tg/2 output entries: one workgroup per row, an LDS hash table
+// of tg slots (a power of two; dynamic LDS).
+__global__ void __launch_bounds__(kWG) num_block_kernel(SgOperands O, SgOut Co, const int32_t* rows,
+                                                        int64_t n_rows, int tg_log2) {
+  extern __shared__ int32_t s_dyn[];
+  const int tg = 1 << tg_log2;
+  const int shift = 32 - tg_log2;
+  int32_t* key = s_dyn;
+  float* val = reinterpret_cast<float*>(key + tg);
+  int32_t* s_pref = reinterpret_cast<int32_t*>(val + tg);
+  int32_t* s_start = s_pref + kWG + 1;
+  float* s_aval = reinterpret_cast<float*>(s_start + kWG);
+  int32_t* s_tmp = reinterpret_cast<int32_t*>(s_aval + kWG);
+  const int tid = threadIdx.x;
+  for (int64_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
+    const int32_t i = rows[r];
+    for (int j = tid; j < tg; j += kWG) {
+      key[j] = -1;
+      val[j] = 0.0f;
+    }
+    __syncthreads();
+    block_products<true>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref, s_start, s_aval, s_tmp,
+                         [&](int32_t col, float prod) {
+                           uint32_t h = hash_slot(col, shift);
+                           for (;;) {
+                             const int32_t old = atomicCAS(&key[h], -1, col);
+                             if (old == -1 || old == col) break;
+                             h = (h + 1) & (uint32_t)(tg - 1);
+                           }
+                           atomicAdd(&val[h], prod);
+                         });
+    for (int j = tid; j < tg; j += kWG)
+      if (key[j] < 0) key[j] = 0x7fffffff;
+    __syncthreads();
+    // bitonic sort over tg slots (tg is a template-free runtime power of two)
+    for (int k = 2; k <= tg; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int t = tid; t < tg / 2; t += kWG) {
+          const int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));  // j is a power of two
+          const int b = a + j;
+          const bool up = (a & k) == 0;
+          const int32_t ka = key[a], kb = key[b];
+          if ((ka > kb) == up) {
+            key[a] = kb;
+            key[b] = ka;
+            const float va = val[a];
+            val[a] = val[b];
+            val[b] = va;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    const int32_t base = Co.rowptrC[i], cnt = Co.rowptrC[i + 1] - base;
+    for (int j = tid; j < cnt; j += kWG) {
+      Co.colC[base + j] = key[j];
+      Co.valC[base + j] = val[j];
+    }
+    __syncthreads();
+  }
+}
+
+// Long rows: workgroup b owns slot b (N floats + a bitmap of N bits, all zero
+// between rows) and takes rows b, b + grid, ...; products accumulate with
+// workgroup-scope atomics (only this workgroup touches the slot), then the bitmap is
+// walked in column order to write the row and clear what it set.
+__global__ void __launch_bounds__(kWG) num_dense_kernel(SgOperands O, SgOut Co, const int32_t* rows,
+                                                        int64_t n_rows, float* gvals, uint32_t* gbits,
+                                                        int64_t slot_words) {
+  __shared__ int32_t s_pref[kWG + 1], s_start[kWG];
+  __shared__ float s_aval[kWG];
+  __shared__ int32_t s_tmp[kWGWaves];
+  float* vals = gvals + (int64_t)blockIdx.x * slot_words * 32;
+  uint32_t* bits = gbits + (int64_t)blockIdx.x * slot_words;
+  const int64_t words = (O.N + 31) / 32;
+  const int tid = threadIdx.x;
+  for (int64_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
+    const int32_t i = rows[r];
+    block_products<true>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref, s_start, s_aval, s_tmp,
+                         [&](int32_t col, float prod) {
+                           __hip_atomic_fetch_or(bits + (col >> 5), 1u << (col & 31), __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+                           __hip_atomic_fetch_add(vals + col, prod, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                         });
+    __threadfence();
+    __syncthreads();
+    int32_t out = Co.rowptrC[i];
+    for (int64_t w0 = 0; w0 < words; w0 += kWG) {
+      const int64_t wi = w0 + tid;
+      uint32_t word = 0;
+      if (wi < words) word = __hip_atomic_load(bits + wi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int32_t excl;
+      const int32_t tot = block_scan(__popc(word), &excl, s_tmp);
+      int32_t pos = out + excl;
+      while (word) {
+        const int b = __ffs(word) - 1;
+        word &= word - 1;
+        const int64_t col = wi * 32 + b;
+        Co.colC[pos] = (int32_t)col;
+        Co.valC[pos] = __hip_atomic_load(vals + col, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(vals + col, 0.0f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ++pos;
+      }
+      if (wi < words) __hip_atomic_store(bits + wi, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      out += tot;
+    }
+    __threadfence();
+    __syncthreads();
+  }
+}
+
+// Numeric classes: wave tables of 256 / 512 / 1024 slots, the workgroup table,
+// the dense slots.  Symbolic classes: wave sets of 256 / 512 / 1024 slots, bitmap.
+constexpr int kNumClasses = 5;
+constexpr int kSymClasses = 4;
+
+int64_t grid_for(int64_t items, int64_t per_block) {
+  return std::max<int64_t>(1, std::min<int64_t>((items + per_block - 1) / per_block, kMaxGridBlocks));
+}
+
+}  // namespace
+}  // namespace spmm
+
+using spmm::kNumClasses;
+using spmm::kSymClasses;
+
+struct spgemm_s {
+  int64_t M = 0, K = 0, N = 0;
+  spmm_csr A = {}, B = {};
+  int device = 0;
+  int64_t nnz_c = 0, products = 0;
+  int32_t* rowptrC = nullptr;   // device, M + 1
+  int32_t* rows = nullptr;      // device: rows grouped by numeric class
+  int64_t cls_off[kNumClasses] = {}, cls_cnt[kNumClasses] = {};
+  int tg_log2 = 0;              // workgroup table of 2^tg_log2 slots
+  size_t lds_block = 0;         // its dynamic LDS bytes
+  float* slot_vals = nullptr;   // dense slots: n_slots x (slot_words * 32) floats
+  uint32_t* slot_bits = nullptr;
+  int64_t slot_words = 0;
+  int n_slots = 0;
+  ~spgemm_s() {
+    if (rowptrC) (void)hipFree(rowptrC);
+    if (rows) (void)hipFree(rows);
+    if (slot_vals) (void)hipFree(slot_vals);
+    if (slot_bits) (void)hipFree(slot_bits);
+  }
+};
+
+namespace {
+
+#define SG_TRY(expr)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return spmm::set_error(SPMM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+hipError_t dmalloc(T** p, int64_t n) {
+  return hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)(n > 0 ? n : 1));
+}
+
+spmm::SgOperands operands(const spgemm_s* h) {
+  spmm::SgOperands O;
+  O.rowptrA = h->A.rowptr;
+  O.colA = h->A.colind;
+  O.valA = h->A.values;
+  O.rowptrB = h->B.rowptr;
+  O.colB = h->B.colind;
+  O.valB = h->B.values;
+  O.M = h->M;
+  O.N = h->N;
+  return O;
+}
+
+constexpr size_t kBlockFixedLds = sizeof(int32_t) * (size_t)(3 * spmm::kWG + 1 + 2 * spmm::kWGWaves);
+
+// Dense slots for `want` concurrent rows (values + bitmap over N columns), zeroed.
+spmm_status ensure_slots(spgemm_s* h, int want, hipStream_t s) {
+  if (want <= h->n_slots) return SPMM_OK;
+  if (h->slot_vals) (void)hipFree(h->slot_vals);
+  if (h->slot_bits) (void)hipFree(h->slot_bits);
+  h->slot_vals = nullptr;
+  h->slot_bits = nullptr;
+  h->n_slots = 0;
+  h->slot_words = (h->N + 31) / 32;
+  if (dmalloc(&h->slot_vals, (int64_t)want * h->slot_words * 32) != hipSuccess ||
+      dmalloc(&h->slot_bits, (int64_t)want * h->slot_words) != hipSuccess)
+    return spmm::set_error(SPMM_ERR_ALLOC, "device allocation of %d dense SpGEMM rows failed", want);
+  SG_TRY(hipMemsetAsync(h->slot_vals, 0, sizeof(float) * (size_t)want * h->slot_words * 32, s));
+  SG_TRY(hipMemsetAsync(h->slot_bits, 0, sizeof(uint32_t) * (size_t)want * h->slot_words, s));
+  h->n_slots = want;
+  return SPMM_OK;
+}
+
+// Slots for rows handled one workgroup each: a few per CU, within 1 GiB.
+int slot_count(const spgemm_s* h, int64_t rows, int cus) {
+  const double slot_bytes = 4.0 * (double)((h->N + 31) / 32) * 33.0;
+  const int64_t by_mem = std::max<int64_t>(1, (int64_t)((double)(1ll << 30) / slot_bytes));
+  return (int)std::max<int64_t>(1, std::min<int64_t>({rows, (int64_t)cus * 2, by_mem}));
+}
+
+}  // namespace
+
+extern "C" {
+
+spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsigned flags, void* stream,
+                          spgemm_t* out) {
+  if (!out) return spmm::set_error(SPMM_ERR_INVALID_ARG, "out is null");
+  *out = nullptr;
+  if (!A || !B) return spmm::set_error(SPMM_ERR_INVALID_ARG, "A/B is null");
+  if (M < 0 || M >= ((int64_t)1 << 31)) return spmm::set_error(SPMM_ERR_INVALID_ARG, "M out of range");
+  if (A->cols < 0 || A->cols >= ((int64_t)1 << 31) || B->cols < 0 || B->cols >= ((int64_t)1 << 31))
+    return spmm::set_error(SPMM_ERR_INVALID_ARG, "column count out of range");
+  if (A->nnz < 0 || B->nnz < 0) return spmm::set_error(SPMM_ERR_INVALID_ARG, "negative nnz");
+  if (A->nnz >= ((int64_t)1 << 31) || B->nnz >= ((int64_t)1 << 31))
+    return spmm::set_error(SPMM_ERR_UNSUPPORTED, "nnz >= 2^31 needs 64-bit indices");
+  if (!A->rowptr || !B->rowptr) return spmm::set_error(SPMM_ERR_INVALID_ARG, "rowptr is null");
+  if ((A->nnz > 0 && (!A->colind || !A->values)) || (B->nnz > 0 && (!B->colind || !B->values)))
+    return spmm::set_error(SPMM_ERR_INVALID_ARG, "colind/values null");
+  if (flags & ~SPMM_TILE_VALIDATE) return spmm::set_error(SPMM_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (flags & SPMM_TILE_VALIDATE) {
+    const spmm_status st = spmm::validate_csr(A->rowptr, A->colind, M, A->cols, A->nnz, s);
+    if (st != SPMM_OK) return st;
+    const spmm_status st2 = spmm::validate_csr(B->rowptr, B->colind, A->cols, B->cols, B->nnz, s);
+    if (st2 != SPMM_OK) return st2;
+  }
+  spgemm_s* h = new (std::nothrow) spgemm_s();
+  if (!h) return spmm::set_error(SPMM_ERR_ALLOC, "host allocation failed");
+  h->M = M;
+  h->K = A->cols;
+  h->N = B->cols;
+  h->A = *A;
+  h->B = *B;
+  (void)hipGetDevice(&h->device);
+  auto body = [&]() -> spmm_status {
+    int cus = 0, lds_max = 0;
+    SG_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
+    SG_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
+    const spmm::SgOperands O = operands(h);
+    // products per row
+    int64_t* d_fl = nullptr;
+    int32_t* d_nnz = nullptr;
+    int32_t* d_rows = nullptr;
+    std::vector<int64_t> fl((size_t)M);
+    std::vector<int32_t> nz((size_t)M);
+    auto cleanup = [&]() {
+      if (d_fl) (void)hipFree(d_fl);
+      if (d_nnz) (void)hipFree(d_nnz);
+      if (d_rows) (void)hipFree(d_rows);
+    };
+    auto run = [&]() -> spmm_status {
+      if (dmalloc(&d_fl, M) != hipSuccess || dmalloc(&d_nnz, M) != hipSuccess || dmalloc(&d_rows, M) != hipSuccess ||
+          dmalloc(&h->rowptrC, M + 1) != hipSuccess || dmalloc(&h->rows, M) != hipSuccess)
+        return spmm::set_error(SPMM_ERR_ALLOC, "device allocation of the SpGEMM plan failed");
+      if (M > 0) {
+        hipLaunchKernelGGL(spmm::row_products_kernel, dim3((unsigned)spmm::grid_for(M, spmm::kBlock / 64)),
+                           dim3(spmm::kBlock), 0, s, O, d_fl);
+        SG_TRY(hipGetLastError());
+        SG_TRY(hipMemcpyAsync(fl.data(), d_fl, sizeof(int64_t) * (size_t)M, hipMemcpyDeviceToHost, s));
+        SG_TRY(hipStreamSynchronize(s));
+      }
+      // symbolic classes by products
+      std::vector<int32_t> list((size_t)M);
+      int64_t off[kSymClasses + 1] = {}, cnt[kSymClasses] = {};
+      auto sym_cls = [&](int64_t f) { return f == 0 ? -1 : f <= 128 ? 0 : f <= 256 ? 1 : f <= 512 ? 2 : 3; };
+      for (int64_t i = 0; i < M; ++i) {
+        h->products += fl[(size_t)i];
+        const int c = sym_cls(fl[(size_t)i]);
+        if (c >= 0) ++cnt[c];
+        else nz[(size_t)i] = 0;
+      }
+      for (int c = 0; c < kSymClasses; ++c) off[c + 1] = off[c] + cnt[c];
+      {
+        int64_t pos[kSymClasses];
+        for (int c = 0; c < kSymClasses; ++c) pos[c] = off[c];
+        for (int64_t i = 0; i < M; ++i) {
+          const int c = sym_cls(fl[(size_t)i]);
+          if (c >= 0) list[(size_t)pos[c]++] = (int32_t)i;
+        }
+      }
+      if (M > 0) {
+        SG_TRY(hipMemsetAsync(d_nnz, 0, sizeof(int32_t) * (size_t)M, s));
+        SG_TRY(hipMemcpyAsync(d_rows, list.data(), sizeof(int32_t) * (size_t)M, hipMemcpyHostToDevice, s));
+      }
+      if (cnt[0]) hipLaunchKernelGGL(spmm::sym_wave_kernel<256>, dim3((unsigned)spmm::grid_for(cnt[0], 4)),
+                                     dim3(spmm::kBlock), 0, s, O, d_rows + off[0], cnt[0], d_nnz);
+      if (cnt[1]) hipLaunchKernelGGL(spmm::sym_wave_kernel<512>, dim3((unsigned)spmm::grid_for(cnt[1], 4)),
+                                     dim3(spmm::kBlock), 0, s, O, d_rows + off[1], cnt[1], d_nnz);
+      if (cnt[2]) hipLaunchKernelGGL(spmm::sym_wave_kernel<1024>, dim3((unsigned)spmm::grid_for(cnt[2], 4)),
+                                     dim3(spmm::kBlock), 0, s, O, d_rows + off[2], cnt[2], d_nnz);
+      SG_TRY(hipGetLastError());
+      if (cnt[3]) {
+        const int64_t words = (h->N + 31) / 32;
+        const size_t lds = kBlockFixedLds + sizeof(uint32_t) * (size_t)words;
+        if (lds <= (size_t)lds_max) {
+          (void)hipFuncSetAttribute(reinterpret_cast<const void*>(spmm::sym_bitmap_kernel<false>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+          const int64_t grid = std::min<int64_t>(cnt[3], (int64_t)cus * 8);
+          hipLaunchKernelGGL(spmm::sym_bitmap_kernel<false>, dim3((unsigned)grid), dim3(spmm::kWG), lds, s, O,
+                             d_rows + off[3], cnt[3], d_nnz, (uint32_t*)nullptr, (int64_t)0);
+        } else {
+          const spmm_status st = ensure_slots(h, slot_count(h, cnt[3], cus), s);
+          if (st != SPMM_OK) return st;
+          hipLaunchKernelGGL(spmm::sym_bitmap_kernel<true>, dim3((unsigned)h->n_slots), dim3(spmm::kWG),
+                             kBlockFixedLds, s, O, d_rows + off[3], cnt[3], d_nnz, h->slot_bits, h->slot_words);
+        }
+        SG_TRY(hipGetLastError());
+      }
+      if (M > 0) {
+        SG_TRY(hipMemcpyAsync(nz.data(), d_nnz, sizeof(int32_t) * (size_t)M, hipMemcpyDeviceToHost, s));
+        SG_TRY(hipStreamSynchronize(s));
+      }
+      // row pointer of C
+      std::vector<int32_t> rp((size_t)M + 1);
+      int64_t total = 0;
+      for (int64_t i = 0; i < M; ++i) {
+        rp[(size_t)i] = (int32_t)total;
+        total += nz[(size_t)i];
+        if (total >= ((int64_t)1 << 31)) return spmm::set_error(SPMM_ERR_UNSUPPORTED, "C would hold >= 2^31 entries");
+      }
+      rp[(size_t)M] = (int32_t)total;
+      h->nnz_c = total;
+      SG_TRY(hipMemcpyAsync(h->rowptrC, rp.data(), sizeof(int32_t) * rp.size(), hipMemcpyHostToDevice, s));
+      // numeric classes by output entries
+      int tg_log2 = 8;
+      while (tg_log2 < 16 && kBlockFixedLds + 8 * ((size_t)1 << (tg_log2 + 1)) <= (size_t)lds_max) ++tg_log2;
+      h->tg_log2 = tg_log2;
+      h->lds_block = kBlockFixedLds + 8 * ((size_t)1 << tg_log2);
+      const int64_t tg_half = (int64_t)1 << (tg_log2 - 1);
+      auto num_cls = [&](int64_t n) {
+        return n == 0 ? -1 : n <= 128 ? 0 : n <= 256 ? 1 : n <= 512 ? 2 : n <= tg_half ? 3 : 4;
+      };
+      for (int c = 0; c < kNumClasses; ++c) h->cls_cnt[c] = 0;
+      for (int64_t i = 0; i < M; ++i) {
+        const int c = num_cls(nz[(size_t)i]);
+        if (c >= 0) ++h->cls_cnt[c];
+      }
+      h->cls_off[0] = 0;
+      for (int c = 1; c < kNumClasses; ++c) h->cls_off[c] = h->cls_off[c - 1] + h->cls_cnt[c - 1];
+      {
+        int64_t pos[kNumClasses];
+        for (int c = 0; c < kNumClasses; ++c) pos[c] = h->cls_off[c];
+        for (int64_t i = 0; i < M; ++i) {
+          const int c = num_cls(nz[(size_t)i]);
+          if (c >= 0) list[(size_t)pos[c]++] = (int32_t)i;
+        }
+      }
+      if (M > 0)
+        SG_TRY(hipMemcpyAsync(h->rows, list.data(), sizeof(int32_t) * (size_t)M, hipMemcpyHostToDevice, s));
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(spmm::num_block_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_block);
+      if (h->cls_cnt[4]) {
+        const spmm_status st = ensure_slots(h, slot_count(h, h->cls_cnt[4], cus), s);
+        if (st != SPMM_OK) return st;
+      }
+      SG_TRY(hipStreamSynchronize(s));
+      return SPMM_OK;
+    };
+    const spmm_status st = run();
+    cleanup();
+    return st;
+  };
+  const spmm_status st = body();
+  if (st != SPMM_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return SPMM_OK;
+}
+
+spmm_status spgemm_destroy(spgemm_t plan) {
+  if (!plan) return spmm::set_error(SPMM_ERR_INVALID_ARG, "plan is null");
+  (void)hipDeviceSynchronize();
+  delete plan;
+  return SPMM_OK;
+}
+
+spmm_status spgemm_info(spgemm_t plan, int64_t* nnz_c, int64_t* products) {
+  if (!plan) return spmm::set_error(SPMM_ERR_INVALID_ARG, "plan is null");
+  if (nnz_c) *nnz_c = plan->nnz_c;
+  if (products) *products = plan->products;
+  return SPMM_OK;
+}
+
+spmm_status spgemm_rowptr(spgemm_t plan, int32_t* rowptrC, void* stream) {
+  if (!plan || !rowptrC) return spmm::set_error(SPMM_ERR_INVALID_ARG, "null argument");
+  SG_TRY(hipMemcpyAsync(rowptrC, plan->rowptrC, sizeof(int32_t) * (size_t)(plan->M + 1), hipMemcpyDeviceToDevice,
+                        static_cast<hipStream_t>(stream)));
+  return SPMM_OK;
+}
+
+spmm_status spgemm_compute(spgemm_t plan, int32_t* colindC, float* valuesC, void* stream) {
+  if (!plan) return spmm::set_error(SPMM_ERR_INVALID_ARG, "plan is null");
+  if (plan->nnz_c > 0 && (!colindC || !valuesC)) return spmm::set_error(SPMM_ERR_INVALID_ARG, "colindC/valuesC null");
+  int dev = 0;
+  SG_TRY(hipGetDevice(&dev));
+  if (dev != plan->device) return spmm::set_error(SPMM_ERR_INVALID_ARG, "current device differs from the plan's");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const spmm::SgOperands O = operands(plan);
+  spmm::SgOut Co{plan->rowptrC, colindC, valuesC};
+  const int32_t* rows = plan->rows;
+  const int64_t* off = plan->cls_off;
+  const int64_t* cnt = plan->cls_cnt;
+  if (cnt[0]) hipLaunchKernelGGL(spmm::num_wave_kernel<256>, dim3((unsigned)spmm::grid_for(cnt[0], 4)),
+                                 dim3(spmm::kBlock), 0, s, O, Co, rows + off[0], cnt[0]);
+  if (cnt[1]) hipLaunchKernelGGL(spmm::num_wave_kernel<512>, dim3((unsigned)spmm::grid_for(cnt[1], 4)),
+                                 dim3(spmm::kBlock), 0, s, O, Co, rows + off[1], cnt[1]);
+  if (cnt[2]) hipLaunchKernelGGL(spmm::num_wave_kernel<1024>, dim3((unsigned)spmm::grid_for(cnt[2], 4)),
+                                 dim3(spmm::kBlock), 0, s, O, Co, rows + off[2], cnt[2]);
+  SG_TRY(hipGetLastError());
+  if (cnt[3]) {
+    const int64_t grid = std::min<int64_t>(cnt[3], 65536);
+    hipLaunchKernelGGL(spmm::num_block_kernel, dim3((unsigned)grid), dim3(spmm::kWG), plan->lds_block, s, O, Co,
+                       rows + off[3], cnt[3], plan->tg_log2);
+    SG_TRY(hipGetLastError());
+  }
+  if (cnt[4]) {
+    hipLaunchKernelGGL(spmm::num_dense_kernel, dim3((unsigned)plan->n_slots), dim3(spmm::kWG), 0, s, O, Co,
+                       rows + off[4], cnt[4], plan->slot_vals, plan->slot_bits, plan->slot_words);
+    SG_TRY(hipGetLastError());
+  }
+  return SPMM_OK;
+}
+
+}  // extern "C"

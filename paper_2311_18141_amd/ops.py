@@ -339,3 +339,71 @@ def spmm_batched(batch: Batch, Bs: Sequence[torch.Tensor], Cs: Sequence[torch.Te
     ws_n = workspace.numel() * workspace.element_size() if workspace is not None else 0
     check(lib().spmm_batched(batch.handle, b.data_ptr(), lb.data_ptr(), c.data_ptr(), lc.data_ptr(),
                              1 if accumulate else 0, ws_ptr, ws_n, _stream_ptr(stream)))
+
+
+# ---------------------------------------------------------------- local SpGEMM
+
+class SpgemmPlan:
+    """Plan of C = A B (CSR x CSR): C's structure is known at creation; values come from spgemm_compute."""
+
+    def __init__(self, handle: int, M: int, N: int, nnz_c: int, products: int, keep: list):
+        self.handle = handle
+        self.M = M
+        self.N = N
+        self.nnz_c = nnz_c
+        self.products = products
+        self._keep = keep
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                lib().spgemm_destroy(self.handle)
+            except Exception:
+                pass
+            self.handle = None
+
+
+def _csr_struct(rowptr, colind, values, cols, name):
+    for t, dt in ((rowptr, torch.int32), (colind, torch.int32), (values, torch.float32)):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("%s arrays must be contiguous device tensors (int32 rowptr/colind, float32 values)" % name)
+    return SpmmCsr(int(cols), int(colind.numel()), rowptr.data_ptr(), colind.data_ptr(), values.data_ptr())
+
+
+def spgemm_create(M: int, A: Tuple[torch.Tensor, torch.Tensor, torch.Tensor, int],
+                  B: Tuple[torch.Tensor, torch.Tensor, torch.Tensor, int], validate: bool = True,
+                  stream: Optional[torch.cuda.Stream] = None) -> SpgemmPlan:
+    """Structure analysis and symbolic product of C = A B (A: M x A.cols, B: A.cols x B.cols)."""
+    a = _csr_struct(*A, "A")
+    b = _csr_struct(*B, "B")
+    if A[0].numel() != M + 1 or B[0].numel() != int(A[3]) + 1:
+        raise ValueError("A needs M + 1 row pointers and B A.cols + 1")
+    h = ctypes.c_void_p()
+    check(lib().spgemm_create(int(M), ctypes.byref(a), ctypes.byref(b), 1 if validate else 0, _stream_ptr(stream),
+                              ctypes.byref(h)))
+    nnz = ctypes.c_int64()
+    prods = ctypes.c_int64()
+    check(lib().spgemm_info(h.value, ctypes.byref(nnz), ctypes.byref(prods)))
+    return SpgemmPlan(h.value, int(M), int(B[3]), nnz.value, prods.value, [A, B])
+
+
+def spgemm_rowptr(plan: SpgemmPlan, rowptrC: Optional[torch.Tensor] = None,
+                  stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    if rowptrC is None:
+        rowptrC = torch.empty(plan.M + 1, dtype=torch.int32, device=plan._keep[0][0].device)
+    check(lib().spgemm_rowptr(plan.handle, rowptrC.data_ptr(), _stream_ptr(stream)))
+    return rowptrC
+
+
+def spgemm_compute(plan: SpgemmPlan, colindC: Optional[torch.Tensor] = None, valuesC: Optional[torch.Tensor] = None,
+                   stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """C's column indices (sorted per row) and values, reading A's and B's values live."""
+    dev = plan._keep[0][0].device
+    if colindC is None:
+        colindC = torch.empty(max(plan.nnz_c, 1), dtype=torch.int32, device=dev)
+    if valuesC is None:
+        valuesC = torch.empty(max(plan.nnz_c, 1), dtype=torch.float32, device=dev)
+    if colindC.numel() < plan.nnz_c or valuesC.numel() < plan.nnz_c:
+        raise ValueError("outputs need nnz(C) = %d entries" % plan.nnz_c)
+    check(lib().spgemm_compute(plan.handle, colindC.data_ptr(), valuesC.data_ptr(), _stream_ptr(stream)))
+    return colindC[:plan.nnz_c], valuesC[:plan.nnz_c]

@@ -16,7 +16,7 @@ HEADER = os.path.join(ROOT, "include", "spmm.h")
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(spmm_[a-z0-9_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b((?:spmm|spgemm)_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -176,3 +176,19 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(name, "size")] == ctypes.sizeof(cls), name
         for field, _ in cls._fields_:
             assert got[(name, field)] == getattr(cls, field).offset, (name, field)
+
+
+def test_spgemm_argument_errors():
+    L = _lib.lib()
+    out = ctypes.c_void_p(7)
+    a = SpmmCsr(4, 0, None, None, None)
+    assert L.spgemm_create(4, None, None, 0, None, ctypes.byref(out)) == 1
+    assert L.spgemm_create(4, ctypes.byref(a), ctypes.byref(a), 0, None, None) == 1
+    assert L.spgemm_create(-1, ctypes.byref(a), ctypes.byref(a), 0, None, ctypes.byref(out)) == 1
+    assert L.spgemm_create(4, ctypes.byref(a), ctypes.byref(a), 0, None, ctypes.byref(out)) == 1  # rowptr null
+    big = SpmmCsr(4, 1 << 31, 8, 8, 8)
+    assert L.spgemm_create(4, ctypes.byref(big), ctypes.byref(a), 0, None, ctypes.byref(out)) == 3
+    assert L.spgemm_destroy(None) == 1
+    assert L.spgemm_info(None, None, None) == 1
+    assert L.spgemm_rowptr(None, None, None) == 1
+    assert L.spgemm_compute(None, None, None, None) == 1
