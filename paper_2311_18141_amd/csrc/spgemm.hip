@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(kBlock) sym_wave_kernel(SgOperands O, const in
     wave_products<false>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref[w], s_start[w], nullptr,
                          [&](int32_t col, float) {
                            uint32_t h = hash_slot(col, SHIFT);
-                           for (;;) {
+                           for (int probe = 0; probe < TS; ++probe) {  // the table is at most half full
                              const int32_t old = atomicCAS(&tab[h], -1, col);
                              if (old == -1) {
                                ++cnt;
@@ -321,12 +321,14 @@ __global__ void __launch_bounds__(kBlock) num_wave_kernel(SgOperands O, SgOut Co
     wave_products<true>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref[w], s_start[w], s_aval[w],
                         [&](int32_t col, float prod) {
                           uint32_t h = hash_slot(col, SHIFT);
-                          for (;;) {
+                          for (int probe = 0; probe < TS; ++probe) {  // at most half full
                             const int32_t old = atomicCAS(&key[h], -1, col);
-                            if (old == -1 || old == col) break;
+                            if (old == -1 || old == col) {
+                              atomicAdd(&val[h], prod);
+                              break;
+                            }
                             h = (h + 1) & (TS - 1);
                           }
-                          atomicAdd(&val[h], prod);
                         });
     for (int j = lane; j < TS; j += 64)
       if (key[j] < 0) key[j] = 0x7fffffff;  // empty slots sort last
@@ -365,12 +367,14 @@ __global__ void __launch_bounds__(kWG) num_block_kernel(SgOperands O, SgOut Co, 
     block_products<true>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref, s_start, s_aval, s_tmp,
                          [&](int32_t col, float prod) {
                            uint32_t h = hash_slot(col, shift);
-                           for (;;) {
+                           for (int probe = 0; probe < tg; ++probe) {  // at most half full
                              const int32_t old = atomicCAS(&key[h], -1, col);
-                             if (old == -1 || old == col) break;
+                             if (old == -1 || old == col) {
+                               atomicAdd(&val[h], prod);
+                               break;
+                             }
                              h = (h + 1) & (uint32_t)(tg - 1);
                            }
-                           atomicAdd(&val[h], prod);
                          });
     for (int j = tid; j < tg; j += kWG)
       if (key[j] < 0) key[j] = 0x7fffffff;
@@ -428,6 +432,7 @@ __global__ void __launch_bounds__(kWG) num_dense_kernel(SgOperands O, SgOut Co, 
     __threadfence();
     __syncthreads();
     int32_t out = Co.rowptrC[i];
+    const int32_t end = Co.rowptrC[i + 1];  // writes stay inside the row even if the counts disagreed
     for (int64_t w0 = 0; w0 < words; w0 += kWG) {
       const int64_t wi = w0 + tid;
       uint32_t word = 0;
@@ -439,8 +444,10 @@ __global__ void __launch_bounds__(kWG) num_dense_kernel(SgOperands O, SgOut Co, 
         const int b = __ffs(word) - 1;
         word &= word - 1;
         const int64_t col = wi * 32 + b;
-        Co.colC[pos] = (int32_t)col;
-        Co.valC[pos] = __hip_atomic_load(vals + col, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (pos < end) {
+          Co.colC[pos] = (int32_t)col;
+          Co.valC[pos] = __hip_atomic_load(vals + col, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         __hip_atomic_store(vals + col, 0.0f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ++pos;
       }

@@ -1,0 +1,193 @@
+"""Local SpGEMM C = A B on the GPU against the FP64 oracle: exact structure (row pointer and
+sorted column indices), FP32 values within the tolerance of the sum's scale (integer data:
+exact), every row class (wave hash sets and tables, workgroup bitmap and table, dense rows,
+the global bitmap for wide B) at and around its boundaries, live values, graph replay."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import compare
+from paper_2311_18141_amd import ops
+from paper_2311_18141_amd._lib import SpmmError
+
+import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _rng(s):
+    return np.random.Generator(np.random.PCG64(s))
+
+
+def _plan(A, B, validate=True):
+    dA = G.to_dev(A)
+    dB = G.to_dev(B)
+    return ops.spgemm_create(A.rows, dA, dB, validate=validate), dA, dB
+
+
+def _products_per_row(A, B):
+    lb = B.row_lengths()
+    rowid = np.repeat(np.arange(A.rows), A.row_lengths())
+    return np.bincount(rowid, weights=lb[A.colind], minlength=A.rows).astype(np.int64)
+
+
+def _check(A, B, exact=False, plan=None):
+    if plan is None:
+        plan, dA, dB = _plan(A, B)
+    rp = ops.spgemm_rowptr(plan)
+    ci, va = ops.spgemm_compute(plan)
+    torch.cuda.synchronize()
+    r_rp, r_ci, r_va, S = oracle.spgemm((A.rowptr, A.colind, A.values), (B.rowptr, B.colind, B.values), B.cols)
+    assert plan.nnz_c == int(r_rp[-1])
+    assert plan.products == int(_products_per_row(A, B).sum())
+    assert np.array_equal(rp.cpu().numpy().astype(np.int64), r_rp)
+    assert np.array_equal(ci.cpu().numpy().astype(np.int64), r_ci)
+    got = va.cpu().numpy().astype(np.float64)
+    if exact:
+        assert np.array_equal(got, r_va)
+    else:
+        n_terms = np.repeat(_products_per_row(A, B) + 1, np.diff(r_rp))
+        st = compare.fp32_stats(got, r_va, S, n_terms=n_terms)
+        assert compare.fp32_ok(st), st
+    return plan
+
+
+def _b_rows_of_lengths(lengths, cols, rng, kind="pm1"):
+    return synth.random_csr(len(lengths), cols, np.asarray(lengths), rng, kind)
+
+
+def _select_rows(K, picks, rng, kind="pm1"):
+    """A with row r holding the (sorted, distinct) B rows picks[r]."""
+    M = len(picks)
+    L = np.array([len(p) for p in picks])
+    rp = np.concatenate([[0], np.cumsum(L)]).astype(np.int32)
+    ci = np.concatenate([np.sort(np.asarray(p, dtype=np.int32)) for p in picks]) if L.sum() else np.zeros(0, np.int32)
+    A = synth.random_csr(M, K, L, rng, kind)
+    return synth.CSR(M, K, rp, ci.astype(np.int32), A.values)
+
+
+@pytest.mark.parametrize("M,K,N,d", [(1, 1, 1, 1.0), (5, 7, 3, 0.5), (200, 150, 300, 0.02), (1000, 1000, 1000, 0.01)])
+def test_spgemm_small_vs_oracle(M, K, N, d):
+    G.note("spgemm small M=%d K=%d N=%d" % (M, K, N))
+    rng = _rng(M + N)
+    A = synth.random_csr(M, K, rng.binomial(K, d, size=M), rng, "normal")
+    B = synth.random_csr(K, N, rng.binomial(N, d, size=K), rng, "normal")
+    _check(A, B)
+
+
+def test_spgemm_class_boundaries_integer_exact():
+    """Rows whose product and output counts sit on each side of every class boundary
+    (128, 256, 512 for the wave classes; the workgroup table's half size; dense rows)."""
+    G.note("spgemm class boundaries")
+    rng = _rng(11)
+    N = 30000
+    lengths = [0, 1, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1000, 4095, 4096, 4097, 8191, 8192, 8193,
+               12000, 20000]
+    B = _b_rows_of_lengths(lengths, N, rng, "int8")
+    K = B.rows
+    picks = [[k] for k in range(K)]                       # one B row each: products = output = length
+    picks += [list(range(K))]                             # everything: dense, high compression
+    picks += [[2, 3, 4], [9, 10], [13, 14, 15], [16, 17], [], [0], [18, 19]]
+    A = _select_rows(K, picks, rng, "int8")
+    _check(A, B, exact=True)
+
+
+def test_spgemm_wide_b_global_bitmap():
+    """B wide enough that a bitmap over its columns does not fit in LDS: the symbolic
+    pass uses the global per-workgroup bitmaps."""
+    G.note("spgemm wide B")
+    rng = _rng(12)
+    N = 3_000_000
+    B = _b_rows_of_lengths([600, 700, 2000, 40, 9000], N, rng, "int8")
+    A = _select_rows(B.rows, [[0], [1, 2], [0, 1, 2, 3, 4], [3], [4], []], rng, "int8")
+    _check(A, B, exact=True)
+
+
+def test_spgemm_rmat_aa():
+    """C = A A on a skewed R-MAT matrix: all classes at once."""
+    G.note("spgemm rmat14 A*A")
+    A = synth.rmat_csr(14, 8, seed=13)
+    _check(A, A)
+
+
+def test_spgemm_rmat_aa_integer_exact():
+    G.note("spgemm rmat13 A*A int")
+    rng = _rng(14)
+    A0 = synth.rmat_csr(13, 8, seed=14)
+    A = synth.CSR(A0.rows, A0.cols, A0.rowptr, A0.colind, rng.integers(-3, 4, size=A0.nnz).astype(np.float32))
+    _check(A, A, exact=True)
+
+
+def test_spgemm_cancellation_and_empty():
+    G.note("spgemm cancellation and empty")
+    A = synth.CSR(3, 2, np.array([0, 2, 2, 3], np.int32), np.array([0, 1, 1], np.int32),
+                  np.array([1, 1, 2], np.float32))
+    B = synth.CSR(2, 4, np.array([0, 2, 4], np.int32), np.array([1, 3, 1, 2], np.int32),
+                  np.array([1, 5, -1, 7], np.float32))
+    plan = _check(A, B, exact=True)
+    assert plan.nnz_c == 3 + 2  # row 0: cols 1 (1 - 1 = 0, kept), 2, 3; row 2: cols 1, 2
+    Z = synth.CSR(4, 2, np.zeros(5, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    plan, _, _ = _plan(Z, B)
+    assert plan.nnz_c == 0 and plan.products == 0
+    assert ops.spgemm_rowptr(plan).cpu().tolist() == [0] * 5
+    ops.spgemm_compute(plan)
+    torch.cuda.synchronize()
+
+
+def test_spgemm_values_read_live_and_repeat():
+    """The plan caches structure only: new values of A take effect; integer data repeats exactly."""
+    G.note("spgemm live values")
+    rng = _rng(15)
+    A = synth.random_csr(500, 400, rng.integers(0, 30, size=500), rng, "int8")
+    B = synth.random_csr(400, 600, rng.integers(0, 30, size=400), rng, "int8")
+    plan, dA, dB = _plan(A, B)
+    ci1, va1 = ops.spgemm_compute(plan)
+    ci1, va1 = ci1.clone(), va1.clone()
+    ci2, va2 = ops.spgemm_compute(plan)
+    torch.cuda.synchronize()
+    assert torch.equal(ci1, ci2) and torch.equal(va1, va2)
+    dA[2].mul_(-2.0)
+    A2 = synth.CSR(A.rows, A.cols, A.rowptr, A.colind, (A.values * -2.0).astype(np.float32))
+    _check(A2, B, exact=True, plan=plan)
+
+
+def test_spgemm_graph_replay():
+    G.note("spgemm graph replay")
+    rng = _rng(16)
+    A = synth.random_csr(3000, 2000, rng.integers(0, 40, size=3000), rng, "int8")
+    B = synth.random_csr(2000, 5000, rng.integers(0, 40, size=2000), rng, "int8")
+    plan, dA, dB = _plan(A, B)
+    ci = torch.empty(plan.nnz_c, dtype=torch.int32, device=G.DEV)
+    va = torch.empty(plan.nnz_c, dtype=torch.float32, device=G.DEV)
+    ops.spgemm_compute(plan, ci, va)
+    torch.cuda.synchronize()
+    ref_ci, ref_va = ci.clone(), va.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ops.spgemm_compute(plan, ci, va)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ops.spgemm_compute(plan, ci, va)
+    for r in range(4):
+        ci.fill_(-1)
+        va.fill_(float("nan"))
+        _ = (dA[2] * 3).sum()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(ci, ref_ci) and torch.equal(va, ref_va), r
+
+
+def test_spgemm_rejects_bad_csr():
+    G.note("spgemm bad csr")
+    rng = _rng(17)
+    A = synth.random_csr(10, 10, np.full(10, 3), rng)
+    bad = synth.CSR(A.rows, A.cols, A.rowptr, A.colind.copy(), A.values)
+    bad.colind[4] = 99
+    with pytest.raises(SpmmError):
+        _plan(bad, A)
+    with pytest.raises(SpmmError):
+        _plan(A, bad)
