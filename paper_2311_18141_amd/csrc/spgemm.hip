@@ -273,15 +273,15 @@ struct SgOut {
   float* valC;
 };
 
-// Sort TS (key, value) pairs by key with bitonic merges; `lanes` threads starting at
-// thread `t0` take part; sync() orders the stages.
-template <int TS, typename Sync>
-__device__ __forceinline__ void bitonic_sort(int32_t* key, float* val, int t0, int lanes, Sync&& sync) {
-  for (int k = 2; k <= TS; k <<= 1) {
+// Sort the first P (a power of two) (key, value) pairs by key with bitonic merges;
+// `lanes` threads starting at thread `t0` take part; sync() orders the stages.
+template <typename Sync>
+__device__ __forceinline__ void bitonic_sort(int32_t* key, float* val, int P, int t0, int lanes, Sync&& sync) {
+  for (int k = 2; k <= P; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = t0; t < TS / 2; t += lanes) {
-        // t-th pair of this stage: lower index a, partner a + j
-        const int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));  // j is a power of two
+      for (int t = t0; t < P / 2; t += lanes) {
+        // t-th pair of this stage: lower index a, partner a + j (j is a power of two)
+        const int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));
         const int b = a + j;
         const bool up = (a & k) == 0;
         const int32_t ka = key[a], kb = key[b];
@@ -296,6 +296,12 @@ __device__ __forceinline__ void bitonic_sort(int32_t* key, float* val, int t0, i
       sync();
     }
   }
+}
+
+__device__ __forceinline__ int pow2_at_least(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
 }
 
 // Rows with at most TS/2 output entries: a wave-local hash table of (column, sum).
@@ -330,11 +336,29 @@ __global__ void __launch_bounds__(kBlock) num_wave_kernel(SgOperands O, SgOut Co
                             h = (h + 1) & (TS - 1);
                           }
                         });
-    for (int j = lane; j < TS; j += 64)
-      if (key[j] < 0) key[j] = 0x7fffffff;  // empty slots sort last
+    // Move the occupied slots to the front, in place, 64 slots at a time (each chunk is
+    // read before it is written, and lands at or below its own slots), then sort only
+    // the smallest power of two that holds them.
+    int n = 0;
+    for (int c0 = 0; c0 < TS; c0 += 64) {
+      const int32_t k = key[c0 + lane];
+      const float v = val[c0 + lane];
+      const bool occ = k >= 0;
+      const uint64_t m = __ballot(occ);
+      const int pos = n + __popcll(m & ((1ull << lane) - 1));
+      wave_sync_lds();
+      if (occ) {
+        key[pos] = k;
+        val[pos] = v;
+      }
+      n += __popcll(m);
+      wave_sync_lds();
+    }
+    const int P = pow2_at_least(n);
+    for (int j = n + lane; j < P; j += 64) key[j] = 0x7fffffff;  // padding sorts last
     wave_sync_lds();
-    bitonic_sort<TS>(key, val, lane, 64, [] { wave_sync_lds(); });
-    const int32_t base = Co.rowptrC[i], cnt = Co.rowptrC[i + 1] - base;
+    bitonic_sort(key, val, P, lane, 64, [] { wave_sync_lds(); });
+    const int32_t base = Co.rowptrC[i], cnt = min(Co.rowptrC[i + 1] - base, n);
     for (int j = lane; j < cnt; j += 64) {
       Co.colC[base + j] = key[j];
       Co.valC[base + j] = val[j];
@@ -376,29 +400,32 @@ __global__ void __launch_bounds__(kWG) num_block_kernel(SgOperands O, SgOut Co, 
                              h = (h + 1) & (uint32_t)(tg - 1);
                            }
                          });
-    for (int j = tid; j < tg; j += kWG)
-      if (key[j] < 0) key[j] = 0x7fffffff;
-    __syncthreads();
-    // bitonic sort over tg slots (tg is a template-free runtime power of two)
-    for (int k = 2; k <= tg; k <<= 1) {
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int t = tid; t < tg / 2; t += kWG) {
-          const int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));  // j is a power of two
-          const int b = a + j;
-          const bool up = (a & k) == 0;
-          const int32_t ka = key[a], kb = key[b];
-          if ((ka > kb) == up) {
-            key[a] = kb;
-            key[b] = ka;
-            const float va = val[a];
-            val[a] = val[b];
-            val[b] = va;
-          }
-        }
-        __syncthreads();
+    // compact the occupied slots to the front (chunks of kWG, read before written), then
+    // sort the smallest power of two that holds them
+    int n = 0;
+    for (int c0 = 0; c0 < tg; c0 += kWG) {
+      const int j = c0 + tid;
+      int32_t k = -1;
+      float v = 0.0f;
+      if (j < tg) {
+        k = key[j];
+        v = val[j];
       }
+      const int occ = k >= 0 ? 1 : 0;
+      int32_t excl;
+      const int32_t tot = block_scan(occ, &excl, s_tmp);  // synchronises: all reads are done
+      if (occ) {
+        key[n + excl] = k;
+        val[n + excl] = v;
+      }
+      n += tot;
+      __syncthreads();
     }
-    const int32_t base = Co.rowptrC[i], cnt = Co.rowptrC[i + 1] - base;
+    const int P = pow2_at_least(n);
+    for (int j = n + tid; j < P; j += kWG) key[j] = 0x7fffffff;
+    __syncthreads();
+    bitonic_sort(key, val, P, tid, kWG, [] { __syncthreads(); });
+    const int32_t base = Co.rowptrC[i], cnt = min(Co.rowptrC[i + 1] - base, n);
     for (int j = tid; j < cnt; j += kWG) {
       Co.colC[base + j] = key[j];
       Co.valC[base + j] = val[j];
