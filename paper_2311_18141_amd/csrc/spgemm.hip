@@ -143,11 +143,23 @@ __device__ __forceinline__ int32_t block_scan(int32_t v, int32_t* excl, int32_t*
   return total;
 }
 
-// Visit the products of A entries [a0, a1) with the whole workgroup: f(col, a * b).
-// LDS: s_pref[kWG + 1], s_start[kWG], s_aval[kWG], s_tmp[kWGWaves].
-template <bool VALS, typename F>
+// First position in colB[lo, hi) whose column is >= x (colB is sorted within a row).
+__device__ __forceinline__ int32_t lower_bound(const int32_t* colB, int32_t lo, int32_t hi, int32_t x) {
+  while (lo < hi) {
+    const int32_t mid = lo + ((hi - lo) >> 1);
+    if (colB[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Visit the products of A entries [a0, a1) with the whole workgroup: f(col, a * b);
+// with WIN, only the products whose column lies in [c0, c1) (found by binary search
+// in each sorted B row).  LDS: s_pref[kWG + 1], s_start[kWG], s_aval[kWG], s_tmp[kWGWaves].
+template <bool VALS, bool WIN, typename F>
 __device__ __forceinline__ void block_products(const SgOperands& O, int32_t a0, int32_t a1, int32_t* s_pref,
-                                               int32_t* s_start, float* s_aval, int32_t* s_tmp, F&& f) {
+                                               int32_t* s_start, float* s_aval, int32_t* s_tmp, F&& f,
+                                               int32_t c0 = 0, int32_t c1 = 0) {
   const int tid = threadIdx.x;
   for (int32_t c = a0; c < a1; c += kWG) {
     const int n = min(kWG, a1 - c);
@@ -156,7 +168,12 @@ __device__ __forceinline__ void block_products(const SgOperands& O, int32_t a0, 
     if (tid < n) {
       const int32_t k = O.colA[c + tid];
       st = O.rowptrB[k];
-      len = O.rowptrB[k + 1] - st;
+      int32_t en = O.rowptrB[k + 1];
+      if constexpr (WIN) {
+        st = lower_bound(O.colB, st, en, c0);
+        en = lower_bound(O.colB, st, en, c1);
+      }
+      len = en - st;
       if constexpr (VALS) av = O.valA[c + tid];
     }
     int32_t excl;
@@ -215,53 +232,72 @@ __global__ void __launch_bounds__(kBlock) sym_wave_kernel(SgOperands O, const in
 
 // Other rows: one workgroup per row, a bitmap over the N output columns (LDS when
 // `words` fit, else the workgroup's global slot), counting bits as they turn on.
+// With wcnt, also the entries per column window of 2^(win_words_log2 + 5) columns:
+// wcnt[r * n_win + w] for the r-th row of the list (they place long rows' windows).
 template <bool GLOBAL>
 __global__ void __launch_bounds__(kWG) sym_bitmap_kernel(SgOperands O, const int32_t* rows, int64_t n_rows,
-                                                         int32_t* nnz_row, uint32_t* gbits, int64_t slot_words) {
+                                                         int32_t* nnz_row, uint32_t* gbits, int64_t slot_words,
+                                                         int32_t* wcnt, int n_win, int win_words_log2) {
   extern __shared__ int32_t s_dyn[];
   int32_t* s_pref = s_dyn;
   int32_t* s_start = s_pref + kWG + 1;
   int32_t* s_tmp = s_start + kWG;
   int32_t* s_cnt = s_tmp + kWGWaves;
+  int32_t* s_wc = s_cnt + kWGWaves;  // n_win counters when wcnt is given
   uint32_t* bits = GLOBAL ? gbits + (int64_t)blockIdx.x * slot_words
-                          : reinterpret_cast<uint32_t*>(s_cnt + kWGWaves);
+                          : reinterpret_cast<uint32_t*>(s_wc + (wcnt ? n_win : 0));
   const int64_t words = (O.N + 31) / 32;
   const int tid = threadIdx.x;
   if constexpr (!GLOBAL) {
     for (int64_t j = tid; j < words; j += kWG) bits[j] = 0u;
   }
+  if (wcnt)
+    for (int w = tid; w < n_win; w += kWG) s_wc[w] = 0;
   __syncthreads();
   for (int64_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
     const int32_t i = rows[r];
     int cnt = 0;
-    block_products<false>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref, s_start, nullptr, s_tmp,
-                          [&](int32_t col, float) {
-                            const uint32_t bit = 1u << (col & 31);
-                            uint32_t old;
-                            if constexpr (GLOBAL)
-                              old = __hip_atomic_fetch_or(bits + (col >> 5), bit, __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_WORKGROUP);
-                            else
-                              old = atomicOr(bits + (col >> 5), bit);
-                            if (!(old & bit)) ++cnt;
-                          });
+    block_products<false, false>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref, s_start, nullptr, s_tmp,
+                                 [&](int32_t col, float) {
+                                   const uint32_t bit = 1u << (col & 31);
+                                   uint32_t old;
+                                   if constexpr (GLOBAL)
+                                     old = __hip_atomic_fetch_or(bits + (col >> 5), bit, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+                                   else
+                                     old = atomicOr(bits + (col >> 5), bit);
+                                   if (!(old & bit)) ++cnt;
+                                 });
     cnt = wave_sum(cnt);
     if ((tid & 63) == 0) s_cnt[tid >> 6] = cnt;
+    if constexpr (GLOBAL) __threadfence();
     __syncthreads();
     if (tid == 0) {
       int total = 0;
       for (int u = 0; u < kWGWaves; ++u) total += s_cnt[u];
       nnz_row[i] = total;
     }
-    // clear for the next row
+    // window counts, and clear for the next row
     for (int64_t j = tid; j < words; j += kWG) {
-      if constexpr (GLOBAL)
+      uint32_t word;
+      if constexpr (GLOBAL) {
+        word = __hip_atomic_load(bits + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(bits + j, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      else
+      } else {
+        word = bits[j];
         bits[j] = 0u;
+      }
+      if (wcnt && word) atomicAdd(&s_wc[j >> win_words_log2], __popc(word));
     }
     if constexpr (GLOBAL) __threadfence();
     __syncthreads();
+    if (wcnt) {
+      for (int w = tid; w < n_win; w += kWG) {
+        wcnt[r * n_win + w] = s_wc[w];
+        s_wc[w] = 0;
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -372,23 +408,28 @@ __global__ void __launch_bounds__(kBlock) num_wave_kernel(SgOperands O, SgOut Co
 __global__ void __launch_bounds__(kWG) num_block_kernel(SgOperands O, SgOut Co, const int32_t* rows,
                                                         int64_t n_rows, int tg_log2) {
   extern __shared__ int32_t s_dyn[];
-  const int tg = 1 << tg_log2;
-  const int shift = 32 - tg_log2;
+  const int tg_max = 1 << tg_log2;
   int32_t* key = s_dyn;
-  float* val = reinterpret_cast<float*>(key + tg);
-  int32_t* s_pref = reinterpret_cast<int32_t*>(val + tg);
+  float* val = reinterpret_cast<float*>(key + tg_max);
+  int32_t* s_pref = reinterpret_cast<int32_t*>(val + tg_max);
   int32_t* s_start = s_pref + kWG + 1;
   float* s_aval = reinterpret_cast<float*>(s_start + kWG);
   int32_t* s_tmp = reinterpret_cast<int32_t*>(s_aval + kWG);
   const int tid = threadIdx.x;
   for (int64_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
     const int32_t i = rows[r];
+    // this row's table: a power of two of at least twice its entries (>= kWG)
+    const int32_t nrow = Co.rowptrC[i + 1] - Co.rowptrC[i];
+    int tl = tg_log2 < 10 ? tg_log2 : 10;
+    while (tl < tg_log2 && (1 << tl) < 2 * nrow) ++tl;
+    const int tg = 1 << tl;
+    const int shift = 32 - tl;
     for (int j = tid; j < tg; j += kWG) {
       key[j] = -1;
       val[j] = 0.0f;
     }
     __syncthreads();
-    block_products<true>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref, s_start, s_aval, s_tmp,
+    block_products<true, false>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref, s_start, s_aval, s_tmp,
                          [&](int32_t col, float prod) {
                            uint32_t h = hash_slot(col, shift);
                            for (int probe = 0; probe < tg; ++probe) {  // at most half full
@@ -434,6 +475,66 @@ __global__ void __launch_bounds__(kWG) num_block_kernel(SgOperands O, SgOut Co, 
   }
 }
 
+// Long rows, one (row, column window) item per workgroup at a time: the window's
+// 2^win_log2 sums and its bitmap live in LDS (zeroed once, and cleared entry by
+// entry as the compaction reads them), products accumulate with LDS atomics, and
+// the bitmap walk writes the window's entries in column order at the item's offset.
+struct SgItem {
+  int32_t row, win, out, cnt;
+};
+
+__global__ void __launch_bounds__(kWG) num_window_kernel(SgOperands O, SgOut Co, const SgItem* items,
+                                                         int64_t n_items, int win_log2) {
+  extern __shared__ int32_t s_dyn[];
+  const int W = 1 << win_log2;
+  const int ww = W >> 5;
+  float* acc = reinterpret_cast<float*>(s_dyn);
+  uint32_t* bits = reinterpret_cast<uint32_t*>(acc + W);
+  int32_t* s_pref = reinterpret_cast<int32_t*>(bits + ww);
+  int32_t* s_start = s_pref + kWG + 1;
+  float* s_aval = reinterpret_cast<float*>(s_start + kWG);
+  int32_t* s_tmp = reinterpret_cast<int32_t*>(s_aval + kWG);
+  const int tid = threadIdx.x;
+  for (int j = tid; j < W; j += kWG) acc[j] = 0.0f;
+  for (int j = tid; j < ww; j += kWG) bits[j] = 0u;
+  __syncthreads();
+  for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const SgItem item = items[it];
+    const int32_t c0 = item.win << win_log2;
+    const int32_t c1 = (int32_t)min((int64_t)c0 + W, O.N);
+    block_products<true, true>(O, O.rowptrA[item.row], O.rowptrA[item.row + 1], s_pref, s_start, s_aval, s_tmp,
+                               [&](int32_t col, float prod) {
+                                 const int32_t x = col - c0;
+                                 atomicOr(bits + (x >> 5), 1u << (x & 31));
+                                 atomicAdd(acc + x, prod);
+                               },
+                               c0, c1);
+    int32_t out = item.out;
+    const int32_t end = item.out + item.cnt;
+    for (int w0 = 0; w0 < ww; w0 += kWG) {
+      const int wi = w0 + tid;
+      uint32_t word = wi < ww ? bits[wi] : 0u;
+      int32_t excl;
+      const int32_t tot = block_scan(__popc(word), &excl, s_tmp);
+      int32_t pos = out + excl;
+      while (word) {
+        const int b = __ffs(word) - 1;
+        word &= word - 1;
+        const int x = wi * 32 + b;
+        if (pos < end) {
+          Co.colC[pos] = c0 + x;
+          Co.valC[pos] = acc[x];
+        }
+        acc[x] = 0.0f;
+        ++pos;
+      }
+      if (wi < ww) bits[wi] = 0u;
+      out += tot;
+    }
+    __syncthreads();
+  }
+}
+
 // Long rows: workgroup b owns slot b (N floats + a bitmap of N bits, all zero
 // between rows) and takes rows b, b + grid, ...; products accumulate with
 // workgroup-scope atomics (only this workgroup touches the slot), then the bitmap is
@@ -450,7 +551,7 @@ __global__ void __launch_bounds__(kWG) num_dense_kernel(SgOperands O, SgOut Co, 
   const int tid = threadIdx.x;
   for (int64_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
     const int32_t i = rows[r];
-    block_products<true>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref, s_start, s_aval, s_tmp,
+    block_products<true, false>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref, s_start, s_aval, s_tmp,
                          [&](int32_t col, float prod) {
                            __hip_atomic_fetch_or(bits + (col >> 5), 1u << (col & 31), __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -490,6 +591,7 @@ __global__ void __launch_bounds__(kWG) num_dense_kernel(SgOperands O, SgOut Co, 
 // the dense slots.  Symbolic classes: wave sets of 256 / 512 / 1024 slots, bitmap.
 constexpr int kNumClasses = 5;
 constexpr int kSymClasses = 4;
+constexpr int kMaxWindows = 4096;   // column windows per long row (else the dense slots)
 
 int64_t grid_for(int64_t items, int64_t per_block) {
   return std::max<int64_t>(1, std::min<int64_t>((items + per_block - 1) / per_block, kMaxGridBlocks));
@@ -515,9 +617,14 @@ struct spgemm_s {
   uint32_t* slot_bits = nullptr;
   int64_t slot_words = 0;
   int n_slots = 0;
+  int win_log2 = 0;             // long rows by column windows of 2^win_log2 (0: dense slots)
+  size_t lds_window = 0;        // the window kernel's dynamic LDS bytes
+  spmm::SgItem* items = nullptr;  // device: (row, window, offset, count) of the long rows
+  int64_t n_items = 0;
   ~spgemm_s() {
     if (rowptrC) (void)hipFree(rowptrC);
     if (rows) (void)hipFree(rows);
+    if (items) (void)hipFree(items);
     if (slot_vals) (void)hipFree(slot_vals);
     if (slot_bits) (void)hipFree(slot_bits);
   }
@@ -656,6 +763,7 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
           if (c >= 0) list[(size_t)pos[c]++] = (int32_t)i;
         }
       }
+      const std::vector<int32_t> list_sym(list);
       if (M > 0) {
         SG_TRY(hipMemsetAsync(d_nnz, 0, sizeof(int32_t) * (size_t)M, s));
         SG_TRY(hipMemcpyAsync(d_rows, list.data(), sizeof(int32_t) * (size_t)M, hipMemcpyHostToDevice, s));
@@ -667,22 +775,55 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
       if (cnt[2]) hipLaunchKernelGGL(spmm::sym_wave_kernel<1024>, dim3((unsigned)spmm::grid_for(cnt[2], 4)),
                                      dim3(spmm::kBlock), 0, s, O, d_rows + off[2], cnt[2], d_nnz);
       SG_TRY(hipGetLastError());
+      // Column windows for the long rows: the largest power of two (at most 32K columns)
+      // whose sums and bitmap fit in LDS next to the product scratch; window counts
+      // come from the symbolic bitmap pass when there are at most kMaxWindows windows.
+      {
+        int wl = 10;
+        while (wl < 15 && kBlockFixedLds + (size_t)4 * (((size_t)1 << (wl + 1)) + ((size_t)1 << (wl - 4))) <=
+                              (size_t)lds_max)
+          ++wl;
+        const int64_t n_win = (h->N + ((int64_t)1 << wl) - 1) >> wl;
+        h->win_log2 = (n_win <= spmm::kMaxWindows && h->N > 0) ? wl : 0;
+        h->lds_window = kBlockFixedLds + (size_t)4 * (((size_t)1 << wl) + ((size_t)1 << (wl - 5)));
+      }
+      const int n_win = h->win_log2 ? (int)((h->N + ((int64_t)1 << h->win_log2) - 1) >> h->win_log2) : 0;
+      std::vector<int32_t> wc;
+      int32_t* d_wc = nullptr;
       if (cnt[3]) {
         const int64_t words = (h->N + 31) / 32;
-        const size_t lds = kBlockFixedLds + sizeof(uint32_t) * (size_t)words;
+        if (n_win) {
+          if (dmalloc(&d_wc, cnt[3] * (int64_t)n_win) != hipSuccess)
+            return spmm::set_error(SPMM_ERR_ALLOC, "device allocation of window counts failed");
+        }
+        const size_t lds_fixed = kBlockFixedLds + sizeof(int32_t) * (size_t)n_win;
+        const size_t lds = lds_fixed + sizeof(uint32_t) * (size_t)words;
+        const int wwl = h->win_log2 ? h->win_log2 - 5 : 0;
         if (lds <= (size_t)lds_max) {
           (void)hipFuncSetAttribute(reinterpret_cast<const void*>(spmm::sym_bitmap_kernel<false>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
           const int64_t grid = std::min<int64_t>(cnt[3], (int64_t)cus * 8);
           hipLaunchKernelGGL(spmm::sym_bitmap_kernel<false>, dim3((unsigned)grid), dim3(spmm::kWG), lds, s, O,
-                             d_rows + off[3], cnt[3], d_nnz, (uint32_t*)nullptr, (int64_t)0);
+                             d_rows + off[3], cnt[3], d_nnz, (uint32_t*)nullptr, (int64_t)0, d_wc, n_win, wwl);
         } else {
           const spmm_status st = ensure_slots(h, slot_count(h, cnt[3], cus), s);
-          if (st != SPMM_OK) return st;
-          hipLaunchKernelGGL(spmm::sym_bitmap_kernel<true>, dim3((unsigned)h->n_slots), dim3(spmm::kWG),
-                             kBlockFixedLds, s, O, d_rows + off[3], cnt[3], d_nnz, h->slot_bits, h->slot_words);
+          if (st != SPMM_OK) {
+            if (d_wc) (void)hipFree(d_wc);
+            return st;
+          }
+          (void)hipFuncSetAttribute(reinterpret_cast<const void*>(spmm::sym_bitmap_kernel<true>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_fixed);
+          hipLaunchKernelGGL(spmm::sym_bitmap_kernel<true>, dim3((unsigned)h->n_slots), dim3(spmm::kWG), lds_fixed,
+                             s, O, d_rows + off[3], cnt[3], d_nnz, h->slot_bits, h->slot_words, d_wc, n_win, wwl);
         }
-        SG_TRY(hipGetLastError());
+        hipError_t le = hipGetLastError();
+        if (le == hipSuccess && d_wc) {
+          wc.resize((size_t)cnt[3] * (size_t)n_win);
+          le = hipMemcpyAsync(wc.data(), d_wc, sizeof(int32_t) * wc.size(), hipMemcpyDeviceToHost, s);
+          if (le == hipSuccess) le = hipStreamSynchronize(s);
+        }
+        if (d_wc) (void)hipFree(d_wc);
+        SG_TRY(le);
       }
       if (M > 0) {
         SG_TRY(hipMemcpyAsync(nz.data(), d_nnz, sizeof(int32_t) * (size_t)M, hipMemcpyDeviceToHost, s));
@@ -727,7 +868,33 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
         SG_TRY(hipMemcpyAsync(h->rows, list.data(), sizeof(int32_t) * (size_t)M, hipMemcpyHostToDevice, s));
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(spmm::num_block_kernel),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_block);
-      if (h->cls_cnt[4]) {
+      if (h->cls_cnt[4] && h->win_log2) {
+        // (row, window) items of the long rows, with their output offsets, largest first
+        std::vector<int64_t> bitmap_index((size_t)M, -1);
+        for (int64_t r = 0; r < cnt[3]; ++r) bitmap_index[(size_t)list_sym[(size_t)(off[3] + r)]] = r;
+        std::vector<spmm::SgItem> items;
+        for (int64_t t = 0; t < h->cls_cnt[4]; ++t) {
+          const int32_t i = list[(size_t)(h->cls_off[4] + t)];
+          const int64_t r = bitmap_index[(size_t)i];
+          if (r < 0) return spmm::set_error(SPMM_ERR_HIP, "internal: long row %d has no window counts", i);
+          int32_t out = rp[(size_t)i];
+          for (int w = 0; w < n_win; ++w) {
+            const int32_t c = wc[(size_t)r * n_win + w];
+            if (c > 0) items.push_back(spmm::SgItem{i, w, out, c});
+            out += c;
+          }
+          if (out != rp[(size_t)i + 1]) return spmm::set_error(SPMM_ERR_HIP, "internal: window counts of row %d", i);
+        }
+        std::stable_sort(items.begin(), items.end(),
+                         [](const spmm::SgItem& x, const spmm::SgItem& y) { return x.cnt > y.cnt; });
+        h->n_items = (int64_t)items.size();
+        if (dmalloc(&h->items, h->n_items) != hipSuccess)
+          return spmm::set_error(SPMM_ERR_ALLOC, "device allocation of the window items failed");
+        if (h->n_items)
+          SG_TRY(hipMemcpyAsync(h->items, items.data(), sizeof(spmm::SgItem) * items.size(), hipMemcpyHostToDevice, s));
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(spmm::num_window_kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_window);
+      } else if (h->cls_cnt[4]) {
         const spmm_status st = ensure_slots(h, slot_count(h, h->cls_cnt[4], cus), s);
         if (st != SPMM_OK) return st;
       }
@@ -793,7 +960,16 @@ spmm_status spgemm_compute(spgemm_t plan, int32_t* colindC, float* valuesC, void
                        rows + off[3], cnt[3], plan->tg_log2);
     SG_TRY(hipGetLastError());
   }
-  if (cnt[4]) {
+  if (cnt[4] && plan->win_log2) {
+    if (plan->n_items) {
+      int cus = 0;
+      SG_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+      const int64_t grid = std::min<int64_t>(plan->n_items, (int64_t)cus * 2);
+      hipLaunchKernelGGL(spmm::num_window_kernel, dim3((unsigned)grid), dim3(spmm::kWG), plan->lds_window, s, O, Co,
+                         plan->items, plan->n_items, plan->win_log2);
+      SG_TRY(hipGetLastError());
+    }
+  } else if (cnt[4]) {
     hipLaunchKernelGGL(spmm::num_dense_kernel, dim3((unsigned)plan->n_slots), dim3(spmm::kWG), 0, s, O, Co,
                        rows + off[4], cnt[4], plan->slot_vals, plan->slot_bits, plan->slot_words);
     SG_TRY(hipGetLastError());

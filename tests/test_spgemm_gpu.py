@@ -33,13 +33,24 @@ def _products_per_row(A, B):
     return np.bincount(rowid, weights=lb[A.colind], minlength=A.rows).astype(np.int64)
 
 
-def _check(A, B, exact=False, plan=None):
+def _oracle(A, B, compress_cols=False):
+    if not compress_cols:
+        return oracle.spgemm((A.rowptr, A.colind, A.values), (B.rowptr, B.colind, B.values), B.cols)
+    # B's used columns, in order, renumbered 0..u-1: an order-preserving bijection, so the
+    # oracle on the compressed problem gives C's entries in the same order
+    used = np.unique(B.colind)
+    cB = np.searchsorted(used, B.colind).astype(np.int32)
+    rp, ci, va, S = oracle.spgemm((A.rowptr, A.colind, A.values), (B.rowptr, cB, B.values), max(len(used), 1))
+    return rp, used[ci].astype(np.int64), va, S
+
+
+def _check(A, B, exact=False, plan=None, compress_cols=False):
     if plan is None:
         plan, dA, dB = _plan(A, B)
     rp = ops.spgemm_rowptr(plan)
     ci, va = ops.spgemm_compute(plan)
     torch.cuda.synchronize()
-    r_rp, r_ci, r_va, S = oracle.spgemm((A.rowptr, A.colind, A.values), (B.rowptr, B.colind, B.values), B.cols)
+    r_rp, r_ci, r_va, S = _oracle(A, B, compress_cols)
     assert plan.nnz_c == int(r_rp[-1])
     assert plan.products == int(_products_per_row(A, B).sum())
     assert np.array_equal(rp.cpu().numpy().astype(np.int64), r_rp)
@@ -102,7 +113,7 @@ def test_spgemm_wide_b_global_bitmap():
     N = 3_000_000
     B = _b_rows_of_lengths([600, 700, 2000, 40, 9000], N, rng, "int8")
     A = _select_rows(B.rows, [[0], [1, 2], [0, 1, 2, 3, 4], [3], [4], []], rng, "int8")
-    _check(A, B, exact=True)
+    _check(A, B, exact=True, compress_cols=True)
 
 
 def test_spgemm_rmat_aa():
@@ -191,3 +202,14 @@ def test_spgemm_rejects_bad_csr():
         _plan(bad, A)
     with pytest.raises(SpmmError):
         _plan(A, bad)
+
+
+def test_spgemm_very_wide_b_dense_slots():
+    """B so wide (about 201M columns) that long rows cannot be cut into column windows:
+    they accumulate in dense global rows (values + bitmap) instead."""
+    G.note("spgemm very wide B (dense slots)")
+    rng = _rng(18)
+    N = (1 << 27) + (1 << 26)
+    B = _b_rows_of_lengths([5000, 6000, 700, 20], N, rng, "int8")
+    A = _select_rows(B.rows, [[0, 1], [2], [0, 1, 2, 3], [3], []], rng, "int8")
+    _check(A, B, exact=True, compress_cols=True)
