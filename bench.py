@@ -14,6 +14,9 @@ times dense B_k of 1,048,576 x 128 FP32, accumulated over its 4 k-tiles into a
                             forward + dA (sampled dense-dense product) + dB = A^T dC
     rmat23_n256_bf16        R-MAT scale 23, edge factor 32, N = 256, BF16 B and C
     rmat23_n256_f32         the same with FP32 B and C
+    spgemm_rmat18_ef16_aa   local SpGEMM C = A A, R-MAT scale 18, edge factor 16 (numeric phase;
+                            the symbolic phase is reported beside it)
+    spgemm_er1m16_aa        local SpGEMM C = A A, 1,048,576^2 uniform, 16 per row
     uneven512_batched       512 uneven tiles (rows 1,024..65,536, 4..256 non-zeros per row,
                             N_t in {32..256}) in one batched launch, per-tile autotuned
                             variants; the per-tile launch loop and the persistent (claim
@@ -133,10 +136,14 @@ def _threads():
 
 
 # ---------------------------------------------------------------------------
+METRIC = "SpMM GFLOP/s (2*nnz*N) and % HBM roofline, fwd+bwd, BF16/batched vs FP32"
+
+
 class Workload:
     name = ""
     dtype = "f32"
     kernel = ""
+    metric = METRIC
 
     def setup(self):  # build device inputs and handles
         raise NotImplementedError
@@ -400,6 +407,67 @@ class Batched(Workload):
         return flops, t_total, "oracle FP64 forward on the first %d of %d tiles" % (used, self.count)
 
 
+class SpgemmAA(Workload):
+    """Local SpGEMM C = A A (the local step of the paper's SpGEMM experiments).  A step is the
+    numeric phase (spgemm_compute); the symbolic phase (plan creation) is timed beside it."""
+
+    metric = "SpGEMM GFLOP/s (2 * products) and % HBM roofline"
+
+    def __init__(self, name, make, config):
+        self.name = name
+        self.make = make
+        self.config = config
+        self.kernel = "spgemm_compute (num_wave / num_block / num_window)"
+
+    def setup(self):
+        import torch
+        from paper_2311_18141_amd import ops
+        t0 = time.time()
+        self.A = self.make()
+        A = self.A
+        _log("%s: inputs generated in %.1f s (nnz %d)" % (self.name, time.time() - t0, A.nnz))
+        dev = "cuda:0"
+        self.d = (torch.from_numpy(A.rowptr).to(dev), torch.from_numpy(A.colind).to(dev),
+                  torch.from_numpy(A.values).to(dev), A.cols)
+        torch.cuda.synchronize()
+        ops.spgemm_create(A.rows, self.d, self.d, validate=True)  # first call: code objects, allocator
+        torch.cuda.synchronize()
+        reps = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            plan = ops.spgemm_create(A.rows, self.d, self.d, validate=False)
+            torch.cuda.synchronize()
+            reps.append((time.perf_counter() - t0) * 1e3)
+            if _ < 2:
+                del plan
+        self.plan = plan
+        self.symbolic_ms = min(reps)
+        self.ci = torch.empty(max(plan.nnz_c, 1), dtype=torch.int32, device=dev)
+        self.va = torch.empty(max(plan.nnz_c, 1), dtype=torch.float32, device=dev)
+        self.flops = 2.0 * plan.products
+        M = A.rows
+        self.alg_bytes = float(2 * (8 * A.nnz + 4 * (M + 1)) + 8 * plan.nnz_c + 4 * (M + 1))
+        self.config = dict(self.config, rows=M, nnz=A.nnz, products=plan.products, nnz_c=plan.nnz_c,
+                           compression=round(plan.products / max(plan.nnz_c, 1), 3),
+                           symbolic_ms=round(self.symbolic_ms, 3))
+
+    def step(self):
+        from paper_2311_18141_amd import ops
+        ops.spgemm_compute(self.plan, self.ci, self.va)
+
+    def cpu_sample(self):
+        import oracle
+        A = self.A
+        L = A.row_lengths()
+        fl = np.bincount(np.repeat(np.arange(A.rows), L), weights=L[A.colind], minlength=A.rows)
+        r = int(min(A.rows, np.searchsorted(np.cumsum(fl), 1.0e9) + 1))
+        rows = np.arange(r, dtype=np.int64)
+        t0 = time.perf_counter()
+        oracle.spgemm((A.rowptr, A.colind, A.values), (A.rowptr, A.colind, A.values), A.cols, rows=rows, scale=False)
+        dt = time.perf_counter() - t0
+        return 2.0 * float(fl[:r].sum()), dt, "oracle FP64 SpGEMM on rows [0, %d) of %d" % (r, A.rows)
+
+
 class CopyCalibration(Workload):
     """A plain device copy of 1 GiB: the reference against which HBM counters are scaled."""
 
@@ -430,6 +498,13 @@ def workloads():
     import synth
     return {
         "copy_1gib": lambda: CopyCalibration(),
+        "spgemm_rmat18_ef16_aa": lambda: SpgemmAA(
+            "spgemm_rmat18_ef16_aa", lambda: synth.rmat_csr(18, 16, seed=7),
+            {"workload": "spgemm_rmat18_ef16_aa", "matrix": "R-MAT scale 18, edge factor 16, "
+             "(0.57,0.19,0.19,0.05), C = A A", "seed": 7}),
+        "spgemm_er1m16_aa": lambda: SpgemmAA(
+            "spgemm_er1m16_aa", lambda: synth.uniform_csr(1 << 20, 1 << 20, 16, seed=8),
+            {"workload": "spgemm_er1m16_aa", "matrix": "1,048,576^2 uniform, 16 nnz/row, C = A A", "seed": 8}),
         "uneven512_batched": lambda: Batched(
             "uneven512_batched", 512,
             {"workload": "uneven512_batched", "matrix": "512 square tiles, rows log-uniform in [1024, 65536], "
@@ -507,7 +582,7 @@ def main():
          % (args.steps, ms_step, avg_kernel_ms, min(per), max(per)))
     traffic = stored_traffic(args.workload)
     out = {
-        "metric": "SpMM GFLOP/s (2*nnz*N) and % HBM roofline, fwd+bwd, BF16/batched vs FP32",
+        "metric": wl.metric,
         "value": round(value, 2),
         "unit": "GFLOP/s",
         "n_gpus": 1,

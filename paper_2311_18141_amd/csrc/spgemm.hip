@@ -156,10 +156,13 @@ __device__ __forceinline__ int32_t lower_bound(const int32_t* colB, int32_t lo, 
 // Visit the products of A entries [a0, a1) with the whole workgroup: f(col, a * b);
 // with WIN, only the products whose column lies in [c0, c1) (found by binary search
 // in each sorted B row).  LDS: s_pref[kWG + 1], s_start[kWG], s_aval[kWG], s_tmp[kWGWaves].
+// With a split table (bsplit[k * stride + w] = first position of B row k at column
+// >= w * window), the window's sub-range is read instead of searched.
 template <bool VALS, bool WIN, typename F>
 __device__ __forceinline__ void block_products(const SgOperands& O, int32_t a0, int32_t a1, int32_t* s_pref,
                                                int32_t* s_start, float* s_aval, int32_t* s_tmp, F&& f,
-                                               int32_t c0 = 0, int32_t c1 = 0) {
+                                               int32_t c0 = 0, int32_t c1 = 0, const int32_t* bsplit = nullptr,
+                                               int64_t stride = 0, int win = 0) {
   const int tid = threadIdx.x;
   for (int32_t c = a0; c < a1; c += kWG) {
     const int n = min(kWG, a1 - c);
@@ -170,8 +173,14 @@ __device__ __forceinline__ void block_products(const SgOperands& O, int32_t a0, 
       st = O.rowptrB[k];
       int32_t en = O.rowptrB[k + 1];
       if constexpr (WIN) {
-        st = lower_bound(O.colB, st, en, c0);
-        en = lower_bound(O.colB, st, en, c1);
+        if (bsplit) {
+          const int32_t* sp = bsplit + (int64_t)k * stride + win;
+          st = sp[0];
+          en = sp[1];
+        } else {
+          st = lower_bound(O.colB, st, en, c0);
+          en = lower_bound(O.colB, st, en, c1);
+        }
       }
       len = en - st;
       if constexpr (VALS) av = O.valA[c + tid];
@@ -483,8 +492,22 @@ struct SgItem {
   int32_t row, win, out, cnt;
 };
 
+// bsplit[k * (n_win + 1) + w]: first position of B row k at column >= w * 2^win_log2
+// (w = n_win: the row's end).
+__global__ void __launch_bounds__(kBlock) bsplit_kernel(const int32_t* rowptrB, const int32_t* colB, int64_t K,
+                                                        int n_win, int win_log2, int32_t* bsplit) {
+  const int64_t stride = n_win + 1;
+  for (int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x; x < K * stride; x += (int64_t)gridDim.x * kBlock) {
+    const int64_t k = x / stride;
+    const int w = (int)(x - k * stride);
+    const int32_t lo = rowptrB[k], hi = rowptrB[k + 1];
+    bsplit[x] = w == n_win ? hi : lower_bound(colB, lo, hi, (int32_t)((int64_t)w << win_log2));
+  }
+}
+
 __global__ void __launch_bounds__(kWG) num_window_kernel(SgOperands O, SgOut Co, const SgItem* items,
-                                                         int64_t n_items, int win_log2) {
+                                                         int64_t n_items, int win_log2, const int32_t* bsplit,
+                                                         int n_win) {
   extern __shared__ int32_t s_dyn[];
   const int W = 1 << win_log2;
   const int ww = W >> 5;
@@ -508,7 +531,7 @@ __global__ void __launch_bounds__(kWG) num_window_kernel(SgOperands O, SgOut Co,
                                  atomicOr(bits + (x >> 5), 1u << (x & 31));
                                  atomicAdd(acc + x, prod);
                                },
-                               c0, c1);
+                               c0, c1, bsplit, (int64_t)n_win + 1, item.win);
     int32_t out = item.out;
     const int32_t end = item.out + item.cnt;
     for (int w0 = 0; w0 < ww; w0 += kWG) {
@@ -587,11 +610,14 @@ __global__ void __launch_bounds__(kWG) num_dense_kernel(SgOperands O, SgOut Co, 
   }
 }
 
-// Numeric classes: wave tables of 256 / 512 / 1024 slots, the workgroup table,
-// the dense slots.  Symbolic classes: wave sets of 256 / 512 / 1024 slots, bitmap.
-constexpr int kNumClasses = 5;
+// Numeric classes: wave tables of 256 / 512 / 1024 slots (0..2), workgroup tables of
+// 2K / 4K / 8K / 16K slots (3..6, each launched with just the LDS it needs), long
+// rows (7).  Symbolic classes: wave sets of 256 / 512 / 1024 slots, bitmap.
+constexpr int kNumClasses = 8;
+constexpr int kLongClass = 7;
 constexpr int kSymClasses = 4;
 constexpr int kMaxWindows = 4096;   // column windows per long row (else the dense slots)
+constexpr int64_t kSplitBudget = (int64_t)1 << 26;  // B-row window split table entries (else binary search)
 
 int64_t grid_for(int64_t items, int64_t per_block) {
   return std::max<int64_t>(1, std::min<int64_t>((items + per_block - 1) / per_block, kMaxGridBlocks));
@@ -600,6 +626,7 @@ int64_t grid_for(int64_t items, int64_t per_block) {
 }  // namespace
 }  // namespace spmm
 
+using spmm::kLongClass;
 using spmm::kNumClasses;
 using spmm::kSymClasses;
 
@@ -621,10 +648,13 @@ struct spgemm_s {
   size_t lds_window = 0;        // the window kernel's dynamic LDS bytes
   spmm::SgItem* items = nullptr;  // device: (row, window, offset, count) of the long rows
   int64_t n_items = 0;
+  int32_t* bsplit = nullptr;      // device: B rows' window split positions (nullable)
+  int n_win = 0;
   ~spgemm_s() {
     if (rowptrC) (void)hipFree(rowptrC);
     if (rows) (void)hipFree(rows);
     if (items) (void)hipFree(items);
+    if (bsplit) (void)hipFree(bsplit);
     if (slot_vals) (void)hipFree(slot_vals);
     if (slot_bits) (void)hipFree(slot_bits);
   }
@@ -845,9 +875,14 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
       while (tg_log2 < 16 && kBlockFixedLds + 8 * ((size_t)1 << (tg_log2 + 1)) <= (size_t)lds_max) ++tg_log2;
       h->tg_log2 = tg_log2;
       h->lds_block = kBlockFixedLds + 8 * ((size_t)1 << tg_log2);
-      const int64_t tg_half = (int64_t)1 << (tg_log2 - 1);
       auto num_cls = [&](int64_t n) {
-        return n == 0 ? -1 : n <= 128 ? 0 : n <= 256 ? 1 : n <= 512 ? 2 : n <= tg_half ? 3 : 4;
+        if (n == 0) return -1;
+        if (n <= 512) return n <= 128 ? 0 : n <= 256 ? 1 : 2;
+        for (int c = 3; c < kLongClass; ++c) {
+          const int tl = c + 8;  // table of 2^tl slots holds up to 2^(tl-1) entries
+          if (tl <= tg_log2 && n <= ((int64_t)1 << (tl - 1))) return c;
+        }
+        return kLongClass;
       };
       for (int c = 0; c < kNumClasses; ++c) h->cls_cnt[c] = 0;
       for (int64_t i = 0; i < M; ++i) {
@@ -868,13 +903,13 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
         SG_TRY(hipMemcpyAsync(h->rows, list.data(), sizeof(int32_t) * (size_t)M, hipMemcpyHostToDevice, s));
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(spmm::num_block_kernel),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_block);
-      if (h->cls_cnt[4] && h->win_log2) {
+      if (h->cls_cnt[kLongClass] && h->win_log2) {
         // (row, window) items of the long rows, with their output offsets, largest first
         std::vector<int64_t> bitmap_index((size_t)M, -1);
         for (int64_t r = 0; r < cnt[3]; ++r) bitmap_index[(size_t)list_sym[(size_t)(off[3] + r)]] = r;
         std::vector<spmm::SgItem> items;
-        for (int64_t t = 0; t < h->cls_cnt[4]; ++t) {
-          const int32_t i = list[(size_t)(h->cls_off[4] + t)];
+        for (int64_t t = 0; t < h->cls_cnt[kLongClass]; ++t) {
+          const int32_t i = list[(size_t)(h->cls_off[kLongClass] + t)];
           const int64_t r = bitmap_index[(size_t)i];
           if (r < 0) return spmm::set_error(SPMM_ERR_HIP, "internal: long row %d has no window counts", i);
           int32_t out = rp[(size_t)i];
@@ -894,8 +929,16 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
           SG_TRY(hipMemcpyAsync(h->items, items.data(), sizeof(spmm::SgItem) * items.size(), hipMemcpyHostToDevice, s));
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(spmm::num_window_kernel),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_window);
-      } else if (h->cls_cnt[4]) {
-        const spmm_status st = ensure_slots(h, slot_count(h, h->cls_cnt[4], cus), s);
+        h->n_win = n_win;
+        const int64_t split_entries = h->K * ((int64_t)n_win + 1);
+        if (split_entries <= spmm::kSplitBudget && dmalloc(&h->bsplit, split_entries) == hipSuccess) {
+          hipLaunchKernelGGL(spmm::bsplit_kernel, dim3((unsigned)spmm::grid_for(split_entries, spmm::kBlock)),
+                             dim3(spmm::kBlock), 0, s, h->B.rowptr, h->B.colind, h->K, n_win, h->win_log2,
+                             h->bsplit);
+          SG_TRY(hipGetLastError());
+        }
+      } else if (h->cls_cnt[kLongClass]) {
+        const spmm_status st = ensure_slots(h, slot_count(h, h->cls_cnt[kLongClass], cus), s);
         if (st != SPMM_OK) return st;
       }
       SG_TRY(hipStreamSynchronize(s));
@@ -954,24 +997,27 @@ spmm_status spgemm_compute(spgemm_t plan, int32_t* colindC, float* valuesC, void
   if (cnt[2]) hipLaunchKernelGGL(spmm::num_wave_kernel<1024>, dim3((unsigned)spmm::grid_for(cnt[2], 4)),
                                  dim3(spmm::kBlock), 0, s, O, Co, rows + off[2], cnt[2]);
   SG_TRY(hipGetLastError());
-  if (cnt[3]) {
-    const int64_t grid = std::min<int64_t>(cnt[3], 65536);
-    hipLaunchKernelGGL(spmm::num_block_kernel, dim3((unsigned)grid), dim3(spmm::kWG), plan->lds_block, s, O, Co,
-                       rows + off[3], cnt[3], plan->tg_log2);
+  for (int c = 3; c < kLongClass; ++c) {
+    if (!cnt[c]) continue;
+    const int tl = c + 8;
+    const size_t lds = kBlockFixedLds + 8 * ((size_t)1 << tl);
+    const int64_t grid = std::min<int64_t>(cnt[c], 65536);
+    hipLaunchKernelGGL(spmm::num_block_kernel, dim3((unsigned)grid), dim3(spmm::kWG), lds, s, O, Co, rows + off[c],
+                       cnt[c], tl);
     SG_TRY(hipGetLastError());
   }
-  if (cnt[4] && plan->win_log2) {
+  if (cnt[kLongClass] && plan->win_log2) {
     if (plan->n_items) {
       int cus = 0;
       SG_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
       const int64_t grid = std::min<int64_t>(plan->n_items, (int64_t)cus * 2);
       hipLaunchKernelGGL(spmm::num_window_kernel, dim3((unsigned)grid), dim3(spmm::kWG), plan->lds_window, s, O, Co,
-                         plan->items, plan->n_items, plan->win_log2);
+                         plan->items, plan->n_items, plan->win_log2, plan->bsplit, plan->n_win);
       SG_TRY(hipGetLastError());
     }
-  } else if (cnt[4]) {
+  } else if (cnt[kLongClass]) {
     hipLaunchKernelGGL(spmm::num_dense_kernel, dim3((unsigned)plan->n_slots), dim3(spmm::kWG), 0, s, O, Co,
-                       rows + off[4], cnt[4], plan->slot_vals, plan->slot_bits, plan->slot_words);
+                       rows + off[kLongClass], cnt[kLongClass], plan->slot_vals, plan->slot_bits, plan->slot_words);
     SG_TRY(hipGetLastError());
   }
   return SPMM_OK;

@@ -213,3 +213,17 @@ def test_spgemm_very_wide_b_dense_slots():
     B = _b_rows_of_lengths([5000, 6000, 700, 20], N, rng, "int8")
     A = _select_rows(B.rows, [[0, 1], [2], [0, 1, 2, 3], [3], []], rng, "int8")
     _check(A, B, exact=True, compress_cols=True)
+
+
+def test_spgemm_long_rows_without_split_table():
+    """B with so many rows that its window split table would exceed its budget (800K rows x
+    93 windows): long rows find each window's B-row range by binary search instead."""
+    G.note("spgemm long rows, binary-searched windows")
+    rng = _rng(19)
+    K, N = 800_000, 3_000_000
+    L = np.zeros(K, dtype=np.int64)
+    hot = rng.choice(K, size=6, replace=False)
+    L[hot] = [9000, 7000, 3000, 600, 40, 5]
+    B = synth.random_csr(K, N, L, rng, "int8")
+    A = _select_rows(K, [list(hot[:2]), list(hot), [hot[2]], list(hot[3:]), []], rng, "int8")
+    _check(A, B, exact=True, compress_cols=True)
