@@ -82,19 +82,47 @@ __global__ void __launch_bounds__(kBlock) row_products_kernel(SgOperands O, int6
   }
 }
 
-// Visit the products of A entries [a0, a1) with one wave: f(col, a * b).
-template <bool VALS, typename F>
+// First position in colB[lo, hi) whose column is >= x (colB is sorted within a row).
+__device__ __forceinline__ int32_t lower_bound(const int32_t* colB, int32_t lo, int32_t hi, int32_t x) {
+  while (lo < hi) {
+    const int32_t mid = lo + ((hi - lo) >> 1);
+    if (colB[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Visit products with one wave: f(col, a * b).  The wave takes A entries in chunks of
+// 64 starting at a0 and advancing by `step` (64 for a wave on its own; 64 x waves when
+// the waves of a workgroup share a row), up to a1.  With WIN, only the products whose
+// column lies in [c0, c1): each B row is cut to that range, by the split table when
+// given (bsplit[k * stride + win] = first position at column >= win * window) or by
+// binary search.  s_pref/s_start/s_aval hold 64 entries each (this wave's).
+template <bool VALS, bool WIN = false, typename F>
 __device__ __forceinline__ void wave_products(const SgOperands& O, int32_t a0, int32_t a1, int32_t* s_pref,
-                                              int32_t* s_start, float* s_aval, F&& f) {
+                                              int32_t* s_start, float* s_aval, F&& f, int32_t step = 64,
+                                              int32_t c0 = 0, int32_t c1 = 0, const int32_t* bsplit = nullptr,
+                                              int64_t stride = 0, int win = 0) {
   const int lane = threadIdx.x & 63;
-  for (int32_t c = a0; c < a1; c += 64) {
+  for (int32_t c = a0; c < a1; c += step) {
     const int n = min(64, a1 - c);
     int32_t st = 0, len = 0;
     float av = 0.0f;
     if (lane < n) {
       const int32_t k = O.colA[c + lane];
       st = O.rowptrB[k];
-      len = O.rowptrB[k + 1] - st;
+      int32_t en = O.rowptrB[k + 1];
+      if constexpr (WIN) {
+        if (bsplit) {
+          const int32_t* sp = bsplit + (int64_t)k * stride + win;
+          st = sp[0];
+          en = sp[1];
+        } else {
+          st = lower_bound(O.colB, st, en, c0);
+          en = lower_bound(O.colB, st, en, c1);
+        }
+      }
+      len = en - st;
       if constexpr (VALS) av = O.valA[c + lane];
     }
     int32_t incl = len;
@@ -108,13 +136,26 @@ __device__ __forceinline__ void wave_products(const SgOperands& O, int32_t a0, i
     if constexpr (VALS) s_aval[lane] = av;
     const int32_t tot = __builtin_amdgcn_readlane(incl, 63);
     wave_sync_lds();
-    for (int32_t t = lane; t < tot; t += 64) {
-      int pi = 0;
+    // four products per lane per pass: their searches and loads are independent, so
+    // their latencies overlap
+    for (int32_t t0 = lane; t0 < tot; t0 += 4 * 64) {
+      int32_t col[4];
+      float prod[4];
 #pragma unroll
-      for (int step = 32; step > 0; step >>= 1)
-        if (s_pref[pi + step] <= t) pi += step;
-      const int32_t q = s_start[pi] + (t - s_pref[pi]);
-      f(O.colB[q], VALS ? s_aval[pi] * O.valB[q] : 0.0f);
+      for (int u = 0; u < 4; ++u) {
+        const int32_t t = t0 + u * 64;
+        const int32_t tc = t < tot ? t : tot - 1;
+        int pi = 0;
+#pragma unroll
+        for (int sp = 32; sp > 0; sp >>= 1)
+          if (s_pref[pi + sp] <= tc) pi += sp;
+        const int32_t q = s_start[pi] + (tc - s_pref[pi]);
+        col[u] = O.colB[q];
+        prod[u] = VALS ? s_aval[pi] * O.valB[q] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (t0 + u * 64 < tot) f(col[u], prod[u]);
     }
     wave_sync_lds();
   }
@@ -141,66 +182,6 @@ __device__ __forceinline__ int32_t block_scan(int32_t v, int32_t* excl, int32_t*
   __syncthreads();
   *excl = base + incl - v;
   return total;
-}
-
-// First position in colB[lo, hi) whose column is >= x (colB is sorted within a row).
-__device__ __forceinline__ int32_t lower_bound(const int32_t* colB, int32_t lo, int32_t hi, int32_t x) {
-  while (lo < hi) {
-    const int32_t mid = lo + ((hi - lo) >> 1);
-    if (colB[mid] < x) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
-
-// Visit the products of A entries [a0, a1) with the whole workgroup: f(col, a * b);
-// with WIN, only the products whose column lies in [c0, c1) (found by binary search
-// in each sorted B row).  LDS: s_pref[kWG + 1], s_start[kWG], s_aval[kWG], s_tmp[kWGWaves].
-// With a split table (bsplit[k * stride + w] = first position of B row k at column
-// >= w * window), the window's sub-range is read instead of searched.
-template <bool VALS, bool WIN, typename F>
-__device__ __forceinline__ void block_products(const SgOperands& O, int32_t a0, int32_t a1, int32_t* s_pref,
-                                               int32_t* s_start, float* s_aval, int32_t* s_tmp, F&& f,
-                                               int32_t c0 = 0, int32_t c1 = 0, const int32_t* bsplit = nullptr,
-                                               int64_t stride = 0, int win = 0) {
-  const int tid = threadIdx.x;
-  for (int32_t c = a0; c < a1; c += kWG) {
-    const int n = min(kWG, a1 - c);
-    int32_t st = 0, len = 0;
-    float av = 0.0f;
-    if (tid < n) {
-      const int32_t k = O.colA[c + tid];
-      st = O.rowptrB[k];
-      int32_t en = O.rowptrB[k + 1];
-      if constexpr (WIN) {
-        if (bsplit) {
-          const int32_t* sp = bsplit + (int64_t)k * stride + win;
-          st = sp[0];
-          en = sp[1];
-        } else {
-          st = lower_bound(O.colB, st, en, c0);
-          en = lower_bound(O.colB, st, en, c1);
-        }
-      }
-      len = en - st;
-      if constexpr (VALS) av = O.valA[c + tid];
-    }
-    int32_t excl;
-    const int32_t tot = block_scan(len, &excl, s_tmp);
-    s_pref[tid] = excl;
-    s_start[tid] = st;
-    if constexpr (VALS) s_aval[tid] = av;
-    __syncthreads();
-    for (int32_t t = tid; t < tot; t += kWG) {
-      int pi = 0;
-#pragma unroll
-      for (int step = kWG / 2; step > 0; step >>= 1)
-        if (pi + step < kWG && s_pref[pi + step] <= t) pi += step;
-      const int32_t q = s_start[pi] + (t - s_pref[pi]);
-      f(O.colB[q], VALS ? s_aval[pi] * O.valB[q] : 0.0f);
-    }
-    __syncthreads();
-  }
 }
 
 // ---------------------------------------------------------------- symbolic
@@ -266,7 +247,8 @@ __global__ void __launch_bounds__(kWG) sym_bitmap_kernel(SgOperands O, const int
   for (int64_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
     const int32_t i = rows[r];
     int cnt = 0;
-    block_products<false, false>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref, s_start, nullptr, s_tmp,
+    const int wv = tid >> 6;
+    wave_products<false>(O, O.rowptrA[i] + 64 * wv, O.rowptrA[i + 1], s_pref + 64 * wv, s_start + 64 * wv, nullptr,
                                  [&](int32_t col, float) {
                                    const uint32_t bit = 1u << (col & 31);
                                    uint32_t old;
@@ -276,7 +258,8 @@ __global__ void __launch_bounds__(kWG) sym_bitmap_kernel(SgOperands O, const int
                                    else
                                      old = atomicOr(bits + (col >> 5), bit);
                                    if (!(old & bit)) ++cnt;
-                                 });
+                                 },
+                                 64 * kWGWaves);
     cnt = wave_sum(cnt);
     if ((tid & 63) == 0) s_cnt[tid >> 6] = cnt;
     if constexpr (GLOBAL) __threadfence();
@@ -438,7 +421,9 @@ __global__ void __launch_bounds__(kWG) num_block_kernel(SgOperands O, SgOut Co, 
       val[j] = 0.0f;
     }
     __syncthreads();
-    block_products<true, false>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref, s_start, s_aval, s_tmp,
+    const int wv = tid >> 6;
+    wave_products<true>(O, O.rowptrA[i] + 64 * wv, O.rowptrA[i + 1], s_pref + 64 * wv, s_start + 64 * wv,
+                        s_aval + 64 * wv,
                          [&](int32_t col, float prod) {
                            uint32_t h = hash_slot(col, shift);
                            for (int probe = 0; probe < tg; ++probe) {  // at most half full
@@ -449,7 +434,9 @@ __global__ void __launch_bounds__(kWG) num_block_kernel(SgOperands O, SgOut Co, 
                              }
                              h = (h + 1) & (uint32_t)(tg - 1);
                            }
-                         });
+                         },
+                         64 * kWGWaves);
+    __syncthreads();
     // compact the occupied slots to the front (chunks of kWG, read before written), then
     // sort the smallest power of two that holds them
     int n = 0;
@@ -525,13 +512,16 @@ __global__ void __launch_bounds__(kWG) num_window_kernel(SgOperands O, SgOut Co,
     const SgItem item = items[it];
     const int32_t c0 = item.win << win_log2;
     const int32_t c1 = (int32_t)min((int64_t)c0 + W, O.N);
-    block_products<true, true>(O, O.rowptrA[item.row], O.rowptrA[item.row + 1], s_pref, s_start, s_aval, s_tmp,
-                               [&](int32_t col, float prod) {
-                                 const int32_t x = col - c0;
-                                 atomicOr(bits + (x >> 5), 1u << (x & 31));
-                                 atomicAdd(acc + x, prod);
-                               },
-                               c0, c1, bsplit, (int64_t)n_win + 1, item.win);
+    const int wv = tid >> 6;
+    wave_products<true, true>(O, O.rowptrA[item.row] + 64 * wv, O.rowptrA[item.row + 1], s_pref + 64 * wv,
+                              s_start + 64 * wv, s_aval + 64 * wv,
+                              [&](int32_t col, float prod) {
+                                const int32_t x = col - c0;
+                                atomicOr(bits + (x >> 5), 1u << (x & 31));
+                                atomicAdd(acc + x, prod);
+                              },
+                              64 * kWGWaves, c0, c1, bsplit, (int64_t)n_win + 1, item.win);
+    __syncthreads();
     int32_t out = item.out;
     const int32_t end = item.out + item.cnt;
     for (int w0 = 0; w0 < ww; w0 += kWG) {
@@ -574,12 +564,15 @@ __global__ void __launch_bounds__(kWG) num_dense_kernel(SgOperands O, SgOut Co, 
   const int tid = threadIdx.x;
   for (int64_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
     const int32_t i = rows[r];
-    block_products<true, false>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref, s_start, s_aval, s_tmp,
+    const int wv = tid >> 6;
+    wave_products<true>(O, O.rowptrA[i] + 64 * wv, O.rowptrA[i + 1], s_pref + 64 * wv, s_start + 64 * wv,
+                        s_aval + 64 * wv,
                          [&](int32_t col, float prod) {
                            __hip_atomic_fetch_or(bits + (col >> 5), 1u << (col & 31), __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
                            __hip_atomic_fetch_add(vals + col, prod, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                         });
+                         },
+                         64 * kWGWaves);
     __threadfence();
     __syncthreads();
     int32_t out = Co.rowptrC[i];
