@@ -184,6 +184,56 @@ __device__ __forceinline__ int32_t block_scan(int32_t v, int32_t* excl, int32_t*
   return total;
 }
 
+// Visit the products of A entries [a0, a1) with the whole workgroup: f(col, a * b);
+// with WIN, only the products whose column lies in [c0, c1) (found by binary search
+// in each sorted B row).  LDS: s_pref[kWG + 1], s_start[kWG], s_aval[kWG], s_tmp[kWGWaves].
+// With a split table (bsplit[k * stride + w] = first position of B row k at column
+// >= w * window), the window's sub-range is read instead of searched.
+template <bool VALS, bool WIN, typename F>
+__device__ __forceinline__ void block_products(const SgOperands& O, int32_t a0, int32_t a1, int32_t* s_pref,
+                                               int32_t* s_start, float* s_aval, int32_t* s_tmp, F&& f,
+                                               int32_t c0 = 0, int32_t c1 = 0, const int32_t* bsplit = nullptr,
+                                               int64_t stride = 0, int win = 0) {
+  const int tid = threadIdx.x;
+  for (int32_t c = a0; c < a1; c += kWG) {
+    const int n = min(kWG, a1 - c);
+    int32_t st = 0, len = 0;
+    float av = 0.0f;
+    if (tid < n) {
+      const int32_t k = O.colA[c + tid];
+      st = O.rowptrB[k];
+      int32_t en = O.rowptrB[k + 1];
+      if constexpr (WIN) {
+        if (bsplit) {
+          const int32_t* sp = bsplit + (int64_t)k * stride + win;
+          st = sp[0];
+          en = sp[1];
+        } else {
+          st = lower_bound(O.colB, st, en, c0);
+          en = lower_bound(O.colB, st, en, c1);
+        }
+      }
+      len = en - st;
+      if constexpr (VALS) av = O.valA[c + tid];
+    }
+    int32_t excl;
+    const int32_t tot = block_scan(len, &excl, s_tmp);
+    s_pref[tid] = excl;
+    s_start[tid] = st;
+    if constexpr (VALS) s_aval[tid] = av;
+    __syncthreads();
+    for (int32_t t = tid; t < tot; t += kWG) {
+      int pi = 0;
+#pragma unroll
+      for (int step = kWG / 2; step > 0; step >>= 1)
+        if (pi + step < kWG && s_pref[pi + step] <= t) pi += step;
+      const int32_t q = s_start[pi] + (t - s_pref[pi]);
+      f(O.colB[q], VALS ? s_aval[pi] * O.valB[q] : 0.0f);
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- symbolic
 
 // Rows with at most TS/2 products: distinct columns in a wave-local hash set.
@@ -247,8 +297,7 @@ __global__ void __launch_bounds__(kWG) sym_bitmap_kernel(SgOperands O, const int
   for (int64_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
     const int32_t i = rows[r];
     int cnt = 0;
-    const int wv = tid >> 6;
-    wave_products<false>(O, O.rowptrA[i] + 64 * wv, O.rowptrA[i + 1], s_pref + 64 * wv, s_start + 64 * wv, nullptr,
+    block_products<false, false>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref, s_start, nullptr, s_tmp,
                                  [&](int32_t col, float) {
                                    const uint32_t bit = 1u << (col & 31);
                                    uint32_t old;
@@ -258,8 +307,7 @@ __global__ void __launch_bounds__(kWG) sym_bitmap_kernel(SgOperands O, const int
                                    else
                                      old = atomicOr(bits + (col >> 5), bit);
                                    if (!(old & bit)) ++cnt;
-                                 },
-                                 64 * kWGWaves);
+                                 });
     cnt = wave_sum(cnt);
     if ((tid & 63) == 0) s_cnt[tid >> 6] = cnt;
     if constexpr (GLOBAL) __threadfence();
@@ -396,7 +444,12 @@ __global__ void __launch_bounds__(kBlock) num_wave_kernel(SgOperands O, SgOut Co
 }
 
 // Rows with at most tg/2 output entries: one workgroup per row, an LDS hash table
-// of tg slots (a power of two; dynamic LDS).
+// of up to 2^tg_log2 slots (a power of two; dynamic LDS), sized per row.  Output
+// order: with BM, a bitmap over all N columns (in LDS after the table) marks each new
+// key, and a walk over it writes the row in column order, looking each value up in
+// the table; without BM (N too wide for LDS), the occupied slots are compacted and
+// bitonic-sorted.
+template <bool BM>
 __global__ void __launch_bounds__(kWG) num_block_kernel(SgOperands O, SgOut Co, const int32_t* rows,
                                                         int64_t n_rows, int tg_log2) {
   extern __shared__ int32_t s_dyn[];
@@ -407,7 +460,12 @@ __global__ void __launch_bounds__(kWG) num_block_kernel(SgOperands O, SgOut Co, 
   int32_t* s_start = s_pref + kWG + 1;
   float* s_aval = reinterpret_cast<float*>(s_start + kWG);
   int32_t* s_tmp = reinterpret_cast<int32_t*>(s_aval + kWG);
+  uint32_t* bits = reinterpret_cast<uint32_t*>(s_tmp + kWGWaves);  // BM: ceil(N / 32) words
+  const int64_t words = (O.N + 31) / 32;
   const int tid = threadIdx.x;
+  if constexpr (BM) {
+    for (int64_t j = tid; j < words; j += kWG) bits[j] = 0u;
+  }
   for (int64_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
     const int32_t i = rows[r];
     // this row's table: a power of two of at least twice its entries (>= kWG)
@@ -421,53 +479,86 @@ __global__ void __launch_bounds__(kWG) num_block_kernel(SgOperands O, SgOut Co, 
       val[j] = 0.0f;
     }
     __syncthreads();
-    const int wv = tid >> 6;
-    wave_products<true>(O, O.rowptrA[i] + 64 * wv, O.rowptrA[i + 1], s_pref + 64 * wv, s_start + 64 * wv,
-                        s_aval + 64 * wv,
-                         [&](int32_t col, float prod) {
-                           uint32_t h = hash_slot(col, shift);
-                           for (int probe = 0; probe < tg; ++probe) {  // at most half full
-                             const int32_t old = atomicCAS(&key[h], -1, col);
-                             if (old == -1 || old == col) {
-                               atomicAdd(&val[h], prod);
-                               break;
-                             }
-                             h = (h + 1) & (uint32_t)(tg - 1);
-                           }
-                         },
-                         64 * kWGWaves);
-    __syncthreads();
-    // compact the occupied slots to the front (chunks of kWG, read before written), then
-    // sort the smallest power of two that holds them
-    int n = 0;
-    for (int c0 = 0; c0 < tg; c0 += kWG) {
-      const int j = c0 + tid;
-      int32_t k = -1;
-      float v = 0.0f;
-      if (j < tg) {
-        k = key[j];
-        v = val[j];
+    block_products<true, false>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref, s_start, s_aval, s_tmp,
+                        [&](int32_t col, float prod) {
+                          uint32_t h = hash_slot(col, shift);
+                          for (int probe = 0; probe < tg; ++probe) {  // at most half full
+                            const int32_t old = atomicCAS(&key[h], -1, col);
+                            if (old == -1 || old == col) {
+                              atomicAdd(&val[h], prod);
+                              if (BM && old == -1) atomicOr(bits + (col >> 5), 1u << (col & 31));
+                              break;
+                            }
+                            h = (h + 1) & (uint32_t)(tg - 1);
+                          }
+                        });
+    const int32_t base = Co.rowptrC[i];
+    if constexpr (BM) {
+      // walk the bitmap in column order; each set bit's value comes from the table
+      const int32_t end = Co.rowptrC[i + 1];
+      int32_t out = base;
+      for (int64_t w0 = 0; w0 < words; w0 += kWG) {
+        const int64_t wi = w0 + tid;
+        uint32_t word = wi < words ? bits[wi] : 0u;
+        int32_t excl;
+        const int32_t tot = block_scan(__popc(word), &excl, s_tmp);
+        int32_t pos = out + excl;
+        while (word) {
+          const int b = __ffs(word) - 1;
+          word &= word - 1;
+          const int32_t col = (int32_t)(wi * 32 + b);
+          uint32_t h = hash_slot(col, shift);
+          float v = 0.0f;
+          for (int probe = 0; probe < tg; ++probe) {
+            if (key[h] == col) {
+              v = val[h];
+              break;
+            }
+            h = (h + 1) & (uint32_t)(tg - 1);
+          }
+          if (pos < end) {
+            Co.colC[pos] = col;
+            Co.valC[pos] = v;
+          }
+          ++pos;
+        }
+        if (wi < words) bits[wi] = 0u;
+        out += tot;
       }
-      const int occ = k >= 0 ? 1 : 0;
-      int32_t excl;
-      const int32_t tot = block_scan(occ, &excl, s_tmp);  // synchronises: all reads are done
-      if (occ) {
-        key[n + excl] = k;
-        val[n + excl] = v;
+      __syncthreads();
+    } else {
+      // compact the occupied slots to the front (chunks of kWG, read before written),
+      // then sort the smallest power of two that holds them
+      int n = 0;
+      for (int c0 = 0; c0 < tg; c0 += kWG) {
+        const int j = c0 + tid;
+        int32_t k = -1;
+        float v = 0.0f;
+        if (j < tg) {
+          k = key[j];
+          v = val[j];
+        }
+        const int occ = k >= 0 ? 1 : 0;
+        int32_t excl;
+        const int32_t tot = block_scan(occ, &excl, s_tmp);  // synchronises: all reads are done
+        if (occ) {
+          key[n + excl] = k;
+          val[n + excl] = v;
+        }
+        n += tot;
+        __syncthreads();
       }
-      n += tot;
+      const int P = pow2_at_least(n);
+      for (int j = n + tid; j < P; j += kWG) key[j] = 0x7fffffff;
+      __syncthreads();
+      bitonic_sort(key, val, P, tid, kWG, [] { __syncthreads(); });
+      const int32_t cnt = min(Co.rowptrC[i + 1] - base, n);
+      for (int j = tid; j < cnt; j += kWG) {
+        Co.colC[base + j] = key[j];
+        Co.valC[base + j] = val[j];
+      }
       __syncthreads();
     }
-    const int P = pow2_at_least(n);
-    for (int j = n + tid; j < P; j += kWG) key[j] = 0x7fffffff;
-    __syncthreads();
-    bitonic_sort(key, val, P, tid, kWG, [] { __syncthreads(); });
-    const int32_t base = Co.rowptrC[i], cnt = min(Co.rowptrC[i + 1] - base, n);
-    for (int j = tid; j < cnt; j += kWG) {
-      Co.colC[base + j] = key[j];
-      Co.valC[base + j] = val[j];
-    }
-    __syncthreads();
   }
 }
 
@@ -512,16 +603,13 @@ __global__ void __launch_bounds__(kWG) num_window_kernel(SgOperands O, SgOut Co,
     const SgItem item = items[it];
     const int32_t c0 = item.win << win_log2;
     const int32_t c1 = (int32_t)min((int64_t)c0 + W, O.N);
-    const int wv = tid >> 6;
-    wave_products<true, true>(O, O.rowptrA[item.row] + 64 * wv, O.rowptrA[item.row + 1], s_pref + 64 * wv,
-                              s_start + 64 * wv, s_aval + 64 * wv,
-                              [&](int32_t col, float prod) {
-                                const int32_t x = col - c0;
-                                atomicOr(bits + (x >> 5), 1u << (x & 31));
-                                atomicAdd(acc + x, prod);
-                              },
-                              64 * kWGWaves, c0, c1, bsplit, (int64_t)n_win + 1, item.win);
-    __syncthreads();
+    block_products<true, true>(O, O.rowptrA[item.row], O.rowptrA[item.row + 1], s_pref, s_start, s_aval, s_tmp,
+                               [&](int32_t col, float prod) {
+                                 const int32_t x = col - c0;
+                                 atomicOr(bits + (x >> 5), 1u << (x & 31));
+                                 atomicAdd(acc + x, prod);
+                               },
+                               c0, c1, bsplit, (int64_t)n_win + 1, item.win);
     int32_t out = item.out;
     const int32_t end = item.out + item.cnt;
     for (int w0 = 0; w0 < ww; w0 += kWG) {
@@ -564,15 +652,12 @@ __global__ void __launch_bounds__(kWG) num_dense_kernel(SgOperands O, SgOut Co, 
   const int tid = threadIdx.x;
   for (int64_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
     const int32_t i = rows[r];
-    const int wv = tid >> 6;
-    wave_products<true>(O, O.rowptrA[i] + 64 * wv, O.rowptrA[i + 1], s_pref + 64 * wv, s_start + 64 * wv,
-                        s_aval + 64 * wv,
+    block_products<true, false>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref, s_start, s_aval, s_tmp,
                          [&](int32_t col, float prod) {
                            __hip_atomic_fetch_or(bits + (col >> 5), 1u << (col & 31), __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
                            __hip_atomic_fetch_add(vals + col, prod, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                         },
-                         64 * kWGWaves);
+                         });
     __threadfence();
     __syncthreads();
     int32_t out = Co.rowptrC[i];
@@ -633,6 +718,7 @@ struct spgemm_s {
   int64_t cls_off[kNumClasses] = {}, cls_cnt[kNumClasses] = {};
   int tg_log2 = 0;              // workgroup table of 2^tg_log2 slots
   size_t lds_block = 0;         // its dynamic LDS bytes
+  size_t lds_max = 0;           // dynamic LDS a workgroup may use on this device
   float* slot_vals = nullptr;   // dense slots: n_slots x (slot_words * 32) floats
   uint32_t* slot_bits = nullptr;
   int64_t slot_words = 0;
@@ -894,8 +980,11 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
       }
       if (M > 0)
         SG_TRY(hipMemcpyAsync(h->rows, list.data(), sizeof(int32_t) * (size_t)M, hipMemcpyHostToDevice, s));
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(spmm::num_block_kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_block);
+      h->lds_max = (size_t)lds_max;
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(spmm::num_block_kernel<false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(spmm::num_block_kernel<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
       if (h->cls_cnt[kLongClass] && h->win_log2) {
         // (row, window) items of the long rows, with their output offsets, largest first
         std::vector<int64_t> bitmap_index((size_t)M, -1);
@@ -994,9 +1083,14 @@ spmm_status spgemm_compute(spgemm_t plan, int32_t* colindC, float* valuesC, void
     if (!cnt[c]) continue;
     const int tl = c + 8;
     const size_t lds = kBlockFixedLds + 8 * ((size_t)1 << tl);
+    const size_t lds_bm = lds + sizeof(uint32_t) * (size_t)((plan->N + 31) / 32);
     const int64_t grid = std::min<int64_t>(cnt[c], 65536);
-    hipLaunchKernelGGL(spmm::num_block_kernel, dim3((unsigned)grid), dim3(spmm::kWG), lds, s, O, Co, rows + off[c],
-                       cnt[c], tl);
+    if (lds_bm <= plan->lds_max)
+      hipLaunchKernelGGL(spmm::num_block_kernel<true>, dim3((unsigned)grid), dim3(spmm::kWG), lds_bm, s, O, Co,
+                         rows + off[c], cnt[c], tl);
+    else
+      hipLaunchKernelGGL(spmm::num_block_kernel<false>, dim3((unsigned)grid), dim3(spmm::kWG), lds, s, O, Co,
+                         rows + off[c], cnt[c], tl);
     SG_TRY(hipGetLastError());
   }
   if (cnt[kLongClass] && plan->win_log2) {
