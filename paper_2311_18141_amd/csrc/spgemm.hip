@@ -185,10 +185,14 @@ __device__ __forceinline__ int32_t block_scan(int32_t v, int32_t* excl, int32_t*
 }
 
 // Visit the products of A entries [a0, a1) with the whole workgroup: f(col, a * b);
-// with WIN, only the products whose column lies in [c0, c1) (found by binary search
-// in each sorted B row).  LDS: s_pref[kWG + 1], s_start[kWG], s_aval[kWG], s_tmp[kWGWaves].
-// With a split table (bsplit[k * stride + w] = first position of B row k at column
-// >= w * window), the window's sub-range is read instead of searched.
+// with WIN, only the products whose column lies in [c0, c1), each B row cut to that
+// range by the split table when given (bsplit[k * stride + win] = first position at
+// column >= win * window) or by binary search.  The workgroup takes kWG A entries at a
+// time; their (cut) B-row lengths are prefix-summed and each thread walks one
+// contiguous run of ceil(total / kWG) products: one binary search in the prefix per
+// run, then a linear step over segment boundaries (products of one B row are
+// contiguous, so a thread's loads walk along the B row).
+// LDS: s_pref[kWG + 1], s_start[kWG], s_aval[kWG], s_tmp[kWGWaves].
 template <bool VALS, bool WIN, typename F>
 __device__ __forceinline__ void block_products(const SgOperands& O, int32_t a0, int32_t a1, int32_t* s_pref,
                                                int32_t* s_start, float* s_aval, int32_t* s_tmp, F&& f,
@@ -221,14 +225,52 @@ __device__ __forceinline__ void block_products(const SgOperands& O, int32_t a0, 
     s_pref[tid] = excl;
     s_start[tid] = st;
     if constexpr (VALS) s_aval[tid] = av;
+    if (tid == 0) s_pref[kWG] = tot;
     __syncthreads();
-    for (int32_t t = tid; t < tot; t += kWG) {
+    const int32_t run = (tot + kWG - 1) / kWG;
+    int32_t t = tid * run;
+    const int32_t t_end = min(t + run, tot);
+    if (t < t_end) {
       int pi = 0;
 #pragma unroll
       for (int step = kWG / 2; step > 0; step >>= 1)
-        if (pi + step < kWG && s_pref[pi + step] <= t) pi += step;
-      const int32_t q = s_start[pi] + (t - s_pref[pi]);
-      f(O.colB[q], VALS ? s_aval[pi] * O.valB[q] : 0.0f);
+        if (s_pref[pi + step] <= t) pi += step;
+      int32_t next = s_pref[pi + 1];
+      int32_t q = s_start[pi] + (t - s_pref[pi]);
+      float a = VALS ? s_aval[pi] : 0.0f;
+      // four products per pass: positions first, then the loads, then f
+      while (t < t_end) {
+        int32_t qs[4] = {q, q, q, q};
+        float as[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (t < t_end) {
+            while (t >= next) {  // cross into the next non-empty segment
+              ++pi;
+              next = s_pref[pi + 1];
+              q = s_start[pi];
+              if constexpr (VALS) a = s_aval[pi];
+            }
+            qs[u] = q;
+            as[u] = a;
+            ++q;
+            ++t;
+            cnt = u + 1;
+          }
+        }
+        int32_t col[4];
+        float prod[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int32_t qq = qs[u < cnt ? u : 0];
+          col[u] = O.colB[qq];
+          prod[u] = VALS ? as[u] * O.valB[qq] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (u < cnt) f(col[u], prod[u]);
+      }
     }
     __syncthreads();
   }
@@ -954,12 +996,19 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
       while (tg_log2 < 16 && kBlockFixedLds + 8 * ((size_t)1 << (tg_log2 + 1)) <= (size_t)lds_max) ++tg_log2;
       h->tg_log2 = tg_log2;
       h->lds_block = kBlockFixedLds + 8 * ((size_t)1 << tg_log2);
+      // A workgroup table writes its row in column order through an LDS bitmap over C's
+      // columns when that fits beside it; where it does not and the long-row windows
+      // are few, the row goes to the windows instead of the sorting table.
+      const size_t bm_bytes = sizeof(uint32_t) * (size_t)((h->N + 31) / 32);
       auto num_cls = [&](int64_t n) {
         if (n == 0) return -1;
         if (n <= 512) return n <= 128 ? 0 : n <= 256 ? 1 : 2;
         for (int c = 3; c < kLongClass; ++c) {
           const int tl = c + 8;  // table of 2^tl slots holds up to 2^(tl-1) entries
-          if (tl <= tg_log2 && n <= ((int64_t)1 << (tl - 1))) return c;
+          if (tl <= tg_log2 && n <= ((int64_t)1 << (tl - 1))) {
+            const bool bm = kBlockFixedLds + 8 * ((size_t)1 << tl) + bm_bytes <= (size_t)lds_max;
+            return (bm || !h->win_log2 || n_win > 16) ? c : kLongClass;
+          }
         }
         return kLongClass;
       };

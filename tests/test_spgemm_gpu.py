@@ -227,3 +227,14 @@ def test_spgemm_long_rows_without_split_table():
     B = synth.random_csr(K, N, L, rng, "int8")
     A = _select_rows(K, [list(hot[:2]), list(hot), [hot[2]], list(hot[3:]), []], rng, "int8")
     _check(A, B, exact=True, compress_cols=True)
+
+
+def test_spgemm_medium_rows_to_windows():
+    """C with 300K columns: rows of 4K-8K entries cannot keep a column bitmap beside their
+    16K-slot table, and there are few windows, so they take the window path."""
+    G.note("spgemm medium rows through windows")
+    rng = _rng(20)
+    N = 300_000
+    B = _b_rows_of_lengths([4500, 6000, 8100, 600, 3000, 20000], N, rng, "int8")
+    A = _select_rows(B.rows, [[0], [1], [2], [3, 4], [0, 3], [5], [1, 2, 3]], rng, "int8")
+    _check(A, B, exact=True)
