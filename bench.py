@@ -460,7 +460,7 @@ class SpgemmAA(Workload):
         A = self.A
         L = A.row_lengths()
         fl = np.bincount(np.repeat(np.arange(A.rows), L), weights=L[A.colind], minlength=A.rows)
-        r = int(min(A.rows, np.searchsorted(np.cumsum(fl), 1.0e9) + 1))
+        r = int(min(A.rows, np.searchsorted(np.cumsum(fl), 1.0e10) + 1))  # the whole matrix here (a few s)
         rows = np.arange(r, dtype=np.int64)
         t0 = time.perf_counter()
         oracle.spgemm((A.rowptr, A.colind, A.values), (A.rowptr, A.colind, A.values), A.cols, rows=rows, scale=False)
