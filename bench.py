@@ -14,6 +14,9 @@ times dense B_k of 1,048,576 x 128 FP32, accumulated over its 4 k-tiles into a
                             forward + dA (sampled dense-dense product) + dB = A^T dC
     rmat23_n256_bf16        R-MAT scale 23, edge factor 32, N = 256, BF16 B and C
     rmat23_n256_f32         the same with FP32 B and C
+    stationary_a_rmat22_tile00_n128x4
+                            stationary-A local step: partial products of R-MAT tile (0,0) with 4
+                            column blocks of N = 128, each added into its C tile
     spgemm_rmat18_ef16_aa   local SpGEMM C = A A, R-MAT scale 18, edge factor 16 (numeric phase;
                             the symbolic phase is reported beside it)
     spgemm_er1m16_aa        local SpGEMM C = A A, 1,048,576^2 uniform, 16 per row
@@ -407,6 +410,62 @@ class Batched(Workload):
         return flops, t_total, "oracle FP64 forward on the first %d of %d tiles" % (used, self.count)
 
 
+class StationaryA(Workload):
+    """The stationary-A local step (Section 3.2, Algorithm 1) on one GPU: the owner of A(i,k)
+    forms the partial products P_j = A(i,k) B(k,j) (accumulate = 0) for every column block j,
+    and the owner of each C(i,j) adds its partial (spmm_tile_accumulate).  Here both owners are
+    this GPU: tile (0,0) of the R-MAT scale-22 4 x 4 grid against 4 column blocks of N = 128."""
+
+    def __init__(self, name, config):
+        self.name = name
+        self.config = config
+        self.kernel = "spmm_fwd (partials) + spmm_tile_accumulate"
+
+    def setup(self):
+        import torch
+        import synth
+        from paper_2311_18141_amd import ops
+        t0 = time.time()
+        self.A = synth.rmat_row_block(22, 16, 4, 0, seed=2).tiles[0]
+        A = self.A
+        _log("%s: inputs generated in %.1f s (nnz %d)" % (self.name, time.time() - t0, A.nnz))
+        self.N, self.J = 128, 4
+        rng = synth.streams(2)[2]
+        dev = "cuda:0"
+        self.Bh = [synth.dense(A.cols, self.N, rng) for _ in range(self.J)]
+        self.B = [torch.from_numpy(b).to(dev) for b in self.Bh]
+        self.C = [torch.from_numpy(synth.dense(A.rows, self.N, rng)).to(dev) for _ in range(self.J)]
+        self.P = [torch.empty(A.rows, self.N, device=dev) for _ in range(self.J)]
+        d = (torch.from_numpy(A.rowptr).to(dev), torch.from_numpy(A.colind).to(dev),
+             torch.from_numpy(A.values).to(dev), A.cols)
+        self.tile = ops.spmm_tile_create(A.rows, [d], validate=True, **_handle_opts("rmat22_rowblock0_4x4_n128"))
+        self.config["variant"] = _apply_pin("rmat22_rowblock0_4x4_n128", self.tile, self.N, torch.float32)
+        self.ws = self.tile.workspace(self.N)
+        self.flops = 2.0 * A.nnz * self.N * self.J
+        fwd = 8 * A.nnz + 4 * (A.rows + 1) + 4 * (A.cols + A.rows) * self.N
+        acc = 3 * 4 * A.rows * self.N
+        self.alg_bytes = float(self.J * (fwd + acc))
+        self.config = dict(self.config, nnz=A.nnz, rows=A.rows, N=self.N, column_blocks=self.J)
+
+    def step(self):
+        from paper_2311_18141_amd import ops
+        for j in range(self.J):
+            ops.spmm_fwd(self.tile, [self.B[j]], C=self.P[j], workspace=self.ws)
+            ops.spmm_tile_accumulate(self.C[j], self.P[j])
+
+    def cpu_sample(self):
+        import oracle
+        A = self.A
+        lens = A.row_lengths()
+        target = 2.0e10 / (2.0 * self.N)
+        r = int(min(A.rows, np.searchsorted(np.cumsum(lens), target) + 1))
+        rows = np.arange(r, dtype=np.int64)
+        t0 = time.perf_counter()
+        oracle.spmm([(A.rowptr, A.colind, A.values)], [self.Bh[0]], rows=rows, scale=False)
+        dt = time.perf_counter() - t0
+        return 2.0 * float(lens[:r].sum()) * self.N, dt, "oracle FP64 partial product on rows [0, %d)" % r
+
+
 class SpgemmAA(Workload):
     """Local SpGEMM C = A A (the local step of the paper's SpGEMM experiments).  A step is the
     numeric phase (spgemm_compute); the symbolic phase (plan creation) is timed beside it."""
@@ -498,6 +557,10 @@ def workloads():
     import synth
     return {
         "copy_1gib": lambda: CopyCalibration(),
+        "stationary_a_rmat22_tile00_n128x4": lambda: StationaryA(
+            "stationary_a_rmat22_tile00_n128x4",
+            {"workload": "stationary_a_rmat22_tile00_n128x4", "matrix": "tile (0,0) of the R-MAT scale 22, "
+             "edge factor 16 4x4 grid; 4 column blocks of N = 128", "seed": 2}),
         "spgemm_rmat18_ef16_aa": lambda: SpgemmAA(
             "spgemm_rmat18_ef16_aa", lambda: synth.rmat_csr(18, 16, seed=7),
             {"workload": "spgemm_rmat18_ef16_aa", "matrix": "R-MAT scale 18, edge factor 16, "
