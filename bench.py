@@ -83,17 +83,19 @@ def _log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-# Sources of the kernels the SpMM workloads launch (forward, split-row fix-up, SDDMM,
-# value gather): stored counter readings are valid while these are unchanged.
-KERNEL_SOURCES = ("elem.hpp", "fwd_common.hpp", "fwd.hip", "bwd.hip")
+# Sources of the kernels a workload launches (forward, split-row fix-up; for the
+# backward also SDDMM and value gather): a stored counter reading is valid while these
+# are unchanged.
+FWD_SOURCES = ("elem.hpp", "fwd_common.hpp", "fwd.hip")
+KERNEL_SOURCES = {"powerlaw2m_n128_fwdbwd": FWD_SOURCES + ("bwd.hip",)}
 
 
-def kernel_source_digest() -> str:
-    """SHA-256 over the SpMM kernel sources, to tell whether stored counter readings still describe them."""
+def kernel_source_digest(workload: str = "") -> str:
+    """SHA-256 over the sources of the kernels `workload` launches (the forward's by default)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2311_18141_amd", "csrc")
-    for name in KERNEL_SOURCES:
+    for name in KERNEL_SOURCES.get(workload, FWD_SOURCES):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
@@ -111,7 +113,7 @@ def stored_traffic(workload: str):
             if ":" in line and line.startswith("- "):
                 k, v = line[2:].split(":", 1)
                 fields[k.strip()] = v.strip().strip("`")
-    if fields.get("source_sha256") != kernel_source_digest():
+    if fields.get("source_sha256") != kernel_source_digest(workload):
         return None
     try:
         return float(fields["hbm_bytes_per_step"])

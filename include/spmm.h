@@ -127,7 +127,7 @@ spmm_status spmm_tile_export_transpose(spmm_tile_t tile, int32_t* rowptrT, int32
    bit-for-bit on integer-valued inputs). */
 #define SPMM_KERNEL_AUTO 0
 #define SPMM_KERNEL_ROWSPLIT 1   /* a group of `lanes` lanes owns one row and a column window */
-#define SPMM_KERNEL_STREAM 2     /* a wave streams the non-zeros of 64 consecutive rows */
+#define SPMM_KERNEL_STREAM 2     /* a wave streams the non-zeros of `lanes` (4..64) consecutive rows */
 typedef struct {
   int32_t kind;    /* SPMM_KERNEL_* */
   int32_t lanes;   /* ROWSPLIT: lanes per row; STREAM: rows per wave; 4..64, power of two;
@@ -181,15 +181,18 @@ spmm_status spmm_bwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes /* 
 
 /*
  * Backward of C = A B for a K = 1 handle built with SPMM_TILE_TRANSPOSE, given
- * dC = dL/dC (device, rows x N, ld lddc) and B (device, cols x N, ld ldb), FP32:
- *   dA_values[p] = sum_n dC[i, n] * B[colind[p], n]   for p in row i   (nullable: skipped)
- *   dB = A^T dC   (device, cols x N, ld lddb; nullable: skipped)
- * dA is on A's pattern, in A's CSR order; no gradient flows to the pattern.
- * Asynchronous.  Errors: INVALID_ARG, UNSUPPORTED (no transpose, num_k > 1,
- * BF16), WORKSPACE, HIP.
+ * dC = dL/dC (device, rows x N, ld lddc) and B (device, cols x N, ld ldb), both in
+ * `dtype` (FP32, or BF16 for the backward of a BF16 forward):
+ *   dA_values[p] = sum_n dC[i, n] * B[colind[p], n]   for p in row i   (FP32; nullable: skipped)
+ *   dB = A^T dC   (device, cols x N, ld lddb, in `dtype`; nullable: skipped)
+ * Products and sums are FP32; a BF16 dB is rounded once (RNE) at the store.  dA is
+ * on A's pattern, in A's CSR order; no gradient flows to the pattern.  The gradient
+ * pass is not in the paper: it is this library's addition (the forward's adjoint).
+ * Asynchronous.  Errors: INVALID_ARG, UNSUPPORTED (no transpose, num_k > 1, ld too
+ * large), WORKSPACE, HIP.
  */
-spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* B, int64_t ldb,
-                     int64_t N, float* dA_values, float* dB, int64_t lddb, void* workspace,
+spmm_status spmm_bwd(spmm_tile_t A, const void* dC, int64_t lddc, const void* B, int64_t ldb, int64_t N,
+                     spmm_dtype dtype, float* dA_values, void* dB, int64_t lddb, void* workspace,
                      size_t ws_bytes, void* stream);
 
 /*
@@ -197,7 +200,7 @@ spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* 
  * one launch per kernel class present in the batch (a class is one kernel shape:
  * stream V, row-split G, or split-row unit V), plus, when some tile has split rows,
  * a fix-up launch.  The batch form and its load balancing are additions of this
- * library; they stand in, on one GPU, for the work claiming of Section 4 (a remote
+ * library; they stand in, on one GPU, for the work claiming of Section 3.4 (a remote
  * fetch-and-add per work item, Algorithm 3).
  *
  * spmm_batch_create builds, synchronously, the work list: items of up to 64 rows

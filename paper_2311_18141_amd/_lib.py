@@ -68,7 +68,7 @@ EXPORTS = {
     "spmm_fwd_workspace_bytes": (c_int, [c_vp, c_i64, c_vp]),
     "spmm_fwd": (c_int, [c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_i64, c_int, c_i64, c_int, c_vp, c_size, c_vp]),
     "spmm_bwd_workspace_bytes": (c_int, [c_vp, c_i64, c_vp]),
-    "spmm_bwd": (c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, c_i64, c_vp, c_vp, c_i64, c_vp, c_size, c_vp]),
+    "spmm_bwd": (c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, c_i64, c_int, c_vp, c_vp, c_i64, c_vp, c_size, c_vp]),
     "spgemm_create": (c_int, [c_i64, c_vp, c_vp, c_uint, c_vp, c_vp]),
     "spgemm_destroy": (c_int, [c_vp]),
     "spgemm_info": (c_int, [c_vp, c_vp, c_vp]),

@@ -1,8 +1,8 @@
 """torch.autograd.Function for C = A B with A in CSR (one tile), A's values and B differentiable.
 
 Forward runs spmm_fwd; backward runs spmm_bwd: dA on A's pattern (sampled
-dense-dense product) and dB = A^T dC through the transposed structure.  No
-gradient flows to the pattern.  The tile handle must have been created with
+dense-dense product, FP32 like A's values) and dB = A^T dC through the transposed
+structure, in B's dtype (FP32 or BF16).  No gradient flows to the pattern.  The tile handle must have been created with
 transpose=True over the same ``values`` tensor that is passed to ``apply``
 (values are read live, so in-place updates of that tensor are seen).
 """
@@ -31,7 +31,8 @@ class SpMMFunction(torch.autograd.Function):
         want_dA, want_dB = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         if not (want_dA or want_dB):
             return None, None, None
-        dA, dB = spmm_bwd(ctx.tile, dC.contiguous().float(), B.contiguous(), want_dA=want_dA, want_dB=want_dB)
+        # dC arrives in C's dtype (B's): FP32, or BF16 for a BF16 forward (FP32 accumulation)
+        dA, dB = spmm_bwd(ctx.tile, dC.contiguous().to(B.dtype), B.contiguous(), want_dA=want_dA, want_dB=want_dB)
         return dA, dB, None
 
 

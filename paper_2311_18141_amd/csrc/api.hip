@@ -727,9 +727,13 @@ spmm_status spmm_tile_accumulate(void* C, int64_t ldc, const void* Ptile, int64_
   return SPMM_OK;
 }
 
-spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* B, int64_t ldb, int64_t N,
-                     float* dA_values, float* dB, int64_t lddb, void* workspace, size_t ws_bytes, void* stream) {
+spmm_status spmm_bwd(spmm_tile_t A, const void* dC, int64_t lddc, const void* B, int64_t ldb, int64_t N,
+                     spmm_dtype dtype, float* dA_values, void* dB, int64_t lddb, void* workspace, size_t ws_bytes,
+                     void* stream) {
   if (!A) return fail(SPMM_ERR_INVALID_ARG, "A is null");
+  if (dtype != SPMM_F32 && dtype != SPMM_BF16) return fail(SPMM_ERR_INVALID_ARG, "unknown dtype");
+  const DT dt = dtype == SPMM_F32 ? DT::F32 : DT::BF16;
+  const int64_t esize = dt == DT::F32 ? 4 : 2;
   if (A->num_k != 1) return fail(SPMM_ERR_UNSUPPORTED, "spmm_bwd needs a single-tile handle");
   if (!A->has_t) return fail(SPMM_ERR_UNSUPPORTED, "handle was created without SPMM_TILE_TRANSPOSE");
   if (N < 1) return fail(SPMM_ERR_INVALID_ARG, "N=%lld < 1", (long long)N);
@@ -738,7 +742,7 @@ spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* 
   if (dA_values && !B && A->t[0].cols > 0) return fail(SPMM_ERR_INVALID_ARG, "B is null");
   if (dA_values && ldb < N) return fail(SPMM_ERR_INVALID_ARG, "ldb < N");
   if (dB && lddb < N) return fail(SPMM_ERR_INVALID_ARG, "lddb < N");
-  if (lddc * 4 >= ((int64_t)1 << 32)) return fail(SPMM_ERR_UNSUPPORTED, "lddc * 4 >= 2^32");
+  if (lddc * esize >= ((int64_t)1 << 32)) return fail(SPMM_ERR_UNSUPPORTED, "lddc too large");
   const spmm_csr& t = A->t[0];
   const size_t need = dB ? bwd_workspace(A, N) : 0;
   if (need > 0) {
@@ -763,10 +767,10 @@ spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* 
     P.ldb = ldb;
     P.N = N;
     P.dA = dA_values;
-    const uintptr_t a = reinterpret_cast<uintptr_t>(dC) | reinterpret_cast<uintptr_t>(B) | (uintptr_t)(lddc * 4) |
-                        (uintptr_t)(ldb * 4);
-    int V = 4;
-    while (V > 1 && ((N % V) != 0 || (a % (uintptr_t)(V * 4)) != 0)) V /= 2;
+    const uintptr_t a = reinterpret_cast<uintptr_t>(dC) | reinterpret_cast<uintptr_t>(B) |
+                        (uintptr_t)(lddc * esize) | (uintptr_t)(ldb * esize);
+    int V = (int)(16 / esize);
+    while (V > 1 && ((N % V) != 0 || (a % (uintptr_t)(V * esize)) != 0)) V /= 2;
     // Column slices: one launch per slice of `slice` columns (all of N when 0).
     const int64_t slice = (A->bwd_slice > 0 && A->bwd_slice < N && (A->bwd_slice % V) == 0) ? A->bwd_slice : N;
     const int64_t need_lanes = (slice + V - 1) / V;
@@ -785,7 +789,7 @@ spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* 
       P.c_begin = c;
       P.c_end = c + slice < N ? c + slice : N;
       P.accumulate = c > 0 ? 1 : 0;
-      HIP_TRY(spmm::launch_sddmm(P, G, V, U, s));
+      HIP_TRY(spmm::launch_sddmm(P, G, V, U, dt, s));
     }
   }
   if (dB && t.cols > 0) {
@@ -811,9 +815,9 @@ spmm_status spmm_bwd(spmm_tile_t A, const float* dC, int64_t lddc, const float* 
     P.n_long = A->planT.n_long;
     P.partial = static_cast<float*>(workspace);
     P.ldp = (int64_t)partial_ld(N);
-    const uintptr_t a = reinterpret_cast<uintptr_t>(dC) | reinterpret_cast<uintptr_t>(dB) | (uintptr_t)(lddc * 4) |
-                        (uintptr_t)(lddb * 4);
-    HIP_TRY(spmm::launch_fwd(P, pick_variant(N, DT::F32, a, t.cols), DT::F32, s));
+    const uintptr_t a = reinterpret_cast<uintptr_t>(dC) | reinterpret_cast<uintptr_t>(dB) |
+                        (uintptr_t)(lddc * esize) | (uintptr_t)(lddb * esize);
+    HIP_TRY(spmm::launch_fwd(P, pick_variant(N, dt, a, t.cols), dt, s));
   }
   return SPMM_OK;
 }

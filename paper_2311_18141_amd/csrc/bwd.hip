@@ -1,5 +1,6 @@
 // Backward of C = A B with respect to A's stored values: the sampled dense-dense
-// product on A's pattern,  dA[p] = <dC[row(p), :], B[colind[p], :]>.
+// product on A's pattern,  dA[p] = <dC[row(p), :], B[colind[p], :]>, with dC and B
+// in FP32 or BF16 (FP32 products and sums; dA in FP32, as A's values).
 // (dB = A^T dC reuses the forward kernels on the transposed structure.)
 //
 // A group of G lanes owns U consecutive non-zeros.  Lane l < U of the group reads the
@@ -26,9 +27,12 @@ __device__ __forceinline__ float group_sum(float x) {
   return x;
 }
 
-template <int G, int V, int U>
+template <int G, int V, int U, typename E>
 __global__ void __launch_bounds__(kBlock) sddmm_kernel(SddmmParams P) {
   static_assert(U <= G, "one lane per non-zero reads the structure");
+  using T = typename E::T;
+  const T* Bp = static_cast<const T*>(P.B);
+  const T* dCp = static_cast<const T*>(P.dC);
   constexpr int GPB = kBlock / G;
   const int gl = threadIdx.x & (G - 1);
   // grid-stride over groups of U non-zeros (the grid is capped below 2^32 threads)
@@ -53,12 +57,12 @@ __global__ void __launch_bounds__(kBlock) sddmm_kernel(SddmmParams P) {
     for (int64_t col = P.c_begin + (int64_t)gl * V; col < P.c_end; col += G * V) {
       float x[U][V], y[U][V];
 #pragma unroll
-      for (int u = 0; u < U; ++u) load_f32v<V>(P.B + (int64_t)c[u] * P.ldb + col, y[u]);
-      load_f32v<V>(P.dC + (int64_t)r[0] * P.lddc + col, x[0]);
+      for (int u = 0; u < U; ++u) load_vec<E, V>(Bp + (int64_t)c[u] * P.ldb + col, y[u]);
+      load_vec<E, V>(dCp + (int64_t)r[0] * P.lddc + col, x[0]);
 #pragma unroll
       for (int u = 1; u < U; ++u) {
         if (r[u] != r[u - 1]) {
-          load_f32v<V>(P.dC + (int64_t)r[u] * P.lddc + col, x[u]);
+          load_vec<E, V>(dCp + (int64_t)r[u] * P.lddc + col, x[u]);
         } else {
 #pragma unroll
           for (int e = 0; e < V; ++e) x[u][e] = x[u - 1][e];
@@ -83,7 +87,7 @@ __global__ void __launch_bounds__(kBlock) sddmm_kernel(SddmmParams P) {
   }
 }
 
-template <int V, int U>
+template <typename E, int V, int U>
 hipError_t launch_sddmm_vu(const SddmmParams& P, int G, hipStream_t s) {
   auto go = [&](auto kern, int gpb) {
     const int64_t per_block = (int64_t)gpb * U;
@@ -93,22 +97,22 @@ hipError_t launch_sddmm_vu(const SddmmParams& P, int G, hipStream_t s) {
     return hipGetLastError();
   };
   switch (G) {
-    case 4: if constexpr (U <= 4) return go(sddmm_kernel<4, V, U>, kBlock / 4); else return hipErrorInvalidValue;
-    case 8: return go(sddmm_kernel<8, V, U>, kBlock / 8);
-    case 16: return go(sddmm_kernel<16, V, U>, kBlock / 16);
-    case 32: return go(sddmm_kernel<32, V, U>, kBlock / 32);
-    case 64: return go(sddmm_kernel<64, V, U>, kBlock / 64);
+    case 4: if constexpr (U <= 4) return go(sddmm_kernel<4, V, U, E>, kBlock / 4); else return hipErrorInvalidValue;
+    case 8: return go(sddmm_kernel<8, V, U, E>, kBlock / 8);
+    case 16: return go(sddmm_kernel<16, V, U, E>, kBlock / 16);
+    case 32: return go(sddmm_kernel<32, V, U, E>, kBlock / 32);
+    case 64: return go(sddmm_kernel<64, V, U, E>, kBlock / 64);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int V>
+template <typename E, int V>
 hipError_t launch_sddmm_v(const SddmmParams& P, int G, int U, hipStream_t s) {
   switch (U) {
-    case 1: return launch_sddmm_vu<V, 1>(P, G, s);
-    case 2: return launch_sddmm_vu<V, 2>(P, G, s);
-    case 4: return launch_sddmm_vu<V, 4>(P, G, s);
-    case 8: return launch_sddmm_vu<V, 8>(P, G, s);
+    case 1: return launch_sddmm_vu<E, V, 1>(P, G, s);
+    case 2: return launch_sddmm_vu<E, V, 2>(P, G, s);
+    case 4: return launch_sddmm_vu<E, V, 4>(P, G, s);
+    case 8: return launch_sddmm_vu<E, V, 8>(P, G, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -174,11 +178,20 @@ hipError_t launch_gather_values(const int32_t* perm, const float* values, float*
   return hipGetLastError();
 }
 
-hipError_t launch_sddmm(const SddmmParams& P, int G, int V, int U, hipStream_t s) {
+hipError_t launch_sddmm(const SddmmParams& P, int G, int V, int U, DT dt, hipStream_t s) {
+  if (dt == DT::F32) {
+    switch (V) {
+      case 1: return launch_sddmm_v<F32E, 1>(P, G, U, s);
+      case 2: return launch_sddmm_v<F32E, 2>(P, G, U, s);
+      case 4: return launch_sddmm_v<F32E, 4>(P, G, U, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (V) {
-    case 1: return launch_sddmm_v<1>(P, G, U, s);
-    case 2: return launch_sddmm_v<2>(P, G, U, s);
-    case 4: return launch_sddmm_v<4>(P, G, U, s);
+    case 1: return launch_sddmm_v<BF16E, 1>(P, G, U, s);
+    case 2: return launch_sddmm_v<BF16E, 2>(P, G, U, s);
+    case 4: return launch_sddmm_v<BF16E, 4>(P, G, U, s);
+    case 8: return launch_sddmm_v<BF16E, 8>(P, G, U, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -132,9 +132,9 @@ struct SddmmParams {
   const int32_t* rowid;
   const int32_t* colind;
   int64_t nnz;
-  const float* dC;
+  const void* dC;          // FP32 or BF16, as the launch's dtype
   int64_t lddc;
-  const float* B;
+  const void* B;
   int64_t ldb;
   int64_t N;
   float* dA;
@@ -144,7 +144,7 @@ struct SddmmParams {
 // out[q] = values[perm[q]] for q < nnz.
 hipError_t launch_gather_values(const int32_t* perm, const float* values, float* out, int64_t nnz, hipStream_t s);
 // G lanes per group, V columns per lane and load, U non-zeros per group.
-hipError_t launch_sddmm(const SddmmParams& P, int G, int V, int U, hipStream_t s);
+hipError_t launch_sddmm(const SddmmParams& P, int G, int V, int U, DT dt, hipStream_t s);
 hipError_t launch_accumulate(void* C, int64_t ldc, const void* Pt, int64_t ldp, int64_t rows, int64_t N, DT dt,
                              int V, hipStream_t s);
 

@@ -217,12 +217,15 @@ def spmm_bwd(tile: Tile, dC: torch.Tensor, B: torch.Tensor, want_dA: bool = True
              dA: Optional[torch.Tensor] = None, dB: Optional[torch.Tensor] = None,
              workspace: Optional[torch.Tensor] = None,
              stream: Optional[torch.cuda.Stream] = None) -> Tuple[Optional[torch.Tensor], Optional[torch.Tensor]]:
-    """(dA on A's pattern, dB = A^T dC) for a single-tile handle built with transpose=True."""
+    """(dA on A's pattern, dB = A^T dC) for a single-tile handle built with transpose=True.
+
+    dC and B share one dtype (float32 or bfloat16); dA is float32 (A's values are), dB has dC's dtype."""
     if tile.num_k != 1:
         raise ValueError("spmm_bwd needs a single-tile handle")
     N = dC.shape[1]
-    if dC.dtype != torch.float32 or B.dtype != torch.float32:
-        raise ValueError("spmm_bwd takes float32 dC and B")
+    dt = dC.dtype
+    if dt not in _DTYPES or B.dtype != dt:
+        raise ValueError("spmm_bwd takes dC and B of one dtype, float32 or bfloat16")
     if dC.shape != (tile.rows, N) or B.shape != (tile.cols[0], N):
         raise ValueError("dC must be (%d, N) and B (%d, N)" % (tile.rows, tile.cols[0]))
     lddc = _row_major_ld(dC, "dC")
@@ -230,13 +233,17 @@ def spmm_bwd(tile: Tile, dC: torch.Tensor, B: torch.Tensor, want_dA: bool = True
     if want_dA and dA is None:
         dA = torch.empty(tile.nnz[0], dtype=torch.float32, device=dC.device)
     if want_dB and dB is None:
-        dB = torch.empty(tile.cols[0], N, dtype=torch.float32, device=dC.device)
+        dB = torch.empty(tile.cols[0], N, dtype=dt, device=dC.device)
+    if want_dA and (dA.dtype != torch.float32 or dA.numel() < tile.nnz[0]):
+        raise ValueError("dA must be float32 with nnz entries")
+    if want_dB and (dB.dtype != dt or dB.shape != (tile.cols[0], N)):
+        raise ValueError("dB must be %s of shape (%d, %d)" % (dt, tile.cols[0], N))
     lddb = _row_major_ld(dB, "dB") if want_dB else 0
     if workspace is None and want_dB:
         workspace = tile.workspace(N, "bwd")
     ws_ptr = workspace.data_ptr() if workspace is not None else None
     ws_n = workspace.numel() * workspace.element_size() if workspace is not None else 0
-    check(lib().spmm_bwd(tile.handle, dC.data_ptr(), lddc, B.data_ptr(), ldb, N,
+    check(lib().spmm_bwd(tile.handle, dC.data_ptr(), lddc, B.data_ptr(), ldb, N, _DTYPES[dt],
                          dA.data_ptr() if want_dA else None, dB.data_ptr() if want_dB else None, lddb,
                          ws_ptr, ws_n, _stream_ptr(stream)))
     return (dA if want_dA else None), (dB if want_dB else None)

@@ -122,7 +122,7 @@ def test_null_handle_calls():
     assert L.spmm_fwd_workspace_bytes(None, 8, ctypes.byref(n)) == 1
     assert L.spmm_bwd_workspace_bytes(None, 8, ctypes.byref(n)) == 1
     assert L.spmm_fwd(None, 0, None, None, 0, None, 8, 0, 8, 0, None, 0, None) == 1
-    assert L.spmm_bwd(None, None, 8, None, 8, 8, None, None, 8, None, 0, None) == 1
+    assert L.spmm_bwd(None, None, 8, None, 8, 8, 0, None, None, 8, None, 0, None) == 1
     assert L.spmm_tile_export_transpose(None, None, None, None, None) == 1
 
 

@@ -204,3 +204,68 @@ def test_sddmm_variant_argument_errors():
     with pytest.raises(ops.SpmmError):
         ops.spmm_tile_set_sddmm_variant(tile, 0, 8, 4)
     ops.spmm_tile_set_sddmm_variant(tile, 32, 0)   # clearing an absent entry is fine
+
+
+@pytest.mark.parametrize("name", ["powerlaw", "hot_column", "rmat"])
+def test_backward_bf16_vs_oracle(name):
+    """BF16 dC and B (the backward of a BF16 forward): dA in FP32 within the FP32 bound of the
+    oracle on bf16(dC), bf16(B); dB rounded once to BF16, within the BF16 bound."""
+    G.note("backward bf16 %s" % name)
+    A = _case(name)
+    rng = _rng(41 + len(name))
+    N = 128
+    B = synth.dense(A.cols, N, rng, "normal")
+    dC = synth.dense(A.rows, N, rng, "normal")
+    tile = G.make_tile([A], transpose=True)
+    dA, dB = ops.spmm_bwd(tile, G.dense_dev(dC, torch.bfloat16), G.dense_dev(B, torch.bfloat16))
+    torch.cuda.synchronize()
+    assert dA.dtype == torch.float32 and dB.dtype == torch.bfloat16
+    Bt, dCt = G.bf16_as_f32(B), G.bf16_as_f32(dC)
+    rA, SA = oracle.sddmm(A.rowptr, A.colind, dCt, Bt)
+    st = compare.fp32_stats(dA.cpu().numpy(), rA, SA, n_terms=np.full(A.nnz, N))
+    assert compare.fp32_ok(st), st
+    rB, SB = oracle.spmm_t(A.rowptr, A.colind, A.values, A.cols, dCt)
+    G.assert_bf16_close(dB.float().cpu().numpy(), rB, SB, what="dB bf16")
+
+
+def test_backward_bf16_integer_exact():
+    """Integer data: dA exact; dB equals the exact sum rounded once to BF16 (round to nearest even)."""
+    G.note("backward bf16 integer exact")
+    rng = _rng(43)
+    M, K, N = 3000, 2500, 64
+    L = rng.integers(0, 30, size=M)
+    L[7] = 2400
+    A = synth.random_csr(M, K, L, rng, "int8")
+    B = synth.dense(K, N, rng, "int8")
+    dC = synth.dense(M, N, rng, "int8")
+    tile = G.make_tile([A], transpose=True, long_row=64, segment=16)
+    dA, dB = ops.spmm_bwd(tile, G.dense_dev(dC, torch.bfloat16), G.dense_dev(B, torch.bfloat16))
+    torch.cuda.synchronize()
+    rA, _ = oracle.sddmm(A.rowptr, A.colind, dC, B)
+    assert np.array_equal(dA.cpu().numpy().astype(np.float64), rA)
+    rB, _ = oracle.spmm_t(A.rowptr, A.colind, A.values, K, dC)
+    assert np.abs(rB).max() < 2 ** 24          # exact in FP32 before the one rounding
+    want = oracle.f32_to_bf16(rB.astype(np.float32))
+    got = dB.cpu().view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(got, want)
+
+
+def test_autograd_bf16():
+    G.note("autograd bf16")
+    rng = _rng(44)
+    A = synth.powerlaw_csr(4096, 3000, 16, 1024, seed=21)
+    B = synth.dense(A.cols, 64, rng, "normal")
+    dC = synth.dense(A.rows, 64, rng, "normal")
+    rp, ci, va, _ = G.to_dev(A)
+    tile = ops.spmm_tile_create(A.rows, [(rp, ci, va, A.cols)], validate=True, transpose=True)
+    values = va.requires_grad_(True)
+    Bt = G.dense_dev(B, torch.bfloat16).requires_grad_(True)
+    C = SpMMFunction.apply(values, Bt, tile)
+    assert C.dtype == torch.bfloat16
+    C.backward(G.dense_dev(dC, torch.bfloat16))
+    assert values.grad.dtype == torch.float32 and Bt.grad.dtype == torch.bfloat16
+    Btf, dCt = G.bf16_as_f32(B), G.bf16_as_f32(dC)
+    rA, SA = oracle.sddmm(A.rowptr, A.colind, dCt, Btf)
+    assert compare.fp32_ok(compare.fp32_stats(values.grad.cpu().numpy(), rA, SA))
+    rB, SB = oracle.spmm_t(A.rowptr, A.colind, A.values, A.cols, dCt)
+    G.assert_bf16_close(Bt.grad.float().cpu().numpy(), rB, SB, what="dB")
