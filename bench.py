@@ -12,6 +12,7 @@ times dense B_k of 1,048,576 x 128 FP32, accumulated over its 4 k-tiles into a
     er4096_n32              4096^2 uniform tile, 16 non-zeros per row, N = 32, forward
     powerlaw2m_n128_fwdbwd  2,097,152^2 heavy-tailed rows (mean 32, max 65,536), N = 128,
                             forward + dA (sampled dense-dense product) + dB = A^T dC
+    powerlaw2m_n128_fwdbwd_bf16  the same with B, C, dC and dB in BF16 (FP32 accumulation)
     rmat23_n256_bf16        R-MAT scale 23, edge factor 32, N = 256, BF16 B and C
     rmat23_n256_f32         the same with FP32 B and C
     stationary_a_rmat22_tile00_n128x4
@@ -55,6 +56,7 @@ AUTOTUNE = False
 PINNED = {
     "rmat22_rowblock0_4x4_n128": {"variant": ("stream", 64, 1), "long_row": 128, "segment": 64},
     "powerlaw2m_n128_fwdbwd": {"variant": ("stream", 64, 1), "long_row": 128, "segment": 64},
+    "powerlaw2m_n128_fwdbwd_bf16": {"variant": ("stream", 64, 2), "long_row": 128, "segment": 64},
     "rmat23_n256_bf16": {"variant": ("rowsplit", 16, 8), "long_row": 256, "segment": 128},
     "rmat23_n256_f32": {"variant": ("stream", 64, 2), "long_row": 256, "segment": 128},
 }
@@ -239,12 +241,13 @@ class TileRowForward(Workload):
 class ForwardBackward(Workload):
     """Forward, dA = SDDMM on A's pattern, dB = A^T dC: three passes of 2 nnz N flops."""
 
-    def __init__(self, name, make_tile, N, config):
+    def __init__(self, name, make_tile, N, config, dtype="f32"):
         self.name = name
         self.make_tile = make_tile
         self.N = N
         self.config = config
-        self.kernel = "spmm_fwd + spmm_bwd (fwd_main, fwd_fixup, sddmm_kernel)"
+        self.dtype = dtype
+        self.kernel = "spmm_fwd + spmm_bwd (fwd_stream, fwd_fixup, sddmm_kernel, gather_values)"
 
     def setup(self):
         import torch
@@ -261,25 +264,27 @@ class ForwardBackward(Workload):
              torch.from_numpy(self.A.values).to(dev), self.A.cols)
         self.tile = ops.spmm_tile_create(self.A.rows, [t], validate=True, transpose=True,
                                          **_handle_opts(self.name))
-        self.B = torch.from_numpy(self.Bh).to(dev)
-        self.dC = torch.from_numpy(self.dCh).to(dev)
-        self.C = torch.empty(self.A.rows, self.N, device=dev)
+        tdt = torch.float32 if self.dtype == "f32" else torch.bfloat16
+        self.B = torch.from_numpy(self.Bh).to(tdt).to(dev)
+        self.dC = torch.from_numpy(self.dCh).to(tdt).to(dev)
+        self.C = torch.empty(self.A.rows, self.N, device=dev, dtype=tdt)
         if AUTOTUNE:
             t0 = time.time()
             chosen = ops.spmm_tile_autotune(self.tile, [self.B], self.C, tune_plan=True)
             _log("%s: forward autotuned in %.1f s: %s" % (self.name, time.time() - t0, chosen))
             self.config["variant"] = chosen
         else:
-            self.config["variant"] = _apply_pin(self.name, self.tile, self.N, torch.float32)
+            self.config["variant"] = _apply_pin(self.name, self.tile, self.N, tdt)
         self.dA = torch.empty(self.A.nnz, device=dev)
-        self.dB = torch.empty(self.A.cols, self.N, device=dev)
+        self.dB = torch.empty(self.A.cols, self.N, device=dev, dtype=tdt)
         self.wsf = self.tile.workspace(self.N, "fwd")
         self.wsb = self.tile.workspace(self.N, "bwd")
         A, N = self.A, self.N
+        e = 4 if self.dtype == "f32" else 2
         self.flops = 3 * 2.0 * A.nnz * N
-        fwd = 8 * A.nnz + 4 * (A.rows + 1) + 4 * A.cols * N + 4 * A.rows * N
-        sddmm = 4 * A.nnz + 4 * (A.rows + 1) + 4 * A.rows * N + 4 * A.cols * N + 4 * A.nnz
-        dB = 4 * (A.cols + 1) + 12 * A.nnz + 4 * A.rows * N + 4 * A.cols * N
+        fwd = 8 * A.nnz + 4 * (A.rows + 1) + e * A.cols * N + e * A.rows * N
+        sddmm = 4 * A.nnz + 4 * (A.rows + 1) + e * A.rows * N + e * A.cols * N + 4 * A.nnz
+        dB = 4 * (A.cols + 1) + 12 * A.nnz + e * A.rows * N + e * A.cols * N
         self.alg_bytes = float(fwd + sddmm + dB)
         st = self.tile.stats()
         self.config = dict(self.config, nnz=A.nnz, rows=A.rows, N=N,
@@ -588,6 +593,10 @@ def workloads():
         "rmat23_n256_f32": lambda: TileRowForward(
             "rmat23_n256_f32", lambda: [synth.rmat_csr(23, 32, seed=5)], 256, "f32",
             {"workload": "rmat23_n256_f32", "matrix": "R-MAT scale 23, edge factor 32", "seed": 5}),
+        "powerlaw2m_n128_fwdbwd_bf16": lambda: ForwardBackward(
+            "powerlaw2m_n128_fwdbwd_bf16", lambda: synth.powerlaw_csr(1 << 21, 1 << 21, 32, 65536, seed=3), 128,
+            {"workload": "powerlaw2m_n128_fwdbwd_bf16", "matrix": "2,097,152^2, Pareto(2.1) row degrees, mean 32, "
+             "max 65,536, values N(0,1)/sqrt(deg); B, C, dC, dB in BF16", "seed": 3}, dtype="bf16"),
         "powerlaw2m_n128_fwdbwd": lambda: ForwardBackward(
             "powerlaw2m_n128_fwdbwd", lambda: synth.powerlaw_csr(1 << 21, 1 << 21, 32, 65536, seed=3), 128,
             {"workload": "powerlaw2m_n128_fwdbwd", "matrix": "2,097,152^2, Pareto(2.1) row degrees, mean 32, "
