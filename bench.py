@@ -214,7 +214,8 @@ class TileRowForward(Workload):
         self.alg_bytes = float(_fwd_bytes(self.tiles, self.N, 4 if self.dtype == "f32" else 2))
         self.config = dict(self.config, nnz=nnz, rows=self.tiles[0].rows, N=self.N, k_tiles=len(self.tiles),
                            tile_stats={k: v for k, v in self.tile.stats().items()
-                                       if k in ("max_row", "empty_rows", "long_rows", "segments")})
+                                       if k in ("max_row", "empty_rows", "long_rows", "segments", "long_row",
+                                                "segment")})
 
     def step(self):
         from paper_2311_18141_amd import ops
@@ -289,7 +290,7 @@ class ForwardBackward(Workload):
         st = self.tile.stats()
         self.config = dict(self.config, nnz=A.nnz, rows=A.rows, N=N,
                            tile_stats={k: st[k] for k in ("max_row", "empty_rows", "long_rows", "segments",
-                                                          "long_rows_t", "segments_t")})
+                                                          "long_rows_t", "segments_t", "long_row", "segment")})
 
     def step(self):
         from paper_2311_18141_amd import ops
