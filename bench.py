@@ -56,7 +56,7 @@ AUTOTUNE = False
 PINNED = {
     "rmat22_rowblock0_4x4_n128": {"variant": ("stream", 64, 1), "long_row": 128, "segment": 64},
     "powerlaw2m_n128_fwdbwd": {"variant": ("stream", 64, 1), "long_row": 128, "segment": 64},
-    "powerlaw2m_n128_fwdbwd_bf16": {"variant": ("stream", 64, 2), "long_row": 128, "segment": 64},
+    "powerlaw2m_n128_fwdbwd_bf16": {"variant": ("rowsplit", 16, 8), "long_row": 128, "segment": 64},
     "rmat23_n256_bf16": {"variant": ("rowsplit", 16, 8), "long_row": 256, "segment": 128},
     "rmat23_n256_f32": {"variant": ("stream", 64, 2), "long_row": 256, "segment": 128},
 }
@@ -89,7 +89,8 @@ def _log(msg):
 # backward also SDDMM and value gather): a stored counter reading is valid while these
 # are unchanged.
 FWD_SOURCES = ("elem.hpp", "fwd_common.hpp", "fwd.hip")
-KERNEL_SOURCES = {"powerlaw2m_n128_fwdbwd": FWD_SOURCES + ("bwd.hip",)}
+KERNEL_SOURCES = {"powerlaw2m_n128_fwdbwd": FWD_SOURCES + ("bwd.hip",),
+                  "powerlaw2m_n128_fwdbwd_bf16": FWD_SOURCES + ("bwd.hip",)}
 
 
 def kernel_source_digest(workload: str = "") -> str:
@@ -208,6 +209,8 @@ class TileRowForward(Workload):
             self.config["variant"] = chosen
         else:
             self.config["variant"] = _apply_pin(self.name, self.tile, self.N, tdt)
+        fk = "fwd_stream" if (self.config["variant"] or {}).get("kind") == "stream" else "fwd_main"
+        self.kernel = "spmm_fwd (%s + fwd_fixup)" % fk
         self.ws = self.tile.workspace(self.N)
         nnz = sum(t.nnz for t in self.tiles)
         self.flops = 2.0 * nnz * self.N
@@ -276,6 +279,8 @@ class ForwardBackward(Workload):
             self.config["variant"] = chosen
         else:
             self.config["variant"] = _apply_pin(self.name, self.tile, self.N, tdt)
+        fk = "fwd_main" if (self.config["variant"] or {}).get("kind") == "rowsplit" else "fwd_stream"
+        self.kernel = "spmm_fwd + spmm_bwd (%s, fwd_fixup, sddmm_kernel, gather_values)" % fk
         self.dA = torch.empty(self.A.nnz, device=dev)
         self.dB = torch.empty(self.A.cols, self.N, device=dev, dtype=tdt)
         self.wsf = self.tile.workspace(self.N, "fwd")
