@@ -54,11 +54,11 @@ AUTOTUNE = False
 # Pinned, so that a profiled run launches exactly the kernels the timed run launches
 # (no autotuner trials); --autotune re-tunes in set-up instead.
 PINNED = {
-    "rmat22_rowblock0_4x4_n128": {"variant": ("stream", 64, 1), "long_row": 128, "segment": 64},
+    "rmat22_rowblock0_4x4_n128": {"variant": ("stream", 64, 2), "long_row": 128, "segment": 64},
     "powerlaw2m_n128_fwdbwd": {"variant": ("stream", 64, 1), "long_row": 128, "segment": 64},
     "powerlaw2m_n128_fwdbwd_bf16": {"variant": ("rowsplit", 16, 8), "long_row": 128, "segment": 64},
-    "rmat23_n256_bf16": {"variant": ("rowsplit", 16, 8), "long_row": 256, "segment": 128},
-    "rmat23_n256_f32": {"variant": ("stream", 64, 2), "long_row": 256, "segment": 128},
+    "rmat23_n256_bf16": {"variant": ("rowsplit", 64, 4), "long_row": 128, "segment": 64},
+    "rmat23_n256_f32": {"variant": ("stream", 64, 2), "long_row": 128, "segment": 64},
 }
 
 
@@ -85,10 +85,10 @@ def _log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-# Sources of the kernels a workload launches (forward, split-row fix-up; for the
+# Sources of the kernels a workload launches (forward, split-row fix-up, hot-row staging; for the
 # backward also SDDMM and value gather): a stored counter reading is valid while these
 # are unchanged.
-FWD_SOURCES = ("elem.hpp", "fwd_common.hpp", "fwd.hip")
+FWD_SOURCES = ("elem.hpp", "fwd_common.hpp", "fwd.hip", "hot.hip")
 KERNEL_SOURCES = {"powerlaw2m_n128_fwdbwd": FWD_SOURCES + ("bwd.hip",),
                   "powerlaw2m_n128_fwdbwd_bf16": FWD_SOURCES + ("bwd.hip",)}
 
@@ -210,7 +210,8 @@ class TileRowForward(Workload):
         else:
             self.config["variant"] = _apply_pin(self.name, self.tile, self.N, tdt)
         fk = "fwd_stream" if (self.config["variant"] or {}).get("kind") == "stream" else "fwd_main"
-        self.kernel = "spmm_fwd (%s + fwd_fixup)" % fk
+        hs = "hot_stage + " if self.tile.stats()["hot_rows"] > 0 else ""
+        self.kernel = "spmm_fwd (%s%s + fwd_fixup)" % (hs, fk)
         self.ws = self.tile.workspace(self.N)
         nnz = sum(t.nnz for t in self.tiles)
         self.flops = 2.0 * nnz * self.N
@@ -218,7 +219,7 @@ class TileRowForward(Workload):
         self.config = dict(self.config, nnz=nnz, rows=self.tiles[0].rows, N=self.N, k_tiles=len(self.tiles),
                            tile_stats={k: v for k, v in self.tile.stats().items()
                                        if k in ("max_row", "empty_rows", "long_rows", "segments", "long_row",
-                                                "segment")})
+                                                "segment", "hot_rows", "hot_nnz")})
 
     def step(self):
         from paper_2311_18141_amd import ops
@@ -295,7 +296,8 @@ class ForwardBackward(Workload):
         st = self.tile.stats()
         self.config = dict(self.config, nnz=A.nnz, rows=A.rows, N=N,
                            tile_stats={k: st[k] for k in ("max_row", "empty_rows", "long_rows", "segments",
-                                                          "long_rows_t", "segments_t", "long_row", "segment")})
+                                                          "long_rows_t", "segments_t", "long_row", "segment",
+                                                          "hot_rows", "hot_nnz")})
 
     def step(self):
         from paper_2311_18141_amd import ops

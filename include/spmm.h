@@ -74,6 +74,14 @@ typedef struct {
                               of max(segment, ceil(sqrt(L)))); 0 = library default (64) */
   int32_t bwd_slice;       /* spmm_bwd computes dA in column slices of this width, one launch
                               per slice, so a slice of B can stay cache-resident; 0 = one launch */
+  int32_t hot_rows;        /* hot-row staging of the forward: the B rows of each k-tile's most used
+                              columns are copied on every spmm_fwd call into one contiguous block of
+                              the workspace and read there (the handle keeps a copy of colind with
+                              those entries tagged; results are bit-identical).  -1 = off; 0 =
+                              library rule (up to 16384 rows per k-tile, each used >= 16 times, for
+                              tiles of >= 2^20 non-zeros, where they serve >= 1/8 of the k-tile's
+                              non-zeros and >= 8x their share of its columns); n > 0 = up to n
+                              most used columns of every k-tile (n <= 2^24), no further test */
 } spmm_tile_opts;
 
 /* Opaque handle to one tile row (A_i0 ... A_i,K-1): the sparse operand of one C
@@ -93,6 +101,8 @@ typedef struct {
   int64_t has_transpose;
   int64_t long_rows_t, segments_t;   /* the same for the transposed structure */
   int64_t long_row, segment;         /* split threshold and unit length of the current plan */
+  int64_t hot_rows;                  /* staged B rows over all k-tiles (0: staging off) */
+  int64_t hot_nnz;                   /* non-zeros that read a staged row */
 } spmm_tile_stats;
 
 /*
@@ -158,7 +168,10 @@ spmm_status spmm_tile_autotune(spmm_tile_t tile, int64_t N, spmm_dtype dtype, co
                                const int64_t* ldb, void* C, int64_t ldc, int tune_plan, void* stream,
                                spmm_variant* chosen /* host */);
 
-/* Workspace (device bytes) spmm_fwd needs for this handle at width N. */
+/* Workspace (device bytes) spmm_fwd needs for this handle at width N: FP32 partial
+   rows of the split-row units, plus, with hot-row staging, 4 * ceil8(N) bytes per
+   staged row (after a 256-byte boundary).  Calls that share a workspace must not
+   overlap. */
 spmm_status spmm_fwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes /* host */);
 
 /*

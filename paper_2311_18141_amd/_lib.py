@@ -32,14 +32,16 @@ class SpmmCsr(ctypes.Structure):
 
 
 class SpmmTileOpts(ctypes.Structure):
-    _fields_ = [("flags", c_uint), ("long_row", c_i32), ("segment", c_i32), ("bwd_slice", c_i32)]
+    _fields_ = [("flags", c_uint), ("long_row", c_i32), ("segment", c_i32), ("bwd_slice", c_i32),
+                ("hot_rows", c_i32)]
 
 
 class SpmmTileStats(ctypes.Structure):
     _fields_ = [("rows", c_i64), ("num_k", c_i64), ("nnz_total", c_i64), ("max_row", c_i64),
                 ("empty_rows", c_i64), ("long_rows", c_i64), ("segments", c_i64),
                 ("hist_log2", c_i64 * 33), ("nnz_per_k", c_i64 * 16), ("has_transpose", c_i64),
-                ("long_rows_t", c_i64), ("segments_t", c_i64), ("long_row", c_i64), ("segment", c_i64)]
+                ("long_rows_t", c_i64), ("segments_t", c_i64), ("long_row", c_i64), ("segment", c_i64),
+                ("hot_rows", c_i64), ("hot_nnz", c_i64)]
 
 
 class SpmmVariant(ctypes.Structure):

@@ -38,6 +38,15 @@ spmm_status fail(spmm_status st, const char* fmt, ...) {
 
 constexpr int32_t kDefaultLongRow = 128;
 constexpr int32_t kDefaultSegment = 64;
+// Hot-row staging, library default: up to this many B rows per k-tile, each used by at
+// least kHotMinUses non-zeros, for tiles of at least kHotMinNnz non-zeros in total, and
+// only where the staged rows serve at least 1/8 of the k-tile's non-zeros and at least
+// kHotConcentration times their share of its columns (a skewed column distribution).
+constexpr int32_t kDefaultHotRows = 16384;
+constexpr int32_t kMaxHotRows = 1 << 24;
+constexpr int32_t kHotMinUses = 16;
+constexpr int64_t kHotMinNnz = (int64_t)1 << 20;
+constexpr int64_t kHotConcentration = 8;
 
 // Device allocation owned by a handle.
 template <typename T>
@@ -129,6 +138,8 @@ spmm_status build_plan(const int32_t* const* rowptr, int K, int64_t rows, int32_
 }
 
 size_t partial_ld(int64_t N) { return (size_t)((N + 7) / 8 * 8); }
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Rows per wave of the stream kernel: enough waves to fill the GPU for short tiles,
 // 64 (one per lane) for large ones.
@@ -233,6 +244,14 @@ struct spmm_tile_s {
   };
   SddmmEntry sd[8];
   int nsd = 0;
+  // Hot-row staging: per k-tile a tagged copy of colind (null: the k-tile stages no
+  // rows and the caller's colind is read), the B row of every slot, slots of k-tile k
+  // at [hot_off[k], hot_off[k + 1]).
+  int32_t* hcol[kMaxK] = {};
+  int32_t* hot_src = nullptr;
+  int64_t hot_off[kMaxK + 1] = {};
+
+  int64_t hot_total() const { return hot_off[num_k]; }
 
   ~spmm_tile_s() {
     free_plan(plan);
@@ -241,6 +260,9 @@ struct spmm_tile_s {
     if (rowptrT) (void)hipFree(rowptrT);
     if (colindT) (void)hipFree(colindT);
     if (perm) (void)hipFree(perm);
+    for (int k = 0; k < kMaxK; ++k)
+      if (hcol[k]) (void)hipFree(hcol[k]);
+    if (hot_src) (void)hipFree(hot_src);
   }
 };
 
@@ -268,18 +290,56 @@ spmm::Variant resolve_variant(const spmm_tile_s* A, int64_t N, DT dt, uintptr_t 
   return base;
 }
 
-// Fill the forward parameters for a handle and launch (arguments already checked).
+// Forward workspace: FP32 partial rows of the plan's split-row units, then (at a
+// 256-byte boundary) the staged hot rows, ceil8(N) elements apart (sized for FP32).
+size_t fwd_partial_bytes(const Plan& plan, int64_t N) { return sizeof(float) * partial_ld(N) * (size_t)plan.n_seg; }
+size_t fwd_workspace(const spmm_tile_s* A, const Plan& plan, int64_t N) {
+  const size_t part = fwd_partial_bytes(plan, N);
+  if (A->hot_total() == 0) return part;
+  return align256(part) + sizeof(float) * partial_ld(N) * (size_t)A->hot_total();
+}
+
+// Fill the forward parameters for a handle and launch (arguments already checked):
+// first the copy of the staged hot rows (when the handle has any), then the forward.
 hipError_t launch_forward(const spmm_tile_s* A, const Plan& plan, int k_offset, const void* const* B,
                           const int64_t* ldb, DT dt, void* C, int64_t ldc, int64_t N, int accumulate,
                           void* workspace, const spmm::Variant& v, hipStream_t s) {
   const int K = A->num_k;
+  const int64_t esize = dt == DT::F32 ? 4 : 2;
+  const int64_t ldh = (int64_t)partial_ld(N);
+  char* hot = A->hot_total() > 0 ? static_cast<char*>(workspace) + align256(fwd_partial_bytes(plan, N)) : nullptr;
   spmm::FwdParams P{};
   for (int k = 0; k < K; ++k) {
     P.t[k].rowptr = A->t[k].rowptr;
-    P.t[k].colind = A->t[k].colind;
+    P.t[k].colind = A->hcol[k] ? A->hcol[k] : A->t[k].colind;
     P.t[k].values = A->t[k].values;
     P.t[k].B = B[k];
     P.t[k].ldb = ldb[k];
+    if (A->hcol[k]) {
+      P.t[k].hot = hot + A->hot_off[k] * ldh * esize;
+      P.t[k].ldh = ldh;
+    } else {  // no tagged entries: the staged-row address is never taken
+      P.t[k].hot = B[k];
+      P.t[k].ldh = ldb[k];
+    }
+  }
+  if (hot) {
+    spmm::HotStageParams H{};
+    uintptr_t align_or = (uintptr_t)(N * esize);
+    for (int k = 0; k < K; ++k) {
+      H.B[k] = B[k];
+      H.ldb_bytes[k] = ldb[k] * esize;
+      if (A->hot_off[k + 1] > A->hot_off[k]) align_or |= reinterpret_cast<uintptr_t>(B[k]) | (uintptr_t)(ldb[k] * esize);
+    }
+    for (int k = 0; k <= K; ++k) H.off[k] = A->hot_off[k];
+    H.num_k = K;
+    H.src = A->hot_src;
+    H.dst = hot;
+    H.ldh_bytes = ldh * esize;
+    H.row_bytes = N * esize;
+    const int width = (align_or % 16) == 0 ? 16 : ((align_or % 4) == 0 ? 4 : 2);
+    hipError_t e = spmm::launch_hot_stage(H, width, s);
+    if (e != hipSuccess) return e;
   }
   P.num_k = K;
   P.k_offset = (int)(((k_offset % K) + K) % K);
@@ -296,6 +356,79 @@ hipError_t launch_forward(const spmm_tile_s* A, const Plan& plan, int k_offset, 
   P.partial = static_cast<float*>(workspace);
   P.ldp = (int64_t)partial_ld(N);
   return spmm::launch_fwd(P, v, dt, s);
+}
+
+// Choose each k-tile's staged hot rows and build its tagged colind (synchronous).
+// want < 0: none; want = 0: the library rule (kDefaultHotRows per k-tile, subject to
+// the use, size and skew tests); want > 0: up to `want` of each k-tile's most used
+// columns (used at least once), no further test.  Columns are ranked by use count,
+// ties by index.
+spmm_status select_hot(spmm_tile_s* h, const spmm_csr* tiles, int K, int32_t want, hipStream_t s,
+                       int64_t* hot_nnz) {
+  *hot_nnz = 0;
+  if (want < 0) return SPMM_OK;
+  const bool forced = want > 0;
+  const int64_t hmax = forced ? want : kDefaultHotRows;
+  const int32_t min_uses = forced ? 1 : kHotMinUses;
+  int64_t nnz_total = 0, max_cols = 0;
+  for (int k = 0; k < K; ++k) {
+    nnz_total += tiles[k].nnz;
+    max_cols = std::max<int64_t>(max_cols, tiles[k].cols);
+  }
+  if (nnz_total == 0 || max_cols == 0 || (!forced && nnz_total < kHotMinNnz)) return SPMM_OK;
+  int32_t* dbuf = nullptr;  // column counts, then the slot of each column
+  HIP_TRY(hipMalloc(reinterpret_cast<void**>(&dbuf), sizeof(int32_t) * (size_t)max_cols));
+  std::vector<std::vector<int32_t>> chosen(K);
+  std::vector<int32_t> cnt, slot_of;
+  auto run = [&]() -> spmm_status {
+    for (int k = 0; k < K; ++k) {
+      const spmm_csr& t = tiles[k];
+      if (t.nnz == 0 || t.cols == 0) continue;
+      cnt.assign((size_t)t.cols, 0);
+      HIP_TRY(hipMemsetAsync(dbuf, 0, sizeof(int32_t) * (size_t)t.cols, s));
+      HIP_TRY(spmm::launch_count_columns(t.colind, t.nnz, dbuf, s));
+      HIP_TRY(hipMemcpyAsync(cnt.data(), dbuf, sizeof(int32_t) * (size_t)t.cols, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      std::vector<int32_t>& c = chosen[k];
+      for (int64_t j = 0; j < t.cols; ++j)
+        if (cnt[j] >= min_uses) c.push_back((int32_t)j);
+      auto hotter = [&](int32_t a, int32_t b) { return cnt[a] != cnt[b] ? cnt[a] > cnt[b] : a < b; };
+      if ((int64_t)c.size() > hmax) {
+        std::nth_element(c.begin(), c.begin() + hmax, c.end(), hotter);
+        c.resize((size_t)hmax);
+      }
+      std::sort(c.begin(), c.end(), hotter);
+      int64_t cov = 0;
+      for (int32_t j : c) cov += cnt[j];
+      const int64_t H = (int64_t)c.size();
+      if (!forced && (8 * cov < t.nnz || cov * t.cols < kHotConcentration * H * t.nnz)) c.clear();
+      if (!c.empty()) *hot_nnz += cov;
+    }
+    int64_t total = 0;
+    for (int k = 0; k < K; ++k) {
+      h->hot_off[k] = total;
+      total += (int64_t)chosen[k].size();
+    }
+    h->hot_off[K] = total;
+    if (total == 0) return SPMM_OK;
+    if (dalloc(&h->hot_src, total) != hipSuccess) return fail(SPMM_ERR_ALLOC, "device allocation of the hot-row list failed");
+    for (int k = 0; k < K; ++k) {
+      const std::vector<int32_t>& c = chosen[k];
+      if (c.empty()) continue;
+      const spmm_csr& t = tiles[k];
+      slot_of.assign((size_t)t.cols, -1);
+      for (size_t i = 0; i < c.size(); ++i) slot_of[(size_t)c[i]] = (int32_t)i;
+      if (dalloc(&h->hcol[k], t.nnz) != hipSuccess) return fail(SPMM_ERR_ALLOC, "device allocation of the tagged colind failed");
+      HIP_TRY(hipMemcpyAsync(dbuf, slot_of.data(), sizeof(int32_t) * (size_t)t.cols, hipMemcpyHostToDevice, s));
+      HIP_TRY(spmm::launch_tag_hot(t.colind, t.nnz, dbuf, h->hcol[k], s));
+      HIP_TRY(hipMemcpyAsync(h->hot_src + h->hot_off[k], c.data(), sizeof(int32_t) * c.size(), hipMemcpyHostToDevice, s));
+      HIP_TRY(hipStreamSynchronize(s));
+    }
+    return SPMM_OK;
+  };
+  spmm_status st = run();
+  (void)hipFree(dbuf);
+  return st;
 }
 
 bool valid_variant(const spmm_variant& v, spmm_dtype dtype) {
@@ -337,6 +470,9 @@ spmm_status spmm_tile_create(int64_t rows, int num_k, const spmm_csr* tiles, con
   int32_t segment = (opts && opts->segment > 0) ? opts->segment : kDefaultSegment;
   if (opts && (opts->long_row < 0 || opts->segment < 0 || opts->bwd_slice < 0))
     return fail(SPMM_ERR_INVALID_ARG, "negative long_row/segment/bwd_slice");
+  const int32_t hot_rows = opts ? opts->hot_rows : 0;
+  if (hot_rows < -1 || hot_rows > kMaxHotRows)
+    return fail(SPMM_ERR_INVALID_ARG, "hot_rows=%d outside [-1, %d]", hot_rows, kMaxHotRows);
   int64_t units_bound = 0;
   for (int k = 0; k < num_k; ++k) {
     const spmm_csr& t = tiles[k];
@@ -367,6 +503,7 @@ spmm_status spmm_tile_create(int64_t rows, int num_k, const spmm_csr* tiles, con
   h->bwd_slice = opts ? opts->bwd_slice : 0;
   (void)hipGetDevice(&h->device);
 
+  int64_t hot_nnz = 0;
   auto body = [&]() -> spmm_status {
     if (flags & SPMM_TILE_VALIDATE) {
       uint32_t* status = nullptr;
@@ -401,6 +538,8 @@ spmm_status spmm_tile_create(int64_t rows, int num_k, const spmm_csr* tiles, con
     const int32_t* rps[kMaxK];
     for (int k = 0; k < num_k; ++k) rps[k] = tiles[k].rowptr;
     spmm_status st = build_plan(rps, num_k, rows, long_row, segment, s, &h->plan);
+    if (st != SPMM_OK) return st;
+    st = select_hot(h, tiles, num_k, hot_rows, s, &hot_nnz);
     if (st != SPMM_OK) return st;
     if (flags & SPMM_TILE_TRANSPOSE) {
       const spmm_csr& t = tiles[0];
@@ -443,6 +582,8 @@ spmm_status spmm_tile_create(int64_t rows, int num_k, const spmm_csr* tiles, con
   S.segments_t = h->planT.n_seg;
   S.long_row = h->plan.long_row;
   S.segment = h->plan.segment;
+  S.hot_rows = h->hot_total();
+  S.hot_nnz = hot_nnz;
   *out = h;
   return SPMM_OK;
 }
@@ -478,7 +619,7 @@ spmm_status spmm_tile_export_transpose(spmm_tile_t tile, int32_t* rowptrT, int32
 spmm_status spmm_fwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes) {
   if (!A || !bytes) return fail(SPMM_ERR_INVALID_ARG, "null argument");
   if (N < 1) return fail(SPMM_ERR_INVALID_ARG, "N=%lld < 1", (long long)N);
-  *bytes = sizeof(float) * partial_ld(N) * (size_t)A->plan.n_seg;
+  *bytes = fwd_workspace(A, A->plan, N);
   return SPMM_OK;
 }
 
@@ -517,10 +658,9 @@ spmm_status spmm_fwd(spmm_tile_t A, int k_offset, const void* const* B, const in
     if (!B[k] && A->t[k].cols > 0) return fail(SPMM_ERR_INVALID_ARG, "B[%d] is null", k);
     if (ldb[k] < N) return fail(SPMM_ERR_INVALID_ARG, "ldb[%d]=%lld < N", k, (long long)ldb[k]);
     if (ldb[k] * esize >= ((int64_t)1 << 32)) return fail(SPMM_ERR_UNSUPPORTED, "ldb[%d] * element size >= 2^32", k);
-    if (ldb[k] * esize >= ((int64_t)1 << 32)) return fail(SPMM_ERR_UNSUPPORTED, "ldb[%d] * element size >= 2^32", k);
     align_or |= reinterpret_cast<uintptr_t>(B[k]) | (uintptr_t)(ldb[k] * esize);
   }
-  const size_t need = sizeof(float) * partial_ld(N) * (size_t)A->plan.n_seg;
+  const size_t need = fwd_workspace(A, A->plan, N);
   if (need > 0) {
     if (!workspace || ws_bytes < need)
       return fail(SPMM_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? ws_bytes : 0);
@@ -659,7 +799,7 @@ spmm_status spmm_tile_autotune(spmm_tile_t A, int64_t N, spmm_dtype dtype, const
       if (st != SPMM_OK) break;
       plan = &plans[pi];
     }
-    const size_t need = sizeof(float) * partial_ld(N) * (size_t)plan->n_seg;
+    const size_t need = fwd_workspace(A, *plan, N);
     if (need > ws_cap) {
       if (ws) (void)hipFree(ws);
       ws = nullptr;
@@ -801,6 +941,8 @@ spmm_status spmm_bwd(spmm_tile_t A, const void* dC, int64_t lddc, const void* B,
     P.t[0].values = valuesT;
     P.t[0].B = dC;
     P.t[0].ldb = lddc;
+    P.t[0].hot = dC;  // the transposed structure has no tagged entries
+    P.t[0].ldh = lddc;
     P.num_k = 1;
     P.k_offset = 0;
     P.rows = t.cols;

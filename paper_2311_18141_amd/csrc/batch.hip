@@ -174,6 +174,8 @@ __device__ __forceinline__ void item_rowsplit(const BatchTileDev& bt, const Ops<
   t.values = bt.values;
   t.B = op.B;
   t.ldb = op.ldb;
+  t.hot = op.B;  // batches read the caller's colind: no tagged entries
+  t.ldh = op.ldb;
   const char* brow = reinterpret_cast<const char*>(op.B) + cl * (int64_t)sizeof(T);
   const uint32_t ldbb = (uint32_t)(op.ldb * (int64_t)sizeof(T));
   // the item's row extents, loaded once: lane l holds rows r0 + l (nrows <= 64)
@@ -214,6 +216,8 @@ __device__ __forceinline__ void item_unit(const BatchParams& P, const BatchTileD
   t.values = bt.values;
   t.B = op.B;
   t.ldb = op.ldb;
+  t.hot = op.B;  // batches read the caller's colind: no tagged entries
+  t.ldh = op.ldb;
   const Seg d = bt.seg[s];
   float acc[V];
 #pragma unroll

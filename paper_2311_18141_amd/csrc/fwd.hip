@@ -41,9 +41,10 @@ __global__ void __launch_bounds__(kBlock) fwd_main(FwdParams P) {
     if (s >= P.n_seg) return;
     const Seg d = P.seg[s];
     const TileDev& t = P.t[d.k];
-    accumulate_range<G, V, E>(t, d.p0, d.p1,
-                              static_cast<const char*>(t.B) + cl * (int64_t)sizeof(typename E::T),
-                              (uint32_t)(t.ldb * (int64_t)sizeof(typename E::T)), gl, acc);
+    accumulate_range<G, V, E, true>(t, d.p0, d.p1, static_cast<const char*>(t.B) + cl * (int64_t)sizeof(typename E::T),
+                                    (uint32_t)(t.ldb * (int64_t)sizeof(typename E::T)), gl, acc,
+                                    static_cast<const char*>(t.hot) + cl * (int64_t)sizeof(typename E::T),
+                                    (uint32_t)(t.ldh * (int64_t)sizeof(typename E::T)));
     if (active) store_f32v<V>(P.partial + s * P.ldp + c0, acc);
     return;
   }
@@ -57,9 +58,11 @@ __global__ void __launch_bounds__(kBlock) fwd_main(FwdParams P) {
     int k = kk + P.k_offset;
     if (k >= P.num_k) k -= P.num_k;
     const TileDev& t = P.t[k];
-    accumulate_range<G, V, E>(t, t.rowptr[row], t.rowptr[row + 1],
-                              static_cast<const char*>(t.B) + cl * (int64_t)sizeof(typename E::T),
-                              (uint32_t)(t.ldb * (int64_t)sizeof(typename E::T)), gl, acc);
+    accumulate_range<G, V, E, true>(t, t.rowptr[row], t.rowptr[row + 1],
+                                    static_cast<const char*>(t.B) + cl * (int64_t)sizeof(typename E::T),
+                                    (uint32_t)(t.ldb * (int64_t)sizeof(typename E::T)), gl, acc,
+                                    static_cast<const char*>(t.hot) + cl * (int64_t)sizeof(typename E::T),
+                                    (uint32_t)(t.ldh * (int64_t)sizeof(typename E::T)));
   }
   if (!active) return;
   typename E::T* c = static_cast<typename E::T*>(P.C) + row * P.ldc + c0;
@@ -122,8 +125,10 @@ __global__ void __launch_bounds__(kBlock) fwd_stream(FwdParams P) {
     if (s >= P.n_seg) return;
     const Seg d = P.seg[s];
     const TileDev& t = P.t[d.k];
-    accumulate_range<64, V, E>(t, d.p0, d.p1, static_cast<const char*>(t.B) + cl * (int64_t)sizeof(T),
-                               (uint32_t)(t.ldb * (int64_t)sizeof(T)), lane, acc);
+    accumulate_range<64, V, E, true>(t, d.p0, d.p1, static_cast<const char*>(t.B) + cl * (int64_t)sizeof(T),
+                                     (uint32_t)(t.ldb * (int64_t)sizeof(T)), lane, acc,
+                                     static_cast<const char*>(t.hot) + cl * (int64_t)sizeof(T),
+                                     (uint32_t)(t.ldh * (int64_t)sizeof(T)));
     if (active) store_f32v<V>(P.partial + s * P.ldp + c0, acc);
     return;
   }
@@ -198,12 +203,16 @@ __global__ void __launch_bounds__(kBlock) fwd_stream(FwdParams P) {
     const float* valp = P.t[0].values;
     const char* bp = static_cast<const char*>(P.t[0].B);
     int64_t ldbb = P.t[0].ldb;
+    const char* hp = static_cast<const char*>(P.t[0].hot);
+    int64_t ldhh = P.t[0].ldh;
     for (int t = 1; t < K; ++t) {
       if (k == t) {
         colp = P.t[t].colind;
         valp = P.t[t].values;
         bp = static_cast<const char*>(P.t[t].B);
         ldbb = P.t[t].ldb;
+        hp = static_cast<const char*>(P.t[t].hot);
+        ldhh = P.t[t].ldh;
       }
     }
     uint64_t addr = 0;
@@ -212,7 +221,8 @@ __global__ void __launch_bounds__(kBlock) fwd_stream(FwdParams P) {
     if (lane < n) {
       const uint32_t col = (uint32_t)__builtin_nontemporal_load(colp + p);
       val = __builtin_nontemporal_load(valp + p);
-      addr = reinterpret_cast<uint64_t>(bp) + (uint64_t)col * (uint64_t)(ldbb * (int64_t)sizeof(T));
+      addr = reinterpret_cast<uint64_t>(entry_row<true>(col, bp, (uint32_t)(ldbb * (int64_t)sizeof(T)), hp,
+                                                        (uint32_t)(ldhh * (int64_t)sizeof(T))));
       end = (q + 1 == s_pref[ri + 1]) ? 1 : 0;
     }
     const uint32_t alo = (uint32_t)addr, ahi = (uint32_t)(addr >> 32);

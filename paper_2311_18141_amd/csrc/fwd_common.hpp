@@ -34,13 +34,29 @@ constexpr int unroll_for() {
   return V >= 8 ? 4 : 8;
 }
 
+// Address of column window c0 of the B row an entry names: B row `col`, or, for a
+// tagged entry (bit 31 set), staged row col & ~kHotTag of the hot block.  brow / hrow
+// already include the window offset c0 (bytes).
+template <bool HOT>
+__device__ __forceinline__ const char* entry_row(uint32_t col, const char* brow, uint32_t ldb_bytes,
+                                                 const char* hrow, uint32_t ldh_bytes) {
+  if constexpr (HOT) {
+    const bool h = (col & kHotTag) != 0;
+    return (h ? hrow : brow) + (uint64_t)(col & ~kHotTag) * (h ? ldh_bytes : ldb_bytes);
+  } else {
+    return brow + (uint64_t)col * ldb_bytes;
+  }
+}
+
 // acc += sum over p in [p0, p1) of val(p) * B[col(p), c0 .. c0+V), where
-// brow = B + c0 (bytes) and B rows are ldb_bytes apart (< 2^32, checked by the host).
+// brow = B + c0 (bytes) and B rows are ldb_bytes apart (< 2^32, checked by the host);
+// with HOT, tagged entries read the staged row at hrow + slot * ldh_bytes instead.
 // Full batches of U non-zeros issue U independent row loads before any FMA; the
 // last partial batch is predicated without branches (clamped source, zeroed terms).
-template <int G, int V, typename E>
+template <int G, int V, typename E, bool HOT = false>
 __device__ __forceinline__ void accumulate_range(const TileDev& t, int p0, int p1, const char* brow,
-                                                 uint32_t ldb_bytes, int gl, float (&acc)[V]) {
+                                                 uint32_t ldb_bytes, int gl, float (&acc)[V],
+                                                 const char* hrow = nullptr, uint32_t ldh_bytes = 0) {
   constexpr int U = unroll_for<V>();
   using T = typename E::T;
   for (int pc = p0; pc < p1; pc += G) {
@@ -57,7 +73,7 @@ __device__ __forceinline__ void accumulate_range(const TileDev& t, int p0, int p
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const uint32_t col = (uint32_t)group_bcast<G>(my_col, j + u);
-        load_vec<E, V>(reinterpret_cast<const T*>(brow + (uint64_t)col * ldb_bytes), b[u]);
+        load_vec<E, V>(reinterpret_cast<const T*>(entry_row<HOT>(col, brow, ldb_bytes, hrow, ldh_bytes)), b[u]);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -72,7 +88,7 @@ __device__ __forceinline__ void accumulate_range(const TileDev& t, int p0, int p
       for (int u = 0; u < U; ++u) {
         const int src = min(j + u, cnt - 1);
         const uint32_t col = (uint32_t)group_bcast<G>(my_col, src);
-        load_vec<E, V>(reinterpret_cast<const T*>(brow + (uint64_t)col * ldb_bytes), b[u]);
+        load_vec<E, V>(reinterpret_cast<const T*>(entry_row<HOT>(col, brow, ldb_bytes, hrow, ldh_bytes)), b[u]);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {

@@ -27,11 +27,17 @@ spmm_status validate_csr(const int32_t* rowptr, const int32_t* colind, int64_t r
 // One k-tile as the forward kernels see it.
 struct TileDev {
   const int32_t* rowptr;
-  const int32_t* colind;
+  const int32_t* colind;  // column indices; an entry with bit 31 set names staged row (bit 31 cleared) of `hot`
   const float* values;
   const void* B;         // dense operand rows for this tile's columns
   int64_t ldb;
+  const void* hot;       // staged copies of this tile's most used B rows (forward only; else unused)
+  int64_t ldh;           // row pitch of `hot` in elements
 };
+
+// Column indices at or above this bit pattern name a staged B row (the handle's tagged
+// copy of colind; the caller's arrays never have it: indices are below 2^31).
+constexpr uint32_t kHotTag = 0x80000000u;
 
 // A split work unit: row, k-tile, [p0, p1) in that tile's CSR positions.
 struct Seg {
@@ -74,6 +80,26 @@ struct Variant {
 
 // ---- launchers (defined in the .hip files) --------------------------------
 hipError_t launch_fwd(const FwdParams& P, Variant v, DT dt, hipStream_t s);
+
+// ---- hot-row staging (hot.hip) ----------------------------------------------
+// Per call: copy the staged B rows of every k-tile into the workspace block
+// `dst` (slots of k-tile k at [off[k], off[k+1]), row pitch ldh_bytes), so that the
+// forward reads them from contiguous, evenly spread addresses.
+struct HotStageParams {
+  const void* B[kMaxK];
+  int64_t ldb_bytes[kMaxK];
+  int64_t off[kMaxK + 1];
+  int num_k;
+  const int32_t* src;      // B row of each slot
+  char* dst;
+  int64_t ldh_bytes;
+  int64_t row_bytes;       // N * element size
+};
+hipError_t launch_hot_stage(const HotStageParams& P, int width_bytes, hipStream_t s);
+// cnt[c] += occurrences of column c in colind[0, nnz) (cnt zeroed by the caller).
+hipError_t launch_count_columns(const int32_t* colind, int64_t nnz, int32_t* cnt, hipStream_t s);
+// out[p] = slot_of[colind[p]] >= 0 ? kHotTag | slot_of[colind[p]] : colind[p].
+hipError_t launch_tag_hot(const int32_t* colind, int64_t nnz, const int32_t* slot_of, int32_t* out, hipStream_t s);
 
 // ---- batched persistent launch (batch.hip) --------------------------------
 struct BatchTileDev {

@@ -86,8 +86,10 @@ class Tile:
 
 def spmm_tile_create(rows: int, tiles: Sequence[Tuple[torch.Tensor, torch.Tensor, torch.Tensor, int]],
                      validate: bool = False, transpose: bool = False, long_row: int = 0, segment: int = 0,
-                     bwd_slice: int = 0, stream: Optional[torch.cuda.Stream] = None) -> Tile:
-    """Create a handle from k-tiles given as (rowptr int32, colind int32, values float32, cols)."""
+                     bwd_slice: int = 0, hot_rows: int = 0, stream: Optional[torch.cuda.Stream] = None) -> Tile:
+    """Create a handle from k-tiles given as (rowptr int32, colind int32, values float32, cols).
+
+    hot_rows: forward hot-row staging, -1 off, 0 library rule, n > 0 up to n rows per k-tile."""
     K = len(tiles)
     arr = (SpmmCsr * max(K, 1))()
     keep = []
@@ -114,6 +116,7 @@ def spmm_tile_create(rows: int, tiles: Sequence[Tuple[torch.Tensor, torch.Tensor
     opts.long_row = long_row
     opts.segment = segment
     opts.bwd_slice = bwd_slice
+    opts.hot_rows = hot_rows
     h = ctypes.c_void_p()
     check(lib().spmm_tile_create(rows, K, arr, ctypes.byref(opts), _stream_ptr(stream), ctypes.byref(h)))
     return Tile(h.value, rows, cols, nnz, keep, vals)

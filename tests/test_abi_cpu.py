@@ -69,7 +69,7 @@ def _tiles(n=1, cols=10, nnz=5, ptr=0x1000):
 @pytest.mark.parametrize("case,expect", [
     ("null_out", 1), ("neg_rows", 1), ("huge_rows", 1), ("k0", 1), ("k17", 1), ("null_tiles", 1),
     ("neg_cols", 1), ("neg_nnz", 1), ("big_nnz", 3), ("null_rowptr", 1), ("null_colind", 1),
-    ("bad_flags", 1), ("transpose_k2", 3), ("neg_long_row", 1),
+    ("bad_flags", 1), ("transpose_k2", 3), ("neg_long_row", 1), ("hot_rows_m2", 1), ("hot_rows_huge", 1),
 ])
 def test_create_argument_errors(case, expect):
     L = _lib.lib()
@@ -108,6 +108,10 @@ def test_create_argument_errors(case, expect):
         opts.flags = _lib.SPMM_TILE_TRANSPOSE
     elif case == "neg_long_row":
         opts.long_row = -3
+    elif case == "hot_rows_m2":
+        opts.hot_rows = -2
+    elif case == "hot_rows_huge":
+        opts.hot_rows = (1 << 24) + 1
     st, h, msg = _create(rows, K, t, opts)
     assert st == expect, (case, st, msg)
     assert h is None
