@@ -78,10 +78,13 @@ typedef struct {
                               columns are copied on every spmm_fwd call into one contiguous block of
                               the workspace and read there (the handle keeps a copy of colind with
                               those entries tagged; results are bit-identical).  -1 = off; 0 =
-                              library rule (up to 16384 rows per k-tile, each used >= 16 times, for
-                              tiles of >= 2^20 non-zeros, where they serve >= 1/8 of the k-tile's
-                              non-zeros and >= 8x their share of its columns); n > 0 = up to n
-                              most used columns of every k-tile (n <= 2^24), no further test */
+                              library rule (up to 16384 rows per k-tile of <= 2^27 columns, each
+                              used >= 16 times, for tiles of >= 2^20 non-zeros, where they serve
+                              >= 1/8 of the k-tile's non-zeros and >= 8x their share of its
+                              columns); n > 0 = up to n most used columns of every k-tile
+                              (n <= 2^24), no further test.  Staging rows needs workspace (see
+                              spmm_fwd_workspace_bytes); the handle's staging choice holds for
+                              every N and dtype. */
 } spmm_tile_opts;
 
 /* Opaque handle to one tile row (A_i0 ... A_i,K-1): the sparse operand of one C

@@ -47,6 +47,9 @@ constexpr int32_t kMaxHotRows = 1 << 24;
 constexpr int32_t kHotMinUses = 16;
 constexpr int64_t kHotMinNnz = (int64_t)1 << 20;
 constexpr int64_t kHotConcentration = 8;
+// The rule looks only at k-tiles of at most this many columns (the selection keeps two
+// host arrays of one int32 per column).
+constexpr int64_t kHotMaxCols = (int64_t)1 << 27;
 
 // Device allocation owned by a handle.
 template <typename T>
@@ -373,7 +376,7 @@ spmm_status select_hot(spmm_tile_s* h, const spmm_csr* tiles, int K, int32_t wan
   int64_t nnz_total = 0, max_cols = 0;
   for (int k = 0; k < K; ++k) {
     nnz_total += tiles[k].nnz;
-    max_cols = std::max<int64_t>(max_cols, tiles[k].cols);
+    if (forced || tiles[k].cols <= kHotMaxCols) max_cols = std::max<int64_t>(max_cols, tiles[k].cols);
   }
   if (nnz_total == 0 || max_cols == 0 || (!forced && nnz_total < kHotMinNnz)) return SPMM_OK;
   int32_t* dbuf = nullptr;  // column counts, then the slot of each column
@@ -383,7 +386,7 @@ spmm_status select_hot(spmm_tile_s* h, const spmm_csr* tiles, int K, int32_t wan
   auto run = [&]() -> spmm_status {
     for (int k = 0; k < K; ++k) {
       const spmm_csr& t = tiles[k];
-      if (t.nnz == 0 || t.cols == 0) continue;
+      if (t.nnz == 0 || t.cols == 0 || (!forced && t.cols > kHotMaxCols)) continue;
       cnt.assign((size_t)t.cols, 0);
       HIP_TRY(hipMemsetAsync(dbuf, 0, sizeof(int32_t) * (size_t)t.cols, s));
       HIP_TRY(spmm::launch_count_columns(t.colind, t.nnz, dbuf, s));
@@ -426,7 +429,7 @@ spmm_status select_hot(spmm_tile_s* h, const spmm_csr* tiles, int K, int32_t wan
     }
     return SPMM_OK;
   };
-  spmm_status st = run();
+  spmm_status st = spmm::guarded(run);
   (void)hipFree(dbuf);
   return st;
 }
@@ -560,7 +563,7 @@ spmm_status spmm_tile_create(int64_t rows, int num_k, const spmm_csr* tiles, con
     }
     return SPMM_OK;
   };
-  spmm_status st = body();
+  spmm_status st = spmm::guarded(body);
   if (st != SPMM_OK) {
     delete h;
     return st;
@@ -725,9 +728,19 @@ spmm_status spmm_tile_set_sddmm_variant(spmm_tile_t A, int64_t N, int32_t lanes,
   return SPMM_OK;
 }
 
+static spmm_status autotune_impl(spmm_tile_t A, int64_t N, spmm_dtype dtype, const void* const* B,
+                                 const int64_t* ldb, void* C, int64_t ldc, int tune_plan, void* stream,
+                                 spmm_variant* chosen);
+
 spmm_status spmm_tile_autotune(spmm_tile_t A, int64_t N, spmm_dtype dtype, const void* const* B,
                                const int64_t* ldb, void* C, int64_t ldc, int tune_plan, void* stream,
                                spmm_variant* chosen) {
+  return spmm::guarded([&]() { return autotune_impl(A, N, dtype, B, ldb, C, ldc, tune_plan, stream, chosen); });
+}
+
+static spmm_status autotune_impl(spmm_tile_t A, int64_t N, spmm_dtype dtype, const void* const* B,
+                                 const int64_t* ldb, void* C, int64_t ldc, int tune_plan, void* stream,
+                                 spmm_variant* chosen) {
   if (!A) return fail(SPMM_ERR_INVALID_ARG, "tile is null");
   if (!B || !ldb) return fail(SPMM_ERR_INVALID_ARG, "B/ldb array is null");
   if (N < 1) return fail(SPMM_ERR_INVALID_ARG, "N=%lld < 1", (long long)N);
@@ -1204,7 +1217,7 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
     }
     return SPMM_OK;
   };
-  spmm_status st = body();
+  spmm_status st = spmm::guarded(body);
   if (st != SPMM_OK) {
     delete b;
     return st;

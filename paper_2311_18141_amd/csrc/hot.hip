@@ -27,11 +27,6 @@ __global__ void __launch_bounds__(kBlock) hot_stage_kernel(HotStageParams P) {
   }
 }
 
-__global__ void __launch_bounds__(kBlock) count_columns_kernel(const int32_t* colind, int64_t nnz, int32_t* cnt) {
-  for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * kBlock)
-    atomicAdd(&cnt[colind[p]], 1);
-}
-
 __global__ void __launch_bounds__(kBlock) tag_hot_kernel(const int32_t* colind, int64_t nnz, const int32_t* slot_of,
                                                          int32_t* out) {
   for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * kBlock) {
@@ -64,12 +59,6 @@ hipError_t launch_hot_stage(const HotStageParams& P, int width_bytes, hipStream_
     default:
       return hipErrorInvalidValue;
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_count_columns(const int32_t* colind, int64_t nnz, int32_t* cnt, hipStream_t s) {
-  if (nnz == 0) return hipSuccess;
-  hipLaunchKernelGGL(count_columns_kernel, dim3(grid_for(nnz)), dim3(kBlock), 0, s, colind, nnz, cnt);
   return hipGetLastError();
 }
 

@@ -6,6 +6,8 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <exception>
+#include <new>
 
 #include "spmm.h"
 
@@ -20,6 +22,19 @@ enum class DT : int { F32 = 0, BF16 = 1 };
 
 // Record the thread-local message spmm_last_error() returns; returns st.
 spmm_status set_error(spmm_status st, const char* fmt, ...);
+
+// Runs f() and turns a C++ exception (a failed host allocation, in practice) into a
+// status, so that no exception leaves an entry point of the C ABI.
+template <typename F>
+spmm_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return set_error(SPMM_ERR_ALLOC, "host allocation failed");
+  } catch (const std::exception& e) {
+    return set_error(SPMM_ERR_HIP, "unexpected error: %s", e.what());
+  }
+}
 // Row-pointer and column-index checks of one CSR matrix (synchronous on s).
 spmm_status validate_csr(const int32_t* rowptr, const int32_t* colind, int64_t rows, int64_t cols, int64_t nnz,
                          hipStream_t s);
@@ -96,7 +111,8 @@ struct HotStageParams {
   int64_t row_bytes;       // N * element size
 };
 hipError_t launch_hot_stage(const HotStageParams& P, int width_bytes, hipStream_t s);
-// cnt[c] += occurrences of column c in colind[0, nnz) (cnt zeroed by the caller).
+// cnt[c] += occurrences of column c in colind[0, nnz) (cnt zeroed by the caller;
+// structure.hip).
 hipError_t launch_count_columns(const int32_t* colind, int64_t nnz, int32_t* cnt, hipStream_t s);
 // out[p] = slot_of[colind[p]] >= 0 ? kHotTag | slot_of[colind[p]] : colind[p].
 hipError_t launch_tag_hot(const int32_t* colind, int64_t nnz, const int32_t* slot_of, int32_t* out, hipStream_t s);

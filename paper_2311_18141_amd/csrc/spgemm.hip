@@ -1079,7 +1079,7 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
     cleanup();
     return st;
   };
-  const spmm_status st = body();
+  const spmm_status st = spmm::guarded(body);
   if (st != SPMM_OK) {
     delete h;
     return st;

@@ -242,7 +242,9 @@ __global__ void __launch_bounds__(kBlock) expand_rows_kernel(const int32_t* rowp
   for (int64_t p = (int64_t)rowptr[i] + lane; p < rowptr[i + 1]; p += 64) rowid[p] = (int32_t)i;
 }
 
-__global__ void __launch_bounds__(kBlock) count_cols_kernel(const int32_t* colind, int64_t nnz, int32_t* cnt) {
+// cnt[c] += uses of column c (one device atomic per non-zero; integer sums, so the
+// result does not depend on the order).
+__global__ void __launch_bounds__(kBlock) count_columns_kernel(const int32_t* colind, int64_t nnz, int32_t* cnt) {
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p < nnz) atomicAdd(&cnt[colind[p]], 1);
 }
@@ -313,6 +315,12 @@ hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* t
   return hipGetLastError();
 }
 
+hipError_t launch_count_columns(const int32_t* colind, int64_t nnz, int32_t* cnt, hipStream_t s) {
+  if (nnz == 0) return hipSuccess;
+  hipLaunchKernelGGL(count_columns_kernel, dim3(blocks_for(nnz, kBlock)), dim3(kBlock), 0, s, colind, nnz, cnt);
+  return hipGetLastError();
+}
+
 int64_t transpose_temp_bytes(int64_t rows, int64_t cols, int64_t nnz) {
   (void)rows;
   const int64_t nb = (nnz + kRsTile - 1) / kRsTile;
@@ -341,10 +349,8 @@ hipError_t build_transpose(const int32_t* rowptr, const int32_t* colind, int64_t
   const int64_t nb = (nnz + kRsTile - 1) / kRsTile;
   int32_t* hist = t + 4 * nnz;
   int32_t* scan_tmp = hist + 256 * (nb > 0 ? nb : 1);
-  if (nnz > 0) {
-    hipLaunchKernelGGL(count_cols_kernel, dim3(blocks_for(nnz, kBlock)), dim3(kBlock), 0, s, colind, nnz, rowptrT);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
+  e = launch_count_columns(colind, nnz, rowptrT, s);
+  if (e != hipSuccess) return e;
   e = scan_exclusive(rowptrT, rowptrT, cols, rowptrT + cols, scan_tmp, s);
   if (e != hipSuccess) return e;
   if (nnz == 0) return hipSuccess;
