@@ -166,6 +166,9 @@ class Workload:
     def cpu_sample(self):  # -> (flops, seconds, description)
         raise NotImplementedError
 
+    def extra(self, kernel_ms):  # further objects for the JSON line, given the per-step kernel time
+        return {}
+
 
 def _fwd_bytes(tiles, N, esize):
     b = 0
@@ -215,7 +218,10 @@ class TileRowForward(Workload):
         self.ws = self.tile.workspace(self.N)
         nnz = sum(t.nnz for t in self.tiles)
         self.flops = 2.0 * nnz * self.N
-        self.alg_bytes = float(_fwd_bytes(self.tiles, self.N, 4 if self.dtype == "f32" else 2))
+        e = 4 if self.dtype == "f32" else 2
+        self.alg_bytes = float(_fwd_bytes(self.tiles, self.N, e))
+        # each non-zero gathers its B row (e N bytes) from the k-tiles' B (sum of cols_k x e N bytes)
+        self.gather_items = [(float(nnz) * e * self.N, sum(t.cols for t in self.tiles) * e * self.N, e * self.N)]
         self.config = dict(self.config, nnz=nnz, rows=self.tiles[0].rows, N=self.N, k_tiles=len(self.tiles),
                            tile_stats={k: v for k, v in self.tile.stats().items()
                                        if k in ("max_row", "empty_rows", "long_rows", "segments", "long_row",
@@ -224,6 +230,9 @@ class TileRowForward(Workload):
     def step(self):
         from paper_2311_18141_amd import ops
         ops.spmm_fwd(self.tile, self.B, C=self.C, workspace=self.ws)
+
+    def extra(self, kernel_ms):
+        return {"cache_gather": gather_ceiling_report(self.gather_items, kernel_ms)}
 
     def cpu_sample(self):
         import oracle
@@ -371,6 +380,8 @@ class Batched(Workload):
         self.persistent_ms = self._time(lambda: ops.spmm_batched(pb, self.B, self.C, workspace=pws), reps=5)
         del pb, pws
         self.tuned_loop_ms = self._time(self._loop, reps=5)
+        # each non-zero gathers its B row (4 N bytes) from the tile's B (cols x 4 N bytes)
+        self.gather_items = [(float(t.nnz) * 4 * N, t.cols * 4 * N, 4 * N) for t, N in zip(self.tiles, self.Ns)]
         kinds = {}
         for t in range(self.count):
             v = self.batch.variant(t)
@@ -393,6 +404,9 @@ class Batched(Workload):
         from paper_2311_18141_amd import ops
         for h, B, C in zip(self.handles, self.B, self.C):
             ops.spmm_fwd(h, [B], C=C)
+
+    def extra(self, kernel_ms):
+        return {"cache_gather": gather_ceiling_report(self.gather_items, kernel_ms)}
 
     @staticmethod
     def _time(fn, reps):
@@ -423,6 +437,67 @@ class Batched(Workload):
             if t_total > 15.0:
                 break
         return flops, t_total, "oracle FP64 forward on the first %d of %d tiles" % (used, self.count)
+
+
+# ---------------------------------------------------------------------------
+# Gather ceiling: the rate at which whole rows of a dense table can be gathered at
+# random (spmm_gather_probe: the forward's loads without its arithmetic), measured for
+# table sizes that fit the L2s (4 MiB per XCD), the Infinity Cache (256 MiB) or only HBM.
+# A workload's ceiling time is the sum over its parts of the bytes they gather at the
+# probe rate for their row width and table size (interpolated in log2 of the size).
+PROBE_MIB = (1, 4, 16, 64, 256, 1024, 4096)
+_PROBE = {}
+
+
+def _probe_rate(width, mib):
+    import torch
+    from paper_2311_18141_amd import ops
+    key = (width, mib)
+    if key not in _PROBE:
+        dev = "cuda:0"
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(11)
+        size = mib << 20
+        table = torch.randint(-(1 << 31), (1 << 31) - 1, (size // 4,), dtype=torch.int32, device=dev, generator=gen)
+        n = min(1 << 24, (2 << 30) // width)
+        idx = torch.randint(0, size // width, (n,), dtype=torch.int32, device=dev, generator=gen)
+        out = torch.empty(1, dtype=torch.int32, device=dev)
+        ms = Batched._time(lambda: ops.spmm_gather_probe(table, width, idx, out), reps=3)
+        _PROBE[key] = n * width / (ms * 1e-3)
+        del table, idx
+    return _PROBE[key]
+
+
+def _probe_width(row_bytes):
+    """The probe row for a gather of row_bytes: capped at 1 KiB (the widest rows here)."""
+    w = min(int(row_bytes), 1024)
+    return max(16, w - w % 16)
+
+
+def gather_ceiling_report(items, kernel_ms):
+    """items: (bytes gathered, table bytes, row bytes) per part of a step."""
+    lg = np.log2(np.array(PROBE_MIB, dtype=np.float64))
+    total, ceil_s, used = 0.0, 0.0, {}
+    for g, table, row in items:
+        w = _probe_width(row)
+        x = float(np.clip(np.log2(max(table, 1) / float(1 << 20)), lg[0], lg[-1]))
+        k = int(np.searchsorted(lg, x))
+        lo, hi = max(k - 1, 0), min(k, len(lg) - 1)
+        if lg[hi] == x:
+            lo = hi
+        r_lo, r_hi = _probe_rate(w, PROBE_MIB[lo]), _probe_rate(w, PROBE_MIB[hi])
+        rate = r_lo if hi == lo else r_lo + (r_hi - r_lo) * (x - lg[lo]) / (lg[hi] - lg[lo])
+        for m in (PROBE_MIB[lo], PROBE_MIB[hi]):
+            used.setdefault("%dB" % w, {})["%dMiB" % m] = round(_PROBE[(w, m)] / 1e9, 1)
+        total += g
+        ceil_s += g / rate
+    return {"probe": "spmm_gather_probe: random whole rows (up to 1 KiB) of a table of the part's size",
+            "probe_GBps": used,
+            "gathered_GB": round(total / 1e9, 2),
+            "achieved_GBps": round(total / (kernel_ms * 1e-3) / 1e9, 1),
+            "ceiling_ms": round(ceil_s * 1e3, 3),
+            "frac": round(ceil_s * 1e3 / kernel_ms, 4)}
+
 
 
 class StationaryA(Workload):
@@ -685,6 +760,7 @@ def main():
                      "traffic_frac": (round(traffic / (avg_kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
                                       if traffic else None)},
     }
+    out.update(wl.extra(avg_kernel_ms))
     if not args.no_cpu_baseline:
         threads = _threads()
         os.environ["OMP_NUM_THREADS"] = str(threads)

@@ -301,6 +301,20 @@ spmm_status spgemm_rowptr(spgemm_t plan, int32_t* rowptrC /* device, M + 1 */, v
 spmm_status spgemm_compute(spgemm_t plan, int32_t* colindC /* device, nnz(C) */, float* valuesC /* device */,
                            void* stream);
 
+/*
+ * Gather micro-benchmark (a measurement aid beside the method, not a step of it):
+ * the forward's memory access without its arithmetic.  For i in [0, n), the row
+ * idx[i] of `table` (device, rows x row_bytes bytes, 16-byte aligned) is read whole
+ * with 16-byte vector loads, several rows in flight per wave; indices outside
+ * [0, rows) are skipped.  *out (device, one word) receives the XOR of every 32-bit
+ * word read (order-free, so a CPU can check it).  Timing a call over a table that
+ * fits a cache level gives that level's ceiling for such gathers.  row_bytes: a
+ * multiple of 16 up to 1024, or of 1024 up to 4096.  Asynchronous.
+ * Errors: INVALID_ARG, HIP.
+ */
+spmm_status spmm_gather_probe(const void* table, int64_t rows, int64_t row_bytes, const int32_t* idx /* device */,
+                              int64_t n, uint32_t* out /* device */, void* stream);
+
 const char* spmm_status_string(spmm_status status);
 const char* spmm_last_error(void);
 

@@ -82,6 +82,7 @@ EXPORTS = {
     "spmm_batch_get_variant": (c_int, [c_vp, c_int, c_vp]),
     "spmm_batched": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_int, c_vp, c_size, c_vp]),
     "spmm_tile_accumulate": (c_int, [c_vp, c_i64, c_vp, c_i64, c_i64, c_i64, c_int, c_vp]),
+    "spmm_gather_probe": (c_int, [c_vp, c_i64, c_i64, c_vp, c_i64, c_vp, c_vp]),
     "spmm_status_string": (ctypes.c_char_p, [c_int]),
     "spmm_last_error": (ctypes.c_char_p, []),
 }

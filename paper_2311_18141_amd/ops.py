@@ -417,3 +417,21 @@ def spgemm_compute(plan: SpgemmPlan, colindC: Optional[torch.Tensor] = None, val
         raise ValueError("outputs need nnz(C) = %d entries" % plan.nnz_c)
     check(lib().spgemm_compute(plan.handle, colindC.data_ptr(), valuesC.data_ptr(), _stream_ptr(stream)))
     return colindC[:plan.nnz_c], valuesC[:plan.nnz_c]
+
+
+def spmm_gather_probe(table: torch.Tensor, row_bytes: int, idx: torch.Tensor, out: Optional[torch.Tensor] = None,
+                      stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """Gather micro-benchmark: read rows idx of `table` (a contiguous device tensor viewed as
+    rows of `row_bytes` bytes) whole; returns a one-word device tensor with the XOR of every
+    32-bit word read."""
+    if not table.is_cuda or not table.is_contiguous():
+        raise ValueError("table must be a contiguous device tensor")
+    nbytes = table.numel() * table.element_size()
+    if row_bytes <= 0 or nbytes % row_bytes:
+        raise ValueError("table size %d is not a multiple of row_bytes %d" % (nbytes, row_bytes))
+    _need(idx, torch.int32, "idx")
+    if out is None:
+        out = torch.empty(1, dtype=torch.int32, device=table.device)
+    check(lib().spmm_gather_probe(table.data_ptr(), nbytes // row_bytes, row_bytes, idx.data_ptr() if idx.numel() else None,
+                                  idx.numel(), out.data_ptr(), _stream_ptr(stream)))
+    return out

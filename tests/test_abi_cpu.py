@@ -196,3 +196,27 @@ def test_spgemm_argument_errors():
     assert L.spgemm_info(None, None, None) == 1
     assert L.spgemm_rowptr(None, None, None) == 1
     assert L.spgemm_compute(None, None, None, None) == 1
+
+
+@pytest.mark.parametrize("case", ["null_out", "no_rows", "null_table", "row_bytes_0", "row_bytes_24", "row_bytes_1040",
+                                  "row_bytes_8192", "neg_n", "null_idx", "misaligned"])
+def test_gather_probe_argument_errors(case):
+    """The gather micro-benchmark checks its arguments before any HIP call."""
+    L = _lib.lib()
+    args = dict(table=0x1000, rows=8, row_bytes=64, idx=0x2000, n=5, out=0x3000)
+    if case == "null_out":
+        args["out"] = None
+    elif case == "no_rows":
+        args["rows"] = 0
+    elif case == "null_table":
+        args["table"] = None
+    elif case.startswith("row_bytes_"):
+        args["row_bytes"] = int(case.split("_")[-1])
+    elif case == "neg_n":
+        args["n"] = -1
+    elif case == "null_idx":
+        args["idx"] = None
+    elif case == "misaligned":
+        args["table"] = 0x1008
+    st = L.spmm_gather_probe(args["table"], args["rows"], args["row_bytes"], args["idx"], args["n"], args["out"], None)
+    assert st == 1, (case, st, L.spmm_last_error())

@@ -55,3 +55,21 @@ def test_committed_readings_parse():
             pytest.skip("no stored reading for %s" % wl)
         text = open(path).read()
         assert "- hbm_bytes_per_step:" in text and "- source_sha256:" in text
+
+
+def test_gather_ceiling_interpolation(monkeypatch):
+    """The ceiling time sums each part's bytes at the probe rate for its row width and table
+    size, interpolated in log2 of the size between the probed sizes (rates given here, so no GPU)."""
+    rates = {(512, m): 1e12 * (2.0 if m <= 4 else 1.0) for m in bench.PROBE_MIB}
+    rates.update({(128, m): 5e11 for m in bench.PROBE_MIB})
+    monkeypatch.setattr(bench, "_PROBE", dict(rates))
+    mib = 1 << 20
+    # exactly on a probed size: 2e12 bytes at 2 TB/s = 1 s
+    r = bench.gather_ceiling_report([(2e12, 4 * mib, 512)], kernel_ms=2000.0)
+    assert r["ceiling_ms"] == pytest.approx(1000.0) and r["frac"] == pytest.approx(0.5)
+    # halfway (in log2) between 4 and 16 MiB: 1.5 TB/s; below 1 MiB clamps to 1 MiB
+    r = bench.gather_ceiling_report([(1.5e12, 8 * mib, 512), (1e12, 1024, 128)], kernel_ms=1000.0)
+    assert r["ceiling_ms"] == pytest.approx(1000.0 + 2000.0)
+    assert r["gathered_GB"] == pytest.approx(2500.0)
+    # rows wider than 1 KiB use the 1 KiB probe
+    assert bench._probe_width(4096) == 1024 and bench._probe_width(256) == 256
