@@ -90,7 +90,8 @@ def _log(msg):
 # are unchanged.
 FWD_SOURCES = ("elem.hpp", "fwd_common.hpp", "fwd.hip", "hot.hip")
 KERNEL_SOURCES = {"powerlaw2m_n128_fwdbwd": FWD_SOURCES + ("bwd.hip",),
-                  "powerlaw2m_n128_fwdbwd_bf16": FWD_SOURCES + ("bwd.hip",)}
+                  "powerlaw2m_n128_fwdbwd_bf16": FWD_SOURCES + ("bwd.hip",),
+                  "uneven512_batched": ("elem.hpp", "fwd_common.hpp", "batch.hip")}
 
 
 def kernel_source_digest(workload: str = "") -> str:
@@ -302,6 +303,12 @@ class ForwardBackward(Workload):
         sddmm = 4 * A.nnz + 4 * (A.rows + 1) + e * A.rows * N + e * A.cols * N + 4 * A.nnz
         dB = 4 * (A.cols + 1) + 12 * A.nnz + e * A.rows * N + e * A.cols * N
         self.alg_bytes = float(fwd + sddmm + dB)
+        # gathers: the forward and the SDDMM read a B row per non-zero, dB a dC row per
+        # non-zero, and the value gather one 4-byte value per non-zero at random (timed as a
+        # 16-byte row, the probe's smallest, from a table of the values' size)
+        row = e * N
+        self.gather_items = [(float(A.nnz) * row, A.cols * row, row), (float(A.nnz) * row, A.cols * row, row),
+                             (float(A.nnz) * row, A.rows * row, row), (float(A.nnz) * 16, 4 * A.nnz, 16)]
         st = self.tile.stats()
         self.config = dict(self.config, nnz=A.nnz, rows=A.rows, N=N,
                            tile_stats={k: st[k] for k in ("max_row", "empty_rows", "long_rows", "segments",
@@ -312,6 +319,9 @@ class ForwardBackward(Workload):
         from paper_2311_18141_amd import ops
         ops.spmm_fwd(self.tile, [self.B], C=self.C, workspace=self.wsf)
         ops.spmm_bwd(self.tile, self.dC, self.B, dA=self.dA, dB=self.dB, workspace=self.wsb)
+
+    def extra(self, kernel_ms):
+        return {"cache_gather": gather_ceiling_report(self.gather_items, kernel_ms)}
 
     def cpu_sample(self):
         import oracle

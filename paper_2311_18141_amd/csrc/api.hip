@@ -321,6 +321,7 @@ hipError_t launch_forward(const spmm_tile_s* A, const Plan& plan, int k_offset, 
     if (A->hcol[k]) {
       P.t[k].hot = hot + A->hot_off[k] * ldh * esize;
       P.t[k].ldh = ldh;
+      P.hot = 1;
     } else {  // no tagged entries: the staged-row address is never taken
       P.t[k].hot = B[k];
       P.t[k].ldh = ldb[k];

@@ -23,7 +23,7 @@
 namespace spmm {
 namespace {
 
-template <int G, int V, typename E>
+template <int G, int V, typename E, bool HOT>
 __global__ void __launch_bounds__(kBlock) fwd_main(FwdParams P) {
   constexpr int GPB = kBlock / G;  // groups per workgroup
   const int gl = threadIdx.x & (G - 1);
@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(kBlock) fwd_main(FwdParams P) {
     if (s >= P.n_seg) return;
     const Seg d = P.seg[s];
     const TileDev& t = P.t[d.k];
-    accumulate_range<G, V, E, true>(t, d.p0, d.p1, static_cast<const char*>(t.B) + cl * (int64_t)sizeof(typename E::T),
+    accumulate_range<G, V, E, HOT>(t, d.p0, d.p1, static_cast<const char*>(t.B) + cl * (int64_t)sizeof(typename E::T),
                                     (uint32_t)(t.ldb * (int64_t)sizeof(typename E::T)), gl, acc,
                                     static_cast<const char*>(t.hot) + cl * (int64_t)sizeof(typename E::T),
                                     (uint32_t)(t.ldh * (int64_t)sizeof(typename E::T)));
@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(kBlock) fwd_main(FwdParams P) {
     int k = kk + P.k_offset;
     if (k >= P.num_k) k -= P.num_k;
     const TileDev& t = P.t[k];
-    accumulate_range<G, V, E, true>(t, t.rowptr[row], t.rowptr[row + 1],
+    accumulate_range<G, V, E, HOT>(t, t.rowptr[row], t.rowptr[row + 1],
                                     static_cast<const char*>(t.B) + cl * (int64_t)sizeof(typename E::T),
                                     (uint32_t)(t.ldb * (int64_t)sizeof(typename E::T)), gl, acc,
                                     static_cast<const char*>(t.hot) + cl * (int64_t)sizeof(typename E::T),
@@ -103,7 +103,7 @@ __device__ __forceinline__ void store_row(const FwdParams& P, int64_t row, int64
   store_vec_nt<E, V>(c, acc);
 }
 
-template <int V, typename E, bool ACC>
+template <int V, typename E, bool ACC, bool HOT>
 __global__ void __launch_bounds__(kBlock) fwd_stream(FwdParams P) {
   constexpr int GPB = kBlock / 64;
   constexpr int U = stream_unroll<V>();
@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(kBlock) fwd_stream(FwdParams P) {
     if (s >= P.n_seg) return;
     const Seg d = P.seg[s];
     const TileDev& t = P.t[d.k];
-    accumulate_range<64, V, E, true>(t, d.p0, d.p1, static_cast<const char*>(t.B) + cl * (int64_t)sizeof(T),
+    accumulate_range<64, V, E, HOT>(t, d.p0, d.p1, static_cast<const char*>(t.B) + cl * (int64_t)sizeof(T),
                                      (uint32_t)(t.ldb * (int64_t)sizeof(T)), lane, acc,
                                      static_cast<const char*>(t.hot) + cl * (int64_t)sizeof(T),
                                      (uint32_t)(t.ldh * (int64_t)sizeof(T)));
@@ -221,7 +221,7 @@ __global__ void __launch_bounds__(kBlock) fwd_stream(FwdParams P) {
     if (lane < n) {
       const uint32_t col = (uint32_t)__builtin_nontemporal_load(colp + p);
       val = __builtin_nontemporal_load(valp + p);
-      addr = reinterpret_cast<uint64_t>(entry_row<true>(col, bp, (uint32_t)(ldbb * (int64_t)sizeof(T)), hp,
+      addr = reinterpret_cast<uint64_t>(entry_row<HOT>(col, bp, (uint32_t)(ldbb * (int64_t)sizeof(T)), hp,
                                                         (uint32_t)(ldhh * (int64_t)sizeof(T))));
       end = (q + 1 == s_pref[ri + 1]) ? 1 : 0;
     }
@@ -319,8 +319,8 @@ __global__ void __launch_bounds__(kBlock) fwd_fixup(FwdParams P) {
   store_vec<E, V>(c, acc);
 }
 
-template <int G, int V, typename E>
-hipError_t launch_gv(const FwdParams& P0, bool stream, hipStream_t s) {
+template <int G, int V, typename E, bool HOT>
+hipError_t launch_gvh(const FwdParams& P0, bool stream, hipStream_t s) {
   FwdParams P = P0;
   constexpr int GPB = kBlock / G;
   const int64_t unit_blocks = (P.n_seg + GPB - 1) / GPB;
@@ -332,14 +332,14 @@ hipError_t launch_gv(const FwdParams& P0, bool stream, hipStream_t s) {
     const size_t lds = sizeof(int32_t) * (size_t)GPB * (65 + 128 * (size_t)P.num_k);
     dim3 grid((unsigned)(unit_blocks + row_blocks), (unsigned)windows);
     if (P.accumulate)
-      hipLaunchKernelGGL((fwd_stream<V, E, true>), grid, dim3(kBlock), lds, s, P);
+      hipLaunchKernelGGL((fwd_stream<V, E, true, HOT>), grid, dim3(kBlock), lds, s, P);
     else
-      hipLaunchKernelGGL((fwd_stream<V, E, false>), grid, dim3(kBlock), lds, s, P);
+      hipLaunchKernelGGL((fwd_stream<V, E, false, HOT>), grid, dim3(kBlock), lds, s, P);
   } else {
     const int64_t row_blocks = (P.rows + GPB - 1) / GPB;
     P.row_blocks = row_blocks;
     dim3 grid((unsigned)(unit_blocks + row_blocks), (unsigned)windows);
-    hipLaunchKernelGGL((fwd_main<G, V, E>), grid, dim3(kBlock), 0, s, P);
+    hipLaunchKernelGGL((fwd_main<G, V, E, HOT>), grid, dim3(kBlock), 0, s, P);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -349,6 +349,13 @@ hipError_t launch_gv(const FwdParams& P0, bool stream, hipStream_t s) {
     return hipGetLastError();
   }
   return hipSuccess;
+}
+
+// Kernels that read staged hot rows are separate instances, so that handles without
+// staging pay nothing for the address select.
+template <int G, int V, typename E>
+hipError_t launch_gv(const FwdParams& P, bool stream, hipStream_t s) {
+  return P.hot ? launch_gvh<G, V, E, true>(P, stream, s) : launch_gvh<G, V, E, false>(P, stream, s);
 }
 
 template <typename E, int V>

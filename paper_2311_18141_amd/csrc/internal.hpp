@@ -82,6 +82,7 @@ struct FwdParams {
   int64_t ldp;
   int64_t row_blocks;    // workgroups of the row-split part (units come after)
   int32_t stream_rows;   // stream variant: rows per wave (1..64)
+  int32_t hot;           // some k-tile reads staged hot rows (tagged colind)
 };
 
 // Kernel variant: G lanes per row (group), V elements per lane per load;
