@@ -50,13 +50,16 @@ HANDLE_OPTS = {}
 AUTOTUNE = False
 
 # Kernel variant (kind, lanes, vec) and split-row plan (long_row, segment) of each
-# single-tile workload: what spmm_tile_autotune(tune_plan=1) picks for it on MI355X.
+# single-tile workload: what spmm_tile_autotune(tune_plan=1) picks for it on MI355X
+# (and for the backward's dB pass, what spmm_tile_autotune_bwd picks).
 # Pinned, so that a profiled run launches exactly the kernels the timed run launches
 # (no autotuner trials); --autotune re-tunes in set-up instead.
 PINNED = {
     "rmat22_rowblock0_4x4_n128": {"variant": ("stream", 64, 2), "long_row": 128, "segment": 64},
-    "powerlaw2m_n128_fwdbwd": {"variant": ("stream", 64, 1), "long_row": 128, "segment": 64},
-    "powerlaw2m_n128_fwdbwd_bf16": {"variant": ("rowsplit", 16, 8), "long_row": 128, "segment": 64},
+    "powerlaw2m_n128_fwdbwd": {"variant": ("rowsplit", 64, 1), "long_row": 1024, "segment": 512,
+                               "bwd_variant": ("rowsplit", 64, 1)},
+    "powerlaw2m_n128_fwdbwd_bf16": {"variant": ("rowsplit", 64, 2), "long_row": 512, "segment": 256,
+                                    "bwd_variant": ("rowsplit", 64, 2)},
     "rmat23_n256_bf16": {"variant": ("rowsplit", 64, 4), "long_row": 128, "segment": 64},
     "rmat23_n256_f32": {"variant": ("stream", 64, 2), "long_row": 128, "segment": 64},
 }
@@ -290,10 +293,21 @@ class ForwardBackward(Workload):
             self.config["variant"] = chosen
         else:
             self.config["variant"] = _apply_pin(self.name, self.tile, self.N, tdt)
-        fk = "fwd_main" if (self.config["variant"] or {}).get("kind") == "rowsplit" else "fwd_stream"
-        self.kernel = "spmm_fwd + spmm_bwd (%s, fwd_fixup, sddmm_kernel, gather_values)" % fk
         self.dA = torch.empty(self.A.nnz, device=dev)
         self.dB = torch.empty(self.A.cols, self.N, device=dev, dtype=tdt)
+        # the dB pass (forward kernels over the transpose) has its own variant
+        if AUTOTUNE:
+            t0 = time.time()
+            chosen = ops.spmm_tile_autotune_bwd(self.tile, self.dC, self.dB)
+            _log("%s: dB pass autotuned in %.1f s: %s" % (self.name, time.time() - t0, chosen))
+            self.config["bwd_variant"] = chosen
+        elif PINNED.get(self.name, {}).get("bwd_variant"):
+            kind, lanes, vec = PINNED[self.name]["bwd_variant"]
+            ops.spmm_tile_set_bwd_variant(self.tile, self.N, tdt, kind, lanes, vec)
+            self.config["bwd_variant"] = {"kind": kind, "lanes": lanes, "vec": vec, "pinned": True}
+        fk = "fwd_main" if (self.config["variant"] or {}).get("kind") == "rowsplit" else "fwd_stream"
+        bk = "fwd_main" if (self.config.get("bwd_variant") or {}).get("kind") == "rowsplit" else "fwd_stream"
+        self.kernel = "spmm_fwd + spmm_bwd (%s, fwd_fixup, sddmm_kernel, gather_values, %s on the transpose)" % (fk, bk)
         self.wsf = self.tile.workspace(self.N, "fwd")
         self.wsb = self.tile.workspace(self.N, "bwd")
         A, N = self.A, self.N

@@ -190,6 +190,20 @@ spmm_status spmm_fwd(spmm_tile_t A, int k_offset, const void* const* B, const in
                      spmm_dtype b_dtype, void* C, int64_t ldc, spmm_dtype c_dtype, int64_t N,
                      int accumulate, void* workspace, size_t ws_bytes, void* stream);
 
+/* The backward's dB pass (dB = A^T dC) runs the forward kernels over the transposed
+   structure; it keeps its own variant per (N, dtype), set here (v != NULL) or cleared
+   (v == NULL; the fixed rule then applies).  Results of every variant agree as the
+   forward's do.  Errors: INVALID_ARG (bad field values, table of 16 entries full). */
+spmm_status spmm_tile_set_bwd_variant(spmm_tile_t tile, int64_t N, spmm_dtype dtype, const spmm_variant* v);
+
+/* Time the dB pass's variants on the caller's dC (rows x N, ld lddc) for a K = 1 handle
+   built with SPMM_TILE_TRANSPOSE and keep the fastest for (N, dtype).  Synchronous;
+   allocates its own scratch; overwrites dB (cols x N, ld lddb).  `chosen` (nullable)
+   receives the winner.  Errors: INVALID_ARG, UNSUPPORTED (no transpose, num_k > 1,
+   ld too large), ALLOC, HIP. */
+spmm_status spmm_tile_autotune_bwd(spmm_tile_t tile, int64_t N, spmm_dtype dtype, const void* dC, int64_t lddc,
+                                   void* dB, int64_t lddb, void* stream, spmm_variant* chosen /* host */);
+
 /* Workspace (device bytes) spmm_bwd needs for this handle at width N when dB is
    wanted: FP32 partial rows of the transposed plan's split rows plus 4 bytes per
    non-zero (A's values gathered into the transposed order on every call). */

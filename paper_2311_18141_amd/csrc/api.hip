@@ -238,8 +238,10 @@ struct spmm_tile_s {
     int dtype;
     spmm_variant v;
   };
-  VarEntry vt[16];
+  VarEntry vt[16];          // forward variants
   int nvt = 0;
+  VarEntry vtT[16];         // variants of the backward's dB pass (forward kernels on the transpose)
+  int nvtT = 0;
   int64_t bwd_slice = 0;   // SDDMM column slice (0 = all columns in one launch)
   struct SddmmEntry {
     int64_t N;
@@ -271,18 +273,20 @@ struct spmm_tile_s {
 
 namespace {
 
-// The variant for one call: the handle's entry for (N, dtype) when it fits the
-// call's alignment, otherwise the fixed rule.
-spmm::Variant resolve_variant(const spmm_tile_s* A, int64_t N, DT dt, uintptr_t align_or) {
-  const spmm::Variant base = pick_variant(N, dt, align_or, A->rows);
+using VarEntry = spmm_tile_s::VarEntry;
+
+// The variant for one call: the table's entry for (N, dtype) when it fits the call's
+// alignment, otherwise the fixed rule (for a pass over `rows` rows).
+spmm::Variant resolve_variant_in(const VarEntry* vt, int nvt, int64_t rows, int64_t N, DT dt, uintptr_t align_or) {
+  const spmm::Variant base = pick_variant(N, dt, align_or, rows);
   const int esize = dt == DT::F32 ? 4 : 2;
   const int want = dt == DT::F32 ? SPMM_F32 : SPMM_BF16;
-  for (int i = 0; i < A->nvt; ++i) {
-    const auto& e = A->vt[i];
+  for (int i = 0; i < nvt; ++i) {
+    const auto& e = vt[i];
     if (e.N != N || e.dtype != want || e.v.kind == SPMM_KERNEL_AUTO) continue;
     const int V = e.v.vec ? e.v.vec : base.V;
     if ((N % V) != 0 || (align_or % (uintptr_t)(V * esize)) != 0) return base;
-    if (e.v.kind == SPMM_KERNEL_STREAM) return spmm::Variant{64, V, true, e.v.lanes ? e.v.lanes : stream_rows_for(A->rows)};
+    if (e.v.kind == SPMM_KERNEL_STREAM) return spmm::Variant{64, V, true, e.v.lanes ? e.v.lanes : stream_rows_for(rows)};
     int G = e.v.lanes;
     if (G == 0) {
       G = 4;
@@ -291,6 +295,59 @@ spmm::Variant resolve_variant(const spmm_tile_s* A, int64_t N, DT dt, uintptr_t 
     return spmm::Variant{G, V, false};
   }
   return base;
+}
+
+spmm::Variant resolve_variant(const spmm_tile_s* A, int64_t N, DT dt, uintptr_t align_or) {
+  return resolve_variant_in(A->vt, A->nvt, A->rows, N, dt, align_or);
+}
+
+// Set (v != null) or clear (v == null) a table's entry for (N, dtype).
+spmm_status set_variant_in(VarEntry* vt, int* nvt, int64_t N, spmm_dtype dtype, const spmm_variant* v) {
+  int slot = -1;
+  for (int i = 0; i < *nvt; ++i)
+    if (vt[i].N == N && vt[i].dtype == dtype) slot = i;
+  if (!v) {
+    if (slot >= 0) {
+      vt[slot] = vt[*nvt - 1];
+      --*nvt;
+    }
+    return SPMM_OK;
+  }
+  if (slot < 0) {
+    if (*nvt >= 16) return fail(SPMM_ERR_INVALID_ARG, "variant table is full");
+    slot = (*nvt)++;
+  }
+  vt[slot].N = N;
+  vt[slot].dtype = dtype;
+  vt[slot].v = *v;
+  return SPMM_OK;
+}
+
+// Autotuner candidates for width N: the two widest aligned vector widths, for each the
+// covering group size, half of it and a full wave, a full-wave group at a quarter of
+// the widest width, and the stream kernel (64, 16 and 4 rows per wave).
+std::vector<spmm::Variant> candidate_variants(int64_t N, DT dt, uintptr_t align_or, int64_t rows) {
+  const int esize = dt == DT::F32 ? 4 : 2;
+  std::vector<spmm::Variant> kv;
+  auto add = [&](spmm::Variant v) {
+    for (auto& u : kv)
+      if (u.G == v.G && u.V == v.V && u.stream == v.stream && (!v.stream || u.rows == v.rows)) return;
+    kv.push_back(v);
+  };
+  add(pick_variant(N, dt, align_or, rows));
+  int vmax = 16 / esize;
+  while (vmax > 1 && ((N % vmax) != 0 || (align_or % (uintptr_t)(vmax * esize)) != 0)) vmax /= 2;
+  for (int V = vmax; V >= 1 && V >= vmax / 4; V /= 2) {
+    if ((N % V) != 0) continue;
+    for (int R : {64, 16, 4}) add(spmm::Variant{64, V, true, R});
+    add(spmm::Variant{64, V, false});
+    if (V < vmax / 2) continue;
+    int G = 4;
+    while (G < 64 && G < (N + V - 1) / V) G *= 2;
+    if (G >= 8) add(spmm::Variant{G / 2, V, false});
+    add(spmm::Variant{G, V, false});
+  }
+  return kv;
 }
 
 // Forward workspace: FP32 partial rows of the plan's split-row units, then (at a
@@ -687,24 +744,15 @@ spmm_status spmm_tile_set_variant(spmm_tile_t A, int64_t N, spmm_dtype dtype, co
   if (N < 1) return fail(SPMM_ERR_INVALID_ARG, "N=%lld < 1", (long long)N);
   if (dtype != SPMM_F32 && dtype != SPMM_BF16) return fail(SPMM_ERR_INVALID_ARG, "unknown dtype");
   if (v && !valid_variant(*v, dtype)) return fail(SPMM_ERR_INVALID_ARG, "invalid variant fields");
-  int slot = -1;
-  for (int i = 0; i < A->nvt; ++i)
-    if (A->vt[i].N == N && A->vt[i].dtype == dtype) slot = i;
-  if (!v) {
-    if (slot >= 0) {
-      A->vt[slot] = A->vt[A->nvt - 1];
-      --A->nvt;
-    }
-    return SPMM_OK;
-  }
-  if (slot < 0) {
-    if (A->nvt >= 16) return fail(SPMM_ERR_INVALID_ARG, "variant table is full");
-    slot = A->nvt++;
-  }
-  A->vt[slot].N = N;
-  A->vt[slot].dtype = dtype;
-  A->vt[slot].v = *v;
-  return SPMM_OK;
+  return set_variant_in(A->vt, &A->nvt, N, dtype, v);
+}
+
+spmm_status spmm_tile_set_bwd_variant(spmm_tile_t A, int64_t N, spmm_dtype dtype, const spmm_variant* v) {
+  if (!A) return fail(SPMM_ERR_INVALID_ARG, "tile is null");
+  if (N < 1) return fail(SPMM_ERR_INVALID_ARG, "N=%lld < 1", (long long)N);
+  if (dtype != SPMM_F32 && dtype != SPMM_BF16) return fail(SPMM_ERR_INVALID_ARG, "unknown dtype");
+  if (v && !valid_variant(*v, dtype)) return fail(SPMM_ERR_INVALID_ARG, "invalid variant fields");
+  return set_variant_in(A->vtT, &A->nvtT, N, dtype, v);
 }
 
 spmm_status spmm_tile_set_sddmm_variant(spmm_tile_t A, int64_t N, int32_t lanes, int32_t nnz_per_group) {
@@ -764,28 +812,8 @@ static spmm_status autotune_impl(spmm_tile_t A, int64_t N, spmm_dtype dtype, con
   if (dev != A->device) return fail(SPMM_ERR_INVALID_ARG, "current device differs from the handle's");
   hipStream_t s = static_cast<hipStream_t>(stream);
 
-  // Kernel candidates: the two widest aligned vector widths, for each the covering
-  // group size, half of it and a full wave, plus the stream kernel.
   const spmm::Variant base = pick_variant(N, dt, align_or, A->rows);
-  std::vector<spmm::Variant> kv;
-  auto add = [&](spmm::Variant v) {
-    for (auto& u : kv)
-      if (u.G == v.G && u.V == v.V && u.stream == v.stream && (!v.stream || u.rows == v.rows)) return;
-    kv.push_back(v);
-  };
-  add(base);
-  int vmax = 16 / esize;
-  while (vmax > 1 && ((N % vmax) != 0 || (align_or % (uintptr_t)(vmax * esize)) != 0)) vmax /= 2;
-  for (int V = vmax; V >= 1 && V >= vmax / 4; V /= 2) {
-    if ((N % V) != 0) continue;
-    for (int R : {64, 16, 4}) add(spmm::Variant{64, V, true, R});
-    if (V < vmax / 2) continue;
-    int G = 4;
-    while (G < 64 && G < (N + V - 1) / V) G *= 2;
-    if (G >= 8) add(spmm::Variant{G / 2, V, false});
-    add(spmm::Variant{G, V, false});
-    add(spmm::Variant{64, V, false});
-  }
+  const std::vector<spmm::Variant> kv = candidate_variants(N, dt, align_or, A->rows);
   // Split-plan candidates (threshold, unit length).
   std::vector<std::pair<int32_t, int32_t>> pc;
   pc.push_back({A->plan.long_row, A->plan.segment});
@@ -973,9 +1001,97 @@ spmm_status spmm_bwd(spmm_tile_t A, const void* dC, int64_t lddc, const void* B,
     P.ldp = (int64_t)partial_ld(N);
     const uintptr_t a = reinterpret_cast<uintptr_t>(dC) | reinterpret_cast<uintptr_t>(dB) |
                         (uintptr_t)(lddc * esize) | (uintptr_t)(lddb * esize);
-    HIP_TRY(spmm::launch_fwd(P, pick_variant(N, dt, a, t.cols), dt, s));
+    HIP_TRY(spmm::launch_fwd(P, resolve_variant_in(A->vtT, A->nvtT, t.cols, N, dt, a), dt, s));
   }
   return SPMM_OK;
+}
+
+static spmm_status autotune_bwd_impl(spmm_tile_t A, int64_t N, spmm_dtype dtype, const void* dC, int64_t lddc,
+                                     void* dB, int64_t lddb, void* stream, spmm_variant* chosen) {
+  if (!A) return fail(SPMM_ERR_INVALID_ARG, "tile is null");
+  if (A->num_k != 1) return fail(SPMM_ERR_UNSUPPORTED, "the dB pass needs a single-tile handle");
+  if (!A->has_t) return fail(SPMM_ERR_UNSUPPORTED, "handle was created without SPMM_TILE_TRANSPOSE");
+  if (N < 1) return fail(SPMM_ERR_INVALID_ARG, "N=%lld < 1", (long long)N);
+  if (dtype != SPMM_F32 && dtype != SPMM_BF16) return fail(SPMM_ERR_INVALID_ARG, "unknown dtype");
+  const DT dt = dtype == SPMM_F32 ? DT::F32 : DT::BF16;
+  const int64_t esize = dt == DT::F32 ? 4 : 2;
+  const spmm_csr& t = A->t[0];
+  if (!dC && A->rows > 0) return fail(SPMM_ERR_INVALID_ARG, "dC is null");
+  if (!dB && t.cols > 0) return fail(SPMM_ERR_INVALID_ARG, "dB is null");
+  if (lddc < N || lddb < N) return fail(SPMM_ERR_INVALID_ARG, "leading dimension < N");
+  if (lddc * esize >= ((int64_t)1 << 32)) return fail(SPMM_ERR_UNSUPPORTED, "lddc too large");
+  if ((N + 63) / 64 > 65535) return fail(SPMM_ERR_UNSUPPORTED, "N too large for one launch");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != A->device) return fail(SPMM_ERR_INVALID_ARG, "current device differs from the handle's");
+  const uintptr_t a = reinterpret_cast<uintptr_t>(dC) | reinterpret_cast<uintptr_t>(dB) | (uintptr_t)(lddc * esize) |
+                      (uintptr_t)(lddb * esize);
+  spmm::Variant best_v = pick_variant(N, dt, a, t.cols);
+  if (t.cols > 0 && t.nnz > 0) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const std::vector<spmm::Variant> kv = candidate_variants(N, dt, a, t.cols);
+    void* ws = nullptr;
+    HIP_TRY(hipMalloc(&ws, bwd_workspace(A, N)));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    spmm_status st = SPMM_OK;
+    float best = 1e30f;
+    auto run = [&]() -> spmm_status {
+      HIP_TRY(hipEventCreate(&e0));
+      HIP_TRY(hipEventCreate(&e1));
+      float* valuesT = reinterpret_cast<float*>(static_cast<char*>(ws) + bwd_partial_bytes(A, N));
+      HIP_TRY(spmm::launch_gather_values(A->perm, t.values, valuesT, t.nnz, s));
+      spmm::FwdParams P{};
+      P.t[0].rowptr = A->rowptrT;
+      P.t[0].colind = A->colindT;
+      P.t[0].values = valuesT;
+      P.t[0].B = dC;
+      P.t[0].ldb = lddc;
+      P.t[0].hot = dC;
+      P.t[0].ldh = lddc;
+      P.num_k = 1;
+      P.rows = t.cols;
+      P.N = N;
+      P.C = dB;
+      P.ldc = lddb;
+      P.long_row = A->planT.long_row;
+      P.seg = A->planT.seg;
+      P.n_seg = A->planT.n_seg;
+      P.lrow = A->planT.lrow;
+      P.n_long = A->planT.n_long;
+      P.partial = static_cast<float*>(ws);
+      P.ldp = (int64_t)partial_ld(N);
+      for (const auto& v : kv) {
+        HIP_TRY(spmm::launch_fwd(P, v, dt, s));
+        HIP_TRY(hipEventRecord(e0, s));
+        for (int r = 0; r < 3; ++r) HIP_TRY(spmm::launch_fwd(P, v, dt, s));
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+          best = ms;
+          best_v = v;
+        }
+      }
+      return SPMM_OK;
+    };
+    st = run();
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(ws);
+    if (st != SPMM_OK) return st;
+  }
+  spmm_variant out{best_v.stream ? SPMM_KERNEL_STREAM : SPMM_KERNEL_ROWSPLIT, best_v.stream ? best_v.rows : best_v.G,
+                   best_v.V};
+  spmm_status st = set_variant_in(A->vtT, &A->nvtT, N, dtype, &out);
+  if (st == SPMM_OK && chosen) *chosen = out;
+  return st;
+}
+
+spmm_status spmm_tile_autotune_bwd(spmm_tile_t A, int64_t N, spmm_dtype dtype, const void* dC, int64_t lddc,
+                                   void* dB, int64_t lddb, void* stream, spmm_variant* chosen) {
+  return spmm::guarded([&]() { return autotune_bwd_impl(A, N, dtype, dC, lddc, dB, lddb, stream, chosen); });
 }
 
 }  // extern "C"

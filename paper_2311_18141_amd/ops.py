@@ -149,6 +149,36 @@ def spmm_tile_set_variant(tile: Tile, N: int, dtype=torch.float32, kind: Optiona
     check(lib().spmm_tile_set_variant(tile.handle, N, _DTYPES[dtype], ctypes.byref(v)))
 
 
+def spmm_tile_set_bwd_variant(tile: Tile, N: int, dtype=torch.float32, kind: Optional[str] = "auto",
+                              lanes: int = 0, vec: int = 0) -> None:
+    """Pin the kernel variant of the backward's dB pass for width N (kind None clears the entry)."""
+    if kind is None:
+        check(lib().spmm_tile_set_bwd_variant(tile.handle, N, _DTYPES[dtype], None))
+        return
+    v = SpmmVariant(KERNELS[kind], lanes, vec)
+    check(lib().spmm_tile_set_bwd_variant(tile.handle, N, _DTYPES[dtype], ctypes.byref(v)))
+
+
+def spmm_tile_autotune_bwd(tile: Tile, dC: torch.Tensor, dB: Optional[torch.Tensor] = None,
+                           stream: Optional[torch.cuda.Stream] = None) -> dict:
+    """Time the dB pass's variants on this dC (dB is overwritten); keep the fastest."""
+    dt = dC.dtype
+    if dt not in _DTYPES:
+        raise ValueError("dC must be float32 or bfloat16")
+    N = dC.shape[1]
+    if dC.shape != (tile.rows, N):
+        raise ValueError("dC must be (%d, N)" % tile.rows)
+    if dB is None:
+        dB = torch.empty(tile.cols[0], N, dtype=dt, device=dC.device)
+    if dB.dtype != dt or dB.shape != (tile.cols[0], N):
+        raise ValueError("dB must be %s of shape (%d, %d)" % (dt, tile.cols[0], N))
+    out = SpmmVariant()
+    check(lib().spmm_tile_autotune_bwd(tile.handle, N, _DTYPES[dt], dC.data_ptr(), _row_major_ld(dC, "dC"),
+                                       dB.data_ptr(), _row_major_ld(dB, "dB"), _stream_ptr(stream), ctypes.byref(out)))
+    inv = {v: k for k, v in KERNELS.items()}
+    return {"kind": inv[out.kind], "lanes": out.lanes, "vec": out.vec}
+
+
 def spmm_tile_set_sddmm_variant(tile: Tile, N: int, lanes: int = 0, nnz_per_group: int = 4) -> None:
     """Shape of the backward's SDDMM kernel at width N (lanes = 0: library choice)."""
     check(lib().spmm_tile_set_sddmm_variant(tile.handle, N, lanes, nnz_per_group if lanes else 0))

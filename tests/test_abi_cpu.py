@@ -220,3 +220,11 @@ def test_gather_probe_argument_errors(case):
         args["table"] = 0x1008
     st = L.spmm_gather_probe(args["table"], args["rows"], args["row_bytes"], args["idx"], args["n"], args["out"], None)
     assert st == 1, (case, st, L.spmm_last_error())
+
+
+def test_bwd_variant_argument_errors():
+    """The dB-pass variant setter and autotuner check their arguments before any HIP call."""
+    L = _lib.lib()
+    v = _lib.SpmmVariant(_lib.SPMM_KERNEL_ROWSPLIT, 16, 4)
+    assert L.spmm_tile_set_bwd_variant(None, 64, 0, ctypes.byref(v)) == 1
+    assert L.spmm_tile_autotune_bwd(None, 64, 0, 0x1000, 64, 0x2000, 64, None, None) == 1

@@ -269,3 +269,72 @@ def test_autograd_bf16():
     assert compare.fp32_ok(compare.fp32_stats(values.grad.cpu().numpy(), rA, SA))
     rB, SB = oracle.spmm_t(A.rowptr, A.colind, A.values, A.cols, dCt)
     G.assert_bf16_close(Bt.grad.float().cpu().numpy(), rB, SB, what="dB")
+
+
+BWD_VARIANTS = [("stream", 64, 1), ("stream", 64, 2), ("stream", 16, 4), ("rowsplit", 8, 4), ("rowsplit", 16, 4),
+                ("rowsplit", 32, 2), ("rowsplit", 64, 2), ("rowsplit", 64, 1)]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("variant", BWD_VARIANTS)
+def test_dB_variants_integer_exact(variant, dtype):
+    """Every kernel variant of the dB pass (forward kernels over the transpose, split rows
+    included) gives the exact integer sum (rounded once to BF16 for a BF16 dB)."""
+    kind, lanes, vec = variant
+    G.note("dB variant %s %s" % (variant, dtype))
+    rng = _rng(95)
+    M, K, N = 4000, 2000, 64
+    L = rng.integers(0, 24, size=M)
+    A = synth.random_csr(M, K, L, rng, "int8")
+    hub = rng.choice(M, size=300, replace=False)          # column 5 is used by 300 rows: split in A^T
+    cols = [np.union1d(A.colind[A.rowptr[i]:A.rowptr[i + 1]], [5]) if i in set(hub) else
+            A.colind[A.rowptr[i]:A.rowptr[i + 1]] for i in range(M)]
+    lengths = np.array([len(c) for c in cols])
+    A = synth.CSR(M, K, synth.rowptr_from_lengths(lengths), np.concatenate(cols).astype(np.int32),
+                  rng.integers(-8, 9, size=int(lengths.sum())).astype(np.float32))
+    B = synth.dense(K, N, rng, "int8")
+    dC = synth.dense(M, N, rng, "int8")
+    tdt = torch.float32 if dtype == "f32" else torch.bfloat16
+    tile = G.make_tile([A], transpose=True, long_row=128, segment=32)
+    assert tile.stats()["long_rows_t"] > 0
+    ops.spmm_tile_set_bwd_variant(tile, N, tdt, kind, lanes, vec)
+    _, dB = ops.spmm_bwd(tile, G.dense_dev(dC, tdt), G.dense_dev(B, tdt), want_dA=False)
+    torch.cuda.synchronize()
+    rB, _ = oracle.spmm_t(A.rowptr, A.colind, A.values, K, dC)
+    if dtype == "f32":
+        assert np.array_equal(dB.cpu().numpy().astype(np.float64), rB)
+    else:
+        assert np.abs(rB).max() < 2 ** 24
+        got = dB.cpu().view(torch.int16).numpy().view(np.uint16)
+        assert np.array_equal(got, oracle.f32_to_bf16(rB.astype(np.float32)))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_autotune_bwd(dtype):
+    """The dB-pass autotuner keeps a variant; the backward then still matches the oracle."""
+    G.note("autotune dB %s" % dtype)
+    rng = _rng(96)
+    A = synth.powerlaw_csr(1 << 14, 1 << 14, 16, 4096, seed=9)
+    A = synth.CSR(A.rows, A.cols, A.rowptr, A.colind, rng.integers(-8, 9, size=A.nnz).astype(np.float32))
+    N = 128
+    B = synth.dense(A.cols, N, rng, "int8")
+    dC = synth.dense(A.rows, N, rng, "int8")
+    tdt = torch.float32 if dtype == "f32" else torch.bfloat16
+    tile = G.make_tile([A], transpose=True)
+    dCd, Bd = G.dense_dev(dC, tdt), G.dense_dev(B, tdt)
+    chosen = ops.spmm_tile_autotune_bwd(tile, dCd)
+    assert chosen["kind"] in ("stream", "rowsplit") and chosen["vec"] >= 1
+    dA, dB = ops.spmm_bwd(tile, dCd, Bd)
+    torch.cuda.synchronize()
+    rA, _ = oracle.sddmm(A.rowptr, A.colind, dC, B)
+    rB, _ = oracle.spmm_t(A.rowptr, A.colind, A.values, A.cols, dC)
+    assert np.array_equal(dA.cpu().numpy().astype(np.float64), rA)
+    if dtype == "f32":
+        assert np.array_equal(dB.cpu().numpy().astype(np.float64), rB)
+    else:
+        got = dB.cpu().view(torch.int16).numpy().view(np.uint16)
+        assert np.array_equal(got, oracle.f32_to_bf16(rB.astype(np.float32)))
+    ops.spmm_tile_set_bwd_variant(tile, N, tdt, None)          # cleared: the fixed rule again
+    _, dB2 = ops.spmm_bwd(tile, dCd, Bd, want_dA=False)
+    torch.cuda.synchronize()
+    assert torch.equal(dB, dB2)
