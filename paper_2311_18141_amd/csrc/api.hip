@@ -956,11 +956,12 @@ spmm_status spmm_bwd(spmm_tile_t A, const void* dC, int64_t lddc, const void* B,
     // Column slices: one launch per slice of `slice` columns (all of N when 0).
     const int64_t slice = (A->bwd_slice > 0 && A->bwd_slice < N && (A->bwd_slice % V) == 0) ? A->bwd_slice : N;
     const int64_t need_lanes = (slice + V - 1) / V;
-    // 8 lanes x U = 4 non-zeros per group: 32 B rows in flight per wave measured best
-    // on the heavy-tailed 2M x 2M matrix at N = 128 (narrower slices use fewer lanes).
+    // 8 lanes x U non-zeros per group measured best on the heavy-tailed 2M x 2M matrix at
+    // N = 128: U = 4 (32 B rows in flight per wave) for FP32, U = 2 for BF16, whose
+    // 16-element loads make each row fetch twice as wide (narrower slices use fewer lanes).
     int G = 4;
     while (G < 8 && G < need_lanes) G *= 2;
-    int U = 4;
+    int U = dt == DT::F32 ? 4 : 2;
     for (int i = 0; i < A->nsd; ++i)
       if (A->sd[i].N == N) {
         G = A->sd[i].G;
