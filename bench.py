@@ -57,9 +57,9 @@ AUTOTUNE = False
 PINNED = {
     "rmat22_rowblock0_4x4_n128": {"variant": ("stream", 64, 2), "long_row": 128, "segment": 64},
     "powerlaw2m_n128_fwdbwd": {"variant": ("rowsplit", 64, 1), "long_row": 1024, "segment": 512,
-                               "bwd_variant": ("rowsplit", 64, 1)},
+                               "bwd_variant": ("rowsplit", 64, 1), "sddmm": (8, 4)},
     "powerlaw2m_n128_fwdbwd_bf16": {"variant": ("rowsplit", 64, 2), "long_row": 512, "segment": 256,
-                                    "bwd_variant": ("rowsplit", 64, 2)},
+                                    "bwd_variant": ("rowsplit", 64, 2), "sddmm": (8, 2)},
     "rmat23_n256_bf16": {"variant": ("rowsplit", 64, 4), "long_row": 128, "segment": 64},
     "rmat23_n256_f32": {"variant": ("stream", 64, 2), "long_row": 128, "segment": 64},
 }
@@ -98,13 +98,16 @@ KERNEL_SOURCES = {"powerlaw2m_n128_fwdbwd": FWD_SOURCES + ("bwd.hip",),
 
 
 def kernel_source_digest(workload: str = "") -> str:
-    """SHA-256 over the sources of the kernels `workload` launches (the forward's by default)."""
+    """SHA-256 over the sources of the kernels `workload` launches (the forward's by default)
+    and over its pinned kernel shapes, so that a stored reading lapses when either changes."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2311_18141_amd", "csrc")
     for name in KERNEL_SOURCES.get(workload, FWD_SOURCES):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
+    if workload in PINNED:
+        h.update(b"pin\0" + json.dumps(PINNED[workload], sort_keys=True).encode())
     return h.hexdigest()
 
 
@@ -305,6 +308,11 @@ class ForwardBackward(Workload):
             kind, lanes, vec = PINNED[self.name]["bwd_variant"]
             ops.spmm_tile_set_bwd_variant(self.tile, self.N, tdt, kind, lanes, vec)
             self.config["bwd_variant"] = {"kind": kind, "lanes": lanes, "vec": vec, "pinned": True}
+        # the SDDMM's shape (lanes x non-zeros per group), pinned like the variants
+        sd = PINNED.get(self.name, {}).get("sddmm")
+        if sd:
+            ops.spmm_tile_set_sddmm_variant(self.tile, self.N, sd[0], sd[1])
+            self.config["sddmm"] = {"lanes": sd[0], "nnz_per_group": sd[1], "pinned": True}
         fk = "fwd_main" if (self.config["variant"] or {}).get("kind") == "rowsplit" else "fwd_stream"
         bk = "fwd_main" if (self.config.get("bwd_variant") or {}).get("kind") == "rowsplit" else "fwd_stream"
         self.kernel = "spmm_fwd + spmm_bwd (%s, fwd_fixup, sddmm_kernel, gather_values, %s on the transpose)" % (fk, bk)
