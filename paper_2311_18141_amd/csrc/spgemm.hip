@@ -188,10 +188,11 @@ __device__ __forceinline__ int32_t block_scan(int32_t v, int32_t* excl, int32_t*
 // with WIN, only the products whose column lies in [c0, c1), each B row cut to that
 // range by the split table when given (bsplit[k * stride + win] = first position at
 // column >= win * window) or by binary search.  The workgroup takes kWG A entries at a
-// time; their (cut) B-row lengths are prefix-summed and each thread walks one
-// contiguous run of ceil(total / kWG) products: one binary search in the prefix per
-// run, then a linear step over segment boundaries (products of one B row are
-// contiguous, so a thread's loads walk along the B row).
+// time; their (cut) B-row lengths are prefix-summed, each wave takes one contiguous
+// share (1/kWGWaves) of the products and its lanes take consecutive ones
+// (lane l: l, l + 64, ...): one binary search in the prefix per lane, then a forward
+// step over segment boundaries, four loads in flight; the 64 loads of an instruction
+// are consecutive entries of one or two B rows, so they coalesce.
 // LDS: s_pref[kWG + 1], s_start[kWG], s_aval[kWG], s_tmp[kWGWaves].
 template <bool VALS, bool WIN, typename F>
 __device__ __forceinline__ void block_products(const SgOperands& O, int32_t a0, int32_t a1, int32_t* s_pref,
@@ -227,35 +228,40 @@ __device__ __forceinline__ void block_products(const SgOperands& O, int32_t a0, 
     if constexpr (VALS) s_aval[tid] = av;
     if (tid == 0) s_pref[kWG] = tot;
     __syncthreads();
-    const int32_t run = (tot + kWG - 1) / kWG;
-    int32_t t = tid * run;
-    const int32_t t_end = min(t + run, tot);
-    if (t < t_end) {
+    // each wave takes a contiguous share of the products; its lanes take consecutive
+    // products (lane l: l, l + 64, ...), so the B loads of a wave are contiguous
+    constexpr int kWaves = kWG / 64;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int32_t per_wave = (((tot + kWaves - 1) / kWaves) + 63) & ~63;
+    const int32_t w0 = wv * per_wave;
+    const int32_t w1 = min(w0 + per_wave, tot);
+    int32_t t = w0 + lane;
+    if (t < w1) {
       int pi = 0;
 #pragma unroll
       for (int step = kWG / 2; step > 0; step >>= 1)
         if (s_pref[pi + step] <= t) pi += step;
       int32_t next = s_pref[pi + 1];
-      int32_t q = s_start[pi] + (t - s_pref[pi]);
+      int32_t base = s_start[pi] - s_pref[pi];
       float a = VALS ? s_aval[pi] : 0.0f;
-      // four products per pass: positions first, then the loads, then f
-      while (t < t_end) {
-        int32_t qs[4] = {q, q, q, q};
-        float as[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      while (t < w1) {
+        int32_t qs[4];
+        float as[4];
         int cnt = 0;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          if (t < t_end) {
-            while (t >= next) {  // cross into the next non-empty segment
+          qs[u] = 0;
+          as[u] = 0.0f;
+          if (t < w1) {
+            while (t >= next) {  // forward to the segment holding t
               ++pi;
               next = s_pref[pi + 1];
-              q = s_start[pi];
+              base = s_start[pi] - s_pref[pi];
               if constexpr (VALS) a = s_aval[pi];
             }
-            qs[u] = q;
+            qs[u] = base + t;
             as[u] = a;
-            ++q;
-            ++t;
+            t += 64;
             cnt = u + 1;
           }
         }
