@@ -184,16 +184,83 @@ __device__ __forceinline__ int32_t block_scan(int32_t v, int32_t* excl, int32_t*
   return total;
 }
 
+// Visit the products of the workgroup's B-row segments: thread tid < n holds segment
+// [st, st + len) of B (len = 0 elsewhere) scaled by av; f(col, av * b) for each entry.
+// The lengths are prefix-summed, each wave takes one contiguous share (1/kWGWaves) of
+// the products and its lanes take consecutive ones (lane l: l, l + 64, ...): one binary
+// search in the prefix per lane, then a forward step over segment boundaries, four
+// loads in flight; the 64 loads of an instruction are consecutive entries of one or two
+// B rows, so they coalesce.  Ends with a barrier.
+// LDS: s_pref[kWG + 1], s_start[kWG], s_aval[kWG], s_tmp[kWGWaves].
+template <bool VALS, typename F>
+__device__ __forceinline__ void walk_products(const SgOperands& O, int32_t st, int32_t len, float av,
+                                              int32_t* s_pref, int32_t* s_start, float* s_aval, int32_t* s_tmp,
+                                              F&& f) {
+  const int tid = threadIdx.x;
+  int32_t excl;
+  const int32_t tot = block_scan(len, &excl, s_tmp);
+  s_pref[tid] = excl;
+  s_start[tid] = st;
+  if constexpr (VALS) s_aval[tid] = av;
+  if (tid == 0) s_pref[kWG] = tot;
+  __syncthreads();
+  // each wave takes a contiguous share of the products; its lanes take consecutive
+  // products (lane l: l, l + 64, ...), so the B loads of a wave are contiguous
+  constexpr int kWaves = kWG / 64;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int32_t per_wave = (((tot + kWaves - 1) / kWaves) + 63) & ~63;
+  const int32_t w0 = wv * per_wave;
+  const int32_t w1 = min(w0 + per_wave, tot);
+  int32_t t = w0 + lane;
+  if (t < w1) {
+    int pi = 0;
+#pragma unroll
+    for (int step = kWG / 2; step > 0; step >>= 1)
+      if (s_pref[pi + step] <= t) pi += step;
+    int32_t next = s_pref[pi + 1];
+    int32_t base = s_start[pi] - s_pref[pi];
+    float a = VALS ? s_aval[pi] : 0.0f;
+    while (t < w1) {
+      int32_t qs[4];
+      float as[4];
+      int cnt = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        qs[u] = 0;
+        as[u] = 0.0f;
+        if (t < w1) {
+          while (t >= next) {  // forward to the segment holding t
+            ++pi;
+            next = s_pref[pi + 1];
+            base = s_start[pi] - s_pref[pi];
+            if constexpr (VALS) a = s_aval[pi];
+          }
+          qs[u] = base + t;
+          as[u] = a;
+          t += 64;
+          cnt = u + 1;
+        }
+      }
+      int32_t col[4];
+      float prod[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int32_t qq = qs[u < cnt ? u : 0];
+        col[u] = O.colB[qq];
+        prod[u] = VALS ? as[u] * O.valB[qq] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (u < cnt) f(col[u], prod[u]);
+    }
+  }
+  __syncthreads();
+}
+
 // Visit the products of A entries [a0, a1) with the whole workgroup: f(col, a * b);
 // with WIN, only the products whose column lies in [c0, c1), each B row cut to that
 // range by the split table when given (bsplit[k * stride + win] = first position at
-// column >= win * window) or by binary search.  The workgroup takes kWG A entries at a
-// time; their (cut) B-row lengths are prefix-summed, each wave takes one contiguous
-// share (1/kWGWaves) of the products and its lanes take consecutive ones
-// (lane l: l, l + 64, ...): one binary search in the prefix per lane, then a forward
-// step over segment boundaries, four loads in flight; the 64 loads of an instruction
-// are consecutive entries of one or two B rows, so they coalesce.
-// LDS: s_pref[kWG + 1], s_start[kWG], s_aval[kWG], s_tmp[kWGWaves].
+// column >= win * window) or by binary search.  kWG A entries at a time.
 template <bool VALS, bool WIN, typename F>
 __device__ __forceinline__ void block_products(const SgOperands& O, int32_t a0, int32_t a1, int32_t* s_pref,
                                                int32_t* s_start, float* s_aval, int32_t* s_tmp, F&& f,
@@ -221,64 +288,7 @@ __device__ __forceinline__ void block_products(const SgOperands& O, int32_t a0, 
       len = en - st;
       if constexpr (VALS) av = O.valA[c + tid];
     }
-    int32_t excl;
-    const int32_t tot = block_scan(len, &excl, s_tmp);
-    s_pref[tid] = excl;
-    s_start[tid] = st;
-    if constexpr (VALS) s_aval[tid] = av;
-    if (tid == 0) s_pref[kWG] = tot;
-    __syncthreads();
-    // each wave takes a contiguous share of the products; its lanes take consecutive
-    // products (lane l: l, l + 64, ...), so the B loads of a wave are contiguous
-    constexpr int kWaves = kWG / 64;
-    const int lane = tid & 63, wv = tid >> 6;
-    const int32_t per_wave = (((tot + kWaves - 1) / kWaves) + 63) & ~63;
-    const int32_t w0 = wv * per_wave;
-    const int32_t w1 = min(w0 + per_wave, tot);
-    int32_t t = w0 + lane;
-    if (t < w1) {
-      int pi = 0;
-#pragma unroll
-      for (int step = kWG / 2; step > 0; step >>= 1)
-        if (s_pref[pi + step] <= t) pi += step;
-      int32_t next = s_pref[pi + 1];
-      int32_t base = s_start[pi] - s_pref[pi];
-      float a = VALS ? s_aval[pi] : 0.0f;
-      while (t < w1) {
-        int32_t qs[4];
-        float as[4];
-        int cnt = 0;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          qs[u] = 0;
-          as[u] = 0.0f;
-          if (t < w1) {
-            while (t >= next) {  // forward to the segment holding t
-              ++pi;
-              next = s_pref[pi + 1];
-              base = s_start[pi] - s_pref[pi];
-              if constexpr (VALS) a = s_aval[pi];
-            }
-            qs[u] = base + t;
-            as[u] = a;
-            t += 64;
-            cnt = u + 1;
-          }
-        }
-        int32_t col[4];
-        float prod[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int32_t qq = qs[u < cnt ? u : 0];
-          col[u] = O.colB[qq];
-          prod[u] = VALS ? as[u] * O.valB[qq] : 0.0f;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (u < cnt) f(col[u], prod[u]);
-      }
-    }
-    __syncthreads();
+    walk_products<VALS>(O, st, len, av, s_pref, s_start, s_aval, s_tmp, f);
   }
 }
 
@@ -618,6 +628,11 @@ struct SgItem {
   int32_t row, win, out, cnt;
 };
 
+// A long row's non-empty windows: items[first, first + count).
+struct SgRow {
+  int32_t row, first, count, pad;
+};
+
 // bsplit[k * (n_win + 1) + w]: first position of B row k at column >= w * 2^win_log2
 // (w = n_win: the row's end).
 __global__ void __launch_bounds__(kBlock) bsplit_kernel(const int32_t* rowptrB, const int32_t* colB, int64_t K,
@@ -631,6 +646,37 @@ __global__ void __launch_bounds__(kBlock) bsplit_kernel(const int32_t* rowptrB, 
   }
 }
 
+// Write a window's entries in column order at [out, out + cnt) from its LDS sums and
+// bitmap (ww words), clearing both as they are read.  Ends with a barrier.
+__device__ __forceinline__ void window_emit(const SgOut& Co, float* acc, uint32_t* bits, int ww, int32_t c0,
+                                            int32_t out, int32_t cnt, int32_t* s_tmp) {
+  const int tid = threadIdx.x;
+  const int32_t end = out + cnt;
+  for (int w0 = 0; w0 < ww; w0 += kWG) {
+    const int wi = w0 + tid;
+    uint32_t word = wi < ww ? bits[wi] : 0u;
+    int32_t excl;
+    const int32_t tot = block_scan(__popc(word), &excl, s_tmp);
+    int32_t pos = out + excl;
+    while (word) {
+      const int b = __ffs(word) - 1;
+      word &= word - 1;
+      const int x = wi * 32 + b;
+      if (pos < end) {
+        Co.colC[pos] = c0 + x;
+        Co.valC[pos] = acc[x];
+      }
+      acc[x] = 0.0f;
+      ++pos;
+    }
+    if (wi < ww) bits[wi] = 0u;
+    out += tot;
+  }
+  __syncthreads();
+}
+
+// Long rows without a split table: one (row, window) item per workgroup at a time, each
+// B row cut to the window by binary search.
 __global__ void __launch_bounds__(kWG) num_window_kernel(SgOperands O, SgOut Co, const SgItem* items,
                                                          int64_t n_items, int win_log2, const int32_t* bsplit,
                                                          int n_win) {
@@ -658,29 +704,87 @@ __global__ void __launch_bounds__(kWG) num_window_kernel(SgOperands O, SgOut Co,
                                  atomicAdd(acc + x, prod);
                                },
                                c0, c1, bsplit, (int64_t)n_win + 1, item.win);
-    int32_t out = item.out;
-    const int32_t end = item.out + item.cnt;
-    for (int w0 = 0; w0 < ww; w0 += kWG) {
-      const int wi = w0 + tid;
-      uint32_t word = wi < ww ? bits[wi] : 0u;
-      int32_t excl;
-      const int32_t tot = block_scan(__popc(word), &excl, s_tmp);
-      int32_t pos = out + excl;
-      while (word) {
-        const int b = __ffs(word) - 1;
-        word &= word - 1;
-        const int x = wi * 32 + b;
-        if (pos < end) {
-          Co.colC[pos] = c0 + x;
-          Co.valC[pos] = acc[x];
-        }
-        acc[x] = 0.0f;
-        ++pos;
+    window_emit(Co, acc, bits, ww, c0, item.out, item.cnt, s_tmp);
+  }
+}
+
+// Long rows with a split table: one row per workgroup at a time, its non-empty windows
+// (items[first, first + count), in column order) one after the other.  A row of at
+// most kWG A entries keeps each entry's B row and value in a register across its
+// windows and prefetches the next window's split-table bounds while the current window
+// accumulates, so a window costs its products and its compaction, not a chain of
+// dependent loads; longer rows take each window through block_products.
+__global__ void __launch_bounds__(kWG) num_rowwin_kernel(SgOperands O, SgOut Co, const SgItem* items,
+                                                         const SgRow* rows, int64_t n_rows, int win_log2,
+                                                         const int32_t* bsplit, int n_win) {
+  extern __shared__ int32_t s_dyn[];
+  const int W = 1 << win_log2;
+  const int ww = W >> 5;
+  float* acc = reinterpret_cast<float*>(s_dyn);
+  uint32_t* bits = reinterpret_cast<uint32_t*>(acc + W);
+  int32_t* s_pref = reinterpret_cast<int32_t*>(bits + ww);
+  int32_t* s_start = s_pref + kWG + 1;
+  float* s_aval = reinterpret_cast<float*>(s_start + kWG);
+  int32_t* s_tmp = reinterpret_cast<int32_t*>(s_aval + kWG);
+  const int tid = threadIdx.x;
+  const int64_t stride = (int64_t)n_win + 1;
+  for (int j = tid; j < W; j += kWG) acc[j] = 0.0f;
+  for (int j = tid; j < ww; j += kWG) bits[j] = 0u;
+  __syncthreads();
+  for (int64_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
+    const SgRow R = rows[r];
+    const int32_t a0 = O.rowptrA[R.row], a1 = O.rowptrA[R.row + 1];
+    if (a1 - a0 <= kWG) {
+      const bool mine = tid < a1 - a0;
+      int32_t k = 0;
+      float av = 0.0f;
+      if (mine) {
+        k = O.colA[a0 + tid];
+        av = O.valA[a0 + tid];
       }
-      if (wi < ww) bits[wi] = 0u;
-      out += tot;
+      const int32_t* sp = bsplit + (int64_t)k * stride;
+      SgItem item = items[R.first];
+      int32_t st = 0, en = 0;
+      if (mine) {
+        st = sp[item.win];
+        en = sp[item.win + 1];
+      }
+      for (int32_t j = 0; j < R.count; ++j) {
+        SgItem nxt = item;
+        int32_t nst = 0, nen = 0;
+        if (j + 1 < R.count) {
+          nxt = items[R.first + j + 1];
+          if (mine) {
+            nst = sp[nxt.win];
+            nen = sp[nxt.win + 1];
+          }
+        }
+        const int32_t c0 = item.win << win_log2;
+        walk_products<true>(O, st, en - st, av, s_pref, s_start, s_aval, s_tmp, [&](int32_t col, float prod) {
+          const int32_t x = col - c0;
+          atomicOr(bits + (x >> 5), 1u << (x & 31));
+          atomicAdd(acc + x, prod);
+        });
+        window_emit(Co, acc, bits, ww, c0, item.out, item.cnt, s_tmp);
+        item = nxt;
+        st = nst;
+        en = nen;
+      }
+    } else {
+      for (int32_t j = 0; j < R.count; ++j) {
+        const SgItem item = items[R.first + j];
+        const int32_t c0 = item.win << win_log2;
+        const int32_t c1 = (int32_t)min((int64_t)c0 + W, O.N);
+        block_products<true, true>(O, a0, a1, s_pref, s_start, s_aval, s_tmp,
+                                   [&](int32_t col, float prod) {
+                                     const int32_t x = col - c0;
+                                     atomicOr(bits + (x >> 5), 1u << (x & 31));
+                                     atomicAdd(acc + x, prod);
+                                   },
+                                   c0, c1, bsplit, stride, item.win);
+        window_emit(Co, acc, bits, ww, c0, item.out, item.cnt, s_tmp);
+      }
     }
-    __syncthreads();
   }
 }
 
@@ -775,12 +879,15 @@ struct spgemm_s {
   size_t lds_window = 0;        // the window kernel's dynamic LDS bytes
   spmm::SgItem* items = nullptr;  // device: (row, window, offset, count) of the long rows
   int64_t n_items = 0;
+  spmm::SgRow* wrows = nullptr;   // device, with a split table: each long row's run of items
+  int64_t n_wrows = 0;
   int32_t* bsplit = nullptr;      // device: B rows' window split positions (nullable)
   int n_win = 0;
   ~spgemm_s() {
     if (rowptrC) (void)hipFree(rowptrC);
     if (rows) (void)hipFree(rows);
     if (items) (void)hipFree(items);
+    if (wrows) (void)hipFree(wrows);
     if (bsplit) (void)hipFree(bsplit);
     if (slot_vals) (void)hipFree(slot_vals);
     if (slot_bits) (void)hipFree(slot_bits);
@@ -1057,15 +1164,6 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
           }
           if (out != rp[(size_t)i + 1]) return spmm::set_error(SPMM_ERR_HIP, "internal: window counts of row %d", i);
         }
-        std::stable_sort(items.begin(), items.end(),
-                         [](const spmm::SgItem& x, const spmm::SgItem& y) { return x.cnt > y.cnt; });
-        h->n_items = (int64_t)items.size();
-        if (dmalloc(&h->items, h->n_items) != hipSuccess)
-          return spmm::set_error(SPMM_ERR_ALLOC, "device allocation of the window items failed");
-        if (h->n_items)
-          SG_TRY(hipMemcpyAsync(h->items, items.data(), sizeof(spmm::SgItem) * items.size(), hipMemcpyHostToDevice, s));
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(spmm::num_window_kernel),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_window);
         h->n_win = n_win;
         const int64_t split_entries = h->K * ((int64_t)n_win + 1);
         if (split_entries <= spmm::kSplitBudget && dmalloc(&h->bsplit, split_entries) == hipSuccess) {
@@ -1073,7 +1171,37 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
                              dim3(spmm::kBlock), 0, s, h->B.rowptr, h->B.colind, h->K, n_win, h->win_log2,
                              h->bsplit);
           SG_TRY(hipGetLastError());
+          // row-ordered items (each row's windows in column order), rows largest first
+          std::vector<spmm::SgRow> wr;
+          for (size_t a = 0; a < items.size();) {
+            size_t b = a;
+            while (b < items.size() && items[b].row == items[a].row) ++b;
+            wr.push_back(spmm::SgRow{items[a].row, (int32_t)a, (int32_t)(b - a), 0});
+            a = b;
+          }
+          std::stable_sort(wr.begin(), wr.end(), [&](const spmm::SgRow& x, const spmm::SgRow& y) {
+            return rp[(size_t)x.row + 1] - rp[(size_t)x.row] > rp[(size_t)y.row + 1] - rp[(size_t)y.row];
+          });
+          h->n_wrows = (int64_t)wr.size();
+          if (dmalloc(&h->wrows, h->n_wrows) != hipSuccess)
+            return spmm::set_error(SPMM_ERR_ALLOC, "device allocation of the window rows failed");
+          if (h->n_wrows)
+            SG_TRY(hipMemcpyAsync(h->wrows, wr.data(), sizeof(spmm::SgRow) * wr.size(), hipMemcpyHostToDevice, s));
+          (void)hipFuncSetAttribute(reinterpret_cast<const void*>(spmm::num_rowwin_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_window);
+          SG_TRY(hipStreamSynchronize(s));  // wr is read before it goes out of scope
+        } else {
+          // (row, window) items largest first
+          std::stable_sort(items.begin(), items.end(),
+                           [](const spmm::SgItem& x, const spmm::SgItem& y) { return x.cnt > y.cnt; });
+          (void)hipFuncSetAttribute(reinterpret_cast<const void*>(spmm::num_window_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_window);
         }
+        h->n_items = (int64_t)items.size();
+        if (dmalloc(&h->items, h->n_items) != hipSuccess)
+          return spmm::set_error(SPMM_ERR_ALLOC, "device allocation of the window items failed");
+        if (h->n_items)
+          SG_TRY(hipMemcpyAsync(h->items, items.data(), sizeof(spmm::SgItem) * items.size(), hipMemcpyHostToDevice, s));
       } else if (h->cls_cnt[kLongClass]) {
         const spmm_status st = ensure_slots(h, slot_count(h, h->cls_cnt[kLongClass], cus), s);
         if (st != SPMM_OK) return st;
@@ -1152,9 +1280,15 @@ spmm_status spgemm_compute(spgemm_t plan, int32_t* colindC, float* valuesC, void
     if (plan->n_items) {
       int cus = 0;
       SG_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-      const int64_t grid = std::min<int64_t>(plan->n_items, (int64_t)cus * 2);
-      hipLaunchKernelGGL(spmm::num_window_kernel, dim3((unsigned)grid), dim3(spmm::kWG), plan->lds_window, s, O, Co,
-                         plan->items, plan->n_items, plan->win_log2, plan->bsplit, plan->n_win);
+      if (plan->wrows) {
+        const int64_t grid = std::min<int64_t>(plan->n_wrows, (int64_t)cus * 2);
+        hipLaunchKernelGGL(spmm::num_rowwin_kernel, dim3((unsigned)grid), dim3(spmm::kWG), plan->lds_window, s, O,
+                           Co, plan->items, plan->wrows, plan->n_wrows, plan->win_log2, plan->bsplit, plan->n_win);
+      } else {
+        const int64_t grid = std::min<int64_t>(plan->n_items, (int64_t)cus * 2);
+        hipLaunchKernelGGL(spmm::num_window_kernel, dim3((unsigned)grid), dim3(spmm::kWG), plan->lds_window, s, O,
+                           Co, plan->items, plan->n_items, plan->win_log2, plan->bsplit, plan->n_win);
+      }
       SG_TRY(hipGetLastError());
     }
   } else if (cnt[kLongClass]) {
