@@ -249,3 +249,52 @@ def test_mixed_staged_and_plain_k_tiles():
         for t in (on, off):
             ops.spmm_tile_set_variant(t, N, torch.float32, kind)
         assert torch.equal(G.fwd(on, dB, k_offset=2), G.fwd(off, dB, k_offset=2)), kind
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("N", [1, 2, 7])
+def test_staging_narrow_rows(dtype, N):
+    """Rows of 1, 2 and 7 elements: the staging copy's 4- and 2-byte paths (integer data: exact)."""
+    G.note("hot narrow N=%d %s" % (N, dtype))
+    tiles = _skewed_tiles(seed=17, kind="int4")
+    rng = _rng(17 + N)
+    Bs = [synth.dense(t.cols, N, rng, "int4") for t in tiles]
+    tdt = torch.float32 if dtype == "f32" else torch.bfloat16
+    dB = [G.dense_dev(b, tdt) for b in Bs]
+    on = G.make_tile(tiles, hot_rows=200, long_row=32, segment=8)
+    off = G.make_tile(tiles, hot_rows=-1, long_row=32, segment=8)
+    for kind in ("stream", "rowsplit"):
+        for t in (on, off):
+            ops.spmm_tile_set_variant(t, N, tdt, kind)
+        a, b = G.fwd(on, dB, k_offset=3), G.fwd(off, dB, k_offset=3)
+        assert torch.equal(a, b), kind
+    ref, _ = G.oracle_fwd(tiles, Bs, k_offset=3)
+    got = G.host_f32(G.fwd(on, dB, k_offset=3))
+    if dtype == "f32":
+        assert np.array_equal(got.astype(np.float64), ref)
+    else:
+        assert np.array_equal(got, G.bf16_as_f32(ref.astype(np.float32)))
+
+
+def test_staging_sixteen_k_tiles_and_empty_columns():
+    """The most k-tiles a handle takes (16), one of them without columns (its B has no rows)."""
+    G.note("hot 16 k-tiles")
+    vrng = _rng(118)
+    tiles = [synth.CSR(t.rows, t.cols, t.rowptr, t.colind, synth.draw_values(vrng, t.nnz, "int4"))
+             for t in synth.rmat_row_block(12, 16, 16, 0, seed=18).tiles]
+    t5 = tiles[5]
+    tiles[5] = synth.CSR(t5.rows, 0, np.zeros(t5.rows + 1, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    rng = _rng(18)
+    N = 48
+    Bs = [synth.dense(t.cols, N, rng, "int4") for t in tiles]
+    dB = [G.dense_dev(b) for b in Bs]
+    on = G.make_tile(tiles, hot_rows=32, long_row=16, segment=4)
+    off = G.make_tile(tiles, hot_rows=-1, long_row=16, segment=4)
+    assert on.stats()["hot_rows"] == sum(_top_cover(t, 32)[0] for t in tiles if t.nnz)
+    for kind in ("stream", "rowsplit"):
+        for t in (on, off):
+            ops.spmm_tile_set_variant(t, N, torch.float32, kind)
+        for k_offset in (0, 7, 15):
+            assert torch.equal(G.fwd(on, dB, k_offset=k_offset), G.fwd(off, dB, k_offset=k_offset)), (kind, k_offset)
+    ref, _ = G.oracle_fwd(tiles, Bs, k_offset=7)
+    assert np.array_equal(G.host_f32(G.fwd(on, dB, k_offset=7)).astype(np.float64), ref)
