@@ -636,6 +636,20 @@ class SpgemmAA(Workload):
         from paper_2311_18141_amd import ops
         ops.spgemm_compute(self.plan, self.ci, self.va)
 
+    def extra(self, kernel_ms):
+        """The local SpGEMM roofline of Section 4 (Gu et al.): arithmetic intensity
+        cf / ((3 + 2 cf) b) with cf the multiply-adds per output entry and b = 8 bytes per
+        entry (int32 index, FP32 value), i.e. (3 + 2 cf) b bytes per output entry, each
+        product reading its B entry; its time at the HBM peak against the measured one."""
+        nnz_c = max(self.plan.nnz_c, 1)
+        cf = self.plan.products / nnz_c
+        b = 8.0
+        bytes_step = nnz_c * (3.0 + 2.0 * cf) * b
+        t_ms = bytes_step / (HBM_PEAK_GBS * 1e9) * 1e3
+        return {"local_spgemm_roofline": {"cf": round(cf, 3), "ai_products_per_byte": round(cf / ((3 + 2 * cf) * b), 5),
+                                          "bytes_per_step": bytes_step, "time_at_peak_ms": round(t_ms, 3),
+                                          "frac": round(t_ms / kernel_ms, 4)}}
+
     def cpu_sample(self):
         import oracle
         A = self.A
