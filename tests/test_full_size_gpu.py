@@ -32,6 +32,11 @@ def _bench_tile(workload, tiles, N, dtypes=(torch.float32,), transpose=False, de
     for d in dtypes:
         kind, lanes, vec = pin["variant"]
         ops.spmm_tile_set_variant(tile, N, d, kind, lanes, vec)
+        if "bwd_variant" in pin:                      # the backward's dB pass
+            kind, lanes, vec = pin["bwd_variant"]
+            ops.spmm_tile_set_bwd_variant(tile, N, d, kind, lanes, vec)
+    if "sddmm" in pin:
+        ops.spmm_tile_set_sddmm_variant(tile, N, pin["sddmm"][0], pin["sddmm"][1])
     return tile
 
 
@@ -130,6 +135,35 @@ def test_powerlaw2m_fwd_bwd_sampled(powerlaw2m):
     rB, SB = oracle.spmm_t(A.rowptr, A.colind, A.values, A.cols, dC, out_rows=cols.astype(np.int64))
     gotB = dB[torch.from_numpy(cols).to(dB.device)].cpu().numpy()
     G.assert_fp32_close(gotB, rB, SB, cnt[cols], what="dB")
+
+
+def test_powerlaw2m_fwd_bwd_bf16_sampled(powerlaw2m):
+    """The BF16 forward + backward workload (B, C, dC, dB in BF16; dA FP32) at full size with its
+    pinned shapes: C and dB within the BF16 bound, dA within the FP32 bound, on bf16(B), bf16(dC)."""
+    A, B, dC, _, _ = powerlaw2m
+    G.note("full powerlaw 2M fwd+bwd bf16 sampled")
+    tile = _bench_tile("powerlaw2m_n128_fwdbwd_bf16", [A], 128, dtypes=(torch.bfloat16,), transpose=True)
+    Bd, dCd = G.dense_dev(B, torch.bfloat16), G.dense_dev(dC, torch.bfloat16)
+    C = G.fwd(tile, [Bd])
+    dA, dB = ops.spmm_bwd(tile, dCd, Bd)
+    torch.cuda.synchronize()
+    Bt, dCt = G.bf16_as_f32(B), G.bf16_as_f32(dC)
+    rng = _rng(33)
+    lens = A.row_lengths()
+    rows = _sample_rows(lens, rng)
+    ref, S = G.oracle_fwd([A], [Bt], rows=rows)
+    G.assert_bf16_close(C[torch.from_numpy(rows).to(C.device)].float().cpu().numpy(), ref, S, what="C bf16")
+    ents = np.unique(np.concatenate([rng.choice(A.nnz, 1000, replace=False),
+                                     np.arange(A.rowptr[np.argmax(lens)], A.rowptr[np.argmax(lens)] + 50)]))
+    rA, SA = oracle.sddmm(A.rowptr, A.colind, dCt, Bt, entries=ents.astype(np.int64))
+    st = compare.fp32_stats(dA[torch.from_numpy(ents).to(dA.device)].cpu().numpy(), rA, SA,
+                            n_terms=np.full(ents.size, 128))
+    assert compare.fp32_ok(st), st
+    cnt = np.bincount(A.colind, minlength=A.cols)
+    cols = np.unique(np.concatenate([rng.choice(A.cols, 1000, replace=False), np.argsort(cnt)[-20:]]))
+    rB, SB = oracle.spmm_t(A.rowptr, A.colind, A.values, A.cols, dCt, out_rows=cols.astype(np.int64))
+    G.assert_bf16_close(dB[torch.from_numpy(cols).to(dB.device)].float().cpu().numpy(), rB, SB, what="dB bf16")
+    del tile
 
 
 def test_powerlaw2m_finite_differences(powerlaw2m):
