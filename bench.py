@@ -406,10 +406,12 @@ class Batched(Workload):
         _log("%s: autotuned %d tiles in %.1f s" % (self.name, self.count, time.time() - t0))
         self.batch = ops.spmm_batch_create(self.handles, self.Ns)
         self.ws = self.batch.workspace()
-        # The persistent hand-out (claim counters), timed for comparison.
+        # The persistent hand-out (claim counters), timed for comparison; both hand-outs also
+        # as one captured HIP graph replayed.
         pb = ops.spmm_batch_create(self.handles, self.Ns, persistent=True)
         pws = pb.workspace()
         self.persistent_ms = self._time(lambda: ops.spmm_batched(pb, self.B, self.C, workspace=pws), reps=5)
+        self.graph_ms = {"flat": self._graph_ms(self.batch, self.ws), "persistent": self._graph_ms(pb, pws)}
         del pb, pws
         self.tuned_loop_ms = self._time(self._loop, reps=5)
         # each non-zero gathers its B row (4 N bytes) from the tile's B (cols x 4 N bytes)
@@ -430,12 +432,30 @@ class Batched(Workload):
                            per_tile_loop_autotuned={"ms": round(self.tuned_loop_ms, 4),
                                                     "gflops": round(self.flops / (self.tuned_loop_ms * 1e-3) / 1e9, 1)},
                            persistent={"ms": round(self.persistent_ms, 4),
-                                       "gflops": round(self.flops / (self.persistent_ms * 1e-3) / 1e9, 1)})
+                                       "gflops": round(self.flops / (self.persistent_ms * 1e-3) / 1e9, 1)},
+                           graph_replay={k: {"ms": round(v, 4), "gflops": round(self.flops / (v * 1e-3) / 1e9, 1)}
+                                         for k, v in self.graph_ms.items()})
 
     def _loop(self):
         from paper_2311_18141_amd import ops
         for h, B, C in zip(self.handles, self.B, self.C):
             ops.spmm_fwd(h, [B], C=C)
+
+    def _graph_ms(self, batch, ws, reps=5):
+        """Mean time of a replay of one captured spmm_batched call."""
+        import torch
+        from paper_2311_18141_amd import ops
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):  # operand arrays are built (and cached) outside the capture
+            ops.spmm_batched(batch, self.B, self.C, workspace=ws)
+        torch.cuda.current_stream().wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            ops.spmm_batched(batch, self.B, self.C, workspace=ws)
+        ms = self._time(g.replay, reps)
+        del g
+        return ms
 
     def extra(self, kernel_ms):
         return {"cache_gather": gather_ceiling_report(self.gather_items, kernel_ms)}
