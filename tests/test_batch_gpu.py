@@ -101,7 +101,7 @@ def test_batch_graph_replay_deterministic(persistent):
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         ops.spmm_batched(batch, Bs, Cs, workspace=ws)
-    for r in range(5):
+    for r in range(10):
         for c in Cs:
             c.fill_(float("nan"))
         _ = (Bs[0] * 3).sum()
