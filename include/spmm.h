@@ -241,8 +241,10 @@ spmm_status spmm_bwd(spmm_tile_t A, const void* dC, int64_t lddc, const void* B,
  * ordered tile by tile (largest first) and column window by column window.
  * `flags`: 0 = one wave per item, handed out by the hardware dispatcher in list
  * order; SPMM_BATCH_PERSISTENT = resident workgroups (#CU x occupancy) whose waves
- * claim 8 items at a time from a device counter per class (a reset kernel runs
- * first).  Both give identical results.  Every tile must be a single-tile handle
+ * claim one item at a time with a fetch-and-add on device counters (each class's
+ * list cut into one contiguous slice per XCD with its own counter; a wave drains its
+ * XCD's slice, then the others; a reset kernel runs first).  Both give identical
+ * results.  Every tile must be a single-tile handle
  * (num_k = 1) on the current device, and must outlive the batch.  The batch
  * allocates its own device memory (work list; claim counters when persistent).
  * Errors: INVALID_ARG, UNSUPPORTED (num_k > 1, work list too long), ALLOC, HIP.

@@ -1106,7 +1106,7 @@ struct spmm_batch_s {
   int64_t n_items = 0;
   spmm::BatchItem* d_fix = nullptr;
   int64_t n_fix = 0;
-  unsigned* d_counter = nullptr;  // persistent mode: one claim counter per item class
+  unsigned* d_counter = nullptr;  // persistent mode: kClaimSlices claim counters per item class
   bool persistent = false;
   size_t ws_bytes = 0;
   int64_t class_off[spmm::kBatchClasses] = {};
@@ -1306,14 +1306,14 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
     b->ws_bytes = sizeof(float) * (size_t)part;
     if (dalloc(&b->d_tiles, count) != hipSuccess || dalloc(&b->d_items, b->n_items) != hipSuccess ||
         dalloc(&b->d_fix, b->n_fix) != hipSuccess ||
-        (b->persistent && dalloc(&b->d_counter, spmm::kBatchClasses) != hipSuccess))
+        (b->persistent && dalloc(&b->d_counter, spmm::kBatchCounters) != hipSuccess))
       return fail(SPMM_ERR_ALLOC, "device allocation of the batch failed");
     HIP_TRY(hipMemcpyAsync(b->d_tiles, bt.data(), sizeof(spmm::BatchTileDev) * bt.size(), hipMemcpyHostToDevice, s));
     if (b->n_items)
       HIP_TRY(hipMemcpyAsync(b->d_items, list.data(), sizeof(spmm::BatchItem) * list.size(), hipMemcpyHostToDevice, s));
     if (b->n_fix)
       HIP_TRY(hipMemcpyAsync(b->d_fix, fix.data(), sizeof(spmm::BatchItem) * fix.size(), hipMemcpyHostToDevice, s));
-    if (b->persistent) HIP_TRY(hipMemsetAsync(b->d_counter, 0, sizeof(unsigned) * spmm::kBatchClasses, s));
+    if (b->persistent) HIP_TRY(hipMemsetAsync(b->d_counter, 0, sizeof(unsigned) * spmm::kBatchCounters, s));
     HIP_TRY(hipStreamSynchronize(s));
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -1322,6 +1322,8 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
     for (int c = 0; c < spmm::kBatchClasses; ++c) {
       const int64_t waves = (int64_t)(spmm::kBlock / 64);
       if (b->persistent) {
+        if (b->class_cnt[c] >= ((int64_t)1 << 31))
+          return fail(SPMM_ERR_UNSUPPORTED, "work list too long for 32-bit claim counters");
         // resident workgroups, at most one wave per claim chunk: small classes launch small grids
         const int64_t full = (int64_t)cus * std::max(1, occ[c]);
         const int64_t need = (b->class_cnt[c] + waves * spmm::kClaimChunk - 1) / (waves * spmm::kClaimChunk);

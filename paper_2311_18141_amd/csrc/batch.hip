@@ -6,12 +6,18 @@
 // one slice of one tile's B in the caches at a time.
 //
 // Two ways to hand items to waves:
-//  * flat (default): one wave per item, in list order; the hardware dispatcher
-//    hands out workgroups as CUs free up, which is the dynamic load balancing.
+//  * flat (default): one wave per item; the hardware dispatcher hands out
+//    workgroups as CUs free up, which is the dynamic load balancing.
 //  * persistent: #CU x occupancy resident workgroups; each wave claims kClaimChunk
-//    consecutive items with one fetch-and-add on the class's device counter (the
-//    single-GPU form of claiming work with a remote fetch-and-add) until the list
-//    is drained.
+//    consecutive items with one fetch-and-add on a device counter (the single-GPU
+//    form of claiming work with a remote fetch-and-add) until the list is drained.
+//    The list is cut into one contiguous slice per XCD, each with its own counter:
+//    a wave claims from its XCD's slice, then from the others in turn, and asks for
+//    its next chunk before it works through the current one.  On the 512-tile
+//    uneven batch, contiguous per-XCD slices ran 1.26x faster than chunks dealt to
+//    the counters in turn, and one item per claim 1.34x faster than eight.
+// Workgroups are dealt to the XCDs round-robin, so in the flat mode every XCD takes
+// every eighth item and all of them work on the same few tiles at any time.
 // Items write disjoint output rows (split rows: disjoint partial rows) and every
 // row is summed in CSR order by one wave, so the result does not depend on which
 // wave runs which item; split rows are finished by a second, fix-up launch.
@@ -242,6 +248,13 @@ __device__ __forceinline__ void run_item(const BatchParams& P, int64_t it, int32
   }
 }
 
+// One claim of kClaimChunk items from slice s (lane 0's fetch-and-add, broadcast).
+__device__ __forceinline__ unsigned claim(unsigned* counter, int s, int lane) {
+  unsigned c = 0;
+  if (lane == 0) c = atomicAdd(counter + (int64_t)s * kCounterStride, (unsigned)kClaimChunk);
+  return (unsigned)__builtin_amdgcn_readlane((int)c, 0);
+}
+
 // One kernel per item class and hand-out mode.
 template <typename E, bool ACC, int CLS, bool PERSIST>
 __global__ void __launch_bounds__(kBlock) batch_class(BatchParams P) {
@@ -251,12 +264,24 @@ __global__ void __launch_bounds__(kBlock) batch_class(BatchParams P) {
   int32_t* s_pref = s_mem + w * 129;
   int32_t* s_beg = s_pref + 65;
   if constexpr (PERSIST) {
+    // slice s = items [n s / S, n (s + 1) / S); start on this XCD's slice, then visit
+    // the others in turn; a wave leaves after finding every slice drained
+    int s = (int)(blockIdx.x % kClaimSlices);
+    int visited = 1;
+    unsigned got = claim(P.counter, s, lane);
     for (;;) {
-      unsigned claimed = 0;
-      if (lane == 0) claimed = atomicAdd(P.counter, (unsigned)kClaimChunk);
-      const int64_t base = (unsigned)__builtin_amdgcn_readlane((int)claimed, 0);
-      if (base >= P.n_items) break;  // every wave leaves once the list is drained
-      const int64_t end = base + kClaimChunk < P.n_items ? base + kClaimChunk : P.n_items;
+      const int64_t lo = P.n_items * s / kClaimSlices;
+      const int64_t hi = P.n_items * (s + 1) / kClaimSlices;
+      const int64_t base = lo + got;
+      if (base >= hi) {
+        if (visited == kClaimSlices) break;
+        ++visited;
+        s = (s + 1) % kClaimSlices;
+        got = claim(P.counter, s, lane);
+        continue;
+      }
+      const int64_t end = base + kClaimChunk < hi ? base + kClaimChunk : hi;
+      got = claim(P.counter, s, lane);  // the next chunk, in flight during this one
       for (int64_t it = base; it < end; ++it) run_item<E, ACC, CLS>(P, it, s_pref, s_beg);
     }
   } else {
@@ -302,8 +327,8 @@ __global__ void __launch_bounds__(kBlock) batch_fixup(BatchParams P) {
 
 // Reset the claim counters inside the stream (a kernel, so that a captured graph
 // resets them on every replay).
-__global__ void batch_reset(unsigned* counter, int n) {
-  if ((int)threadIdx.x < n) counter[threadIdx.x] = 0u;
+__global__ void __launch_bounds__(kBlock) batch_reset(unsigned* counter, int n) {
+  for (int i = (int)threadIdx.x; i < n; i += kBlock) counter[i] = 0u;
 }
 
 template <typename E, bool ACC, int CLS>
@@ -320,7 +345,7 @@ hipError_t launch_batch_t(const BatchParams& P0, const int64_t* off, const int64
                           bool persistent, hipStream_t s) {
   hipError_t e = hipSuccess;
   if (persistent) {
-    hipLaunchKernelGGL(batch_reset, dim3(1), dim3(64), 0, s, P0.counter, kBatchClasses);
+    hipLaunchKernelGGL(batch_reset, dim3(1), dim3(kBlock), 0, s, P0.counter, kBatchCounters);
     e = hipGetLastError();
   }
   // units first (their partials feed the fix-up), then the row classes
@@ -331,7 +356,7 @@ hipError_t launch_batch_t(const BatchParams& P0, const int64_t* off, const int64
     BatchParams P = P0;
     P.items = P0.items + off[c];
     P.n_items = cnt[c];
-    P.counter = P0.counter ? P0.counter + c : nullptr;
+    P.counter = P0.counter ? P0.counter + (int64_t)c * kClaimSlices * kCounterStride : nullptr;
     switch (c) {
       case 0: e = launch_class<E, ACC, 0>(P, grid[c], persistent, s); break;
       case 1: e = launch_class<E, ACC, 1>(P, grid[c], persistent, s); break;

@@ -153,20 +153,29 @@ struct BatchParams {
   void* const* C;          // device array: C[t]
   const int64_t* ldc;      // device array
   float* partial;
-  unsigned* counter;       // persistent mode: one claim counter per item class
+  unsigned* counter;       // persistent mode: the class's kClaimSlices claim counters
   int accumulate;
 };
 // Items a persistent wave claims with one fetch-and-add.
-constexpr int kClaimChunk = 8;
+constexpr int kClaimChunk = 1;
+// The chip's XCDs (each with its own L2); workgroups are dealt to them round-robin
+// in workgroup-id order.
+constexpr int kXcds = 8;
+// Persistent mode splits each class's item list into kClaimSlices contiguous slices
+// with a counter each (one per XCD), kCounterStride unsigned apart (one 256-byte
+// line per counter); a batch holds kBatchClasses x kClaimSlices counters.
+constexpr int kClaimSlices = kXcds;
+constexpr int kCounterStride = 64;
 // Item classes: stream V = 1, 2, 4 (0..2); row-split G = 8, 16, 32, 64 with V = 4 (3..6);
 // split-row units with V = 1, 2, 4 (7..9).
 constexpr int kClassRowsplit = 3;
 constexpr int kClassUnit = 7;
 constexpr int kBatchClasses = 10;
+constexpr int kBatchCounters = kBatchClasses * kClaimSlices * kCounterStride;
 // One launch per item class present (off/cnt: the class's slice of the item list;
 // grid: its workgroups), then the fix-up.  persistent = false: one wave per item;
 // true: `grid` resident workgroups claim kClaimChunk items at a time from the
-// class's counter (reset by a kernel first, so graph replays start clean).
+// class's counters (reset by a kernel first, so graph replays start clean).
 hipError_t launch_batch(const BatchParams& P, const int64_t* off, const int64_t* cnt, const int* grid, DT dt,
                         bool persistent, hipStream_t s);
 void batch_blocks_per_cu(DT dt, int* out);
