@@ -154,6 +154,14 @@ typedef struct {
    16 entries full). */
 spmm_status spmm_tile_set_variant(spmm_tile_t tile, int64_t N, spmm_dtype dtype, const spmm_variant* v);
 
+/* Read back the entry for width N and `dtype` of the forward's variant table (bwd = 0)
+   or of the backward's dB-pass table (bwd = 1): the variant set by spmm_tile_set_variant,
+   spmm_tile_set_bwd_variant or an autotuner, or kind SPMM_KERNEL_AUTO when there is
+   none.  With the setters it lets a caller keep autotuned choices (for instance in a
+   file) and apply them to a later handle of the same structure.  Errors: INVALID_ARG. */
+spmm_status spmm_tile_get_variant(spmm_tile_t tile, int64_t N, spmm_dtype dtype, int32_t bwd,
+                                  spmm_variant* out /* host */);
+
 /* Shape of the backward's sampled dense-dense kernel (dA on A's pattern; a gradient
    pass this library adds, not a kernel of the paper) at width N: groups of
    `lanes` lanes (4, 8, 16, 32, 64), each owning `nnz_per_group` consecutive non-zeros

@@ -67,6 +67,7 @@ EXPORTS = {
     "spmm_tile_set_variant": (c_int, [c_vp, c_i64, c_int, c_vp]),
     "spmm_tile_set_sddmm_variant": (c_int, [c_vp, c_i64, c_int, c_int]),
     "spmm_tile_set_bwd_variant": (c_int, [c_vp, c_i64, c_int, c_vp]),
+    "spmm_tile_get_variant": (c_int, [c_vp, c_i64, c_int, c_int, c_vp]),
     "spmm_tile_autotune_bwd": (c_int, [c_vp, c_i64, c_int, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp]),
     "spmm_tile_autotune": (c_int, [c_vp, c_i64, c_int, c_vp, c_vp, c_vp, c_i64, c_int, c_vp, c_vp]),
     "spmm_fwd_workspace_bytes": (c_int, [c_vp, c_i64, c_vp]),

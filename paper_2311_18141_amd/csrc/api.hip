@@ -755,6 +755,20 @@ spmm_status spmm_tile_set_bwd_variant(spmm_tile_t A, int64_t N, spmm_dtype dtype
   return set_variant_in(A->vtT, &A->nvtT, N, dtype, v);
 }
 
+spmm_status spmm_tile_get_variant(spmm_tile_t A, int64_t N, spmm_dtype dtype, int32_t bwd, spmm_variant* out) {
+  if (!A) return fail(SPMM_ERR_INVALID_ARG, "tile is null");
+  if (!out) return fail(SPMM_ERR_INVALID_ARG, "out is null");
+  if (N < 1) return fail(SPMM_ERR_INVALID_ARG, "N=%lld < 1", (long long)N);
+  if (dtype != SPMM_F32 && dtype != SPMM_BF16) return fail(SPMM_ERR_INVALID_ARG, "unknown dtype");
+  if (bwd != 0 && bwd != 1) return fail(SPMM_ERR_INVALID_ARG, "bwd=%d is not 0 or 1", (int)bwd);
+  const spmm_tile_s::VarEntry* vt = bwd ? A->vtT : A->vt;
+  const int n = bwd ? A->nvtT : A->nvt;
+  *out = spmm_variant{SPMM_KERNEL_AUTO, 0, 0};
+  for (int i = 0; i < n; ++i)
+    if (vt[i].N == N && vt[i].dtype == (int)dtype) *out = vt[i].v;
+  return SPMM_OK;
+}
+
 spmm_status spmm_tile_set_sddmm_variant(spmm_tile_t A, int64_t N, int32_t lanes, int32_t nnz_per_group) {
   if (!A) return fail(SPMM_ERR_INVALID_ARG, "tile is null");
   if (N < 1) return fail(SPMM_ERR_INVALID_ARG, "N=%lld < 1", (long long)N);

@@ -159,6 +159,16 @@ def spmm_tile_set_bwd_variant(tile: Tile, N: int, dtype=torch.float32, kind: Opt
     check(lib().spmm_tile_set_bwd_variant(tile.handle, N, _DTYPES[dtype], ctypes.byref(v)))
 
 
+def spmm_tile_get_variant(tile: Tile, N: int, dtype=torch.float32, bwd: bool = False) -> Optional[dict]:
+    """The forward's (or, with bwd, the dB pass's) variant entry for width N; None when unset."""
+    v = SpmmVariant()
+    check(lib().spmm_tile_get_variant(tile.handle, N, _DTYPES[dtype], 1 if bwd else 0, ctypes.byref(v)))
+    if v.kind == KERNELS["auto"]:
+        return None
+    inv = {val: k for k, val in KERNELS.items()}
+    return {"kind": inv[v.kind], "lanes": v.lanes, "vec": v.vec}
+
+
 def spmm_tile_autotune_bwd(tile: Tile, dC: torch.Tensor, dB: Optional[torch.Tensor] = None,
                            stream: Optional[torch.cuda.Stream] = None) -> dict:
     """Time the dB pass's variants on this dC (dB is overwritten); keep the fastest."""

@@ -227,4 +227,6 @@ def test_bwd_variant_argument_errors():
     L = _lib.lib()
     v = _lib.SpmmVariant(_lib.SPMM_KERNEL_ROWSPLIT, 16, 4)
     assert L.spmm_tile_set_bwd_variant(None, 64, 0, ctypes.byref(v)) == 1
+    assert L.spmm_tile_get_variant(None, 64, 0, 0, ctypes.byref(v)) == 1
+    assert L.spmm_tile_get_variant(None, 64, 0, 1, None) == 1
     assert L.spmm_tile_autotune_bwd(None, 64, 0, 0x1000, 64, 0x2000, 64, None, None) == 1
