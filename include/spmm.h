@@ -55,7 +55,8 @@ typedef enum { SPMM_F32 = 0, SPMM_BF16 = 1 } spmm_dtype;
 /* One CSR tile A_ik of a tile row. */
 typedef struct {
   int64_t cols;            /* columns of the tile = rows of its dense operand B_k */
-  int64_t nnz;             /* stored entries; must be < 2^31 */
+  int64_t nnz;             /* stored entries; at most 2^31 - 2^16 (int32 positions, with headroom
+                              for the kernels' strides) */
   const int32_t* rowptr;   /* device, rows+1 entries, rowptr[0] = 0, rowptr[rows] = nnz */
   const int32_t* colind;   /* device, nnz entries, tile-local, strictly increasing per row */
   const float* values;     /* device, nnz entries, FP32; read on every call */
@@ -115,8 +116,8 @@ typedef struct {
  * perm) by a stable sort on column index.  Synchronous.  The library allocates
  * the handle's own device memory here (released by spmm_tile_destroy); the
  * tile arrays stay owned by the caller and must outlive the handle.
- * Errors: INVALID_ARG (null/negative/num_k out of range/nnz >= 2^31),
- * BAD_CSR (with VALIDATE), UNSUPPORTED (TRANSPOSE with num_k > 1), ALLOC, HIP.
+ * Errors: INVALID_ARG (null/negative/num_k out of range), BAD_CSR (with VALIDATE),
+ * UNSUPPORTED (TRANSPOSE with num_k > 1, nnz > 2^31 - 2^16), ALLOC, HIP.
  */
 spmm_status spmm_tile_create(int64_t rows, int num_k, const spmm_csr* tiles /* host, num_k */,
                              const spmm_tile_opts* opts /* host, nullable */, void* stream,
@@ -313,7 +314,7 @@ spmm_status spmm_tile_accumulate(void* C, int64_t ldc, const void* Ptile, int64_
  * may differ between calls) into device buffers of nnz(C) entries, reading A's
  * and B's values live; asynchronous, no allocation, no host synchronisation.
  * Calls on one plan must not overlap (they share the dense accumulators).
- * Errors: INVALID_ARG, BAD_CSR (with SPMM_TILE_VALIDATE), UNSUPPORTED (nnz >= 2^31,
+ * Errors: INVALID_ARG, BAD_CSR (with SPMM_TILE_VALIDATE), UNSUPPORTED (nnz > 2^31 - 2^16,
  * C with >= 2^31 entries), ALLOC, HIP.
  */
 typedef struct spgemm_s* spgemm_t;

@@ -539,7 +539,7 @@ spmm_status spmm_tile_create(int64_t rows, int num_k, const spmm_csr* tiles, con
     const spmm_csr& t = tiles[k];
     if (t.cols < 0 || t.cols >= ((int64_t)1 << 31)) return fail(SPMM_ERR_INVALID_ARG, "tile %d: cols out of range", k);
     if (t.nnz < 0) return fail(SPMM_ERR_INVALID_ARG, "tile %d: negative nnz", k);
-    if (t.nnz >= ((int64_t)1 << 31)) return fail(SPMM_ERR_UNSUPPORTED, "tile %d: nnz >= 2^31 needs 64-bit indices", k);
+    if (t.nnz > spmm::kMaxNnz) return fail(SPMM_ERR_UNSUPPORTED, "tile %d: nnz > 2^31 - 2^16 needs 64-bit indices", k);
     if (!t.rowptr) return fail(SPMM_ERR_INVALID_ARG, "tile %d: rowptr is null", k);
     if (t.nnz > 0 && (!t.colind || !t.values)) return fail(SPMM_ERR_INVALID_ARG, "tile %d: colind/values null", k);
     units_bound += t.nnz / segment + rows;

@@ -14,6 +14,10 @@
 namespace spmm {
 
 constexpr int kMaxK = 16;      // k-tiles per tile row in one fused launch
+// Largest non-zero count of a sparse operand: positions are int32, and the kernels step
+// them by up to 1024 (a group, wave or workgroup width) while below the count, so the
+// count keeps 2^16 of headroom under 2^31.
+constexpr int64_t kMaxNnz = ((int64_t)1 << 31) - ((int64_t)1 << 16);
 constexpr int kBlock = 256;    // threads per workgroup for every kernel here
 // Grid cap for grid-stride kernels: a launch must stay below 2^32 threads.
 constexpr int64_t kMaxGridBlocks = (int64_t)1 << 20;

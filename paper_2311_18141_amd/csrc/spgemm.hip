@@ -960,8 +960,8 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
   if (A->cols < 0 || A->cols >= ((int64_t)1 << 31) || B->cols < 0 || B->cols >= ((int64_t)1 << 31))
     return spmm::set_error(SPMM_ERR_INVALID_ARG, "column count out of range");
   if (A->nnz < 0 || B->nnz < 0) return spmm::set_error(SPMM_ERR_INVALID_ARG, "negative nnz");
-  if (A->nnz >= ((int64_t)1 << 31) || B->nnz >= ((int64_t)1 << 31))
-    return spmm::set_error(SPMM_ERR_UNSUPPORTED, "nnz >= 2^31 needs 64-bit indices");
+  if (A->nnz > spmm::kMaxNnz || B->nnz > spmm::kMaxNnz)
+    return spmm::set_error(SPMM_ERR_UNSUPPORTED, "nnz > 2^31 - 2^16 needs 64-bit indices");
   if (!A->rowptr || !B->rowptr) return spmm::set_error(SPMM_ERR_INVALID_ARG, "rowptr is null");
   if ((A->nnz > 0 && (!A->colind || !A->values)) || (B->nnz > 0 && (!B->colind || !B->values)))
     return spmm::set_error(SPMM_ERR_INVALID_ARG, "colind/values null");

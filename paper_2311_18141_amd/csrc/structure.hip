@@ -93,9 +93,9 @@ __global__ void __launch_bounds__(kBlock) plan_emit_kernel(PlanEmitParams P) {
   const int32_t sl = (int32_t)unit_length(len, P.segment);
   for (int k = 0; k < P.num_k; ++k) {
     const int32_t p0 = P.rowptr[k][i], p1 = P.rowptr[k][i + 1];
-    for (int32_t p = p0; p < p1; p += sl) {
-      const int32_t e = (p1 - p > sl) ? p + sl : p1;
-      P.seg[o++] = Seg{(int32_t)i, k, p, e};
+    for (int64_t p = p0; p < p1; p += sl) {  // 64-bit: p + sl may pass 2^31 for a large unit
+      const int64_t e = (p1 - p > sl) ? p + sl : p1;
+      P.seg[o++] = Seg{(int32_t)i, k, (int32_t)p, (int32_t)e};
     }
   }
 }

@@ -68,7 +68,7 @@ def _tiles(n=1, cols=10, nnz=5, ptr=0x1000):
 
 @pytest.mark.parametrize("case,expect", [
     ("null_out", 1), ("neg_rows", 1), ("huge_rows", 1), ("k0", 1), ("k17", 1), ("null_tiles", 1),
-    ("neg_cols", 1), ("neg_nnz", 1), ("big_nnz", 3), ("null_rowptr", 1), ("null_colind", 1),
+    ("neg_cols", 1), ("neg_nnz", 1), ("big_nnz", 3), ("cap_nnz", 3), ("null_rowptr", 1), ("null_colind", 1),
     ("bad_flags", 1), ("transpose_k2", 3), ("neg_long_row", 1), ("hot_rows_m2", 1), ("hot_rows_huge", 1),
 ])
 def test_create_argument_errors(case, expect):
@@ -96,6 +96,8 @@ def test_create_argument_errors(case, expect):
         t[0].nnz = -5
     elif case == "big_nnz":
         t[0].nnz = 1 << 31
+    elif case == "cap_nnz":  # one past the largest count whose int32 positions keep stride headroom
+        t[0].nnz = (1 << 31) - (1 << 16) + 1
     elif case == "null_rowptr":
         t[0].rowptr = None
     elif case == "null_colind":
@@ -192,6 +194,8 @@ def test_spgemm_argument_errors():
     assert L.spgemm_create(4, ctypes.byref(a), ctypes.byref(a), 0, None, ctypes.byref(out)) == 1  # rowptr null
     big = SpmmCsr(4, 1 << 31, 8, 8, 8)
     assert L.spgemm_create(4, ctypes.byref(big), ctypes.byref(a), 0, None, ctypes.byref(out)) == 3
+    cap = SpmmCsr(4, (1 << 31) - (1 << 16) + 1, 8, 8, 8)
+    assert L.spgemm_create(4, ctypes.byref(a), ctypes.byref(cap), 0, None, ctypes.byref(out)) == 3
     assert L.spgemm_destroy(None) == 1
     assert L.spgemm_info(None, None, None) == 1
     assert L.spgemm_rowptr(None, None, None) == 1
