@@ -150,7 +150,8 @@ typedef struct {
 } spmm_variant;
 
 /* Set (v != NULL) or clear (v == NULL) the variant used for width N and `dtype`.
-   A variant whose vector width does not fit a call's alignment falls back to the
+   A variant whose vector width does not fit a call's alignment, or whose column
+   windows (lanes x vec columns each) would number more than 65535, falls back to the
    library's choice for that call.  Errors: INVALID_ARG (bad field values, table of
    16 entries full). */
 spmm_status spmm_tile_set_variant(spmm_tile_t tile, int64_t N, spmm_dtype dtype, const spmm_variant* v);
@@ -192,8 +193,10 @@ spmm_status spmm_fwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes /* 
  * B: host array of K device pointers; B[k] is cols_k x N row-major with leading
  * dimension ldb[k] (host array).  C: device, rows x N, leading dimension ldc.
  * dtype: (F32, F32) or (BF16, BF16) for (B, C); products and sums are FP32 and
- * a BF16 C is rounded once (nearest-even) at the store.  N >= 1.  Asynchronous.
- * Errors: INVALID_ARG, UNSUPPORTED (mixed dtypes), WORKSPACE, HIP.
+ * a BF16 C is rounded once (nearest-even) at the store.  1 <= N <= 64 x 65535
+ * (4,194,240: one launch walks the column windows of 64 or more columns in its grid's
+ * second dimension).  Asynchronous.
+ * Errors: INVALID_ARG, UNSUPPORTED (mixed dtypes, N > 4,194,240), WORKSPACE, HIP.
  */
 spmm_status spmm_fwd(spmm_tile_t A, int k_offset, const void* const* B, const int64_t* ldb,
                      spmm_dtype b_dtype, void* C, int64_t ldc, spmm_dtype c_dtype, int64_t N,
@@ -227,8 +230,8 @@ spmm_status spmm_bwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes /* 
  * Products and sums are FP32; a BF16 dB is rounded once (RNE) at the store.  dA is
  * on A's pattern, in A's CSR order; no gradient flows to the pattern.  The gradient
  * pass is not in the paper: it is this library's addition (the forward's adjoint).
- * Asynchronous.  Errors: INVALID_ARG, UNSUPPORTED (no transpose, num_k > 1, ld too
- * large), WORKSPACE, HIP.
+ * 1 <= N <= 4,194,240, as for spmm_fwd.  Asynchronous.  Errors: INVALID_ARG,
+ * UNSUPPORTED (no transpose, num_k > 1, ld too large, N too large), WORKSPACE, HIP.
  */
 spmm_status spmm_bwd(spmm_tile_t A, const void* dC, int64_t lddc, const void* B, int64_t ldb, int64_t N,
                      spmm_dtype dtype, float* dA_values, void* dB, int64_t lddb, void* workspace,

@@ -175,6 +175,11 @@ spmm::Variant pick_variant(int64_t N, DT dt, uintptr_t align_or, int64_t rows) {
 
 bool pow2_lanes(int g) { return g == 4 || g == 8 || g == 16 || g == 32 || g == 64; }
 
+// The forward launches one grid row per column window of G * V columns; a launch's grid
+// has at most 65535 rows.  (The library's own choices use windows of at least 64
+// columns, and N is checked against 64 * 65535.)
+bool fits_grid(int64_t N, const spmm::Variant& v) { return (N + (int64_t)v.G * v.V - 1) / ((int64_t)v.G * v.V) <= 65535; }
+
 }  // namespace
 
 namespace spmm {
@@ -292,6 +297,7 @@ spmm::Variant resolve_variant_in(const VarEntry* vt, int nvt, int64_t rows, int6
       G = 4;
       while (G < 64 && G < (N + V - 1) / V) G *= 2;
     }
+    if (!fits_grid(N, spmm::Variant{G, V, false})) return base;
     return spmm::Variant{G, V, false};
   }
   return base;
@@ -330,6 +336,7 @@ std::vector<spmm::Variant> candidate_variants(int64_t N, DT dt, uintptr_t align_
   const int esize = dt == DT::F32 ? 4 : 2;
   std::vector<spmm::Variant> kv;
   auto add = [&](spmm::Variant v) {
+    if (!fits_grid(N, v)) return;
     for (auto& u : kv)
       if (u.G == v.G && u.V == v.V && u.stream == v.stream && (!v.stream || u.rows == v.rows)) return;
     kv.push_back(v);
