@@ -769,7 +769,7 @@ def main():
     AUTOTUNE = args.autotune
     HANDLE_OPTS.update(long_row=args.long_row, segment=args.segment)
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the stationary-C tile row is "
+        print("bench.py measures one GPU: the library has no multi-GPU path (the stationary-C tile row is "
               "one GPU's share); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch

@@ -44,7 +44,7 @@ typedef enum {
   SPMM_OK = 0,
   SPMM_ERR_INVALID_ARG = 1,  /* null pointer, negative size, ld < width, bad enum ... */
   SPMM_ERR_BAD_CSR = 2,      /* validation found a malformed CSR tile */
-  SPMM_ERR_UNSUPPORTED = 3,  /* valid request this build does not implement */
+  SPMM_ERR_UNSUPPORTED = 3,  /* valid request the library does not implement */
   SPMM_ERR_WORKSPACE = 4,    /* workspace pointer null or smaller than required */
   SPMM_ERR_HIP = 5,          /* a HIP runtime call failed; see spmm_last_error() */
   SPMM_ERR_ALLOC = 6         /* host or device allocation failed (creation calls only) */
