@@ -23,6 +23,11 @@
  *     spmm_fwd, spmm_bwd and spmm_batched only enqueue work: no host
  *     synchronisation, no device allocation, so they can be captured in a
  *     HIP graph.  Creation and destruction calls are synchronous.
+ *   - With SPMM_TRACE set (to anything but 0) in the environment, the main entry
+ *     points (tile and batch creation, spmm_fwd, spmm_bwd, spmm_batched,
+ *     spmm_tile_accumulate, spgemm_create, spgemm_compute) each open a roctx range
+ *     named after themselves, for rocprofv3's marker trace; the roctx library is
+ *     loaded on the first range, and without it tracing stays off.
  *   - Every function returns an spmm_status; nothing is thrown across the ABI.
  *     Argument checks finish before any HIP call.  spmm_last_error() returns a
  *     thread-local message describing the most recent failure.

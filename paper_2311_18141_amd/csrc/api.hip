@@ -10,6 +10,8 @@
 #include <algorithm>
 #include <vector>
 
+#include <dlfcn.h>
+
 #include "internal.hpp"
 #include "spmm.h"
 
@@ -183,6 +185,41 @@ bool fits_grid(int64_t N, const spmm::Variant& v) { return (N + (int64_t)v.G * v
 }  // namespace
 
 namespace spmm {
+
+namespace {
+struct Roctx {
+  int (*push)(const char*) = nullptr;
+  int (*pop)() = nullptr;
+};
+
+// Opened once, on the first range, and only when SPMM_TRACE asks for it.
+const Roctx& roctx() {
+  static const Roctx r = [] {
+    Roctx x;
+    const char* e = std::getenv("SPMM_TRACE");
+    if (!e || !*e || std::strcmp(e, "0") == 0) return x;
+    void* h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_LOCAL);
+    if (!h) h = dlopen("libroctx64.so.4", RTLD_NOW | RTLD_LOCAL);
+    if (!h) return x;
+    auto push = reinterpret_cast<int (*)(const char*)>(dlsym(h, "roctxRangePushA"));
+    auto pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+    if (push && pop) {
+      x.push = push;
+      x.pop = pop;
+    }
+    return x;
+  }();
+  return r;
+}
+}  // namespace
+
+TraceRange::TraceRange(const char* name) : on(roctx().push != nullptr) {
+  if (on) roctx().push(name);
+}
+
+TraceRange::~TraceRange() {
+  if (on) roctx().pop();
+}
 
 spmm_status set_error(spmm_status st, const char* fmt, ...) {
   char buf[512];
@@ -527,6 +564,7 @@ const char* spmm_last_error(void) { return g_err.c_str(); }
 
 spmm_status spmm_tile_create(int64_t rows, int num_k, const spmm_csr* tiles, const spmm_tile_opts* opts,
                              void* stream, spmm_tile_t* out) {
+  spmm::TraceRange trace_range("spmm_tile_create");
   if (!out) return fail(SPMM_ERR_INVALID_ARG, "out is null");
   *out = nullptr;
   if (rows < 0 || rows >= ((int64_t)1 << 31)) return fail(SPMM_ERR_INVALID_ARG, "rows=%lld out of range", (long long)rows);
@@ -710,6 +748,7 @@ spmm_status spmm_bwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes) {
 spmm_status spmm_fwd(spmm_tile_t A, int k_offset, const void* const* B, const int64_t* ldb, spmm_dtype b_dtype,
                      void* C, int64_t ldc, spmm_dtype c_dtype, int64_t N, int accumulate, void* workspace,
                      size_t ws_bytes, void* stream) {
+  spmm::TraceRange trace_range("spmm_fwd");
   if (!A) return fail(SPMM_ERR_INVALID_ARG, "A is null");
   if (!B || !ldb) return fail(SPMM_ERR_INVALID_ARG, "B/ldb array is null");
   if (N < 1) return fail(SPMM_ERR_INVALID_ARG, "N=%lld < 1", (long long)N);
@@ -914,6 +953,7 @@ static spmm_status autotune_impl(spmm_tile_t A, int64_t N, spmm_dtype dtype, con
 
 spmm_status spmm_tile_accumulate(void* C, int64_t ldc, const void* Ptile, int64_t ldp, int64_t rows, int64_t N,
                                  spmm_dtype dtype, void* stream) {
+  spmm::TraceRange trace_range("spmm_tile_accumulate");
   if (rows < 0 || N < 1) return fail(SPMM_ERR_INVALID_ARG, "rows=%lld N=%lld", (long long)rows, (long long)N);
   if (dtype != SPMM_F32 && dtype != SPMM_BF16) return fail(SPMM_ERR_INVALID_ARG, "unknown dtype");
   if (ldc < N || ldp < N) return fail(SPMM_ERR_INVALID_ARG, "leading dimension < N");
@@ -933,6 +973,7 @@ spmm_status spmm_tile_accumulate(void* C, int64_t ldc, const void* Ptile, int64_
 spmm_status spmm_bwd(spmm_tile_t A, const void* dC, int64_t lddc, const void* B, int64_t ldb, int64_t N,
                      spmm_dtype dtype, float* dA_values, void* dB, int64_t lddb, void* workspace, size_t ws_bytes,
                      void* stream) {
+  spmm::TraceRange trace_range("spmm_bwd");
   if (!A) return fail(SPMM_ERR_INVALID_ARG, "A is null");
   if (dtype != SPMM_F32 && dtype != SPMM_BF16) return fail(SPMM_ERR_INVALID_ARG, "unknown dtype");
   const DT dt = dtype == SPMM_F32 ? DT::F32 : DT::BF16;
@@ -1185,6 +1226,7 @@ extern "C" {
 
 spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t* N, spmm_dtype dtype,
                               int64_t item_nnz, unsigned flags, void* stream, spmm_batch_t* out) {
+  spmm::TraceRange trace_range("spmm_batch_create");
   if (!out) return fail(SPMM_ERR_INVALID_ARG, "out is null");
   *out = nullptr;
   if (count < 1) return fail(SPMM_ERR_INVALID_ARG, "count=%d < 1", count);
@@ -1388,6 +1430,7 @@ spmm_status spmm_batch_get_variant(spmm_batch_t batch, int t, spmm_variant* out)
 
 spmm_status spmm_batched(spmm_batch_t batch, const void* const* B, const int64_t* ldb, void* const* C,
                          const int64_t* ldc, int accumulate, void* workspace, size_t ws_bytes, void* stream) {
+  spmm::TraceRange trace_range("spmm_batched");
   if (!batch) return fail(SPMM_ERR_INVALID_ARG, "batch is null");
   if (!B || !ldb || !C || !ldc) return fail(SPMM_ERR_INVALID_ARG, "operand arrays must be device arrays, not null");
   if (batch->ws_bytes > 0) {

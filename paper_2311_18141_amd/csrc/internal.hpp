@@ -27,6 +27,17 @@ enum class DT : int { F32 = 0, BF16 = 1 };
 // Record the thread-local message spmm_last_error() returns; returns st.
 spmm_status set_error(spmm_status st, const char* fmt, ...);
 
+// A named roctx range around an entry point, for timelines from rocprofv3's marker
+// trace: on only when the environment sets SPMM_TRACE (to anything but 0) and the
+// roctx library can be opened; otherwise a range costs one predictable branch.
+struct TraceRange {
+  explicit TraceRange(const char* name);
+  ~TraceRange();
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+  bool on;
+};
+
 // Runs f() and turns a C++ exception (a failed host allocation, in practice) into a
 // status, so that no exception leaves an entry point of the C ABI.
 template <typename F>

@@ -953,6 +953,7 @@ extern "C" {
 
 spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsigned flags, void* stream,
                           spgemm_t* out) {
+  spmm::TraceRange trace_range("spgemm_create");
   if (!out) return spmm::set_error(SPMM_ERR_INVALID_ARG, "out is null");
   *out = nullptr;
   if (!A || !B) return spmm::set_error(SPMM_ERR_INVALID_ARG, "A/B is null");
@@ -1244,6 +1245,7 @@ spmm_status spgemm_rowptr(spgemm_t plan, int32_t* rowptrC, void* stream) {
 }
 
 spmm_status spgemm_compute(spgemm_t plan, int32_t* colindC, float* valuesC, void* stream) {
+  spmm::TraceRange trace_range("spgemm_compute");
   if (!plan) return spmm::set_error(SPMM_ERR_INVALID_ARG, "plan is null");
   if (plan->nnz_c > 0 && (!colindC || !valuesC)) return spmm::set_error(SPMM_ERR_INVALID_ARG, "colindC/valuesC null");
   int dev = 0;

@@ -234,3 +234,23 @@ def test_bwd_variant_argument_errors():
     assert L.spmm_tile_get_variant(None, 64, 0, 0, ctypes.byref(v)) == 1
     assert L.spmm_tile_get_variant(None, 64, 0, 1, None) == 1
     assert L.spmm_tile_autotune_bwd(None, 64, 0, 0x1000, 64, 0x2000, 64, None, None) == 1
+
+
+def test_trace_ranges_switch_on_without_changing_results():
+    """With SPMM_TRACE=1 the entry points open roctx ranges (the marker library is loaded on
+    the first one); argument checks still return their status.  Run in a child process so
+    that the switch, read once per process, starts fresh."""
+    import subprocess
+    import sys
+    code = ("import ctypes\n"
+            "from paper_2311_18141_amd import _lib\n"
+            "L = _lib.lib()\n"
+            "assert L.spmm_fwd(None, 0, None, None, 0, None, 8, 0, 8, 0, None, 0, None) == 1\n"
+            "assert L.spmm_batched(None, None, None, None, None, 0, None, 0, None) == 1\n"
+            "assert L.spgemm_compute(None, None, None, None) == 1\n"
+            "print('ok')\n")
+    for flag in ("1", "0"):
+        env = dict(os.environ, SPMM_TRACE=flag)
+        r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                           timeout=120)
+        assert r.returncode == 0 and r.stdout.strip() == "ok", (flag, r.stdout, r.stderr[-2000:])
