@@ -432,6 +432,99 @@ __device__ __forceinline__ void bitonic_sort(int32_t* key, float* val, int P, in
   }
 }
 
+// x from lane (lane xor j).  j = 1, 2: one DPP quad permutation; j = 4: the quad
+// permutation xor 3, then the half-row mirror (lane i of 8 reads 7 - i = i xor 7);
+// j = 8: the half-row mirror, then the row mirror (i xor 15): register moves that
+// leave the LDS pipe alone.  j = 16, 32: a lane shuffle.
+__device__ __forceinline__ int32_t lane_xor(int32_t x, int j) {
+  constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kQuadXor3 = 0x1B;  // quad_perm [1,0,3,2], [2,3,0,1], [3,2,1,0]
+  constexpr int kRowMirror = 0x140, kRowHalfMirror = 0x141;
+  switch (j) {  // a constant once the sorting network is unrolled
+    case 1:
+      return __builtin_amdgcn_mov_dpp(x, kQuadXor1, 0xF, 0xF, true);
+    case 2:
+      return __builtin_amdgcn_mov_dpp(x, kQuadXor2, 0xF, 0xF, true);
+    case 4:
+      return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(x, kQuadXor3, 0xF, 0xF, true), kRowHalfMirror, 0xF,
+                                      0xF, true);
+    case 8:
+      return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(x, kRowHalfMirror, 0xF, 0xF, true), kRowMirror, 0xF,
+                                      0xF, true);
+    default:
+      return __shfl_xor(x, j, 64);
+  }
+}
+
+// Bitonic sort of P = 64 KPL (key, value) pairs held in one wave's registers: element
+// e = r * 64 + lane sits in register r of that lane.  Stages whose partner distance j
+// is 64 or more pair two registers of one lane; shorter ones pair two lanes (one
+// shuffle per register), and both lanes of a pair compare the same two keys, so they
+// agree on which keeps the smaller.  Keys are distinct apart from the padding, whose
+// pairs never swap.  No LDS and no barrier.
+template <int KPL>
+__device__ __forceinline__ void wave_sort_regs(int32_t (&k)[KPL], float (&v)[KPL], int lane) {
+  constexpr int P = 64 * KPL;
+#pragma unroll
+  for (int kk = 2; kk <= P; kk <<= 1) {
+#pragma unroll
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      if (j >= 64) {
+        const int jr = j >> 6;
+#pragma unroll
+        for (int r = 0; r < KPL; ++r) {
+          if (r & jr) continue;
+          const int r2 = r | jr;
+          const bool up = ((r * 64 + lane) & kk) == 0;
+          if ((k[r] > k[r2]) == up) {
+            const int32_t tk = k[r];
+            k[r] = k[r2];
+            k[r2] = tk;
+            const float tv = v[r];
+            v[r] = v[r2];
+            v[r2] = tv;
+          }
+        }
+      } else {
+        const bool lower = (lane & j) == 0;
+#pragma unroll
+        for (int r = 0; r < KPL; ++r) {
+          const bool up = ((r * 64 + lane) & kk) == 0;
+          const int32_t pk = lane_xor(k[r], j);
+          const float pv = __int_as_float(lane_xor(__float_as_int(v[r]), j));
+          const bool take = (lower == up) ? (pk < k[r]) : (pk > k[r]);
+          if (take) {
+            k[r] = pk;
+            v[r] = pv;
+          }
+        }
+      }
+    }
+  }
+}
+
+// Sort the first 64 KPL (key, value) slots of a wave's table in registers and write
+// the first cnt of them to C at base (element e by lane e mod 64: coalesced).
+template <int KPL>
+__device__ __forceinline__ void sort_emit_wave(const int32_t* key, const float* val, int lane, const SgOut& Co,
+                                               int32_t base, int32_t cnt) {
+  int32_t k[KPL];
+  float v[KPL];
+#pragma unroll
+  for (int r = 0; r < KPL; ++r) {
+    k[r] = key[r * 64 + lane];
+    v[r] = val[r * 64 + lane];
+  }
+  wave_sort_regs<KPL>(k, v, lane);
+#pragma unroll
+  for (int r = 0; r < KPL; ++r) {
+    const int e = r * 64 + lane;
+    if (e < cnt) {
+      Co.colC[base + e] = k[r];
+      Co.valC[base + e] = v[r];
+    }
+  }
+}
+
 __device__ __forceinline__ int pow2_at_least(int n) {
   int p = 1;
   while (p < n) p <<= 1;
@@ -488,14 +581,22 @@ __global__ void __launch_bounds__(kBlock) num_wave_kernel(SgOperands O, SgOut Co
       n += __popcll(m);
       wave_sync_lds();
     }
-    const int P = pow2_at_least(n);
+    // sort the smallest power of two (at least 64, at most TS / 2) that holds them, in
+    // registers
+    const int P = n <= 64 ? 64 : pow2_at_least(n);
     for (int j = n + lane; j < P; j += 64) key[j] = 0x7fffffff;  // padding sorts last
     wave_sync_lds();
-    bitonic_sort(key, val, P, lane, 64, [] { wave_sync_lds(); });
     const int32_t base = Co.rowptrC[i], cnt = min(Co.rowptrC[i + 1] - base, n);
-    for (int j = lane; j < cnt; j += 64) {
-      Co.colC[base + j] = key[j];
-      Co.valC[base + j] = val[j];
+    if (P == 64) {
+      sort_emit_wave<1>(key, val, lane, Co, base, cnt);
+    } else if (P == 128) {
+      sort_emit_wave<2>(key, val, lane, Co, base, cnt);
+    } else if constexpr (TS >= 512) {
+      if (P == 256) {
+        sort_emit_wave<4>(key, val, lane, Co, base, cnt);
+      } else if constexpr (TS >= 1024) {
+        sort_emit_wave<8>(key, val, lane, Co, base, cnt);
+      }
     }
     wave_sync_lds();
   }
