@@ -89,12 +89,14 @@ def _log(msg):
 
 
 # Sources of the kernels a workload launches (forward, split-row fix-up, hot-row staging; for the
-# backward also SDDMM and value gather): a stored counter reading is valid while these
-# are unchanged.
+# backward also SDDMM and value gather; the SpGEMM numeric kernels): a stored counter reading is
+# valid while these are unchanged.
 FWD_SOURCES = ("elem.hpp", "fwd_common.hpp", "fwd.hip", "hot.hip")
 KERNEL_SOURCES = {"powerlaw2m_n128_fwdbwd": FWD_SOURCES + ("bwd.hip",),
                   "powerlaw2m_n128_fwdbwd_bf16": FWD_SOURCES + ("bwd.hip",),
-                  "uneven512_batched": ("elem.hpp", "fwd_common.hpp", "batch.hip")}
+                  "uneven512_batched": ("elem.hpp", "fwd_common.hpp", "batch.hip"),
+                  "spgemm_rmat18_ef16_aa": ("spgemm.hip",),
+                  "spgemm_er1m16_aa": ("spgemm.hip",)}
 
 
 def kernel_source_digest(workload: str = "") -> str:
