@@ -38,20 +38,21 @@ def fp32_stats(got: np.ndarray, ref: np.ndarray, S: np.ndarray, tol: float = FP3
     pos = S > 0
     rel = np.zeros_like(err)
     rel[pos] = err[pos] / S[pos]
-    zero_mismatch = int(np.count_nonzero(err[~pos] != 0))
-    nan = int(np.count_nonzero(~np.isfinite(got)))
+    zero_bad = ~pos & (err != 0)
+    # A NaN compares false with every bound, so non-finite results are counted on their own.
+    nonfinite = ~np.isfinite(got)
     out = {
         "max_rel_to_scale": float(rel.max()) if rel.size else 0.0,
         "mean_rel_to_scale": float(rel.mean()) if rel.size else 0.0,
-        "n_over_tol": int(np.count_nonzero(rel > tol)) + zero_mismatch + nan,
-        "zero_scale_mismatch": zero_mismatch,
-        "nonfinite": nan,
+        "n_over_tol": int(np.count_nonzero((rel > tol) | zero_bad | nonfinite)),
+        "zero_scale_mismatch": int(np.count_nonzero(zero_bad)),
+        "nonfinite": int(np.count_nonzero(nonfinite)),
         "normwise": float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)),
         "entries": int(err.size),
     }
     if n_terms is not None:
         bound = gamma(n_terms) * S
-        out["n_over_gamma_bound"] = int(np.count_nonzero(err > bound))
+        out["n_over_gamma_bound"] = int(np.count_nonzero((err > bound) | nonfinite))
     return out
 
 
@@ -68,11 +69,15 @@ def bf16_stats(got: np.ndarray, ref: np.ndarray, S: np.ndarray, tol: float = FP3
     rel = np.zeros_like(err)
     pos = denom > 0
     rel[pos] = err[pos] / denom[pos]
-    zero_mismatch = int(np.count_nonzero(err[~pos] != 0))
+    zero_bad = ~pos & (err != 0)
+    # A NaN compares false with every bound, so non-finite results are counted on their own.
+    nonfinite = ~np.isfinite(got)
     return {
         "max_rel": float(rel.max()) if rel.size else 0.0,
         "mean_rel": float(rel.mean()) if rel.size else 0.0,
-        "n_over_bound": int(np.count_nonzero(err > bound)) + zero_mismatch,
+        "n_over_bound": int(np.count_nonzero((err > bound) | zero_bad | nonfinite)),
+        "zero_scale_mismatch": int(np.count_nonzero(zero_bad)),
+        "nonfinite": int(np.count_nonzero(nonfinite)),
         "normwise": float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)),
         "entries": int(err.size),
     }
@@ -88,4 +93,5 @@ def relative_stats(got: np.ndarray, ref: np.ndarray, S: np.ndarray) -> Dict[str,
     rel[pos] = err[pos] / denom[pos]
     return {"max_rel": float(rel.max()) if rel.size else 0.0,
             "mean_rel": float(rel.mean()) if rel.size else 0.0,
+            "nonfinite": int(np.count_nonzero(~np.isfinite(got))),
             "normwise": float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))}

@@ -85,3 +85,85 @@ def test_pins_catch_mutant(name, tmp_path):
     finally:
         oracle._lib = saved
     assert caught, "no pin caught mutant %s" % name
+
+
+# Planted mistakes in the acceptance logic (oracle/compare.py, and the BF16 widening in
+# oracle/__init__.py): a copy of the module with one edit is loaded under another name and
+# the pins of test_compare.py run against it; at least one of them must fail.
+import importlib.util  # noqa: E402
+
+import test_compare as TC  # noqa: E402
+
+_COMPARE_SRC = os.path.join(os.path.dirname(oracle._SRC), "compare.py")
+_ORACLE_PY = os.path.join(os.path.dirname(oracle._SRC), "__init__.py")
+
+COMPARE_MUTANTS = {
+    "tol_x10": ('"n_over_tol": int(np.count_nonzero((rel > tol) |', '"n_over_tol": int(np.count_nonzero((rel > 10 * tol) |'),
+    "fp32_drop_zero_scale": ("(rel > tol) | zero_bad | nonfinite", "(rel > tol) | nonfinite"),
+    "fp32_nan_passthrough": ("(rel > tol) | zero_bad | nonfinite", "(rel > tol) | zero_bad"),
+    "fp32_scale_is_abs_ref": ("rel[pos] = err[pos] / S[pos]", "rel[pos] = err[pos] / np.abs(ref[pos])"),
+    "fp32_ok_ignores_gamma": ('return stats["n_over_tol"] == 0 and stats.get("n_over_gamma_bound", 0) == 0',
+                              'return stats["n_over_tol"] == 0'),
+    "bf16_nan_passthrough": ("(err > bound) | zero_bad | nonfinite", "(err > bound) | zero_bad"),
+    # (dropping zero_bad from the BF16 count is an equivalent edit: where ref = 0 and S = 0 the
+    # bound is exactly 0, so err > bound already fails the entry)
+    "bf16_wrong_bound_factor": ("bound = U_BF16 * np.abs(ref)", "bound = 2 * U_BF16 * np.abs(ref)"),
+    "bf16_bound_drops_scale_term": ("bound = U_BF16 * np.abs(ref) + tol * S * (1.0 + U_BF16)",
+                                    "bound = U_BF16 * np.abs(ref)"),
+    "gamma_no_denominator": ("return n * u / (1.0 - n * u)", "return n * u"),
+    "unit_roundoff_wrong": ("U32 = 2.0 ** -24", "U32 = 2.0 ** -23"),
+    "relative_floor_dropped": ('the relative error reported per result."""\n    got = np.asarray(got, dtype=np.float64)\n'
+                               '    err = np.abs(got - ref)\n    denom = np.maximum(np.abs(ref), 2.0 ** -20 * S)',
+                               'the relative error reported per result."""\n    got = np.asarray(got, dtype=np.float64)\n'
+                               '    err = np.abs(got - ref)\n    denom = np.abs(ref)'),
+    "relative_nan_hidden": ('"nonfinite": int(np.count_nonzero(~np.isfinite(got))),\n            "normwise"',
+                            '"nonfinite": 0,\n            "normwise"'),
+}
+
+WIDEN_MUTANTS = {
+    "widen_shift_15": ("astype(np.uint32) << 16).view(np.float32)", "astype(np.uint32) << 15).view(np.float32)"),
+    "widen_drops_sign": ("(np.asarray(h, dtype=np.uint16).astype(np.uint32) << 16)",
+                         "((np.asarray(h, dtype=np.uint16) & 0x7FFF).astype(np.uint32) << 16)"),
+}
+
+
+def _load_mutant(src_path, old, new, tmp_path, name):
+    with open(src_path) as f:
+        src = f.read()
+    assert src.count(old) == 1, "mutation site not found uniquely"
+    path = tmp_path / (name + ".py")
+    path.write_text(src.replace(old, new))
+    spec = importlib.util.spec_from_file_location("mutant_" + name, str(path))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def _caught(pins, mod):
+    caught = []
+    for i, pin in enumerate(pins):
+        try:
+            pin(mod)
+        except (AssertionError, IndexError, ValueError, ZeroDivisionError):
+            caught.append(i)
+    return caught
+
+
+@pytest.mark.parametrize("name", sorted(COMPARE_MUTANTS))
+def test_compare_pins_catch_mutant(name, tmp_path):
+    old, new = COMPARE_MUTANTS[name]
+    mod = _load_mutant(_COMPARE_SRC, old, new, tmp_path, name)
+    assert _caught(TC.COMPARE_PINS, mod), "no pin caught compare mutant %s" % name
+
+
+@pytest.mark.parametrize("name", sorted(WIDEN_MUTANTS))
+def test_widening_pin_catches_mutant(name, tmp_path):
+    old, new = WIDEN_MUTANTS[name]
+    mod = _load_mutant(_ORACLE_PY, old, new, tmp_path, name)
+    assert _caught([TC.pin_bf16_widening_all_patterns], mod), "widening mutant %s not caught" % name
+
+
+def test_unmutated_compare_passes_every_pin(tmp_path):
+    """The harness itself: the unedited module loaded the same way passes every pin."""
+    mod = _load_mutant(_COMPARE_SRC, "U32 = 2.0 ** -24", "U32 = 2.0 ** -24", tmp_path, "identity")
+    assert _caught(TC.COMPARE_PINS, mod) == []
