@@ -75,11 +75,14 @@ typedef struct {
   unsigned flags;
   int32_t long_row;        /* rows whose length over all k-tiles exceeds this are split across
                               work units with a deterministic fix-up; 0 = library default
-                              (128, doubled while below twice the mean row length) */
+                              (128, doubled while below twice the mean row length); at most
+                              33,554,431 ((2^31 - 1) / 64), else INVALID_ARG */
   int32_t segment;         /* minimum non-zeros per split work unit (a row of length L gets units
                               of max(segment, ceil(sqrt(L)))); 0 = library default (64) */
   int32_t bwd_slice;       /* spmm_bwd computes dA in column slices of this width, one launch
-                              per slice, so a slice of B can stay cache-resident; 0 = one launch */
+                              per slice, so a slice of B can stay cache-resident (the two-pass
+                              backward: no fused pass while a slice narrower than N is set);
+                              0 = one launch */
   int32_t hot_rows;        /* hot-row staging of the forward: the B rows of each k-tile's most used
                               columns are copied on every spmm_fwd call into one contiguous block of
                               the workspace and read there (the handle keeps a copy of colind with
@@ -147,6 +150,8 @@ spmm_status spmm_tile_export_transpose(spmm_tile_t tile, int32_t* rowptrT, int32
 #define SPMM_KERNEL_AUTO 0
 #define SPMM_KERNEL_ROWSPLIT 1   /* a group of `lanes` lanes owns one row and a column window */
 #define SPMM_KERNEL_STREAM 2     /* a wave streams the non-zeros of `lanes` (4..64) consecutive rows */
+#define SPMM_KERNEL_FUSED 3      /* backward only: dA and dB in one pass over the transposed structure,
+                                    `lanes` lanes per row of A^T covering all N columns (lanes x vec >= N) */
 typedef struct {
   int32_t kind;    /* SPMM_KERNEL_* */
   int32_t lanes;   /* ROWSPLIT: lanes per row; STREAM: rows per wave; 4..64, power of two;
@@ -207,23 +212,34 @@ spmm_status spmm_fwd(spmm_tile_t A, int k_offset, const void* const* B, const in
                      spmm_dtype b_dtype, void* C, int64_t ldc, spmm_dtype c_dtype, int64_t N,
                      int accumulate, void* workspace, size_t ws_bytes, void* stream);
 
-/* The backward's dB pass (dB = A^T dC) runs the forward kernels over the transposed
-   structure; it keeps its own variant per (N, dtype), set here (v != NULL) or cleared
-   (v == NULL; the fixed rule then applies).  Results of every variant agree as the
-   forward's do.  Errors: INVALID_ARG (bad field values, table of 16 entries full). */
+/* The backward keeps its own variant per (N, dtype), set here (v != NULL) or cleared
+   (v == NULL; the library rule then applies).  Kind SPMM_KERNEL_FUSED selects the fused
+   backward (when spmm_bwd is asked for both dA and dB): a group of `lanes` lanes owns one
+   row of A^T with `vec` columns per lane, lanes x vec >= N (0 = library choice; a shape
+   that does not fit a call's alignment or does not cover N falls back to the library's).
+   Kinds ROWSPLIT and STREAM select the two-pass backward (SDDMM for dA, then the forward
+   kernels over the transposed structure for dB) and name the dB pass's kernel.  Without
+   an entry the fused backward runs whenever a group of at most 64 lanes covers N.
+   Results of every variant agree as the forward's do (dB bit-identical between the fused
+   and two-pass forms at the same vector width and split plan; dA within FP32 summation
+   order).  Errors: INVALID_ARG (bad field values, table of 16 entries full). */
 spmm_status spmm_tile_set_bwd_variant(spmm_tile_t tile, int64_t N, spmm_dtype dtype, const spmm_variant* v);
 
-/* Time the dB pass's variants on the caller's dC (rows x N, ld lddc) for a K = 1 handle
-   built with SPMM_TILE_TRANSPOSE and keep the fastest for (N, dtype).  Synchronous;
-   allocates its own scratch; overwrites dB (cols x N, ld lddb).  `chosen` (nullable)
-   receives the winner.  Errors: INVALID_ARG, UNSUPPORTED (no transpose, num_k > 1,
-   ld too large), ALLOC, HIP. */
+/* Time the backward's variants on the caller's operands for a K = 1 handle built with
+   SPMM_TILE_TRANSPOSE and keep the fastest for (N, dtype): dC (rows x N, ld lddc), dB
+   (cols x N, ld lddb) and, when B (cols x N, ld ldb) and dA (nnz FP32) are both given, the
+   whole backward (fused shapes and the two-pass form with each dB-pass kernel) through
+   spmm_bwd; with B or dA NULL only the dB pass's kernels (dB alone).  Synchronous;
+   allocates its own scratch; overwrites dB (and dA).  `chosen` (nullable) receives the
+   winner.  Errors: INVALID_ARG, UNSUPPORTED (no transpose, num_k > 1, ld too large),
+   ALLOC, HIP. */
 spmm_status spmm_tile_autotune_bwd(spmm_tile_t tile, int64_t N, spmm_dtype dtype, const void* dC, int64_t lddc,
-                                   void* dB, int64_t lddb, void* stream, spmm_variant* chosen /* host */);
+                                   const void* B /* nullable */, int64_t ldb, float* dA /* nullable */, void* dB,
+                                   int64_t lddb, void* stream, spmm_variant* chosen /* host */);
 
 /* Workspace (device bytes) spmm_bwd needs for this handle at width N when dB is
    wanted: FP32 partial rows of the transposed plan's split rows plus 4 bytes per
-   non-zero (A's values gathered into the transposed order on every call). */
+   non-zero (A's values gathered into the transposed order by the two-pass form). */
 spmm_status spmm_bwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes /* host */);
 
 /*
@@ -235,6 +251,9 @@ spmm_status spmm_bwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes /* 
  * Products and sums are FP32; a BF16 dB is rounded once (RNE) at the store.  dA is
  * on A's pattern, in A's CSR order; no gradient flows to the pattern.  The gradient
  * pass is not in the paper: it is this library's addition (the forward's adjoint).
+ * With both outputs wanted (and no column slices set), one pass over the transposed
+ * structure gathers each dC row once for both (see SPMM_KERNEL_FUSED); otherwise dA is
+ * a sampled dense-dense product in A's order and dB a pass of the forward kernels.
  * 1 <= N <= 4,194,240, as for spmm_fwd.  Asynchronous.  Errors: INVALID_ARG,
  * UNSUPPORTED (no transpose, num_k > 1, ld too large, N too large), WORKSPACE, HIP.
  */

@@ -51,6 +51,7 @@ class SpmmVariant(ctypes.Structure):
 SPMM_KERNEL_AUTO = 0
 SPMM_KERNEL_ROWSPLIT = 1
 SPMM_KERNEL_STREAM = 2
+SPMM_KERNEL_FUSED = 3
 
 
 class SpmmError(RuntimeError):
@@ -68,7 +69,8 @@ EXPORTS = {
     "spmm_tile_set_sddmm_variant": (c_int, [c_vp, c_i64, c_int, c_int]),
     "spmm_tile_set_bwd_variant": (c_int, [c_vp, c_i64, c_int, c_vp]),
     "spmm_tile_get_variant": (c_int, [c_vp, c_i64, c_int, c_int, c_vp]),
-    "spmm_tile_autotune_bwd": (c_int, [c_vp, c_i64, c_int, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp]),
+    "spmm_tile_autotune_bwd": (c_int, [c_vp, c_i64, c_int, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp, c_i64, c_vp,
+                                       c_vp]),
     "spmm_tile_autotune": (c_int, [c_vp, c_i64, c_int, c_vp, c_vp, c_vp, c_i64, c_int, c_vp, c_vp]),
     "spmm_fwd_workspace_bytes": (c_int, [c_vp, c_i64, c_vp]),
     "spmm_fwd": (c_int, [c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_i64, c_int, c_i64, c_int, c_vp, c_size, c_vp]),

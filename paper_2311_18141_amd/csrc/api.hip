@@ -40,6 +40,8 @@ spmm_status fail(spmm_status st, const char* fmt, ...) {
 
 constexpr int32_t kDefaultLongRow = 128;
 constexpr int32_t kDefaultSegment = 64;
+// Largest split threshold: 64 rows of at most this length sum below 2^31.
+constexpr int32_t kMaxLongRow = ((int64_t)1 << 31) / 64 - 1;
 // Hot-row staging, library default: up to this many B rows per k-tile, each used by at
 // least kHotMinUses non-zeros, for tiles of at least kHotMinNnz non-zeros in total, and
 // only where the staged rows serve at least 1/8 of the k-tile's non-zeros and at least
@@ -325,7 +327,7 @@ spmm::Variant resolve_variant_in(const VarEntry* vt, int nvt, int64_t rows, int6
   const int want = dt == DT::F32 ? SPMM_F32 : SPMM_BF16;
   for (int i = 0; i < nvt; ++i) {
     const auto& e = vt[i];
-    if (e.N != N || e.dtype != want || e.v.kind == SPMM_KERNEL_AUTO) continue;
+    if (e.N != N || e.dtype != want || e.v.kind == SPMM_KERNEL_AUTO || e.v.kind == SPMM_KERNEL_FUSED) continue;
     const int V = e.v.vec ? e.v.vec : base.V;
     if ((N % V) != 0 || (align_or % (uintptr_t)(V * esize)) != 0) return base;
     if (e.v.kind == SPMM_KERNEL_STREAM) return spmm::Variant{64, V, true, e.v.lanes ? e.v.lanes : stream_rows_for(rows)};
@@ -342,6 +344,45 @@ spmm::Variant resolve_variant_in(const VarEntry* vt, int nvt, int64_t rows, int6
 
 spmm::Variant resolve_variant(const spmm_tile_s* A, int64_t N, DT dt, uintptr_t align_or) {
   return resolve_variant_in(A->vt, A->nvt, A->rows, N, dt, align_or);
+}
+
+// Shape of the fused backward (one pass over the transposed structure for dA and dB)
+// at width N, or false when the two-pass backward applies: an entry of the backward's
+// table for (N, dtype) that names a dB-pass kernel, or no group of at most 64 lanes
+// covering N.  A fused entry's lanes / vec (0 = library choice) must fit the call's
+// alignment and cover N, else the library's shape is used: the widest aligned vector
+// (16 bytes a lane) and the smallest power-of-two group covering N.  U = 8 entries in
+// flight per group (4 for groups of 4 lanes).
+struct FusedShape {
+  int G, V, U;
+};
+bool fused_shape(const spmm_tile_s* A, int64_t N, DT dt, uintptr_t align_or, FusedShape* out) {
+  const int esize = dt == DT::F32 ? 4 : 2;
+  const int want = dt == DT::F32 ? SPMM_F32 : SPMM_BF16;
+  const spmm_variant* ent = nullptr;
+  for (int i = 0; i < A->nvtT; ++i)
+    if (A->vtT[i].N == N && A->vtT[i].dtype == want && A->vtT[i].v.kind != SPMM_KERNEL_AUTO) ent = &A->vtT[i].v;
+  if (ent && ent->kind != SPMM_KERNEL_FUSED) return false;
+  auto covering = [&](int V) {
+    int G = 4;
+    while (G < 64 && (int64_t)G * V < N) G *= 2;
+    return G;
+  };
+  auto aligned = [&](int V) { return (N % V) == 0 && (align_or % (uintptr_t)(V * esize)) == 0; };
+  int V = 16 / esize;
+  while (V > 1 && !aligned(V)) V /= 2;
+  int G = covering(V);
+  if (ent) {
+    const int Ve = ent->vec ? ent->vec : V;
+    const int Ge = ent->lanes ? ent->lanes : covering(Ve);
+    if (aligned(Ve) && (int64_t)Ge * Ve >= N) {
+      V = Ve;
+      G = Ge;
+    }
+  }
+  if ((int64_t)G * V < N) return false;
+  *out = FusedShape{G, V, G >= 8 ? 8 : 4};
+  return true;
 }
 
 // Set (v != null) or clear (v == null) a table's entry for (N, dtype).
@@ -536,8 +577,9 @@ spmm_status select_hot(spmm_tile_s* h, const spmm_csr* tiles, int K, int32_t wan
   return st;
 }
 
-bool valid_variant(const spmm_variant& v, spmm_dtype dtype) {
-  if (v.kind < SPMM_KERNEL_AUTO || v.kind > SPMM_KERNEL_STREAM) return false;
+// Fields of a variant entry; the fused backward kind belongs to the backward's table only.
+bool valid_variant(const spmm_variant& v, spmm_dtype dtype, bool bwd) {
+  if (v.kind < SPMM_KERNEL_AUTO || v.kind > (bwd ? SPMM_KERNEL_FUSED : SPMM_KERNEL_STREAM)) return false;
   if (v.lanes != 0 && !pow2_lanes(v.lanes)) return false;
   if (v.vec != 0 && v.vec != 1 && v.vec != 2 && v.vec != 4 && !(v.vec == 8 && dtype == SPMM_BF16)) return false;
   return true;
@@ -576,6 +618,9 @@ spmm_status spmm_tile_create(int64_t rows, int num_k, const spmm_csr* tiles, con
   int32_t segment = (opts && opts->segment > 0) ? opts->segment : kDefaultSegment;
   if (opts && (opts->long_row < 0 || opts->segment < 0 || opts->bwd_slice < 0))
     return fail(SPMM_ERR_INVALID_ARG, "negative long_row/segment/bwd_slice");
+  // The stream kernels sum the lengths of 64 unsplit rows in 32 bits.
+  if (long_row > kMaxLongRow)
+    return fail(SPMM_ERR_INVALID_ARG, "long_row=%d above %d ((2^31 - 1) / 64)", long_row, kMaxLongRow);
   const int32_t hot_rows = opts ? opts->hot_rows : 0;
   if (hot_rows < -1 || hot_rows > kMaxHotRows)
     return fail(SPMM_ERR_INVALID_ARG, "hot_rows=%d outside [-1, %d]", hot_rows, kMaxHotRows);
@@ -789,7 +834,7 @@ spmm_status spmm_tile_set_variant(spmm_tile_t A, int64_t N, spmm_dtype dtype, co
   if (!A) return fail(SPMM_ERR_INVALID_ARG, "tile is null");
   if (N < 1) return fail(SPMM_ERR_INVALID_ARG, "N=%lld < 1", (long long)N);
   if (dtype != SPMM_F32 && dtype != SPMM_BF16) return fail(SPMM_ERR_INVALID_ARG, "unknown dtype");
-  if (v && !valid_variant(*v, dtype)) return fail(SPMM_ERR_INVALID_ARG, "invalid variant fields");
+  if (v && !valid_variant(*v, dtype, false)) return fail(SPMM_ERR_INVALID_ARG, "invalid variant fields");
   return set_variant_in(A->vt, &A->nvt, N, dtype, v);
 }
 
@@ -797,7 +842,7 @@ spmm_status spmm_tile_set_bwd_variant(spmm_tile_t A, int64_t N, spmm_dtype dtype
   if (!A) return fail(SPMM_ERR_INVALID_ARG, "tile is null");
   if (N < 1) return fail(SPMM_ERR_INVALID_ARG, "N=%lld < 1", (long long)N);
   if (dtype != SPMM_F32 && dtype != SPMM_BF16) return fail(SPMM_ERR_INVALID_ARG, "unknown dtype");
-  if (v && !valid_variant(*v, dtype)) return fail(SPMM_ERR_INVALID_ARG, "invalid variant fields");
+  if (v && !valid_variant(*v, dtype, true)) return fail(SPMM_ERR_INVALID_ARG, "invalid variant fields");
   return set_variant_in(A->vtT, &A->nvtT, N, dtype, v);
 }
 
@@ -970,6 +1015,48 @@ spmm_status spmm_tile_accumulate(void* C, int64_t ldc, const void* Ptile, int64_
   return SPMM_OK;
 }
 
+// The fused backward (dA and dB in one pass over the transposed structure), then the
+// fix-up of the transposed plan's split rows (arguments already checked).
+static hipError_t launch_backward_fused(const spmm_tile_s* A, const FusedShape& fs, const void* dC, int64_t lddc,
+                                        const void* B, int64_t ldb, float* dA, void* dB, int64_t lddb, int64_t N,
+                                        DT dt, void* workspace, hipStream_t s) {
+  const spmm_csr& t = A->t[0];
+  spmm::BwdFusedParams F{};
+  F.rowptrT = A->rowptrT;
+  F.colindT = A->colindT;
+  F.perm = A->perm;
+  F.values = t.values;
+  F.dC = dC;
+  F.lddc = lddc;
+  F.B = B;
+  F.ldb = ldb;
+  F.dA = dA;
+  F.dB = dB;
+  F.lddb = lddb;
+  F.cols = t.cols;
+  F.N = N;
+  F.long_row = A->planT.long_row;
+  F.seg = A->planT.seg;
+  F.n_seg = A->planT.n_seg;
+  F.partial = static_cast<float*>(workspace);
+  F.ldp = (int64_t)partial_ld(N);
+  hipError_t e = spmm::launch_bwd_fused(F, fs.G, fs.V, fs.U, dt, s);
+  if (e != hipSuccess || A->planT.n_long == 0) return e;
+  spmm::FwdParams P{};
+  P.num_k = 1;
+  P.rows = t.cols;
+  P.N = N;
+  P.C = dB;
+  P.ldc = lddb;
+  P.seg = A->planT.seg;
+  P.n_seg = A->planT.n_seg;
+  P.lrow = A->planT.lrow;
+  P.n_long = A->planT.n_long;
+  P.partial = F.partial;
+  P.ldp = F.ldp;
+  return spmm::launch_fixup(P, fs.G, fs.V, dt, s);
+}
+
 spmm_status spmm_bwd(spmm_tile_t A, const void* dC, int64_t lddc, const void* B, int64_t ldb, int64_t N,
                      spmm_dtype dtype, float* dA_values, void* dB, int64_t lddb, void* workspace, size_t ws_bytes,
                      void* stream) {
@@ -999,6 +1086,17 @@ spmm_status spmm_bwd(spmm_tile_t A, const void* dC, int64_t lddc, const void* B,
   HIP_TRY(hipGetDevice(&dev));
   if (dev != A->device) return fail(SPMM_ERR_INVALID_ARG, "current device %d differs from the handle's %d", dev, A->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
+
+  // Both gradients, no column slices requested: one fused pass when a group covers N.
+  FusedShape fs{};
+  if (dA_values && dB && t.cols > 0 && !(A->bwd_slice > 0 && A->bwd_slice < N) &&
+      fused_shape(A, N, dt,
+                  reinterpret_cast<uintptr_t>(dC) | reinterpret_cast<uintptr_t>(B) | reinterpret_cast<uintptr_t>(dB) |
+                      (uintptr_t)(lddc * esize) | (uintptr_t)(ldb * esize) | (uintptr_t)(lddb * esize),
+                  &fs)) {
+    HIP_TRY(launch_backward_fused(A, fs, dC, lddc, B, ldb, dA_values, dB, lddb, N, dt, workspace, s));
+    return SPMM_OK;
+  }
 
   if (dA_values && t.nnz > 0) {
     spmm::SddmmParams P{};
@@ -1070,7 +1168,8 @@ spmm_status spmm_bwd(spmm_tile_t A, const void* dC, int64_t lddc, const void* B,
 }
 
 static spmm_status autotune_bwd_impl(spmm_tile_t A, int64_t N, spmm_dtype dtype, const void* dC, int64_t lddc,
-                                     void* dB, int64_t lddb, void* stream, spmm_variant* chosen) {
+                                     const void* B, int64_t ldb, float* dA, void* dB, int64_t lddb, void* stream,
+                                     spmm_variant* chosen) {
   if (!A) return fail(SPMM_ERR_INVALID_ARG, "tile is null");
   if (A->num_k != 1) return fail(SPMM_ERR_UNSUPPORTED, "the dB pass needs a single-tile handle");
   if (!A->has_t) return fail(SPMM_ERR_UNSUPPORTED, "handle was created without SPMM_TILE_TRANSPOSE");
@@ -1082,79 +1181,89 @@ static spmm_status autotune_bwd_impl(spmm_tile_t A, int64_t N, spmm_dtype dtype,
   if (!dC && A->rows > 0) return fail(SPMM_ERR_INVALID_ARG, "dC is null");
   if (!dB && t.cols > 0) return fail(SPMM_ERR_INVALID_ARG, "dB is null");
   if (lddc < N || lddb < N) return fail(SPMM_ERR_INVALID_ARG, "leading dimension < N");
+  const bool full = B != nullptr && dA != nullptr;  // time whole backward passes, fused shapes included
+  if (full && ldb < N) return fail(SPMM_ERR_INVALID_ARG, "ldb < N");
   if (lddc * esize >= ((int64_t)1 << 32)) return fail(SPMM_ERR_UNSUPPORTED, "lddc too large");
   if ((N + 63) / 64 > 65535) return fail(SPMM_ERR_UNSUPPORTED, "N too large for one launch");
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   if (dev != A->device) return fail(SPMM_ERR_INVALID_ARG, "current device differs from the handle's");
-  const uintptr_t a = reinterpret_cast<uintptr_t>(dC) | reinterpret_cast<uintptr_t>(dB) | (uintptr_t)(lddc * esize) |
-                      (uintptr_t)(lddb * esize);
-  spmm::Variant best_v = pick_variant(N, dt, a, t.cols);
-  if (t.cols > 0 && t.nnz > 0) {
+  uintptr_t a = reinterpret_cast<uintptr_t>(dC) | reinterpret_cast<uintptr_t>(dB) | (uintptr_t)(lddc * esize) |
+                (uintptr_t)(lddb * esize);
+  // Candidates: the dB pass's kernel variants (two-pass backward) and, when B and dA are
+  // given, fused shapes at the widest aligned vector width and at half and a quarter of it.
+  std::vector<spmm_variant> cand;
+  for (const auto& v : candidate_variants(N, dt, a, t.cols))
+    cand.push_back(spmm_variant{v.stream ? SPMM_KERNEL_STREAM : SPMM_KERNEL_ROWSPLIT, v.stream ? v.rows : v.G, v.V});
+  if (full) {
+    a |= reinterpret_cast<uintptr_t>(B) | (uintptr_t)(ldb * esize);
+    int vmax = (int)(16 / esize);
+    while (vmax > 1 && ((N % vmax) != 0 || (a % (uintptr_t)(vmax * esize)) != 0)) vmax /= 2;
+    for (int V = vmax; V >= 1 && V >= vmax / 4; V /= 2) {
+      if ((N % V) != 0) continue;
+      int G = 4;
+      while (G < 64 && (int64_t)G * V < N) G *= 2;
+      if ((int64_t)G * V >= N) cand.push_back(spmm_variant{SPMM_KERNEL_FUSED, G, V});
+    }
+  }
+  // Each candidate is timed through spmm_bwd itself with the candidate as the table's
+  // entry (3 calls after a warm-up call), so the choice measures exactly what later
+  // calls run; the entry found before tuning is restored if a call fails.
+  spmm_variant prev{SPMM_KERNEL_AUTO, 0, 0};
+  (void)spmm_tile_get_variant(A, N, dtype, 1, &prev);
+  spmm_variant best = cand.empty() ? spmm_variant{SPMM_KERNEL_AUTO, 0, 0} : cand[0];
+  if (t.cols > 0 && !cand.empty()) {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const std::vector<spmm::Variant> kv = candidate_variants(N, dt, a, t.cols);
+    const size_t wsb = bwd_workspace(A, N);
     void* ws = nullptr;
-    HIP_TRY(hipMalloc(&ws, bwd_workspace(A, N)));
+    HIP_TRY(hipMalloc(&ws, wsb > 0 ? wsb : 16));
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    spmm_status st = SPMM_OK;
-    float best = 1e30f;
+    float best_ms = 1e30f;
     auto run = [&]() -> spmm_status {
       HIP_TRY(hipEventCreate(&e0));
       HIP_TRY(hipEventCreate(&e1));
-      float* valuesT = reinterpret_cast<float*>(static_cast<char*>(ws) + bwd_partial_bytes(A, N));
-      HIP_TRY(spmm::launch_gather_values(A->perm, t.values, valuesT, t.nnz, s));
-      spmm::FwdParams P{};
-      P.t[0].rowptr = A->rowptrT;
-      P.t[0].colind = A->colindT;
-      P.t[0].values = valuesT;
-      P.t[0].B = dC;
-      P.t[0].ldb = lddc;
-      P.t[0].hot = dC;
-      P.t[0].ldh = lddc;
-      P.num_k = 1;
-      P.rows = t.cols;
-      P.N = N;
-      P.C = dB;
-      P.ldc = lddb;
-      P.long_row = A->planT.long_row;
-      P.seg = A->planT.seg;
-      P.n_seg = A->planT.n_seg;
-      P.lrow = A->planT.lrow;
-      P.n_long = A->planT.n_long;
-      P.partial = static_cast<float*>(ws);
-      P.ldp = (int64_t)partial_ld(N);
-      for (const auto& v : kv) {
-        HIP_TRY(spmm::launch_fwd(P, v, dt, s));
+      for (const auto& v : cand) {
+        spmm_status st = set_variant_in(A->vtT, &A->nvtT, N, dtype, &v);
+        if (st != SPMM_OK) return st;
+        auto call = [&]() {
+          return spmm_bwd(A, dC, lddc, full ? B : nullptr, ldb, N, dtype, full ? dA : nullptr, dB, lddb, ws, wsb,
+                          stream);
+        };
+        if ((st = call()) != SPMM_OK) return st;
         HIP_TRY(hipEventRecord(e0, s));
-        for (int r = 0; r < 3; ++r) HIP_TRY(spmm::launch_fwd(P, v, dt, s));
+        for (int r = 0; r < 3; ++r)
+          if ((st = call()) != SPMM_OK) return st;
         HIP_TRY(hipEventRecord(e1, s));
         HIP_TRY(hipEventSynchronize(e1));
         float ms = 0.0f;
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) {
-          best = ms;
-          best_v = v;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = v;
         }
       }
       return SPMM_OK;
     };
-    st = run();
+    spmm_status st = run();
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(s);
     (void)hipFree(ws);
-    if (st != SPMM_OK) return st;
+    if (st != SPMM_OK) {
+      (void)set_variant_in(A->vtT, &A->nvtT, N, dtype, prev.kind == SPMM_KERNEL_AUTO ? nullptr : &prev);
+      return st;
+    }
   }
-  spmm_variant out{best_v.stream ? SPMM_KERNEL_STREAM : SPMM_KERNEL_ROWSPLIT, best_v.stream ? best_v.rows : best_v.G,
-                   best_v.V};
-  spmm_status st = set_variant_in(A->vtT, &A->nvtT, N, dtype, &out);
-  if (st == SPMM_OK && chosen) *chosen = out;
+  spmm_status st = set_variant_in(A->vtT, &A->nvtT, N, dtype, best.kind == SPMM_KERNEL_AUTO ? nullptr : &best);
+  if (st == SPMM_OK && chosen) *chosen = best;
   return st;
 }
 
 spmm_status spmm_tile_autotune_bwd(spmm_tile_t A, int64_t N, spmm_dtype dtype, const void* dC, int64_t lddc,
-                                   void* dB, int64_t lddb, void* stream, spmm_variant* chosen) {
-  return spmm::guarded([&]() { return autotune_bwd_impl(A, N, dtype, dC, lddc, dB, lddb, stream, chosen); });
+                                   const void* B, int64_t ldb, float* dA, void* dB, int64_t lddb, void* stream,
+                                   spmm_variant* chosen) {
+  return spmm::guarded(
+      [&]() { return autotune_bwd_impl(A, N, dtype, dC, lddc, B, ldb, dA, dB, lddb, stream, chosen); });
 }
 
 }  // extern "C"

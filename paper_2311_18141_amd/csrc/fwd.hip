@@ -141,7 +141,10 @@ __global__ void __launch_bounds__(kBlock) fwd_stream(FwdParams P) {
   int32_t* s_koff = s_beg + 64 * K;               // [kk][lane]: offset of tile kk inside the row
   const int64_t row = r0 + lane;
   const bool inrow = lane < R && row < P.rows;
-  int32_t L = 0;
+  // A row's length over up to 16 k-tiles can pass 2^31: summed in 64 bits.  Streamed rows
+  // are at most long_row long (checked against 2^31 / 64 at creation), so the 64-lane
+  // prefix below and every in-row offset fit in 32 bits; offsets of split rows are never read.
+  int64_t L = 0;
   for (int kk = 0; kk < K; ++kk) {
     int k = kk + P.k_offset;
     if (k >= K) k -= K;
@@ -151,10 +154,10 @@ __global__ void __launch_bounds__(kBlock) fwd_stream(FwdParams P) {
       l = P.t[k].rowptr[row + 1] - b;
     }
     s_beg[kk * 64 + lane] = b;
-    s_koff[kk * 64 + lane] = L;
+    s_koff[kk * 64 + lane] = (int32_t)L;
     L += l;
   }
-  const int32_t Ls = (L > P.long_row) ? 0 : L;  // split rows are not streamed
+  const int32_t Ls = (L > P.long_row) ? 0 : (int32_t)L;  // split rows are not streamed
   int32_t incl = Ls;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -375,7 +378,42 @@ hipError_t launch_v(const FwdParams& P, const Variant& v, hipStream_t s) {
   }
 }
 
+template <typename E, int V>
+hipError_t launch_fixup_v(const FwdParams& P, int G, hipStream_t s) {
+  if (P.n_long == 0) return hipSuccess;
+  const int64_t windows = (P.N + (int64_t)G * V - 1) / ((int64_t)G * V);
+  const int64_t rows_blocks = (P.n_long * G + kBlock - 1) / kBlock;
+  dim3 grid((unsigned)rows_blocks, (unsigned)windows);
+  switch (G) {
+    case 4: hipLaunchKernelGGL((fwd_fixup<4, V, E>), grid, dim3(kBlock), 0, s, P); break;
+    case 8: hipLaunchKernelGGL((fwd_fixup<8, V, E>), grid, dim3(kBlock), 0, s, P); break;
+    case 16: hipLaunchKernelGGL((fwd_fixup<16, V, E>), grid, dim3(kBlock), 0, s, P); break;
+    case 32: hipLaunchKernelGGL((fwd_fixup<32, V, E>), grid, dim3(kBlock), 0, s, P); break;
+    case 64: hipLaunchKernelGGL((fwd_fixup<64, V, E>), grid, dim3(kBlock), 0, s, P); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_fixup(const FwdParams& P, int G, int V, DT dt, hipStream_t s) {
+  if (dt == DT::F32) {
+    switch (V) {
+      case 1: return launch_fixup_v<F32E, 1>(P, G, s);
+      case 2: return launch_fixup_v<F32E, 2>(P, G, s);
+      case 4: return launch_fixup_v<F32E, 4>(P, G, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (V) {
+    case 1: return launch_fixup_v<BF16E, 1>(P, G, s);
+    case 2: return launch_fixup_v<BF16E, 2>(P, G, s);
+    case 4: return launch_fixup_v<BF16E, 4>(P, G, s);
+    case 8: return launch_fixup_v<BF16E, 8>(P, G, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_fwd(const FwdParams& P, Variant v, DT dt, hipStream_t s) {
   if (dt == DT::F32) {

@@ -208,6 +208,38 @@ struct SddmmParams {
   int64_t c_begin, c_end;  // column range of this launch
   int accumulate;          // add to dA (later slices)
 };
+// Fused backward over the transposed structure (one pass gathers each dC row once for
+// both gradients): for every row j of A^T (column j of A), with B[j, :] held in
+// registers, each entry q (original row i = colindT[q], position p = perm[q]) gives
+//   dA[p] = <dC[i, :], B[j, :]>   and   dB[j, :] += values[p] * dC[i, :].
+// Rows of A^T longer than long_row are cut into the transposed plan's units, whose dB
+// partial rows go to `partial` and are summed by the forward's fix-up.
+struct BwdFusedParams {
+  const int32_t* rowptrT;
+  const int32_t* colindT;
+  const int32_t* perm;
+  const float* values;     // A's values in A's CSR order (read through perm)
+  const void* dC;          // rows x N, FP32 or BF16 as the launch's dtype
+  int64_t lddc;
+  const void* B;           // cols x N
+  int64_t ldb;
+  float* dA;               // nnz, A's CSR order
+  void* dB;                // cols x N
+  int64_t lddb;
+  int64_t cols;            // rows of A^T
+  int64_t N;
+  int32_t long_row;
+  const Seg* seg;          // transposed plan's split units
+  int64_t n_seg;
+  float* partial;          // n_seg x ldp
+  int64_t ldp;
+};
+// G lanes per row of A^T, V columns per lane and load (G * V >= N), U entries in flight.
+hipError_t launch_bwd_fused(const BwdFusedParams& P, int G, int V, int U, DT dt, hipStream_t s);
+// The forward's split-row fix-up alone (sums each split row's unit partials into C),
+// with G * V columns per group.
+hipError_t launch_fixup(const FwdParams& P, int G, int V, DT dt, hipStream_t s);
+
 // out[q] = values[perm[q]] for q < nnz.
 hipError_t launch_gather_values(const int32_t* perm, const float* values, float* out, int64_t nnz, hipStream_t s);
 // G lanes per group, V columns per lane and load, U non-zeros per group.

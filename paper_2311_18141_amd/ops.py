@@ -136,7 +136,8 @@ def spmm_tile_export_transpose(tile: Tile, stream=None) -> Tuple[torch.Tensor, t
     return rpT, ciT, perm
 
 
-KERNELS = {"auto": _lib.SPMM_KERNEL_AUTO, "rowsplit": _lib.SPMM_KERNEL_ROWSPLIT, "stream": _lib.SPMM_KERNEL_STREAM}
+KERNELS = {"auto": _lib.SPMM_KERNEL_AUTO, "rowsplit": _lib.SPMM_KERNEL_ROWSPLIT, "stream": _lib.SPMM_KERNEL_STREAM,
+           "fused": _lib.SPMM_KERNEL_FUSED}
 
 
 def spmm_tile_set_variant(tile: Tile, N: int, dtype=torch.float32, kind: Optional[str] = "auto",
@@ -170,8 +171,11 @@ def spmm_tile_get_variant(tile: Tile, N: int, dtype=torch.float32, bwd: bool = F
 
 
 def spmm_tile_autotune_bwd(tile: Tile, dC: torch.Tensor, dB: Optional[torch.Tensor] = None,
+                           B: Optional[torch.Tensor] = None, dA: Optional[torch.Tensor] = None,
                            stream: Optional[torch.cuda.Stream] = None) -> dict:
-    """Time the dB pass's variants on this dC (dB is overwritten); keep the fastest."""
+    """Time the backward's variants on these operands and keep the fastest (dB, and dA when
+    given, are overwritten).  With B given the whole backward is timed, fused shapes included;
+    without it only the dB pass's kernels."""
     dt = dC.dtype
     if dt not in _DTYPES:
         raise ValueError("dC must be float32 or bfloat16")
@@ -182,8 +186,19 @@ def spmm_tile_autotune_bwd(tile: Tile, dC: torch.Tensor, dB: Optional[torch.Tens
         dB = torch.empty(tile.cols[0], N, dtype=dt, device=dC.device)
     if dB.dtype != dt or dB.shape != (tile.cols[0], N):
         raise ValueError("dB must be %s of shape (%d, %d)" % (dt, tile.cols[0], N))
+    ldb = 0
+    if B is not None:
+        if B.dtype != dt or B.shape != (tile.cols[0], N):
+            raise ValueError("B must be %s of shape (%d, %d)" % (dt, tile.cols[0], N))
+        ldb = _row_major_ld(B, "B")
+        if dA is None:
+            dA = torch.empty(tile.nnz[0], dtype=torch.float32, device=dC.device)
+        if dA.dtype != torch.float32 or dA.numel() < tile.nnz[0]:
+            raise ValueError("dA must be float32 with nnz entries")
     out = SpmmVariant()
     check(lib().spmm_tile_autotune_bwd(tile.handle, N, _DTYPES[dt], dC.data_ptr(), _row_major_ld(dC, "dC"),
+                                       B.data_ptr() if B is not None else None, ldb,
+                                       dA.data_ptr() if B is not None else None,
                                        dB.data_ptr(), _row_major_ld(dB, "dB"), _stream_ptr(stream), ctypes.byref(out)))
     inv = {v: k for k, v in KERNELS.items()}
     return {"kind": inv[out.kind], "lanes": out.lanes, "vec": out.vec}

@@ -69,7 +69,8 @@ def _tiles(n=1, cols=10, nnz=5, ptr=0x1000):
 @pytest.mark.parametrize("case,expect", [
     ("null_out", 1), ("neg_rows", 1), ("huge_rows", 1), ("k0", 1), ("k17", 1), ("null_tiles", 1),
     ("neg_cols", 1), ("neg_nnz", 1), ("big_nnz", 3), ("cap_nnz", 3), ("null_rowptr", 1), ("null_colind", 1),
-    ("bad_flags", 1), ("transpose_k2", 3), ("neg_long_row", 1), ("hot_rows_m2", 1), ("hot_rows_huge", 1),
+    ("bad_flags", 1), ("transpose_k2", 3), ("neg_long_row", 1), ("huge_long_row", 1), ("hot_rows_m2", 1),
+    ("hot_rows_huge", 1),
 ])
 def test_create_argument_errors(case, expect):
     L = _lib.lib()
@@ -110,6 +111,8 @@ def test_create_argument_errors(case, expect):
         opts.flags = _lib.SPMM_TILE_TRANSPOSE
     elif case == "neg_long_row":
         opts.long_row = -3
+    elif case == "huge_long_row":  # 64 unsplit rows of this length would overflow a 32-bit prefix sum
+        opts.long_row = (1 << 31) // 64
     elif case == "hot_rows_m2":
         opts.hot_rows = -2
     elif case == "hot_rows_huge":
@@ -233,7 +236,7 @@ def test_bwd_variant_argument_errors():
     assert L.spmm_tile_set_bwd_variant(None, 64, 0, ctypes.byref(v)) == 1
     assert L.spmm_tile_get_variant(None, 64, 0, 0, ctypes.byref(v)) == 1
     assert L.spmm_tile_get_variant(None, 64, 0, 1, None) == 1
-    assert L.spmm_tile_autotune_bwd(None, 64, 0, 0x1000, 64, 0x2000, 64, None, None) == 1
+    assert L.spmm_tile_autotune_bwd(None, 64, 0, 0x1000, 64, None, 0, None, 0x2000, 64, None, None) == 1
 
 
 def test_trace_ranges_switch_on_without_changing_results():

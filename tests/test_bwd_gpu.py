@@ -324,6 +324,10 @@ def test_autotune_bwd(dtype):
     dCd, Bd = G.dense_dev(dC, tdt), G.dense_dev(B, tdt)
     chosen = ops.spmm_tile_autotune_bwd(tile, dCd)
     assert chosen["kind"] in ("stream", "rowsplit") and chosen["vec"] >= 1
+    # with B the whole backward is timed, fused shapes included
+    chosen_full = ops.spmm_tile_autotune_bwd(tile, dCd, B=Bd)
+    assert chosen_full["kind"] in ("stream", "rowsplit", "fused") and chosen_full["vec"] >= 1
+    assert ops.spmm_tile_get_variant(tile, N, tdt, bwd=True) == chosen_full
     dA, dB = ops.spmm_bwd(tile, dCd, Bd)
     torch.cuda.synchronize()
     rA, _ = oracle.sddmm(A.rowptr, A.colind, dC, B)
@@ -334,7 +338,81 @@ def test_autotune_bwd(dtype):
     else:
         got = dB.cpu().view(torch.int16).numpy().view(np.uint16)
         assert np.array_equal(got, oracle.f32_to_bf16(rB.astype(np.float32)))
-    ops.spmm_tile_set_bwd_variant(tile, N, tdt, None)          # cleared: the fixed rule again
-    _, dB2 = ops.spmm_bwd(tile, dCd, Bd, want_dA=False)
+    ops.spmm_tile_set_bwd_variant(tile, N, tdt, None)          # cleared: the library rule again
+    dA2, dB2 = ops.spmm_bwd(tile, dCd, Bd)
     torch.cuda.synchronize()
-    assert torch.equal(dB, dB2)
+    assert torch.equal(dA, dA2) and torch.equal(dB, dB2)
+
+
+FUSED_SHAPES = {"f32": [(4, 1), (8, 2), (16, 4), (32, 2), (64, 1), (64, 4)],
+                "bf16": [(8, 1), (4, 2), (8, 8), (16, 4), (32, 2), (32, 4), (64, 2), (64, 8)]}
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("N", [1, 3, 36, 64, 100])
+def test_fused_backward_integer_exact(N, dtype):
+    """The fused backward (one pass over A^T for dA and dB) at every group shape that covers N,
+    split rows of A^T included: dA and dB exact on integer data (dB rounded once for BF16), as the
+    two-pass form's."""
+    rng = _rng(500 + N)
+    M, K = 3000, 1200
+    L = rng.integers(0, 20, size=M)
+    A = synth.random_csr(M, K, L, rng, "int8")
+    hub = rng.choice(M, size=400, replace=False)          # column 7 is used by >= 400 rows: split in A^T
+    cols = [np.union1d(A.colind[A.rowptr[i]:A.rowptr[i + 1]], [7]) if i in set(hub) else
+            A.colind[A.rowptr[i]:A.rowptr[i + 1]] for i in range(M)]
+    lengths = np.array([len(c) for c in cols])
+    A = synth.CSR(M, K, synth.rowptr_from_lengths(lengths), np.concatenate(cols).astype(np.int32),
+                  rng.integers(-8, 9, size=int(lengths.sum())).astype(np.float32))
+    small = dtype == "bf16"      # BF16: |dC|, |B| <= 4 keeps every dot product exact
+    B = synth.dense(K, N, rng, "int8")
+    dC = synth.dense(M, N, rng, "int8")
+    if small:
+        B, dC = np.clip(B, -4, 4), np.clip(dC, -4, 4)
+    tdt = torch.float32 if dtype == "f32" else torch.bfloat16
+    tile = G.make_tile([A], transpose=True, long_row=128, segment=32)
+    assert tile.stats()["long_rows_t"] > 0
+    rA, _ = oracle.sddmm(A.rowptr, A.colind, dC, B)
+    rB, _ = oracle.spmm_t(A.rowptr, A.colind, A.values, K, dC)
+    assert np.abs(rB).max() < 2 ** 24 and np.abs(rA).max() < 2 ** 24
+    want_B = (rB if dtype == "f32" else oracle.f32_to_bf16(rB.astype(np.float32)))
+    Bd, dCd = G.dense_dev(B, tdt), G.dense_dev(dC, tdt)
+    ops.spmm_tile_set_bwd_variant(tile, N, tdt, "rowsplit", 0, 0)
+    _, dB_two = ops.spmm_bwd(tile, dCd, Bd)
+    ran = 0
+    for lanes, vec in FUSED_SHAPES[dtype]:
+        if N % vec or lanes * vec < N:
+            continue
+        G.note("fused backward N=%d %s lanes=%d vec=%d" % (N, dtype, lanes, vec))
+        ops.spmm_tile_set_bwd_variant(tile, N, tdt, "fused", lanes, vec)
+        dA, dB = ops.spmm_bwd(tile, dCd, Bd)
+        torch.cuda.synchronize()
+        ran += 1
+        assert np.array_equal(dA.cpu().numpy().astype(np.float64), rA), (lanes, vec)
+        if dtype == "f32":
+            assert np.array_equal(dB.cpu().numpy().astype(np.float64), want_B), (lanes, vec)
+        else:
+            assert np.array_equal(dB.cpu().view(torch.int16).numpy().view(np.uint16), want_B), (lanes, vec)
+        assert torch.equal(dB, dB_two), (lanes, vec)
+    assert ran > 0
+
+
+def test_fused_backward_choice():
+    """Without an entry both gradients come from the fused pass whenever a group covers N: the
+    results match the two-pass form within FP32 order (dA) and bit for bit (dB, same vector
+    width); with a column slice set, or N too wide for one group, the two-pass form runs."""
+    G.note("fused backward choice")
+    rng = _rng(510)
+    A = synth.powerlaw_csr(1 << 13, 1 << 13, 16, 2048, seed=13)
+    for N, slice_ in [(128, 0), (128, 32), (260, 0)]:
+        B = synth.dense(A.cols, N, rng, "normal")
+        dC = synth.dense(A.rows, N, rng, "normal")
+        tile = G.make_tile([A], transpose=True, bwd_slice=slice_)
+        Bd, dCd = G.dense_dev(B), G.dense_dev(dC)
+        dA, dB = ops.spmm_bwd(tile, dCd, Bd)
+        torch.cuda.synchronize()
+        rA, SA = oracle.sddmm(A.rowptr, A.colind, dC, B)
+        st = compare.fp32_stats(dA.cpu().numpy(), rA, SA, n_terms=np.full(A.nnz, N))
+        assert compare.fp32_ok(st), (N, slice_, st)
+        rB, SB = oracle.spmm_t(A.rowptr, A.colind, A.values, A.cols, dC)
+        G.assert_fp32_close(G.host_f32(dB), rB, SB, np.bincount(A.colind, minlength=A.cols), what="dB")
