@@ -3,12 +3,18 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 
 A step is one pass of the hot path over one batch of synthetic input that is
-already resident in HBM.  The default workload is one GPU's share of a 4 x 4
-stationary-C SpMM (Algorithm 2): row block 0 of an R-MAT scale-22, edge-factor-16
-matrix (Graph500 quadrant probabilities, duplicates merged, U[-1,1) FP32 values)
-times dense B_k of 1,048,576 x 128 FP32, accumulated over its 4 k-tiles into a
-1,048,576 x 128 FP32 C tile that is written once.  Other workloads:
+already resident in HBM.  The default workload is the forward and backward of one
+GNN-shaped layer: a 2,097,152^2 sparse A with heavy-tailed row degrees (Pareto(2.1)
+with mean 32 and longest row 65,536, uniform distinct columns, values N(0,1)/sqrt(deg)),
+dense B and dC of 2,097,152 x 128 FP32 N(0,1): C = A B, dA = the sampled dense-dense
+product on A's pattern, dB = A^T dC (three passes of 2 nnz N flops).  The same step with
+B, C, dC and dB in BF16 is reported beside it, and the error of every result against
+the FP64 oracle on a sample.  Other workloads:
 
+    rmat22_rowblock0_4x4_n128  one GPU's share of a 4 x 4 stationary-C SpMM (Algorithm 2):
+                            row block 0 of an R-MAT scale-22, edge-factor-16 matrix (Graph500
+                            quadrant probabilities, duplicates merged, U[-1,1) FP32 values) times
+                            B_k of 1,048,576 x 128 FP32 over its 4 k-tiles, C written once
     er4096_n32              4096^2 uniform tile, 16 non-zeros per row, N = 32, forward
     powerlaw2m_n128_fwdbwd  2,097,152^2 heavy-tailed rows (mean 32, max 65,536), N = 128,
                             forward + dA (sampled dense-dense product) + dB = A^T dC
@@ -57,9 +63,9 @@ AUTOTUNE = False
 PINNED = {
     "rmat22_rowblock0_4x4_n128": {"variant": ("stream", 64, 2), "long_row": 128, "segment": 64},
     "powerlaw2m_n128_fwdbwd": {"variant": ("rowsplit", 64, 1), "long_row": 1024, "segment": 512,
-                               "bwd_variant": ("rowsplit", 64, 1), "sddmm": (8, 4)},
+                               "bwd_variant": ("fused", 32, 4)},
     "powerlaw2m_n128_fwdbwd_bf16": {"variant": ("rowsplit", 64, 2), "long_row": 512, "segment": 256,
-                                    "bwd_variant": ("rowsplit", 64, 2), "sddmm": (8, 2)},
+                                    "bwd_variant": ("fused", 16, 8)},
     "rmat23_n256_bf16": {"variant": ("rowsplit", 64, 4), "long_row": 128, "segment": 64},
     "rmat23_n256_f32": {"variant": ("stream", 64, 2), "long_row": 128, "segment": 64},
 }
@@ -179,6 +185,22 @@ class Workload:
         return {}
 
 
+REL_DEFINITION = ("rel = |x - x64| / max(|x64|, 2^-20 S); rel_to_scale = |x - x64| / S, S = sum |a||b|; x64 = the "
+                  "FP64 oracle on the FP32 operands (total error) or on their BF16 roundings (the kernels' own error)")
+
+
+def _err_stats(got, ref, S):
+    """Max / mean relative error of one sampled result against the oracle."""
+    from oracle import compare
+    g = got.float().cpu().numpy().astype(np.float64)
+    rel = compare.relative_stats(g, ref, S)
+    sc = compare.fp32_stats(g, ref, S)
+    return {"max_rel": float("%.4g" % rel["max_rel"]), "mean_rel": float("%.4g" % rel["mean_rel"]),
+            "max_rel_to_scale": float("%.4g" % sc["max_rel_to_scale"]),
+            "mean_rel_to_scale": float("%.4g" % sc["mean_rel_to_scale"]),
+            "nonfinite": rel["nonfinite"], "entries": int(g.size)}
+
+
 def _fwd_bytes(tiles, N, esize):
     b = 0
     for t in tiles:
@@ -241,7 +263,57 @@ class TileRowForward(Workload):
         ops.spmm_fwd(self.tile, self.B, C=self.C, workspace=self.ws)
 
     def extra(self, kernel_ms):
-        return {"cache_gather": gather_ceiling_report(self.gather_items, kernel_ms)}
+        out = {"cache_gather": gather_ceiling_report(self.gather_items, kernel_ms)}
+        if self.dtype == "bf16":
+            out["f32"] = self._f32_companion(kernel_ms)
+        return out
+
+    def _f32_companion(self, bf16_ms, steps=10):
+        """The same forward with FP32 B and C (the draws before rounding) on the same handle."""
+        import torch
+        from paper_2311_18141_amd import ops
+        self.Bf = [torch.from_numpy(b).to(self.B[0].device) for b in self.Bh]
+        self.Cf = torch.empty(self.tiles[0].rows, self.N, device=self.B[0].device)
+        pin = PINNED.get(self.name.replace("_bf16", "_f32"))
+        cfg = None
+        if pin and not AUTOTUNE:
+            kind, lanes, vec = pin["variant"]
+            ops.spmm_tile_set_variant(self.tile, self.N, torch.float32, kind, lanes, vec)
+            cfg = {"kind": kind, "lanes": lanes, "vec": vec, "pinned": True}
+        ws = self.tile.workspace(self.N)
+        step = lambda: ops.spmm_fwd(self.tile, self.Bf, C=self.Cf, workspace=ws)  # noqa: E731
+        for _ in range(2):
+            step()
+        ms = Batched._time(step, steps)
+        return {"ms_per_step": round(ms, 5), "value": round(self.flops / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+                "bf16_speedup": round(ms / bf16_ms, 3), "variant": cfg, "steps": steps,
+                "note": "same handle and draws as the BF16 step, B and C in FP32"}
+
+    def accuracy(self):
+        """Max and mean relative error of C against the FP64 oracle on 2,000 random rows and the
+        longest row, after the timed region: against the oracle on the FP32 draws of B (total
+        error) and, for BF16 storage, on their BF16 roundings (the kernels' own error)."""
+        import torch
+        import oracle
+        lens = sum(t.row_lengths() for t in self.tiles)
+        rng = np.random.Generator(np.random.PCG64(17))
+        rows = np.unique(np.concatenate([rng.choice(self.tiles[0].rows, 2000, replace=False),
+                                         [int(np.argmax(lens))]]))
+        r_t = torch.from_numpy(rows).to(self.C.device)
+        csr = [(t.rowptr, t.colind, t.values) for t in self.tiles]
+        torch.cuda.synchronize()
+        out = {"sample": "%d rows of C" % len(rows), "definition": REL_DEFINITION}
+        rC, SC = oracle.spmm(csr, self.Bh, rows=rows)
+        if self.dtype == "f32":
+            out["f32"] = {"C": _err_stats(self.C[r_t], rC, SC)}
+            return out
+        Bt = [oracle.bf16_to_f32(oracle.f32_to_bf16(b)) for b in self.Bh]
+        rCt, SCt = oracle.spmm(csr, Bt, rows=rows)
+        out["bf16_vs_f32_operands"] = {"C": _err_stats(self.C[r_t], rC, SC)}
+        out["bf16_vs_bf16_operands"] = {"C": _err_stats(self.C[r_t], rCt, SCt)}
+        if hasattr(self, "Cf"):
+            out["f32"] = {"C": _err_stats(self.Cf[r_t], rC, SC)}
+        return out
 
     def cpu_sample(self):
         import oracle
@@ -303,8 +375,8 @@ class ForwardBackward(Workload):
         # the dB pass (forward kernels over the transpose) has its own variant
         if AUTOTUNE:
             t0 = time.time()
-            chosen = ops.spmm_tile_autotune_bwd(self.tile, self.dC, self.dB)
-            _log("%s: dB pass autotuned in %.1f s: %s" % (self.name, time.time() - t0, chosen))
+            chosen = ops.spmm_tile_autotune_bwd(self.tile, self.dC, self.dB, B=self.B, dA=self.dA)
+            _log("%s: backward autotuned in %.1f s: %s" % (self.name, time.time() - t0, chosen))
             self.config["bwd_variant"] = chosen
         elif PINNED.get(self.name, {}).get("bwd_variant"):
             kind, lanes, vec = PINNED[self.name]["bwd_variant"]
@@ -316,8 +388,14 @@ class ForwardBackward(Workload):
             ops.spmm_tile_set_sddmm_variant(self.tile, self.N, sd[0], sd[1])
             self.config["sddmm"] = {"lanes": sd[0], "nnz_per_group": sd[1], "pinned": True}
         fk = "fwd_main" if (self.config["variant"] or {}).get("kind") == "rowsplit" else "fwd_stream"
-        bk = "fwd_main" if (self.config.get("bwd_variant") or {}).get("kind") == "rowsplit" else "fwd_stream"
-        self.kernel = "spmm_fwd + spmm_bwd (%s, fwd_fixup, sddmm_kernel, gather_values, %s on the transpose)" % (fk, bk)
+        bkind = (self.config.get("bwd_variant") or {}).get("kind")
+        self.fused = bkind == "fused"
+        if self.fused:
+            self.kernel = "spmm_fwd + spmm_bwd (%s, fwd_fixup, bwd_fused over the transpose)" % fk
+        else:
+            bk = "fwd_main" if bkind == "rowsplit" else "fwd_stream"
+            self.kernel = ("spmm_fwd + spmm_bwd (%s, fwd_fixup, sddmm_kernel, gather_values, %s on the transpose)"
+                           % (fk, bk))
         self.wsf = self.tile.workspace(self.N, "fwd")
         self.wsb = self.tile.workspace(self.N, "bwd")
         A, N = self.A, self.N
@@ -327,12 +405,15 @@ class ForwardBackward(Workload):
         sddmm = 4 * A.nnz + 4 * (A.rows + 1) + e * A.rows * N + e * A.cols * N + 4 * A.nnz
         dB = 4 * (A.cols + 1) + 12 * A.nnz + e * A.rows * N + e * A.cols * N
         self.alg_bytes = float(fwd + sddmm + dB)
-        # gathers: the forward and the SDDMM read a B row per non-zero, dB a dC row per
-        # non-zero, and the value gather one 4-byte value per non-zero at random (timed as a
-        # 16-byte row, the probe's smallest, from a table of the values' size)
+        # gathers: the forward reads a B row per non-zero; the fused backward a dC row per
+        # non-zero (the two-pass form: the SDDMM a B row and the dB pass a dC row per non-zero);
+        # both backward forms read one 4-byte value per non-zero at random (timed as a 16-byte
+        # row, the probe's smallest, from a table of the values' size)
         row = e * N
-        self.gather_items = [(float(A.nnz) * row, A.cols * row, row), (float(A.nnz) * row, A.cols * row, row),
-                             (float(A.nnz) * row, A.rows * row, row), (float(A.nnz) * 16, 4 * A.nnz, 16)]
+        self.gather_items = [(float(A.nnz) * row, A.cols * row, row), (float(A.nnz) * row, A.rows * row, row),
+                             (float(A.nnz) * 16, 4 * A.nnz, 16)]
+        if not self.fused:
+            self.gather_items.append((float(A.nnz) * row, A.cols * row, row))
         st = self.tile.stats()
         self.config = dict(self.config, nnz=A.nnz, rows=A.rows, N=N,
                            tile_stats={k: st[k] for k in ("max_row", "empty_rows", "long_rows", "segments",
@@ -344,8 +425,97 @@ class ForwardBackward(Workload):
         ops.spmm_fwd(self.tile, [self.B], C=self.C, workspace=self.wsf)
         ops.spmm_bwd(self.tile, self.dC, self.B, dA=self.dA, dB=self.dB, workspace=self.wsb)
 
+    def _pass_ms(self, B, C, dC, dA, dB, reps=10):
+        """Mean time of the forward call and of the backward call, each timed on its own."""
+        from paper_2311_18141_amd import ops
+        f = Batched._time(lambda: ops.spmm_fwd(self.tile, [B], C=C, workspace=self.wsf), reps)
+        b = Batched._time(lambda: ops.spmm_bwd(self.tile, dC, B, dA=dA, dB=dB, workspace=self.wsb), reps)
+        return {"fwd_ms": round(f, 4), "bwd_ms": round(b, 4)}
+
     def extra(self, kernel_ms):
-        return {"cache_gather": gather_ceiling_report(self.gather_items, kernel_ms)}
+        out = {"cache_gather": gather_ceiling_report(self.gather_items, kernel_ms),
+               "passes": self._pass_ms(self.B, self.C, self.dC, self.dA, self.dB)}
+        if self.dtype == "f32":
+            out["bf16"] = self._bf16_companion(kernel_ms)
+        return out
+
+    def _bf16_companion(self, f32_ms, steps=20):
+        """The same step with B, C, dC and dB in BF16 (RNE of the FP32 draws; FP32 accumulation,
+        dA in FP32) on the same handle, with the BF16 workload's pinned kernel shapes."""
+        import torch
+        from paper_2311_18141_amd import ops
+        bf = torch.bfloat16
+        self.Bb, self.dCb = self.B.to(bf), self.dC.to(bf)
+        self.Cb = torch.empty(self.A.rows, self.N, dtype=bf, device=self.B.device)
+        self.dBb = torch.empty_like(self.Bb)
+        self.dAb = torch.empty_like(self.dA)
+        pin = PINNED.get(self.name + "_bf16", {})
+        cfg = {}
+        if not AUTOTUNE and pin:
+            kind, lanes, vec = pin["variant"]
+            ops.spmm_tile_set_variant(self.tile, self.N, bf, kind, lanes, vec)
+            kind, lanes, vec = pin["bwd_variant"]
+            ops.spmm_tile_set_bwd_variant(self.tile, self.N, bf, kind, lanes, vec)
+            cfg = {"variant": pin["variant"], "bwd_variant": pin["bwd_variant"], "pinned": True}
+        else:
+            cfg["variant"] = ops.spmm_tile_autotune(self.tile, [self.Bb], self.Cb, tune_plan=False)
+            cfg["bwd_variant"] = ops.spmm_tile_autotune_bwd(self.tile, self.dCb, self.dBb, B=self.Bb, dA=self.dAb)
+        self.wsf = self.tile.workspace(self.N, "fwd")
+        self.wsb = self.tile.workspace(self.N, "bwd")
+
+        def step():
+            ops.spmm_fwd(self.tile, [self.Bb], C=self.Cb, workspace=self.wsf)
+            ops.spmm_bwd(self.tile, self.dCb, self.Bb, dA=self.dAb, dB=self.dBb, workspace=self.wsb)
+
+        for _ in range(3):
+            step()
+        ms = Batched._time(step, steps)
+        return {"ms_per_step": round(ms, 5), "value": round(self.flops / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+                "speedup_vs_f32": round(f32_ms / ms, 3), "kernels": cfg, "steps": steps,
+                "passes": self._pass_ms(self.Bb, self.Cb, self.dCb, self.dAb, self.dBb),
+                "note": "same handle and inputs as the FP32 step, B / C / dC / dB stored in BF16"}
+
+    def accuracy(self):
+        """Max and mean relative error of C, dA and dB against the FP64 oracle on a sample (2,000
+        random rows of C with all their dA entries, 2,000 random rows of dB, plus the longest row
+        and the most used column), after the timed region.  FP32 step: against the oracle on the
+        FP32 operands.  BF16 companion: against the oracle on the FP32 operands (total error) and
+        on the BF16-rounded operands (the kernels' own error)."""
+        import torch
+        import oracle
+        A = self.A
+        rng = np.random.Generator(np.random.PCG64(17))
+        lens = A.row_lengths()
+        cnt = np.bincount(A.colind, minlength=A.cols)
+        rows = np.unique(np.concatenate([rng.choice(A.rows, 2000, replace=False), [int(np.argmax(lens))]]))
+        cols = np.unique(np.concatenate([rng.choice(A.cols, 2000, replace=False), [int(np.argmax(cnt))]]))
+        ents = np.concatenate([np.arange(A.rowptr[r], A.rowptr[r + 1], dtype=np.int64) for r in rows])
+        dev = self.C.device
+        r_t = torch.from_numpy(rows).to(dev)
+        c_t = torch.from_numpy(cols).to(dev)
+        e_t = torch.from_numpy(ents).to(dev)
+
+        def one(C, dA, dB, Bh, dCh):
+            rC, SC = oracle.spmm([(A.rowptr, A.colind, A.values)], [Bh], rows=rows)
+            rA, SA = oracle.sddmm(A.rowptr, A.colind, dCh, Bh, entries=ents)
+            rB, SB = oracle.spmm_t(A.rowptr, A.colind, A.values, A.cols, dCh, out_rows=cols)
+            return {name: _err_stats(got, ref, S)
+                    for name, got, ref, S in (("C", C[r_t], rC, SC), ("dA", dA[e_t], rA, SA), ("dB", dB[c_t], rB, SB))}
+
+        torch.cuda.synchronize()
+        out = {"sample": "%d rows of C (%d dA entries), %d rows of dB" % (len(rows), len(ents), len(cols)),
+               "definition": REL_DEFINITION}
+        Bt = oracle.bf16_to_f32(oracle.f32_to_bf16(self.Bh))
+        dCt = oracle.bf16_to_f32(oracle.f32_to_bf16(self.dCh))
+        if self.dtype == "f32":
+            out["f32"] = one(self.C, self.dA, self.dB, self.Bh, self.dCh)
+            if hasattr(self, "Cb"):
+                out["bf16_vs_f32_operands"] = one(self.Cb, self.dAb, self.dBb, self.Bh, self.dCh)
+                out["bf16_vs_bf16_operands"] = one(self.Cb, self.dAb, self.dBb, Bt, dCt)
+        else:
+            out["bf16_vs_f32_operands"] = one(self.C, self.dA, self.dB, self.Bh, self.dCh)
+            out["bf16_vs_bf16_operands"] = one(self.C, self.dA, self.dB, Bt, dCt)
+        return out
 
     def cpu_sample(self):
         import oracle
@@ -711,10 +881,51 @@ class CopyCalibration(Workload):
         return 0.0, dt, "numpy copy of 256 MiB (%.0f)" % float(y[0])
 
 
+class GatherCalibration(Workload):
+    """spmm_gather_probe over a table of known size: n random whole rows, every byte of each
+    row read once (plus the 4-byte index), so the bytes a counter should see are known.  Used to
+    calibrate the HBM counters for gathers of the row widths the kernels issue."""
+
+    def __init__(self, row_bytes, table_mib, n):
+        self.row_bytes, self.table_mib, self.n = row_bytes, table_mib, n
+        self.name = "gather_%db_%dmib" % (row_bytes, table_mib)
+        self.kernel = "spmm_gather_probe (probe_gather_kernel)"
+        self.config = {"workload": self.name, "row_bytes": row_bytes, "table_bytes": table_mib << 20, "rows_gathered": n}
+
+    def setup(self):
+        import torch
+        dev = "cuda:0"
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(11)
+        size = self.table_mib << 20
+        self.table = torch.randint(-(1 << 31), (1 << 31) - 1, (size // 4,), dtype=torch.int32, device=dev,
+                                   generator=gen)
+        self.idx = torch.randint(0, size // self.row_bytes, (self.n,), dtype=torch.int32, device=dev, generator=gen)
+        self.out = torch.empty(1, dtype=torch.int32, device=dev)
+        self.flops = 0.0
+        self.alg_bytes = float(self.n) * (self.row_bytes + 4)
+        self.metric = "gathered GB/s"
+
+    def step(self):
+        from paper_2311_18141_amd import ops
+        ops.spmm_gather_probe(self.table, self.row_bytes, self.idx, self.out)
+
+    def cpu_sample(self):
+        t = self.table[: 1 << 20].cpu().numpy()
+        i = self.idx[: 1 << 20].cpu().numpy() % (t.size * 4 // self.row_bytes)
+        t0 = time.perf_counter()
+        x = np.bitwise_xor.reduce(t.view(np.uint8).reshape(-1, self.row_bytes)[i].view(np.uint32).ravel())
+        dt = time.perf_counter() - t0
+        return 0.0, dt, "numpy gather of 2^20 rows (xor %d)" % int(x)
+
+
 def workloads():
     import synth
     return {
         "copy_1gib": lambda: CopyCalibration(),
+        "gather_512b_4096mib": lambda: GatherCalibration(512, 4096, 1 << 23),
+        "gather_128b_4096mib": lambda: GatherCalibration(128, 4096, 1 << 25),
+        "gather_16b_4096mib": lambda: GatherCalibration(16, 4096, 1 << 26),
         "stationary_a_rmat22_tile00_n128x4": lambda: StationaryA(
             "stationary_a_rmat22_tile00_n128x4",
             {"workload": "stationary_a_rmat22_tile00_n128x4", "matrix": "tile (0,0) of the R-MAT scale 22, "
@@ -760,7 +971,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rmat22_rowblock0_4x4_n128")
+    ap.add_argument("--workload", default="powerlaw2m_n128_fwdbwd")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--long-row", type=int, default=0, help="split-row threshold (0 = library default)")
     ap.add_argument("--segment", type=int, default=0, help="non-zeros per split unit (0 = library default)")
@@ -809,7 +1020,7 @@ def main():
     out = {
         "metric": wl.metric,
         "value": round(value, 2),
-        "unit": "GFLOP/s",
+        "unit": "GFLOP/s" if wl.flops else "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -830,12 +1041,18 @@ def main():
     }
     out.update(wl.extra(avg_kernel_ms))
     if not args.no_cpu_baseline:
+        # The oracle legs: its time on the host cores, and (for workloads that define it) the
+        # error of the step's results against it on a sample, both after the timed region.
         threads = _threads()
         os.environ["OMP_NUM_THREADS"] = str(threads)
         flops, secs, desc = wl.cpu_sample()
         out["cpu_baseline"] = {"value": round(flops / secs / 1e9, 3), "unit": "GFLOP/s", "cores": threads,
                                "kind": "oracle", "sample": desc, "seconds": round(secs, 2),
                                "cpu_model": _cpu_model()}
+        if hasattr(wl, "accuracy"):
+            t0 = time.time()
+            out["accuracy"] = wl.accuracy()
+            _log("accuracy sample in %.1f s" % (time.time() - t0))
     print(json.dumps(out), flush=True)
 
 
