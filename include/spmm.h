@@ -212,6 +212,25 @@ spmm_status spmm_fwd(spmm_tile_t A, int k_offset, const void* const* B, const in
                      spmm_dtype b_dtype, void* C, int64_t ldc, spmm_dtype c_dtype, int64_t N,
                      int accumulate, void* workspace, size_t ws_bytes, void* stream);
 
+/*
+ * The forward without a workspace, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, kernels and results as spmm_fwd (bit for bit); the scratch spmm_fwd
+ * takes as `workspace` (split-row partial rows, staged hot rows) is instead a fixed
+ * device array of spmm_noalloc_scratch_bytes() bytes (64 MiB) per GPU, which the
+ * library holds from its load until the process ends; its address on each device is
+ * looked up on the first call made there.  The call allocates nothing and makes no
+ * allocating library call.  Every call on one GPU shares that GPU's array, so calls
+ * that overlap on one GPU (other streams, other threads) race and must not be made;
+ * the array keeps the last call's contents, none of which a later call reads before
+ * writing.  Errors: as spmm_fwd, and WORKSPACE when spmm_fwd_workspace_bytes(A, N)
+ * exceeds the array (use spmm_fwd with a workspace then).
+ */
+spmm_status spmm_fwd_noalloc(spmm_tile_t A, int k_offset, const void* const* B, const int64_t* ldb,
+                             spmm_dtype b_dtype, void* C, int64_t ldc, spmm_dtype c_dtype, int64_t N, int accumulate,
+                             void* stream);
+size_t spmm_noalloc_scratch_bytes(void);
+
 /* The backward keeps its own variant per (N, dtype), set here (v != NULL) or cleared
    (v == NULL; the library rule then applies).  Kind SPMM_KERNEL_FUSED selects the fused
    backward (when spmm_bwd is asked for both dA and dB): a group of `lanes` lanes owns one

@@ -74,6 +74,8 @@ EXPORTS = {
     "spmm_tile_autotune": (c_int, [c_vp, c_i64, c_int, c_vp, c_vp, c_vp, c_i64, c_int, c_vp, c_vp]),
     "spmm_fwd_workspace_bytes": (c_int, [c_vp, c_i64, c_vp]),
     "spmm_fwd": (c_int, [c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_i64, c_int, c_i64, c_int, c_vp, c_size, c_vp]),
+    "spmm_fwd_noalloc": (c_int, [c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_i64, c_int, c_i64, c_int, c_vp]),
+    "spmm_noalloc_scratch_bytes": (c_size, []),
     "spmm_bwd_workspace_bytes": (c_int, [c_vp, c_i64, c_vp]),
     "spmm_bwd": (c_int, [c_vp, c_vp, c_i64, c_vp, c_i64, c_i64, c_int, c_vp, c_vp, c_i64, c_vp, c_size, c_vp]),
     "spgemm_create": (c_int, [c_i64, c_vp, c_vp, c_uint, c_vp, c_vp]),

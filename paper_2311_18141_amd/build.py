@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libspmm.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["api.hip", "fwd.hip", "bwd.hip", "structure.hip", "batch.hip", "spgemm.hip", "hot.hip", "probe.hip"]
+SOURCES = ["api.hip", "fwd.hip", "bwd.hip", "structure.hip", "batch.hip", "spgemm.hip", "hot.hip", "probe.hip",
+           "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

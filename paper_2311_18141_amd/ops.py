@@ -271,6 +271,35 @@ def spmm_fwd(tile: Tile, Bs: Sequence[torch.Tensor], C: Optional[torch.Tensor] =
     return C
 
 
+def spmm_noalloc_scratch_bytes() -> int:
+    """Size of the fixed per-GPU scratch array spmm_fwd_noalloc uses."""
+    return int(lib().spmm_noalloc_scratch_bytes())
+
+
+def spmm_fwd_noalloc(tile: Tile, Bs: Sequence[torch.Tensor], C: torch.Tensor, k_offset: int = 0,
+                     accumulate: bool = False, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """spmm_fwd without a workspace (the library's fixed per-GPU scratch array); C is the caller's."""
+    K = tile.num_k
+    if len(Bs) != K:
+        raise ValueError("expected %d dense operands, got %d" % (K, len(Bs)))
+    dt = Bs[0].dtype
+    if dt not in _DTYPES:
+        raise ValueError("dense operands must be float32 or bfloat16")
+    N = Bs[0].shape[1]
+    ptrs = (ctypes.c_void_p * K)()
+    lds = (ctypes.c_int64 * K)()
+    for k, B in enumerate(Bs):
+        if B.dtype != dt or not B.is_cuda or B.shape[1] != N or B.shape[0] != tile.cols[k]:
+            raise ValueError("B[%d] must be a device %s tensor of shape (%d, %d)" % (k, dt, tile.cols[k], N))
+        lds[k] = _row_major_ld(B, "B[%d]" % k)
+        ptrs[k] = B.data_ptr()
+    if C.dtype != dt or C.shape != (tile.rows, N):
+        raise ValueError("C must be %s of shape (%d, %d)" % (dt, tile.rows, N))
+    check(lib().spmm_fwd_noalloc(tile.handle, k_offset, ptrs, lds, _DTYPES[dt], C.data_ptr(), _row_major_ld(C, "C"),
+                                 _DTYPES[dt], N, 1 if accumulate else 0, _stream_ptr(stream)))
+    return C
+
+
 def spmm_bwd(tile: Tile, dC: torch.Tensor, B: torch.Tensor, want_dA: bool = True, want_dB: bool = True,
              dA: Optional[torch.Tensor] = None, dB: Optional[torch.Tensor] = None,
              workspace: Optional[torch.Tensor] = None,

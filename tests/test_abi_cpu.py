@@ -257,3 +257,12 @@ def test_trace_ranges_switch_on_without_changing_results():
         r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
                            timeout=120)
         assert r.returncode == 0 and r.stdout.strip() == "ok", (flag, r.stdout, r.stderr[-2000:])
+
+
+def test_noalloc_forward_argument_errors():
+    """The forward that allocates nothing checks its arguments before any HIP call; its scratch
+    size is fixed."""
+    L = _lib.lib()
+    assert L.spmm_noalloc_scratch_bytes() == 64 << 20
+    assert L.spmm_fwd_noalloc(None, 0, None, None, 0, None, 8, 0, 8, 0, None) == 1
+    assert L.spmm_last_error()
