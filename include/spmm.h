@@ -298,13 +298,22 @@ spmm_status spmm_bwd(spmm_tile_t A, const void* dC, int64_t lddc, const void* B,
  * order; SPMM_BATCH_PERSISTENT = resident workgroups (#CU x occupancy) whose waves
  * claim one item at a time with a fetch-and-add on device counters (each class's
  * list cut into one contiguous slice per XCD with its own counter; a wave drains its
- * XCD's slice, then the others; a reset kernel runs first).  Both give identical
- * results.  Every tile must be a single-tile handle
+ * XCD's slice, then the others; a reset kernel runs first).  SPMM_BATCH_SINGLE (alone
+ * or with SPMM_BATCH_PERSISTENT) = one launch for the whole batch: one kernel runs
+ * every class, switching per item; the work list is ordered tile by tile regardless of
+ * class; a split row is summed by whichever of its units finishes last (no fix-up
+ * launch); with SPMM_BATCH_PERSISTENT its resident workgroups claim items from one
+ * contiguous slice of the whole list per XCD, stealing from the others when theirs is
+ * drained.  Its counters are 64-bit and never reset (each call advances them by a known
+ * amount), so a call is exactly one launch, graph replays included.  All forms give
+ * identical results.  Every tile must be a single-tile handle
  * (num_k = 1) on the current device, and must outlive the batch.  The batch
  * allocates its own device memory (work list; claim counters when persistent).
- * Errors: INVALID_ARG, UNSUPPORTED (num_k > 1, work list too long), ALLOC, HIP.
+ * Errors: INVALID_ARG, UNSUPPORTED (num_k > 1, work list too long; single launch: more
+ * than 2^23 split-row fix-ups or 2^31 items), ALLOC, HIP.
  */
 #define SPMM_BATCH_PERSISTENT 1u
+#define SPMM_BATCH_SINGLE 2u
 typedef struct spmm_batch_s* spmm_batch_t;
 spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles /* host, count */,
                               const int64_t* N /* host, count */, spmm_dtype dtype, int64_t item_nnz,
@@ -322,8 +331,10 @@ spmm_status spmm_batch_get_variant(spmm_batch_t batch, int t, spmm_variant* out 
  * on a 16-byte boundary (base pointer and ld * element size multiples of 16); the
  * library cannot check device-resident arguments.  Asynchronous; no host
  * synchronisation, no allocation: capturable in a HIP graph (a persistent batch
- * resets its claim counters by a kernel on every replay).  Calls on one batch must
- * not overlap (they share the claim counters and the workspace).  Errors: INVALID_ARG, WORKSPACE, HIP.
+ * resets its claim counters by a kernel on every replay; a single-launch batch needs
+ * no reset).  Calls on one batch must not overlap (they share the claim counters and
+ * the workspace; a single-launch batch's counters also assume that every earlier call
+ * ran to completion).  Errors: INVALID_ARG, WORKSPACE, HIP.
  */
 spmm_status spmm_batched(spmm_batch_t batch, const void* const* B, const int64_t* ldb, void* const* C,
                          const int64_t* ldc, int accumulate, void* workspace, size_t ws_bytes, void* stream);

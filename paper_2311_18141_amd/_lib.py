@@ -25,6 +25,8 @@ SPMM_F32 = 0
 SPMM_BF16 = 1
 SPMM_TILE_VALIDATE = 1
 SPMM_TILE_TRANSPOSE = 2
+SPMM_BATCH_PERSISTENT = 1
+SPMM_BATCH_SINGLE = 2
 
 
 class SpmmCsr(ctypes.Structure):

@@ -1279,6 +1279,11 @@ struct spmm_batch_s {
   int64_t n_fix = 0;
   unsigned* d_counter = nullptr;  // persistent mode: kClaimSlices claim counters per item class
   bool persistent = false;
+  // Single-launch form: 64-bit claim counters (kClaimSlices, kCounter64Stride apart) then
+  // one arrival counter per fix-up item; never reset.
+  bool single = false;
+  unsigned long long* d_c64 = nullptr;
+  int single_grid = 0;
   size_t ws_bytes = 0;
   int64_t class_off[spmm::kBatchClasses] = {};
   int64_t class_cnt[spmm::kBatchClasses] = {};
@@ -1289,6 +1294,7 @@ struct spmm_batch_s {
     if (d_items) (void)hipFree(d_items);
     if (d_fix) (void)hipFree(d_fix);
     if (d_counter) (void)hipFree(d_counter);
+    if (d_c64) (void)hipFree(d_c64);
   }
 };
 
@@ -1343,7 +1349,8 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
   if (dtype != SPMM_F32 && dtype != SPMM_BF16) return fail(SPMM_ERR_INVALID_ARG, "unknown dtype");
   if (item_nnz != 0 && (item_nnz < 64 || item_nnz > ((int64_t)1 << 20)))
     return fail(SPMM_ERR_INVALID_ARG, "item_nnz=%lld out of range", (long long)item_nnz);
-  if (flags & ~(unsigned)SPMM_BATCH_PERSISTENT) return fail(SPMM_ERR_INVALID_ARG, "unknown batch flags 0x%x", flags);
+  if (flags & ~(unsigned)(SPMM_BATCH_PERSISTENT | SPMM_BATCH_SINGLE))
+    return fail(SPMM_ERR_INVALID_ARG, "unknown batch flags 0x%x", flags);
   const double item_target = item_nnz ? (double)item_nnz : 256.0;
   for (int t = 0; t < count; ++t) {
     if (!tiles[t]) return fail(SPMM_ERR_INVALID_ARG, "tile %d is null", t);
@@ -1363,6 +1370,7 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
   b->dt = dt;
   b->device = dev;
   b->persistent = (flags & SPMM_BATCH_PERSISTENT) != 0;
+  b->single = (flags & SPMM_BATCH_SINGLE) != 0;
   b->variants.resize(count);
   auto body = [&]() -> spmm_status {
     std::vector<spmm::BatchTileDev> bt(count);
@@ -1375,6 +1383,8 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
     int64_t part = 0;
     std::vector<int32_t> rp;
     std::vector<spmm::Seg> segs;
+    std::vector<spmm::LongRow> lrows;
+    std::vector<int32_t> seg_row;  // single-launch form: the split row of each unit
     for (int t = 0; t < count; ++t) {
       const spmm_tile_s* A = tiles[t];
       spmm::BatchTileDev& d = bt[t];
@@ -1427,10 +1437,29 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
           items.push_back({(double)(nz + (r1 - r0)) * width, spmm::BatchItem{t, (int32_t)r0, w, (int32_t)((r1 - r0) << 8)}});
         }
       }
+      // single-launch form: each unit item carries the index of its split row's fix-up
+      // item (the row's arrival counter): fix items are (tile, split row, window) in order
+      const int64_t fix_base = (int64_t)fix.size();
+      if (b->single && A->plan.n_long > 0) {
+        lrows.resize((size_t)A->plan.n_long);
+        HIP_TRY(hipMemcpyAsync(lrows.data(), A->plan.lrow, sizeof(spmm::LongRow) * lrows.size(),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        seg_row.assign((size_t)A->plan.n_seg, -1);
+        for (int64_t r = 0; r < A->plan.n_long; ++r)
+          for (int32_t si = lrows[r].s0; si < lrows[r].s1; ++si) seg_row[si] = (int32_t)r;
+      }
       for (int64_t si = 0; si < A->plan.n_seg; ++si)
         for (int w = 0; w < nw_unit; ++w) {
           const double width = (double)std::min<int64_t>(wunit, N[t] - w * wunit);
-          items.push_back({(double)(segs[si].p1 - segs[si].p0) * width, spmm::BatchItem{t, (int32_t)si, w, 1}});
+          int32_t type = 1;
+          if (b->single) {
+            const int64_t f = fix_base + (int64_t)seg_row[si] * nw_unit + w;
+            if (seg_row[si] < 0 || f >= spmm::kMaxSingleFix)
+              return fail(SPMM_ERR_UNSUPPORTED, "single-launch batch: more than 2^23 split-row fix-ups");
+            type = (int32_t)(1 | (f << 8));
+          }
+          items.push_back({(double)(segs[si].p1 - segs[si].p0) * width, spmm::BatchItem{t, (int32_t)si, w, type}});
         }
       for (int64_t r = 0; r < A->plan.n_long; ++r)
         for (int w = 0; w < nw_unit; ++w) fix.push_back(spmm::BatchItem{t, (int32_t)r, w, 2});
@@ -1459,7 +1488,7 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
     };
     std::stable_sort(items.begin(), items.end(), [&](const Costed& x, const Costed& y) {
       const int cx = cls(x.it), cy = cls(y.it);
-      if (cx != cy) return cx < cy;
+      if (cx != cy && !b->single) return cx < cy;  // one launch per class: class by class
       if (x.it.tile != y.it.tile) return rank[x.it.tile] < rank[y.it.tile];
       // one column window at a time: the waves then share that window's slice of B
       if (x.it.window != y.it.window) return x.it.window < y.it.window;
@@ -1478,17 +1507,31 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
     b->ws_bytes = sizeof(float) * (size_t)part;
     if (dalloc(&b->d_tiles, count) != hipSuccess || dalloc(&b->d_items, b->n_items) != hipSuccess ||
         dalloc(&b->d_fix, b->n_fix) != hipSuccess ||
-        (b->persistent && dalloc(&b->d_counter, spmm::kBatchCounters) != hipSuccess))
+        (b->persistent && !b->single && dalloc(&b->d_counter, spmm::kBatchCounters) != hipSuccess) ||
+        (b->single && dalloc(&b->d_c64, (int64_t)spmm::kClaimSlices * spmm::kCounter64Stride + b->n_fix) != hipSuccess))
       return fail(SPMM_ERR_ALLOC, "device allocation of the batch failed");
+    if (b->single && b->n_items >= ((int64_t)1 << 31))
+      return fail(SPMM_ERR_UNSUPPORTED, "work list too long for the single-launch form");
     HIP_TRY(hipMemcpyAsync(b->d_tiles, bt.data(), sizeof(spmm::BatchTileDev) * bt.size(), hipMemcpyHostToDevice, s));
     if (b->n_items)
       HIP_TRY(hipMemcpyAsync(b->d_items, list.data(), sizeof(spmm::BatchItem) * list.size(), hipMemcpyHostToDevice, s));
     if (b->n_fix)
       HIP_TRY(hipMemcpyAsync(b->d_fix, fix.data(), sizeof(spmm::BatchItem) * fix.size(), hipMemcpyHostToDevice, s));
-    if (b->persistent) HIP_TRY(hipMemsetAsync(b->d_counter, 0, sizeof(unsigned) * spmm::kBatchCounters, s));
+    if (b->d_counter) HIP_TRY(hipMemsetAsync(b->d_counter, 0, sizeof(unsigned) * spmm::kBatchCounters, s));
+    if (b->d_c64)
+      HIP_TRY(hipMemsetAsync(b->d_c64, 0,
+                             sizeof(unsigned long long) * ((size_t)spmm::kClaimSlices * spmm::kCounter64Stride + b->n_fix),
+                             s));
     HIP_TRY(hipStreamSynchronize(s));
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (b->single) {
+      // resident workgroups of the union kernel (persistent), at most one wave per item
+      const int64_t full = (int64_t)cus * spmm::batch_single_blocks_per_cu(dt);
+      const int64_t need = (b->n_items + spmm::kBlock / 64 - 1) / (spmm::kBlock / 64);
+      b->single_grid = (int)std::max<int64_t>(1, std::min(full, need));
+      return SPMM_OK;
+    }
     int occ[spmm::kBatchClasses] = {};
     if (b->persistent) spmm::batch_blocks_per_cu(dt, occ);
     for (int c = 0; c < spmm::kBatchClasses; ++c) {
@@ -1564,6 +1607,13 @@ spmm_status spmm_batched(spmm_batch_t batch, const void* const* B, const int64_t
   P.partial = static_cast<float*>(workspace);
   P.counter = batch->d_counter;
   P.accumulate = accumulate ? 1 : 0;
+  if (batch->single) {
+    P.counter64 = batch->d_c64;
+    P.arrive = batch->d_c64 + (int64_t)spmm::kClaimSlices * spmm::kCounter64Stride;
+    HIP_TRY(spmm::launch_batch_single(P, batch->single_grid, batch->dt, batch->persistent,
+                                      static_cast<hipStream_t>(stream)));
+    return SPMM_OK;
+  }
   HIP_TRY(spmm::launch_batch(P, batch->class_off, batch->class_cnt, batch->class_grid, batch->dt, batch->persistent,
                              static_cast<hipStream_t>(stream)));
   return SPMM_OK;

@@ -331,6 +331,120 @@ __global__ void __launch_bounds__(kBlock) batch_reset(unsigned* counter, int n) 
   for (int i = (int)threadIdx.x; i < n; i += kBlock) counter[i] = 0u;
 }
 
+// ---- Single-launch form ---------------------------------------------------------
+// Every item class in one kernel: each item (one wave) switches, uniformly, to its
+// class's code, so the whole batch is one launch.  Split rows need no second launch:
+// a unit, after storing its partial row, releases it and counts itself on its row's
+// arrival counter; the unit that completes the count acquires the others' partials and
+// sums them in unit order (the same fixed order as the fix-up kernel, so results are
+// bit-identical to the per-class form).
+//
+// Counters are 64-bit and never reset, which keeps the form to one launch (graph
+// replays included): every call adds exactly n_units to a split row's arrival counter,
+// so the last arriver of each call is the one whose count becomes a multiple of
+// n_units; in the persistent hand-out every wave makes exactly one failed claim on each
+// slice it visits (all of them), so every call adds exactly items + waves to a slice's
+// counter and a claim's place in this call is its value modulo that.  Calls on one
+// batch must not overlap (they never could: they share the workspace).
+
+__device__ __forceinline__ uint64_t claim64(unsigned long long* counter, int s, int lane) {
+  unsigned long long c = 0;
+  if (lane == 0) c = atomicAdd(counter + (int64_t)s * kCounter64Stride, 1ull);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)c, 0);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(c >> 32), 0);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <typename E, bool ACC>
+__device__ __forceinline__ void union_item(const BatchParams& P, int64_t it, int32_t* s_pref, int32_t* s_beg) {
+  const int lane = threadIdx.x & 63;
+  const BatchItem item = P.items[it];
+  const BatchTileDev& bt = P.tiles[item.tile];
+  const int type = item.type & 255;
+  const int lv = bt.V == 4 ? 2 : (bt.V == 2 ? 1 : 0);
+  int cls;
+  if (type == 1)
+    cls = kClassUnit + lv;
+  else if (bt.kind == 0)
+    cls = lv;
+  else
+    cls = kClassRowsplit + (bt.G == 8 ? 0 : (bt.G == 16 ? 1 : (bt.G == 32 ? 2 : 3)));
+  switch (cls) {
+    case 0: run_item<E, ACC, 0>(P, it, s_pref, s_beg); break;
+    case 1: run_item<E, ACC, 1>(P, it, s_pref, s_beg); break;
+    case 2: run_item<E, ACC, 2>(P, it, s_pref, s_beg); break;
+    case 3: run_item<E, ACC, 3>(P, it, s_pref, s_beg); break;
+    case 4: run_item<E, ACC, 4>(P, it, s_pref, s_beg); break;
+    case 5: run_item<E, ACC, 5>(P, it, s_pref, s_beg); break;
+    case 6: run_item<E, ACC, 6>(P, it, s_pref, s_beg); break;
+    case 7: run_item<E, ACC, 7>(P, it, s_pref, s_beg); break;
+    case 8: run_item<E, ACC, 8>(P, it, s_pref, s_beg); break;
+    default: run_item<E, ACC, 9>(P, it, s_pref, s_beg); break;
+  }
+  if (type != 1) return;
+  // release this unit's partial row, count it, and sum the row if it was the last
+  __threadfence();
+  const int64_t f = (int64_t)(item.type >> 8);
+  unsigned long long old = 0;
+  if (lane == 0) old = atomicAdd(P.arrive + f, 1ull);
+  const uint64_t o = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(old >> 32), 0) << 32) |
+                     (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)old, 0);
+  const BatchItem fx = P.fix[f];
+  const BatchTileDev& ft = P.tiles[fx.tile];
+  const LongRow lr = ft.lrow[fx.a];
+  const uint64_t n = (uint64_t)(lr.s1 - lr.s0);
+  if ((o + 1) % n != 0) return;
+  __threadfence();
+  const Ops<E> op = item_ops<E>(P, fx.tile);
+  switch (ft.V) {
+    case 1: fix_row<1, E, ACC>(P, ft, op, fx.a, fx.window); return;
+    case 2: fix_row<2, E, ACC>(P, ft, op, fx.a, fx.window); return;
+    default: fix_row<4, E, ACC>(P, ft, op, fx.a, fx.window); return;
+  }
+}
+
+template <typename E, bool ACC, bool PERSIST>
+__global__ void __launch_bounds__(kBlock) batch_union(BatchParams P) {
+  __shared__ int32_t s_mem[(kBlock / 64) * 129];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  int32_t* s_pref = s_mem + w * 129;
+  int32_t* s_beg = s_pref + 65;
+  if constexpr (PERSIST) {
+    const uint64_t waves = (uint64_t)gridDim.x * (kBlock / 64);
+    int s = (int)(blockIdx.x % kClaimSlices);
+    int visited = 1;
+    uint64_t got = claim64(P.counter64, s, lane);
+    for (;;) {
+      const int64_t lo = P.n_items * s / kClaimSlices;
+      const int64_t hi = P.n_items * (s + 1) / kClaimSlices;
+      const int64_t it = lo + (int64_t)(got % ((uint64_t)(hi - lo) + waves));
+      if (it >= hi) {
+        if (visited == kClaimSlices) break;
+        ++visited;
+        s = (s + 1) % kClaimSlices;
+        got = claim64(P.counter64, s, lane);
+        continue;
+      }
+      got = claim64(P.counter64, s, lane);  // the next item, in flight during this one
+      union_item<E, ACC>(P, (int64_t)__builtin_amdgcn_readfirstlane((int)it), s_pref, s_beg);
+    }
+  } else {
+    const int64_t it = (int64_t)blockIdx.x * (kBlock / 64) + w;
+    if (it < P.n_items) union_item<E, ACC>(P, (int64_t)__builtin_amdgcn_readfirstlane((int)it), s_pref, s_beg);
+  }
+}
+
+template <typename E, bool ACC>
+hipError_t launch_single_t(const BatchParams& P, int grid, bool persistent, hipStream_t s) {
+  if (P.n_items == 0) return hipSuccess;
+  if (persistent)
+    hipLaunchKernelGGL((batch_union<E, ACC, true>), dim3((unsigned)grid), dim3(kBlock), 0, s, P);
+  else
+    hipLaunchKernelGGL((batch_union<E, ACC, false>), dim3((unsigned)((P.n_items + 3) / 4)), dim3(kBlock), 0, s, P);
+  return hipGetLastError();
+}
+
 template <typename E, bool ACC, int CLS>
 hipError_t launch_class(const BatchParams& P, int grid, bool persistent, hipStream_t s) {
   if (persistent)
@@ -407,6 +521,22 @@ hipError_t launch_batch(const BatchParams& P, const int64_t* off, const int64_t*
                         : launch_batch_t<F32E, false>(P, off, cnt, grid, persistent, s);
   return P.accumulate ? launch_batch_t<BF16E, true>(P, off, cnt, grid, persistent, s)
                       : launch_batch_t<BF16E, false>(P, off, cnt, grid, persistent, s);
+}
+
+hipError_t launch_batch_single(const BatchParams& P, int grid, DT dt, bool persistent, hipStream_t s) {
+  if (dt == DT::F32)
+    return P.accumulate ? launch_single_t<F32E, true>(P, grid, persistent, s)
+                        : launch_single_t<F32E, false>(P, grid, persistent, s);
+  return P.accumulate ? launch_single_t<BF16E, true>(P, grid, persistent, s)
+                      : launch_single_t<BF16E, false>(P, grid, persistent, s);
+}
+
+int batch_single_blocks_per_cu(DT dt) {
+  int n = 0;
+  const hipError_t e = dt == DT::F32
+                           ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_union<F32E, false, true>, kBlock, 0)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_union<BF16E, false, true>, kBlock, 0);
+  return (e == hipSuccess && n > 0) ? n : 2;
 }
 
 void batch_blocks_per_cu(DT dt, int* out) {

@@ -170,7 +170,21 @@ struct BatchParams {
   float* partial;
   unsigned* counter;       // persistent mode: the class's kClaimSlices claim counters
   int accumulate;
+  // Single-launch form (every class in one kernel): per-XCD claim counters and one
+  // arrival counter per fix-up item, both 64-bit and never reset (see batch_union).
+  unsigned long long* counter64;
+  unsigned long long* arrive;
 };
+// Single-launch form: a unit item's type is 1 | (fix item << 8), so at most 2^23 fix items.
+constexpr int64_t kMaxSingleFix = (int64_t)1 << 23;
+// 64-bit claim counters of the single-launch form, 32 apart (one 256-byte line each).
+constexpr int kCounter64Stride = 32;
+// One launch of the single-launch form: every item of the list (tile by tile) by one
+// kernel that switches on the item's class; split rows are summed by the unit that
+// arrives last.  persistent = false: one wave per item (grid = ceil(n_items / 4));
+// true: `grid` resident workgroups claiming from per-XCD slices.
+hipError_t launch_batch_single(const BatchParams& P, int grid, DT dt, bool persistent, hipStream_t s);
+int batch_single_blocks_per_cu(DT dt);
 // Items a persistent wave claims with one fetch-and-add.
 constexpr int kClaimChunk = 1;
 // The chip's XCDs (each with its own L2); workgroups are dealt to them round-robin

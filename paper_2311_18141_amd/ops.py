@@ -411,12 +411,15 @@ class Batch:
 
 
 def spmm_batch_create(tiles: Sequence[Tile], Ns: Sequence[int], dtype=torch.float32, item_nnz: int = 0,
-                      persistent: bool = False, stream: Optional[torch.cuda.Stream] = None) -> Batch:
-    """Work list for spmm_batched over single-tile handles (persistent: claim-counter hand-out)."""
+                      persistent: bool = False, single: bool = False,
+                      stream: Optional[torch.cuda.Stream] = None) -> Batch:
+    """Work list for spmm_batched over single-tile handles (persistent: claim-counter hand-out;
+    single: one launch for every kernel class, split rows finished in the same launch)."""
     arr = (ctypes.c_void_p * len(tiles))(*[t.handle for t in tiles])
     ns = (ctypes.c_int64 * len(tiles))(*[int(n) for n in Ns])
     h = ctypes.c_void_p()
-    check(lib().spmm_batch_create(len(tiles), arr, ns, _DTYPES[dtype], item_nnz, 1 if persistent else 0,
+    flags = (_lib.SPMM_BATCH_PERSISTENT if persistent else 0) | (_lib.SPMM_BATCH_SINGLE if single else 0)
+    check(lib().spmm_batch_create(len(tiles), arr, ns, _DTYPES[dtype], item_nnz, flags,
                                   _stream_ptr(stream), ctypes.byref(h)))
     return Batch(h.value, list(tiles), [int(n) for n in Ns], dtype)
 

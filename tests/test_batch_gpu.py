@@ -1,5 +1,5 @@
-"""Batched launch (flat and persistent hand-out): every tile of the batch against the FP64 oracle,
-the two modes against each other, graph replays."""
+"""Batched launch (flat and persistent hand-out, one launch per class or a single launch for every
+class): every tile of the batch against the FP64 oracle, the modes against each other, graph replays."""
 import numpy as np
 import pytest
 import torch
@@ -30,8 +30,12 @@ def _tiles(count, seed, rows_hi=4096, value_kind="pm1", long_rows=False):
     return out, Ns
 
 
+MODES = {"flat": (False, False), "persistent": (True, False), "single": (False, True),
+         "single_persistent": (True, True)}
+
+
 def _run(As, Ns, dtype=torch.float32, kw=None, variants=None, accumulate=False, value_kind="pm1", seed=0,
-         persistent=False, item_nnz=0):
+         mode="flat", item_nnz=0):
     rng = _rng(seed)
     handles = [G.make_tile([A], **(kw or {})) for A in As]
     if variants is not None:
@@ -41,20 +45,21 @@ def _run(As, Ns, dtype=torch.float32, kw=None, variants=None, accumulate=False, 
     C0 = [synth.dense(A.rows, N, rng, value_kind) for A, N in zip(As, Ns)]
     Bs = [G.dense_dev(b, dtype) for b in Bh]
     Cs = [G.dense_dev(c, dtype) for c in C0]
-    batch = ops.spmm_batch_create(handles, Ns, dtype, item_nnz=item_nnz, persistent=persistent)
+    persistent, single = MODES[mode]
+    batch = ops.spmm_batch_create(handles, Ns, dtype, item_nnz=item_nnz, persistent=persistent, single=single)
     ops.spmm_batched(batch, Bs, Cs, accumulate=accumulate)
     torch.cuda.synchronize()
     return handles, batch, Bh, C0, Bs, Cs
 
 
-@pytest.mark.parametrize("persistent", [False, True])
+@pytest.mark.parametrize("mode", sorted(MODES))
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
 @pytest.mark.parametrize("long_rows", [False, True])
-def test_batch_matches_oracle(dtype, long_rows, persistent):
-    G.note("batch dtype=%s long_rows=%s persistent=%s" % (dtype, long_rows, persistent))
+def test_batch_matches_oracle(dtype, long_rows, mode):
+    G.note("batch dtype=%s long_rows=%s mode=%s" % (dtype, long_rows, mode))
     As, Ns = _tiles(24, 3, long_rows=long_rows)
     kw = dict(long_row=256, segment=128) if long_rows else {}
-    handles, batch, Bh, C0, Bs, Cs = _run(As, Ns, dtype, kw, seed=4, persistent=persistent)
+    handles, batch, Bh, C0, Bs, Cs = _run(As, Ns, dtype, kw, seed=4, mode=mode)
     for t, (A, N) in enumerate(zip(As, Ns)):
         got = G.host_f32(Cs[t])
         if dtype == torch.float32:
@@ -65,28 +70,26 @@ def test_batch_matches_oracle(dtype, long_rows, persistent):
             G.assert_bf16_close(got, ref, S, what="tile %d" % t)
 
 
-@pytest.mark.parametrize("persistent", [False, True])
+@pytest.mark.parametrize("mode", sorted(MODES))
 @pytest.mark.parametrize("variant", [("stream", 0, 1), ("stream", 0, 2), ("stream", 0, 4),
                                      ("rowsplit", 8, 0), ("rowsplit", 16, 0), ("rowsplit", 32, 0),
                                      ("rowsplit", 64, 0)])
-def test_batch_variants_integer_exact(variant, persistent):
-    G.note("batch variant %s persistent=%s" % (variant, persistent))
+def test_batch_variants_integer_exact(variant, mode):
+    G.note("batch variant %s mode=%s" % (variant, mode))
     As, Ns = _tiles(12, 5, value_kind="int8", long_rows=True)
     Ns = [128] * len(As)
     handles, batch, Bh, C0, Bs, Cs = _run(As, Ns, kw=dict(long_row=256, segment=100), value_kind="int8",
-                                          variants=[variant] * len(As), accumulate=True, seed=6,
-                                          persistent=persistent)
+                                          variants=[variant] * len(As), accumulate=True, seed=6, mode=mode)
     for t, A in enumerate(As):
         ref, _ = G.oracle_fwd([A], [Bh[t]], accumulate=True, C0=C0[t])
         assert np.array_equal(G.host_f32(Cs[t]).astype(np.float64), ref), (t, variant, batch.variant(t))
 
 
-@pytest.mark.parametrize("persistent", [False, True])
-def test_batch_graph_replay_deterministic(persistent):
-    G.note("batch graph replay persistent=%s" % persistent)
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_batch_graph_replay_deterministic(mode):
+    G.note("batch graph replay mode=%s" % mode)
     As, Ns = _tiles(40, 7, long_rows=True)
-    handles, batch, Bh, C0, Bs, Cs = _run(As, Ns, kw=dict(long_row=256, segment=128), seed=8,
-                                          persistent=persistent)
+    handles, batch, Bh, C0, Bs, Cs = _run(As, Ns, kw=dict(long_row=256, segment=128), seed=8, mode=mode)
     eager = [c.clone() for c in Cs]
     ws = batch.workspace()
     ops.spmm_batched(batch, Bs, Cs, workspace=ws)
@@ -132,13 +135,36 @@ def test_batch_autotuned_tiles():
 
 @pytest.mark.parametrize("item_nnz", [64, 1024, 1 << 20])
 def test_batch_modes_and_item_sizes_agree(item_nnz):
-    """Flat and persistent hand-out, any item size: bitwise the same output (each row is summed
-    in CSR order by one wave whatever the item boundaries)."""
+    """Every hand-out and launch form, any item size: bitwise the same output (each row is summed
+    in CSR order by one wave whatever the item boundaries, split rows in unit order)."""
     G.note("batch modes item_nnz=%d" % item_nnz)
     As, Ns = _tiles(30, 11, long_rows=True)
     kw = dict(long_row=256, segment=128)
     _, _, _, _, _, C_ref = _run(As, Ns, kw=kw, seed=12)
-    for persistent in (False, True):
-        _, batch, _, _, _, Cs = _run(As, Ns, kw=kw, seed=12, persistent=persistent, item_nnz=item_nnz)
+    for mode in sorted(MODES):
+        _, batch, _, _, _, Cs = _run(As, Ns, kw=kw, seed=12, mode=mode, item_nnz=item_nnz)
         for t, (c, r) in enumerate(zip(Cs, C_ref)):
-            assert torch.equal(c, r), (t, persistent, batch.variant(t))
+            assert torch.equal(c, r), (t, mode, batch.variant(t))
+
+
+@pytest.mark.parametrize("mode", ["single", "single_persistent"])
+def test_single_launch_repeated_calls(mode):
+    """The single-launch form's counters are never reset: many calls in a row (eager, varying
+    accumulate) keep giving the first call's bits."""
+    G.note("batch single launch repeated mode=%s" % mode)
+    As, Ns = _tiles(20, 13, long_rows=True)
+    kw = dict(long_row=128, segment=64)
+    handles, batch, Bh, C0, Bs, Cs = _run(As, Ns, kw=kw, seed=14, mode=mode)
+    first = [c.clone() for c in Cs]
+    ws = batch.workspace()
+    for r in range(25):
+        for c in Cs:
+            c.fill_(float("nan"))
+        ops.spmm_batched(batch, Bs, Cs, workspace=ws)
+        if r % 5 == 4:
+            torch.cuda.synchronize()
+            for t, (c, e) in enumerate(zip(Cs, first)):
+                assert torch.equal(c, e), (r, t)
+    torch.cuda.synchronize()
+    for t, (c, e) in enumerate(zip(Cs, first)):
+        assert torch.equal(c, e), t

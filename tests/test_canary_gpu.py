@@ -145,9 +145,9 @@ def test_bwd_guard_bands(dtype, band, N):
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
-@pytest.mark.parametrize("persistent", [False, True])
-def test_batched_guard_bands(dtype, persistent):
-    G.note("canary batched dtype=%s persistent=%s" % (dtype, persistent))
+@pytest.mark.parametrize("persistent,single", [(False, False), (True, False), (False, True), (True, True)])
+def test_batched_guard_bands(dtype, persistent, single):
+    G.note("canary batched dtype=%s persistent=%s single=%s" % (dtype, persistent, single))
     rng = _rng(5)
     As, Ns = [], [32, 64, 128, 256, 64, 32, 128, 8]
     for t, N in enumerate(Ns):
@@ -156,7 +156,7 @@ def test_batched_guard_bands(dtype, persistent):
         L[rng.integers(0, rows, size=2)] = min(rows, 900)
         As.append(synth.random_csr(rows, rows, L, rng, "int8"))
     handles = [G.make_tile([A], long_row=256, segment=128) for A in As]
-    batch = ops.spmm_batch_create(handles, Ns, dtype, persistent=persistent)
+    batch = ops.spmm_batch_create(handles, Ns, dtype, persistent=persistent, single=single)
     Bh = [synth.dense(A.cols, N, rng, "int8") for A, N in zip(As, Ns)]
     C0 = [synth.dense(A.rows, N, rng, "int8") for A, N in zip(As, Ns)]
     # rows start on 16-byte boundaries, as the batched launch requires

@@ -58,15 +58,15 @@ def test_k_tiles_with_empty_members():
         assert np.array_equal(G.host_f32(C).astype(np.float64), ref)
 
 
-@pytest.mark.parametrize("persistent", [False, True])
-def test_batch_with_empty_tiles(persistent):
-    G.note("degenerate batch persistent=%s" % persistent)
+@pytest.mark.parametrize("persistent,single", [(False, False), (True, False), (False, True), (True, True)])
+def test_batch_with_empty_tiles(persistent, single):
+    G.note("degenerate batch persistent=%s single=%s" % (persistent, single))
     rng = _rng(53)
     As = [_empty(0, 10), _empty(64, 64), synth.random_csr(200, 150, rng.integers(0, 30, size=200), rng, "int8"),
           _empty(9, 0), synth.random_csr(1, 1, np.array([1]), rng, "int8")]
     Ns = [32, 64, 32, 8, 32]
     handles = [G.make_tile([A]) for A in As]
-    batch = ops.spmm_batch_create(handles, Ns, persistent=persistent)
+    batch = ops.spmm_batch_create(handles, Ns, persistent=persistent, single=single)
     Bh = [synth.dense(A.cols, N, rng, "int8") for A, N in zip(As, Ns)]
     C0 = [synth.dense(A.rows, N, rng, "int8") for A, N in zip(As, Ns)]
     Cs = [G.dense_dev(c) for c in C0]

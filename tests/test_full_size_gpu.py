@@ -288,10 +288,13 @@ def test_uneven512_batched_sampled():
         worst = max(worst, st["max_rel_to_scale"])
     print("uneven512 batched: worst |err|/S over sampled rows %.3g" % worst)
     flat = [c.clone() for c in Cs]
-    pb = ops.spmm_batch_create(handles, Ns, persistent=True)
-    for c in Cs:
-        c.fill_(float("nan"))
-    ops.spmm_batched(pb, Bs, Cs)
-    torch.cuda.synchronize()
-    for t, (c, f) in enumerate(zip(Cs, flat)):
-        assert torch.equal(c, f), t
+    for kw in (dict(persistent=True), dict(single=True), dict(single=True, persistent=True)):
+        G.note("uneven512 batched %s" % kw)
+        pb = ops.spmm_batch_create(handles, Ns, **kw)
+        for c in Cs:
+            c.fill_(float("nan"))
+        ops.spmm_batched(pb, Bs, Cs, workspace=pb.workspace())
+        torch.cuda.synchronize()
+        for t, (c, f) in enumerate(zip(Cs, flat)):
+            assert torch.equal(c, f), (t, kw)
+        del pb
