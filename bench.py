@@ -28,9 +28,12 @@ the FP64 oracle on a sample.  Other workloads:
                             the symbolic phase is reported beside it)
     spgemm_er1m16_aa        local SpGEMM C = A A, 1,048,576^2 uniform, 16 per row
     uneven512_batched       512 uneven tiles (rows 1,024..65,536, 4..256 non-zeros per row,
-                            N_t in {32..256}) in one batched launch, per-tile autotuned
-                            variants; the per-tile launch loop and the persistent (claim
-                            counter) hand-out are reported beside it
+                            N_t in {32..256}) in one batched launch (one kernel for every item
+                            class, persistent claiming), per-tile autotuned variants; the
+                            per-tile launch loop and the other launch forms are reported beside it
+    gather_<w>b_4096mib     gather probe over a 4 GiB table (w = 512, 128, 16 bytes per row): a
+                            kernel of known bytes for calibrating the HBM counters
+    copy_1gib               a plain 1 GiB device copy, the same for streaming traffic
 
 value = 2 * nnz * N * passes / step time (GFLOP/s).  The roofline object prices
 the step's kernels with their algorithmic bytes (CSR arrays + dense inputs read
@@ -116,10 +119,12 @@ def kernel_source_digest(workload: str = "") -> str:
             h.update(name.encode() + b"\0" + f.read())
     if workload in PINNED:
         h.update(b"pin\0" + json.dumps(PINNED[workload], sort_keys=True).encode())
+    if workload == "powerlaw2m_n128_fwdbwd":  # its line also runs the BF16 workload's pinned kernels
+        h.update(b"pin\0" + json.dumps(PINNED[workload + "_bf16"], sort_keys=True).encode())
     return h.hexdigest()
 
 
-def stored_traffic(workload: str):
+def stored_traffic(workload: str, key: str = "hbm_bytes_per_step"):
     """HBM bytes per step measured by rocprofv3 counters (profiles/traffic_<workload>.md), or None when
     absent or taken on different kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.md" % workload)
@@ -134,7 +139,7 @@ def stored_traffic(workload: str):
     if fields.get("source_sha256") != kernel_source_digest(workload):
         return None
     try:
-        return float(fields["hbm_bytes_per_step"])
+        return float(fields[key])
     except (KeyError, ValueError):
         return None
 
@@ -470,8 +475,11 @@ class ForwardBackward(Workload):
         for _ in range(3):
             step()
         ms = Batched._time(step, steps)
+        traffic = stored_traffic(self.name, "bf16_hbm_bytes_per_step") if not AUTOTUNE else None
         return {"ms_per_step": round(ms, 5), "value": round(self.flops / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
                 "speedup_vs_f32": round(f32_ms / ms, 3), "kernels": cfg, "steps": steps,
+                "traffic": traffic,
+                "traffic_frac": round(traffic / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
                 "passes": self._pass_ms(self.Bb, self.Cb, self.dCb, self.dAb, self.dBb),
                 "note": "same handle and inputs as the FP32 step, B / C / dC / dB stored in BF16"}
 
@@ -538,15 +546,17 @@ class ForwardBackward(Workload):
 
 
 class Batched(Workload):
-    """Many independent uneven tiles in one batched launch (flat hand-out), per-tile variants from the
-    autotuner; the per-tile launch loop (default and autotuned variants) and the persistent hand-out are
-    timed beside it."""
+    """Many independent uneven tiles in one batched launch: the single-launch form (one kernel for
+    every item class, resident workgroups claiming items from per-XCD slices, split rows summed by
+    their last unit), per-tile variants from the autotuner; the per-tile launch loop (default and
+    autotuned variants), the one-launch-per-class forms (flat and persistent hand-out) and the
+    single launch with the flat hand-out are timed beside it, eagerly and as graph replays."""
 
     def __init__(self, name, count, config):
         self.name = name
         self.count = count
         self.config = config
-        self.kernel = "spmm_batched (batch_class per kernel class + batch_fixup)"
+        self.kernel = "spmm_batched (batch_union: one launch, persistent hand-out)"
 
     def setup(self):
         import torch
@@ -576,15 +586,19 @@ class Batched(Workload):
         for h, B, C in zip(self.handles, self.B, self.C):
             ops.spmm_tile_autotune(h, [B], C, tune_plan=False)
         _log("%s: autotuned %d tiles in %.1f s" % (self.name, self.count, time.time() - t0))
-        self.batch = ops.spmm_batch_create(self.handles, self.Ns)
+        self.batch = ops.spmm_batch_create(self.handles, self.Ns, single=True, persistent=True)
         self.ws = self.batch.workspace()
-        # The persistent hand-out (claim counters), timed for comparison; both hand-outs also
-        # as one captured HIP graph replayed.
-        pb = ops.spmm_batch_create(self.handles, self.Ns, persistent=True)
-        pws = pb.workspace()
-        self.persistent_ms = self._time(lambda: ops.spmm_batched(pb, self.B, self.C, workspace=pws), reps=5)
-        self.graph_ms = {"flat": self._graph_ms(self.batch, self.ws), "persistent": self._graph_ms(pb, pws)}
-        del pb, pws
+        # The other forms, timed for comparison, eagerly and as one captured HIP graph replayed:
+        # one launch per item class with the flat (hardware dispatcher) or persistent (claim
+        # counter) hand-out, and the single launch with the flat hand-out.
+        self.forms_ms, self.graph_ms = {}, {"single_persistent": self._graph_ms(self.batch, self.ws)}
+        for key, kw in (("per_class_flat", {}), ("per_class_persistent", {"persistent": True}),
+                        ("single_flat", {"single": True})):
+            ob = ops.spmm_batch_create(self.handles, self.Ns, **kw)
+            ows = ob.workspace()
+            self.forms_ms[key] = self._time(lambda: ops.spmm_batched(ob, self.B, self.C, workspace=ows), reps=5)
+            self.graph_ms[key] = self._graph_ms(ob, ows)
+            del ob, ows
         self.tuned_loop_ms = self._time(self._loop, reps=5)
         # each non-zero gathers its B row (4 N bytes) from the tile's B (cols x 4 N bytes)
         self.gather_items = [(float(t.nnz) * 4 * N, t.cols * 4 * N, 4 * N) for t, N in zip(self.tiles, self.Ns)]
@@ -603,8 +617,8 @@ class Batched(Workload):
                                           "gflops": round(self.flops / (self.loop_ms * 1e-3) / 1e9, 1)},
                            per_tile_loop_autotuned={"ms": round(self.tuned_loop_ms, 4),
                                                     "gflops": round(self.flops / (self.tuned_loop_ms * 1e-3) / 1e9, 1)},
-                           persistent={"ms": round(self.persistent_ms, 4),
-                                       "gflops": round(self.flops / (self.persistent_ms * 1e-3) / 1e9, 1)},
+                           other_forms={k: {"ms": round(v, 4), "gflops": round(self.flops / (v * 1e-3) / 1e9, 1)}
+                                        for k, v in self.forms_ms.items()},
                            graph_replay={k: {"ms": round(v, 4), "gflops": round(self.flops / (v * 1e-3) / 1e9, 1)}
                                          for k, v in self.graph_ms.items()})
 
