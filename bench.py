@@ -24,6 +24,11 @@ the FP64 oracle on a sample.  Other workloads:
     stationary_a_rmat22_tile00_n128x4
                             stationary-A local step: partial products of R-MAT tile (0,0) with 4
                             column blocks of N = 128, each added into its C tile
+    stationary_a_rmat22_rowblock0_4x4_grid
+                            stationary-A step of a row block with work stealing: the 16 products
+                            A(0,k) B(k,j) handed out through a 2-D reservation grid, partials drained
+                            in k order; the 3-D grid, no stealing, no grid and a launch per product
+                            are reported beside it
     spgemm_rmat18_ef16_aa   local SpGEMM C = A A, R-MAT scale 18, edge factor 16 (numeric phase;
                             the symbolic phase is reported beside it)
     spgemm_er1m16_aa        local SpGEMM C = A A, 1,048,576^2 uniform, 16 per row
@@ -794,6 +799,99 @@ class StationaryA(Workload):
         return 2.0 * float(lens[:r].sum()) * self.N, dt, "oracle FP64 partial product on rows [0, %d)" % r
 
 
+class StationaryAGrid(Workload):
+    """The stationary-A step of one row block with work stealing (Section 3.4, Algorithm 3), on one
+    GPU: row block 0 of the R-MAT scale-22 4 x 4 grid, A(0,k) for k = 0..3 (the stationary
+    tiles, nnz 20.7M / 7.1M / 7.1M / 2.4M), against B(k,j) for 4 column blocks j of N = 128.
+    The 16 component products A(0,k) B(k,j) form one batch handed out through a 2-D
+    reservation grid over (0, k): workers (waves of resident workgroups, owners by XCD) take
+    their own tile's products in j order with one fetch-and-add per item, then steal from the
+    other tiles' entries; each product writes a partial tile, and the owner of C(0,j) drains its
+    four partials in k order (spmm_tile_accumulate_n).  Beside it: the locality-aware 3-D grid,
+    the grid without stealing, the single launch without a grid, and one spmm_fwd launch per
+    product (the static order)."""
+
+    def __init__(self, name, config):
+        self.name = name
+        self.config = config
+        self.kernel = "spmm_batched (batch_reserve, 2-D grid) + spmm_tile_accumulate_n"
+
+    def setup(self):
+        import torch
+        import synth
+        from paper_2311_18141_amd import ops
+        t0 = time.time()
+        self.As = synth.rmat_row_block(22, 16, 4, 0, seed=2).tiles
+        K, J, N = len(self.As), 4, 128
+        self.K, self.J, self.N = K, J, N
+        rows = self.As[0].rows
+        _log("%s: inputs generated in %.1f s (nnz %d)" % (self.name, time.time() - t0, sum(a.nnz for a in self.As)))
+        dev = "cuda:0"
+        rng = synth.streams(2)[2]
+        self.handles = []
+        for A in self.As:
+            d = (torch.from_numpy(A.rowptr).to(dev), torch.from_numpy(A.colind).to(dev),
+                 torch.from_numpy(A.values).to(dev), A.cols)
+            h = ops.spmm_tile_create(rows, [d], validate=True, **_handle_opts("rmat22_rowblock0_4x4_n128"))
+            _apply_pin("rmat22_rowblock0_4x4_n128", h, N, torch.float32)
+            self.handles.append(h)
+        self.Bh = [[synth.dense(A.cols, N, rng) for _ in range(J)] for A in self.As]
+        self.C0 = [synth.dense(rows, N, rng) for _ in range(J)]
+        self.Bd, self.Pd, tiles, coords = [], [], [], []
+        for k in range(K):
+            for j in range(J):
+                self.Bd.append(torch.from_numpy(self.Bh[k][j]).to(dev))
+                self.Pd.append(torch.empty(rows, N, device=dev))
+                tiles.append(self.handles[k])
+                coords.append((0, j, k))
+        self.C = [torch.from_numpy(c).to(dev) for c in self.C0]
+        self.batches = {m: ops.spmm_batch_create_grid(tiles, [N] * len(tiles), coords, m) for m in ("2d", "3d", "own")}
+        self.batches["single"] = ops.spmm_batch_create(tiles, [N] * len(tiles), single=True, persistent=True)
+        self.ws = {m: b.workspace() for m, b in self.batches.items()}
+        self.fws = [h.workspace(N) for h in self.handles]
+        nnz = sum(a.nnz for a in self.As)
+        self.flops = 2.0 * nnz * N * J
+        prod = sum(J * (8 * a.nnz + 4 * (rows + 1)) + 4 * a.cols * N * J + 4 * rows * N * J for a in self.As)
+        acc = J * (2 + K) * 4 * rows * N
+        self.alg_bytes = float(prod + acc)
+        torch.cuda.synchronize()
+        self.forms_ms = {}
+        for m in ("3d", "own", "single", "loop"):
+            self.forms_ms[m] = Batched._time(lambda: self._run(m), reps=3)
+        self.config = dict(self.config, nnz=nnz, rows=rows, N=N, k_tiles=K, column_blocks=J,
+                           nnz_per_k=[a.nnz for a in self.As],
+                           other_forms={m: {"ms": round(v, 4), "gflops": round(self.flops / (v * 1e-3) / 1e9, 1)}
+                                        for m, v in self.forms_ms.items()},
+                           forms="2d/3d/own: reservation grids (random stealing, locality-aware stealing, "
+                                 "no stealing); single: one launch, per-XCD slices, no grid; loop: one "
+                                 "spmm_fwd per product")
+
+    def _run(self, mode):
+        from paper_2311_18141_amd import ops
+        if mode == "loop":
+            for t in range(self.K * self.J):
+                ops.spmm_fwd(self.handles[t // self.J], [self.Bd[t]], C=self.Pd[t], workspace=self.fws[t // self.J])
+        else:
+            ops.spmm_batched(self.batches[mode], self.Bd, self.Pd, workspace=self.ws[mode])
+        for j in range(self.J):
+            ops.spmm_tile_accumulate_n(self.C[j], [self.Pd[k * self.J + j] for k in range(self.K)])
+
+    def step(self):
+        self._run("2d")
+
+    def cpu_sample(self):
+        import oracle
+        lens = sum(a.row_lengths() for a in self.As)
+        target = 2.0e10 / (2.0 * self.N)
+        r = int(min(self.As[0].rows, np.searchsorted(np.cumsum(lens), target) + 1))
+        rows = np.arange(r, dtype=np.int64)
+        t0 = time.perf_counter()
+        oracle.spmm([(a.rowptr, a.colind, a.values) for a in self.As], [self.Bh[k][0] for k in range(self.K)],
+                    rows=rows, scale=False)
+        dt = time.perf_counter() - t0
+        return 2.0 * float(lens[:r].sum()) * self.N, dt, "oracle FP64 C(0,0) rows [0, %d) over the 4 k-tiles" % r
+
+
 class SpgemmAA(Workload):
     """Local SpGEMM C = A A (the local step of the paper's SpGEMM experiments).  A step is the
     numeric phase (spgemm_compute); the symbolic phase (plan creation) is timed beside it."""
@@ -940,6 +1038,10 @@ def workloads():
         "gather_512b_4096mib": lambda: GatherCalibration(512, 4096, 1 << 23),
         "gather_128b_4096mib": lambda: GatherCalibration(128, 4096, 1 << 25),
         "gather_16b_4096mib": lambda: GatherCalibration(16, 4096, 1 << 26),
+        "stationary_a_rmat22_rowblock0_4x4_grid": lambda: StationaryAGrid(
+            "stationary_a_rmat22_rowblock0_4x4_grid",
+            {"workload": "stationary_a_rmat22_rowblock0_4x4_grid", "matrix": "row block 0 of the R-MAT scale 22, "
+             "edge factor 16 4x4 grid (4 stationary tiles A(0,k)) against 4 column blocks of N = 128", "seed": 2}),
         "stationary_a_rmat22_tile00_n128x4": lambda: StationaryA(
             "stationary_a_rmat22_tile00_n128x4",
             {"workload": "stationary_a_rmat22_tile00_n128x4", "matrix": "tile (0,0) of the R-MAT scale 22, "

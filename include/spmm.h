@@ -299,18 +299,18 @@ spmm_status spmm_bwd(spmm_tile_t A, const void* dC, int64_t lddc, const void* B,
  * claim one item at a time with a fetch-and-add on device counters (each class's
  * list cut into one contiguous slice per XCD with its own counter; a wave drains its
  * XCD's slice, then the others; a reset kernel runs first).  SPMM_BATCH_SINGLE (alone
- * or with SPMM_BATCH_PERSISTENT) = one launch for the whole batch: one kernel runs
- * every class, switching per item; the work list is ordered tile by tile regardless of
- * class; a split row is summed by whichever of its units finishes last (no fix-up
- * launch); with SPMM_BATCH_PERSISTENT its resident workgroups claim items from one
- * contiguous slice of the whole list per XCD, stealing from the others when theirs is
- * drained.  Its counters are 64-bit and never reset (each call advances them by a known
- * amount), so a call is exactly one launch, graph replays included.  All forms give
+ * or with SPMM_BATCH_PERSISTENT) = one launch for every item of the batch: one kernel
+ * runs every class, switching per item, over a work list ordered tile by tile regardless
+ * of class (followed by the fix-up launch when some tile has split rows); with
+ * SPMM_BATCH_PERSISTENT its resident workgroups claim items from one contiguous slice
+ * of the whole list per XCD, stealing from the others when theirs is drained, with
+ * 64-bit claim counters that are never reset (each call advances them by a known
+ * amount), so no reset launch is needed, graph replays included.  All forms give
  * identical results.  Every tile must be a single-tile handle
  * (num_k = 1) on the current device, and must outlive the batch.  The batch
  * allocates its own device memory (work list; claim counters when persistent).
- * Errors: INVALID_ARG, UNSUPPORTED (num_k > 1, work list too long; single launch: more
- * than 2^23 split-row fix-ups or 2^31 items), ALLOC, HIP.
+ * Errors: INVALID_ARG, UNSUPPORTED (num_k > 1, work list too long; single launch: 2^31
+ * items or more), ALLOC, HIP.
  */
 #define SPMM_BATCH_PERSISTENT 1u
 #define SPMM_BATCH_SINGLE 2u
@@ -325,6 +325,37 @@ spmm_status spmm_batch_workspace_bytes(spmm_batch_t batch, size_t* bytes /* host
 spmm_status spmm_batch_get_variant(spmm_batch_t batch, int t, spmm_variant* out /* host */);
 
 /*
+ * A batch whose items are handed out through a reservation grid, the single-GPU form
+ * of the work-stealing algorithms' work grids (Section 3.4, Algorithm 3).  Tile t of
+ * the batch is one component product C(i,j) (+)= A(i,k) B(k,j); coords[3t..3t+2]
+ * (host) = (i, j, k).  `mode`:
+ *   SPMM_RESERVE_2D  grid over (i, k): the entry of a stationary tile A(i,k) hands out,
+ *                    one fetch-and-add per item, the items of its products in j order
+ *                    ("the next piece of work of that tile"); workers take their own
+ *                    entries, then steal from every other entry in cyclic order
+ *                    (random work stealing);
+ *   SPMM_RESERVE_3D  grid over (i, j, k), one entry per product: workers take the
+ *                    entries of their C tile, then those sharing their A tile, then
+ *                    their B tile, then the rest (locality-aware work stealing);
+ *   SPMM_RESERVE_OWN grid over (i, k), own entries only (no stealing).
+ * Workers are the waves of #CU x occupancy resident workgroups; their own entries
+ * follow their XCD (with E entries, E >= 8: XCD x owns the x-th eighth; fewer: entry
+ * x E / 8).  Each call zeroes the grid's counters with a reset kernel, then runs one
+ * kernel for every item class (and the fix-up launch when some tile has split rows, as
+ * with SPMM_BATCH_SINGLE).  Results are bit-identical to the other batch forms.  A tile
+ * handle may appear several times (the same A(i,k) against each B(k,j)).  item_nnz as
+ * for spmm_batch_create (items of at most 64 rows; larger items suit large tiles).
+ * Errors: as spmm_batch_create, INVALID_ARG (bad coords or mode).
+ */
+#define SPMM_RESERVE_2D 1
+#define SPMM_RESERVE_3D 2
+#define SPMM_RESERVE_OWN 3
+spmm_status spmm_batch_create_grid(int count, const spmm_tile_t* tiles /* host, count */,
+                                   const int64_t* N /* host, count */, spmm_dtype dtype,
+                                   const int32_t* coords /* host, 3 x count */, int mode, int64_t item_nnz,
+                                   void* stream, spmm_batch_t* out /* host */);
+
+/*
  * Run the batch: B, ldb, C, ldc are DEVICE arrays of `count` entries (pointers to
  * each tile's B_t (cols_t x N_t) and C_t (rows_t x N_t), row-major, in the batch's
  * dtype, and their leading dimensions).  Every row of every B_t and C_t must start
@@ -333,8 +364,8 @@ spmm_status spmm_batch_get_variant(spmm_batch_t batch, int t, spmm_variant* out 
  * synchronisation, no allocation: capturable in a HIP graph (a persistent batch
  * resets its claim counters by a kernel on every replay; a single-launch batch needs
  * no reset).  Calls on one batch must not overlap (they share the claim counters and
- * the workspace; a single-launch batch's counters also assume that every earlier call
- * ran to completion).  Errors: INVALID_ARG, WORKSPACE, HIP.
+ * the workspace; a persistent single-launch batch's counters also assume that every
+ * earlier call ran to completion).  Errors: INVALID_ARG, WORKSPACE, HIP.
  */
 spmm_status spmm_batched(spmm_batch_t batch, const void* const* B, const int64_t* ldb, void* const* C,
                          const int64_t* ldc, int accumulate, void* workspace, size_t ws_bytes, void* stream);
@@ -348,6 +379,16 @@ spmm_status spmm_batched(spmm_batch_t batch, const void* const* B, const int64_t
  */
 spmm_status spmm_tile_accumulate(void* C, int64_t ldc, const void* Ptile, int64_t ldp, int64_t rows, int64_t N,
                                  spmm_dtype dtype, void* stream);
+
+/*
+ * The owner's accumulate of several partial tiles (Algorithm 3's queue of partial
+ * products, drained in order):  C = C + P_0 + ... + P_{n-1}, summed in FP32 in that
+ * order; a BF16 C is rounded once per 16 partials.  P (host array of n device
+ * pointers) and ldp (host, n) describe the partials, rows x N each, in `dtype`.
+ * Asynchronous.  Errors: INVALID_ARG, HIP.
+ */
+spmm_status spmm_tile_accumulate_n(void* C, int64_t ldc, const void* const* P, const int64_t* ldp, int n,
+                                   int64_t rows, int64_t N, spmm_dtype dtype, void* stream);
 
 /*
  * Local sparse-times-sparse product C = A B (CSR x CSR -> CSR): the local step of

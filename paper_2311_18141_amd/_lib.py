@@ -27,6 +27,9 @@ SPMM_TILE_VALIDATE = 1
 SPMM_TILE_TRANSPOSE = 2
 SPMM_BATCH_PERSISTENT = 1
 SPMM_BATCH_SINGLE = 2
+SPMM_RESERVE_2D = 1
+SPMM_RESERVE_3D = 2
+SPMM_RESERVE_OWN = 3
 
 
 class SpmmCsr(ctypes.Structure):
@@ -86,11 +89,13 @@ EXPORTS = {
     "spgemm_rowptr": (c_int, [c_vp, c_vp, c_vp]),
     "spgemm_compute": (c_int, [c_vp, c_vp, c_vp, c_vp]),
     "spmm_batch_create": (c_int, [c_int, c_vp, c_vp, c_int, c_i64, c_uint, c_vp, c_vp]),
+    "spmm_batch_create_grid": (c_int, [c_int, c_vp, c_vp, c_int, c_vp, c_int, c_i64, c_vp, c_vp]),
     "spmm_batch_destroy": (c_int, [c_vp]),
     "spmm_batch_workspace_bytes": (c_int, [c_vp, c_vp]),
     "spmm_batch_get_variant": (c_int, [c_vp, c_int, c_vp]),
     "spmm_batched": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_int, c_vp, c_size, c_vp]),
     "spmm_tile_accumulate": (c_int, [c_vp, c_i64, c_vp, c_i64, c_i64, c_i64, c_int, c_vp]),
+    "spmm_tile_accumulate_n": (c_int, [c_vp, c_i64, c_vp, c_vp, c_int, c_i64, c_i64, c_int, c_vp]),
     "spmm_gather_probe": (c_int, [c_vp, c_i64, c_i64, c_vp, c_i64, c_vp, c_vp]),
     "spmm_status_string": (ctypes.c_char_p, [c_int]),
     "spmm_last_error": (ctypes.c_char_p, []),

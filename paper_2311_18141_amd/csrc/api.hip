@@ -8,6 +8,7 @@
 #include <new>
 #include <string>
 #include <algorithm>
+#include <array>
 #include <vector>
 
 #include <dlfcn.h>
@@ -1057,6 +1058,30 @@ static hipError_t launch_backward_fused(const spmm_tile_s* A, const FusedShape& 
   return spmm::launch_fixup(P, fs.G, fs.V, dt, s);
 }
 
+spmm_status spmm_tile_accumulate_n(void* C, int64_t ldc, const void* const* Pt, const int64_t* ldp, int n,
+                                   int64_t rows, int64_t N, spmm_dtype dtype, void* stream) {
+  spmm::TraceRange trace_range("spmm_tile_accumulate_n");
+  if (rows < 0 || N < 1 || n < 0) return fail(SPMM_ERR_INVALID_ARG, "rows=%lld N=%lld n=%d", (long long)rows,
+                                               (long long)N, n);
+  if (dtype != SPMM_F32 && dtype != SPMM_BF16) return fail(SPMM_ERR_INVALID_ARG, "unknown dtype");
+  if (n > 0 && (!Pt || !ldp)) return fail(SPMM_ERR_INVALID_ARG, "P/ldp is null");
+  if (ldc < N) return fail(SPMM_ERR_INVALID_ARG, "ldc < N");
+  if (rows > 0 && !C) return fail(SPMM_ERR_INVALID_ARG, "C is null");
+  const DT dt = dtype == SPMM_F32 ? DT::F32 : DT::BF16;
+  const int esize = dt == DT::F32 ? 4 : 2;
+  uintptr_t a = reinterpret_cast<uintptr_t>(C) | (uintptr_t)(ldc * esize);
+  for (int t = 0; t < n; ++t) {
+    if (ldp[t] < N) return fail(SPMM_ERR_INVALID_ARG, "ldp[%d] < N", t);
+    if (rows > 0 && !Pt[t]) return fail(SPMM_ERR_INVALID_ARG, "P[%d] is null", t);
+    a |= reinterpret_cast<uintptr_t>(Pt[t]) | (uintptr_t)(ldp[t] * esize);
+  }
+  if (rows == 0 || n == 0) return SPMM_OK;
+  int V = 16 / esize;
+  while (V > 1 && ((N % V) != 0 || (a % (uintptr_t)(V * esize)) != 0)) V /= 2;
+  HIP_TRY(spmm::launch_accumulate_n(C, ldc, Pt, ldp, n, rows, N, dt, V, static_cast<hipStream_t>(stream)));
+  return SPMM_OK;
+}
+
 spmm_status spmm_bwd(spmm_tile_t A, const void* dC, int64_t lddc, const void* B, int64_t ldb, int64_t N,
                      spmm_dtype dtype, float* dA_values, void* dB, int64_t lddb, void* workspace, size_t ws_bytes,
                      void* stream) {
@@ -1284,6 +1309,14 @@ struct spmm_batch_s {
   bool single = false;
   unsigned long long* d_c64 = nullptr;
   int single_grid = 0;
+  // Reservation-grid form: mode (0 = none), entries, their item offsets and coordinates,
+  // one claim counter per entry.
+  int grid_mode = 0;
+  int n_entries = 0;
+  unsigned class_mask = 0;  // single-launch forms: the kernel instance covering the batch's classes
+  int32_t* d_entry_off = nullptr;
+  int32_t* d_entry_ijk = nullptr;
+  unsigned* d_counterE = nullptr;
   size_t ws_bytes = 0;
   int64_t class_off[spmm::kBatchClasses] = {};
   int64_t class_cnt[spmm::kBatchClasses] = {};
@@ -1295,6 +1328,9 @@ struct spmm_batch_s {
     if (d_fix) (void)hipFree(d_fix);
     if (d_counter) (void)hipFree(d_counter);
     if (d_c64) (void)hipFree(d_c64);
+    if (d_entry_off) (void)hipFree(d_entry_off);
+    if (d_entry_ijk) (void)hipFree(d_entry_ijk);
+    if (d_counterE) (void)hipFree(d_counterE);
   }
 };
 
@@ -1339,9 +1375,14 @@ void batch_variant(const spmm_tile_s* A, int64_t N, DT dt, spmm::BatchTileDev* b
 
 extern "C" {
 
-spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t* N, spmm_dtype dtype,
-                              int64_t item_nnz, unsigned flags, void* stream, spmm_batch_t* out) {
-  spmm::TraceRange trace_range("spmm_batch_create");
+}  // extern "C"
+
+namespace {
+
+// Batch creation; coords (3 per tile) and grid_mode select the reservation-grid form.
+spmm_status batch_create_impl(int count, const spmm_tile_t* tiles, const int64_t* N, spmm_dtype dtype,
+                              int64_t item_nnz, unsigned flags, const int32_t* coords, int grid_mode, void* stream,
+                              spmm_batch_t* out) {
   if (!out) return fail(SPMM_ERR_INVALID_ARG, "out is null");
   *out = nullptr;
   if (count < 1) return fail(SPMM_ERR_INVALID_ARG, "count=%d < 1", count);
@@ -1370,8 +1411,29 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
   b->dt = dt;
   b->device = dev;
   b->persistent = (flags & SPMM_BATCH_PERSISTENT) != 0;
-  b->single = (flags & SPMM_BATCH_SINGLE) != 0;
+  b->single = (flags & SPMM_BATCH_SINGLE) != 0 || grid_mode != 0;
+  b->grid_mode = grid_mode;
   b->variants.resize(count);
+  // Reservation grid: entry of each tile, (i, k) or (i, j, k), entries in lexicographic order.
+  std::vector<int32_t> entry_of;
+  std::vector<int32_t> entry_ijk;
+  if (grid_mode) {
+    std::vector<std::array<int32_t, 3>> keys(count);
+    for (int t = 0; t < count; ++t)
+      keys[t] = grid_mode == SPMM_RESERVE_3D ? std::array<int32_t, 3>{coords[3 * t], coords[3 * t + 1], coords[3 * t + 2]}
+                                             : std::array<int32_t, 3>{coords[3 * t], 0, coords[3 * t + 2]};
+    std::vector<std::array<int32_t, 3>> uniq(keys);
+    std::sort(uniq.begin(), uniq.end());
+    uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+    entry_of.resize(count);
+    for (int t = 0; t < count; ++t)
+      entry_of[t] = (int32_t)(std::lower_bound(uniq.begin(), uniq.end(), keys[t]) - uniq.begin());
+    b->n_entries = (int)uniq.size();
+    // an entry's coordinates: those of its first tile (for 2D, j of that tile; unused)
+    entry_ijk.assign(3 * uniq.size(), 0);
+    for (int t = count - 1; t >= 0; --t)
+      for (int c = 0; c < 3; ++c) entry_ijk[3 * entry_of[t] + c] = coords[3 * t + c];
+  }
   auto body = [&]() -> spmm_status {
     std::vector<spmm::BatchTileDev> bt(count);
     struct Costed {
@@ -1383,8 +1445,6 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
     int64_t part = 0;
     std::vector<int32_t> rp;
     std::vector<spmm::Seg> segs;
-    std::vector<spmm::LongRow> lrows;
-    std::vector<int32_t> seg_row;  // single-launch form: the split row of each unit
     for (int t = 0; t < count; ++t) {
       const spmm_tile_s* A = tiles[t];
       spmm::BatchTileDev& d = bt[t];
@@ -1437,29 +1497,10 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
           items.push_back({(double)(nz + (r1 - r0)) * width, spmm::BatchItem{t, (int32_t)r0, w, (int32_t)((r1 - r0) << 8)}});
         }
       }
-      // single-launch form: each unit item carries the index of its split row's fix-up
-      // item (the row's arrival counter): fix items are (tile, split row, window) in order
-      const int64_t fix_base = (int64_t)fix.size();
-      if (b->single && A->plan.n_long > 0) {
-        lrows.resize((size_t)A->plan.n_long);
-        HIP_TRY(hipMemcpyAsync(lrows.data(), A->plan.lrow, sizeof(spmm::LongRow) * lrows.size(),
-                               hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        seg_row.assign((size_t)A->plan.n_seg, -1);
-        for (int64_t r = 0; r < A->plan.n_long; ++r)
-          for (int32_t si = lrows[r].s0; si < lrows[r].s1; ++si) seg_row[si] = (int32_t)r;
-      }
       for (int64_t si = 0; si < A->plan.n_seg; ++si)
         for (int w = 0; w < nw_unit; ++w) {
           const double width = (double)std::min<int64_t>(wunit, N[t] - w * wunit);
-          int32_t type = 1;
-          if (b->single) {
-            const int64_t f = fix_base + (int64_t)seg_row[si] * nw_unit + w;
-            if (seg_row[si] < 0 || f >= spmm::kMaxSingleFix)
-              return fail(SPMM_ERR_UNSUPPORTED, "single-launch batch: more than 2^23 split-row fix-ups");
-            type = (int32_t)(1 | (f << 8));
-          }
-          items.push_back({(double)(segs[si].p1 - segs[si].p0) * width, spmm::BatchItem{t, (int32_t)si, w, type}});
+          items.push_back({(double)(segs[si].p1 - segs[si].p0) * width, spmm::BatchItem{t, (int32_t)si, w, 1}});
         }
       for (int64_t r = 0; r < A->plan.n_long; ++r)
         for (int w = 0; w < nw_unit; ++w) fix.push_back(spmm::BatchItem{t, (int32_t)r, w, 2});
@@ -1489,6 +1530,13 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
     std::stable_sort(items.begin(), items.end(), [&](const Costed& x, const Costed& y) {
       const int cx = cls(x.it), cy = cls(y.it);
       if (cx != cy && !b->single) return cx < cy;  // one launch per class: class by class
+      if (grid_mode) {  // entry by entry; inside an entry, its products in j order
+        const int ex = entry_of[x.it.tile], ey = entry_of[y.it.tile];
+        if (ex != ey) return ex < ey;
+        const int jx = coords[3 * x.it.tile + 1], jy = coords[3 * y.it.tile + 1];
+        if (jx != jy) return jx < jy;
+        if (x.it.tile != y.it.tile) return x.it.tile < y.it.tile;
+      }
       if (x.it.tile != y.it.tile) return rank[x.it.tile] < rank[y.it.tile];
       // one column window at a time: the waves then share that window's slice of B
       if (x.it.window != y.it.window) return x.it.window < y.it.window;
@@ -1497,10 +1545,13 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
       return false;                                               // rows keep their order
     });
     std::vector<spmm::BatchItem> list(items.size());
+    unsigned present = 0u;
     for (size_t i = 0; i < items.size(); ++i) {
       list[i] = items[i].it;
       b->class_cnt[cls(list[i])] += 1;
+      present |= 1u << cls(list[i]);
     }
+    b->class_mask = spmm::single_mask_for(present);
     for (int c = 1; c < spmm::kBatchClasses; ++c) b->class_off[c] = b->class_off[c - 1] + b->class_cnt[c - 1];
     b->n_items = (int64_t)list.size();
     b->n_fix = (int64_t)fix.size();
@@ -1508,7 +1559,7 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
     if (dalloc(&b->d_tiles, count) != hipSuccess || dalloc(&b->d_items, b->n_items) != hipSuccess ||
         dalloc(&b->d_fix, b->n_fix) != hipSuccess ||
         (b->persistent && !b->single && dalloc(&b->d_counter, spmm::kBatchCounters) != hipSuccess) ||
-        (b->single && dalloc(&b->d_c64, (int64_t)spmm::kClaimSlices * spmm::kCounter64Stride + b->n_fix) != hipSuccess))
+        (b->single && dalloc(&b->d_c64, (int64_t)spmm::kClaimSlices * spmm::kCounter64Stride) != hipSuccess))
       return fail(SPMM_ERR_ALLOC, "device allocation of the batch failed");
     if (b->single && b->n_items >= ((int64_t)1 << 31))
       return fail(SPMM_ERR_UNSUPPORTED, "work list too long for the single-launch form");
@@ -1519,15 +1570,31 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
       HIP_TRY(hipMemcpyAsync(b->d_fix, fix.data(), sizeof(spmm::BatchItem) * fix.size(), hipMemcpyHostToDevice, s));
     if (b->d_counter) HIP_TRY(hipMemsetAsync(b->d_counter, 0, sizeof(unsigned) * spmm::kBatchCounters, s));
     if (b->d_c64)
-      HIP_TRY(hipMemsetAsync(b->d_c64, 0,
-                             sizeof(unsigned long long) * ((size_t)spmm::kClaimSlices * spmm::kCounter64Stride + b->n_fix),
+      HIP_TRY(hipMemsetAsync(b->d_c64, 0, sizeof(unsigned long long) * (size_t)spmm::kClaimSlices * spmm::kCounter64Stride,
                              s));
     HIP_TRY(hipStreamSynchronize(s));
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (grid_mode) {
+      std::vector<int32_t> eoff(b->n_entries + 1, 0);
+      for (const auto& it : list) eoff[entry_of[it.tile] + 1] += 1;
+      for (int e = 0; e < b->n_entries; ++e) eoff[e + 1] += eoff[e];
+      if (dalloc(&b->d_entry_off, b->n_entries + 1) != hipSuccess ||
+          dalloc(&b->d_entry_ijk, 3 * (int64_t)b->n_entries) != hipSuccess ||
+          dalloc(&b->d_counterE, (int64_t)b->n_entries * spmm::kCounterStride) != hipSuccess)
+        return fail(SPMM_ERR_ALLOC, "device allocation of the reservation grid failed");
+      HIP_TRY(hipMemcpyAsync(b->d_entry_off, eoff.data(), sizeof(int32_t) * eoff.size(), hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(b->d_entry_ijk, entry_ijk.data(), sizeof(int32_t) * entry_ijk.size(), hipMemcpyHostToDevice,
+                             s));
+      HIP_TRY(hipStreamSynchronize(s));
+      // resident workgroups, a multiple of the XCD count so every XCD has workers
+      const int64_t full = (int64_t)cus * spmm::batch_reserve_blocks_per_cu(dt, b->class_mask);
+      b->single_grid = (int)std::max<int64_t>(spmm::kXcds, full - full % spmm::kXcds);
+      return SPMM_OK;
+    }
     if (b->single) {
       // resident workgroups of the union kernel (persistent), at most one wave per item
-      const int64_t full = (int64_t)cus * spmm::batch_single_blocks_per_cu(dt);
+      const int64_t full = (int64_t)cus * spmm::batch_single_blocks_per_cu(dt, b->class_mask);
       const int64_t need = (b->n_items + spmm::kBlock / 64 - 1) / (spmm::kBlock / 64);
       b->single_grid = (int)std::max<int64_t>(1, std::min(full, need));
       return SPMM_OK;
@@ -1559,6 +1626,31 @@ spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t
   }
   *out = b;
   return SPMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+spmm_status spmm_batch_create(int count, const spmm_tile_t* tiles, const int64_t* N, spmm_dtype dtype,
+                              int64_t item_nnz, unsigned flags, void* stream, spmm_batch_t* out) {
+  spmm::TraceRange trace_range("spmm_batch_create");
+  return batch_create_impl(count, tiles, N, dtype, item_nnz, flags, nullptr, 0, stream, out);
+}
+
+spmm_status spmm_batch_create_grid(int count, const spmm_tile_t* tiles, const int64_t* N, spmm_dtype dtype,
+                                   const int32_t* coords, int mode, int64_t item_nnz, void* stream, spmm_batch_t* out) {
+  spmm::TraceRange trace_range("spmm_batch_create_grid");
+  if (!out) return fail(SPMM_ERR_INVALID_ARG, "out is null");
+  *out = nullptr;
+  if (mode != SPMM_RESERVE_2D && mode != SPMM_RESERVE_3D && mode != SPMM_RESERVE_OWN)
+    return fail(SPMM_ERR_INVALID_ARG, "unknown reservation mode %d", mode);
+  if (!coords) return fail(SPMM_ERR_INVALID_ARG, "coords is null");
+  for (int t = 0; t < count; ++t)
+    for (int c = 0; c < 3; ++c)
+      if (coords[3 * t + c] < 0) return fail(SPMM_ERR_INVALID_ARG, "tile %d: negative grid coordinate", t);
+  return batch_create_impl(count, tiles, N, dtype, item_nnz, SPMM_BATCH_SINGLE | SPMM_BATCH_PERSISTENT, coords, mode,
+                           stream, out);
 }
 
 spmm_status spmm_batch_destroy(spmm_batch_t batch) {
@@ -1607,10 +1699,19 @@ spmm_status spmm_batched(spmm_batch_t batch, const void* const* B, const int64_t
   P.partial = static_cast<float*>(workspace);
   P.counter = batch->d_counter;
   P.accumulate = accumulate ? 1 : 0;
+  if (batch->grid_mode) {
+    P.entry_off = batch->d_entry_off;
+    P.entry_ijk = batch->d_entry_ijk;
+    P.n_entries = batch->n_entries;
+    P.grid_mode = batch->grid_mode;
+    P.counterE = batch->d_counterE;
+    HIP_TRY(spmm::launch_batch_reserve(P, batch->single_grid, batch->class_mask, batch->dt,
+                                       static_cast<hipStream_t>(stream)));
+    return SPMM_OK;
+  }
   if (batch->single) {
     P.counter64 = batch->d_c64;
-    P.arrive = batch->d_c64 + (int64_t)spmm::kClaimSlices * spmm::kCounter64Stride;
-    HIP_TRY(spmm::launch_batch_single(P, batch->single_grid, batch->dt, batch->persistent,
+    HIP_TRY(spmm::launch_batch_single(P, batch->single_grid, batch->class_mask, batch->dt, batch->persistent,
                                       static_cast<hipStream_t>(stream)));
     return SPMM_OK;
   }

@@ -21,6 +21,8 @@
 // Items write disjoint output rows (split rows: disjoint partial rows) and every
 // row is summed in CSR order by one wave, so the result does not depend on which
 // wave runs which item; split rows are finished by a second, fix-up launch.
+#include <algorithm>
+
 #include "elem.hpp"
 #include "fwd_common.hpp"
 #include "internal.hpp"
@@ -333,19 +335,17 @@ __global__ void __launch_bounds__(kBlock) batch_reset(unsigned* counter, int n) 
 
 // ---- Single-launch form ---------------------------------------------------------
 // Every item class in one kernel: each item (one wave) switches, uniformly, to its
-// class's code, so the whole batch is one launch.  Split rows need no second launch:
-// a unit, after storing its partial row, releases it and counts itself on its row's
-// arrival counter; the unit that completes the count acquires the others' partials and
-// sums them in unit order (the same fixed order as the fix-up kernel, so results are
-// bit-identical to the per-class form).
+// class's code, so the whole batch is one launch, followed by the fix-up launch when
+// some tile has split rows.  (Summing a split row in the same launch, by the unit that
+// arrives last, needs an agent-scope release per unit, and on this GPU that writes back
+// the XCD's L2 each time: on the R-MAT row block's 16 products, 1.29M units per call,
+// it made the launch 5x slower than a separate fix-up launch.)
 //
-// Counters are 64-bit and never reset, which keeps the form to one launch (graph
-// replays included): every call adds exactly n_units to a split row's arrival counter,
-// so the last arriver of each call is the one whose count becomes a multiple of
-// n_units; in the persistent hand-out every wave makes exactly one failed claim on each
-// slice it visits (all of them), so every call adds exactly items + waves to a slice's
-// counter and a claim's place in this call is its value modulo that.  Calls on one
-// batch must not overlap (they never could: they share the workspace).
+// The claim counters of the persistent hand-out are 64-bit and never reset, which keeps
+// the items to one launch (graph replays included): every wave makes exactly one failed
+// claim on each slice it visits (all of them), so every call adds exactly items + waves
+// to a slice's counter and a claim's place in this call is its value modulo that.
+// Calls on one batch must not overlap (they never could: they share the workspace).
 
 __device__ __forceinline__ uint64_t claim64(unsigned long long* counter, int s, int lane) {
   unsigned long long c = 0;
@@ -355,9 +355,11 @@ __device__ __forceinline__ uint64_t claim64(unsigned long long* counter, int s, 
   return ((uint64_t)hi << 32) | lo;
 }
 
-template <typename E, bool ACC>
+// MASK: the item classes a kernel instance contains (bit c = class c); the host picks the
+// narrowest precompiled mask that covers the classes of its batch, since one kernel for
+// every class holds the registers of the widest one.
+template <typename E, bool ACC, unsigned MASK>
 __device__ __forceinline__ void union_item(const BatchParams& P, int64_t it, int32_t* s_pref, int32_t* s_beg) {
-  const int lane = threadIdx.x & 63;
   const BatchItem item = P.items[it];
   const BatchTileDev& bt = P.tiles[item.tile];
   const int type = item.type & 255;
@@ -370,40 +372,20 @@ __device__ __forceinline__ void union_item(const BatchParams& P, int64_t it, int
   else
     cls = kClassRowsplit + (bt.G == 8 ? 0 : (bt.G == 16 ? 1 : (bt.G == 32 ? 2 : 3)));
   switch (cls) {
-    case 0: run_item<E, ACC, 0>(P, it, s_pref, s_beg); break;
-    case 1: run_item<E, ACC, 1>(P, it, s_pref, s_beg); break;
-    case 2: run_item<E, ACC, 2>(P, it, s_pref, s_beg); break;
-    case 3: run_item<E, ACC, 3>(P, it, s_pref, s_beg); break;
-    case 4: run_item<E, ACC, 4>(P, it, s_pref, s_beg); break;
-    case 5: run_item<E, ACC, 5>(P, it, s_pref, s_beg); break;
-    case 6: run_item<E, ACC, 6>(P, it, s_pref, s_beg); break;
-    case 7: run_item<E, ACC, 7>(P, it, s_pref, s_beg); break;
-    case 8: run_item<E, ACC, 8>(P, it, s_pref, s_beg); break;
-    default: run_item<E, ACC, 9>(P, it, s_pref, s_beg); break;
-  }
-  if (type != 1) return;
-  // release this unit's partial row, count it, and sum the row if it was the last
-  __threadfence();
-  const int64_t f = (int64_t)(item.type >> 8);
-  unsigned long long old = 0;
-  if (lane == 0) old = atomicAdd(P.arrive + f, 1ull);
-  const uint64_t o = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(old >> 32), 0) << 32) |
-                     (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)old, 0);
-  const BatchItem fx = P.fix[f];
-  const BatchTileDev& ft = P.tiles[fx.tile];
-  const LongRow lr = ft.lrow[fx.a];
-  const uint64_t n = (uint64_t)(lr.s1 - lr.s0);
-  if ((o + 1) % n != 0) return;
-  __threadfence();
-  const Ops<E> op = item_ops<E>(P, fx.tile);
-  switch (ft.V) {
-    case 1: fix_row<1, E, ACC>(P, ft, op, fx.a, fx.window); return;
-    case 2: fix_row<2, E, ACC>(P, ft, op, fx.a, fx.window); return;
-    default: fix_row<4, E, ACC>(P, ft, op, fx.a, fx.window); return;
+    case 0: if constexpr ((MASK >> 0) & 1u) run_item<E, ACC, 0>(P, it, s_pref, s_beg); break;
+    case 1: if constexpr ((MASK >> 1) & 1u) run_item<E, ACC, 1>(P, it, s_pref, s_beg); break;
+    case 2: if constexpr ((MASK >> 2) & 1u) run_item<E, ACC, 2>(P, it, s_pref, s_beg); break;
+    case 3: if constexpr ((MASK >> 3) & 1u) run_item<E, ACC, 3>(P, it, s_pref, s_beg); break;
+    case 4: if constexpr ((MASK >> 4) & 1u) run_item<E, ACC, 4>(P, it, s_pref, s_beg); break;
+    case 5: if constexpr ((MASK >> 5) & 1u) run_item<E, ACC, 5>(P, it, s_pref, s_beg); break;
+    case 6: if constexpr ((MASK >> 6) & 1u) run_item<E, ACC, 6>(P, it, s_pref, s_beg); break;
+    case 7: if constexpr ((MASK >> 7) & 1u) run_item<E, ACC, 7>(P, it, s_pref, s_beg); break;
+    case 8: if constexpr ((MASK >> 8) & 1u) run_item<E, ACC, 8>(P, it, s_pref, s_beg); break;
+    default: if constexpr ((MASK >> 9) & 1u) run_item<E, ACC, 9>(P, it, s_pref, s_beg); break;
   }
 }
 
-template <typename E, bool ACC, bool PERSIST>
+template <typename E, bool ACC, bool PERSIST, unsigned MASK>
 __global__ void __launch_bounds__(kBlock) batch_union(BatchParams P) {
   __shared__ int32_t s_mem[(kBlock / 64) * 129];
   const int lane = threadIdx.x & 63;
@@ -427,22 +409,162 @@ __global__ void __launch_bounds__(kBlock) batch_union(BatchParams P) {
         continue;
       }
       got = claim64(P.counter64, s, lane);  // the next item, in flight during this one
-      union_item<E, ACC>(P, (int64_t)__builtin_amdgcn_readfirstlane((int)it), s_pref, s_beg);
+      union_item<E, ACC, MASK>(P, (int64_t)__builtin_amdgcn_readfirstlane((int)it), s_pref, s_beg);
     }
   } else {
     const int64_t it = (int64_t)blockIdx.x * (kBlock / 64) + w;
-    if (it < P.n_items) union_item<E, ACC>(P, (int64_t)__builtin_amdgcn_readfirstlane((int)it), s_pref, s_beg);
+    if (it < P.n_items) union_item<E, ACC, MASK>(P, (int64_t)__builtin_amdgcn_readfirstlane((int)it), s_pref, s_beg);
   }
 }
 
-template <typename E, bool ACC>
-hipError_t launch_single_t(const BatchParams& P, int grid, bool persistent, hipStream_t s) {
-  if (P.n_items == 0) return hipSuccess;
-  if (persistent)
-    hipLaunchKernelGGL((batch_union<E, ACC, true>), dim3((unsigned)grid), dim3(kBlock), 0, s, P);
-  else
-    hipLaunchKernelGGL((batch_union<E, ACC, false>), dim3((unsigned)((P.n_items + 3) / 4)), dim3(kBlock), 0, s, P);
+// ---- Reservation-grid hand-out -------------------------------------------------
+// The work-stealing algorithms of Section 3.4 (Algorithm 3) reserve work with a
+// fetch-and-add on an element of a work grid: a 2-D grid over the stationary operand's
+// tiles (i, k), whose counter hands out the next piece of work of that tile (here the
+// next item: a row range and window of the next column block j, in j order), or, for
+// locality-aware stealing, a 3-D grid over the products (i, j, k).  Workers (the waves
+// of resident workgroups) do their own work first and then steal.  Ownership follows
+// the XCD (workgroup b runs on XCD b mod 8): with E >= 8 entries XCD x owns the x-th
+// eighth of them, with fewer, entry x E / 8, so an entry's workers share an L2.
+//  * SPMM_RESERVE_2D: own entries, then every other entry in cyclic order (random stealing).
+//  * SPMM_RESERVE_3D: entries sharing the first own entry's C tile (i, j), then its A tile
+//    (i, k), then its B tile (k, j), then the rest, each pass in cyclic order.
+//  * SPMM_RESERVE_OWN: own entries only (no stealing), the static assignment that
+//    stealing is measured against.
+__device__ __forceinline__ bool reserve_in_pass(const int32_t* ijk, int e, int e0, int pass) {
+  const int i = ijk[3 * e], j = ijk[3 * e + 1], k = ijk[3 * e + 2];
+  const int i0 = ijk[3 * e0], j0 = ijk[3 * e0 + 1], k0 = ijk[3 * e0 + 2];
+  const bool c = i == i0 && j == j0, a = i == i0 && k == k0, b = k == k0 && j == j0;
+  switch (pass) {
+    case 0: return c;
+    case 1: return a && !c;
+    case 2: return b && !c && !a;
+    default: return !c && !a && !b;
+  }
+}
+
+template <typename E, bool ACC, unsigned MASK>
+__global__ void __launch_bounds__(kBlock) batch_reserve(BatchParams P) {
+  __shared__ int32_t s_mem[(kBlock / 64) * 129];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  int32_t* s_pref = s_mem + w * 129;
+  int32_t* s_beg = s_pref + 65;
+  const int ne = P.n_entries;
+  const int x = (int)(blockIdx.x % kXcds);
+  int own_lo, own_n;
+  if (ne >= kXcds) {
+    own_lo = (x * ne + kXcds - 1) / kXcds;
+    own_n = ((x + 1) * ne + kXcds - 1) / kXcds - own_lo;
+  } else {
+    own_lo = x * ne / kXcds;
+    own_n = 1;
+  }
+  const bool three_d = P.grid_mode == SPMM_RESERVE_3D;
+  const int visit = P.grid_mode == SPMM_RESERVE_OWN ? own_n : ne;
+  for (int pass = 0; pass < (three_d ? 4 : 1); ++pass) {
+    for (int idx = 0; idx < visit; ++idx) {
+      const int e = (own_lo + idx) % ne;
+      if (three_d && !reserve_in_pass(P.entry_ijk, e, own_lo, pass)) continue;
+      const int64_t lo = P.entry_off[e];
+      const int64_t n = (int64_t)P.entry_off[e + 1] - lo;
+      unsigned got = claim(P.counterE, e, lane);
+      while ((int64_t)got < n) {
+        const unsigned next = claim(P.counterE, e, lane);  // the next item, in flight during this one
+        union_item<E, ACC, MASK>(P, (int64_t)__builtin_amdgcn_readfirstlane((int)(lo + got)), s_pref, s_beg);
+        got = next;
+      }
+    }
+  }
+}
+
+template <typename E, bool ACC, unsigned MASK>
+hipError_t launch_reserve_m(const BatchParams& P, int grid, hipStream_t s) {
+  const int nc = P.n_entries * kCounterStride;
+  hipLaunchKernelGGL(batch_reset, dim3((unsigned)((nc + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, P.counterE, nc);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((batch_reserve<E, ACC, MASK>), dim3((unsigned)grid), dim3(kBlock), 0, s, P);
+  e = hipGetLastError();
+  if (e != hipSuccess || P.n_fix == 0) return e;
+  hipLaunchKernelGGL((batch_fixup<E, ACC>), dim3((unsigned)((P.n_fix + 3) / 4)), dim3(kBlock), 0, s, P);
   return hipGetLastError();
+}
+
+template <typename E, bool ACC>
+hipError_t launch_reserve_t(const BatchParams& P, int grid, unsigned mask, hipStream_t s) {
+  if (P.n_items == 0) return hipSuccess;
+  switch (mask) {
+    case kMaskStream1: return launch_reserve_m<E, ACC, kMaskStream1>(P, grid, s);
+    case kMaskStream2: return launch_reserve_m<E, ACC, kMaskStream2>(P, grid, s);
+    case kMaskStream4: return launch_reserve_m<E, ACC, kMaskStream4>(P, grid, s);
+    case kMaskRowsplit: return launch_reserve_m<E, ACC, kMaskRowsplit>(P, grid, s);
+    default: return launch_reserve_m<E, ACC, kMaskAll>(P, grid, s);
+  }
+}
+
+// C += P_0 + ... + P_{n-1} over a rows x N block, in that order; one thread per V elements.
+template <int V, typename E>
+__global__ void __launch_bounds__(kBlock) accumulate_n_kernel(typename E::T* C, int64_t ldc, AccList L, int64_t rows,
+                                                              int64_t N) {
+  const int64_t per_row = N / V;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < rows * per_row; i += (int64_t)gridDim.x * kBlock) {
+    const int64_t r = i / per_row, c = (i - r * per_row) * V;
+    float x[V];
+    load_vec<E, V>(C + r * ldc + c, x);
+    for (int t = 0; t < L.n; ++t) {
+      float y[V];
+      load_vec<E, V>(static_cast<const typename E::T*>(L.p[t]) + r * L.ld[t] + c, y);
+#pragma unroll
+      for (int e = 0; e < V; ++e) x[e] += y[e];
+    }
+    store_vec<E, V>(C + r * ldc + c, x);
+  }
+}
+
+template <typename E, bool ACC, unsigned MASK>
+hipError_t launch_single_m(const BatchParams& P, int grid, bool persistent, hipStream_t s) {
+  if (persistent)
+    hipLaunchKernelGGL((batch_union<E, ACC, true, MASK>), dim3((unsigned)grid), dim3(kBlock), 0, s, P);
+  else
+    hipLaunchKernelGGL((batch_union<E, ACC, false, MASK>), dim3((unsigned)((P.n_items + 3) / 4)), dim3(kBlock), 0, s,
+                       P);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || P.n_fix == 0) return e;
+  hipLaunchKernelGGL((batch_fixup<E, ACC>), dim3((unsigned)((P.n_fix + 3) / 4)), dim3(kBlock), 0, s, P);
+  return hipGetLastError();
+}
+
+template <typename E, bool ACC>
+hipError_t launch_single_t(const BatchParams& P, int grid, bool persistent, unsigned mask, hipStream_t s) {
+  if (P.n_items == 0) return hipSuccess;
+  switch (mask) {
+    case kMaskStream1: return launch_single_m<E, ACC, kMaskStream1>(P, grid, persistent, s);
+    case kMaskStream2: return launch_single_m<E, ACC, kMaskStream2>(P, grid, persistent, s);
+    case kMaskStream4: return launch_single_m<E, ACC, kMaskStream4>(P, grid, persistent, s);
+    case kMaskRowsplit: return launch_single_m<E, ACC, kMaskRowsplit>(P, grid, persistent, s);
+    default: return launch_single_m<E, ACC, kMaskAll>(P, grid, persistent, s);
+  }
+}
+
+template <typename E, unsigned MASK>
+int occ_of(bool reserve) {
+  int n = 0;
+  const hipError_t e =
+      reserve ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_reserve<E, false, MASK>, kBlock, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_union<E, false, true, MASK>, kBlock, 0);
+  return (e == hipSuccess && n > 0) ? n : 2;
+}
+
+template <typename E>
+int occ_mask(unsigned mask, bool reserve) {
+  switch (mask) {
+    case kMaskStream1: return occ_of<E, kMaskStream1>(reserve);
+    case kMaskStream2: return occ_of<E, kMaskStream2>(reserve);
+    case kMaskStream4: return occ_of<E, kMaskStream4>(reserve);
+    case kMaskRowsplit: return occ_of<E, kMaskRowsplit>(reserve);
+    default: return occ_of<E, kMaskAll>(reserve);
+  }
 }
 
 template <typename E, bool ACC, int CLS>
@@ -523,20 +645,63 @@ hipError_t launch_batch(const BatchParams& P, const int64_t* off, const int64_t*
                       : launch_batch_t<BF16E, false>(P, off, cnt, grid, persistent, s);
 }
 
-hipError_t launch_batch_single(const BatchParams& P, int grid, DT dt, bool persistent, hipStream_t s) {
+hipError_t launch_batch_single(const BatchParams& P, int grid, unsigned mask, DT dt, bool persistent, hipStream_t s) {
   if (dt == DT::F32)
-    return P.accumulate ? launch_single_t<F32E, true>(P, grid, persistent, s)
-                        : launch_single_t<F32E, false>(P, grid, persistent, s);
-  return P.accumulate ? launch_single_t<BF16E, true>(P, grid, persistent, s)
-                      : launch_single_t<BF16E, false>(P, grid, persistent, s);
+    return P.accumulate ? launch_single_t<F32E, true>(P, grid, persistent, mask, s)
+                        : launch_single_t<F32E, false>(P, grid, persistent, mask, s);
+  return P.accumulate ? launch_single_t<BF16E, true>(P, grid, persistent, mask, s)
+                      : launch_single_t<BF16E, false>(P, grid, persistent, mask, s);
 }
 
-int batch_single_blocks_per_cu(DT dt) {
-  int n = 0;
-  const hipError_t e = dt == DT::F32
-                           ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_union<F32E, false, true>, kBlock, 0)
-                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_union<BF16E, false, true>, kBlock, 0);
-  return (e == hipSuccess && n > 0) ? n : 2;
+hipError_t launch_batch_reserve(const BatchParams& P, int grid, unsigned mask, DT dt, hipStream_t s) {
+  if (dt == DT::F32)
+    return P.accumulate ? launch_reserve_t<F32E, true>(P, grid, mask, s)
+                        : launch_reserve_t<F32E, false>(P, grid, mask, s);
+  return P.accumulate ? launch_reserve_t<BF16E, true>(P, grid, mask, s)
+                      : launch_reserve_t<BF16E, false>(P, grid, mask, s);
+}
+
+int batch_reserve_blocks_per_cu(DT dt, unsigned mask) {
+  return dt == DT::F32 ? occ_mask<F32E>(mask, true) : occ_mask<BF16E>(mask, true);
+}
+
+template <typename E, int V>
+hipError_t launch_acc_n(void* C, int64_t ldc, const AccList& L, int64_t rows, int64_t N, hipStream_t s) {
+  const int64_t n = rows * (N / V);
+  if (n == 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, kMaxGridBlocks);
+  hipLaunchKernelGGL((accumulate_n_kernel<V, E>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                     static_cast<typename E::T*>(C), ldc, L, rows, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_accumulate_n(void* C, int64_t ldc, const void* const* Pt, const int64_t* ldp, int n, int64_t rows,
+                               int64_t N, DT dt, int V, hipStream_t s) {
+  // partials in launches of up to kAccMax each, in order
+  for (int t0 = 0; t0 < n; t0 += kAccMax) {
+    AccList L{};
+    L.n = std::min(kAccMax, n - t0);
+    for (int t = 0; t < L.n; ++t) {
+      L.p[t] = Pt[t0 + t];
+      L.ld[t] = ldp[t0 + t];
+    }
+    hipError_t e;
+    if (dt == DT::F32) {
+      e = V == 4 ? launch_acc_n<F32E, 4>(C, ldc, L, rows, N, s)
+                 : (V == 2 ? launch_acc_n<F32E, 2>(C, ldc, L, rows, N, s) : launch_acc_n<F32E, 1>(C, ldc, L, rows, N, s));
+    } else {
+      e = V == 8 ? launch_acc_n<BF16E, 8>(C, ldc, L, rows, N, s)
+                 : (V == 4 ? launch_acc_n<BF16E, 4>(C, ldc, L, rows, N, s)
+                           : (V == 2 ? launch_acc_n<BF16E, 2>(C, ldc, L, rows, N, s)
+                                     : launch_acc_n<BF16E, 1>(C, ldc, L, rows, N, s)));
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+int batch_single_blocks_per_cu(DT dt, unsigned mask) {
+  return dt == DT::F32 ? occ_mask<F32E>(mask, false) : occ_mask<BF16E>(mask, false);
 }
 
 void batch_blocks_per_cu(DT dt, int* out) {

@@ -170,21 +170,43 @@ struct BatchParams {
   float* partial;
   unsigned* counter;       // persistent mode: the class's kClaimSlices claim counters
   int accumulate;
-  // Single-launch form (every class in one kernel): per-XCD claim counters and one
-  // arrival counter per fix-up item, both 64-bit and never reset (see batch_union).
+  // Single-launch form (every class in one kernel): per-XCD claim counters, 64-bit and
+  // never reset (see batch_union).
   unsigned long long* counter64;
-  unsigned long long* arrive;
+  // Reservation-grid hand-out (the single-GPU form of Algorithm 3's work grids): the list is
+  // grouped into n_entries entries (items [entry_off[e], entry_off[e + 1])), entry e with
+  // grid coordinates entry_ijk[3e..3e+2] and a claim counter counterE[e * kCounterStride],
+  // zeroed by a reset kernel before each call.
+  const int32_t* entry_off;
+  const int32_t* entry_ijk;
+  int32_t n_entries;
+  int32_t grid_mode;       // SPMM_RESERVE_*
+  unsigned* counterE;
 };
-// Single-launch form: a unit item's type is 1 | (fix item << 8), so at most 2^23 fix items.
-constexpr int64_t kMaxSingleFix = (int64_t)1 << 23;
 // 64-bit claim counters of the single-launch form, 32 apart (one 256-byte line each).
 constexpr int kCounter64Stride = 32;
-// One launch of the single-launch form: every item of the list (tile by tile) by one
-// kernel that switches on the item's class; split rows are summed by the unit that
-// arrives last.  persistent = false: one wave per item (grid = ceil(n_items / 4));
-// true: `grid` resident workgroups claiming from per-XCD slices.
-hipError_t launch_batch_single(const BatchParams& P, int grid, DT dt, bool persistent, hipStream_t s);
-int batch_single_blocks_per_cu(DT dt);
+// The single-launch form: every item of the list (tile by tile) by one kernel that
+// switches on the item's class, then, when some tile has split rows, the fix-up launch.
+// persistent = false: one wave per item (grid = ceil(n_items / 4)); true: `grid`
+// resident workgroups claiming from per-XCD slices.
+// `mask` (one of the kMask* below) selects the kernel instance that holds just the item
+// classes of the batch.
+hipError_t launch_batch_single(const BatchParams& P, int grid, unsigned mask, DT dt, bool persistent, hipStream_t s);
+int batch_single_blocks_per_cu(DT dt, unsigned mask);
+// Reservation-grid hand-out: a reset kernel zeroes the entry counters, then `grid`
+// resident workgroups claim items entry by entry in each worker's visiting order.
+hipError_t launch_batch_reserve(const BatchParams& P, int grid, unsigned mask, DT dt, hipStream_t s);
+int batch_reserve_blocks_per_cu(DT dt, unsigned mask);
+// C = C + P_0 + ... + P_{n-1} (in that order, FP32 sums, one rounding for BF16); the
+// partials go to the kernel kAccMax at a time.
+constexpr int kAccMax = 16;
+struct AccList {
+  const void* p[kAccMax];
+  int64_t ld[kAccMax];
+  int n;
+};
+hipError_t launch_accumulate_n(void* C, int64_t ldc, const void* const* Pt, const int64_t* ldp, int n, int64_t rows,
+                               int64_t N, DT dt, int V, hipStream_t s);
 // Items a persistent wave claims with one fetch-and-add.
 constexpr int kClaimChunk = 1;
 // The chip's XCDs (each with its own L2); workgroups are dealt to them round-robin
@@ -201,6 +223,19 @@ constexpr int kClassRowsplit = 3;
 constexpr int kClassUnit = 7;
 constexpr int kBatchClasses = 10;
 constexpr int kBatchCounters = kBatchClasses * kClaimSlices * kCounterStride;
+// Class sets of the precompiled single-launch instances (bit c = item class c): stream
+// V = 1, 2 or 4 with the units of the same V; every row-split class with every unit; all.
+constexpr unsigned kMaskStream1 = (1u << 0) | (1u << kClassUnit);
+constexpr unsigned kMaskStream2 = (1u << 1) | (1u << (kClassUnit + 1));
+constexpr unsigned kMaskStream4 = (1u << 2) | (1u << (kClassUnit + 2));
+constexpr unsigned kMaskRowsplit = (0xFu << kClassRowsplit) | (0x7u << kClassUnit);
+constexpr unsigned kMaskAll = (1u << kBatchClasses) - 1u;
+// The narrowest of those sets that contains `present`.
+inline unsigned single_mask_for(unsigned present) {
+  for (unsigned m : {kMaskStream1, kMaskStream2, kMaskStream4, kMaskRowsplit})
+    if ((present & ~m) == 0u) return m;
+  return kMaskAll;
+}
 // One launch per item class present (off/cnt: the class's slice of the item list;
 // grid: its workgroups), then the fix-up.  persistent = false: one wave per item;
 // true: `grid` resident workgroups claim kClaimChunk items at a time from the

@@ -336,6 +336,23 @@ def spmm_bwd(tile: Tile, dC: torch.Tensor, B: torch.Tensor, want_dA: bool = True
     return (dA if want_dA else None), (dB if want_dB else None)
 
 
+def spmm_tile_accumulate_n(C: torch.Tensor, Ps: Sequence[torch.Tensor],
+                           stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """C += Ps[0] + Ps[1] + ... in that order (the owner draining its queue of partial tiles)."""
+    if C.dtype not in _DTYPES or not C.is_cuda:
+        raise ValueError("C must be a device float32 or bfloat16 tensor")
+    for P in Ps:
+        if P.dtype != C.dtype or P.shape != C.shape or not P.is_cuda:
+            raise ValueError("every partial must be a device tensor of C's shape and dtype")
+    n = len(Ps)
+    ptrs = (ctypes.c_void_p * max(n, 1))(*[P.data_ptr() for P in Ps])
+    lds = (ctypes.c_int64 * max(n, 1))(*[_row_major_ld(P, "P") for P in Ps])
+    rows, N = C.shape
+    check(lib().spmm_tile_accumulate_n(C.data_ptr(), _row_major_ld(C, "C"), ptrs, lds, n, rows, N, _DTYPES[C.dtype],
+                                       _stream_ptr(stream)))
+    return C
+
+
 def spmm_tile_accumulate(C: torch.Tensor, Ptile: torch.Tensor, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
     """C += Ptile (the owner-side accumulate of a stationary-A partial product)."""
     if C.dtype != Ptile.dtype or C.dtype not in _DTYPES or C.shape != Ptile.shape or not (C.is_cuda and Ptile.is_cuda):
@@ -424,9 +441,29 @@ def spmm_batch_create(tiles: Sequence[Tile], Ns: Sequence[int], dtype=torch.floa
     return Batch(h.value, list(tiles), [int(n) for n in Ns], dtype)
 
 
+RESERVE_MODES = {"2d": _lib.SPMM_RESERVE_2D, "3d": _lib.SPMM_RESERVE_3D, "own": _lib.SPMM_RESERVE_OWN}
+
+
+def spmm_batch_create_grid(tiles: Sequence[Tile], Ns: Sequence[int], coords: Sequence[Tuple[int, int, int]],
+                           mode: str = "2d", dtype=torch.float32, item_nnz: int = 0,
+                           stream: Optional[torch.cuda.Stream] = None) -> Batch:
+    """A batch of component products C(i,j) (+)= A(i,k) B(k,j), tile t at coords[t] = (i, j, k), handed
+    out through a reservation grid: "2d" (over (i, k), random stealing), "3d" (over (i, j, k),
+    locality-aware stealing) or "own" (over (i, k), no stealing)."""
+    if len(coords) != len(tiles):
+        raise ValueError("one (i, j, k) per tile")
+    arr = (ctypes.c_void_p * len(tiles))(*[t.handle for t in tiles])
+    ns = (ctypes.c_int64 * len(tiles))(*[int(n) for n in Ns])
+    cc = (ctypes.c_int32 * (3 * len(tiles)))(*[int(v) for c in coords for v in c])
+    h = ctypes.c_void_p()
+    check(lib().spmm_batch_create_grid(len(tiles), arr, ns, _DTYPES[dtype], cc, RESERVE_MODES[mode], item_nnz,
+                                       _stream_ptr(stream), ctypes.byref(h)))
+    return Batch(h.value, list(tiles), [int(n) for n in Ns], dtype)
+
+
 def spmm_batched(batch: Batch, Bs: Sequence[torch.Tensor], Cs: Sequence[torch.Tensor], accumulate: bool = False,
                  workspace: Optional[torch.Tensor] = None, stream: Optional[torch.cuda.Stream] = None) -> None:
-    """C_t = [C_t] + A_t B_t for every tile of the batch (one launch per kernel class, then the fix-up)."""
+    """C_t = [C_t] + A_t B_t for every tile of the batch, in the launch form the batch was built with."""
     if len(Bs) != len(batch.tiles) or len(Cs) != len(batch.tiles):
         raise ValueError("one B and one C per tile")
     b, lb, c, lc = batch.operand_arrays(Bs, Cs)

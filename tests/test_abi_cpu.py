@@ -266,3 +266,26 @@ def test_noalloc_forward_argument_errors():
     assert L.spmm_noalloc_scratch_bytes() == 64 << 20
     assert L.spmm_fwd_noalloc(None, 0, None, None, 0, None, 8, 0, 8, 0, None) == 1
     assert L.spmm_last_error()
+
+
+def test_reservation_grid_and_accumulate_n_argument_errors():
+    """The reservation-grid batch and the multi-partial accumulate check their arguments before any
+    HIP call."""
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    coords = (ctypes.c_int32 * 3)(0, 0, 0)
+    assert L.spmm_batch_create_grid(1, None, None, 0, coords, 1, 0, None, None) == 1          # null out
+    assert L.spmm_batch_create_grid(1, None, None, 0, coords, 9, 0, None, ctypes.byref(h)) == 1  # bad mode
+    assert L.spmm_batch_create_grid(1, None, None, 0, None, 1, 0, None, ctypes.byref(h)) == 1    # null coords
+    bad = (ctypes.c_int32 * 3)(0, -1, 0)
+    assert L.spmm_batch_create_grid(1, None, None, 0, bad, 1, 0, None, ctypes.byref(h)) == 1     # negative coord
+    assert L.spmm_batch_create_grid(1, None, None, 0, coords, 1, 0, None, ctypes.byref(h)) == 1  # null tiles
+    assert L.spmm_batch_create_grid(1, None, None, 0, coords, 1, 7, None, ctypes.byref(h)) == 1  # item_nnz
+    assert h.value is None
+    ptrs = (ctypes.c_void_p * 1)(0x1000)
+    lds = (ctypes.c_int64 * 1)(8)
+    assert L.spmm_tile_accumulate_n(0x2000, 8, ptrs, lds, 1, 4, 8, 7, None) == 1   # bad dtype
+    assert L.spmm_tile_accumulate_n(0x2000, 8, None, None, 1, 4, 8, 0, None) == 1  # null partial arrays
+    lds[0] = 4
+    assert L.spmm_tile_accumulate_n(0x2000, 8, ptrs, lds, 1, 4, 8, 0, None) == 1   # ldp < N
+    assert L.spmm_tile_accumulate_n(0x2000, 8, ptrs, lds, -1, 4, 8, 0, None) == 1  # negative count
