@@ -26,8 +26,8 @@ the FP64 oracle on a sample.  Other workloads:
                             column blocks of N = 128, each added into its C tile
     stationary_a_rmat22_rowblock0_4x4_grid
                             stationary-A step of a row block with work stealing: the 16 products
-                            A(0,k) B(k,j) handed out through a 2-D reservation grid, partials drained
-                            in k order; the 3-D grid, no stealing, no grid and a launch per product
+                            A(0,k) B(k,j) handed out through a 3-D reservation grid, partials drained
+                            in k order; the 2-D grid, no stealing, no grid and a launch per product
                             are reported beside it
     spgemm_rmat18_ef16_aa   local SpGEMM C = A A, R-MAT scale 18, edge factor 16 (numeric phase;
                             the symbolic phase is reported beside it)
@@ -803,18 +803,19 @@ class StationaryAGrid(Workload):
     """The stationary-A step of one row block with work stealing (Section 3.4, Algorithm 3), on one
     GPU: row block 0 of the R-MAT scale-22 4 x 4 grid, A(0,k) for k = 0..3 (the stationary
     tiles, nnz 20.7M / 7.1M / 7.1M / 2.4M), against B(k,j) for 4 column blocks j of N = 128.
-    The 16 component products A(0,k) B(k,j) form one batch handed out through a 2-D
-    reservation grid over (0, k): workers (waves of resident workgroups, owners by XCD) take
-    their own tile's products in j order with one fetch-and-add per item, then steal from the
-    other tiles' entries; each product writes a partial tile, and the owner of C(0,j) drains its
-    four partials in k order (spmm_tile_accumulate_n).  Beside it: the locality-aware 3-D grid,
-    the grid without stealing, the single launch without a grid, and one spmm_fwd launch per
+    The 16 component products A(0,k) B(k,j) form one batch handed out through a 3-D
+    reservation grid over (0, j, k) (locality-aware stealing): workers (waves of resident
+    workgroups, owners by XCD) take the items of their own products with one fetch-and-add per
+    item, then those sharing their C tile, A tile, B tile, then the rest; each product writes a
+    partial tile, and the owner of C(0,j) drains its four partials in k order
+    (spmm_tile_accumulate_n).  Beside it: the 2-D grid over (0, k) (random stealing), the 2-D
+    grid without stealing, the single launch without a grid, and one spmm_fwd launch per
     product (the static order)."""
 
     def __init__(self, name, config):
         self.name = name
         self.config = config
-        self.kernel = "spmm_batched (batch_reserve, 2-D grid) + spmm_tile_accumulate_n"
+        self.kernel = "spmm_batched (batch_reserve, 3-D grid) + spmm_tile_accumulate_n"
 
     def setup(self):
         import torch
@@ -856,15 +857,15 @@ class StationaryAGrid(Workload):
         self.alg_bytes = float(prod + acc)
         torch.cuda.synchronize()
         self.forms_ms = {}
-        for m in ("3d", "own", "single", "loop"):
+        for m in ("2d", "own", "single", "loop"):
             self.forms_ms[m] = Batched._time(lambda: self._run(m), reps=3)
         self.config = dict(self.config, nnz=nnz, rows=rows, N=N, k_tiles=K, column_blocks=J,
                            nnz_per_k=[a.nnz for a in self.As],
                            other_forms={m: {"ms": round(v, 4), "gflops": round(self.flops / (v * 1e-3) / 1e9, 1)}
                                         for m, v in self.forms_ms.items()},
-                           forms="2d/3d/own: reservation grids (random stealing, locality-aware stealing, "
-                                 "no stealing); single: one launch, per-XCD slices, no grid; loop: one "
-                                 "spmm_fwd per product")
+                           forms="the step: 3-D reservation grid (locality-aware stealing); 2d: 2-D grid "
+                                 "(random stealing); own: 2-D grid, no stealing; single: one launch, per-XCD "
+                                 "slices, no grid; loop: one spmm_fwd per product (the static order)")
 
     def _run(self, mode):
         from paper_2311_18141_amd import ops
@@ -877,7 +878,7 @@ class StationaryAGrid(Workload):
             ops.spmm_tile_accumulate_n(self.C[j], [self.Pd[k * self.J + j] for k in range(self.K)])
 
     def step(self):
-        self._run("2d")
+        self._run("3d")
 
     def cpu_sample(self):
         import oracle
