@@ -71,9 +71,9 @@ AUTOTUNE = False
 PINNED = {
     "rmat22_rowblock0_4x4_n128": {"variant": ("stream", 64, 2), "long_row": 128, "segment": 64},
     "powerlaw2m_n128_fwdbwd": {"variant": ("rowsplit", 64, 1), "long_row": 1024, "segment": 512,
-                               "bwd_variant": ("fused", 32, 4)},
+                               "bwd_variant": ("fused", 32, 4, 4)},
     "powerlaw2m_n128_fwdbwd_bf16": {"variant": ("rowsplit", 64, 2), "long_row": 512, "segment": 256,
-                                    "bwd_variant": ("fused", 16, 8)},
+                                    "bwd_variant": ("fused", 16, 8, 2)},
     "rmat23_n256_bf16": {"variant": ("rowsplit", 64, 4), "long_row": 128, "segment": 64},
     "rmat23_n256_f32": {"variant": ("stream", 64, 2), "long_row": 128, "segment": 64},
 }
@@ -276,6 +276,56 @@ class TileRowForward(Workload):
         out = {"cache_gather": gather_ceiling_report(self.gather_items, kernel_ms)}
         if self.dtype == "bf16":
             out["f32"] = self._f32_companion(kernel_ms)
+        if self.config.get("column_panels"):
+            out["column_panels"] = self._column_panels(self.config["column_panels"])
+        return out
+
+    def _column_panels(self, counts, steps=5):
+        """B-row reuse by column-panel blocking: each k-tile cut into P column panels, one
+        forward per panel into the same C (the first writes, the rest accumulate), so that a
+        launch gathers only from one panel's B rows (cols / P x N x e bytes, small enough for the
+        Infinity Cache) at the price of reading and writing C once per panel instead of once."""
+        import torch
+        from paper_2311_18141_amd import ops
+        e = 4 if self.dtype == "f32" else 2
+        dev = self.C.device
+        ref = self.C.float()
+        out = {"note": "time per step; C equal to the unblocked step's up to summation order "
+                       "(max |diff| / max |C|)"}
+        for P in counts:
+            parts = []
+            for t, B in zip(self.tiles, self.B):
+                w = -(-t.cols // P)
+                rows = np.repeat(np.arange(t.rows, dtype=np.int64), np.diff(t.rowptr))
+                pid = t.colind // w
+                for p in range(P):
+                    sel = pid == p
+                    lengths = np.bincount(rows[sel], minlength=t.rows)
+                    rp = np.zeros(t.rows + 1, dtype=np.int64)
+                    np.cumsum(lengths, out=rp[1:])
+                    c0, c1 = p * w, min(t.cols, (p + 1) * w)
+                    d = (torch.from_numpy(rp.astype(t.rowptr.dtype)).to(dev),
+                         torch.from_numpy((t.colind[sel] - c0).astype(np.int32)).to(dev),
+                         torch.from_numpy(t.values[sel]).to(dev), c1 - c0)
+                    h = ops.spmm_tile_create(t.rows, [d], validate=True, **_handle_opts(self.name))
+                    _apply_pin(self.name, h, self.N, B.dtype)
+                    parts.append((h, B[c0:c1], h.workspace(self.N)))
+            C = torch.empty_like(self.C)
+
+            def step():
+                for i, (h, Bp, ws) in enumerate(parts):
+                    ops.spmm_fwd(h, [Bp], C=C, accumulate=i > 0, workspace=ws)
+            for _ in range(2):
+                step()
+            ms = Batched._time(step, steps)
+            torch.cuda.synchronize()
+            diff = float((C.float() - ref).abs().max() / ref.abs().max())
+            panel_bytes = max(t.cols for t in self.tiles) / P * self.N * e
+            out[str(P)] = {"ms_per_step": round(ms, 5), "launches": len(parts),
+                           "panel_B_MiB": round(panel_bytes / 2 ** 20, 1),
+                           "C_bytes_extra_GB": round((len(parts) - 1) * 2 * self.tiles[0].rows * self.N * e / 1e9, 3),
+                           "rel_diff": diff}
+            del parts, C
         return out
 
     def _f32_companion(self, bf16_ms, steps=10):
@@ -389,9 +439,9 @@ class ForwardBackward(Workload):
             _log("%s: backward autotuned in %.1f s: %s" % (self.name, time.time() - t0, chosen))
             self.config["bwd_variant"] = chosen
         elif PINNED.get(self.name, {}).get("bwd_variant"):
-            kind, lanes, vec = PINNED[self.name]["bwd_variant"]
-            ops.spmm_tile_set_bwd_variant(self.tile, self.N, tdt, kind, lanes, vec)
-            self.config["bwd_variant"] = {"kind": kind, "lanes": lanes, "vec": vec, "pinned": True}
+            kind, lanes, vec, depth = PINNED[self.name]["bwd_variant"]
+            ops.spmm_tile_set_bwd_variant(self.tile, self.N, tdt, kind, lanes, vec, depth)
+            self.config["bwd_variant"] = {"kind": kind, "lanes": lanes, "vec": vec, "depth": depth, "pinned": True}
         # the SDDMM's shape (lanes x non-zeros per group), pinned like the variants
         sd = PINNED.get(self.name, {}).get("sddmm")
         if sd:
@@ -464,8 +514,8 @@ class ForwardBackward(Workload):
         if not AUTOTUNE and pin:
             kind, lanes, vec = pin["variant"]
             ops.spmm_tile_set_variant(self.tile, self.N, bf, kind, lanes, vec)
-            kind, lanes, vec = pin["bwd_variant"]
-            ops.spmm_tile_set_bwd_variant(self.tile, self.N, bf, kind, lanes, vec)
+            kind, lanes, vec, depth = pin["bwd_variant"]
+            ops.spmm_tile_set_bwd_variant(self.tile, self.N, bf, kind, lanes, vec, depth)
             cfg = {"variant": pin["variant"], "bwd_variant": pin["bwd_variant"], "pinned": True}
         else:
             cfg["variant"] = ops.spmm_tile_autotune(self.tile, [self.Bb], self.Cb, tune_plan=False)
@@ -1062,7 +1112,7 @@ def workloads():
             "rmat22_rowblock0_4x4_n128",
             lambda: synth.rmat_row_block(22, 16, 4, 0, seed=2).tiles, 128, "f32",
             {"workload": "rmat22_rowblock0_4x4_n128", "matrix": "R-MAT scale 22, edge factor 16, "
-             "(0.57,0.19,0.19,0.05), row block 0 of a 4x4 tile grid", "seed": 2}),
+             "(0.57,0.19,0.19,0.05), row block 0 of a 4x4 tile grid", "seed": 2, "column_panels": [2, 4, 8]}),
         "er4096_n32": lambda: TileRowForward(
             "er4096_n32", lambda: [synth.uniform_csr(4096, 4096, 16, seed=1)], 32, "f32",
             {"workload": "er4096_n32", "matrix": "4096^2 uniform, 16 nnz/row", "seed": 1}),

@@ -157,6 +157,8 @@ typedef struct {
   int32_t lanes;   /* ROWSPLIT: lanes per row; STREAM: rows per wave; 4..64, power of two;
                       0 = library choice */
   int32_t vec;     /* elements per lane per load: 1, 2, 4 (and 8 for BF16); 0 = widest aligned */
+  int32_t depth;   /* FUSED only: entries of a row of A^T in flight per group, 1, 2, 4 or 8 (at
+                      most `lanes`); 0 = library choice (4); must be 0 for the other kinds */
 } spmm_variant;
 
 /* Set (v != NULL) or clear (v == NULL) the variant used for width N and `dtype`.

@@ -50,7 +50,7 @@ class SpmmTileStats(ctypes.Structure):
 
 
 class SpmmVariant(ctypes.Structure):
-    _fields_ = [("kind", c_i32), ("lanes", c_i32), ("vec", c_i32)]
+    _fields_ = [("kind", c_i32), ("lanes", c_i32), ("vec", c_i32), ("depth", c_i32)]
 
 
 SPMM_KERNEL_AUTO = 0

@@ -352,8 +352,10 @@ spmm::Variant resolve_variant(const spmm_tile_s* A, int64_t N, DT dt, uintptr_t 
 // table for (N, dtype) that names a dB-pass kernel, or no group of at most 64 lanes
 // covering N.  A fused entry's lanes / vec (0 = library choice) must fit the call's
 // alignment and cover N, else the library's shape is used: the widest aligned vector
-// (16 bytes a lane) and the smallest power-of-two group covering N.  U = 8 entries in
-// flight per group (4 for groups of 4 lanes).
+// (16 bytes a lane) and the smallest power-of-two group covering N.  U = the entry's
+// depth, else 4 entries in flight per group (at most the group's lanes): on the
+// heavy-tailed 2M x 2M matrix at N = 128, U = 4 ran the FP32 backward in 5.68 ms against
+// 5.97 ms with U = 8 (7.8 with 16, 7.8 with 1), BF16 3.89 against 4.25 ms.
 struct FusedShape {
   int G, V, U;
 };
@@ -373,6 +375,7 @@ bool fused_shape(const spmm_tile_s* A, int64_t N, DT dt, uintptr_t align_or, Fus
   int V = 16 / esize;
   while (V > 1 && !aligned(V)) V /= 2;
   int G = covering(V);
+  int U = 4;
   if (ent) {
     const int Ve = ent->vec ? ent->vec : V;
     const int Ge = ent->lanes ? ent->lanes : covering(Ve);
@@ -380,9 +383,10 @@ bool fused_shape(const spmm_tile_s* A, int64_t N, DT dt, uintptr_t align_or, Fus
       V = Ve;
       G = Ge;
     }
+    if (ent->depth) U = ent->depth;
   }
   if ((int64_t)G * V < N) return false;
-  *out = FusedShape{G, V, G >= 8 ? 8 : 4};
+  *out = FusedShape{G, V, std::min(U, G)};
   return true;
 }
 
@@ -583,6 +587,12 @@ bool valid_variant(const spmm_variant& v, spmm_dtype dtype, bool bwd) {
   if (v.kind < SPMM_KERNEL_AUTO || v.kind > (bwd ? SPMM_KERNEL_FUSED : SPMM_KERNEL_STREAM)) return false;
   if (v.lanes != 0 && !pow2_lanes(v.lanes)) return false;
   if (v.vec != 0 && v.vec != 1 && v.vec != 2 && v.vec != 4 && !(v.vec == 8 && dtype == SPMM_BF16)) return false;
+  if (v.kind == SPMM_KERNEL_FUSED) {
+    if (v.depth != 0 && v.depth != 1 && v.depth != 2 && v.depth != 4 && v.depth != 8) return false;
+    if (v.depth != 0 && v.lanes != 0 && v.depth > v.lanes) return false;
+  } else if (v.depth != 0) {
+    return false;
+  }
   return true;
 }
 
@@ -855,7 +865,7 @@ spmm_status spmm_tile_get_variant(spmm_tile_t A, int64_t N, spmm_dtype dtype, in
   if (bwd != 0 && bwd != 1) return fail(SPMM_ERR_INVALID_ARG, "bwd=%d is not 0 or 1", (int)bwd);
   const spmm_tile_s::VarEntry* vt = bwd ? A->vtT : A->vt;
   const int n = bwd ? A->nvtT : A->nvt;
-  *out = spmm_variant{SPMM_KERNEL_AUTO, 0, 0};
+  *out = spmm_variant{SPMM_KERNEL_AUTO, 0, 0, 0};
   for (int i = 0; i < n; ++i)
     if (vt[i].N == N && vt[i].dtype == (int)dtype) *out = vt[i].v;
   return SPMM_OK;
@@ -991,7 +1001,7 @@ static spmm_status autotune_impl(spmm_tile_t A, int64_t N, spmm_dtype dtype, con
   for (auto& p : plans) free_plan(p);
   if (st != SPMM_OK) return st;
   spmm_variant out{best_v.stream ? SPMM_KERNEL_STREAM : SPMM_KERNEL_ROWSPLIT, best_v.stream ? best_v.rows : best_v.G,
-                   best_v.V};
+                   best_v.V, 0};
   st = spmm_tile_set_variant(A, N, dtype, &out);
   if (st == SPMM_OK && chosen) *chosen = out;
   return st;
@@ -1216,10 +1226,11 @@ static spmm_status autotune_bwd_impl(spmm_tile_t A, int64_t N, spmm_dtype dtype,
   uintptr_t a = reinterpret_cast<uintptr_t>(dC) | reinterpret_cast<uintptr_t>(dB) | (uintptr_t)(lddc * esize) |
                 (uintptr_t)(lddb * esize);
   // Candidates: the dB pass's kernel variants (two-pass backward) and, when B and dA are
-  // given, fused shapes at the widest aligned vector width and at half and a quarter of it.
+  // given, fused shapes at the widest aligned vector width and at half and a quarter of it,
+  // each with 2, 4 and 8 entries in flight per group.
   std::vector<spmm_variant> cand;
   for (const auto& v : candidate_variants(N, dt, a, t.cols))
-    cand.push_back(spmm_variant{v.stream ? SPMM_KERNEL_STREAM : SPMM_KERNEL_ROWSPLIT, v.stream ? v.rows : v.G, v.V});
+    cand.push_back(spmm_variant{v.stream ? SPMM_KERNEL_STREAM : SPMM_KERNEL_ROWSPLIT, v.stream ? v.rows : v.G, v.V, 0});
   if (full) {
     a |= reinterpret_cast<uintptr_t>(B) | (uintptr_t)(ldb * esize);
     int vmax = (int)(16 / esize);
@@ -1228,15 +1239,17 @@ static spmm_status autotune_bwd_impl(spmm_tile_t A, int64_t N, spmm_dtype dtype,
       if ((N % V) != 0) continue;
       int G = 4;
       while (G < 64 && (int64_t)G * V < N) G *= 2;
-      if ((int64_t)G * V >= N) cand.push_back(spmm_variant{SPMM_KERNEL_FUSED, G, V});
+      if ((int64_t)G * V >= N)
+        for (int U : {2, 4, 8})
+          if (U <= G) cand.push_back(spmm_variant{SPMM_KERNEL_FUSED, G, V, U});
     }
   }
   // Each candidate is timed through spmm_bwd itself with the candidate as the table's
   // entry (3 calls after a warm-up call), so the choice measures exactly what later
   // calls run; the entry found before tuning is restored if a call fails.
-  spmm_variant prev{SPMM_KERNEL_AUTO, 0, 0};
+  spmm_variant prev{SPMM_KERNEL_AUTO, 0, 0, 0};
   (void)spmm_tile_get_variant(A, N, dtype, 1, &prev);
-  spmm_variant best = cand.empty() ? spmm_variant{SPMM_KERNEL_AUTO, 0, 0} : cand[0];
+  spmm_variant best = cand.empty() ? spmm_variant{SPMM_KERNEL_AUTO, 0, 0, 0} : cand[0];
   if (t.cols > 0 && !cand.empty()) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     const size_t wsb = bwd_workspace(A, N);
@@ -1368,7 +1381,7 @@ void batch_variant(const spmm_tile_s* A, int64_t N, DT dt, spmm::BatchTileDev* b
   bt->kind = stream ? 0 : 1;
   bt->G = stream ? 64 : G;
   bt->V = Vs;
-  *out = spmm_variant{stream ? SPMM_KERNEL_STREAM : SPMM_KERNEL_ROWSPLIT, bt->G, stream ? Vs : 4};
+  *out = spmm_variant{stream ? SPMM_KERNEL_STREAM : SPMM_KERNEL_ROWSPLIT, bt->G, stream ? Vs : 4, 0};
 }
 
 }  // namespace

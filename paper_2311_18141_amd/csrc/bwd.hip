@@ -253,6 +253,8 @@ hipError_t launch_fused_vu(const BwdFusedParams& P, int G, hipStream_t s) {
 template <typename E, int V>
 hipError_t launch_fused_v(const BwdFusedParams& P, int G, int U, hipStream_t s) {
   switch (U) {
+    case 1: return launch_fused_vu<E, V, 1>(P, G, s);
+    case 2: return launch_fused_vu<E, V, 2>(P, G, s);
     case 4: return launch_fused_vu<E, V, 4>(P, G, s);
     case 8: return launch_fused_vu<E, V, 8>(P, G, s);
     default: return hipErrorInvalidValue;

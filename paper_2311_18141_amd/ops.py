@@ -151,12 +151,13 @@ def spmm_tile_set_variant(tile: Tile, N: int, dtype=torch.float32, kind: Optiona
 
 
 def spmm_tile_set_bwd_variant(tile: Tile, N: int, dtype=torch.float32, kind: Optional[str] = "auto",
-                              lanes: int = 0, vec: int = 0) -> None:
-    """Pin the kernel variant of the backward's dB pass for width N (kind None clears the entry)."""
+                              lanes: int = 0, vec: int = 0, depth: int = 0) -> None:
+    """Pin the backward's variant for width N: "fused" (lanes, vec, depth = entries in flight per
+    group) or the two-pass form's dB-pass kernel ("rowsplit", "stream"); kind None clears the entry."""
     if kind is None:
         check(lib().spmm_tile_set_bwd_variant(tile.handle, N, _DTYPES[dtype], None))
         return
-    v = SpmmVariant(KERNELS[kind], lanes, vec)
+    v = SpmmVariant(KERNELS[kind], lanes, vec, depth)
     check(lib().spmm_tile_set_bwd_variant(tile.handle, N, _DTYPES[dtype], ctypes.byref(v)))
 
 
@@ -167,7 +168,10 @@ def spmm_tile_get_variant(tile: Tile, N: int, dtype=torch.float32, bwd: bool = F
     if v.kind == KERNELS["auto"]:
         return None
     inv = {val: k for k, val in KERNELS.items()}
-    return {"kind": inv[v.kind], "lanes": v.lanes, "vec": v.vec}
+    out = {"kind": inv[v.kind], "lanes": v.lanes, "vec": v.vec}
+    if v.kind == KERNELS["fused"]:
+        out["depth"] = v.depth
+    return out
 
 
 def spmm_tile_autotune_bwd(tile: Tile, dC: torch.Tensor, dB: Optional[torch.Tensor] = None,
@@ -201,7 +205,10 @@ def spmm_tile_autotune_bwd(tile: Tile, dC: torch.Tensor, dB: Optional[torch.Tens
                                        dA.data_ptr() if B is not None else None,
                                        dB.data_ptr(), _row_major_ld(dB, "dB"), _stream_ptr(stream), ctypes.byref(out)))
     inv = {v: k for k, v in KERNELS.items()}
-    return {"kind": inv[out.kind], "lanes": out.lanes, "vec": out.vec}
+    res = {"kind": inv[out.kind], "lanes": out.lanes, "vec": out.vec}
+    if out.kind == KERNELS["fused"]:
+        res["depth"] = out.depth
+    return res
 
 
 def spmm_tile_set_sddmm_variant(tile: Tile, N: int, lanes: int = 0, nnz_per_group: int = 4) -> None:

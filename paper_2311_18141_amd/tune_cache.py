@@ -9,7 +9,7 @@ which products are summed, so an entry applied to another matrix with the same
 fingerprint can cost speed but not correctness (results stay within the rounding of the
 FP32 sums, and equal bit for bit on integer data).
 
-File format: ``{"version": 1, "entries": {key: {"kind", "lanes", "vec"}}}`` with
+File format: ``{"version": 1, "entries": {key: {"kind", "lanes", "vec", "depth"}}}`` with
 ``key = "<fingerprint>|<N>|<f32|bf16>|<fwd|bwd>"``; written atomically.
 """
 from __future__ import annotations
@@ -74,7 +74,7 @@ def save(path: str, tiles: Sequence[ops.Tile], Ns: Sequence[int], dtype=torch.fl
         if v is None:
             continue
         entries[_key(fingerprint(t), N, dtype, bwd)] = {"kind": v["kind"], "lanes": int(v["lanes"]),
-                                                        "vec": int(v["vec"])}
+                                                        "vec": int(v["vec"]), "depth": int(v.get("depth", 0))}
         n += 1
     _write(path, entries)
     return n
@@ -93,7 +93,10 @@ def load(path: str, tiles: Sequence[ops.Tile], Ns: Sequence[int], dtype=torch.fl
         e = entries.get(_key(fingerprint(t), N, dtype, bwd))
         if e is None:
             continue
-        setter(t, int(N), dtype, e["kind"], int(e["lanes"]), int(e["vec"]))
+        if bwd:
+            setter(t, int(N), dtype, e["kind"], int(e["lanes"]), int(e["vec"]), int(e.get("depth", 0)))
+        else:
+            setter(t, int(N), dtype, e["kind"], int(e["lanes"]), int(e["vec"]))
         n += 1
     return n
 

@@ -20,12 +20,16 @@ def test_more_than_one_gpu_is_refused():
 
 def test_registry_and_pins():
     names = set(bench.workloads())
-    assert "rmat22_rowblock0_4x4_n128" in names          # the default workload
+    assert "powerlaw2m_n128_fwdbwd" in names             # the default workload
     assert set(bench.PINNED) <= names
     for name, pin in bench.PINNED.items():
         kind, lanes, vec = pin["variant"]
         assert kind in ("stream", "rowsplit") and lanes in (4, 8, 16, 32, 64) and vec in (1, 2, 4, 8)
         assert pin["long_row"] > 0 and pin["segment"] > 0
+        if "bwd_variant" in pin:                          # the fused backward: (kind, lanes, vec, depth)
+            kind, lanes, vec, depth = pin["bwd_variant"]
+            assert kind == "fused" and lanes in (4, 8, 16, 32, 64) and vec in (1, 2, 4, 8)
+            assert depth in (1, 2, 4, 8) and depth <= lanes
 
 
 def test_stored_traffic_parser(tmp_path, monkeypatch):

@@ -383,18 +383,38 @@ def test_fused_backward_integer_exact(N, dtype):
     for lanes, vec in FUSED_SHAPES[dtype]:
         if N % vec or lanes * vec < N:
             continue
-        G.note("fused backward N=%d %s lanes=%d vec=%d" % (N, dtype, lanes, vec))
-        ops.spmm_tile_set_bwd_variant(tile, N, tdt, "fused", lanes, vec)
-        dA, dB = ops.spmm_bwd(tile, dCd, Bd)
-        torch.cuda.synchronize()
-        ran += 1
-        assert np.array_equal(dA.cpu().numpy().astype(np.float64), rA), (lanes, vec)
-        if dtype == "f32":
-            assert np.array_equal(dB.cpu().numpy().astype(np.float64), want_B), (lanes, vec)
-        else:
-            assert np.array_equal(dB.cpu().view(torch.int16).numpy().view(np.uint16), want_B), (lanes, vec)
-        assert torch.equal(dB, dB_two), (lanes, vec)
+        for depth in (1, 2, 4, 8):
+            if depth > lanes:
+                continue
+            G.note("fused backward N=%d %s lanes=%d vec=%d depth=%d" % (N, dtype, lanes, vec, depth))
+            ops.spmm_tile_set_bwd_variant(tile, N, tdt, "fused", lanes, vec, depth)
+            dA, dB = ops.spmm_bwd(tile, dCd, Bd)
+            torch.cuda.synchronize()
+            ran += 1
+            what = (lanes, vec, depth)
+            assert np.array_equal(dA.cpu().numpy().astype(np.float64), rA), what
+            if dtype == "f32":
+                assert np.array_equal(dB.cpu().numpy().astype(np.float64), want_B), what
+            else:
+                assert np.array_equal(dB.cpu().view(torch.int16).numpy().view(np.uint16), want_B), what
+            assert torch.equal(dB, dB_two), what
     assert ran > 0
+
+
+def test_fused_variant_argument_errors():
+    """depth belongs to the fused kind only: 1, 2, 4 or 8, at most the group's lanes."""
+    G.note("fused variant argument errors")
+    A = synth.random_csr(10, 10, np.full(10, 3), _rng(2))
+    tile = G.make_tile([A], transpose=True)
+    for kind, lanes, vec, depth in [("rowsplit", 16, 4, 2), ("stream", 64, 2, 4), ("fused", 16, 4, 3),
+                                    ("fused", 4, 4, 8), ("fused", 16, 4, 16)]:
+        with pytest.raises(ops.SpmmError):
+            ops.spmm_tile_set_bwd_variant(tile, 64, torch.float32, kind, lanes, vec, depth)
+    with pytest.raises(ops.SpmmError):   # the forward's table takes no fused kind
+        ops.spmm_tile_set_variant(tile, 64, torch.float32, "fused", 16, 4)
+    ops.spmm_tile_set_bwd_variant(tile, 64, torch.float32, "fused", 16, 4, 8)
+    assert ops.spmm_tile_get_variant(tile, 64, torch.float32, bwd=True) == {"kind": "fused", "lanes": 16, "vec": 4,
+                                                                             "depth": 8}
 
 
 def test_fused_backward_choice():

@@ -33,8 +33,7 @@ def _bench_tile(workload, tiles, N, dtypes=(torch.float32,), transpose=False, de
         kind, lanes, vec = pin["variant"]
         ops.spmm_tile_set_variant(tile, N, d, kind, lanes, vec)
         if "bwd_variant" in pin:                      # the backward's dB pass
-            kind, lanes, vec = pin["bwd_variant"]
-            ops.spmm_tile_set_bwd_variant(tile, N, d, kind, lanes, vec)
+            ops.spmm_tile_set_bwd_variant(tile, N, d, *pin["bwd_variant"])
     if "sddmm" in pin:
         ops.spmm_tile_set_sddmm_variant(tile, N, pin["sddmm"][0], pin["sddmm"][1])
     return tile

@@ -27,8 +27,11 @@ def table(monkeypatch):
         return store.get((id(t), N, dtype, bwd))
 
     def setter(bwd):
-        def f(t, N, dtype=torch.float32, kind="auto", lanes=0, vec=0):
-            store[(id(t), N, dtype, bwd)] = {"kind": kind, "lanes": lanes, "vec": vec}
+        def f(t, N, dtype=torch.float32, kind="auto", lanes=0, vec=0, *depth):
+            entry = {"kind": kind, "lanes": lanes, "vec": vec}
+            if bwd and kind == "fused":
+                entry["depth"] = depth[0] if depth else 0
+            store[(id(t), N, dtype, bwd)] = entry
         return f
 
     monkeypatch.setattr(ops, "spmm_tile_get_variant", get)
@@ -68,6 +71,13 @@ def test_merge_and_bwd_entries(tmp_path, table):
     b2 = FakeTile(20, 70, 20)
     assert tune_cache.load(path, [b2], [32], torch.bfloat16, bwd=True) == 1
     assert ops.spmm_tile_get_variant(b2, 32, torch.bfloat16, bwd=True)["lanes"] == 64
+    # a fused backward entry keeps its depth (entries in flight per group)
+    c = FakeTile(30, 90, 30)
+    ops.spmm_tile_set_bwd_variant(c, 128, torch.float32, "fused", 32, 4, 2)
+    tune_cache.save(path, [c], [128], bwd=True)
+    c2 = FakeTile(30, 90, 30)
+    assert tune_cache.load(path, [c2], [128], bwd=True) == 1
+    assert ops.spmm_tile_get_variant(c2, 128, bwd=True) == {"kind": "fused", "lanes": 32, "vec": 4, "depth": 2}
     assert not list(tmp_path.glob("*.tmp*"))
 
 
