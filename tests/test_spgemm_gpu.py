@@ -238,3 +238,51 @@ def test_spgemm_medium_rows_to_windows():
     B = _b_rows_of_lengths([4500, 6000, 8100, 600, 3000, 20000], N, rng, "int8")
     A = _select_rows(B.rows, [[0], [1], [2], [3, 4], [0, 3], [5], [1, 2, 3]], rng, "int8")
     _check(A, B, exact=True)
+
+
+def test_spgemm_long_rows_negative_zero_products():
+    """Long rows (column windows) with -0.0 products (an A or a B value stored as -0.0 times
+    a positive value): a column reached only by such products is still a structural entry,
+    so a kernel that told presence from its sum would miss it; the structure stays exact.
+    Both long-row paths (at most and more than 1,024 A entries) are covered, as are rows
+    with no such column, a row whose every product is -0.0, and +0.0 products."""
+    G.note("spgemm long rows, -0.0 products")
+    rng = _rng(21)
+    N = 70000
+    cols0 = rng.choice(N, 9000, replace=False)
+    rest = np.setdiff1d(np.arange(N), cols0)
+    cols1 = rng.choice(rest, 8, replace=False)
+    cols2 = rng.choice(np.setdiff1d(rest, cols1), 6, replace=False)
+    brows = [cols0, cols1, cols2] + [rng.choice(N, 12, replace=False) for _ in range(1100)]
+    bvals = ([rng.integers(1, 4, 9000), rng.integers(1, 4, 8), np.full(6, -0.0)]
+             + [rng.integers(-3, 4, 12) for _ in range(1100)])
+    order = [np.argsort(c) for c in brows]
+    B = synth.CSR(len(brows), N, np.concatenate([[0], np.cumsum([len(c) for c in brows])]).astype(np.int32),
+                  np.concatenate([c[o] for c, o in zip(brows, order)]).astype(np.int32),
+                  np.concatenate([v[o] for v, o in zip(bvals, order)]).astype(np.float32))
+    assert np.signbit(B.values[B.rowptr[2]:B.rowptr[3]]).all()
+    many = list(range(3, 1103))
+    arows = [([0, 1], [1.0, -0.0]),            # B row 1's columns: only -0.0 products
+             ([0, 2], [1.0, 2.0]),             # B row 2's columns: 2 x -0.0
+             ([0, 1, 2], [1.0, -0.0, 5.0]),
+             ([0, 1], [1.0, 2.0]),             # no -0.0 product
+             (many + [1], None),               # more than 1,024 A entries, one -0.0 product row
+             (many, None),
+             ([1], [-0.0]),                    # a short row (hash path)
+             ([0], [-0.0]),                    # every product -0.0: every window redone
+             ([0, 1], [-1.0, 0.0])]            # +0.0 products
+    rp, ci, va = [0], [], []
+    for ks, vs in arows:
+        ks = np.asarray(ks)
+        if vs is None:
+            vs = rng.integers(-3, 4, len(ks)).astype(np.float32)
+            vs[ks == 1] = -0.0
+            vs[(ks != 1) & (vs == 0)] = 1.0
+        vs = np.asarray(vs, np.float32)
+        o = np.argsort(ks)
+        ci.append(ks[o])
+        va.append(vs[o])
+        rp.append(rp[-1] + len(ks))
+    A = synth.CSR(len(arows), B.rows, np.asarray(rp, np.int32), np.concatenate(ci).astype(np.int32),
+                  np.concatenate(va))
+    _check(A, B, exact=True)
