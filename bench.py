@@ -603,7 +603,7 @@ class ForwardBackward(Workload):
 class Batched(Workload):
     """Many independent uneven tiles in one batched launch: the single-launch form (one kernel for
     every item class, resident workgroups claiming items from per-XCD slices, split rows summed by
-    their last unit), per-tile variants from the autotuner; the per-tile launch loop (default and
+    a fix-up launch when a tile has them), per-tile variants from the autotuner; the per-tile launch loop (default and
     autotuned variants), the one-launch-per-class forms (flat and persistent hand-out) and the
     single launch with the flat hand-out are timed beside it, eagerly and as graph replays."""
 
