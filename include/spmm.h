@@ -275,7 +275,8 @@ spmm_status spmm_bwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes /* 
  * With both outputs wanted (and no column slices set), one pass over the transposed
  * structure gathers each dC row once for both (see SPMM_KERNEL_FUSED); otherwise dA is
  * a sampled dense-dense product in A's order and dB a pass of the forward kernels.
- * 1 <= N <= 4,194,240, as for spmm_fwd.  Asynchronous.  Errors: INVALID_ARG,
+ * 1 <= N <= 4,194,240, as for spmm_fwd.  Asynchronous; no allocation and no host
+ * synchronisation, so a call can be captured in a HIP graph.  Errors: INVALID_ARG,
  * UNSUPPORTED (no transpose, num_k > 1, ld too large, N too large), WORKSPACE, HIP.
  */
 spmm_status spmm_bwd(spmm_tile_t A, const void* dC, int64_t lddc, const void* B, int64_t ldb, int64_t N,
