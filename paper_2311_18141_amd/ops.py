@@ -438,7 +438,7 @@ def spmm_batch_create(tiles: Sequence[Tile], Ns: Sequence[int], dtype=torch.floa
                       persistent: bool = False, single: bool = False,
                       stream: Optional[torch.cuda.Stream] = None) -> Batch:
     """Work list for spmm_batched over single-tile handles (persistent: claim-counter hand-out;
-    single: one launch for every kernel class, split rows finished in the same launch)."""
+    single: one launch for every kernel class, then a fix-up launch when some tile has split rows)."""
     arr = (ctypes.c_void_p * len(tiles))(*[t.handle for t in tiles])
     ns = (ctypes.c_int64 * len(tiles))(*[int(n) for n in Ns])
     h = ctypes.c_void_p()
