@@ -151,7 +151,7 @@ spmm_status spmm_tile_export_transpose(spmm_tile_t tile, int32_t* rowptrT, int32
 #define SPMM_KERNEL_ROWSPLIT 1   /* a group of `lanes` lanes owns one row and a column window */
 #define SPMM_KERNEL_STREAM 2     /* a wave streams the non-zeros of `lanes` (4..64) consecutive rows */
 #define SPMM_KERNEL_FUSED 3      /* backward only: dA and dB in one pass over the transposed structure,
-                                    `lanes` lanes per row of A^T covering all N columns (lanes x vec >= N) */
+                                    `lanes` lanes per row of A^T and column window of lanes x vec columns */
 typedef struct {
   int32_t kind;    /* SPMM_KERNEL_* */
   int32_t lanes;   /* ROWSPLIT: lanes per row; STREAM: rows per wave; 4..64, power of two;
@@ -236,11 +236,13 @@ size_t spmm_noalloc_scratch_bytes(void);
 /* The backward keeps its own variant per (N, dtype), set here (v != NULL) or cleared
    (v == NULL; the library rule then applies).  Kind SPMM_KERNEL_FUSED selects the fused
    backward (when spmm_bwd is asked for both dA and dB): a group of `lanes` lanes owns one
-   row of A^T with `vec` columns per lane, lanes x vec >= N (0 = library choice; a shape
-   that does not fit a call's alignment or does not cover N falls back to the library's).
+   row of A^T with `vec` columns per lane, in column windows of lanes x vec columns when
+   that is less than N (at most ceil(N / 256) windows; 0 = library choice; a shape that
+   does not fit a call's alignment or needs more windows falls back to the library's).
    Kinds ROWSPLIT and STREAM select the two-pass backward (SDDMM for dA, then the forward
    kernels over the transposed structure for dB) and name the dB pass's kernel.  Without
-   an entry the fused backward runs whenever a group of at most 64 lanes covers N.
+   an entry the fused backward runs whenever the operands' alignment allows windows of
+   at least 256 columns (or one group covers N).
    Results of every variant agree as the forward's do (dB bit-identical between the fused
    and two-pass forms at the same vector width and split plan; dA within FP32 summation
    order).  Errors: INVALID_ARG (bad field values, table of 16 entries full). */
@@ -259,8 +261,9 @@ spmm_status spmm_tile_autotune_bwd(spmm_tile_t tile, int64_t N, spmm_dtype dtype
                                    int64_t lddb, void* stream, spmm_variant* chosen /* host */);
 
 /* Workspace (device bytes) spmm_bwd needs for this handle at width N when dB is
-   wanted: FP32 partial rows of the transposed plan's split rows plus 4 bytes per
-   non-zero (A's values gathered into the transposed order by the two-pass form). */
+   wanted: FP32 partial rows of the transposed plan's split rows plus 4 x max(1,
+   ceil(N / 256)) bytes per non-zero (A's values gathered into the transposed order by
+   the two-pass form, or the fused form's partial dot products, one per column window). */
 spmm_status spmm_bwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes /* host */);
 
 /*
@@ -273,8 +276,10 @@ spmm_status spmm_bwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes /* 
  * on A's pattern, in A's CSR order; no gradient flows to the pattern.  The gradient
  * pass is not in the paper: it is this library's addition (the forward's adjoint).
  * With both outputs wanted (and no column slices set), one pass over the transposed
- * structure gathers each dC row once for both (see SPMM_KERNEL_FUSED); otherwise dA is
- * a sampled dense-dense product in A's order and dB a pass of the forward kernels.
+ * structure gathers each dC row once for both (see SPMM_KERNEL_FUSED; wider than one
+ * group, in column windows whose partial dot products a small kernel sums
+ * into dA in window order); otherwise dA is a sampled dense-dense product in A's order
+ * and dB a pass of the forward kernels.
  * 1 <= N <= 4,194,240, as for spmm_fwd.  Asynchronous; no allocation and no host
  * synchronisation, so a call can be captured in a HIP graph.  Errors: INVALID_ARG,
  * UNSUPPORTED (no transpose, num_k > 1, ld too large, N too large), WORKSPACE, HIP.

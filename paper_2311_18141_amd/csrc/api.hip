@@ -157,13 +157,21 @@ int stream_rows_for(int64_t rows) {
   return R;
 }
 
-// Kernel variant for width N when the handle has no entry: for N >= 64 the stream
-// kernel over column windows of 64 FP32 / 128 BF16 columns; below that a row-split
-// group with the widest aligned vector and the smallest power-of-two group covering N.
+// Kernel variant for width N when the handle has no entry: for N >= 256 (aligned)
+// column windows of 512 bytes of each B row, the stream kernel over 128 FP32 columns or
+// a full-wave row-split group over 256 BF16 columns; for N >= 64 the stream kernel over
+// windows of 64 FP32 / 128 BF16 columns; below that a row-split group with the widest
+// aligned vector and the smallest power-of-two group covering N.
 spmm::Variant pick_variant(int64_t N, DT dt, uintptr_t align_or, int64_t rows) {
   const int esize = dt == DT::F32 ? 4 : 2;
   int V = 16 / esize;
   while (V > 1 && ((N % V) != 0 || (align_or % (uintptr_t)(V * esize)) != 0)) V /= 2;
+  if (N >= 256) {
+    // the autotuner's picks at N = 256..1024 on the heavy-tailed 2M x 2M matrix and at
+    // N = 256 on R-MAT scale 23: 10% (FP32) to 27% (BF16) faster than 256-byte windows
+    if (dt == DT::F32 && V >= 2) return spmm::Variant{64, 2, true, stream_rows_for(rows)};
+    if (dt == DT::BF16 && V >= 4) return spmm::Variant{64, 4, false};
+  }
   if (N >= 64) {
     // column windows of about 256 bytes of each B row (64 FP32 or 128 BF16 columns):
     // the grid walks the windows one after the other, so a narrower window keeps a
@@ -349,16 +357,21 @@ spmm::Variant resolve_variant(const spmm_tile_s* A, int64_t N, DT dt, uintptr_t 
 
 // Shape of the fused backward (one pass over the transposed structure for dA and dB)
 // at width N, or false when the two-pass backward applies: an entry of the backward's
-// table for (N, dtype) that names a dB-pass kernel, or no group of at most 64 lanes
-// covering N.  A fused entry's lanes / vec (0 = library choice) must fit the call's
-// alignment and cover N, else the library's shape is used: the widest aligned vector
-// (16 bytes a lane) and the smallest power-of-two group covering N.  U = the entry's
+// table for (N, dtype) that names a dB-pass kernel, or a vector width so narrow (the
+// operands' alignment) that 64-lane windows would be more than fused_windows_max(N).
+// A fused entry's lanes / vec (0 = library choice) must fit the call's alignment and
+// need at most that many windows, else the library's shape is used: the widest aligned
+// vector (16 bytes a lane) and the smallest power-of-two group covering N, 64 lanes and
+// ceil(N / (64 V)) column windows when none does.  U = the entry's
 // depth, else 4 entries in flight per group (at most the group's lanes): on the
 // heavy-tailed 2M x 2M matrix at N = 128, U = 4 ran the FP32 backward in 5.68 ms against
 // 5.97 ms with U = 8 (7.8 with 16, 7.8 with 1), BF16 3.89 against 4.25 ms.
 struct FusedShape {
-  int G, V, U;
+  int G, V, U, n_win;
 };
+// The most column windows the fused backward may use at width N (its workspace holds
+// that many arrays of partial dot products): windows of at least 256 columns.
+int64_t fused_windows_max(int64_t N) { return std::max<int64_t>(1, (N + 255) / 256); }
 bool fused_shape(const spmm_tile_s* A, int64_t N, DT dt, uintptr_t align_or, FusedShape* out) {
   const int esize = dt == DT::F32 ? 4 : 2;
   const int want = dt == DT::F32 ? SPMM_F32 : SPMM_BF16;
@@ -376,17 +389,19 @@ bool fused_shape(const spmm_tile_s* A, int64_t N, DT dt, uintptr_t align_or, Fus
   while (V > 1 && !aligned(V)) V /= 2;
   int G = covering(V);
   int U = 4;
+  auto windows = [&](int g, int v) { return (N + (int64_t)g * v - 1) / ((int64_t)g * v); };
   if (ent) {
     const int Ve = ent->vec ? ent->vec : V;
     const int Ge = ent->lanes ? ent->lanes : covering(Ve);
-    if (aligned(Ve) && (int64_t)Ge * Ve >= N) {
+    if (aligned(Ve) && windows(Ge, Ve) <= fused_windows_max(N)) {
       V = Ve;
       G = Ge;
     }
     if (ent->depth) U = ent->depth;
   }
-  if ((int64_t)G * V < N) return false;
-  *out = FusedShape{G, V, std::min(U, G)};
+  const int64_t nw = windows(G, V);
+  if (nw > fused_windows_max(N)) return false;
+  *out = FusedShape{G, V, std::min(U, G), (int)nw};
   return true;
 }
 
@@ -786,12 +801,14 @@ spmm_status spmm_fwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes) {
 }
 
 // Backward workspace: FP32 partial rows of the transposed plan's split rows, then
-// (16-byte aligned) A's values gathered into the transposed order.
+// (16-byte aligned) either A's values gathered into the transposed order (the two-pass
+// form) or the fused form's partial dot products, one array of nnz per column window
+// when G * V < N (at most fused_windows_max(N) windows: at least 256 columns each).
 static size_t bwd_partial_bytes(const spmm_tile_s* A, int64_t N) {
   return (sizeof(float) * partial_ld(N) * (size_t)A->planT.n_seg + 15) & ~(size_t)15;
 }
 static size_t bwd_workspace(const spmm_tile_s* A, int64_t N) {
-  return bwd_partial_bytes(A, N) + sizeof(float) * (size_t)A->t[0].nnz;
+  return bwd_partial_bytes(A, N) + sizeof(float) * (size_t)A->t[0].nnz * (size_t)fused_windows_max(N);
 }
 
 spmm_status spmm_bwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes) {
@@ -1051,6 +1068,10 @@ static hipError_t launch_backward_fused(const spmm_tile_s* A, const FusedShape& 
   F.n_seg = A->planT.n_seg;
   F.partial = static_cast<float*>(workspace);
   F.ldp = (int64_t)partial_ld(N);
+  F.n_win = fs.n_win;
+  F.nnz = t.nnz;
+  F.dA_part = fs.n_win > 1 ? reinterpret_cast<float*>(static_cast<char*>(workspace) + bwd_partial_bytes(A, N))
+                           : nullptr;
   hipError_t e = spmm::launch_bwd_fused(F, fs.G, fs.V, fs.U, dt, s);
   if (e != hipSuccess || A->planT.n_long == 0) return e;
   spmm::FwdParams P{};
@@ -1239,7 +1260,7 @@ static spmm_status autotune_bwd_impl(spmm_tile_t A, int64_t N, spmm_dtype dtype,
       if ((N % V) != 0) continue;
       int G = 4;
       while (G < 64 && (int64_t)G * V < N) G *= 2;
-      if ((int64_t)G * V >= N)
+      if ((N + (int64_t)G * V - 1) / ((int64_t)G * V) <= fused_windows_max(N))
         for (int U : {2, 4, 8})
           if (U <= G) cand.push_back(spmm_variant{SPMM_KERNEL_FUSED, G, V, U});
     }

@@ -142,21 +142,25 @@ __device__ __forceinline__ float group_sum_scatter(float (&d)[U], int gl) {
 }
 
 // Fused backward over the transposed structure.  A group of G lanes owns one row j of
-// A^T (one column of A) and all N columns (G * V >= N): it keeps B[j, :] in registers,
+// A^T (one column of A) and one window of G * V columns (blockIdx.y; one window when
+// G * V >= N): it keeps its part of B[j, :] in registers,
 // walks the row's entries G at a time (lane l loads entry l's original row, position
 // and value, the value read through the position), and for each batch of U entries
 // gathers the U rows of dC once: each row feeds the dB accumulators (acc += a * dC[i, :])
 // and a partial dot product with B[j, :]; the group sums the U dot products with one
-// scattered reduction and the lane holding entry u's sum stores dA at its position.
-// Rows longer than long_row come as the transposed plan's units (first in the grid):
-// a unit's dB partial row goes to the workspace for the fix-up, its dA entries are final.
+// scattered reduction and the lane holding entry u's sum stores dA at its position (with
+// several windows: the window's partial dot product at the entry's transposed position,
+// summed over the windows by bwd_dA_sum).  Rows longer than long_row come as the
+// transposed plan's units (first in the grid): a unit's dB partial row goes to the
+// workspace for the fix-up, its dA entries are final (or partial per window as above).
 template <int G, int V, int U, typename E>
 __global__ void __launch_bounds__(kBlock) bwd_fused(BwdFusedParams P) {
   static_assert(U <= G, "one lane per entry reads the structure");
   using T = typename E::T;
   constexpr int GPB = kBlock / G;
   const int gl = threadIdx.x & (G - 1);
-  const int64_t c0 = (int64_t)gl * V;
+  const int win = (int)blockIdx.y;
+  const int64_t c0 = (int64_t)win * (G * V) + (int64_t)gl * V;
   const bool active = c0 < P.N;
   const int64_t cl = active ? c0 : 0;  // lanes past N read column 0 and contribute nothing
   const int64_t unit_blocks = (P.n_seg + GPB - 1) / GPB;
@@ -220,7 +224,12 @@ __global__ void __launch_bounds__(kBlock) bwd_fused(BwdFusedParams P) {
       const int u = gl / kPer;
       const int src = (int)(threadIdx.x & 63 & ~(G - 1)) + min(jj + u, cnt - 1);
       const int p = __builtin_amdgcn_ds_bpermute(src << 2, my_p);
-      if ((gl & (kPer - 1)) == 0 && jj + u < cnt) P.dA[p] = sum;
+      if ((gl & (kPer - 1)) == 0 && jj + u < cnt) {
+        if (P.n_win == 1)
+          P.dA[p] = sum;
+        else
+          P.dA_part[(int64_t)win * P.nnz + pc + jj + u] = sum;
+      }
     }
   }
   if (!active) return;
@@ -231,13 +240,28 @@ __global__ void __launch_bounds__(kBlock) bwd_fused(BwdFusedParams P) {
   }
 }
 
+// dA[perm[q]] = the sum over the windows of the partial dot products of entry q of the
+// transposed structure, in window order.
+__global__ void __launch_bounds__(kBlock) bwd_dA_sum(const float* part, int n_win, int64_t nnz, const int32_t* perm,
+                                                     float* dA) {
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nnz; q += (int64_t)gridDim.x * kBlock) {
+    float x = part[q];
+    for (int w = 1; w < n_win; ++w) x += part[(int64_t)w * nnz + q];
+    dA[__builtin_nontemporal_load(perm + q)] = x;
+  }
+}
+
 template <typename E, int V, int U>
 hipError_t launch_fused_vu(const BwdFusedParams& P, int G, hipStream_t s) {
   auto go = [&](auto kern, int gpb) {
     const int64_t blocks = (P.n_seg + gpb - 1) / gpb + (P.cols + gpb - 1) / gpb;
     if (blocks == 0) return hipSuccess;
-    if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kBlock), 0, s, P);
+    if (blocks >= ((int64_t)1 << 31) || P.n_win < 1 || P.n_win > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks, (unsigned)P.n_win), dim3(kBlock), 0, s, P);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || P.n_win == 1 || P.nnz == 0) return e;
+    const int64_t sb = std::min<int64_t>((P.nnz + kBlock - 1) / kBlock, 65536);
+    hipLaunchKernelGGL(bwd_dA_sum, dim3((unsigned)sb), dim3(kBlock), 0, s, P.dA_part, P.n_win, P.nnz, P.perm, P.dA);
     return hipGetLastError();
   };
   switch (G) {

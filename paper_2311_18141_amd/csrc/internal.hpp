@@ -282,8 +282,13 @@ struct BwdFusedParams {
   int64_t n_seg;
   float* partial;          // n_seg x ldp
   int64_t ldp;
+  int32_t n_win;           // column windows of G * V columns (blockIdx.y); 1: dA stored directly
+  int64_t nnz;
+  float* dA_part;          // n_win > 1: n_win x nnz partial dot products, transposed order
 };
-// G lanes per row of A^T, V columns per lane and load (G * V >= N), U entries in flight.
+// G lanes per row of A^T, V columns per lane and load, n_win windows of G * V columns,
+// U entries in flight; with n_win > 1 the partial dot products are then summed into dA.
+
 hipError_t launch_bwd_fused(const BwdFusedParams& P, int G, int V, int U, DT dt, hipStream_t s);
 // The forward's split-row fix-up alone (sums each split row's unit partials into C),
 // with G * V columns per group.

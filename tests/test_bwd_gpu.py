@@ -345,15 +345,15 @@ def test_autotune_bwd(dtype):
 
 
 FUSED_SHAPES = {"f32": [(4, 1), (8, 2), (16, 4), (32, 2), (64, 1), (64, 4)],
-                "bf16": [(8, 1), (4, 2), (8, 8), (16, 4), (32, 2), (32, 4), (64, 2), (64, 8)]}
+                "bf16": [(8, 1), (4, 2), (8, 8), (16, 4), (32, 2), (32, 4), (64, 2), (64, 4), (64, 8)]}
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-@pytest.mark.parametrize("N", [1, 3, 36, 64, 100])
+@pytest.mark.parametrize("N", [1, 3, 36, 64, 100, 300, 520])
 def test_fused_backward_integer_exact(N, dtype):
-    """The fused backward (one pass over A^T for dA and dB) at every group shape that covers N,
-    split rows of A^T included: dA and dB exact on integer data (dB rounded once for BF16), as the
-    two-pass form's."""
+    """The fused backward (one pass over A^T for dA and dB) at every group shape that covers N or
+    needs at most ceil(N / 256) column windows, split rows of A^T included: dA and dB exact on
+    integer data (dB rounded once for BF16), as the two-pass form's."""
     rng = _rng(500 + N)
     M, K = 3000, 1200
     L = rng.integers(0, 20, size=M)
@@ -381,7 +381,7 @@ def test_fused_backward_integer_exact(N, dtype):
     _, dB_two = ops.spmm_bwd(tile, dCd, Bd)
     ran = 0
     for lanes, vec in FUSED_SHAPES[dtype]:
-        if N % vec or lanes * vec < N:
+        if N % vec or -(-N // (lanes * vec)) > max(1, -(-N // 256)):
             continue
         for depth in (1, 2, 4, 8):
             if depth > lanes:
@@ -418,13 +418,14 @@ def test_fused_variant_argument_errors():
 
 
 def test_fused_backward_choice():
-    """Without an entry both gradients come from the fused pass whenever a group covers N: the
-    results match the two-pass form within FP32 order (dA) and bit for bit (dB, same vector
-    width); with a column slice set, or N too wide for one group, the two-pass form runs."""
+    """Without an entry both gradients come from the fused pass, in column windows when one
+    group does not cover N (260, 600); with a column slice set, or an N whose vector width
+    would need windows narrower than 256 columns (258: two-element vectors), the two-pass
+    form runs; every form matches the oracle."""
     G.note("fused backward choice")
     rng = _rng(510)
     A = synth.powerlaw_csr(1 << 13, 1 << 13, 16, 2048, seed=13)
-    for N, slice_ in [(128, 0), (128, 32), (260, 0)]:
+    for N, slice_ in [(128, 0), (128, 32), (260, 0), (258, 0), (600, 0)]:
         B = synth.dense(A.cols, N, rng, "normal")
         dC = synth.dense(A.rows, N, rng, "normal")
         tile = G.make_tile([A], transpose=True, bwd_slice=slice_)
@@ -438,19 +439,23 @@ def test_fused_backward_choice():
         G.assert_fp32_close(G.host_f32(dB), rB, SB, np.bincount(A.colind, minlength=A.cols), what="dB")
 
 
-@pytest.mark.parametrize("form", ["fused", "two_pass"])
+@pytest.mark.parametrize("form", ["fused", "fused_windows", "two_pass"])
 def test_backward_deterministic_and_graph_replay(form):
     """spmm_bwd (split rows of A^T included) gives the same bits on every call, and a captured
     HIP graph of it, replayed with unrelated eager work between replays and its outputs poisoned
-    before each, reproduces the eager result every time."""
+    before each, reproduces the eager result every time (the fused form in column windows too:
+    its partial dot products summed by a second kernel)."""
     G.note("backward graph replay %s" % form)
     rng = _rng(520)
-    M, K, N = 6000, 900, 128
+    M, K = 6000, 900
+    N = 384 if form == "fused_windows" else 128
     A = synth.random_csr(M, K, rng.integers(0, 40, size=M), rng, "normal")
     tile = G.make_tile([A], transpose=True, long_row=128, segment=64)
     assert tile.stats()["long_rows_t"] > 0
     if form == "fused":
         ops.spmm_tile_set_bwd_variant(tile, N, torch.float32, "fused", 32, 4, 4)
+    elif form == "fused_windows":
+        ops.spmm_tile_set_bwd_variant(tile, N, torch.float32, "fused", 64, 4, 4)   # 2 windows of 256
     else:
         ops.spmm_tile_set_bwd_variant(tile, N, torch.float32, "rowsplit", 0, 0)
     Bd = G.dense_dev(synth.dense(K, N, rng, "normal"))
