@@ -19,6 +19,8 @@ the FP64 oracle on a sample.  Other workloads:
     powerlaw2m_n128_fwdbwd  2,097,152^2 heavy-tailed rows (mean 32, max 65,536), N = 128,
                             forward + dA (sampled dense-dense product) + dB = A^T dC
     powerlaw2m_n128_fwdbwd_bf16  the same with B, C, dC and dB in BF16 (FP32 accumulation)
+    powerlaw2m_n512_fwdbwd  the same matrix at N = 512 (library default shapes: the fused
+                            backward in column windows)
     rmat23_n256_bf16        R-MAT scale 23, edge factor 32, N = 256, BF16 B and C
     rmat23_n256_f32         the same with FP32 B and C
     stationary_a_rmat22_tile00_n128x4
@@ -96,6 +98,20 @@ def _apply_pin(name, tile, N, dtype):
     kind, lanes, vec = pin["variant"]
     ops.spmm_tile_set_variant(tile, N, dtype, kind, lanes, vec)
     return {"kind": kind, "lanes": lanes, "vec": vec, "pinned": True}
+
+
+def _library_bwd_fused(N, dtype):
+    """Whether spmm_bwd takes the fused form at width N without a variant entry (16-byte aligned
+    operands): the widest vector dividing N and 64-lane groups need at most max(1, ceil(N / 256))
+    column windows."""
+    e = 4 if dtype == "f32" else 2
+    V = 16 // e
+    while V > 1 and N % V:
+        V //= 2
+    G = 4
+    while G < 64 and G * V < N:
+        G *= 2
+    return -(-N // (G * V)) <= max(1, -(-N // 256))
 
 
 def _log(msg):
@@ -449,6 +465,9 @@ class ForwardBackward(Workload):
             self.config["sddmm"] = {"lanes": sd[0], "nnz_per_group": sd[1], "pinned": True}
         fk = "fwd_main" if (self.config["variant"] or {}).get("kind") == "rowsplit" else "fwd_stream"
         bkind = (self.config.get("bwd_variant") or {}).get("kind")
+        if bkind is None:   # no entry: the library's rule, which takes the fused form for these operands
+            bkind = "fused" if _library_bwd_fused(self.N, self.dtype) else "stream"
+            self.config["bwd_variant"] = {"kind": bkind, "library_rule": True}
         self.fused = bkind == "fused"
         if self.fused:
             self.kernel = "spmm_fwd + spmm_bwd (%s, fwd_fixup, bwd_fused over the transpose)" % fk
@@ -1130,6 +1149,11 @@ def workloads():
             "powerlaw2m_n128_fwdbwd", lambda: synth.powerlaw_csr(1 << 21, 1 << 21, 32, 65536, seed=3), 128,
             {"workload": "powerlaw2m_n128_fwdbwd", "matrix": "2,097,152^2, Pareto(2.1) row degrees, mean 32, "
              "max 65,536, values N(0,1)/sqrt(deg)", "seed": 3}),
+        "powerlaw2m_n512_fwdbwd": lambda: ForwardBackward(
+            "powerlaw2m_n512_fwdbwd", lambda: synth.powerlaw_csr(1 << 21, 1 << 21, 32, 65536, seed=3), 512,
+            {"workload": "powerlaw2m_n512_fwdbwd", "matrix": "2,097,152^2, Pareto(2.1) row degrees, mean 32, "
+             "max 65,536, values N(0,1)/sqrt(deg); N = 512: the library's default shapes, the fused backward "
+             "in two 256-column windows", "seed": 3}),
     }
 
 
