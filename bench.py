@@ -124,6 +124,7 @@ def _log(msg):
 FWD_SOURCES = ("elem.hpp", "fwd_common.hpp", "fwd.hip", "hot.hip")
 KERNEL_SOURCES = {"powerlaw2m_n128_fwdbwd": FWD_SOURCES + ("bwd.hip",),
                   "powerlaw2m_n128_fwdbwd_bf16": FWD_SOURCES + ("bwd.hip",),
+                  "powerlaw2m_n512_fwdbwd": FWD_SOURCES + ("bwd.hip",),
                   "uneven512_batched": ("elem.hpp", "fwd_common.hpp", "batch.hip"),
                   "spgemm_rmat18_ef16_aa": ("spgemm.hip",),
                   "spgemm_er1m16_aa": ("spgemm.hip",)}
