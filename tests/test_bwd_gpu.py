@@ -309,14 +309,15 @@ def test_dB_variants_integer_exact(variant, dtype):
         assert np.array_equal(got, oracle.f32_to_bf16(rB.astype(np.float32)))
 
 
+@pytest.mark.parametrize("N", [128, 384])
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-def test_autotune_bwd(dtype):
-    """The dB-pass autotuner keeps a variant; the backward then still matches the oracle."""
-    G.note("autotune dB %s" % dtype)
+def test_autotune_bwd(dtype, N):
+    """The dB-pass autotuner keeps a variant; the backward then still matches the oracle (at
+    N = 384 the fused candidates include column windows)."""
+    G.note("autotune dB %s N=%d" % (dtype, N))
     rng = _rng(96)
     A = synth.powerlaw_csr(1 << 14, 1 << 14, 16, 4096, seed=9)
     A = synth.CSR(A.rows, A.cols, A.rowptr, A.colind, rng.integers(-8, 9, size=A.nnz).astype(np.float32))
-    N = 128
     B = synth.dense(A.cols, N, rng, "int8")
     dC = synth.dense(A.rows, N, rng, "int8")
     tdt = torch.float32 if dtype == "f32" else torch.bfloat16
