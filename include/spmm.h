@@ -87,7 +87,8 @@ typedef struct {
                               columns are copied on every spmm_fwd call into one contiguous block of
                               the workspace and read there (the handle keeps a copy of colind with
                               those entries tagged; results are bit-identical).  -1 = off; 0 =
-                              library rule (up to 16384 rows per k-tile of <= 2^27 columns, each
+                              library rule (up to one row per 128 columns of a k-tile of <= 2^27
+                              columns, at least 16384 and at most 65536 rows, each
                               used >= 16 times, for tiles of >= 2^20 non-zeros, where they serve
                               >= 1/8 of the k-tile's non-zeros and >= 8x their share of its
                               columns); n > 0 = up to n most used columns of every k-tile

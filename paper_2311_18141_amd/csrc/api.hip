@@ -43,11 +43,17 @@ constexpr int32_t kDefaultLongRow = 128;
 constexpr int32_t kDefaultSegment = 64;
 // Largest split threshold: 64 rows of at most this length sum below 2^31.
 constexpr int32_t kMaxLongRow = ((int64_t)1 << 31) / 64 - 1;
-// Hot-row staging, library default: up to this many B rows per k-tile, each used by at
-// least kHotMinUses non-zeros, for tiles of at least kHotMinNnz non-zeros in total, and
-// only where the staged rows serve at least 1/8 of the k-tile's non-zeros and at least
+// Hot-row staging, library default: up to one B row per kHotColsPerRow columns of the
+// k-tile, at least kDefaultHotRows and at most kHotRowsCap, each used by at least
+// kHotMinUses non-zeros, for tiles of at least kHotMinNnz non-zeros in total, and only
+// where the staged rows serve at least 1/8 of the k-tile's non-zeros and at least
 // kHotConcentration times their share of its columns (a skewed column distribution).
+// Measured: on the R-MAT scale-22 row block (k-tiles of 2^20 columns) 4K to 64K rows per
+// k-tile ran within 3% of each other; on R-MAT scale 23 (one tile of 2^23 columns) 64K
+// rows ran 2.7% (BF16) and 2.8% (FP32) faster than 16K, 128K no faster in FP32.
 constexpr int32_t kDefaultHotRows = 16384;
+constexpr int32_t kHotRowsCap = 65536;
+constexpr int64_t kHotColsPerRow = 128;
 constexpr int32_t kMaxHotRows = 1 << 24;
 constexpr int32_t kHotMinUses = 16;
 constexpr int64_t kHotMinNnz = (int64_t)1 << 20;
@@ -525,8 +531,8 @@ hipError_t launch_forward(const spmm_tile_s* A, const Plan& plan, int k_offset, 
 }
 
 // Choose each k-tile's staged hot rows and build its tagged colind (synchronous).
-// want < 0: none; want = 0: the library rule (kDefaultHotRows per k-tile, subject to
-// the use, size and skew tests); want > 0: up to `want` of each k-tile's most used
+// want < 0: none; want = 0: the library rule (kDefaultHotRows to kHotRowsCap per k-tile
+// by its width, subject to the use, size and skew tests); want > 0: up to `want` of each k-tile's most used
 // columns (used at least once), no further test.  Columns are ranked by use count,
 // ties by index.
 spmm_status select_hot(spmm_tile_s* h, const spmm_csr* tiles, int K, int32_t want, hipStream_t s,
@@ -534,7 +540,6 @@ spmm_status select_hot(spmm_tile_s* h, const spmm_csr* tiles, int K, int32_t wan
   *hot_nnz = 0;
   if (want < 0) return SPMM_OK;
   const bool forced = want > 0;
-  const int64_t hmax = forced ? want : kDefaultHotRows;
   const int32_t min_uses = forced ? 1 : kHotMinUses;
   int64_t nnz_total = 0, max_cols = 0;
   for (int k = 0; k < K; ++k) {
@@ -556,6 +561,8 @@ spmm_status select_hot(spmm_tile_s* h, const spmm_csr* tiles, int K, int32_t wan
       HIP_TRY(hipMemcpyAsync(cnt.data(), dbuf, sizeof(int32_t) * (size_t)t.cols, hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       std::vector<int32_t>& c = chosen[k];
+      const int64_t hmax =
+          forced ? want : std::min<int64_t>(kHotRowsCap, std::max<int64_t>(kDefaultHotRows, t.cols / kHotColsPerRow));
       for (int64_t j = 0; j < t.cols; ++j)
         if (cnt[j] >= min_uses) c.push_back((int32_t)j);
       auto hotter = [&](int32_t a, int32_t b) { return cnt[a] != cnt[b] ? cnt[a] > cnt[b] : a < b; };

@@ -197,6 +197,24 @@ def test_default_rule():
         assert torch.equal(G.fwd(t, dB), G.fwd(off, dB)), kind
 
 
+def test_default_rule_scales_with_width():
+    """Library rule on a wide tile (2^23 columns): up to one staged row per 128 columns, at most
+    65,536 (16,384 for tiles of 2^21 columns or fewer); results bit-identical to no staging."""
+    G.note("hot default rule, wide tile")
+    A = _skewed_large(1 << 17, 1 << 23, 24, 80000, 0.7, 14)
+    t = G.make_tile([A])
+    st = t.stats()
+    cnt = np.bincount(A.colind, minlength=A.cols)
+    used16 = np.sort(cnt[cnt >= 16])[::-1]
+    assert used16.size > 65536
+    assert st["hot_rows"] == 65536
+    assert st["hot_nnz"] == int(used16[:65536].sum())
+    N = 64
+    dB = [G.dense_dev(synth.dense(A.cols, N, _rng(15)))]
+    off = G.make_tile([A], hot_rows=-1)
+    assert torch.equal(G.fwd(t, dB), G.fwd(off, dB))
+
+
 def test_autotune_with_staging_integer_exact():
     G.note("hot autotune")
     tiles = _skewed_tiles(seed=14, kind="int8")
