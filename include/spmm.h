@@ -159,7 +159,7 @@ typedef struct {
                       0 = library choice */
   int32_t vec;     /* elements per lane per load: 1, 2, 4 (and 8 for BF16); 0 = widest aligned */
   int32_t depth;   /* FUSED only: entries of a row of A^T in flight per group, 1, 2, 4 or 8 (at
-                      most `lanes`); 0 = library choice (4); must be 0 for the other kinds */
+                      most `lanes`); 0 = library choice (4 FP32, 2 BF16); must be 0 for the other kinds */
 } spmm_variant;
 
 /* Set (v != NULL) or clear (v == NULL) the variant used for width N and `dtype`.

@@ -369,9 +369,10 @@ spmm::Variant resolve_variant(const spmm_tile_s* A, int64_t N, DT dt, uintptr_t 
 // need at most that many windows, else the library's shape is used: the widest aligned
 // vector (16 bytes a lane) and the smallest power-of-two group covering N, 64 lanes and
 // ceil(N / (64 V)) column windows when none does.  U = the entry's
-// depth, else 4 entries in flight per group (at most the group's lanes): on the
-// heavy-tailed 2M x 2M matrix at N = 128, U = 4 ran the FP32 backward in 5.68 ms against
-// 5.97 ms with U = 8 (7.8 with 16, 7.8 with 1), BF16 3.89 against 4.25 ms.
+// depth, else 4 (FP32) or 2 (BF16) entries in flight per group (at most the group's
+// lanes): on the heavy-tailed 2M x 2M matrix at N = 128, U = 4 ran the FP32 backward in
+// 5.68 ms against 5.97 ms with U = 8 (7.8 with 16, 7.8 with 1); BF16 3.79 ms with U = 2
+// against 3.89 with U = 4 and 4.25 with U = 8 (the autotuner also picks U = 2 at N = 512).
 struct FusedShape {
   int G, V, U, n_win;
 };
@@ -394,7 +395,7 @@ bool fused_shape(const spmm_tile_s* A, int64_t N, DT dt, uintptr_t align_or, Fus
   int V = 16 / esize;
   while (V > 1 && !aligned(V)) V /= 2;
   int G = covering(V);
-  int U = 4;
+  int U = dt == DT::F32 ? 4 : 2;
   auto windows = [&](int g, int v) { return (N + (int64_t)g * v - 1) / ((int64_t)g * v); };
   if (ent) {
     const int Ve = ent->vec ? ent->vec : V;
