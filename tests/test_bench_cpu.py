@@ -77,3 +77,14 @@ def test_gather_ceiling_interpolation(monkeypatch):
     assert r["gathered_GB"] == pytest.approx(2500.0)
     # rows wider than 1 KiB use the 1 KiB probe
     assert bench._probe_width(4096) == 1024 and bench._probe_width(256) == 256
+
+
+def test_library_bwd_rule_mirror():
+    """The bench's reading of the backward's library rule (which form runs without an entry):
+    fused while 64-lane windows of the widest vector dividing N stay at least 256 columns wide
+    (or one group covers N), else the two-pass form."""
+    for dtype in ("f32", "bf16"):
+        for N in (1, 3, 64, 100, 128, 256, 260, 300, 512, 600, 1024):
+            assert bench._library_bwd_fused(N, dtype), (N, dtype)
+        assert not bench._library_bwd_fused(258, dtype)          # two-element vectors: 128-column windows
+    assert not bench._library_bwd_fused(1026, "f32")             # 1026 = 2 x 513: 128-column windows
