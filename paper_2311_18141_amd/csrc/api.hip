@@ -163,28 +163,37 @@ int stream_rows_for(int64_t rows) {
   return R;
 }
 
-// Kernel variant for width N when the handle has no entry: for N >= 256 (aligned)
-// column windows of 512 bytes of each B row, the stream kernel over 128 FP32 columns or
-// a full-wave row-split group over 256 BF16 columns; for N >= 64 the stream kernel over
-// windows of 64 FP32 / 128 BF16 columns; below that a row-split group with the widest
-// aligned vector and the smallest power-of-two group covering N.
-spmm::Variant pick_variant(int64_t N, DT dt, uintptr_t align_or, int64_t rows) {
+// Kernel variant for width N when the handle has no entry, by the width and by the
+// share of empty rows (`empty` of `rows`; < 0: unknown, taken as many).  Column windows
+// of 512 bytes of each B row for N >= 256 (128 FP32 / 256 BF16 columns), of 256 bytes for
+// 64 <= N < 256 (64 FP32 / 128 BF16 columns); on them the stream kernel for tiles with
+// more than 1/8 empty rows (R-MAT's, whose short and empty rows a wave streams past),
+// else a full-wave row-split group (64 lanes per row; always for BF16 at N >= 256).
+// Below 64 a row-split group with the widest aligned vector and the smallest
+// power-of-two group covering N.
+spmm::Variant pick_variant(int64_t N, DT dt, uintptr_t align_or, int64_t rows, int64_t empty) {
   const int esize = dt == DT::F32 ? 4 : 2;
   int V = 16 / esize;
   while (V > 1 && ((N % V) != 0 || (align_or % (uintptr_t)(V * esize)) != 0)) V /= 2;
+  const bool sparse = empty < 0 || empty * 8 > rows;
   if (N >= 256) {
     // the autotuner's picks at N = 256..1024 on the heavy-tailed 2M x 2M matrix and at
-    // N = 256 on R-MAT scale 23: 10% (FP32) to 27% (BF16) faster than 256-byte windows
-    if (dt == DT::F32 && V >= 2) return spmm::Variant{64, 2, true, stream_rows_for(rows)};
+    // N = 256 on R-MAT scale 23: 5% (FP32) to 27% (BF16) faster than 256-byte windows
+    // (on the heavy-tailed matrix the FP32 stream kernel is 5% faster than the row-split
+    // group at N = 1024 and even at 256 and 512; on the 512 uneven tiles the row-split
+    // group's per-tile loop took 37.4 ms against 41.3 ms)
+    if (dt == DT::F32 && V >= 2) return sparse ? spmm::Variant{64, 2, true, stream_rows_for(rows)} : spmm::Variant{64, 2, false};
     if (dt == DT::BF16 && V >= 4) return spmm::Variant{64, 4, false};
   }
   if (N >= 64) {
     // column windows of about 256 bytes of each B row (64 FP32 or 128 BF16 columns):
     // the grid walks the windows one after the other, so a narrower window keeps a
     // smaller slice of B in the caches; measured faster than one window over all of
-    // N on the R-MAT and heavy-tailed matrices
+    // N on the R-MAT and heavy-tailed matrices.  Without many empty rows the row-split
+    // group: on the 512 uneven tiles (uniform columns, 4 to 256 per row) the per-tile
+    // loop took 34.7 ms with it against 60.0 ms with the stream kernel (32.2 autotuned)
     const int Vs = (dt == DT::BF16 && N > 64 && V >= 2) ? 2 : 1;
-    return spmm::Variant{64, Vs, true, stream_rows_for(rows)};
+    return sparse ? spmm::Variant{64, Vs, true, stream_rows_for(rows)} : spmm::Variant{64, Vs, false};
   }
   const int64_t need = (N + V - 1) / V;
   int G = 4;
@@ -336,8 +345,9 @@ using VarEntry = spmm_tile_s::VarEntry;
 
 // The variant for one call: the table's entry for (N, dtype) when it fits the call's
 // alignment, otherwise the fixed rule (for a pass over `rows` rows).
-spmm::Variant resolve_variant_in(const VarEntry* vt, int nvt, int64_t rows, int64_t N, DT dt, uintptr_t align_or) {
-  const spmm::Variant base = pick_variant(N, dt, align_or, rows);
+spmm::Variant resolve_variant_in(const VarEntry* vt, int nvt, int64_t rows, int64_t empty, int64_t N, DT dt,
+                                 uintptr_t align_or) {
+  const spmm::Variant base = pick_variant(N, dt, align_or, rows, empty);
   const int esize = dt == DT::F32 ? 4 : 2;
   const int want = dt == DT::F32 ? SPMM_F32 : SPMM_BF16;
   for (int i = 0; i < nvt; ++i) {
@@ -358,7 +368,7 @@ spmm::Variant resolve_variant_in(const VarEntry* vt, int nvt, int64_t rows, int6
 }
 
 spmm::Variant resolve_variant(const spmm_tile_s* A, int64_t N, DT dt, uintptr_t align_or) {
-  return resolve_variant_in(A->vt, A->nvt, A->rows, N, dt, align_or);
+  return resolve_variant_in(A->vt, A->nvt, A->rows, (int64_t)A->plan.stats[1], N, dt, align_or);
 }
 
 // Shape of the fused backward (one pass over the transposed structure for dA and dB)
@@ -437,7 +447,7 @@ spmm_status set_variant_in(VarEntry* vt, int* nvt, int64_t N, spmm_dtype dtype, 
 // Autotuner candidates for width N: the two widest aligned vector widths, for each the
 // covering group size, half of it and a full wave, a full-wave group at a quarter of
 // the widest width, and the stream kernel (64, 16 and 4 rows per wave).
-std::vector<spmm::Variant> candidate_variants(int64_t N, DT dt, uintptr_t align_or, int64_t rows) {
+std::vector<spmm::Variant> candidate_variants(int64_t N, DT dt, uintptr_t align_or, int64_t rows, int64_t empty) {
   const int esize = dt == DT::F32 ? 4 : 2;
   std::vector<spmm::Variant> kv;
   auto add = [&](spmm::Variant v) {
@@ -446,7 +456,7 @@ std::vector<spmm::Variant> candidate_variants(int64_t N, DT dt, uintptr_t align_
       if (u.G == v.G && u.V == v.V && u.stream == v.stream && (!v.stream || u.rows == v.rows)) return;
     kv.push_back(v);
   };
-  add(pick_variant(N, dt, align_or, rows));
+  add(pick_variant(N, dt, align_or, rows, empty));
   int vmax = 16 / esize;
   while (vmax > 1 && ((N % vmax) != 0 || (align_or % (uintptr_t)(vmax * esize)) != 0)) vmax /= 2;
   for (int V = vmax; V >= 1 && V >= vmax / 4; V /= 2) {
@@ -953,8 +963,8 @@ static spmm_status autotune_impl(spmm_tile_t A, int64_t N, spmm_dtype dtype, con
   if (dev != A->device) return fail(SPMM_ERR_INVALID_ARG, "current device differs from the handle's");
   hipStream_t s = static_cast<hipStream_t>(stream);
 
-  const spmm::Variant base = pick_variant(N, dt, align_or, A->rows);
-  const std::vector<spmm::Variant> kv = candidate_variants(N, dt, align_or, A->rows);
+  const spmm::Variant base = pick_variant(N, dt, align_or, A->rows, (int64_t)A->plan.stats[1]);
+  const std::vector<spmm::Variant> kv = candidate_variants(N, dt, align_or, A->rows, (int64_t)A->plan.stats[1]);
   // Split-plan candidates (threshold, unit length).
   std::vector<std::pair<int32_t, int32_t>> pc;
   pc.push_back({A->plan.long_row, A->plan.segment});
@@ -1226,7 +1236,8 @@ spmm_status spmm_bwd(spmm_tile_t A, const void* dC, int64_t lddc, const void* B,
     P.ldp = (int64_t)partial_ld(N);
     const uintptr_t a = reinterpret_cast<uintptr_t>(dC) | reinterpret_cast<uintptr_t>(dB) |
                         (uintptr_t)(lddc * esize) | (uintptr_t)(lddb * esize);
-    HIP_TRY(spmm::launch_fwd(P, resolve_variant_in(A->vtT, A->nvtT, t.cols, N, dt, a), dt, s));
+    HIP_TRY(spmm::launch_fwd(P, resolve_variant_in(A->vtT, A->nvtT, t.cols, (int64_t)A->planT.stats[1], N, dt, a), dt,
+                             s));
   }
   return SPMM_OK;
 }
@@ -1258,7 +1269,7 @@ static spmm_status autotune_bwd_impl(spmm_tile_t A, int64_t N, spmm_dtype dtype,
   // given, fused shapes at the widest aligned vector width and at half and a quarter of it,
   // each with 2, 4 and 8 entries in flight per group.
   std::vector<spmm_variant> cand;
-  for (const auto& v : candidate_variants(N, dt, a, t.cols))
+  for (const auto& v : candidate_variants(N, dt, a, t.cols, (int64_t)A->planT.stats[1]))
     cand.push_back(spmm_variant{v.stream ? SPMM_KERNEL_STREAM : SPMM_KERNEL_ROWSPLIT, v.stream ? v.rows : v.G, v.V, 0});
   if (full) {
     a |= reinterpret_cast<uintptr_t>(B) | (uintptr_t)(ldb * esize);
@@ -1381,7 +1392,6 @@ namespace {
 // Batched variant of one tile: the handle's table entry for (N, dtype), else the rule
 // below; vectors assume 16-byte aligned rows (a documented requirement of spmm_batched).
 void batch_variant(const spmm_tile_s* A, int64_t N, DT dt, spmm::BatchTileDev* bt, spmm_variant* out) {
-  (void)dt;
   int Vs = 4;  // stream / unit vector (at most 4 elements per lane): widest dividing N, not wider than needed
   while (Vs > 1 && ((N % Vs) != 0 || 64 * (Vs / 2) >= N)) Vs /= 2;
   const spmm_variant* e = nullptr;
@@ -1389,7 +1399,10 @@ void batch_variant(const spmm_tile_s* A, int64_t N, DT dt, spmm::BatchTileDev* b
     if (A->vt[i].N == N && A->vt[i].dtype == (dt == DT::F32 ? SPMM_F32 : SPMM_BF16) &&
         A->vt[i].v.kind != SPMM_KERNEL_AUTO)
       e = &A->vt[i].v;
-  bool stream = N >= 64;
+  // without an entry: the stream kernel for N >= 64 on tiles with more than 1/8 empty rows,
+  // else row-split items over 256-byte windows (64 FP32 / 128 BF16 columns), as the
+  // single-tile rule
+  bool stream = N >= 64 && (int64_t)A->plan.stats[1] * 8 > A->rows;
   int G = 8;
   if (e) {
     stream = e->kind == SPMM_KERNEL_STREAM;
@@ -1403,8 +1416,9 @@ void batch_variant(const spmm_tile_s* A, int64_t N, DT dt, spmm::BatchTileDev* b
     if ((N % 4) != 0) {  // row-split items load 4 elements per lane; otherwise stream
       stream = true;
     } else if (!e || e->lanes < 4) {
+      const int g_max = dt == DT::F32 ? 16 : 32;
       G = 8;
-      while (G < 64 && G * 4 < N) G *= 2;
+      while (G < g_max && G * 4 < N) G *= 2;
     }
   }
   bt->kind = stream ? 0 : 1;
