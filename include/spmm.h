@@ -145,7 +145,10 @@ spmm_status spmm_tile_export_transpose(spmm_tile_t tile, int32_t* rowptrT, int32
                                        int32_t* perm, void* stream);
 
 /* Forward kernel variants.  A handle keeps one variant per (N, dtype); without an
-   entry the library picks by a fixed rule.  These entry points exist for tuning and
+   entry the library picks by a fixed rule: column windows of 256 bytes of each B row
+   (512 for N >= 256), the stream kernel on tiles with more than 1/8 empty rows and a
+   full-wave row-split group otherwise, and below N = 64 the row-split group that covers
+   N with the widest aligned vector.  These entry points exist for tuning and
    tests; results of every variant agree within the tolerance of the operation (and
    bit-for-bit on integer-valued inputs). */
 #define SPMM_KERNEL_AUTO 0
