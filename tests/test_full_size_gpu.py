@@ -136,6 +136,39 @@ def test_powerlaw2m_fwd_bwd_sampled(powerlaw2m):
     G.assert_fp32_close(gotB, rB, SB, cnt[cols], what="dB")
 
 
+def test_powerlaw2m_n512_windowed_backward_sampled(powerlaw2m):
+    """The heavy-tailed matrix at N = 512 with the library's default shapes, as the bench's
+    N = 512 workload runs it: the fused backward in two 256-column windows (partial dot
+    products summed by a second kernel) and the row-split forward; sampled C, dA and dB
+    against the FP64 oracle."""
+    A, _, _, tile, _ = powerlaw2m
+    G.note("full powerlaw 2M N=512 windowed backward sampled")
+    N = 512
+    rs = synth.streams(5)
+    B = synth.dense(A.cols, N, rs[2], "normal")
+    dC = synth.dense(A.rows, N, rs[3], "normal")
+    Bd, dCd = G.dense_dev(B), G.dense_dev(dC)
+    C = G.fwd(tile, [Bd])
+    dA, dB = ops.spmm_bwd(tile, dCd, Bd)
+    torch.cuda.synchronize()
+    rng = _rng(37)
+    lens = A.row_lengths()
+    rows = _sample_rows(lens, rng)
+    ref, S = G.oracle_fwd([A], [B], rows=rows)
+    G.assert_fp32_close(C[torch.from_numpy(rows).to(C.device)].cpu().numpy(), ref, S, lens[rows], what="C")
+    ents = np.unique(np.concatenate([rng.choice(A.nnz, 1000, replace=False),
+                                     np.arange(A.rowptr[np.argmax(lens)], A.rowptr[np.argmax(lens)] + 50)]))
+    rA, SA = oracle.sddmm(A.rowptr, A.colind, dC, B, entries=ents.astype(np.int64))
+    gotA = dA[torch.from_numpy(ents).to(dA.device)].cpu().numpy()
+    st = compare.fp32_stats(gotA, rA, SA, n_terms=np.full(ents.size, N))
+    assert compare.fp32_ok(st), st
+    cnt = np.bincount(A.colind, minlength=A.cols)
+    cols = np.unique(np.concatenate([rng.choice(A.cols, 1000, replace=False), np.argsort(cnt)[-20:]]))
+    rB, SB = oracle.spmm_t(A.rowptr, A.colind, A.values, A.cols, dC, out_rows=cols.astype(np.int64))
+    gotB = dB[torch.from_numpy(cols).to(dB.device)].cpu().numpy()
+    G.assert_fp32_close(gotB, rB, SB, cnt[cols], what="dB")
+
+
 def test_powerlaw2m_fwd_bwd_bf16_sampled(powerlaw2m):
     """The BF16 forward + backward workload (B, C, dC, dB in BF16; dA FP32) at full size with its
     pinned shapes: C and dB within the BF16 bound, dA within the FP32 bound, on bf16(B), bf16(dC)."""
