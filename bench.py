@@ -102,8 +102,8 @@ def _apply_pin(name, tile, N, dtype):
 
 def _library_bwd_fused(N, dtype):
     """Whether spmm_bwd takes the fused form at width N without a variant entry (16-byte aligned
-    operands): the widest vector dividing N and 64-lane groups need at most max(1, ceil(N / 256))
-    column windows."""
+    operands): the widest vector dividing N and 64-lane groups need at most min(8, max(1,
+    ceil(N / 256))) column windows."""
     e = 4 if dtype == "f32" else 2
     V = 16 // e
     while V > 1 and N % V:
@@ -111,7 +111,7 @@ def _library_bwd_fused(N, dtype):
     G = 4
     while G < 64 and G * V < N:
         G *= 2
-    return -(-N // (G * V)) <= max(1, -(-N // 256))
+    return -(-N // (G * V)) <= min(8, max(1, -(-N // 256)))
 
 
 def _log(msg):

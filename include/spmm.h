@@ -241,12 +241,13 @@ size_t spmm_noalloc_scratch_bytes(void);
    (v == NULL; the library rule then applies).  Kind SPMM_KERNEL_FUSED selects the fused
    backward (when spmm_bwd is asked for both dA and dB): a group of `lanes` lanes owns one
    row of A^T with `vec` columns per lane, in column windows of lanes x vec columns when
-   that is less than N (at most ceil(N / 256) windows; 0 = library choice; a shape that
-   does not fit a call's alignment or needs more windows falls back to the library's).
+   that is less than N (at most min(8, ceil(N / 256)) windows; 0 = library choice; a
+   shape that does not fit a call's alignment or needs more windows falls back to the
+   library's).
    Kinds ROWSPLIT and STREAM select the two-pass backward (SDDMM for dA, then the forward
    kernels over the transposed structure for dB) and name the dB pass's kernel.  Without
-   an entry the fused backward runs whenever the operands' alignment allows windows of
-   at least 256 columns (or one group covers N).
+   an entry the fused backward runs whenever the operands' alignment allows at most 8
+   windows of at least 256 columns (or one group covers N).
    Results of every variant agree as the forward's do (dB bit-identical between the fused
    and two-pass forms at the same vector width and split plan; dA within FP32 summation
    order).  Errors: INVALID_ARG (bad field values, table of 16 entries full). */
@@ -265,8 +266,8 @@ spmm_status spmm_tile_autotune_bwd(spmm_tile_t tile, int64_t N, spmm_dtype dtype
                                    int64_t lddb, void* stream, spmm_variant* chosen /* host */);
 
 /* Workspace (device bytes) spmm_bwd needs for this handle at width N when dB is
-   wanted: FP32 partial rows of the transposed plan's split rows plus 4 x max(1,
-   ceil(N / 256)) bytes per non-zero (A's values gathered into the transposed order by
+   wanted: FP32 partial rows of the transposed plan's split rows plus 4 x min(8, max(1,
+   ceil(N / 256))) bytes per non-zero (A's values gathered into the transposed order by
    the two-pass form, or the fused form's partial dot products, one per column window). */
 spmm_status spmm_bwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes /* host */);
 

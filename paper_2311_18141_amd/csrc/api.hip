@@ -387,8 +387,11 @@ struct FusedShape {
   int G, V, U, n_win;
 };
 // The most column windows the fused backward may use at width N (its workspace holds
-// that many arrays of partial dot products): windows of at least 256 columns.
-int64_t fused_windows_max(int64_t N) { return std::max<int64_t>(1, (N + 255) / 256); }
+// that many arrays of partial dot products): windows of at least 256 columns, at most
+// kMaxFusedWindows of them (wider N takes the two-pass form, whose workspace does not
+// grow with N).
+constexpr int64_t kMaxFusedWindows = 8;
+int64_t fused_windows_max(int64_t N) { return std::min<int64_t>(kMaxFusedWindows, std::max<int64_t>(1, (N + 255) / 256)); }
 bool fused_shape(const spmm_tile_s* A, int64_t N, DT dt, uintptr_t align_or, FusedShape* out) {
   const int esize = dt == DT::F32 ? 4 : 2;
   const int want = dt == DT::F32 ? SPMM_F32 : SPMM_BF16;
@@ -821,7 +824,8 @@ spmm_status spmm_fwd_workspace_bytes(spmm_tile_t A, int64_t N, size_t* bytes) {
 // Backward workspace: FP32 partial rows of the transposed plan's split rows, then
 // (16-byte aligned) either A's values gathered into the transposed order (the two-pass
 // form) or the fused form's partial dot products, one array of nnz per column window
-// when G * V < N (at most fused_windows_max(N) windows: at least 256 columns each).
+// when G * V < N (at most fused_windows_max(N) windows: at least 256 columns each, at
+// most 8).
 static size_t bwd_partial_bytes(const spmm_tile_s* A, int64_t N) {
   return (sizeof(float) * partial_ld(N) * (size_t)A->planT.n_seg + 15) & ~(size_t)15;
 }

@@ -88,3 +88,5 @@ def test_library_bwd_rule_mirror():
             assert bench._library_bwd_fused(N, dtype), (N, dtype)
         assert not bench._library_bwd_fused(258, dtype)          # two-element vectors: 128-column windows
     assert not bench._library_bwd_fused(1026, "f32")             # 1026 = 2 x 513: 128-column windows
+    assert bench._library_bwd_fused(2048, "f32") and not bench._library_bwd_fused(2304, "f32")   # at most 8
+    assert bench._library_bwd_fused(4096, "bf16") and not bench._library_bwd_fused(4608, "bf16")  # windows

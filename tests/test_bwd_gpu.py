@@ -382,7 +382,7 @@ def test_fused_backward_integer_exact(N, dtype):
     _, dB_two = ops.spmm_bwd(tile, dCd, Bd)
     ran = 0
     for lanes, vec in FUSED_SHAPES[dtype]:
-        if N % vec or -(-N // (lanes * vec)) > max(1, -(-N // 256)):
+        if N % vec or -(-N // (lanes * vec)) > min(8, max(1, -(-N // 256))):
             continue
         for depth in (1, 2, 4, 8):
             if depth > lanes:
