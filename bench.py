@@ -100,6 +100,40 @@ def _apply_pin(name, tile, N, dtype):
     return {"kind": kind, "lanes": lanes, "vec": vec, "pinned": True}
 
 
+def _library_fwd(N, dtype, rows, empty):
+    """The forward kernel (kind, vec) spmm_fwd takes at width N without a variant entry (16-byte
+    aligned operands), by the dtype and the tile's share of empty rows (many: more than 1/8).
+    FP32: stream kernel on tiles with many empty rows, else row-split, over 64-column windows, or
+    128-column ones for N >= 256 and, with many empty rows, for N a multiple of 128.  BF16:
+    row-split over the fewest windows of at most 256 columns on the narrowest vector giving that
+    count (stream at N = 64 with many empty rows)."""
+    e = 4 if dtype == "f32" else 2
+    V = 16 // e
+    while V > 1 and N % V:
+        V //= 2
+    sparse = empty * 8 > rows
+    if N >= 64 and dtype == "bf16":
+        windows = -(-N // 256)
+        vb = 1
+        while vb * 2 <= V and -(-N // (64 * vb)) > windows:
+            vb *= 2
+        return ("stream", 1) if vb == 1 and sparse else ("rowsplit", vb)
+    if N >= 256 and V >= 2:
+        return ("stream" if sparse else "rowsplit", 2)
+    if N >= 64:
+        return ("stream", 2 if V >= 2 and N % 128 == 0 else 1) if sparse else ("rowsplit", 1)
+    return ("rowsplit", V)
+
+
+def _fwd_variant_or_rule(variant, tile, N, dtype):
+    """The forward variant a handle runs at width N: its pinned or tuned entry, else the rule's."""
+    if variant is not None:
+        return variant
+    st = tile.stats()
+    kind, vec = _library_fwd(N, dtype, st["rows"], st["empty_rows"])
+    return {"kind": kind, "vec": vec, "library_rule": True}
+
+
 def _library_bwd_fused(N, dtype):
     """Whether spmm_bwd takes the fused form at width N without a variant entry (16-byte aligned
     operands): the widest vector dividing N and 64-lane groups need at most min(8, max(1,
@@ -270,7 +304,8 @@ class TileRowForward(Workload):
             self.config["variant"] = chosen
         else:
             self.config["variant"] = _apply_pin(self.name, self.tile, self.N, tdt)
-        fk = "fwd_stream" if (self.config["variant"] or {}).get("kind") == "stream" else "fwd_main"
+        self.config["variant"] = _fwd_variant_or_rule(self.config["variant"], self.tile, self.N, self.dtype)
+        fk = "fwd_stream" if self.config["variant"]["kind"] == "stream" else "fwd_main"
         hs = "hot_stage + " if self.tile.stats()["hot_rows"] > 0 else ""
         self.kernel = "spmm_fwd (%s%s + fwd_fixup)" % (hs, fk)
         self.ws = self.tile.workspace(self.N)
@@ -464,7 +499,8 @@ class ForwardBackward(Workload):
         if sd:
             ops.spmm_tile_set_sddmm_variant(self.tile, self.N, sd[0], sd[1])
             self.config["sddmm"] = {"lanes": sd[0], "nnz_per_group": sd[1], "pinned": True}
-        fk = "fwd_main" if (self.config["variant"] or {}).get("kind") == "rowsplit" else "fwd_stream"
+        self.config["variant"] = _fwd_variant_or_rule(self.config["variant"], self.tile, self.N, self.dtype)
+        fk = "fwd_stream" if self.config["variant"]["kind"] == "stream" else "fwd_main"
         bkind = (self.config.get("bwd_variant") or {}).get("kind")
         if bkind is None:   # no entry: the library's rule, which takes the fused form for these operands
             bkind = "fused" if _library_bwd_fused(self.N, self.dtype) else "stream"

@@ -145,10 +145,14 @@ spmm_status spmm_tile_export_transpose(spmm_tile_t tile, int32_t* rowptrT, int32
                                        int32_t* perm, void* stream);
 
 /* Forward kernel variants.  A handle keeps one variant per (N, dtype); without an
-   entry the library picks by a fixed rule: column windows of 256 bytes of each B row
-   (512 for N >= 256), the stream kernel on tiles with more than 1/8 empty rows and a
-   full-wave row-split group otherwise, and below N = 64 the row-split group that covers
-   N with the widest aligned vector.  These entry points exist for tuning and
+   entry the library picks by a fixed rule.  FP32: column windows of 64 columns (256
+   bytes of each B row), of 128 for N >= 256 and, on tiles with more than 1/8 empty
+   rows, for N a multiple of 128; the stream kernel on tiles with more than 1/8 empty
+   rows and a full-wave row-split group otherwise.  BF16: full-wave row-split groups
+   over the fewest windows of at most 256 columns, each on the narrowest vector that
+   gives that count (at N = 64, the stream kernel on tiles with more than 1/8 empty
+   rows).  Below N = 64: the row-split group that covers N with the widest aligned
+   vector.  These entry points exist for tuning and
    tests; results of every variant agree within the tolerance of the operation (and
    bit-for-bit on integer-valued inputs). */
 #define SPMM_KERNEL_AUTO 0

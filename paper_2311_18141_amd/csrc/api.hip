@@ -163,37 +163,54 @@ int stream_rows_for(int64_t rows) {
   return R;
 }
 
-// Kernel variant for width N when the handle has no entry, by the width and by the
-// share of empty rows (`empty` of `rows`; < 0: unknown, taken as many).  Column windows
-// of 512 bytes of each B row for N >= 256 (128 FP32 / 256 BF16 columns), of 256 bytes for
-// 64 <= N < 256 (64 FP32 / 128 BF16 columns); on them the stream kernel for tiles with
-// more than 1/8 empty rows (R-MAT's, whose short and empty rows a wave streams past),
-// else a full-wave row-split group (64 lanes per row; always for BF16 at N >= 256).
-// Below 64 a row-split group with the widest aligned vector and the smallest
-// power-of-two group covering N.
+// Kernel variant for width N when the handle has no entry, by the width, the dtype and
+// the share of empty rows (`empty` of `rows`; < 0: unknown, taken as many; "many" is
+// more than 1/8, R-MAT's, whose short and empty rows a wave of the stream kernel
+// streams past).  FP32: windows of 64 columns (256 bytes of each B row), of 128 for
+// N >= 256 and, on tiles with many empty rows, for N a multiple of 128; the stream
+// kernel on tiles with many empty rows, else a full-wave row-split group.  BF16: a
+// full-wave row-split group over the fewest windows of at most 256 columns, each on the
+// narrowest vector giving that count (the stream kernel at N = 64 on tiles with many
+// empty rows).  Below 64 a row-split group with the widest aligned vector and the
+// smallest power-of-two group covering N.
 spmm::Variant pick_variant(int64_t N, DT dt, uintptr_t align_or, int64_t rows, int64_t empty) {
   const int esize = dt == DT::F32 ? 4 : 2;
   int V = 16 / esize;
   while (V > 1 && ((N % V) != 0 || (align_or % (uintptr_t)(V * esize)) != 0)) V /= 2;
   const bool sparse = empty < 0 || empty * 8 > rows;
-  if (N >= 256) {
-    // the autotuner's picks at N = 256..1024 on the heavy-tailed 2M x 2M matrix and at
-    // N = 256 on R-MAT scale 23: 5% (FP32) to 27% (BF16) faster than 256-byte windows
-    // (on the heavy-tailed matrix the FP32 stream kernel is 5% faster than the row-split
-    // group at N = 1024 and even at 256 and 512; on the 512 uneven tiles the row-split
-    // group's per-tile loop took 37.4 ms against 41.3 ms)
-    if (dt == DT::F32 && V >= 2) return sparse ? spmm::Variant{64, 2, true, stream_rows_for(rows)} : spmm::Variant{64, 2, false};
-    if (dt == DT::BF16 && V >= 4) return spmm::Variant{64, 4, false};
+  if (N >= 64 && dt == DT::BF16) {
+    // BF16: full-wave row-split groups over the fewest windows of at most 256 columns
+    // (512 bytes of each B row), each on the narrowest vector that gives that count.
+    // The autotuner's picks on the heavy-tailed matrix (N = 128..1024) and on three
+    // R-MAT matrices (N = 128, 192, 256): at N = 128 one 128-column window beat the
+    // stream kernel by 13-29%, at N = 192 one 4-wide window beat two 2-wide ones by
+    // 35-38%.  At N = 64 (or one-element vectors) tiles with many empty rows keep the
+    // stream kernel, which streams past them.
+    const int64_t windows = (N + 255) / 256;
+    int Vb = 1;
+    while (Vb * 2 <= V && (N + 64 * Vb - 1) / (64 * Vb) > windows) Vb *= 2;
+    if (Vb == 1 && sparse) return spmm::Variant{64, 1, true, stream_rows_for(rows)};
+    return spmm::Variant{64, Vb, false};
+  }
+  if (N >= 256 && V >= 2) {
+    // FP32 at N >= 256: windows of 128 columns (512 bytes), the autotuner's picks at
+    // N = 256..1024 on the heavy-tailed matrix and at N = 256 on R-MAT: about 5% faster
+    // than 256-byte windows (on the 512 uneven tiles the row-split group's per-tile loop
+    // took 37.4 ms against 41.3 ms with the stream kernel)
+    return sparse ? spmm::Variant{64, 2, true, stream_rows_for(rows)} : spmm::Variant{64, 2, false};
   }
   if (N >= 64) {
-    // column windows of about 256 bytes of each B row (64 FP32 or 128 BF16 columns):
-    // the grid walks the windows one after the other, so a narrower window keeps a
-    // smaller slice of B in the caches; measured faster than one window over all of
-    // N on the R-MAT and heavy-tailed matrices.  Without many empty rows the row-split
-    // group: on the 512 uneven tiles (uniform columns, 4 to 256 per row) the per-tile
-    // loop took 34.7 ms with it against 60.0 ms with the stream kernel (32.2 autotuned)
-    const int Vs = (dt == DT::BF16 && N > 64 && V >= 2) ? 2 : 1;
-    return sparse ? spmm::Variant{64, Vs, true, stream_rows_for(rows)} : spmm::Variant{64, Vs, false};
+    // FP32 windows of 64 columns (256 bytes): the grid walks the windows one after the
+    // other, so a narrower window keeps a smaller slice of B in the caches (faster than
+    // one window over all of N on the heavy-tailed matrix).  On tiles with many empty
+    // rows, the stream kernel, over 128-column windows when they tile N exactly: on three
+    // R-MAT matrices at N = 128 they beat 64-column windows by 9-14% (at N = 192 a ragged
+    // second window lost 3-5%).  Without many empty rows the row-split group: on the 512
+    // uneven tiles (uniform columns, 4 to 256 per row) the per-tile loop took 34.7 ms
+    // with it against 60.0 ms with the stream kernel (32.2 autotuned)
+    if (!sparse) return spmm::Variant{64, 1, false};
+    const int Vs = (V >= 2 && N % 128 == 0) ? 2 : 1;
+    return spmm::Variant{64, Vs, true, stream_rows_for(rows)};
   }
   const int64_t need = (N + V - 1) / V;
   int G = 4;

@@ -90,3 +90,30 @@ def test_library_bwd_rule_mirror():
     assert not bench._library_bwd_fused(1026, "f32")             # 1026 = 2 x 513: 128-column windows
     assert bench._library_bwd_fused(2048, "f32") and not bench._library_bwd_fused(2304, "f32")   # at most 8
     assert bench._library_bwd_fused(4096, "bf16") and not bench._library_bwd_fused(4608, "bf16")  # windows
+
+
+def test_library_fwd_rule_mirror():
+    """bench.py labels a workload without a pinned variant by the library's forward rule; the mirror
+    follows the rule's cases (many empty rows: more than 1/8)."""
+    rows, few, many = 1000, 125, 126
+    # FP32: 64-column windows, 128-column ones for N >= 256 and, on sparse tiles, for N % 128 == 0
+    assert bench._library_fwd(64, "f32", rows, few) == ("rowsplit", 1)
+    assert bench._library_fwd(64, "f32", rows, many) == ("stream", 1)
+    assert bench._library_fwd(128, "f32", rows, few) == ("rowsplit", 1)
+    assert bench._library_fwd(128, "f32", rows, many) == ("stream", 2)
+    assert bench._library_fwd(192, "f32", rows, many) == ("stream", 1)
+    assert bench._library_fwd(512, "f32", rows, few) == ("rowsplit", 2)
+    assert bench._library_fwd(512, "f32", rows, many) == ("stream", 2)
+    assert bench._library_fwd(513, "f32", rows, few) == ("rowsplit", 1)   # odd N: one-element vectors
+    # BF16: row-split over the fewest windows of at most 256 columns, narrowest vector for that count
+    assert bench._library_fwd(64, "bf16", rows, many) == ("stream", 1)
+    assert bench._library_fwd(64, "bf16", rows, few) == ("rowsplit", 1)
+    for empty in (few, many):
+        assert bench._library_fwd(128, "bf16", rows, empty) == ("rowsplit", 2)
+        assert bench._library_fwd(192, "bf16", rows, empty) == ("rowsplit", 4)
+        assert bench._library_fwd(256, "bf16", rows, empty) == ("rowsplit", 4)
+        assert bench._library_fwd(320, "bf16", rows, empty) == ("rowsplit", 4)
+        assert bench._library_fwd(1024, "bf16", rows, empty) == ("rowsplit", 4)
+    # below 64: row-split covering N with the widest vector
+    assert bench._library_fwd(32, "f32", rows, many) == ("rowsplit", 4)
+    assert bench._library_fwd(6, "bf16", rows, many) == ("rowsplit", 2)
