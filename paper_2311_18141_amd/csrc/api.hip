@@ -1421,8 +1421,9 @@ void batch_variant(const spmm_tile_s* A, int64_t N, DT dt, spmm::BatchTileDev* b
         A->vt[i].v.kind != SPMM_KERNEL_AUTO)
       e = &A->vt[i].v;
   // without an entry: the stream kernel for N >= 64 on tiles with more than 1/8 empty rows,
-  // else row-split items over 256-byte windows (64 FP32 / 128 BF16 columns), as the
-  // single-tile rule
+  // else row-split items over 256-byte windows (64 FP32 / 128 BF16 columns); the batch
+  // kernels' row-split items always load 4-element vectors, so their windows differ
+  // from the single-tile rule's at BF16
   bool stream = N >= 64 && (int64_t)A->plan.stats[1] * 8 > A->rows;
   int G = 8;
   if (e) {

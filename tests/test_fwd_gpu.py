@@ -199,6 +199,27 @@ def test_bf16_storage(N, kind):
     assert np.array_equal(got.astype(np.float64), ref)
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("empty_share", [0.5, 0.0])
+def test_default_rule_every_width_class_exact(empty_share, dtype):
+    """No variant entry: the library's own choice at each width class (windows of 64, 128 or 256
+    columns, ragged last windows, stream or row-split by the share of empty rows) on small-integer
+    inputs, exact in FP32 and in BF16 (|C| <= 64 with at most 4 terms a row)."""
+    G.note("default_rule widths empty=%.1f %s" % (empty_share, dtype))
+    rng = _rng(90 + int(empty_share * 10))
+    M, K = 8192, 4096
+    lengths = rng.integers(1, 5, size=M)
+    lengths[rng.random(M) < empty_share] = 0
+    A = synth.random_csr(M, K, lengths, rng, "int4")
+    tile = G.make_tile([A])
+    assert (tile.stats()["empty_rows"] * 8 > M) == (empty_share > 0)
+    for N in (64, 96, 128, 192, 256, 320, 384):
+        B = synth.dense(K, N, rng, "int4")
+        got = G.host_f32(G.fwd(tile, [G.dense_dev(B, dtype)]))
+        ref, _ = G.oracle_fwd([A], [B])
+        assert np.array_equal(got.astype(np.float64), ref), N
+
+
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("N", [32, 128])
 def test_workload_shapes_scaled(N, kind):
