@@ -445,6 +445,19 @@ class TileRowForward(Workload):
         return 2.0 * nnz * self.N, dt, "oracle FP64 forward on rows [0, %d) of %d (%d non-zeros)" % (r, rows, nnz)
 
 
+def _fwdbwd_gather_items(A, N, e, fused):
+    """Gathers of one forward + backward step at element size e: the forward reads a B row per
+    non-zero; the fused backward a dC row per non-zero (the two-pass form: the SDDMM a B row and
+    the dB pass a dC row per non-zero); both backward forms read one 4-byte value per non-zero at
+    random (timed as a 16-byte row, the probe's smallest, from a table of the values' size)."""
+    row = e * N
+    items = [(float(A.nnz) * row, A.cols * row, row), (float(A.nnz) * row, A.rows * row, row),
+             (float(A.nnz) * 16, 4 * A.nnz, 16)]
+    if not fused:
+        items.append((float(A.nnz) * row, A.cols * row, row))
+    return items
+
+
 class ForwardBackward(Workload):
     """Forward, dA = SDDMM on A's pattern, dB = A^T dC: three passes of 2 nnz N flops."""
 
@@ -521,15 +534,7 @@ class ForwardBackward(Workload):
         sddmm = 4 * A.nnz + 4 * (A.rows + 1) + e * A.rows * N + e * A.cols * N + 4 * A.nnz
         dB = 4 * (A.cols + 1) + 12 * A.nnz + e * A.rows * N + e * A.cols * N
         self.alg_bytes = float(fwd + sddmm + dB)
-        # gathers: the forward reads a B row per non-zero; the fused backward a dC row per
-        # non-zero (the two-pass form: the SDDMM a B row and the dB pass a dC row per non-zero);
-        # both backward forms read one 4-byte value per non-zero at random (timed as a 16-byte
-        # row, the probe's smallest, from a table of the values' size)
-        row = e * N
-        self.gather_items = [(float(A.nnz) * row, A.cols * row, row), (float(A.nnz) * row, A.rows * row, row),
-                             (float(A.nnz) * 16, 4 * A.nnz, 16)]
-        if not self.fused:
-            self.gather_items.append((float(A.nnz) * row, A.cols * row, row))
+        self.gather_items = _fwdbwd_gather_items(A, N, e, self.fused)
         st = self.tile.stats()
         self.config = dict(self.config, nnz=A.nnz, rows=A.rows, N=N,
                            tile_stats={k: st[k] for k in ("max_row", "empty_rows", "long_rows", "segments",
@@ -573,9 +578,11 @@ class ForwardBackward(Workload):
             kind, lanes, vec, depth = pin["bwd_variant"]
             ops.spmm_tile_set_bwd_variant(self.tile, self.N, bf, kind, lanes, vec, depth)
             cfg = {"variant": pin["variant"], "bwd_variant": pin["bwd_variant"], "pinned": True}
+            fused = pin["bwd_variant"][0] == "fused"
         else:
             cfg["variant"] = ops.spmm_tile_autotune(self.tile, [self.Bb], self.Cb, tune_plan=False)
             cfg["bwd_variant"] = ops.spmm_tile_autotune_bwd(self.tile, self.dCb, self.dBb, B=self.Bb, dA=self.dAb)
+            fused = cfg["bwd_variant"]["kind"] == "fused"
         self.wsf = self.tile.workspace(self.N, "fwd")
         self.wsb = self.tile.workspace(self.N, "bwd")
 
@@ -591,6 +598,7 @@ class ForwardBackward(Workload):
                 "speedup_vs_f32": round(f32_ms / ms, 3), "kernels": cfg, "steps": steps,
                 "traffic": traffic,
                 "traffic_frac": round(traffic / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
+                "cache_gather": gather_ceiling_report(_fwdbwd_gather_items(self.A, self.N, 2, fused), ms),
                 "passes": self._pass_ms(self.Bb, self.Cb, self.dCb, self.dAb, self.dBb),
                 "note": "same handle and inputs as the FP32 step, B / C / dC / dB stored in BF16"}
 

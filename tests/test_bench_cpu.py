@@ -117,3 +117,14 @@ def test_library_fwd_rule_mirror():
     # below 64: row-split covering N with the widest vector
     assert bench._library_fwd(32, "f32", rows, many) == ("rowsplit", 4)
     assert bench._library_fwd(6, "bf16", rows, many) == ("rowsplit", 2)
+
+
+def test_fwdbwd_gather_items():
+    """A forward + backward step gathers a row of e * N bytes per non-zero in the forward and in
+    the backward (twice in the two-pass form) and one value per non-zero at random."""
+    class A:
+        nnz, rows, cols = 1000, 300, 200
+    f = bench._fwdbwd_gather_items(A, 128, 2, True)
+    assert f == [(1000 * 256.0, 200 * 256, 256), (1000 * 256.0, 300 * 256, 256), (1000 * 16.0, 4000, 16)]
+    t = bench._fwdbwd_gather_items(A, 64, 4, False)
+    assert len(t) == 4 and t[3] == (1000 * 256.0, 200 * 256, 256)
