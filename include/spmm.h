@@ -429,14 +429,25 @@ spmm_status spmm_tile_accumulate_n(void* C, int64_t ldc, const void* const* P, c
  * may differ between calls) into device buffers of nnz(C) entries, reading A's
  * and B's values live; asynchronous, no allocation, no host synchronisation.
  * Calls on one plan must not overlap (they share the dense accumulators).
+ *
+ * The long rows of C (more entries than the largest workgroup table holds: 4,096 or
+ * 8,192, by the LDS left beside a bitmap over C's columns), when they take column
+ * windows through a split table of B, have their columns found once, at plan
+ * creation, and kept in the plan: 4 bytes per such entry, when that takes at most a
+ * quarter of the free device memory (flag SPGEMM_BITMAP_ONLY keeps none).  compute
+ * then adds each of their products into its window's sums without marking a bitmap
+ * and writes the entries in the kept order; the results are the same either way.
+ * spgemm_pattern_entries returns how many entries of C the plan keeps (0: none).
  * Errors: INVALID_ARG, BAD_CSR (with SPMM_TILE_VALIDATE), UNSUPPORTED (nnz > 2^31 - 2^16,
  * C with >= 2^31 entries), ALLOC, HIP.
  */
+#define SPGEMM_BITMAP_ONLY 16u  /* spgemm_create: keep no column pattern of the long rows */
 typedef struct spgemm_s* spgemm_t;
 spmm_status spgemm_create(int64_t M, const spmm_csr* A /* host */, const spmm_csr* B /* host */, unsigned flags,
                           void* stream, spgemm_t* out /* host */);
 spmm_status spgemm_destroy(spgemm_t plan);
 spmm_status spgemm_info(spgemm_t plan, int64_t* nnz_c /* host, nullable */, int64_t* products /* host, nullable */);
+spmm_status spgemm_pattern_entries(spgemm_t plan, int64_t* entries /* host */);
 spmm_status spgemm_rowptr(spgemm_t plan, int32_t* rowptrC /* device, M + 1 */, void* stream);
 spmm_status spgemm_compute(spgemm_t plan, int32_t* colindC /* device, nnz(C) */, float* valuesC /* device */,
                            void* stream);

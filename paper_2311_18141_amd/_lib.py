@@ -27,6 +27,7 @@ SPMM_TILE_VALIDATE = 1
 SPMM_TILE_TRANSPOSE = 2
 SPMM_BATCH_PERSISTENT = 1
 SPMM_BATCH_SINGLE = 2
+SPGEMM_BITMAP_ONLY = 16
 SPMM_RESERVE_2D = 1
 SPMM_RESERVE_3D = 2
 SPMM_RESERVE_OWN = 3
@@ -86,6 +87,7 @@ EXPORTS = {
     "spgemm_create": (c_int, [c_i64, c_vp, c_vp, c_uint, c_vp, c_vp]),
     "spgemm_destroy": (c_int, [c_vp]),
     "spgemm_info": (c_int, [c_vp, c_vp, c_vp]),
+    "spgemm_pattern_entries": (c_int, [c_vp, c_vp]),
     "spgemm_rowptr": (c_int, [c_vp, c_vp, c_vp]),
     "spgemm_compute": (c_int, [c_vp, c_vp, c_vp, c_vp]),
     "spmm_batch_create": (c_int, [c_int, c_vp, c_vp, c_int, c_i64, c_uint, c_vp, c_vp]),

@@ -729,9 +729,10 @@ struct SgItem {
   int32_t row, win, out, cnt;
 };
 
-// A long row's non-empty windows: items[first, first + count).
+// A long row's non-empty windows: items[first, first + count).  With a stored pattern,
+// the row's entry at C position q has its column at pattern[q + pat].
 struct SgRow {
-  int32_t row, first, count, pad;
+  int32_t row, first, count, pat;
 };
 
 // bsplit[k * (n_win + 1) + w]: first position of B row k at column >= w * 2^win_log2
@@ -776,6 +777,45 @@ __device__ __forceinline__ void window_emit(const SgOut& Co, float* acc, uint32_
   __syncthreads();
 }
 
+// The pattern pass of a window: its columns, in order, to dst[0, cnt) from the bitmap
+// (cleared as it is read; the sums are not touched).  Ends with a barrier.
+__device__ __forceinline__ void window_emit_pattern(uint32_t* bits, int ww, int32_t c0, int32_t* dst, int32_t cnt,
+                                                    int32_t* s_tmp) {
+  const int tid = threadIdx.x;
+  int32_t out = 0;
+  for (int w0 = 0; w0 < ww; w0 += kWG) {
+    const int wi = w0 + tid;
+    uint32_t word = wi < ww ? bits[wi] : 0u;
+    int32_t excl;
+    const int32_t tot = block_scan(__popc(word), &excl, s_tmp);
+    int32_t pos = out + excl;
+    while (word) {
+      const int b = __ffs(word) - 1;
+      word &= word - 1;
+      if (pos < cnt) dst[pos] = c0 + wi * 32 + b;
+      ++pos;
+    }
+    if (wi < ww) bits[wi] = 0u;
+    out += tot;
+  }
+  __syncthreads();
+}
+
+// A window's entries at [out, out + cnt) in the order of its stored columns src[0, cnt):
+// each sum is read and cleared by the one thread that writes its entry (the columns of
+// a window are distinct), coalesced global reads and writes.  Ends with a barrier.
+__device__ __forceinline__ void window_emit_values(const SgOut& Co, float* acc, const int32_t* src, int32_t c0,
+                                                   int32_t out, int32_t cnt) {
+  for (int32_t e = threadIdx.x; e < cnt; e += kWG) {
+    const int32_t col = src[e];
+    const int32_t x = col - c0;
+    Co.colC[out + e] = col;
+    Co.valC[out + e] = acc[x];
+    acc[x] = 0.0f;
+  }
+  __syncthreads();
+}
+
 // Long rows without a split table: one (row, window) item per workgroup at a time, each
 // B row cut to the window by binary search.
 __global__ void __launch_bounds__(kWG) num_window_kernel(SgOperands O, SgOut Co, const SgItem* items,
@@ -815,9 +855,32 @@ __global__ void __launch_bounds__(kWG) num_window_kernel(SgOperands O, SgOut Co,
 // windows and prefetches the next window's split-table bounds while the current window
 // accumulates, so a window costs its products and its compaction, not a chain of
 // dependent loads; longer rows take each window through block_products.
+// MODE kRowFull: sums and bitmap by LDS atomics, entries written from the bitmap.
+// kRowPattern (at plan creation): bitmap only, the columns written to `pattern`.
+// kRowValues: sums only, entries written in the stored pattern's order (one LDS atomic
+// per product instead of two, and no bitmap walk).
+constexpr int kRowFull = 0, kRowPattern = 1, kRowValues = 2;
+
+template <int MODE>
+__device__ __forceinline__ void window_add(float* acc, uint32_t* bits, int32_t x, float prod) {
+  if constexpr (MODE != kRowValues) atomicOr(bits + (x >> 5), 1u << (x & 31));
+  if constexpr (MODE != kRowPattern) atomicAdd(acc + x, prod);
+}
+
+template <int MODE>
+__device__ __forceinline__ void window_finish(const SgOut& Co, float* acc, uint32_t* bits, int ww, int32_t c0,
+                                              const SgItem& item, int32_t pat_off, int32_t* pattern,
+                                              int32_t* s_tmp) {
+  if constexpr (MODE == kRowFull) window_emit(Co, acc, bits, ww, c0, item.out, item.cnt, s_tmp);
+  if constexpr (MODE == kRowPattern) window_emit_pattern(bits, ww, c0, pattern + item.out + pat_off, item.cnt, s_tmp);
+  if constexpr (MODE == kRowValues) window_emit_values(Co, acc, pattern + item.out + pat_off, c0, item.out, item.cnt);
+}
+
+template <int MODE>
 __global__ void __launch_bounds__(kWG) num_rowwin_kernel(SgOperands O, SgOut Co, const SgItem* items,
                                                          const SgRow* rows, int64_t n_rows, int win_log2,
-                                                         const int32_t* bsplit, int n_win) {
+                                                         const int32_t* bsplit, int n_win, int32_t* pattern) {
+  constexpr bool VALS = MODE != kRowPattern;
   extern __shared__ int32_t s_dyn[];
   const int W = 1 << win_log2;
   const int ww = W >> 5;
@@ -841,7 +904,7 @@ __global__ void __launch_bounds__(kWG) num_rowwin_kernel(SgOperands O, SgOut Co,
       float av = 0.0f;
       if (mine) {
         k = O.colA[a0 + tid];
-        av = O.valA[a0 + tid];
+        if constexpr (VALS) av = O.valA[a0 + tid];
       }
       const int32_t* sp = bsplit + (int64_t)k * stride;
       SgItem item = items[R.first];
@@ -861,12 +924,9 @@ __global__ void __launch_bounds__(kWG) num_rowwin_kernel(SgOperands O, SgOut Co,
           }
         }
         const int32_t c0 = item.win << win_log2;
-        walk_products<true>(O, st, en - st, av, s_pref, s_start, s_aval, s_tmp, [&](int32_t col, float prod) {
-          const int32_t x = col - c0;
-          atomicOr(bits + (x >> 5), 1u << (x & 31));
-          atomicAdd(acc + x, prod);
-        });
-        window_emit(Co, acc, bits, ww, c0, item.out, item.cnt, s_tmp);
+        walk_products<VALS>(O, st, en - st, av, s_pref, s_start, s_aval, s_tmp,
+                            [&](int32_t col, float prod) { window_add<MODE>(acc, bits, col - c0, prod); });
+        window_finish<MODE>(Co, acc, bits, ww, c0, item, R.pat, pattern, s_tmp);
         item = nxt;
         st = nst;
         en = nen;
@@ -876,14 +936,10 @@ __global__ void __launch_bounds__(kWG) num_rowwin_kernel(SgOperands O, SgOut Co,
         const SgItem item = items[R.first + j];
         const int32_t c0 = item.win << win_log2;
         const int32_t c1 = (int32_t)min((int64_t)c0 + W, O.N);
-        block_products<true, true>(O, a0, a1, s_pref, s_start, s_aval, s_tmp,
-                                   [&](int32_t col, float prod) {
-                                     const int32_t x = col - c0;
-                                     atomicOr(bits + (x >> 5), 1u << (x & 31));
-                                     atomicAdd(acc + x, prod);
-                                   },
+        block_products<VALS, true>(O, a0, a1, s_pref, s_start, s_aval, s_tmp,
+                                   [&](int32_t col, float prod) { window_add<MODE>(acc, bits, col - c0, prod); },
                                    c0, c1, bsplit, stride, item.win);
-        window_emit(Co, acc, bits, ww, c0, item.out, item.cnt, s_tmp);
+        window_finish<MODE>(Co, acc, bits, ww, c0, item, R.pat, pattern, s_tmp);
       }
     }
   }
@@ -984,7 +1040,10 @@ struct spgemm_s {
   int64_t n_wrows = 0;
   int32_t* bsplit = nullptr;      // device: B rows' window split positions (nullable)
   int n_win = 0;
+  int32_t* pattern = nullptr;     // device: the long rows' columns, row after row (nullable)
+  int64_t pattern_entries = 0;
   ~spgemm_s() {
+    if (pattern) (void)hipFree(pattern);
     if (rowptrC) (void)hipFree(rowptrC);
     if (rows) (void)hipFree(rows);
     if (items) (void)hipFree(items);
@@ -1067,7 +1126,8 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
   if (!A->rowptr || !B->rowptr) return spmm::set_error(SPMM_ERR_INVALID_ARG, "rowptr is null");
   if ((A->nnz > 0 && (!A->colind || !A->values)) || (B->nnz > 0 && (!B->colind || !B->values)))
     return spmm::set_error(SPMM_ERR_INVALID_ARG, "colind/values null");
-  if (flags & ~SPMM_TILE_VALIDATE) return spmm::set_error(SPMM_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
+  if (flags & ~(SPMM_TILE_VALIDATE | SPGEMM_BITMAP_ONLY))
+    return spmm::set_error(SPMM_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (flags & SPMM_TILE_VALIDATE) {
     const spmm_status st = spmm::validate_csr(A->rowptr, A->colind, M, A->cols, A->nnz, s);
@@ -1284,13 +1344,36 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
           std::stable_sort(wr.begin(), wr.end(), [&](const spmm::SgRow& x, const spmm::SgRow& y) {
             return rp[(size_t)x.row + 1] - rp[(size_t)x.row] > rp[(size_t)y.row + 1] - rp[(size_t)y.row];
           });
+          // The long rows' pattern (their columns, row after row, in this order), kept
+          // when it takes at most a quarter of the free device memory: compute then
+          // adds each product into its window with one LDS atomic and writes the
+          // window's entries in the pattern's order, instead of also marking a bitmap
+          // and walking it on every call.
+          int64_t pat_total = 0;
+          for (auto& x : wr) {
+            x.pat = (int32_t)(pat_total - rp[(size_t)x.row]);
+            pat_total += rp[(size_t)x.row + 1] - rp[(size_t)x.row];
+          }
+          if (!(flags & SPGEMM_BITMAP_ONLY) && pat_total > 0) {
+            size_t free_b = 0, total_b = 0;
+            if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && (size_t)pat_total * 4 <= free_b / 4) {
+              if (dmalloc(&h->pattern, pat_total) == hipSuccess) {
+                h->pattern_entries = pat_total;
+              } else {
+                h->pattern = nullptr;
+                (void)hipGetLastError();  // no pattern: compute marks and walks the bitmap instead
+              }
+            }
+          }
           h->n_wrows = (int64_t)wr.size();
           if (dmalloc(&h->wrows, h->n_wrows) != hipSuccess)
             return spmm::set_error(SPMM_ERR_ALLOC, "device allocation of the window rows failed");
           if (h->n_wrows)
             SG_TRY(hipMemcpyAsync(h->wrows, wr.data(), sizeof(spmm::SgRow) * wr.size(), hipMemcpyHostToDevice, s));
-          (void)hipFuncSetAttribute(reinterpret_cast<const void*>(spmm::num_rowwin_kernel),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_window);
+          for (const void* f : {reinterpret_cast<const void*>(spmm::num_rowwin_kernel<spmm::kRowFull>),
+                                reinterpret_cast<const void*>(spmm::num_rowwin_kernel<spmm::kRowPattern>),
+                                reinterpret_cast<const void*>(spmm::num_rowwin_kernel<spmm::kRowValues>)})
+            (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_window);
           SG_TRY(hipStreamSynchronize(s));  // wr is read before it goes out of scope
         } else {
           // (row, window) items largest first
@@ -1304,6 +1387,13 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
           return spmm::set_error(SPMM_ERR_ALLOC, "device allocation of the window items failed");
         if (h->n_items)
           SG_TRY(hipMemcpyAsync(h->items, items.data(), sizeof(spmm::SgItem) * items.size(), hipMemcpyHostToDevice, s));
+        if (h->pattern && h->n_wrows) {
+          const int64_t grid = std::min<int64_t>(h->n_wrows, (int64_t)cus * 2);
+          hipLaunchKernelGGL(spmm::num_rowwin_kernel<spmm::kRowPattern>, dim3((unsigned)grid), dim3(spmm::kWG),
+                             h->lds_window, s, O, spmm::SgOut{h->rowptrC, nullptr, nullptr}, h->items, h->wrows,
+                             h->n_wrows, h->win_log2, h->bsplit, h->n_win, h->pattern);
+          SG_TRY(hipGetLastError());
+        }
       } else if (h->cls_cnt[kLongClass]) {
         const spmm_status st = ensure_slots(h, slot_count(h, h->cls_cnt[kLongClass], cus), s);
         if (st != SPMM_OK) return st;
@@ -1335,6 +1425,12 @@ spmm_status spgemm_info(spgemm_t plan, int64_t* nnz_c, int64_t* products) {
   if (!plan) return spmm::set_error(SPMM_ERR_INVALID_ARG, "plan is null");
   if (nnz_c) *nnz_c = plan->nnz_c;
   if (products) *products = plan->products;
+  return SPMM_OK;
+}
+
+spmm_status spgemm_pattern_entries(spgemm_t plan, int64_t* entries) {
+  if (!plan || !entries) return spmm::set_error(SPMM_ERR_INVALID_ARG, "null argument");
+  *entries = plan->pattern_entries;
   return SPMM_OK;
 }
 
@@ -1385,8 +1481,14 @@ spmm_status spgemm_compute(spgemm_t plan, int32_t* colindC, float* valuesC, void
       SG_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
       if (plan->wrows) {
         const int64_t grid = std::min<int64_t>(plan->n_wrows, (int64_t)cus * 2);
-        hipLaunchKernelGGL(spmm::num_rowwin_kernel, dim3((unsigned)grid), dim3(spmm::kWG), plan->lds_window, s, O,
-                           Co, plan->items, plan->wrows, plan->n_wrows, plan->win_log2, plan->bsplit, plan->n_win);
+        if (plan->pattern)
+          hipLaunchKernelGGL(spmm::num_rowwin_kernel<spmm::kRowValues>, dim3((unsigned)grid), dim3(spmm::kWG),
+                             plan->lds_window, s, O, Co, plan->items, plan->wrows, plan->n_wrows, plan->win_log2,
+                             plan->bsplit, plan->n_win, plan->pattern);
+        else
+          hipLaunchKernelGGL(spmm::num_rowwin_kernel<spmm::kRowFull>, dim3((unsigned)grid), dim3(spmm::kWG),
+                             plan->lds_window, s, O, Co, plan->items, plan->wrows, plan->n_wrows, plan->win_log2,
+                             plan->bsplit, plan->n_win, (int32_t*)nullptr);
       } else {
         const int64_t grid = std::min<int64_t>(plan->n_items, (int64_t)cus * 2);
         hipLaunchKernelGGL(spmm::num_window_kernel, dim3((unsigned)grid), dim3(spmm::kWG), plan->lds_window, s, O,

@@ -487,12 +487,14 @@ def spmm_batched(batch: Batch, Bs: Sequence[torch.Tensor], Cs: Sequence[torch.Te
 class SpgemmPlan:
     """Plan of C = A B (CSR x CSR): C's structure is known at creation; values come from spgemm_compute."""
 
-    def __init__(self, handle: int, M: int, N: int, nnz_c: int, products: int, keep: list):
+    def __init__(self, handle: int, M: int, N: int, nnz_c: int, products: int, keep: list,
+                 pattern_entries: int = 0):
         self.handle = handle
         self.M = M
         self.N = N
         self.nnz_c = nnz_c
         self.products = products
+        self.pattern_entries = pattern_entries   # entries of C whose columns the plan keeps
         self._keep = keep
 
     def __del__(self):
@@ -513,19 +515,27 @@ def _csr_struct(rowptr, colind, values, cols, name):
 
 def spgemm_create(M: int, A: Tuple[torch.Tensor, torch.Tensor, torch.Tensor, int],
                   B: Tuple[torch.Tensor, torch.Tensor, torch.Tensor, int], validate: bool = True,
-                  stream: Optional[torch.cuda.Stream] = None) -> SpgemmPlan:
-    """Structure analysis and symbolic product of C = A B (A: M x A.cols, B: A.cols x B.cols)."""
+                  stream: Optional[torch.cuda.Stream] = None, keep_pattern: bool = True) -> SpgemmPlan:
+    """Structure analysis and symbolic product of C = A B (A: M x A.cols, B: A.cols x B.cols).
+    keep_pattern=False: keep no column pattern of the long rows (SPGEMM_BITMAP_ONLY)."""
     a = _csr_struct(*A, "A")
     b = _csr_struct(*B, "B")
     if A[0].numel() != M + 1 or B[0].numel() != int(A[3]) + 1:
         raise ValueError("A needs M + 1 row pointers and B A.cols + 1")
     h = ctypes.c_void_p()
-    check(lib().spgemm_create(int(M), ctypes.byref(a), ctypes.byref(b), 1 if validate else 0, _stream_ptr(stream),
+    flags = (1 if validate else 0) | (0 if keep_pattern else _lib.SPGEMM_BITMAP_ONLY)
+    check(lib().spgemm_create(int(M), ctypes.byref(a), ctypes.byref(b), flags, _stream_ptr(stream),
                               ctypes.byref(h)))
     nnz = ctypes.c_int64()
     prods = ctypes.c_int64()
-    check(lib().spgemm_info(h.value, ctypes.byref(nnz), ctypes.byref(prods)))
-    return SpgemmPlan(h.value, int(M), int(B[3]), nnz.value, prods.value, [A, B])
+    pat = ctypes.c_int64()
+    try:
+        check(lib().spgemm_info(h.value, ctypes.byref(nnz), ctypes.byref(prods)))
+        check(lib().spgemm_pattern_entries(h.value, ctypes.byref(pat)))
+    except Exception:
+        lib().spgemm_destroy(h.value)
+        raise
+    return SpgemmPlan(h.value, int(M), int(B[3]), nnz.value, prods.value, [A, B], pat.value)
 
 
 def spgemm_rowptr(plan: SpgemmPlan, rowptrC: Optional[torch.Tensor] = None,

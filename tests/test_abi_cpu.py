@@ -289,3 +289,15 @@ def test_reservation_grid_and_accumulate_n_argument_errors():
     lds[0] = 4
     assert L.spmm_tile_accumulate_n(0x2000, 8, ptrs, lds, 1, 4, 8, 0, None) == 1   # ldp < N
     assert L.spmm_tile_accumulate_n(0x2000, 8, ptrs, lds, -1, 4, 8, 0, None) == 1  # negative count
+
+
+def test_spgemm_pattern_entries_arguments():
+    L = _lib.lib()
+    x = ctypes.c_int64(7)
+    assert L.spgemm_pattern_entries(None, ctypes.byref(x)) == 1 and x.value == 7
+    assert L.spgemm_pattern_entries(None, None) == 1
+    # an unknown flag bit beside SPGEMM_BITMAP_ONLY is refused before any device work
+    out = ctypes.c_void_p()
+    a = SpmmCsr(4, 0, 8, None, None)   # a non-null (never read) row pointer, no entries
+    assert L.spgemm_create(4, ctypes.byref(a), ctypes.byref(a), 32, None, ctypes.byref(out)) == 1
+    assert b"flag" in L.spmm_last_error()

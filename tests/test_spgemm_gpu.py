@@ -21,10 +21,10 @@ def _rng(s):
     return np.random.Generator(np.random.PCG64(s))
 
 
-def _plan(A, B, validate=True):
+def _plan(A, B, validate=True, keep_pattern=True):
     dA = G.to_dev(A)
     dB = G.to_dev(B)
-    return ops.spgemm_create(A.rows, dA, dB, validate=validate), dA, dB
+    return ops.spgemm_create(A.rows, dA, dB, validate=validate, keep_pattern=keep_pattern), dA, dB
 
 
 def _products_per_row(A, B):
@@ -44,9 +44,11 @@ def _oracle(A, B, compress_cols=False):
     return rp, used[ci].astype(np.int64), va, S
 
 
-def _check(A, B, exact=False, plan=None, compress_cols=False):
+def _check(A, B, exact=False, plan=None, compress_cols=False, keep_pattern=True):
     if plan is None:
-        plan, dA, dB = _plan(A, B)
+        plan, dA, dB = _plan(A, B, keep_pattern=keep_pattern)
+        if not keep_pattern:
+            assert plan.pattern_entries == 0
     rp = ops.spgemm_rowptr(plan)
     ci, va = ops.spgemm_compute(plan)
     torch.cuda.synchronize()
@@ -88,10 +90,12 @@ def test_spgemm_small_vs_oracle(M, K, N, d):
     _check(A, B)
 
 
-def test_spgemm_class_boundaries_integer_exact():
+@pytest.mark.parametrize("keep_pattern", [True, False])
+def test_spgemm_class_boundaries_integer_exact(keep_pattern):
     """Rows whose product and output counts sit on each side of every class boundary
-    (128, 256, 512 for the wave classes; the workgroup table's half size; dense rows)."""
-    G.note("spgemm class boundaries")
+    (128, 256, 512 for the wave classes; the workgroup table's half size; dense rows);
+    the long rows with the kept column pattern and with the bitmap found on every call."""
+    G.note("spgemm class boundaries keep_pattern=%s" % keep_pattern)
     rng = _rng(11)
     N = 30000
     lengths = [0, 1, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1000, 4095, 4096, 4097, 8191, 8192, 8193,
@@ -102,7 +106,13 @@ def test_spgemm_class_boundaries_integer_exact():
     picks += [list(range(K))]                             # everything: dense, high compression
     picks += [[2, 3, 4], [9, 10], [13, 14, 15], [16, 17], [], [0], [18, 19]]
     A = _select_rows(K, picks, rng, "int8")
-    _check(A, B, exact=True)
+    plan = _check(A, B, exact=True, keep_pattern=keep_pattern)
+    if keep_pattern:
+        # the long rows: more than 8,192 entries where a 16K-slot table and a bitmap over C's
+        # columns fit in LDS beside each other, else more than 4,096
+        n = np.diff(ops.spgemm_rowptr(plan).cpu().numpy().astype(np.int64))
+        assert plan.pattern_entries in (int(n[n > 8192].sum()), int(n[n > 4096].sum()))
+        assert plan.pattern_entries > 0
 
 
 def test_spgemm_wide_b_global_bitmap():
@@ -116,19 +126,21 @@ def test_spgemm_wide_b_global_bitmap():
     _check(A, B, exact=True, compress_cols=True)
 
 
-def test_spgemm_rmat_aa():
+@pytest.mark.parametrize("keep_pattern", [True, False])
+def test_spgemm_rmat_aa(keep_pattern):
     """C = A A on a skewed R-MAT matrix: all classes at once."""
-    G.note("spgemm rmat14 A*A")
+    G.note("spgemm rmat14 A*A keep_pattern=%s" % keep_pattern)
     A = synth.rmat_csr(14, 8, seed=13)
-    _check(A, A)
+    _check(A, A, keep_pattern=keep_pattern)
 
 
-def test_spgemm_rmat_aa_integer_exact():
-    G.note("spgemm rmat13 A*A int")
+@pytest.mark.parametrize("keep_pattern", [True, False])
+def test_spgemm_rmat_aa_integer_exact(keep_pattern):
+    G.note("spgemm rmat13 A*A int keep_pattern=%s" % keep_pattern)
     rng = _rng(14)
     A0 = synth.rmat_csr(13, 8, seed=14)
     A = synth.CSR(A0.rows, A0.cols, A0.rowptr, A0.colind, rng.integers(-3, 4, size=A0.nnz).astype(np.float32))
-    _check(A, A, exact=True)
+    _check(A, A, exact=True, keep_pattern=keep_pattern)
 
 
 def test_spgemm_cancellation_and_empty():
@@ -229,24 +241,26 @@ def test_spgemm_long_rows_without_split_table():
     _check(A, B, exact=True, compress_cols=True)
 
 
-def test_spgemm_medium_rows_to_windows():
+@pytest.mark.parametrize("keep_pattern", [True, False])
+def test_spgemm_medium_rows_to_windows(keep_pattern):
     """C with 300K columns: rows of 4K-8K entries cannot keep a column bitmap beside their
     16K-slot table, and there are few windows, so they take the window path."""
-    G.note("spgemm medium rows through windows")
+    G.note("spgemm medium rows through windows keep_pattern=%s" % keep_pattern)
     rng = _rng(20)
     N = 300_000
     B = _b_rows_of_lengths([4500, 6000, 8100, 600, 3000, 20000], N, rng, "int8")
     A = _select_rows(B.rows, [[0], [1], [2], [3, 4], [0, 3], [5], [1, 2, 3]], rng, "int8")
-    _check(A, B, exact=True)
+    _check(A, B, exact=True, keep_pattern=keep_pattern)
 
 
-def test_spgemm_long_rows_negative_zero_products():
+@pytest.mark.parametrize("keep_pattern", [True, False])
+def test_spgemm_long_rows_negative_zero_products(keep_pattern):
     """Long rows (column windows) with -0.0 products (an A or a B value stored as -0.0 times
     a positive value): a column reached only by such products is still a structural entry,
     so a kernel that told presence from its sum would miss it; the structure stays exact.
     Both long-row paths (at most and more than 1,024 A entries) are covered, as are rows
     with no such column, a row whose every product is -0.0, and +0.0 products."""
-    G.note("spgemm long rows, -0.0 products")
+    G.note("spgemm long rows, -0.0 products keep_pattern=%s" % keep_pattern)
     rng = _rng(21)
     N = 70000
     cols0 = rng.choice(N, 9000, replace=False)
@@ -285,4 +299,68 @@ def test_spgemm_long_rows_negative_zero_products():
         rp.append(rp[-1] + len(ks))
     A = synth.CSR(len(arows), B.rows, np.asarray(rp, np.int32), np.concatenate(ci).astype(np.int32),
                   np.concatenate(va))
-    _check(A, B, exact=True)
+    plan = _check(A, B, exact=True, keep_pattern=keep_pattern)
+    assert (plan.pattern_entries > 0) == keep_pattern
+
+
+def _long_rows_case(rng):
+    """Integer data with rows of C longer than 4,096 entries (three 32K-column windows),
+    one of them from more than 1,024 A entries, beside short and medium rows."""
+    N = 70000
+    lengths = [9000, 5000, 700, 40] + [12] * 1100
+    B = _b_rows_of_lengths(lengths, N, rng, "int8")
+    A = _select_rows(B.rows, [[0], [0, 1], [2, 3], list(range(4, 1104)), [1], list(range(1104)), []], rng, "int8")
+    return A, B
+
+
+def test_spgemm_long_rows_live_values_and_repeat():
+    """With the kept pattern the plan still caches structure only: calls repeat exactly on
+    integer data, new values of A and of B take effect, and the results equal those of a
+    plan that finds the long rows' columns on every call."""
+    G.note("spgemm long rows, live values with the kept pattern")
+    rng = _rng(22)
+    A, B = _long_rows_case(rng)
+    plan, dA, dB = _plan(A, B)
+    assert plan.pattern_entries > 0
+    ci1, va1 = ops.spgemm_compute(plan)
+    ci1, va1 = ci1.clone(), va1.clone()
+    ci2, va2 = ops.spgemm_compute(plan)
+    plain, _, _ = _plan(A, B, keep_pattern=False)
+    ci3, va3 = ops.spgemm_compute(plain)
+    torch.cuda.synchronize()
+    assert torch.equal(ci1, ci2) and torch.equal(va1, va2)
+    assert torch.equal(ci1, ci3) and torch.equal(va1, va3)
+    dA[2].mul_(-2.0)
+    dB[2].mul_(3.0)
+    A2 = synth.CSR(A.rows, A.cols, A.rowptr, A.colind, (A.values * -2.0).astype(np.float32))
+    B2 = synth.CSR(B.rows, B.cols, B.rowptr, B.colind, (B.values * 3.0).astype(np.float32))
+    _check(A2, B2, exact=True, plan=plan)
+
+
+def test_spgemm_long_rows_graph_replay():
+    """The kept-pattern long-row kernel replayed from a graph: every replay equals the eager call."""
+    G.note("spgemm long rows, graph replay")
+    rng = _rng(23)
+    A, B = _long_rows_case(rng)
+    plan, dA, dB = _plan(A, B)
+    assert plan.pattern_entries > 0
+    ci = torch.empty(plan.nnz_c, dtype=torch.int32, device=G.DEV)
+    va = torch.empty(plan.nnz_c, dtype=torch.float32, device=G.DEV)
+    ops.spgemm_compute(plan, ci, va)
+    torch.cuda.synchronize()
+    ref_ci, ref_va = ci.clone(), va.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ops.spgemm_compute(plan, ci, va)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ops.spgemm_compute(plan, ci, va)
+    for r in range(4):
+        ci.fill_(-1)
+        va.fill_(float("nan"))
+        _ = (dA[2] * 3).sum()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(ci, ref_ci) and torch.equal(va, ref_va), r
