@@ -607,8 +607,9 @@ __global__ void __launch_bounds__(kBlock) num_wave_kernel(SgOperands O, SgOut Co
 // order: with BM, a bitmap over all N columns (in LDS after the table) marks each new
 // key, and a walk over it writes the row in column order, looking each value up in
 // the table; without BM (N too wide for LDS), the occupied slots are compacted and
-// bitonic-sorted.
-template <bool BM>
+// bitonic-sorted.  Without VALS (the pattern pass at plan creation) only the columns
+// are found and written, to Co.colC.
+template <bool BM, bool VALS = true>
 __global__ void __launch_bounds__(kWG) num_block_kernel(SgOperands O, SgOut Co, const int32_t* rows,
                                                         int64_t n_rows, int tg_log2) {
   extern __shared__ int32_t s_dyn[];
@@ -638,13 +639,13 @@ __global__ void __launch_bounds__(kWG) num_block_kernel(SgOperands O, SgOut Co, 
       val[j] = 0.0f;
     }
     __syncthreads();
-    block_products<true, false>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref, s_start, s_aval, s_tmp,
+    block_products<VALS, false>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref, s_start, s_aval, s_tmp,
                         [&](int32_t col, float prod) {
                           uint32_t h = hash_slot(col, shift);
                           for (int probe = 0; probe < tg; ++probe) {  // at most half full
                             const int32_t old = atomicCAS(&key[h], -1, col);
                             if (old == -1 || old == col) {
-                              atomicAdd(&val[h], prod);
+                              if constexpr (VALS) atomicAdd(&val[h], prod);
                               if (BM && old == -1) atomicOr(bits + (col >> 5), 1u << (col & 31));
                               break;
                             }
@@ -666,18 +667,20 @@ __global__ void __launch_bounds__(kWG) num_block_kernel(SgOperands O, SgOut Co, 
           const int b = __ffs(word) - 1;
           word &= word - 1;
           const int32_t col = (int32_t)(wi * 32 + b);
-          uint32_t h = hash_slot(col, shift);
           float v = 0.0f;
-          for (int probe = 0; probe < tg; ++probe) {
-            if (key[h] == col) {
-              v = val[h];
-              break;
+          if constexpr (VALS) {
+            uint32_t h = hash_slot(col, shift);
+            for (int probe = 0; probe < tg; ++probe) {
+              if (key[h] == col) {
+                v = val[h];
+                break;
+              }
+              h = (h + 1) & (uint32_t)(tg - 1);
             }
-            h = (h + 1) & (uint32_t)(tg - 1);
           }
           if (pos < end) {
             Co.colC[pos] = col;
-            Co.valC[pos] = v;
+            if constexpr (VALS) Co.valC[pos] = v;
           }
           ++pos;
         }
@@ -714,10 +717,50 @@ __global__ void __launch_bounds__(kWG) num_block_kernel(SgOperands O, SgOut Co, 
       const int32_t cnt = min(Co.rowptrC[i + 1] - base, n);
       for (int j = tid; j < cnt; j += kWG) {
         Co.colC[base + j] = key[j];
-        Co.valC[base + j] = val[j];
+        if constexpr (VALS) Co.valC[base + j] = val[j];
       }
       __syncthreads();
     }
+  }
+}
+
+// Rows of at most `cap` output entries whose sorted columns the plan keeps (pattern,
+// indexed like C): one workgroup per row; the columns go to LDS beside their sums,
+// each product finds its column by binary search and adds into its sum with one LDS
+// atomic, and the row is written in order, coalesced.  No table to clear, no bitmap.
+__global__ void __launch_bounds__(kWG) num_block_kept_kernel(SgOperands O, SgOut Co, const int32_t* rows,
+                                                             int64_t n_rows, int cap, const int32_t* pattern) {
+  extern __shared__ int32_t s_dyn[];
+  int32_t* keys = s_dyn;
+  float* sums = reinterpret_cast<float*>(keys + cap);
+  int32_t* s_pref = reinterpret_cast<int32_t*>(sums + cap);
+  int32_t* s_start = s_pref + kWG + 1;
+  float* s_aval = reinterpret_cast<float*>(s_start + kWG);
+  int32_t* s_tmp = reinterpret_cast<int32_t*>(s_aval + kWG);
+  const int tid = threadIdx.x;
+  for (int64_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
+    const int32_t i = rows[r];
+    const int32_t base = Co.rowptrC[i];
+    const int32_t n = min(Co.rowptrC[i + 1] - base, cap);
+    for (int j = tid; j < n; j += kWG) {
+      keys[j] = pattern[base + j];
+      sums[j] = 0.0f;
+    }
+    int hb = 1;  // the largest power of two not above n
+    while (hb * 2 <= n) hb *= 2;
+    __syncthreads();
+    block_products<true, false>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref, s_start, s_aval, s_tmp,
+                                [&](int32_t col, float prod) {
+                                  int pos = -1;  // the last key below col
+                                  for (int step = hb; step > 0; step >>= 1)
+                                    if (pos + step < n && keys[pos + step] < col) pos += step;
+                                  if (pos + 1 < n) atomicAdd(&sums[pos + 1], prod);
+                                });
+    for (int j = tid; j < n; j += kWG) {
+      Co.colC[base + j] = keys[j];
+      Co.valC[base + j] = sums[j];
+    }
+    __syncthreads();
   }
 }
 
@@ -729,10 +772,9 @@ struct SgItem {
   int32_t row, win, out, cnt;
 };
 
-// A long row's non-empty windows: items[first, first + count).  With a stored pattern,
-// the row's entry at C position q has its column at pattern[q + pat].
+// A long row's non-empty windows: items[first, first + count).
 struct SgRow {
-  int32_t row, first, count, pat;
+  int32_t row, first, count, pad;
 };
 
 // bsplit[k * (n_win + 1) + w]: first position of B row k at column >= w * 2^win_log2
@@ -869,11 +911,10 @@ __device__ __forceinline__ void window_add(float* acc, uint32_t* bits, int32_t x
 
 template <int MODE>
 __device__ __forceinline__ void window_finish(const SgOut& Co, float* acc, uint32_t* bits, int ww, int32_t c0,
-                                              const SgItem& item, int32_t pat_off, int32_t* pattern,
-                                              int32_t* s_tmp) {
+                                              const SgItem& item, int32_t* pattern, int32_t* s_tmp) {
   if constexpr (MODE == kRowFull) window_emit(Co, acc, bits, ww, c0, item.out, item.cnt, s_tmp);
-  if constexpr (MODE == kRowPattern) window_emit_pattern(bits, ww, c0, pattern + item.out + pat_off, item.cnt, s_tmp);
-  if constexpr (MODE == kRowValues) window_emit_values(Co, acc, pattern + item.out + pat_off, c0, item.out, item.cnt);
+  if constexpr (MODE == kRowPattern) window_emit_pattern(bits, ww, c0, pattern + item.out, item.cnt, s_tmp);
+  if constexpr (MODE == kRowValues) window_emit_values(Co, acc, pattern + item.out, c0, item.out, item.cnt);
 }
 
 template <int MODE>
@@ -926,7 +967,7 @@ __global__ void __launch_bounds__(kWG) num_rowwin_kernel(SgOperands O, SgOut Co,
         const int32_t c0 = item.win << win_log2;
         walk_products<VALS>(O, st, en - st, av, s_pref, s_start, s_aval, s_tmp,
                             [&](int32_t col, float prod) { window_add<MODE>(acc, bits, col - c0, prod); });
-        window_finish<MODE>(Co, acc, bits, ww, c0, item, R.pat, pattern, s_tmp);
+        window_finish<MODE>(Co, acc, bits, ww, c0, item, pattern, s_tmp);
         item = nxt;
         st = nst;
         en = nen;
@@ -939,7 +980,7 @@ __global__ void __launch_bounds__(kWG) num_rowwin_kernel(SgOperands O, SgOut Co,
         block_products<VALS, true>(O, a0, a1, s_pref, s_start, s_aval, s_tmp,
                                    [&](int32_t col, float prod) { window_add<MODE>(acc, bits, col - c0, prod); },
                                    c0, c1, bsplit, stride, item.win);
-        window_finish<MODE>(Co, acc, bits, ww, c0, item, R.pat, pattern, s_tmp);
+        window_finish<MODE>(Co, acc, bits, ww, c0, item, pattern, s_tmp);
       }
     }
   }
@@ -1040,7 +1081,7 @@ struct spgemm_s {
   int64_t n_wrows = 0;
   int32_t* bsplit = nullptr;      // device: B rows' window split positions (nullable)
   int n_win = 0;
-  int32_t* pattern = nullptr;     // device: the long rows' columns, row after row (nullable)
+  int32_t* pattern = nullptr;     // device: C's columns of the rows of more than 512 entries, indexed like C (nullable)
   int64_t pattern_entries = 0;
   ~spgemm_s() {
     if (pattern) (void)hipFree(pattern);
@@ -1307,8 +1348,11 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
       h->lds_max = (size_t)lds_max;
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(spmm::num_block_kernel<false>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(spmm::num_block_kernel<true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+      for (const void* f : {reinterpret_cast<const void*>(spmm::num_block_kernel<true>),
+                            reinterpret_cast<const void*>(spmm::num_block_kernel<true, false>),
+                            reinterpret_cast<const void*>(spmm::num_block_kernel<false, false>),
+                            reinterpret_cast<const void*>(spmm::num_block_kept_kernel)})
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
       if (h->cls_cnt[kLongClass] && h->win_log2) {
         // (row, window) items of the long rows, with their output offsets, largest first
         std::vector<int64_t> bitmap_index((size_t)M, -1);
@@ -1344,27 +1388,6 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
           std::stable_sort(wr.begin(), wr.end(), [&](const spmm::SgRow& x, const spmm::SgRow& y) {
             return rp[(size_t)x.row + 1] - rp[(size_t)x.row] > rp[(size_t)y.row + 1] - rp[(size_t)y.row];
           });
-          // The long rows' pattern (their columns, row after row, in this order), kept
-          // when it takes at most a quarter of the free device memory: compute then
-          // adds each product into its window with one LDS atomic and writes the
-          // window's entries in the pattern's order, instead of also marking a bitmap
-          // and walking it on every call.
-          int64_t pat_total = 0;
-          for (auto& x : wr) {
-            x.pat = (int32_t)(pat_total - rp[(size_t)x.row]);
-            pat_total += rp[(size_t)x.row + 1] - rp[(size_t)x.row];
-          }
-          if (!(flags & SPGEMM_BITMAP_ONLY) && pat_total > 0) {
-            size_t free_b = 0, total_b = 0;
-            if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && (size_t)pat_total * 4 <= free_b / 4) {
-              if (dmalloc(&h->pattern, pat_total) == hipSuccess) {
-                h->pattern_entries = pat_total;
-              } else {
-                h->pattern = nullptr;
-                (void)hipGetLastError();  // no pattern: compute marks and walks the bitmap instead
-              }
-            }
-          }
           h->n_wrows = (int64_t)wr.size();
           if (dmalloc(&h->wrows, h->n_wrows) != hipSuccess)
             return spmm::set_error(SPMM_ERR_ALLOC, "device allocation of the window rows failed");
@@ -1387,16 +1410,60 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
           return spmm::set_error(SPMM_ERR_ALLOC, "device allocation of the window items failed");
         if (h->n_items)
           SG_TRY(hipMemcpyAsync(h->items, items.data(), sizeof(spmm::SgItem) * items.size(), hipMemcpyHostToDevice, s));
-        if (h->pattern && h->n_wrows) {
-          const int64_t grid = std::min<int64_t>(h->n_wrows, (int64_t)cus * 2);
-          hipLaunchKernelGGL(spmm::num_rowwin_kernel<spmm::kRowPattern>, dim3((unsigned)grid), dim3(spmm::kWG),
-                             h->lds_window, s, O, spmm::SgOut{h->rowptrC, nullptr, nullptr}, h->items, h->wrows,
-                             h->n_wrows, h->win_log2, h->bsplit, h->n_win, h->pattern);
-          SG_TRY(hipGetLastError());
-        }
       } else if (h->cls_cnt[kLongClass]) {
         const spmm_status st = ensure_slots(h, slot_count(h, h->cls_cnt[kLongClass], cus), s);
         if (st != SPMM_OK) return st;
+      }
+      // C's columns for the rows of more than 512 entries (the workgroup tables, and the
+      // long rows when they take windows through a split table), found once here and
+      // kept, indexed like C: compute then adds each product with one LDS atomic (by
+      // binary search over a row's kept columns, or into its window's sums) and writes
+      // the entries in the kept order, instead of finding the columns again with hash
+      // inserts, bitmap atomics and bitmap walks on every call.  Kept when these rows
+      // hold at least a quarter of C and nnz(C) indices take at most a quarter of the
+      // free device memory.
+      int64_t kept = 0;
+      for (int c = 3; c <= kLongClass; ++c) {
+        if (c == kLongClass && !h->wrows) break;
+        for (int64_t t = 0; t < h->cls_cnt[c]; ++t) {
+          const int32_t i = list[(size_t)(h->cls_off[c] + t)];
+          kept += rp[(size_t)i + 1] - rp[(size_t)i];
+        }
+      }
+      if (!(flags & SPGEMM_BITMAP_ONLY) && kept > 0 && kept * 4 >= h->nnz_c) {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && (size_t)h->nnz_c * 4 <= free_b / 4) {
+          if (dmalloc(&h->pattern, h->nnz_c) == hipSuccess) {
+            h->pattern_entries = kept;
+          } else {
+            h->pattern = nullptr;
+            (void)hipGetLastError();  // no pattern: compute finds the columns on every call
+          }
+        }
+      }
+      if (h->pattern) {
+        const spmm::SgOut P{h->rowptrC, h->pattern, nullptr};
+        for (int c = 3; c < kLongClass; ++c) {
+          if (!h->cls_cnt[c]) continue;
+          const int tl = c + 8;
+          const size_t lds = kBlockFixedLds + 8 * ((size_t)1 << tl);
+          const size_t lds_bm = lds + sizeof(uint32_t) * (size_t)((h->N + 31) / 32);
+          const int64_t grid = std::min<int64_t>(h->cls_cnt[c], 65536);
+          if (lds_bm <= h->lds_max)
+            hipLaunchKernelGGL((spmm::num_block_kernel<true, false>), dim3((unsigned)grid), dim3(spmm::kWG), lds_bm,
+                               s, O, P, h->rows + h->cls_off[c], h->cls_cnt[c], tl);
+          else
+            hipLaunchKernelGGL((spmm::num_block_kernel<false, false>), dim3((unsigned)grid), dim3(spmm::kWG), lds,
+                               s, O, P, h->rows + h->cls_off[c], h->cls_cnt[c], tl);
+          SG_TRY(hipGetLastError());
+        }
+        if (h->wrows && h->n_wrows) {
+          const int64_t grid = std::min<int64_t>(h->n_wrows, (int64_t)cus * 2);
+          hipLaunchKernelGGL(spmm::num_rowwin_kernel<spmm::kRowPattern>, dim3((unsigned)grid), dim3(spmm::kWG),
+                             h->lds_window, s, O, P, h->items, h->wrows, h->n_wrows, h->win_log2, h->bsplit,
+                             h->n_win, h->pattern);
+          SG_TRY(hipGetLastError());
+        }
       }
       SG_TRY(hipStreamSynchronize(s));
       return SPMM_OK;
@@ -1467,7 +1534,11 @@ spmm_status spgemm_compute(spgemm_t plan, int32_t* colindC, float* valuesC, void
     const size_t lds = kBlockFixedLds + 8 * ((size_t)1 << tl);
     const size_t lds_bm = lds + sizeof(uint32_t) * (size_t)((plan->N + 31) / 32);
     const int64_t grid = std::min<int64_t>(cnt[c], 65536);
-    if (lds_bm <= plan->lds_max)
+    if (plan->pattern)
+      hipLaunchKernelGGL(spmm::num_block_kept_kernel, dim3((unsigned)grid), dim3(spmm::kWG),
+                         kBlockFixedLds + 4 * ((size_t)1 << tl), s, O, Co, rows + off[c], cnt[c], 1 << (tl - 1),
+                         plan->pattern);
+    else if (lds_bm <= plan->lds_max)
       hipLaunchKernelGGL(spmm::num_block_kernel<true>, dim3((unsigned)grid), dim3(spmm::kWG), lds_bm, s, O, Co,
                          rows + off[c], cnt[c], tl);
     else
