@@ -520,7 +520,7 @@ __device__ __forceinline__ void sort_emit_wave(const int32_t* key, const float* 
     const int e = r * 64 + lane;
     if (e < cnt) {
       Co.colC[base + e] = k[r];
-      Co.valC[base + e] = v[r];
+      if (Co.valC) Co.valC[base + e] = v[r];
     }
   }
 }
@@ -532,7 +532,9 @@ __device__ __forceinline__ int pow2_at_least(int n) {
 }
 
 // Rows with at most TS/2 output entries: a wave-local hash table of (column, sum).
-template <int TS>
+// Without VALS (the pattern pass at plan creation, Co.valC null) only the columns are
+// found and written.
+template <int TS, bool VALS = true>
 __global__ void __launch_bounds__(kBlock) num_wave_kernel(SgOperands O, SgOut Co, const int32_t* rows,
                                                           int64_t n_rows) {
   constexpr int W = kBlock / 64;
@@ -551,13 +553,13 @@ __global__ void __launch_bounds__(kBlock) num_wave_kernel(SgOperands O, SgOut Co
       val[j] = 0.0f;
     }
     wave_sync_lds();
-    wave_products<true>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref[w], s_start[w], s_aval[w],
+    wave_products<VALS>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref[w], s_start[w], s_aval[w],
                         [&](int32_t col, float prod) {
                           uint32_t h = hash_slot(col, SHIFT);
                           for (int probe = 0; probe < TS; ++probe) {  // at most half full
                             const int32_t old = atomicCAS(&key[h], -1, col);
                             if (old == -1 || old == col) {
-                              atomicAdd(&val[h], prod);
+                              if constexpr (VALS) atomicAdd(&val[h], prod);
                               break;
                             }
                             h = (h + 1) & (TS - 1);
@@ -597,6 +599,49 @@ __global__ void __launch_bounds__(kBlock) num_wave_kernel(SgOperands O, SgOut Co
       } else if constexpr (TS >= 1024) {
         sort_emit_wave<8>(key, val, lane, Co, base, cnt);
       }
+    }
+    wave_sync_lds();
+  }
+}
+
+// Rows of at most CAP output entries whose sorted columns the plan keeps (pattern,
+// indexed like C): one wave per row; the columns go to the wave's LDS beside their
+// sums, each product finds its column by binary search and adds into its sum with one
+// LDS atomic, and the row is written in order, coalesced: no hash inserts, no
+// compaction and no sort.
+template <int CAP>
+__global__ void __launch_bounds__(kBlock) num_wave_kept_kernel(SgOperands O, SgOut Co, const int32_t* rows,
+                                                               int64_t n_rows, const int32_t* pattern) {
+  constexpr int W = kBlock / 64;
+  __shared__ int32_t s_key[W][CAP];
+  __shared__ float s_val[W][CAP];
+  __shared__ int32_t s_pref[W][64], s_start[W][64];
+  __shared__ float s_aval[W][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int32_t* keys = s_key[w];
+  float* sums = s_val[w];
+  for (int64_t r = (int64_t)blockIdx.x * W + w; r < n_rows; r += (int64_t)gridDim.x * W) {
+    const int32_t i = rows[r];
+    const int32_t base = Co.rowptrC[i];
+    const int32_t n = min(Co.rowptrC[i + 1] - base, CAP);
+    for (int j = lane; j < n; j += 64) {
+      keys[j] = pattern[base + j];
+      sums[j] = 0.0f;
+    }
+    int hb = 1;  // the largest power of two not above n
+    while (hb * 2 <= n) hb *= 2;
+    wave_sync_lds();
+    wave_products<true>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref[w], s_start[w], s_aval[w],
+                        [&](int32_t col, float prod) {
+                          int pos = -1;  // the last key below col
+                          for (int step = hb; step > 0; step >>= 1)
+                            if (pos + step < n && keys[pos + step] < col) pos += step;
+                          if (pos + 1 < n) atomicAdd(&sums[pos + 1], prod);
+                        });
+    wave_sync_lds();
+    for (int j = lane; j < n; j += 64) {
+      Co.colC[base + j] = keys[j];
+      Co.valC[base + j] = sums[j];
     }
     wave_sync_lds();
   }
@@ -1081,7 +1126,7 @@ struct spgemm_s {
   int64_t n_wrows = 0;
   int32_t* bsplit = nullptr;      // device: B rows' window split positions (nullable)
   int n_win = 0;
-  int32_t* pattern = nullptr;     // device: C's columns of the rows of more than 512 entries, indexed like C (nullable)
+  int32_t* pattern = nullptr;     // device: C's columns, indexed like C (nullable)
   int64_t pattern_entries = 0;
   ~spgemm_s() {
     if (pattern) (void)hipFree(pattern);
@@ -1414,16 +1459,15 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
         const spmm_status st = ensure_slots(h, slot_count(h, h->cls_cnt[kLongClass], cus), s);
         if (st != SPMM_OK) return st;
       }
-      // C's columns for the rows of more than 512 entries (the workgroup tables, and the
-      // long rows when they take windows through a split table), found once here and
-      // kept, indexed like C: compute then adds each product with one LDS atomic (by
-      // binary search over a row's kept columns, or into its window's sums) and writes
-      // the entries in the kept order, instead of finding the columns again with hash
-      // inserts, bitmap atomics and bitmap walks on every call.  Kept when these rows
-      // hold at least a quarter of C and nnz(C) indices take at most a quarter of the
-      // free device memory.
+      // C's columns (of every row but the long rows that take no split table), found
+      // once here and kept, indexed like C: compute then adds each product with one LDS
+      // atomic (by binary search over a row's kept columns, or into its window's sums)
+      // and writes the entries in the kept order, instead of finding the columns again
+      // with hash inserts, sorts, bitmap atomics and bitmap walks on every call.  Kept
+      // when these rows hold at least a quarter of C and nnz(C) indices take at most a
+      // quarter of the free device memory.
       int64_t kept = 0;
-      for (int c = 3; c <= kLongClass; ++c) {
+      for (int c = 0; c <= kLongClass; ++c) {
         if (c == kLongClass && !h->wrows) break;
         for (int64_t t = 0; t < h->cls_cnt[c]; ++t) {
           const int32_t i = list[(size_t)(h->cls_off[c] + t)];
@@ -1443,6 +1487,16 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
       }
       if (h->pattern) {
         const spmm::SgOut P{h->rowptrC, h->pattern, nullptr};
+        const int32_t* rw = h->rows;
+        const int64_t* co = h->cls_off;
+        const int64_t* cc = h->cls_cnt;
+        if (cc[0]) hipLaunchKernelGGL((spmm::num_wave_kernel<256, false>), dim3((unsigned)spmm::grid_for(cc[0], 4)),
+                                      dim3(spmm::kBlock), 0, s, O, P, rw + co[0], cc[0]);
+        if (cc[1]) hipLaunchKernelGGL((spmm::num_wave_kernel<512, false>), dim3((unsigned)spmm::grid_for(cc[1], 4)),
+                                      dim3(spmm::kBlock), 0, s, O, P, rw + co[1], cc[1]);
+        if (cc[2]) hipLaunchKernelGGL((spmm::num_wave_kernel<1024, false>), dim3((unsigned)spmm::grid_for(cc[2], 4)),
+                                      dim3(spmm::kBlock), 0, s, O, P, rw + co[2], cc[2]);
+        SG_TRY(hipGetLastError());
         for (int c = 3; c < kLongClass; ++c) {
           if (!h->cls_cnt[c]) continue;
           const int tl = c + 8;
@@ -1521,12 +1575,22 @@ spmm_status spgemm_compute(spgemm_t plan, int32_t* colindC, float* valuesC, void
   const int32_t* rows = plan->rows;
   const int64_t* off = plan->cls_off;
   const int64_t* cnt = plan->cls_cnt;
-  if (cnt[0]) hipLaunchKernelGGL(spmm::num_wave_kernel<256>, dim3((unsigned)spmm::grid_for(cnt[0], 4)),
-                                 dim3(spmm::kBlock), 0, s, O, Co, rows + off[0], cnt[0]);
-  if (cnt[1]) hipLaunchKernelGGL(spmm::num_wave_kernel<512>, dim3((unsigned)spmm::grid_for(cnt[1], 4)),
-                                 dim3(spmm::kBlock), 0, s, O, Co, rows + off[1], cnt[1]);
-  if (cnt[2]) hipLaunchKernelGGL(spmm::num_wave_kernel<1024>, dim3((unsigned)spmm::grid_for(cnt[2], 4)),
-                                 dim3(spmm::kBlock), 0, s, O, Co, rows + off[2], cnt[2]);
+  if (plan->pattern) {
+    const int32_t* P = plan->pattern;
+    if (cnt[0]) hipLaunchKernelGGL(spmm::num_wave_kept_kernel<128>, dim3((unsigned)spmm::grid_for(cnt[0], 4)),
+                                   dim3(spmm::kBlock), 0, s, O, Co, rows + off[0], cnt[0], P);
+    if (cnt[1]) hipLaunchKernelGGL(spmm::num_wave_kept_kernel<256>, dim3((unsigned)spmm::grid_for(cnt[1], 4)),
+                                   dim3(spmm::kBlock), 0, s, O, Co, rows + off[1], cnt[1], P);
+    if (cnt[2]) hipLaunchKernelGGL(spmm::num_wave_kept_kernel<512>, dim3((unsigned)spmm::grid_for(cnt[2], 4)),
+                                   dim3(spmm::kBlock), 0, s, O, Co, rows + off[2], cnt[2], P);
+  } else {
+    if (cnt[0]) hipLaunchKernelGGL(spmm::num_wave_kernel<256>, dim3((unsigned)spmm::grid_for(cnt[0], 4)),
+                                   dim3(spmm::kBlock), 0, s, O, Co, rows + off[0], cnt[0]);
+    if (cnt[1]) hipLaunchKernelGGL(spmm::num_wave_kernel<512>, dim3((unsigned)spmm::grid_for(cnt[1], 4)),
+                                   dim3(spmm::kBlock), 0, s, O, Co, rows + off[1], cnt[1]);
+    if (cnt[2]) hipLaunchKernelGGL(spmm::num_wave_kernel<1024>, dim3((unsigned)spmm::grid_for(cnt[2], 4)),
+                                   dim3(spmm::kBlock), 0, s, O, Co, rows + off[2], cnt[2]);
+  }
   SG_TRY(hipGetLastError());
   for (int c = 3; c < kLongClass; ++c) {
     if (!cnt[c]) continue;
