@@ -517,7 +517,7 @@ def spgemm_create(M: int, A: Tuple[torch.Tensor, torch.Tensor, torch.Tensor, int
                   B: Tuple[torch.Tensor, torch.Tensor, torch.Tensor, int], validate: bool = True,
                   stream: Optional[torch.cuda.Stream] = None, keep_pattern: bool = True) -> SpgemmPlan:
     """Structure analysis and symbolic product of C = A B (A: M x A.cols, B: A.cols x B.cols).
-    keep_pattern=False: keep no column pattern of the long rows (SPGEMM_BITMAP_ONLY)."""
+    keep_pattern=False: keep no column pattern, find the columns on every compute call (SPGEMM_BITMAP_ONLY)."""
     a = _csr_struct(*A, "A")
     b = _csr_struct(*B, "B")
     if A[0].numel() != M + 1 or B[0].numel() != int(A[3]) + 1:
