@@ -415,7 +415,9 @@ spmm_status spmm_tile_accumulate_n(void* C, int64_t ldc, const void* const* P, c
  *
  * A is M x A->cols, B is A->cols x B->cols; both canonical CSR (int32 indices,
  * FP32 values, strictly increasing columns per row; SPMM_TILE_VALIDATE checks it),
- * device arrays owned by the caller that must outlive the plan.
+ * device arrays owned by the caller that must outlive the plan; their row pointers and
+ * column indices must not change while it lives (the plan is built from them), their
+ * values may.
  *
  * spgemm_create analyses the structure and runs the symbolic product,
  * synchronously: products per row, C's entries per row and C's row pointer
