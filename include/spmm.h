@@ -432,21 +432,25 @@ spmm_status spmm_tile_accumulate_n(void* C, int64_t ldc, const void* const* P, c
  * and B's values live; asynchronous, no allocation, no host synchronisation.
  * Calls on one plan must not overlap (they share the dense accumulators).
  *
- * C's column indices are found once, at plan creation, and kept in the plan (4 bytes
- * per entry of C, indexed like C) when the rows they cover hold at least a quarter of
- * C and the array takes at most a quarter of the free device memory; flag
- * SPGEMM_BITMAP_ONLY keeps none.  They cover every row except the long rows (more
- * entries than the largest workgroup table holds: 4,096 or 8,192, by the LDS left
- * beside a bitmap over C's columns) that go without a split table of B (binary-searched
- * windows, or dense rows for a very wide B).  compute then adds each product of such a row into its sum with one LDS atomic
- * (found by binary search over the row's kept columns, or at its column in the
- * window's sums) and writes the entries in the kept order, instead of finding the
- * columns again with hash tables, sorts and bitmaps; the results are the same either
- * way.  spgemm_pattern_entries returns how many entries of C the plan keeps (0: none).
+ * The plan keeps C's column indices (4 bytes per entry of C, indexed like C, allocated
+ * at creation) when the rows they cover hold at least a quarter of C and the array
+ * takes at most a quarter of the free device memory; flag SPGEMM_BITMAP_ONLY keeps
+ * none.  They cover every row except the long rows (more entries than the largest
+ * workgroup table holds: 4,096 or 8,192, by the LDS left beside a bitmap over C's
+ * columns) that go without a split table of B (binary-searched windows, or dense rows
+ * for a very wide B).  The first compute call finds the columns with hash tables,
+ * sorts and bitmaps, as every call does without a kept pattern, and copies them into
+ * the plan at its end; later calls add each product of a covered row into its sum
+ * with one LDS atomic (found by binary search over the row's kept columns, or at its
+ * column in the window's sums) and write the entries in the kept order.  A call made
+ * while its stream is being captured into a graph keeps nothing (its copy would run
+ * only at replay), so the first call outside capture does.  The results are the same
+ * either way.  spgemm_pattern_entries returns how many entries of C the plan keeps
+ * (0: none).
  * Errors: INVALID_ARG, BAD_CSR (with SPMM_TILE_VALIDATE), UNSUPPORTED (nnz > 2^31 - 2^16,
  * C with >= 2^31 entries), ALLOC, HIP.
  */
-#define SPGEMM_BITMAP_ONLY 16u  /* spgemm_create: keep no column pattern; compute finds the columns every call */
+#define SPGEMM_BITMAP_ONLY 16u  /* spgemm_create: keep no column pattern; every compute call finds the columns */
 typedef struct spgemm_s* spgemm_t;
 spmm_status spgemm_create(int64_t M, const spmm_csr* A /* host */, const spmm_csr* B /* host */, unsigned flags,
                           void* stream, spgemm_t* out /* host */);

@@ -520,7 +520,7 @@ __device__ __forceinline__ void sort_emit_wave(const int32_t* key, const float* 
     const int e = r * 64 + lane;
     if (e < cnt) {
       Co.colC[base + e] = k[r];
-      if (Co.valC) Co.valC[base + e] = v[r];
+      Co.valC[base + e] = v[r];
     }
   }
 }
@@ -532,9 +532,7 @@ __device__ __forceinline__ int pow2_at_least(int n) {
 }
 
 // Rows with at most TS/2 output entries: a wave-local hash table of (column, sum).
-// Without VALS (the pattern pass at plan creation, Co.valC null) only the columns are
-// found and written.
-template <int TS, bool VALS = true>
+template <int TS>
 __global__ void __launch_bounds__(kBlock) num_wave_kernel(SgOperands O, SgOut Co, const int32_t* rows,
                                                           int64_t n_rows) {
   constexpr int W = kBlock / 64;
@@ -553,13 +551,13 @@ __global__ void __launch_bounds__(kBlock) num_wave_kernel(SgOperands O, SgOut Co
       val[j] = 0.0f;
     }
     wave_sync_lds();
-    wave_products<VALS>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref[w], s_start[w], s_aval[w],
+    wave_products<true>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref[w], s_start[w], s_aval[w],
                         [&](int32_t col, float prod) {
                           uint32_t h = hash_slot(col, SHIFT);
                           for (int probe = 0; probe < TS; ++probe) {  // at most half full
                             const int32_t old = atomicCAS(&key[h], -1, col);
                             if (old == -1 || old == col) {
-                              if constexpr (VALS) atomicAdd(&val[h], prod);
+                              atomicAdd(&val[h], prod);
                               break;
                             }
                             h = (h + 1) & (TS - 1);
@@ -652,9 +650,8 @@ __global__ void __launch_bounds__(kBlock) num_wave_kept_kernel(SgOperands O, SgO
 // order: with BM, a bitmap over all N columns (in LDS after the table) marks each new
 // key, and a walk over it writes the row in column order, looking each value up in
 // the table; without BM (N too wide for LDS), the occupied slots are compacted and
-// bitonic-sorted.  Without VALS (the pattern pass at plan creation) only the columns
-// are found and written, to Co.colC.
-template <bool BM, bool VALS = true>
+// bitonic-sorted.
+template <bool BM>
 __global__ void __launch_bounds__(kWG) num_block_kernel(SgOperands O, SgOut Co, const int32_t* rows,
                                                         int64_t n_rows, int tg_log2) {
   extern __shared__ int32_t s_dyn[];
@@ -684,13 +681,13 @@ __global__ void __launch_bounds__(kWG) num_block_kernel(SgOperands O, SgOut Co, 
       val[j] = 0.0f;
     }
     __syncthreads();
-    block_products<VALS, false>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref, s_start, s_aval, s_tmp,
+    block_products<true, false>(O, O.rowptrA[i], O.rowptrA[i + 1], s_pref, s_start, s_aval, s_tmp,
                         [&](int32_t col, float prod) {
                           uint32_t h = hash_slot(col, shift);
                           for (int probe = 0; probe < tg; ++probe) {  // at most half full
                             const int32_t old = atomicCAS(&key[h], -1, col);
                             if (old == -1 || old == col) {
-                              if constexpr (VALS) atomicAdd(&val[h], prod);
+                              atomicAdd(&val[h], prod);
                               if (BM && old == -1) atomicOr(bits + (col >> 5), 1u << (col & 31));
                               break;
                             }
@@ -712,20 +709,18 @@ __global__ void __launch_bounds__(kWG) num_block_kernel(SgOperands O, SgOut Co, 
           const int b = __ffs(word) - 1;
           word &= word - 1;
           const int32_t col = (int32_t)(wi * 32 + b);
+          uint32_t h = hash_slot(col, shift);
           float v = 0.0f;
-          if constexpr (VALS) {
-            uint32_t h = hash_slot(col, shift);
-            for (int probe = 0; probe < tg; ++probe) {
-              if (key[h] == col) {
-                v = val[h];
-                break;
-              }
-              h = (h + 1) & (uint32_t)(tg - 1);
+          for (int probe = 0; probe < tg; ++probe) {
+            if (key[h] == col) {
+              v = val[h];
+              break;
             }
+            h = (h + 1) & (uint32_t)(tg - 1);
           }
           if (pos < end) {
             Co.colC[pos] = col;
-            if constexpr (VALS) Co.valC[pos] = v;
+            Co.valC[pos] = v;
           }
           ++pos;
         }
@@ -762,7 +757,7 @@ __global__ void __launch_bounds__(kWG) num_block_kernel(SgOperands O, SgOut Co, 
       const int32_t cnt = min(Co.rowptrC[i + 1] - base, n);
       for (int j = tid; j < cnt; j += kWG) {
         Co.colC[base + j] = key[j];
-        if constexpr (VALS) Co.valC[base + j] = val[j];
+        Co.valC[base + j] = val[j];
       }
       __syncthreads();
     }
@@ -864,30 +859,6 @@ __device__ __forceinline__ void window_emit(const SgOut& Co, float* acc, uint32_
   __syncthreads();
 }
 
-// The pattern pass of a window: its columns, in order, to dst[0, cnt) from the bitmap
-// (cleared as it is read; the sums are not touched).  Ends with a barrier.
-__device__ __forceinline__ void window_emit_pattern(uint32_t* bits, int ww, int32_t c0, int32_t* dst, int32_t cnt,
-                                                    int32_t* s_tmp) {
-  const int tid = threadIdx.x;
-  int32_t out = 0;
-  for (int w0 = 0; w0 < ww; w0 += kWG) {
-    const int wi = w0 + tid;
-    uint32_t word = wi < ww ? bits[wi] : 0u;
-    int32_t excl;
-    const int32_t tot = block_scan(__popc(word), &excl, s_tmp);
-    int32_t pos = out + excl;
-    while (word) {
-      const int b = __ffs(word) - 1;
-      word &= word - 1;
-      if (pos < cnt) dst[pos] = c0 + wi * 32 + b;
-      ++pos;
-    }
-    if (wi < ww) bits[wi] = 0u;
-    out += tot;
-  }
-  __syncthreads();
-}
-
 // A window's entries at [out, out + cnt) in the order of its stored columns src[0, cnt):
 // each sum is read and cleared by the one thread that writes its entry (the columns of
 // a window are distinct), coalesced global reads and writes.  Ends with a barrier.
@@ -943,22 +914,20 @@ __global__ void __launch_bounds__(kWG) num_window_kernel(SgOperands O, SgOut Co,
 // accumulates, so a window costs its products and its compaction, not a chain of
 // dependent loads; longer rows take each window through block_products.
 // MODE kRowFull: sums and bitmap by LDS atomics, entries written from the bitmap.
-// kRowPattern (at plan creation): bitmap only, the columns written to `pattern`.
-// kRowValues: sums only, entries written in the stored pattern's order (one LDS atomic
-// per product instead of two, and no bitmap walk).
-constexpr int kRowFull = 0, kRowPattern = 1, kRowValues = 2;
+// kRowValues: sums only, entries written in the order of C's kept columns (one LDS
+// atomic per product instead of two, and no bitmap walk).
+constexpr int kRowFull = 0, kRowValues = 1;
 
 template <int MODE>
 __device__ __forceinline__ void window_add(float* acc, uint32_t* bits, int32_t x, float prod) {
-  if constexpr (MODE != kRowValues) atomicOr(bits + (x >> 5), 1u << (x & 31));
-  if constexpr (MODE != kRowPattern) atomicAdd(acc + x, prod);
+  if constexpr (MODE == kRowFull) atomicOr(bits + (x >> 5), 1u << (x & 31));
+  atomicAdd(acc + x, prod);
 }
 
 template <int MODE>
 __device__ __forceinline__ void window_finish(const SgOut& Co, float* acc, uint32_t* bits, int ww, int32_t c0,
                                               const SgItem& item, int32_t* pattern, int32_t* s_tmp) {
   if constexpr (MODE == kRowFull) window_emit(Co, acc, bits, ww, c0, item.out, item.cnt, s_tmp);
-  if constexpr (MODE == kRowPattern) window_emit_pattern(bits, ww, c0, pattern + item.out, item.cnt, s_tmp);
   if constexpr (MODE == kRowValues) window_emit_values(Co, acc, pattern + item.out, c0, item.out, item.cnt);
 }
 
@@ -966,7 +935,6 @@ template <int MODE>
 __global__ void __launch_bounds__(kWG) num_rowwin_kernel(SgOperands O, SgOut Co, const SgItem* items,
                                                          const SgRow* rows, int64_t n_rows, int win_log2,
                                                          const int32_t* bsplit, int n_win, int32_t* pattern) {
-  constexpr bool VALS = MODE != kRowPattern;
   extern __shared__ int32_t s_dyn[];
   const int W = 1 << win_log2;
   const int ww = W >> 5;
@@ -990,7 +958,7 @@ __global__ void __launch_bounds__(kWG) num_rowwin_kernel(SgOperands O, SgOut Co,
       float av = 0.0f;
       if (mine) {
         k = O.colA[a0 + tid];
-        if constexpr (VALS) av = O.valA[a0 + tid];
+        av = O.valA[a0 + tid];
       }
       const int32_t* sp = bsplit + (int64_t)k * stride;
       SgItem item = items[R.first];
@@ -1010,7 +978,7 @@ __global__ void __launch_bounds__(kWG) num_rowwin_kernel(SgOperands O, SgOut Co,
           }
         }
         const int32_t c0 = item.win << win_log2;
-        walk_products<VALS>(O, st, en - st, av, s_pref, s_start, s_aval, s_tmp,
+        walk_products<true>(O, st, en - st, av, s_pref, s_start, s_aval, s_tmp,
                             [&](int32_t col, float prod) { window_add<MODE>(acc, bits, col - c0, prod); });
         window_finish<MODE>(Co, acc, bits, ww, c0, item, pattern, s_tmp);
         item = nxt;
@@ -1022,7 +990,7 @@ __global__ void __launch_bounds__(kWG) num_rowwin_kernel(SgOperands O, SgOut Co,
         const SgItem item = items[R.first + j];
         const int32_t c0 = item.win << win_log2;
         const int32_t c1 = (int32_t)min((int64_t)c0 + W, O.N);
-        block_products<VALS, true>(O, a0, a1, s_pref, s_start, s_aval, s_tmp,
+        block_products<true, true>(O, a0, a1, s_pref, s_start, s_aval, s_tmp,
                                    [&](int32_t col, float prod) { window_add<MODE>(acc, bits, col - c0, prod); },
                                    c0, c1, bsplit, stride, item.win);
         window_finish<MODE>(Co, acc, bits, ww, c0, item, pattern, s_tmp);
@@ -1128,6 +1096,7 @@ struct spgemm_s {
   int n_win = 0;
   int32_t* pattern = nullptr;     // device: C's columns, indexed like C (nullable)
   int64_t pattern_entries = 0;
+  bool pattern_ready = false;     // filled by a compute call outside graph capture
   ~spgemm_s() {
     if (pattern) (void)hipFree(pattern);
     if (rowptrC) (void)hipFree(rowptrC);
@@ -1394,8 +1363,6 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(spmm::num_block_kernel<false>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
       for (const void* f : {reinterpret_cast<const void*>(spmm::num_block_kernel<true>),
-                            reinterpret_cast<const void*>(spmm::num_block_kernel<true, false>),
-                            reinterpret_cast<const void*>(spmm::num_block_kernel<false, false>),
                             reinterpret_cast<const void*>(spmm::num_block_kept_kernel)})
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
       if (h->cls_cnt[kLongClass] && h->win_log2) {
@@ -1439,7 +1406,6 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
           if (h->n_wrows)
             SG_TRY(hipMemcpyAsync(h->wrows, wr.data(), sizeof(spmm::SgRow) * wr.size(), hipMemcpyHostToDevice, s));
           for (const void* f : {reinterpret_cast<const void*>(spmm::num_rowwin_kernel<spmm::kRowFull>),
-                                reinterpret_cast<const void*>(spmm::num_rowwin_kernel<spmm::kRowPattern>),
                                 reinterpret_cast<const void*>(spmm::num_rowwin_kernel<spmm::kRowValues>)})
             (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds_window);
           SG_TRY(hipStreamSynchronize(s));  // wr is read before it goes out of scope
@@ -1459,13 +1425,14 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
         const spmm_status st = ensure_slots(h, slot_count(h, h->cls_cnt[kLongClass], cus), s);
         if (st != SPMM_OK) return st;
       }
-      // C's columns (of every row but the long rows that take no split table), found
-      // once here and kept, indexed like C: compute then adds each product with one LDS
-      // atomic (by binary search over a row's kept columns, or into its window's sums)
-      // and writes the entries in the kept order, instead of finding the columns again
-      // with hash inserts, sorts, bitmap atomics and bitmap walks on every call.  Kept
-      // when these rows hold at least a quarter of C and nnz(C) indices take at most a
-      // quarter of the free device memory.
+      // Room for C's columns, indexed like C, kept from the first compute call on (which
+      // finds them as before and copies them here): later calls add each product with
+      // one LDS atomic (by binary search over a row's kept columns, or into its window's
+      // sums) and write the entries in the kept order, instead of finding the columns
+      // again with hash inserts, sorts, bitmap atomics and bitmap walks.  They cover
+      // every row but the long rows that take no split table; kept when these rows hold
+      // at least a quarter of C and nnz(C) indices take at most a quarter of the free
+      // device memory.
       int64_t kept = 0;
       for (int c = 0; c <= kLongClass; ++c) {
         if (c == kLongClass && !h->wrows) break;
@@ -1483,40 +1450,6 @@ spmm_status spgemm_create(int64_t M, const spmm_csr* A, const spmm_csr* B, unsig
             h->pattern = nullptr;
             (void)hipGetLastError();  // no pattern: compute finds the columns on every call
           }
-        }
-      }
-      if (h->pattern) {
-        const spmm::SgOut P{h->rowptrC, h->pattern, nullptr};
-        const int32_t* rw = h->rows;
-        const int64_t* co = h->cls_off;
-        const int64_t* cc = h->cls_cnt;
-        if (cc[0]) hipLaunchKernelGGL((spmm::num_wave_kernel<256, false>), dim3((unsigned)spmm::grid_for(cc[0], 4)),
-                                      dim3(spmm::kBlock), 0, s, O, P, rw + co[0], cc[0]);
-        if (cc[1]) hipLaunchKernelGGL((spmm::num_wave_kernel<512, false>), dim3((unsigned)spmm::grid_for(cc[1], 4)),
-                                      dim3(spmm::kBlock), 0, s, O, P, rw + co[1], cc[1]);
-        if (cc[2]) hipLaunchKernelGGL((spmm::num_wave_kernel<1024, false>), dim3((unsigned)spmm::grid_for(cc[2], 4)),
-                                      dim3(spmm::kBlock), 0, s, O, P, rw + co[2], cc[2]);
-        SG_TRY(hipGetLastError());
-        for (int c = 3; c < kLongClass; ++c) {
-          if (!h->cls_cnt[c]) continue;
-          const int tl = c + 8;
-          const size_t lds = kBlockFixedLds + 8 * ((size_t)1 << tl);
-          const size_t lds_bm = lds + sizeof(uint32_t) * (size_t)((h->N + 31) / 32);
-          const int64_t grid = std::min<int64_t>(h->cls_cnt[c], 65536);
-          if (lds_bm <= h->lds_max)
-            hipLaunchKernelGGL((spmm::num_block_kernel<true, false>), dim3((unsigned)grid), dim3(spmm::kWG), lds_bm,
-                               s, O, P, h->rows + h->cls_off[c], h->cls_cnt[c], tl);
-          else
-            hipLaunchKernelGGL((spmm::num_block_kernel<false, false>), dim3((unsigned)grid), dim3(spmm::kWG), lds,
-                               s, O, P, h->rows + h->cls_off[c], h->cls_cnt[c], tl);
-          SG_TRY(hipGetLastError());
-        }
-        if (h->wrows && h->n_wrows) {
-          const int64_t grid = std::min<int64_t>(h->n_wrows, (int64_t)cus * 2);
-          hipLaunchKernelGGL(spmm::num_rowwin_kernel<spmm::kRowPattern>, dim3((unsigned)grid), dim3(spmm::kWG),
-                             h->lds_window, s, O, P, h->items, h->wrows, h->n_wrows, h->win_log2, h->bsplit,
-                             h->n_win, h->pattern);
-          SG_TRY(hipGetLastError());
         }
       }
       SG_TRY(hipStreamSynchronize(s));
@@ -1575,7 +1508,10 @@ spmm_status spgemm_compute(spgemm_t plan, int32_t* colindC, float* valuesC, void
   const int32_t* rows = plan->rows;
   const int64_t* off = plan->cls_off;
   const int64_t* cnt = plan->cls_cnt;
-  if (plan->pattern) {
+  // C's kept columns, once a call has filled them; before that, the columns are found
+  // as the rows are computed and copied into the plan at the end of the call
+  const bool kept = plan->pattern && plan->pattern_ready;
+  if (kept) {
     const int32_t* P = plan->pattern;
     if (cnt[0]) hipLaunchKernelGGL(spmm::num_wave_kept_kernel<128>, dim3((unsigned)spmm::grid_for(cnt[0], 4)),
                                    dim3(spmm::kBlock), 0, s, O, Co, rows + off[0], cnt[0], P);
@@ -1598,7 +1534,7 @@ spmm_status spgemm_compute(spgemm_t plan, int32_t* colindC, float* valuesC, void
     const size_t lds = kBlockFixedLds + 8 * ((size_t)1 << tl);
     const size_t lds_bm = lds + sizeof(uint32_t) * (size_t)((plan->N + 31) / 32);
     const int64_t grid = std::min<int64_t>(cnt[c], 65536);
-    if (plan->pattern)
+    if (kept)
       hipLaunchKernelGGL(spmm::num_block_kept_kernel, dim3((unsigned)grid), dim3(spmm::kWG),
                          kBlockFixedLds + 4 * ((size_t)1 << tl), s, O, Co, rows + off[c], cnt[c], 1 << (tl - 1),
                          plan->pattern);
@@ -1616,7 +1552,7 @@ spmm_status spgemm_compute(spgemm_t plan, int32_t* colindC, float* valuesC, void
       SG_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
       if (plan->wrows) {
         const int64_t grid = std::min<int64_t>(plan->n_wrows, (int64_t)cus * 2);
-        if (plan->pattern)
+        if (kept)
           hipLaunchKernelGGL(spmm::num_rowwin_kernel<spmm::kRowValues>, dim3((unsigned)grid), dim3(spmm::kWG),
                              plan->lds_window, s, O, Co, plan->items, plan->wrows, plan->n_wrows, plan->win_log2,
                              plan->bsplit, plan->n_win, plan->pattern);
@@ -1635,6 +1571,17 @@ spmm_status spgemm_compute(spgemm_t plan, int32_t* colindC, float* valuesC, void
     hipLaunchKernelGGL(spmm::num_dense_kernel, dim3((unsigned)plan->n_slots), dim3(spmm::kWG), 0, s, O, Co,
                        rows + off[kLongClass], cnt[kLongClass], plan->slot_vals, plan->slot_bits, plan->slot_words);
     SG_TRY(hipGetLastError());
+  }
+  if (plan->pattern && !kept && plan->nnz_c > 0) {
+    // keep the columns this call wrote; not while the stream is being captured (the
+    // copy would only run at replay, so later eager calls could not rely on it)
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    SG_TRY(hipStreamIsCapturing(s, &cs));
+    if (cs == hipStreamCaptureStatusNone) {
+      SG_TRY(hipMemcpyAsync(plan->pattern, colindC, sizeof(int32_t) * (size_t)plan->nnz_c, hipMemcpyDeviceToDevice,
+                            s));
+      plan->pattern_ready = true;
+    }
   }
   return SPMM_OK;
 }

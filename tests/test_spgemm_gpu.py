@@ -51,19 +51,25 @@ def _check(A, B, exact=False, plan=None, compress_cols=False, keep_pattern=True)
             assert plan.pattern_entries == 0
     rp = ops.spgemm_rowptr(plan)
     ci, va = ops.spgemm_compute(plan)
+    calls = [(ci, va)]
+    if plan.pattern_entries:
+        # the first call found C's columns and kept them; the next one runs the kept-pattern kernels
+        calls.append(ops.spgemm_compute(plan))
+        ci, va = calls[-1]
     torch.cuda.synchronize()
     r_rp, r_ci, r_va, S = _oracle(A, B, compress_cols)
     assert plan.nnz_c == int(r_rp[-1])
     assert plan.products == int(_products_per_row(A, B).sum())
     assert np.array_equal(rp.cpu().numpy().astype(np.int64), r_rp)
-    assert np.array_equal(ci.cpu().numpy().astype(np.int64), r_ci)
-    got = va.cpu().numpy().astype(np.float64)
-    if exact:
-        assert np.array_equal(got, r_va)
-    else:
-        n_terms = np.repeat(_products_per_row(A, B) + 1, np.diff(r_rp))
-        st = compare.fp32_stats(got, r_va, S, n_terms=n_terms)
-        assert compare.fp32_ok(st), st
+    n_terms = np.repeat(_products_per_row(A, B) + 1, np.diff(r_rp))
+    for ci, va in calls:
+        assert np.array_equal(ci.cpu().numpy().astype(np.int64), r_ci)
+        got = va.cpu().numpy().astype(np.float64)
+        if exact:
+            assert np.array_equal(got, r_va)
+        else:
+            st = compare.fp32_stats(got, r_va, S, n_terms=n_terms)
+            assert compare.fp32_ok(st), st
     return plan
 
 
@@ -332,6 +338,40 @@ def test_spgemm_long_rows_live_values_and_repeat():
     A2 = synth.CSR(A.rows, A.cols, A.rowptr, A.colind, (A.values * -2.0).astype(np.float32))
     B2 = synth.CSR(B.rows, B.cols, B.rowptr, B.colind, (B.values * 3.0).astype(np.float32))
     _check(A2, B2, exact=True, plan=plan)
+
+
+def test_spgemm_graph_capture_as_first_call():
+    """A plan's first compute call made under graph capture keeps no columns (its copy would only
+    run at replay): replays and the eager calls after it, the first of which keeps the columns and
+    the next of which uses them, all give the eager result."""
+    G.note("spgemm graph capture as the first call")
+    rng = _rng(24)
+    A, B = _long_rows_case(rng)
+    plan, dA, dB = _plan(A, B)
+    ref, _, _ = _plan(A, B, keep_pattern=False)
+    ref_ci, ref_va = ops.spgemm_compute(ref)
+    ci = torch.empty(plan.nnz_c, dtype=torch.int32, device=G.DEV)
+    va = torch.empty(plan.nnz_c, dtype=torch.float32, device=G.DEV)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        ops.spgemm_compute(plan, ci, va)
+    for r in range(3):
+        ci.fill_(-1)
+        va.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(ci, ref_ci) and torch.equal(va, ref_va), r
+    for r in range(3):   # finds and keeps the columns, then uses them
+        ci.fill_(-1)
+        va.fill_(float("nan"))
+        ops.spgemm_compute(plan, ci, va)
+        torch.cuda.synchronize()
+        assert torch.equal(ci, ref_ci) and torch.equal(va, ref_va), r
+    g.replay()           # the captured (column-finding) form still agrees
+    torch.cuda.synchronize()
+    assert torch.equal(ci, ref_ci) and torch.equal(va, ref_va)
 
 
 def test_spgemm_long_rows_graph_replay():
